@@ -1,0 +1,192 @@
+/*
+ * lbe.h -- C ABI of the MI355X (gfx950) stabilized Lattice Boltzmann-Enskog
+ * library: one time step of the double-distribution, trapezoidal-rule
+ * (DD-TR) scheme of Melchionna and Marini Bettolo Marconi, arXiv:1202.3842.
+ *
+ * The problem follows the paper's statement of it:
+ *   - M species of hard spheres with diameters sigma_a and unit mass
+ *     (Sec. 2; Appendix, sigma_ab = (sigma_aa + sigma_bb)/2);
+ *   - an external potential U with force F = -grad U per particle and an
+ *     optional uniform body force (Sec. 4.1 eq. extpotential, Sec. 4.3);
+ *   - solid nodes with mid-point bounce-back walls for f and g (Sec. 4.3);
+ *   - BGK relaxation with inverse time omega = 1/tau (Sec. 2,
+ *     eq. boltzoriginal) on the D3Q19 lattice with h = dx = 1, v_T^2 = kT;
+ *   - observables n^a and u^a (Sec. 4.1 error measures, Sec. 4.2 moments).
+ *
+ * One step computes, on the GPU only:
+ *   moments n~, Pi~, J~ (Sec. 4.2); weighted densities and contact values;
+ *   the Enskog mean-field force C^mf and the collisional viscous force
+ *   C^visc on the tilde moments (Appendix; Sec. 3 eq. relatemoments);
+ *   the inversions to n, Pi, J; equilibria and sources (Sec. 4.2
+ *   eqs. kernel-f-1 .. kernel-g-1); the trapezoidal BGK update (Sec. 4.1);
+ *   Lagrangian streaming with mid-point bounce-back (Sec. 4.1, 4.3).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns lbe_status; no C++ exception crosses the ABI.
+ *     lbe_last_error() returns a thread-local text for the last failure.
+ *   - Memory: all device memory of a context lives in ONE caller-owned
+ *     device workspace of lbe_workspace_bytes() bytes, 256-byte aligned,
+ *     passed to lbe_create; the library never allocates device memory and
+ *     never frees the workspace.  Host inputs are copied before the call
+ *     returns.  Device inputs (where = LBE_DEVICE) must stay valid until the
+ *     stream reaches the call.
+ *   - Streams: work is enqueued on the HIP stream given to lbe_create (NULL
+ *     = the null stream).  Setters and lbe_step are asynchronous; the getters,
+ *     lbe_diagnostics and lbe_synchronize block until their results are
+ *     ready.
+ *   - Layout: node index idx = x + nx*(y + ny*z).  Scalar fields hold N =
+ *     nx*ny*nz values, vector fields 3N (component-major: all x, then y,
+ *     then z), populations 19N (direction-major, D3Q19 order below).
+ *     D3Q19 order: 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 = (1,1,0),
+ *     (-1,-1,0),(1,-1,0),(-1,1,0),(1,0,1),(-1,0,-1),(1,0,-1),(-1,0,1),
+ *     (0,1,1),(0,-1,-1),(0,1,-1),(0,-1,1).
+ *   - Populations returned and accepted are the post-streaming transformed
+ *     populations f~, g~ of eq. (invertpops) at the current step.
+ *   - After LBE_ERR_UNSTABLE (a packing fraction xi3 >= 1 or a non-finite
+ *     density was met) the context refuses lbe_step until lbe_init_density
+ *     or lbe_set_populations is called.
+ */
+#ifndef LBE_H
+#define LBE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbe_ctx lbe_ctx;
+
+typedef enum {
+  LBE_OK = 0,
+  LBE_ERR_ARG = -1,          /* invalid argument or configuration          */
+  LBE_ERR_STATE = -2,        /* call not valid in the context's state       */
+  LBE_ERR_OOM = -3,          /* workspace too small                         */
+  LBE_ERR_HIP = -4,          /* a HIP runtime call failed                   */
+  LBE_ERR_UNSTABLE = -5,     /* xi3 >= 1 or a non-finite density            */
+  LBE_ERR_UNSUPPORTED = -6   /* configuration outside what is built          */
+} lbe_status;
+
+typedef enum {
+  LBE_FP64 = 0,      /* populations stored in FP64                          */
+  LBE_FP32_POP = 1   /* populations stored in FP32, all arithmetic in FP64  */
+} lbe_precision;
+
+enum { LBE_HOST = 0, LBE_DEVICE = 1 };   /* the 'where' of user pointers    */
+
+/* Scheme switches (readings of the paper where it is ambiguous).
+ *  LBE_VISC         include C^visc (Appendix, eq. viscousforce) in S_f,
+ *                   S_g and the J inversion (Sec. 4.2).
+ *  LBE_PRINTED_INV  the inversions as printed in Sec. 4.2:
+ *                   J = J~ + (C^mf + C^visc + nF)/2,
+ *                   Pi = Pi~ - (beta/2) C^mf.u^a; default is the reading
+ *                   derived from eq. (invertmoments): J = J~ + (C^visc+nF)/2,
+ *                   Pi = Pi~ + (beta/2) C^mf.u^a.
+ *  LBE_KAPPA4       the printed coefficient 4 on H2.u^a in the C^mf part of
+ *                   S_g (Sec. 4.2); default is 2, the Hermite projection.
+ *  LBE_IDEAL        C = 0: the ideal fluid of Sec. 4.1.                     */
+enum {
+  LBE_VISC = 1u << 0,
+  LBE_PRINTED_INV = 1u << 1,
+  LBE_KAPPA4 = 1u << 2,
+  LBE_IDEAL = 1u << 3
+};
+
+#define LBE_MAX_SPECIES 4
+
+typedef struct {
+  int nx, ny, nz;         /* lattice size                                    */
+  unsigned periodic;      /* bit0 = x, bit1 = y, bit2 = z; non-periodic
+                             directions have solid walls just outside       */
+  int nspecies;           /* M = 1..4                                        */
+  double sigma[4];        /* diameters sigma_a in lattice units (0 = point)  */
+  double tau;             /* 1/omega of the BGK term                         */
+  double kT;              /* must be 1/3 (v_T^2 of D3Q19, m = 1)             */
+  lbe_precision prec;     /* population storage                              */
+  unsigned flags;         /* LBE_* switches                                  */
+} lbe_config;
+
+typedef struct {
+  double mass[4];         /* sum over fluid nodes of n^a                     */
+  double gmom[3];         /* sum over species and nodes of J~^a              */
+  double umax;            /* max |u| (barycentric, half-step corrected)      */
+  double err_n;           /* max |n - n_eq| / n_0, n_eq = ideal-gas profile  */
+  double err_u;           /* umax / v_T (Sec. 4.1 Err(u))                    */
+  double err_J;           /* max |J| / (n_0 v_T) (Sec. 4.1 Err(J))           */
+  int unstable;           /* 1 after a packing fraction >= 1 or a NaN        */
+} lbe_diag;
+
+/* Bytes of device workspace a context with this configuration needs, or 0
+ * if the configuration is invalid (lbe_last_error says why). */
+size_t lbe_workspace_bytes(const lbe_config *cfg);
+
+/* Create a context for one lattice box on the current HIP device.
+ * dev_workspace: caller-owned device memory of at least
+ * lbe_workspace_bytes(cfg) bytes (256-byte aligned); hip_stream: a
+ * hipStream_t or NULL.  On success *out holds the context; the populations
+ * are zero until lbe_init_density or lbe_set_populations. */
+lbe_status lbe_create(const lbe_config *cfg, void *dev_workspace,
+                      size_t bytes, void *hip_stream, lbe_ctx **out);
+
+/* Solid mask (Sec. 4.3 walls): N bytes, nonzero = solid.  Populations at
+ * solid nodes are cleared. */
+lbe_status lbe_set_solid(lbe_ctx *ctx, const uint8_t *mask, int where);
+
+/* External potential U per particle (Sec. 4.1 eq. extpotential), N values,
+ * shared by all species; F = -grad_h U with the isotropic D3Q19 gradient
+ * (1/v_T^2) sum_p w_p c_p U(r + c_p), wrapped in periodic directions and
+ * clamped in the others. */
+lbe_status lbe_set_potential(lbe_ctx *ctx, const double *V, int where);
+
+/* Uniform body force per particle on one species (Sec. 4.3 forcing). */
+lbe_status lbe_set_body_force(lbe_ctx *ctx, int species, const double g[3]);
+
+/* Rest-equilibrium initial state f~ = g~ = w_p n0 on fluid nodes (so u = 0
+ * and Pi = n at t = 0), N values. */
+lbe_status lbe_init_density(lbe_ctx *ctx, int species, const double *n0,
+                            int where);
+
+/* Advance nsteps DD-TR steps, asynchronously on the context's stream.
+ * Returns LBE_ERR_UNSTABLE if the context is poisoned by an earlier
+ * instability; an instability met during these steps is reported by the
+ * next lbe_diagnostics or getter. */
+lbe_status lbe_step(lbe_ctx *ctx, int nsteps);
+
+/* n^a = sum_p f~_p (Sec. 4.2), N values. */
+lbe_status lbe_get_density(lbe_ctx *ctx, int species, double *out, int where);
+
+/* u^a = J^a/n^a after the inversion (including the half-step force term),
+ * or the barycentric u = sum_a J^a / sum_a n^a for species = -1; 3N values,
+ * zero on solid nodes. */
+lbe_status lbe_get_velocity(lbe_ctx *ctx, int species, double *out, int where);
+
+/* C^mf (which = 0) or C^visc (which = 1) of one species at the current
+ * state, 3N values. */
+lbe_status lbe_get_force(lbe_ctx *ctx, int species, int which, double *out,
+                         int where);
+
+/* Post-streaming populations f~ (dist = 0) or g~ (dist = 1) of one species,
+ * 19N values in the context's storage precision (double or float). */
+lbe_status lbe_get_populations(lbe_ctx *ctx, int species, int dist, void *out,
+                               int where);
+lbe_status lbe_set_populations(lbe_ctx *ctx, int species, int dist,
+                               const void *in, int where);
+
+/* Mass, g-momentum, spurious-current and Sec. 4.1 error measures of the
+ * current state; synchronises. */
+lbe_status lbe_diagnostics(lbe_ctx *ctx, lbe_diag *out);
+
+/* Block until all work queued by the context has finished. */
+lbe_status lbe_synchronize(lbe_ctx *ctx);
+
+/* Thread-local text of the last failure (never NULL). */
+const char *lbe_last_error(void);
+
+/* Release the context (never frees the caller's workspace). */
+void lbe_destroy(lbe_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,135 @@
+/*
+ * lbe_oracle.h -- plain FP64 CPU oracle of the stabilized Lattice
+ * Boltzmann-Enskog step (double distribution, trapezoidal rule; Melchionna
+ * and Marini Bettolo Marconi, arXiv:1202.3842).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library
+ * against the paper.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load it; the product path never does.
+ * It shares no source, header, table or helper with the GPU library: the
+ * configuration struct below is laid out like the GPU library's on purpose
+ * so one Python harness can drive both, but it is declared independently.
+ *
+ * Everything is host memory, FP64, written for readability rather than
+ * speed: explicit loops in the paper's notation, modular index arithmetic,
+ * no blocking or fusion.  Loops over lattice nodes may run under OpenMP;
+ * every reduction is evaluated in a fixed order so results do not depend on
+ * the thread count.
+ *
+ * Node index: idx = x + nx*(y + ny*z).  Population arrays are
+ * [19][N] per species and distribution (SoA), velocities are [3][N].
+ * The stored state is the post-streaming transformed populations
+ * f~ and g~ of Sec. 3 eq. (invertpops), i.e. the state at the start of a
+ * step.
+ */
+#ifndef LBE_ORACLE_H
+#define LBE_ORACLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbeo_ctx lbeo_ctx;
+
+enum {
+  LBEO_OK = 0,
+  LBEO_ERR_ARG = -1,
+  LBEO_ERR_STATE = -2,
+  LBEO_ERR_OOM = -3,
+  LBEO_ERR_UNSTABLE = -5,
+  LBEO_ERR_UNSUPPORTED = -6
+};
+
+/* Scheme switches (readings of the paper where it is ambiguous):
+ *  VISC         include the collisional viscous force C^visc (Appendix,
+ *               eq. viscousforce) in S_f, S_g and J (Sec. 4.2).
+ *  PRINTED_INV  use the moment inversions as printed in Sec. 4.2
+ *               (Pi = Pi~ - beta/2 C^mf.u^a, J = J~ + 1/2 (C^mf+C^visc+nF))
+ *               instead of the ones derived from eq. (invertmoments).
+ *  KAPPA4       use the printed coefficient 4 on H2.u^a in the C^mf part of
+ *               S_g (Sec. 4.2, eq. kernel-g-1) instead of the projected 2.
+ *  IDEAL        switch the collisional kernel off (C = 0, Sec. 4.1).     */
+enum {
+  LBEO_VISC = 1u << 0,
+  LBEO_PRINTED_INV = 1u << 1,
+  LBEO_KAPPA4 = 1u << 2,
+  LBEO_IDEAL = 1u << 3
+};
+
+typedef struct {
+  int nx, ny, nz;
+  unsigned periodic;   /* bit0 = x, bit1 = y, bit2 = z                      */
+  int nspecies;        /* M, 1..4                                            */
+  double sigma[4];     /* hard-sphere diameters, lattice units               */
+  double tau;          /* 1/omega of the BGK term, eq. (boltzoriginal)       */
+  double kT;           /* k_B T with m = 1; D3Q19 needs kT = v_T^2 = 1/3     */
+  int prec;            /* ignored: the oracle is FP64 throughout             */
+  unsigned flags;      /* LBEO_* switches above                              */
+} lbeo_config;
+
+typedef struct {
+  double mass[4];      /* sum over fluid nodes of n^a                        */
+  double gmom[3];      /* sum over species and nodes of J~^a (from g~)       */
+  double umax;         /* max |u| (barycentric, half-step corrected)         */
+  double err_n;        /* max |n - n_eq| / n_0, n_eq the ideal-gas profile   */
+  double err_u;        /* umax / v_T                                         */
+  double err_J;        /* max |J| / (n_0 v_T)                                */
+  int unstable;        /* 1 if a packing fraction >= 1 or a NaN was met      */
+} lbeo_diag;
+
+int  lbeo_create(const lbeo_config *cfg, lbeo_ctx **out);
+void lbeo_destroy(lbeo_ctx *ctx);
+const char *lbeo_last_error(void);
+void lbeo_set_threads(int nthreads);
+
+int lbeo_set_solid(lbeo_ctx *ctx, const uint8_t *mask);          /* N bytes */
+int lbeo_set_potential(lbeo_ctx *ctx, const double *V);          /* N       */
+int lbeo_set_body_force(lbeo_ctx *ctx, int species, const double g[3]);
+int lbeo_init_density(lbeo_ctx *ctx, int species, const double *n0);
+int lbeo_step(lbeo_ctx *ctx, int nsteps);
+int lbeo_get_density(lbeo_ctx *ctx, int species, double *out);   /* N       */
+int lbeo_get_velocity(lbeo_ctx *ctx, int species, double *out);  /* 3N, -1 = barycentric */
+int lbeo_get_populations(lbeo_ctx *ctx, int species, int dist, double *out); /* 19N */
+int lbeo_set_populations(lbeo_ctx *ctx, int species, int dist, const double *in);
+int lbeo_diagnostics(lbeo_ctx *ctx, lbeo_diag *out);
+
+/* ---- inspection entry points used by the pins ---------------------------- */
+/* C^mf and C^visc of one species at the current state (3N each). */
+int lbeo_get_forces(lbeo_ctx *ctx, int species, double *cmf, double *cvisc);
+/* contact value G_ab at every node for the current state (N). */
+int lbeo_get_contact(lbeo_ctx *ctx, int a, int b, double *G);
+/* weighted (ball-averaged) density of one species (N). */
+int lbeo_get_weighted_density(lbeo_ctx *ctx, int species, double *nbar);
+/* external force per particle F^a = -grad_h V + body force (3N). */
+int lbeo_get_external_force(lbeo_ctx *ctx, int species, double *F);
+/* one streaming pass of one species' post-collision array (19N -> 19N). */
+int lbeo_stream(lbeo_ctx *ctx, const double *post, double *out);
+
+/* lattice shell of radius sigma: fills up to maxpts offsets (3 ints each,
+ * the half shell S+ first, then the mirror images) and the uniform weight.
+ * Returns the full point count, or a negative status. */
+int lbeo_shell(double sigma, int maxpts, int *offs, double *weight);
+/* ball of radius sigma/2: returns the point count, fills up to maxpts. */
+int lbeo_ball(double sigma, int maxpts, int *offs);
+/* BMCSL contact value of pair (a,b) from the weighted densities nbar[M]. */
+double lbeo_bmcsl(int M, const double *sigma, const double *nbar, int a, int b);
+/* the D3Q19 velocity set: c[19][3], w[19], opp[19]. */
+void lbeo_d3q19(int *c, double *w, int *opp);
+
+/* One-node collision of all M species, given the post-streaming populations
+ * ft, gt ([M][19]), the nonlocal forces cmf, cvisc ([M][3]) and the external
+ * force per particle F ([M][3]).  Writes the post-collision populations
+ * fpost, gpost ([M][19]) and, if mom != NULL, per species
+ * {n, Pi, J[3], u^a[3]} followed by the barycentric u[3] (8M+3 doubles). */
+int lbeo_collide_node(int M, double tau, double kT, unsigned flags,
+                      const double *ft, const double *gt,
+                      const double *cmf, const double *cvisc, const double *F,
+                      double *fpost, double *gpost, double *mom);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,552 @@
+// lbe_api.hip -- host runtime behind the C ABI of include/lbe.h: context,
+// workspace carving, shell and ball tables, stepping and read-out.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "lbe_internal.hpp"
+
+using namespace lbe;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+lbe_status fail(lbe_status code, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(LBE_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+#define LAUNCH_CHECK()                                                             \
+  do {                                                                             \
+    hipError_t e_ = hipGetLastError();                                             \
+    if (e_ != hipSuccess)                                                          \
+      return fail(LBE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Lattice shell of radius s: points e != 0 with s - 1/2 <= |e| < s + 1/2,
+// the half with the first nonzero component positive, and the uniform
+// weight 4 pi s / sum_e |e| that makes the weighted first moment
+// (4 pi/3) s delta_ij (Appendix integral over the unit sphere).
+struct HostShell {
+  std::vector<int> e;  // 3 per point of S+
+  double weight = 0.0;
+  int maxc = 0;
+};
+
+HostShell make_shell(double s) {
+  HostShell h;
+  if (s < 0.5) return h;
+  int K = (int)ceil(s + 0.5);
+  double lo = s - 0.5, hi = s + 0.5;
+  double lo2 = lo * lo, hi2 = hi * hi;
+  double sumlen = 0.0;
+  // z-major order keeps neighbouring offsets close in memory
+  for (int z = -K; z <= K; ++z)
+    for (int y = -K; y <= K; ++y)
+      for (int x = -K; x <= K; ++x) {
+        int r2 = x * x + y * y + z * z;
+        if (r2 == 0 || (double)r2 < lo2 || (double)r2 >= hi2) continue;
+        sumlen += sqrt((double)r2);
+        bool plus = x != 0 ? x > 0 : (y != 0 ? y > 0 : z > 0);
+        if (!plus) continue;
+        h.e.push_back(x);
+        h.e.push_back(y);
+        h.e.push_back(z);
+        h.maxc = std::max(h.maxc, std::max(abs(x), std::max(abs(y), abs(z))));
+      }
+  h.weight = sumlen > 0 ? 4.0 * M_PI * s / sumlen : 0.0;
+  return h;
+}
+
+// averaging ball |d| <= sigma/2
+std::vector<int> make_ball(double sigma, int *maxc) {
+  std::vector<int> b;
+  double R = 0.5 * sigma;
+  int K = (int)floor(R);
+  *maxc = K;
+  for (int z = -K; z <= K; ++z)
+    for (int y = -K; y <= K; ++y)
+      for (int x = -K; x <= K; ++x)
+        if ((double)(x * x + y * y + z * z) <= R * R) {
+          b.push_back(x);
+          b.push_back(y);
+          b.push_back(z);
+        }
+  return b;
+}
+
+struct Plan {
+  Geom g;
+  int M = 0, npairs = 0;
+  long long Ns = 0;
+  size_t pop_bytes = 0;  // one ping-pong buffer
+  std::vector<HostShell> shells;
+  std::vector<std::vector<int>> balls;
+  int nshell = 0, nball = 0;
+  size_t off_flag = 0, off_result = 0, off_shell_off = 0, off_shell_e = 0, off_ball = 0,
+         off_bb = 0, off_V = 0, off_F = 0, off_solid = 0, off_pop0 = 0, off_pop1 = 0,
+         off_n = 0, off_G = 0, off_J = 0, off_read = 0, off_part = 0, total = 0;
+  int nblocks = 0;
+};
+
+lbe_status make_plan(const lbe_config *cfg, Plan &pl) {
+  if (!cfg) return fail(LBE_ERR_ARG, "null config");
+  if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1)
+    return fail(LBE_ERR_ARG, "box dimensions must be positive");
+  if ((long long)cfg->nx * cfg->ny * cfg->nz > 0x7fffffffLL)
+    return fail(LBE_ERR_UNSUPPORTED, "more than 2^31-1 nodes in one box");
+  if (cfg->nspecies < 1 || cfg->nspecies > MAXM) return fail(LBE_ERR_ARG, "nspecies must be 1..4");
+  if (!(cfg->tau > 0.0)) return fail(LBE_ERR_ARG, "tau must be positive");
+  if (fabs(cfg->kT - 1.0 / 3.0) > 1e-12)
+    return fail(LBE_ERR_ARG, "D3Q19 requires kT = v_T^2 = 1/3 (m = 1)");
+  if (cfg->prec != LBE_FP64 && cfg->prec != LBE_FP32_POP) return fail(LBE_ERR_ARG, "bad precision");
+  for (int a = 0; a < cfg->nspecies; ++a)
+    if (!(cfg->sigma[a] >= 0.0) || cfg->sigma[a] > 16.0)
+      return fail(LBE_ERR_ARG, "sigma must lie in [0, 16]");
+  pl.M = cfg->nspecies;
+  pl.npairs = pl.M * (pl.M + 1) / 2;
+  int R = 0;
+  pl.shells.clear();
+  pl.balls.clear();
+  pl.nshell = pl.nball = 0;
+  for (int a = 0; a < pl.M; ++a)
+    for (int b = a; b < pl.M; ++b) {
+      HostShell h = make_shell(0.5 * (cfg->sigma[a] + cfg->sigma[b]));
+      R = std::max(R, h.maxc);
+      pl.nshell += (int)h.e.size() / 3;
+      pl.shells.push_back(std::move(h));
+    }
+  for (int a = 0; a < pl.M; ++a) {
+    int mc = 0;
+    pl.balls.push_back(make_ball(cfg->sigma[a], &mc));
+    R = std::max(R, mc);
+    pl.nball += (int)pl.balls.back().size() / 3;
+  }
+  Geom &g = pl.g;
+  g.nx = cfg->nx;
+  g.ny = cfg->ny;
+  g.nz = cfg->nz;
+  g.N = cfg->nx * cfg->ny * cfg->nz;
+  g.R = R;
+  g.PX = g.nx + 2 * R;
+  g.PY = g.ny + 2 * R;
+  g.PZ = g.nz + 2 * R;
+  g.Np = (long long)g.PX * g.PY * g.PZ;
+  g.periodic = cfg->periodic & 7u;
+  if (((g.periodic & 1u) && g.nx < R) || ((g.periodic & 2u) && g.ny < R) ||
+      ((g.periodic & 4u) && g.nz < R))
+    return fail(LBE_ERR_ARG, "a periodic box edge is shorter than the interaction range %d", R);
+  pl.Ns = ((long long)g.N + 63) / 64 * 64;
+  size_t P = cfg->prec == LBE_FP64 ? 8 : 4;
+  pl.pop_bytes = (size_t)2 * pl.M * Q * pl.Ns * P;
+  bool visc = (cfg->flags & LBE_VISC) && !(cfg->flags & LBE_IDEAL);
+  pl.nblocks = diag_nblocks(g);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  pl.off_flag = take(64);
+  pl.off_result = take(sizeof(double) * 16);
+  pl.off_shell_off = take(sizeof(int) * std::max(pl.nshell, 1));
+  pl.off_shell_e = take(sizeof(double) * 3 * std::max(pl.nshell, 1));
+  pl.off_ball = take(sizeof(int) * std::max(pl.nball, 1));
+  pl.off_bb = take(sizeof(uint32_t) * g.N);
+  pl.off_V = take(sizeof(double) * g.N);
+  pl.off_F = take(sizeof(double) * 3 * g.N);
+  pl.off_solid = take(g.N);
+  pl.off_pop0 = take(pl.pop_bytes);
+  pl.off_pop1 = take(pl.pop_bytes);
+  pl.off_n = take(sizeof(double) * pl.M * g.Np);
+  pl.off_G = take(sizeof(double) * pl.npairs * g.Np);
+  pl.off_J = take(visc ? sizeof(double) * 3 * pl.M * g.Np : 0);
+  pl.off_read = take(sizeof(double) * (10 * pl.M + 9) * (size_t)g.N);
+  pl.off_part = take(sizeof(double) * DIAG_K * pl.nblocks);
+  pl.total = o;
+  return LBE_OK;
+}
+
+}  // namespace
+
+struct lbe_ctx {
+  lbe_config cfg;
+  Plan pl;
+  char *ws = nullptr;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int cur = 0;             // ping-pong buffer holding the current state
+  bool poisoned = false;
+  StepArgs args;
+  Readout rd;
+
+  template <typename T>
+  T *at(size_t off) const {
+    return reinterpret_cast<T *>(ws + off);
+  }
+  void *pop(int buf) const { return ws + (buf ? pl.off_pop1 : pl.off_pop0); }
+  size_t psize() const { return cfg.prec == LBE_FP64 ? 8 : 4; }
+  // one (dist, species) block of 19 populations in buffer buf
+  char *block(int buf, int dist, int s) const {
+    return (char *)pop(buf) + (size_t)(dist * pl.M + s) * Q * pl.Ns * psize();
+  }
+};
+
+extern "C" {
+
+const char *lbe_last_error(void) { return g_err; }
+
+size_t lbe_workspace_bytes(const lbe_config *cfg) {
+  Plan pl;
+  if (make_plan(cfg, pl) != LBE_OK) return 0;
+  return pl.total;
+}
+
+lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *stream, lbe_ctx **out) {
+  if (!out) return fail(LBE_ERR_ARG, "null output pointer");
+  *out = nullptr;
+  Plan pl;
+  lbe_status st = make_plan(cfg, pl);
+  if (st != LBE_OK) return st;
+  if (!ws) return fail(LBE_ERR_ARG, "null workspace");
+  if (((uintptr_t)ws & 255u) != 0) return fail(LBE_ERR_ARG, "workspace must be 256-byte aligned");
+  if (bytes < pl.total)
+    return fail(LBE_ERR_OOM, "workspace of %zu bytes, %zu needed", bytes, pl.total);
+  lbe_ctx *c = new (std::nothrow) lbe_ctx();
+  if (!c) return fail(LBE_ERR_OOM, "host allocation failed");
+  c->cfg = *cfg;
+  c->pl = std::move(pl);
+  c->ws = (char *)ws;
+  c->stream = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
+  const Plan &P = c->pl;
+  const Geom &g = P.g;
+  // tables
+  std::vector<int> soff;
+  std::vector<double> seh;
+  StepArgs &a = c->args;
+  memset(&a, 0, sizeof a);
+  a.g = g;
+  a.M = P.M;
+  a.flags = cfg->flags;
+  double omega = 1.0 / cfg->tau;
+  a.acoef = omega / (1.0 + 0.5 * omega);
+  a.bcoef = 1.0 / (1.0 + 0.5 * omega);
+  a.beta = 1.0 / cfg->kT;
+  a.kappa = (cfg->flags & LBE_KAPPA4) ? 4.0 : 2.0;
+  int k = 0;
+  for (int pa = 0; pa < P.M; ++pa)
+    for (int pb = pa; pb < P.M; ++pb, ++k) {
+      const HostShell &h = P.shells[k];
+      int idx = pair_index(P.M, pa, pb);
+      double sab = 0.5 * (cfg->sigma[pa] + cfg->sigma[pb]);
+      a.t.pair_start[idx] = (int)soff.size();
+      a.t.pair_nplus[idx] = (int)h.e.size() / 3;
+      a.t.pair_cmf[idx] = -cfg->kT * sab * sab * h.weight * 0.5;
+      a.t.pair_cvisc[idx] = 2.0 * sab * sab * sqrt(cfg->kT / M_PI) * h.weight * 0.5;
+      double ssum = cfg->sigma[pa] + cfg->sigma[pb];
+      a.t.pair_d[idx] = ssum > 0.0 ? cfg->sigma[pa] * cfg->sigma[pb] / ssum : 0.0;
+      for (size_t j = 0; j < h.e.size(); j += 3) {
+        int ex = h.e[j], ey = h.e[j + 1], ez = h.e[j + 2];
+        soff.push_back(ex + g.PX * (ey + g.PY * ez));
+        double len = sqrt((double)(ex * ex + ey * ey + ez * ez));
+        seh.push_back(ex / len);
+        seh.push_back(ey / len);
+        seh.push_back(ez / len);
+      }
+    }
+  std::vector<int> boff;
+  for (int s = 0; s < P.M; ++s) {
+    a.t.ball_start[s] = (int)boff.size();
+    const std::vector<int> &b = P.balls[s];
+    a.t.ball_n[s] = (int)b.size() / 3;
+    for (size_t j = 0; j < b.size(); j += 3) boff.push_back(b[j] + g.PX * (b[j + 1] + g.PY * b[j + 2]));
+    a.t.sigma[s] = cfg->sigma[s];
+  }
+  a.t.shell_off = c->at<int>(P.off_shell_off);
+  a.t.shell_ehat = c->at<double>(P.off_shell_e);
+  a.t.ball_off = c->at<int>(P.off_ball);
+  a.bb = c->at<uint32_t>(P.off_bb);
+  a.Fext = c->at<double>(P.off_F);
+  a.nfield = c->at<double>(P.off_n);
+  a.Gfield = c->at<double>(P.off_G);
+  a.Jfield = P.off_J ? c->at<double>(P.off_J) : nullptr;
+  if (!((cfg->flags & LBE_VISC) && !(cfg->flags & LBE_IDEAL))) a.Jfield = nullptr;
+  a.errflag = c->at<unsigned>(P.off_flag);
+  double *rb = c->at<double>(P.off_read);
+  size_t N = g.N;
+  int M = P.M;
+  c->rd.ua = rb;
+  c->rd.u = rb + 3 * M * N;
+  c->rd.cmf = c->rd.u + 3 * N;
+  c->rd.cvisc = c->rd.cmf + 3 * M * N;
+  c->rd.n = c->rd.cvisc + 3 * M * N;
+  c->rd.jt = c->rd.n + M * N;
+  c->rd.j = c->rd.jt + 3 * N;
+  hipStream_t s = c->stream;
+  lbe_status rs = LBE_OK;
+  auto upload = [&](size_t off, const void *src, size_t n) -> bool {
+    if (n == 0) return true;
+    return hipMemcpyAsync(c->ws + off, src, n, hipMemcpyHostToDevice, s) == hipSuccess;
+  };
+  if (hipMemsetAsync(c->ws, 0, P.total, s) != hipSuccess ||
+      !upload(P.off_shell_off, soff.data(), soff.size() * sizeof(int)) ||
+      !upload(P.off_shell_e, seh.data(), seh.size() * sizeof(double)) ||
+      !upload(P.off_ball, boff.data(), boff.size() * sizeof(int)))
+    rs = fail(LBE_ERR_HIP, "workspace initialisation failed");
+  if (rs == LBE_OK) {
+    // no solids: bounce-back only at non-periodic box faces
+    launch_bbmask(g, c->at<uint8_t>(P.off_solid), c->at<uint32_t>(P.off_bb), s);
+    launch_extforce(g, c->at<double>(P.off_V), c->at<double>(P.off_F), s);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      rs = fail(LBE_ERR_HIP, "set-up kernels failed");
+  }
+  if (rs != LBE_OK) {
+    delete c;
+    return rs;
+  }
+  *out = c;
+  g_err[0] = 0;
+  return LBE_OK;
+}
+
+void lbe_destroy(lbe_ctx *c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  delete c;
+}
+
+static lbe_status copy_in(lbe_ctx *c, void *dst, const void *src, size_t n, int where) {
+  if (!src) return fail(LBE_ERR_ARG, "null input");
+  if (where != LBE_HOST && where != LBE_DEVICE) return fail(LBE_ERR_ARG, "bad 'where'");
+  HIP_TRY(hipMemcpyAsync(dst, src, n, where == LBE_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                         c->stream));
+  if (where == LBE_HOST) HIP_TRY(hipStreamSynchronize(c->stream));  // host buffer may go away
+  return LBE_OK;
+}
+
+static lbe_status copy_out(lbe_ctx *c, void *dst, const void *src, size_t n, int where) {
+  if (!dst) return fail(LBE_ERR_ARG, "null output");
+  if (where != LBE_HOST && where != LBE_DEVICE) return fail(LBE_ERR_ARG, "bad 'where'");
+  HIP_TRY(hipMemcpyAsync(dst, src, n, where == LBE_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBE_OK;
+}
+
+lbe_status lbe_set_solid(lbe_ctx *c, const uint8_t *mask, int where) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  lbe_status st = copy_in(c, c->ws + c->pl.off_solid, mask, c->pl.g.N, where);
+  if (st != LBE_OK) return st;
+  launch_bbmask(c->pl.g, c->at<uint8_t>(c->pl.off_solid), c->at<uint32_t>(c->pl.off_bb), c->stream);
+  launch_zero_solid(c->pl.g, c->pl.M, c->cfg.prec, c->pop(c->cur), c->args.bb, c->pl.Ns, c->stream);
+  LAUNCH_CHECK();
+  return LBE_OK;
+}
+
+lbe_status lbe_set_potential(lbe_ctx *c, const double *V, int where) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  lbe_status st = copy_in(c, c->ws + c->pl.off_V, V, sizeof(double) * c->pl.g.N, where);
+  if (st != LBE_OK) return st;
+  launch_extforce(c->pl.g, c->at<double>(c->pl.off_V), c->at<double>(c->pl.off_F), c->stream);
+  LAUNCH_CHECK();
+  return LBE_OK;
+}
+
+lbe_status lbe_set_body_force(lbe_ctx *c, int species, const double gb[3]) {
+  if (!c || !gb) return fail(LBE_ERR_ARG, "null argument");
+  if (species < 0 || species >= c->pl.M) return fail(LBE_ERR_ARG, "bad species %d", species);
+  for (int k = 0; k < 3; ++k) c->args.body[species][k] = gb[k];
+  return LBE_OK;
+}
+
+static lbe_status clear_instability(lbe_ctx *c) {
+  HIP_TRY(hipMemsetAsync(c->args.errflag, 0, sizeof(unsigned), c->stream));
+  c->poisoned = false;
+  return LBE_OK;
+}
+
+lbe_status lbe_init_density(lbe_ctx *c, int species, const double *n0, int where) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  if (species < 0 || species >= c->pl.M) return fail(LBE_ERR_ARG, "bad species %d", species);
+  double *stage = c->at<double>(c->pl.off_read);
+  lbe_status st = copy_in(c, stage, n0, sizeof(double) * c->pl.g.N, where);
+  if (st != LBE_OK) return st;
+  for (int d = 0; d < 2; ++d)
+    launch_rest_equilibrium(c->pl.g, c->cfg.prec, c->args.bb, stage, c->block(c->cur, d, species),
+                            c->stream);
+  LAUNCH_CHECK();
+  return clear_instability(c);
+}
+
+static lbe_status enqueue_step(lbe_ctx *c) {
+  hipStream_t s = c->stream;
+  launch_moments(c->args, c->cfg.prec, c->pop(c->cur), s);
+  launch_contact(c->args, s);
+  launch_collide(c->args, c->cfg.prec, c->pop(c->cur), c->pop(c->cur ^ 1), s);
+  LAUNCH_CHECK();
+  c->cur ^= 1;
+  return LBE_OK;
+}
+
+lbe_status lbe_step(lbe_ctx *c, int nsteps) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  if (nsteps < 0) return fail(LBE_ERR_ARG, "nsteps < 0");
+  if (c->poisoned) return fail(LBE_ERR_UNSTABLE, "context is unstable; reinitialise the state");
+  for (int k = 0; k < nsteps; ++k) {
+    lbe_status st = enqueue_step(c);
+    if (st != LBE_OK) return st;
+  }
+  return LBE_OK;
+}
+
+// moments, contact values and the read-out pass of the current state;
+// returns whether the instability flag is set
+static lbe_status readout(lbe_ctx *c, bool *unstable) {
+  hipStream_t s = c->stream;
+  launch_moments(c->args, c->cfg.prec, c->pop(c->cur), s);
+  launch_contact(c->args, s);
+  launch_readout(c->args, c->cfg.prec, c->pop(c->cur), c->rd, s);
+  LAUNCH_CHECK();
+  unsigned flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, c->args.errflag, sizeof flag, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *unstable = flag != 0;
+  if (*unstable) c->poisoned = true;
+  return LBE_OK;
+}
+
+lbe_status lbe_get_density(lbe_ctx *c, int species, double *out, int where) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  if (species < 0 || species >= c->pl.M) return fail(LBE_ERR_ARG, "bad species %d", species);
+  bool bad = false;
+  lbe_status st = readout(c, &bad);
+  if (st != LBE_OK) return st;
+  size_t N = c->pl.g.N;
+  return copy_out(c, out, c->rd.n + species * N, sizeof(double) * N, where);
+}
+
+lbe_status lbe_get_velocity(lbe_ctx *c, int species, double *out, int where) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  if (species < -1 || species >= c->pl.M) return fail(LBE_ERR_ARG, "bad species %d", species);
+  bool bad = false;
+  lbe_status st = readout(c, &bad);
+  if (st != LBE_OK) return st;
+  size_t N = c->pl.g.N;
+  const double *src = species < 0 ? c->rd.u : c->rd.ua + 3 * species * N;
+  st = copy_out(c, out, src, sizeof(double) * 3 * N, where);
+  if (st != LBE_OK) return st;
+  return bad ? fail(LBE_ERR_UNSTABLE, "packing fraction >= 1 or non-finite density") : LBE_OK;
+}
+
+lbe_status lbe_get_force(lbe_ctx *c, int species, int which, double *out, int where) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  if (species < 0 || species >= c->pl.M || which < 0 || which > 1)
+    return fail(LBE_ERR_ARG, "bad species or force index");
+  bool bad = false;
+  lbe_status st = readout(c, &bad);
+  if (st != LBE_OK) return st;
+  size_t N = c->pl.g.N;
+  const double *src = (which == 0 ? c->rd.cmf : c->rd.cvisc) + 3 * species * N;
+  st = copy_out(c, out, src, sizeof(double) * 3 * N, where);
+  if (st != LBE_OK) return st;
+  return bad ? fail(LBE_ERR_UNSTABLE, "packing fraction >= 1 or non-finite density") : LBE_OK;
+}
+
+lbe_status lbe_get_populations(lbe_ctx *c, int species, int dist, void *out, int where) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  if (species < 0 || species >= c->pl.M || dist < 0 || dist > 1)
+    return fail(LBE_ERR_ARG, "bad species or distribution");
+  char *stage = c->block(c->cur ^ 1, dist, species);
+  launch_pull(c->pl.g, c->cfg.prec, c->args.bb, c->block(c->cur, dist, species), stage, c->stream);
+  LAUNCH_CHECK();
+  size_t N = c->pl.g.N, P = c->psize();
+  if (!out) return fail(LBE_ERR_ARG, "null output");
+  // rows are Ns apart in the stage; copy row by row to the packed 19N layout
+  for (int p = 0; p < Q; ++p) {
+    const char *src = stage + (size_t)p * c->pl.Ns * P;
+    char *dst = (char *)out + (size_t)p * N * P;
+    HIP_TRY(hipMemcpyAsync(dst, src, N * P,
+                           where == LBE_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, c->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBE_OK;
+}
+
+lbe_status lbe_set_populations(lbe_ctx *c, int species, int dist, const void *in, int where) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  if (species < 0 || species >= c->pl.M || dist < 0 || dist > 1)
+    return fail(LBE_ERR_ARG, "bad species or distribution");
+  if (!in) return fail(LBE_ERR_ARG, "null input");
+  if (where != LBE_HOST && where != LBE_DEVICE) return fail(LBE_ERR_ARG, "bad 'where'");
+  char *stage = c->block(c->cur ^ 1, dist, species);
+  size_t N = c->pl.g.N, P = c->psize();
+  for (int p = 0; p < Q; ++p)
+    HIP_TRY(hipMemcpyAsync(stage + (size_t)p * c->pl.Ns * P, (const char *)in + (size_t)p * N * P, N * P,
+                           where == LBE_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, c->stream));
+  if (where == LBE_HOST) HIP_TRY(hipStreamSynchronize(c->stream));
+  launch_unstream(c->pl.g, c->cfg.prec, c->args.bb, stage, c->block(c->cur, dist, species), c->stream);
+  LAUNCH_CHECK();
+  return clear_instability(c);
+}
+
+lbe_status lbe_diagnostics(lbe_ctx *c, lbe_diag *out) {
+  if (!c || !out) return fail(LBE_ERR_ARG, "null argument");
+  memset(out, 0, sizeof *out);
+  bool bad = false;
+  lbe_status st = readout(c, &bad);
+  if (st != LBE_OK) return st;
+  const Plan &P = c->pl;
+  hipStream_t s = c->stream;
+  double *part = c->at<double>(P.off_part);
+  double *res = c->at<double>(P.off_result);
+  const double *V = c->at<double>(P.off_V);
+  launch_diag_partials(P.g, P.M, c->args.bb, c->rd, V, c->args.beta, part, P.nblocks, s);
+  launch_diag_final(P.M, part, P.nblocks, res, s);
+  launch_diag_errn(P.g, P.M, c->args.bb, c->rd, V, c->args.beta, res, part, P.nblocks, s);
+  launch_diag_final(P.M, part, P.nblocks, res, s);
+  LAUNCH_CHECK();
+  double h[DIAG_K];
+  HIP_TRY(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double mtot = 0.0;
+  for (int a = 0; a < P.M; ++a) {
+    out->mass[a] = h[a];
+    mtot += h[a];
+  }
+  for (int k = 0; k < 3; ++k) out->gmom[k] = h[4 + k];
+  double nfl = h[10];
+  double n0 = nfl > 0 ? mtot / nfl : 0.0;
+  double vT = sqrt(c->cfg.kT);
+  out->umax = h[8];
+  out->err_u = h[8] / vT;
+  out->err_J = n0 > 0 ? h[9] / (n0 * vT) : 0.0;
+  out->err_n = n0 > 0 ? h[11] / n0 : 0.0;
+  out->unstable = bad ? 1 : 0;
+  return LBE_OK;
+}
+
+lbe_status lbe_synchronize(lbe_ctx *c) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return LBE_OK;
+}
+
+}  // extern "C"

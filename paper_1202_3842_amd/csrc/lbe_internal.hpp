@@ -1,0 +1,105 @@
+// lbe_internal.hpp -- parameter blocks shared by the gfx950 kernels and the
+// host runtime of the Lattice Boltzmann-Enskog library.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbe.h"
+
+namespace lbe {
+
+constexpr int Q = 19;
+constexpr int MAXM = LBE_MAX_SPECIES;
+constexpr int MAXPAIRS = MAXM * (MAXM + 1) / 2;
+
+// index of the unordered species pair (a, b) among the M(M+1)/2 pairs
+__host__ __device__ constexpr int pair_index(int M, int a, int b) {
+  return a <= b ? a * M - a * (a - 1) / 2 + (b - a)
+                : b * M - b * (b - 1) / 2 + (a - b);
+}
+
+// Lattice geometry.  Populations and node-local arrays use the compact
+// index i = x + nx*(y + ny*z).  The gathered scalar fields (densities,
+// contact values, currents) live on a padded box with R ghost layers per
+// side, filled with periodic images or zeros, so a shell or ball offset is
+// one constant added to the padded index.
+struct Geom {
+  int nx, ny, nz;
+  int N;            // nx*ny*nz
+  int R;            // ghost layers
+  int PX, PY, PZ;   // padded extents
+  long long Np;     // padded node count
+  unsigned periodic;
+};
+
+__host__ __device__ inline long long padded_index(const Geom &g, int x, int y, int z) {
+  return (long long)(x + g.R) + (long long)g.PX * ((long long)(y + g.R) + (long long)g.PY * (z + g.R));
+}
+
+// Tables of the pair shells (half shells S+, as padded linear offsets and
+// unit vectors) and of the averaging balls.
+struct Tables {
+  const int *shell_off;       // all pairs' S+ offsets, concatenated
+  const double *shell_ehat;   // 3 doubles per offset
+  int pair_start[MAXPAIRS];
+  int pair_nplus[MAXPAIRS];
+  double pair_cmf[MAXPAIRS];   // -kT sigma_ab^2 w_ab / 2
+  double pair_cvisc[MAXPAIRS]; //  2 sigma_ab^2 sqrt(kT/pi) w_ab / 2
+  double pair_d[MAXPAIRS];     // sigma_a sigma_b / (sigma_a + sigma_b)
+  const int *ball_off;        // all species' balls, concatenated
+  int ball_start[MAXM];
+  int ball_n[MAXM];
+  double sigma[MAXM];
+};
+
+struct StepArgs {
+  Geom g;
+  int M;
+  unsigned flags;
+  double acoef, bcoef;   // omega h/(1+omega h/2), h/(1+omega h/2)
+  double beta;           // 1/kT
+  double kappa;          // coefficient on H2.u^a in the C^mf part of S_g
+  const uint32_t *bb;    // bit 0: node solid; bit p: r - c_p blocked
+  const double *Fext;    // 3N: -grad_h V
+  double body[MAXM][3];
+  double *nfield;        // M * Np
+  double *Gfield;        // npairs * Np
+  double *Jfield;        // 3M * Np (only with LBE_VISC)
+  Tables t;
+  unsigned *errflag;     // bit 0: packing fraction >= 1 or NaN
+};
+
+// Per-node outputs of the read-out pass (component-major, N each):
+//   ua[M][3], u[3], cmf[M][3], cvisc[M][3], n[M], Jt_sum[3], J_sum[3]
+struct Readout {
+  double *ua, *u, *cmf, *cvisc, *n, *jt, *j;
+};
+
+// Launchers (lbe_kernels.hip)
+void launch_bbmask(const Geom &g, const uint8_t *solid, uint32_t *bb, hipStream_t s);
+void launch_extforce(const Geom &g, const double *V, double *F, hipStream_t s);
+void launch_zero_solid(const Geom &g, int M, int prec, void *pop, const uint32_t *bb,
+                       long long stride, hipStream_t s);
+void launch_moments(const StepArgs &a, int prec, const void *pop, hipStream_t s);
+void launch_contact(const StepArgs &a, hipStream_t s);
+void launch_collide(const StepArgs &a, int prec, const void *pin, void *pout, hipStream_t s);
+void launch_readout(const StepArgs &a, int prec, const void *pin, const Readout &r, hipStream_t s);
+void launch_unstream(const Geom &g, int prec, const uint32_t *bb, const void *target_post,
+                     void *pop_post_stream, hipStream_t s);
+void launch_pull(const Geom &g, int prec, const uint32_t *bb, const void *pop_pre,
+                 void *out_post, hipStream_t s);
+void launch_rest_equilibrium(const Geom &g, int prec, const uint32_t *bb, const double *n0,
+                             void *out, hipStream_t s);
+void launch_diag_partials(const Geom &g, int M, const uint32_t *bb, const Readout &r,
+                          const double *V, double beta, double *partials, int nblocks,
+                          hipStream_t s);
+void launch_diag_final(int M, const double *partials, int nblocks, double *result, hipStream_t s);
+// overwrites slot 11 of each block's partials with max |n - n_eq|
+void launch_diag_errn(const Geom &g, int M, const uint32_t *bb, const Readout &r,
+                      const double *V, double beta, const double *result, double *partials,
+                      int nblocks, hipStream_t s);
+int diag_nblocks(const Geom &g);
+constexpr int DIAG_K = 12;  // reduced quantities per block
+
+}  // namespace lbe

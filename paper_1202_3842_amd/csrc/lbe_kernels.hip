@@ -1,0 +1,841 @@
+// lbe_kernels.hip -- gfx950 kernels of one stabilized Lattice Boltzmann-Enskog
+// step (double distribution, trapezoidal rule; arXiv:1202.3842).
+//
+// Data layout in HBM
+//   populations  pop[dist][species][p][Ns]  (dist 0 = f~, 1 = g~), FP64 or
+//                FP32, two ping-pong buffers.  A buffer holds the
+//                post-collision, pre-streaming values; streaming happens in
+//                the pull that the next pass performs.
+//   fields       padded boxes (R ghost layers) of n^a, G_ab and J~^a, with
+//                periodic images in the ghosts (zeros beyond walls), so that
+//                shell and ball gathers are constant offsets.
+//
+// Kernels per step
+//   k_moments  pull populations, n~ (and J~ with C^visc), write fields
+//   k_contact  ball-averaged densities -> BMCSL contact values G_ab
+//   k_collide  shell gather of C^mf (and C^visc), pull, inversion,
+//              equilibria, sources, trapezoidal BGK update, store
+#include <math.h>
+
+#include "lbe_internal.hpp"
+
+namespace lbe {
+namespace {
+
+constexpr int BLOCK = 256;
+
+// D3Q19 velocities (order documented in lbe.h) and weights
+__host__ __device__ constexpr int cvec(int p, int k) {
+  constexpr int c[19][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+                            {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                            {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                            {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+  return c[p][k];
+}
+__host__ __device__ constexpr int opp(int p) { return p == 0 ? 0 : ((p & 1) ? p + 1 : p - 1); }
+__host__ __device__ constexpr double wgt(int p) {
+  return p == 0 ? 1.0 / 3.0 : (p <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+template <typename T>
+__device__ inline double ld(const T *__restrict__ a, long long i) {
+  return (double)a[i];
+}
+
+struct Coord {
+  int x, y, z;
+  int xm, xp, ym, yp, zm, zp;
+};
+
+__device__ inline Coord decode(const Geom &g, int i) {
+  Coord c;
+  c.x = i % g.nx;
+  int t = i / g.nx;
+  c.y = t % g.ny;
+  c.z = t / g.ny;
+  c.xm = c.x == 0 ? g.nx - 1 : c.x - 1;
+  c.xp = c.x == g.nx - 1 ? 0 : c.x + 1;
+  c.ym = c.y == 0 ? g.ny - 1 : c.y - 1;
+  c.yp = c.y == g.ny - 1 ? 0 : c.y + 1;
+  c.zm = c.z == 0 ? g.nz - 1 : c.z - 1;
+  c.zp = c.z == g.nz - 1 ? 0 : c.z + 1;
+  return c;
+}
+
+// node r - c_p (wrapped; blocked neighbours are excluded by the bb mask)
+__device__ inline int upstream(const Geom &g, const Coord &c, int p) {
+  int X = cvec(p, 0) > 0 ? c.xm : (cvec(p, 0) < 0 ? c.xp : c.x);
+  int Y = cvec(p, 1) > 0 ? c.ym : (cvec(p, 1) < 0 ? c.yp : c.y);
+  int Z = cvec(p, 2) > 0 ? c.zm : (cvec(p, 2) < 0 ? c.zp : c.z);
+  return X + g.nx * (Y + g.ny * Z);
+}
+// node r + c_p
+__device__ inline int downstream(const Geom &g, const Coord &c, int p) {
+  int X = cvec(p, 0) > 0 ? c.xp : (cvec(p, 0) < 0 ? c.xm : c.x);
+  int Y = cvec(p, 1) > 0 ? c.yp : (cvec(p, 1) < 0 ? c.ym : c.y);
+  int Z = cvec(p, 2) > 0 ? c.zp : (cvec(p, 2) < 0 ? c.zm : c.z);
+  return X + g.nx * (Y + g.ny * Z);
+}
+
+// Pull the 19 post-streaming populations of one (dist, species) block:
+// f~_p(r) = f~*_p(r - c_p), or f~*_opp(p)(r) when r - c_p is blocked.
+template <typename T>
+__device__ inline void pull19(const Geom &g, const Coord &c, int i, uint32_t m,
+                              const T *__restrict__ blk, long long Ns, double v[19]) {
+#pragma unroll
+  for (int p = 0; p < Q; ++p) {
+    if (p == 0) {
+      v[0] = ld(blk, i);
+    } else if ((m >> p) & 1u) {
+      v[p] = ld(blk, (long long)opp(p) * Ns + i);
+    } else {
+      v[p] = ld(blk, (long long)p * Ns + upstream(g, c, p));
+    }
+  }
+}
+
+__device__ inline void moments0(const double v[19], double &s) {
+  double a = 0.0;
+#pragma unroll
+  for (int p = 0; p < Q; ++p) a += v[p];
+  s = a;
+}
+
+// J = sum_p c_p g_p, summed over +-c pairs so a mirror-symmetric node gives 0
+__device__ inline void moments1(const double v[19], double J[3]) {
+  double jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+  for (int p = 1; p < Q; p += 2) {
+    double d = v[p] - v[p + 1];
+    if (cvec(p, 0) > 0) jx += d;
+    if (cvec(p, 0) < 0) jx -= d;
+    if (cvec(p, 1) > 0) jy += d;
+    if (cvec(p, 1) < 0) jy -= d;
+    if (cvec(p, 2) > 0) jz += d;
+    if (cvec(p, 2) < 0) jz -= d;
+  }
+  J[0] = jx;
+  J[1] = jy;
+  J[2] = jz;
+}
+
+// periodic images of coordinate x in [-R, n+R)
+__device__ inline int images(int x, int n, int R, bool per, int out[3]) {
+  int k = 0;
+  out[k++] = x;
+  if (per) {
+    if (x - n >= -R) out[k++] = x - n;
+    if (x + n < n + R) out[k++] = x + n;
+  }
+  return k;
+}
+
+__device__ inline void store_images(const Geom &g, double *__restrict__ f, const Coord &c,
+                                    double v) {
+  int xs[3], ys[3], zs[3];
+  int kx = images(c.x, g.nx, g.R, g.periodic & 1u, xs);
+  int ky = images(c.y, g.ny, g.R, g.periodic & 2u, ys);
+  int kz = images(c.z, g.nz, g.R, g.periodic & 4u, zs);
+  for (int a = 0; a < kz; ++a)
+    for (int b = 0; b < ky; ++b)
+      for (int d = 0; d < kx; ++d) f[padded_index(g, xs[d], ys[b], zs[a])] = v;
+}
+
+__device__ inline long long pop_stride(const Geom &g) { return ((long long)g.N + 63) / 64 * 64; }
+
+// ------------------------------------------------------------------------
+// set-up kernels
+// ------------------------------------------------------------------------
+__global__ void k_bbmask(Geom g, const uint8_t *__restrict__ solid, uint32_t *__restrict__ bb) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  Coord c = decode(g, i);
+  uint32_t m = solid[i] ? 1u : 0u;
+#pragma unroll
+  for (int p = 1; p < Q; ++p) {
+    int X = c.x - cvec(p, 0), Y = c.y - cvec(p, 1), Z = c.z - cvec(p, 2);
+    bool out = false;
+    if (X < 0 || X >= g.nx) out |= !(g.periodic & 1u);
+    if (Y < 0 || Y >= g.ny) out |= !(g.periodic & 2u);
+    if (Z < 0 || Z >= g.nz) out |= !(g.periodic & 4u);
+    if (!out) out = solid[upstream(g, c, p)] != 0;
+    if (out) m |= 1u << p;
+  }
+  bb[i] = m;
+}
+
+// F = -grad_h V = -(1/v_T^2) sum_p w_p c_p V(r + c_p); clamp at walls
+__global__ void k_extforce(Geom g, const double *__restrict__ V, double *__restrict__ F) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  Coord c = decode(g, i);
+  double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+  for (int p = 1; p < Q; ++p) {
+    int X = c.x + cvec(p, 0), Y = c.y + cvec(p, 1), Z = c.z + cvec(p, 2);
+    X = X < 0 ? ((g.periodic & 1u) ? X + g.nx : 0) : (X >= g.nx ? ((g.periodic & 1u) ? X - g.nx : g.nx - 1) : X);
+    Y = Y < 0 ? ((g.periodic & 2u) ? Y + g.ny : 0) : (Y >= g.ny ? ((g.periodic & 2u) ? Y - g.ny : g.ny - 1) : Y);
+    Z = Z < 0 ? ((g.periodic & 4u) ? Z + g.nz : 0) : (Z >= g.nz ? ((g.periodic & 4u) ? Z - g.nz : g.nz - 1) : Z);
+    double v = wgt(p) * V[X + g.nx * (Y + g.ny * Z)];
+    if (cvec(p, 0)) gx += cvec(p, 0) * v;
+    if (cvec(p, 1)) gy += cvec(p, 1) * v;
+    if (cvec(p, 2)) gz += cvec(p, 2) * v;
+  }
+  // 1/v_T^2 = 3 for D3Q19
+  F[i] = -3.0 * gx;
+  F[g.N + i] = -3.0 * gy;
+  F[2 * g.N + i] = -3.0 * gz;
+}
+
+template <typename T>
+__global__ void k_zero_solid(Geom g, int nblk, T *__restrict__ pop, const uint32_t *__restrict__ bb,
+                             long long Ns) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N || !(bb[i] & 1u)) return;
+  for (int k = 0; k < nblk * Q; ++k) pop[(long long)k * Ns + i] = T(0);
+}
+
+// Pre-streaming values whose pull gives the rest equilibrium w_p n0(r):
+// slot (s, q) streams to s + c_q, or back to (s, opp q) at a wall.
+template <typename T>
+__global__ void k_rest_equilibrium(Geom g, const uint32_t *__restrict__ bb,
+                                   const double *__restrict__ n0, T *__restrict__ out, long long Ns) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  uint32_t m = bb[i];
+  Coord c = decode(g, i);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    double v = 0.0;
+    if (!(m & 1u)) {
+      if (q == 0 || ((m >> opp(q)) & 1u))
+        v = wgt(q) * n0[i];
+      else
+        v = wgt(q) * n0[downstream(g, c, q)];
+    }
+    out[(long long)q * Ns + i] = T(v);
+  }
+}
+
+// inverse of the pull: pre-streaming values from post-streaming targets
+template <typename T>
+__global__ void k_unstream(Geom g, const uint32_t *__restrict__ bb, const T *__restrict__ target,
+                           T *__restrict__ out, long long Ns) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  uint32_t m = bb[i];
+  Coord c = decode(g, i);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    T v = T(0);
+    if (!(m & 1u)) {
+      if (q == 0)
+        v = target[i];
+      else if ((m >> opp(q)) & 1u)
+        v = target[(long long)opp(q) * Ns + i];
+      else
+        v = target[(long long)q * Ns + downstream(g, c, q)];
+    }
+    out[(long long)q * Ns + i] = v;
+  }
+}
+
+template <typename T>
+__global__ void k_pull(Geom g, const uint32_t *__restrict__ bb, const T *__restrict__ pre,
+                       T *__restrict__ out, long long Ns) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  uint32_t m = bb[i];
+  Coord c = decode(g, i);
+#pragma unroll
+  for (int p = 0; p < Q; ++p) {
+    T v = T(0);
+    if (!(m & 1u)) {
+      if (p == 0)
+        v = pre[i];
+      else if ((m >> p) & 1u)
+        v = pre[(long long)opp(p) * Ns + i];
+      else
+        v = pre[(long long)p * Ns + upstream(g, c, p)];
+    }
+    out[(long long)p * Ns + i] = v;
+  }
+}
+
+// ------------------------------------------------------------------------
+// step kernels
+// ------------------------------------------------------------------------
+template <typename T, bool VISC>
+__global__ __launch_bounds__(BLOCK) void k_moments(StepArgs a, const T *__restrict__ pop) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const Geom &g = a.g;
+  if (i >= g.N) return;
+  Coord c = decode(g, i);
+  uint32_t m = a.bb[i];
+  long long Ns = pop_stride(g);
+  for (int s = 0; s < a.M; ++s) {
+    double n = 0.0, J[3] = {0.0, 0.0, 0.0};
+    if (!(m & 1u)) {
+      double v[19];
+      pull19(g, c, i, m, pop + (long long)s * Q * Ns, Ns, v);
+      moments0(v, n);
+      if (VISC) {
+        pull19(g, c, i, m, pop + (long long)(a.M + s) * Q * Ns, Ns, v);
+        moments1(v, J);
+      }
+    }
+    store_images(g, a.nfield + (long long)s * g.Np, c, n);
+    if (VISC)
+      for (int k = 0; k < 3; ++k) store_images(g, a.Jfield + (long long)(3 * s + k) * g.Np, c, J[k]);
+  }
+}
+
+// Weighted densities (ball of radius sigma_b/2, normalised by its size) and
+// the BMCSL contact values G_ab(r) of every pair.
+template <int M>
+__global__ __launch_bounds__(BLOCK) void k_contact(StepArgs a) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const Geom &g = a.g;
+  if (i >= g.N) return;
+  Coord c = decode(g, i);
+  constexpr int NP = M * (M + 1) / 2;
+  double G[NP];
+  if (a.bb[i] & 1u) {
+    for (int k = 0; k < NP; ++k) G[k] = 0.0;
+  } else {
+    long long P = padded_index(g, c.x, c.y, c.z);
+    double xi2 = 0.0, xi3 = 0.0;
+    bool finite = true;
+    for (int b = 0; b < M; ++b) {
+      const double *nb = a.nfield + (long long)b * g.Np + P;
+      const int *off = a.t.ball_off + a.t.ball_start[b];
+      int cnt = a.t.ball_n[b];
+      double s = 0.0;
+      for (int j = 0; j < cnt; ++j) s += nb[off[j]];
+      double nbar = s / (double)cnt;
+      finite &= isfinite(nbar);
+      double sg = a.t.sigma[b];
+      xi2 += sg * sg * nbar;
+      xi3 += sg * sg * sg * nbar;
+    }
+    xi2 *= M_PI / 6.0;
+    xi3 *= M_PI / 6.0;
+    if (!(xi3 < 1.0) || !finite) atomicOr(a.errflag, 1u);
+    double one = 1.0 - xi3;
+    double i1 = 1.0 / one;
+    double i2 = i1 * i1;
+    double i3 = i2 * i1;
+    for (int pa = 0; pa < M; ++pa)
+      for (int pb = pa; pb < M; ++pb) {
+        int k = pair_index(M, pa, pb);
+        double d = a.t.pair_d[k];
+        G[k] = i1 + 3.0 * d * xi2 * i2 + 2.0 * d * d * xi2 * xi2 * i3;
+      }
+  }
+  for (int k = 0; k < NP; ++k) store_images(g, a.Gfield + (long long)k * g.Np, c, G[k]);
+}
+
+// Nonlocal forces at padded index P on the tilde moments:
+//   C^mf_a  = -kT n_a sum_b sigma_ab^2 w_ab sum_{e in S+} e^ [g(r,r+e) n_b(r+e)
+//                                                     - g(r,r-e) n_b(r-e)]
+//   C^visc_a = n_a sum_b 2 sigma_ab^2 sqrt(kT/pi) w_ab sum_e e^ (e^.(u_b(r+e)
+//                                              - u_b(r))) g(r,r+e) n_b(r+e)
+// with g(r,q) = (G(r) + G(q))/2 and n_b u_b = J~_b taken from the field.
+template <int M, bool VISC>
+__device__ inline void gather_forces(const StepArgs &a, long long P, double cmf[M][3],
+                                     double cvisc[M][3]) {
+  const Geom &g = a.g;
+  for (int s = 0; s < M; ++s)
+    for (int k = 0; k < 3; ++k) cmf[s][k] = cvisc[s][k] = 0.0;
+  if (a.flags & LBE_IDEAL) return;
+  for (int s = 0; s < M; ++s) {
+    double ns = a.nfield[(long long)s * g.Np + P];
+    for (int b = 0; b < M; ++b) {
+      int k = pair_index(M, s, b);
+      int np = a.t.pair_nplus[k];
+      if (np == 0) continue;
+      const double *nb = a.nfield + (long long)b * g.Np + P;
+      const double *Gb = a.Gfield + (long long)k * g.Np + P;
+      const int *off = a.t.shell_off + a.t.pair_start[k];
+      const double *eh = a.t.shell_ehat + 3LL * a.t.pair_start[k];
+      double G0 = Gb[0];
+      double mx = 0.0, my = 0.0, mz = 0.0;
+      double vx = 0.0, vy = 0.0, vz = 0.0;
+      double u0x = 0.0, u0y = 0.0, u0z = 0.0;
+      const double *Jx = nullptr, *Jy = nullptr, *Jz = nullptr;
+      if (VISC) {
+        Jx = a.Jfield + (long long)(3 * b) * g.Np + P;
+        Jy = Jx + g.Np;
+        Jz = Jy + g.Np;
+        double n0 = nb[0];
+        if (n0 != 0.0) {
+          u0x = Jx[0] / n0;
+          u0y = Jy[0] / n0;
+          u0z = Jz[0] / n0;
+        }
+      }
+      for (int j = 0; j < np; ++j) {
+        int o = off[j];
+        double ex = eh[3 * j], ey = eh[3 * j + 1], ez = eh[3 * j + 2];
+        double npl = nb[o], nmi = nb[-o];
+        double gp = G0 + Gb[o], gm = G0 + Gb[-o];
+        double d = gp * npl - gm * nmi;
+        mx += ex * d;
+        my += ey * d;
+        mz += ez * d;
+        if (VISC) {
+          double eu = ex * u0x + ey * u0y + ez * u0z;
+          double tp = gp * (ex * Jx[o] + ey * Jy[o] + ez * Jz[o] - eu * npl);
+          double tm = gm * (ex * Jx[-o] + ey * Jy[-o] + ez * Jz[-o] - eu * nmi);
+          double t = tp + tm;
+          vx += ex * t;
+          vy += ey * t;
+          vz += ez * t;
+        }
+      }
+      double cm = a.t.pair_cmf[k] * ns;
+      cmf[s][0] += cm * mx;
+      cmf[s][1] += cm * my;
+      cmf[s][2] += cm * mz;
+      if (VISC) {
+        double cv = a.t.pair_cvisc[k] * ns;
+        cvisc[s][0] += cv * vx;
+        cvisc[s][1] += cv * vy;
+        cvisc[s][2] += cv * vz;
+      }
+    }
+  }
+}
+
+// Inversions, equilibria, sources and the trapezoidal update of one node.
+//  J = J~ + Y/2 (or + X/2 printed), u^a = J/n,
+//  Pi = Pi~ + (beta/2) C^mf.u^a (or - printed), u = sum J / sum n,
+//  f_eq = w [n + 3 c.J + 4.5 n (2 (c.u^a)(c.u) - (c.u)^2) - 1.5 n (2 u^a.u - u.u)]
+//  g_eq = f_eq + w (Pi - n)
+//  S_f  = w [3 c.X + 9 (c.X)(c.u^a) - 3 X.u^a]
+//  S_g  = w [4.5 kappa (c.C)(c.u^a) + (3 - 1.5 kappa) C.u^a
+//            + 3 c.Y + 9 (c.Y)(c.u^a) - 3 Y.u^a]
+//  out  = (1 - a) in + a eq + b S
+template <int M>
+struct NodeMoments {
+  double n[M], Pi[M], J[M][3], ua[M][3], X[M][3], Y[M][3];
+  double u[3];
+};
+
+template <int M>
+__device__ inline void invert(const StepArgs &a, const double ft[M][19], const double gt[M][19],
+                              const double cmf[M][3], const double cvisc[M][3], int i,
+                              NodeMoments<M> &nm) {
+  const bool printed = a.flags & LBE_PRINTED_INV;
+  double ntot = 0.0, Jt0 = 0.0, Jt1 = 0.0, Jt2 = 0.0;
+  for (int s = 0; s < M; ++s) {
+    double n, Pit, Jt[3];
+    moments0(ft[s], n);
+    moments0(gt[s], Pit);
+    moments1(gt[s], Jt);
+    double cu = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      double F = a.Fext[(long long)k * a.g.N + i] + a.body[s][k];
+      double nF = n * F;
+      nm.X[s][k] = cmf[s][k] + cvisc[s][k] + nF;
+      nm.Y[s][k] = cvisc[s][k] + nF;
+      nm.J[s][k] = Jt[k] + 0.5 * (printed ? nm.X[s][k] : nm.Y[s][k]);
+      nm.ua[s][k] = n != 0.0 ? nm.J[s][k] / n : 0.0;
+      cu += cmf[s][k] * nm.ua[s][k];
+    }
+    nm.n[s] = n;
+    nm.Pi[s] = printed ? Pit - 0.5 * a.beta * cu : Pit + 0.5 * a.beta * cu;
+    ntot += n;
+    Jt0 += nm.J[s][0];
+    Jt1 += nm.J[s][1];
+    Jt2 += nm.J[s][2];
+  }
+  nm.u[0] = ntot != 0.0 ? Jt0 / ntot : 0.0;
+  nm.u[1] = ntot != 0.0 ? Jt1 / ntot : 0.0;
+  nm.u[2] = ntot != 0.0 ? Jt2 / ntot : 0.0;
+}
+
+template <int p>
+__device__ inline double cdot(const double v[3]) {
+  double r = 0.0;
+  if (cvec(p, 0) > 0) r += v[0];
+  if (cvec(p, 0) < 0) r -= v[0];
+  if (cvec(p, 1) > 0) r += v[1];
+  if (cvec(p, 1) < 0) r -= v[1];
+  if (cvec(p, 2) > 0) r += v[2];
+  if (cvec(p, 2) < 0) r -= v[2];
+  return r;
+}
+
+template <int p>
+struct CollideP {
+  template <typename T, int M>
+  __device__ static inline void run(const StepArgs &a, int s, const NodeMoments<M> &nm,
+                                    const double cm[3], const double ft, const double gt,
+                                    T *__restrict__ fo, T *__restrict__ go) {
+    const double w = wgt(p);
+    const double n = nm.n[s];
+    const double cJ = cdot<p>(nm.J[s]);
+    const double cua = cdot<p>(nm.ua[s]);
+    const double cu = cdot<p>(nm.u);
+    const double uau = nm.ua[s][0] * nm.u[0] + nm.ua[s][1] * nm.u[1] + nm.ua[s][2] * nm.u[2];
+    const double uu = nm.u[0] * nm.u[0] + nm.u[1] * nm.u[1] + nm.u[2] * nm.u[2];
+    const double feq = w * (n + 3.0 * cJ + 4.5 * n * (2.0 * cua * cu - cu * cu) -
+                            1.5 * n * (2.0 * uau - uu));
+    const double geq = feq + w * (nm.Pi[s] - n);
+    const double cX = cdot<p>(nm.X[s]);
+    const double Xua = nm.X[s][0] * nm.ua[s][0] + nm.X[s][1] * nm.ua[s][1] + nm.X[s][2] * nm.ua[s][2];
+    const double cY = cdot<p>(nm.Y[s]);
+    const double Yua = nm.Y[s][0] * nm.ua[s][0] + nm.Y[s][1] * nm.ua[s][1] + nm.Y[s][2] * nm.ua[s][2];
+    const double cC = cdot<p>(cm);
+    const double Cua = cm[0] * nm.ua[s][0] + cm[1] * nm.ua[s][1] + cm[2] * nm.ua[s][2];
+    const double Sf = w * (3.0 * cX + 9.0 * cX * cua - 3.0 * Xua);
+    const double Sg = w * (4.5 * a.kappa * cC * cua + (3.0 - 1.5 * a.kappa) * Cua + 3.0 * cY +
+                           9.0 * cY * cua - 3.0 * Yua);
+    *fo = T(ft + a.acoef * (feq - ft) + a.bcoef * Sf);
+    *go = T(gt + a.acoef * (geq - gt) + a.bcoef * Sg);
+  }
+};
+
+template <typename T, int M, int p>
+__device__ inline void collide_all_p(const StepArgs &a, int s, const NodeMoments<M> &nm,
+                                     const double cm[3], const double ft[19], const double gt[19],
+                                     T *__restrict__ fblk, T *__restrict__ gblk, long long Ns, int i) {
+  if constexpr (p < Q) {
+    CollideP<p>::template run<T, M>(a, s, nm, cm, ft[p], gt[p], fblk + (long long)p * Ns + i,
+                                    gblk + (long long)p * Ns + i);
+    collide_all_p<T, M, p + 1>(a, s, nm, cm, ft, gt, fblk, gblk, Ns, i);
+  }
+}
+
+template <typename T, int M, bool VISC>
+__global__ __launch_bounds__(BLOCK) void k_collide(StepArgs a, const T *__restrict__ pin,
+                                                   T *__restrict__ pout) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const Geom &g = a.g;
+  if (i >= g.N) return;
+  uint32_t m = a.bb[i];
+  if (m & 1u) return;  // solid slots are never read
+  Coord c = decode(g, i);
+  long long P = padded_index(g, c.x, c.y, c.z);
+  double cmf[M][3], cvisc[M][3];
+  gather_forces<M, VISC>(a, P, cmf, cvisc);
+  long long Ns = pop_stride(g);
+  double ft[M][19], gt[M][19];
+  for (int s = 0; s < M; ++s) {
+    pull19(g, c, i, m, pin + (long long)s * Q * Ns, Ns, ft[s]);
+    pull19(g, c, i, m, pin + (long long)(M + s) * Q * Ns, Ns, gt[s]);
+  }
+  NodeMoments<M> nm;
+  invert<M>(a, ft, gt, cmf, cvisc, i, nm);
+  for (int s = 0; s < M; ++s)
+    collide_all_p<T, M, 0>(a, s, nm, cmf[s], ft[s], gt[s], pout + (long long)s * Q * Ns,
+                           pout + (long long)(M + s) * Q * Ns, Ns, i);
+}
+
+template <typename T, int M, bool VISC>
+__global__ __launch_bounds__(BLOCK) void k_readout(StepArgs a, const T *__restrict__ pin, Readout r) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const Geom &g = a.g;
+  if (i >= g.N) return;
+  uint32_t m = a.bb[i];
+  const int N = g.N;
+  if (m & 1u) {
+    for (int s = 0; s < M; ++s) {
+      r.n[(long long)s * N + i] = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        r.ua[(long long)(3 * s + k) * N + i] = 0.0;
+        r.cmf[(long long)(3 * s + k) * N + i] = 0.0;
+        r.cvisc[(long long)(3 * s + k) * N + i] = 0.0;
+      }
+    }
+    for (int k = 0; k < 3; ++k) {
+      r.u[(long long)k * N + i] = 0.0;
+      r.jt[(long long)k * N + i] = 0.0;
+      r.j[(long long)k * N + i] = 0.0;
+    }
+    return;
+  }
+  Coord c = decode(g, i);
+  long long P = padded_index(g, c.x, c.y, c.z);
+  double cmf[M][3], cvisc[M][3];
+  gather_forces<M, VISC>(a, P, cmf, cvisc);
+  long long Ns = pop_stride(g);
+  double ft[M][19], gt[M][19];
+  for (int s = 0; s < M; ++s) {
+    pull19(g, c, i, m, pin + (long long)s * Q * Ns, Ns, ft[s]);
+    pull19(g, c, i, m, pin + (long long)(M + s) * Q * Ns, Ns, gt[s]);
+  }
+  NodeMoments<M> nm;
+  invert<M>(a, ft, gt, cmf, cvisc, i, nm);
+  double jt[3] = {0.0, 0.0, 0.0}, js[3] = {0.0, 0.0, 0.0};
+  for (int s = 0; s < M; ++s) {
+    double J1[3];
+    moments1(gt[s], J1);
+    r.n[(long long)s * N + i] = nm.n[s];
+    for (int k = 0; k < 3; ++k) {
+      r.ua[(long long)(3 * s + k) * N + i] = nm.ua[s][k];
+      r.cmf[(long long)(3 * s + k) * N + i] = cmf[s][k];
+      r.cvisc[(long long)(3 * s + k) * N + i] = cvisc[s][k];
+      jt[k] += J1[k];
+      js[k] += nm.J[s][k];
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    r.u[(long long)k * N + i] = nm.u[k];
+    r.jt[(long long)k * N + i] = jt[k];
+    r.j[(long long)k * N + i] = js[k];
+  }
+}
+
+// ------------------------------------------------------------------------
+// diagnostics: per-block partial results, then one block combines them in
+// block order (deterministic).  Quantities: mass[4], Jt[3], Z = sum e^{-beta V},
+// umax, jmax, nfluid, spare.
+// ------------------------------------------------------------------------
+__device__ inline double block_sum(double v, double *sh) {
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = BLOCK / 2; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+__device__ inline double block_max(double v, double *sh) {
+  int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = BLOCK / 2; w > 0; w >>= 1) {
+    if (t < w) sh[t] = fmax(sh[t], sh[t + w]);
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_diag_partials(Geom g, int M, const uint32_t *__restrict__ bb,
+                                                        Readout r, const double *__restrict__ V,
+                                                        double beta, double *__restrict__ partials) {
+  __shared__ double sh[BLOCK];
+  double acc[DIAG_K];
+  for (int k = 0; k < DIAG_K; ++k) acc[k] = 0.0;
+  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < g.N; i += gridDim.x * BLOCK) {
+    if (bb[i] & 1u) continue;
+    for (int s = 0; s < M; ++s) acc[s] += r.n[(long long)s * g.N + i];
+    double uu = 0.0, jj = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      acc[4 + k] += r.jt[(long long)k * g.N + i];
+      double u = r.u[(long long)k * g.N + i], j = r.j[(long long)k * g.N + i];
+      uu += u * u;
+      jj += j * j;
+    }
+    acc[7] += exp(-beta * V[i]);
+    acc[8] = fmax(acc[8], sqrt(uu));
+    acc[9] = fmax(acc[9], sqrt(jj));
+    acc[10] += 1.0;
+  }
+  for (int k = 0; k < DIAG_K; ++k) {
+    double v = (k == 8 || k == 9) ? block_max(acc[k], sh) : block_sum(acc[k], sh);
+    if (threadIdx.x == 0) partials[(long long)blockIdx.x * DIAG_K + k] = v;
+  }
+}
+
+__global__ void k_diag_final(int M, const double *__restrict__ partials, int nblocks,
+                             double *__restrict__ result) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double acc[DIAG_K];
+  for (int k = 0; k < DIAG_K; ++k) acc[k] = 0.0;
+  for (int b = 0; b < nblocks; ++b)
+    for (int k = 0; k < DIAG_K; ++k) {
+      double v = partials[(long long)b * DIAG_K + k];
+      acc[k] = (k == 8 || k == 9 || k == 11) ? fmax(acc[k], v) : acc[k] + v;
+    }
+  for (int k = 0; k < DIAG_K; ++k) result[k] = acc[k];
+}
+
+// second pass: max |n_tot - n_eq| with n_eq = mass e^{-beta V} / Z
+__global__ __launch_bounds__(BLOCK) void k_diag_errn(Geom g, int M, const uint32_t *__restrict__ bb,
+                                                    Readout r, const double *__restrict__ V,
+                                                    double beta, const double *__restrict__ res,
+                                                    double *__restrict__ partials) {
+  __shared__ double sh[BLOCK];
+  double mtot = 0.0;
+  for (int s = 0; s < M; ++s) mtot += res[s];
+  double Z = res[7];
+  double e = 0.0;
+  for (int i = blockIdx.x * BLOCK + threadIdx.x; i < g.N; i += gridDim.x * BLOCK) {
+    if (bb[i] & 1u) continue;
+    double nt = 0.0;
+    for (int s = 0; s < M; ++s) nt += r.n[(long long)s * g.N + i];
+    double neq = mtot * exp(-beta * V[i]) / Z;
+    e = fmax(e, fabs(nt - neq));
+  }
+  double v = block_max(e, sh);
+  if (threadIdx.x == 0) partials[(long long)blockIdx.x * DIAG_K + 11] = v;
+}
+
+inline dim3 grid_for(int N) { return dim3((N + BLOCK - 1) / BLOCK); }
+
+}  // namespace
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+void launch_bbmask(const Geom &g, const uint8_t *solid, uint32_t *bb, hipStream_t s) {
+  hipLaunchKernelGGL(k_bbmask, grid_for(g.N), dim3(BLOCK), 0, s, g, solid, bb);
+}
+
+void launch_extforce(const Geom &g, const double *V, double *F, hipStream_t s) {
+  hipLaunchKernelGGL(k_extforce, grid_for(g.N), dim3(BLOCK), 0, s, g, V, F);
+}
+
+void launch_zero_solid(const Geom &g, int M, int prec, void *pop, const uint32_t *bb,
+                       long long stride, hipStream_t s) {
+  if (prec == LBE_FP64)
+    hipLaunchKernelGGL(k_zero_solid<double>, grid_for(g.N), dim3(BLOCK), 0, s, g, 2 * M,
+                       (double *)pop, bb, stride);
+  else
+    hipLaunchKernelGGL(k_zero_solid<float>, grid_for(g.N), dim3(BLOCK), 0, s, g, 2 * M,
+                       (float *)pop, bb, stride);
+}
+
+void launch_rest_equilibrium(const Geom &g, int prec, const uint32_t *bb, const double *n0,
+                             void *out, hipStream_t s) {
+  long long Ns = ((long long)g.N + 63) / 64 * 64;
+  if (prec == LBE_FP64)
+    hipLaunchKernelGGL(k_rest_equilibrium<double>, grid_for(g.N), dim3(BLOCK), 0, s, g, bb, n0,
+                       (double *)out, Ns);
+  else
+    hipLaunchKernelGGL(k_rest_equilibrium<float>, grid_for(g.N), dim3(BLOCK), 0, s, g, bb, n0,
+                       (float *)out, Ns);
+}
+
+void launch_unstream(const Geom &g, int prec, const uint32_t *bb, const void *target, void *out,
+                     hipStream_t s) {
+  long long Ns = ((long long)g.N + 63) / 64 * 64;
+  if (prec == LBE_FP64)
+    hipLaunchKernelGGL(k_unstream<double>, grid_for(g.N), dim3(BLOCK), 0, s, g, bb,
+                       (const double *)target, (double *)out, Ns);
+  else
+    hipLaunchKernelGGL(k_unstream<float>, grid_for(g.N), dim3(BLOCK), 0, s, g, bb,
+                       (const float *)target, (float *)out, Ns);
+}
+
+void launch_pull(const Geom &g, int prec, const uint32_t *bb, const void *pre, void *out,
+                 hipStream_t s) {
+  long long Ns = ((long long)g.N + 63) / 64 * 64;
+  if (prec == LBE_FP64)
+    hipLaunchKernelGGL(k_pull<double>, grid_for(g.N), dim3(BLOCK), 0, s, g, bb,
+                       (const double *)pre, (double *)out, Ns);
+  else
+    hipLaunchKernelGGL(k_pull<float>, grid_for(g.N), dim3(BLOCK), 0, s, g, bb,
+                       (const float *)pre, (float *)out, Ns);
+}
+
+void launch_moments(const StepArgs &a, int prec, const void *pop, hipStream_t s) {
+  bool visc = (a.flags & LBE_VISC) && !(a.flags & LBE_IDEAL);
+  dim3 gr = grid_for(a.g.N);
+  if (prec == LBE_FP64) {
+    if (visc)
+      hipLaunchKernelGGL((k_moments<double, true>), gr, dim3(BLOCK), 0, s, a, (const double *)pop);
+    else
+      hipLaunchKernelGGL((k_moments<double, false>), gr, dim3(BLOCK), 0, s, a, (const double *)pop);
+  } else {
+    if (visc)
+      hipLaunchKernelGGL((k_moments<float, true>), gr, dim3(BLOCK), 0, s, a, (const float *)pop);
+    else
+      hipLaunchKernelGGL((k_moments<float, false>), gr, dim3(BLOCK), 0, s, a, (const float *)pop);
+  }
+}
+
+void launch_contact(const StepArgs &a, hipStream_t s) {
+  dim3 gr = grid_for(a.g.N);
+  switch (a.M) {
+    case 1: hipLaunchKernelGGL(k_contact<1>, gr, dim3(BLOCK), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_contact<2>, gr, dim3(BLOCK), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_contact<3>, gr, dim3(BLOCK), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_contact<4>, gr, dim3(BLOCK), 0, s, a); break;
+  }
+}
+
+template <typename T, int M>
+static void collide_dispatch(const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
+  bool visc = (a.flags & LBE_VISC) && !(a.flags & LBE_IDEAL);
+  dim3 gr = grid_for(a.g.N);
+  if (visc)
+    hipLaunchKernelGGL((k_collide<T, M, true>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, (T *)pout);
+  else
+    hipLaunchKernelGGL((k_collide<T, M, false>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, (T *)pout);
+}
+
+template <typename T>
+static void collide_m(const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
+  switch (a.M) {
+    case 1: collide_dispatch<T, 1>(a, pin, pout, s); break;
+    case 2: collide_dispatch<T, 2>(a, pin, pout, s); break;
+    case 3: collide_dispatch<T, 3>(a, pin, pout, s); break;
+    default: collide_dispatch<T, 4>(a, pin, pout, s); break;
+  }
+}
+
+void launch_collide(const StepArgs &a, int prec, const void *pin, void *pout, hipStream_t s) {
+  if (prec == LBE_FP64)
+    collide_m<double>(a, pin, pout, s);
+  else
+    collide_m<float>(a, pin, pout, s);
+}
+
+template <typename T, int M>
+static void readout_dispatch(const StepArgs &a, const void *pin, const Readout &r, hipStream_t s) {
+  bool visc = (a.flags & LBE_VISC) && !(a.flags & LBE_IDEAL);
+  dim3 gr = grid_for(a.g.N);
+  if (visc)
+    hipLaunchKernelGGL((k_readout<T, M, true>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, r);
+  else
+    hipLaunchKernelGGL((k_readout<T, M, false>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, r);
+}
+
+template <typename T>
+static void readout_m(const StepArgs &a, const void *pin, const Readout &r, hipStream_t s) {
+  switch (a.M) {
+    case 1: readout_dispatch<T, 1>(a, pin, r, s); break;
+    case 2: readout_dispatch<T, 2>(a, pin, r, s); break;
+    case 3: readout_dispatch<T, 3>(a, pin, r, s); break;
+    default: readout_dispatch<T, 4>(a, pin, r, s); break;
+  }
+}
+
+void launch_readout(const StepArgs &a, int prec, const void *pin, const Readout &r, hipStream_t s) {
+  if (prec == LBE_FP64)
+    readout_m<double>(a, pin, r, s);
+  else
+    readout_m<float>(a, pin, r, s);
+}
+
+int diag_nblocks(const Geom &g) {
+  int nb = (g.N + BLOCK - 1) / BLOCK;
+  return nb < 1024 ? nb : 1024;
+}
+
+void launch_diag_partials(const Geom &g, int M, const uint32_t *bb, const Readout &r, const double *V,
+                          double beta, double *partials, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_partials, dim3(nblocks), dim3(BLOCK), 0, s, g, M, bb, r, V, beta, partials);
+}
+
+void launch_diag_final(int M, const double *partials, int nblocks, double *result, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, M, partials, nblocks, result);
+}
+
+void launch_diag_errn(const Geom &g, int M, const uint32_t *bb, const Readout &r, const double *V,
+                      double beta, const double *result, double *partials, int nblocks,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_errn, dim3(nblocks), dim3(BLOCK), 0, s, g, M, bb, r, V, beta, result,
+                     partials);
+}
+
+}  // namespace lbe

@@ -1,0 +1,260 @@
+"""Python binding of the C ABI in ``include/lbe.h`` (liblbe.so, built in-tree).
+
+Argument marshalling only: every step of the method runs in the library's
+gfx950 kernels.  PyTorch supplies the device workspace (one uint8 tensor) and
+the HIP stream.  There is no CPU fallback: if ``liblbe.so`` is missing the
+import-time loader raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import re
+from pathlib import Path
+from typing import Optional, Sequence
+
+import numpy as np
+
+PKG = Path(__file__).resolve().parent
+LIB_PATH = PKG / "liblbe.so"
+HEADER = PKG.parent / "include" / "lbe.h"
+
+LBE_OK = 0
+LBE_ERR_ARG = -1
+LBE_ERR_STATE = -2
+LBE_ERR_OOM = -3
+LBE_ERR_HIP = -4
+LBE_ERR_UNSTABLE = -5
+LBE_ERR_UNSUPPORTED = -6
+
+LBE_FP64 = 0
+LBE_FP32_POP = 1
+LBE_HOST = 0
+LBE_DEVICE = 1
+
+LBE_VISC = 1 << 0
+LBE_PRINTED_INV = 1 << 1
+LBE_KAPPA4 = 1 << 2
+LBE_IDEAL = 1 << 3
+
+
+class lbe_config(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("periodic", C.c_uint), ("nspecies", C.c_int),
+        ("sigma", C.c_double * 4), ("tau", C.c_double), ("kT", C.c_double),
+        ("prec", C.c_int), ("flags", C.c_uint),
+    ]
+
+
+class lbe_diag(C.Structure):
+    _fields_ = [
+        ("mass", C.c_double * 4), ("gmom", C.c_double * 3),
+        ("umax", C.c_double), ("err_n", C.c_double), ("err_u", C.c_double),
+        ("err_J", C.c_double), ("unstable", C.c_int),
+    ]
+
+
+class LBEError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbe status {code}: {msg}")
+        self.code = code
+
+
+_lib: Optional[C.CDLL] = None
+
+
+def declared_symbols() -> list:
+    """Names of the functions declared in include/lbe.h."""
+    text = HEADER.read_text()
+    return sorted(set(re.findall(r"\b(lbe_[a-z_0-9]+)\s*\(", text)))
+
+
+def lib() -> C.CDLL:
+    """Load liblbe.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not LIB_PATH.exists():
+        raise RuntimeError(f"{LIB_PATH} is missing: run paper_1202_3842_amd.build.build() first")
+    L = C.CDLL(str(LIB_PATH))
+    P = C.c_void_p
+    L.lbe_last_error.restype = C.c_char_p
+    L.lbe_workspace_bytes.restype = C.c_size_t
+    L.lbe_workspace_bytes.argtypes = [C.POINTER(lbe_config)]
+    L.lbe_create.argtypes = [C.POINTER(lbe_config), P, C.c_size_t, P, C.POINTER(P)]
+    L.lbe_destroy.argtypes = [P]
+    L.lbe_destroy.restype = None
+    L.lbe_set_solid.argtypes = [P, P, C.c_int]
+    L.lbe_set_potential.argtypes = [P, P, C.c_int]
+    L.lbe_set_body_force.argtypes = [P, C.c_int, C.POINTER(C.c_double)]
+    L.lbe_init_density.argtypes = [P, C.c_int, P, C.c_int]
+    L.lbe_step.argtypes = [P, C.c_int]
+    L.lbe_get_density.argtypes = [P, C.c_int, P, C.c_int]
+    L.lbe_get_velocity.argtypes = [P, C.c_int, P, C.c_int]
+    L.lbe_get_force.argtypes = [P, C.c_int, C.c_int, P, C.c_int]
+    L.lbe_get_populations.argtypes = [P, C.c_int, C.c_int, P, C.c_int]
+    L.lbe_set_populations.argtypes = [P, C.c_int, C.c_int, P, C.c_int]
+    L.lbe_diagnostics.argtypes = [P, C.POINTER(lbe_diag)]
+    L.lbe_synchronize.argtypes = [P]
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != LBE_OK:
+        raise LBEError(st, lib().lbe_last_error().decode())
+
+
+def make_config(nx, ny, nz, sigma: Sequence[float], periodic=7, tau=1.0, kT=1.0 / 3.0,
+                prec=LBE_FP64, flags=LBE_VISC) -> lbe_config:
+    cfg = lbe_config()
+    cfg.nx, cfg.ny, cfg.nz = int(nx), int(ny), int(nz)
+    cfg.periodic = int(periodic)
+    cfg.nspecies = len(sigma)
+    for i, s in enumerate(sigma):
+        cfg.sigma[i] = float(s)
+    cfg.tau = float(tau)
+    cfg.kT = float(kT)
+    cfg.prec = int(prec)
+    cfg.flags = int(flags)
+    return cfg
+
+
+def workspace_bytes(cfg: lbe_config) -> int:
+    n = lib().lbe_workspace_bytes(C.byref(cfg))
+    if n == 0:
+        raise LBEError(LBE_ERR_ARG, lib().lbe_last_error().decode())
+    return int(n)
+
+
+class Box:
+    """One lattice box on the current HIP device.
+
+    Host inputs are numpy arrays shaped (nz, ny, nx) (or flat); device inputs
+    are torch CUDA tensors.  Outputs are numpy arrays unless ``out`` (a torch
+    CUDA tensor) is given.
+    """
+
+    def __init__(self, nx, ny, nz, sigma, periodic=7, tau=1.0, kT=1.0 / 3.0,
+                 prec=LBE_FP64, flags=LBE_VISC, stream=None):
+        import torch
+        self.torch = torch
+        self.cfg = make_config(nx, ny, nz, sigma, periodic, tau, kT, prec, flags)
+        self.shape = (nz, ny, nx)
+        self.N = nx * ny * nz
+        self.M = len(sigma)
+        self.prec = prec
+        nbytes = workspace_bytes(self.cfg)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib().lbe_create(C.byref(self.cfg), C.c_void_p(self.workspace.data_ptr()),
+                                nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    # ---- lifetime -------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- marshalling ----------------------------------------------------
+    def _src(self, a, dtype, count):
+        """(pointer, where, keepalive) for an input array."""
+        t = self.torch
+        if isinstance(a, t.Tensor) and a.is_cuda:
+            a = a.contiguous()
+            assert a.numel() == count and a.element_size() == np.dtype(dtype).itemsize
+            return C.c_void_p(a.data_ptr()), LBE_DEVICE, a
+        arr = np.ascontiguousarray(np.asarray(a), dtype=dtype).reshape(-1)
+        assert arr.size == count, (arr.size, count)
+        return C.c_void_p(arr.ctypes.data), LBE_HOST, arr
+
+    def _dst(self, out, dtype, count):
+        t = self.torch
+        if out is not None:
+            assert out.is_cuda and out.is_contiguous() and out.numel() == count
+            return C.c_void_p(out.data_ptr()), LBE_DEVICE, out
+        arr = np.empty(count, dtype=dtype)
+        return C.c_void_p(arr.ctypes.data), LBE_HOST, arr
+
+    # ---- ABI calls ------------------------------------------------------
+    def set_solid(self, mask):
+        p, w, keep = self._src(mask, np.uint8, self.N)
+        _check(lib().lbe_set_solid(self.h, p, w))
+
+    def set_potential(self, V):
+        p, w, keep = self._src(V, np.float64, self.N)
+        _check(lib().lbe_set_potential(self.h, p, w))
+
+    def set_body_force(self, species, g):
+        arr = (C.c_double * 3)(*[float(v) for v in g])
+        _check(lib().lbe_set_body_force(self.h, int(species), arr))
+
+    def init_density(self, species, n0):
+        p, w, keep = self._src(n0, np.float64, self.N)
+        _check(lib().lbe_init_density(self.h, int(species), p, w))
+
+    def step(self, n=1):
+        _check(lib().lbe_step(self.h, int(n)))
+
+    def synchronize(self):
+        _check(lib().lbe_synchronize(self.h))
+
+    def density(self, species=0, out=None):
+        p, w, arr = self._dst(out, np.float64, self.N)
+        _check(lib().lbe_get_density(self.h, int(species), p, w))
+        return arr.reshape(self.shape) if out is None else arr
+
+    def velocity(self, species=-1, out=None):
+        p, w, arr = self._dst(out, np.float64, 3 * self.N)
+        _check(lib().lbe_get_velocity(self.h, int(species), p, w))
+        return arr.reshape((3,) + self.shape) if out is None else arr
+
+    def force(self, species=0, which=0, out=None):
+        p, w, arr = self._dst(out, np.float64, 3 * self.N)
+        _check(lib().lbe_get_force(self.h, int(species), int(which), p, w))
+        return arr.reshape((3,) + self.shape) if out is None else arr
+
+    @property
+    def pop_dtype(self):
+        return np.float64 if self.prec == LBE_FP64 else np.float32
+
+    def populations(self, species=0, dist=0, out=None):
+        p, w, arr = self._dst(out, self.pop_dtype, 19 * self.N)
+        _check(lib().lbe_get_populations(self.h, int(species), int(dist), p, w))
+        return arr.reshape((19,) + self.shape) if out is None else arr
+
+    def set_populations(self, species, dist, pops):
+        p, w, keep = self._src(pops, self.pop_dtype, 19 * self.N)
+        _check(lib().lbe_set_populations(self.h, int(species), int(dist), p, w))
+
+    def diagnostics(self):
+        d = lbe_diag()
+        _check(lib().lbe_diagnostics(self.h, C.byref(d)))
+        return {
+            "mass": list(d.mass)[: self.M], "gmom": list(d.gmom), "umax": d.umax,
+            "err_n": d.err_n, "err_u": d.err_u, "err_J": d.err_J,
+            "unstable": bool(d.unstable),
+        }
+
+
+def box_from_workload(w, prec=LBE_FP64, flags=LBE_VISC) -> Box:
+    """Create a Box and load a paper_1202_3842_amd.workloads.Workload into it."""
+    b = Box(w.nx, w.ny, w.nz, w.sigma, periodic=w.periodic, tau=w.tau, kT=w.kT,
+            prec=prec, flags=flags)
+    if w.solid is not None:
+        b.set_solid(w.solid)
+    if w.V is not None:
+        b.set_potential(w.V)
+    for a, g in enumerate(w.body):
+        b.set_body_force(a, g)
+    for a, n in enumerate(w.density):
+        b.init_density(a, n)
+    return b

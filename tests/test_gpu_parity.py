@@ -1,0 +1,186 @@
+"""GPU parity: the HIP library against the FP64 oracle, element by element, on
+seeded inputs (FP64 bar: max-norm relative error 1e-11 on n and u)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1202_3842_amd import workloads as W
+from tests.parity_util import banner, compare_state, oracle_from_workload, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def L():
+    import oracle
+    if not oracle.LIB.exists():
+        oracle.build()
+    oracle.set_threads(8)
+    from paper_1202_3842_amd import lbe
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    lbe.lib()
+    return lbe
+
+
+def _pair(L, w, flags, prec=None):
+    import oracle
+    prec = L.LBE_FP64 if prec is None else prec
+    o = oracle_from_workload(w, flags)
+    b = L.box_from_workload(w, prec=prec, flags=flags)
+    return o, b
+
+
+def test_small_well_fp64(L):
+    """32^3 periodic well, sigma = 4, n sigma^3 = 0.3 with noise, C^visc on."""
+    w = W.c1_small_well()
+    banner(f"small well {w.name} fp64")
+    o, b = _pair(L, w, L.LBE_VISC)
+    compare_state(o, b, 1, TOL, "t=0")
+    for k in range(2):
+        o.step(5)
+        b.step(5)
+        compare_state(o, b, 1, TOL, f"t={5 * (k + 1)}")
+    # populations too
+    for dist in (0, 1):
+        assert rel_err(b.populations(0, dist), o.populations(0, dist)) <= TOL
+
+
+@pytest.mark.parametrize("flags_name", ["none", "printed", "kappa4", "ideal", "printed_kappa4_visc"])
+def test_scheme_switches(L, flags_name):
+    import oracle
+    flags = {"none": 0, "printed": L.LBE_PRINTED_INV | L.LBE_VISC, "kappa4": L.LBE_KAPPA4 | L.LBE_VISC,
+             "ideal": L.LBE_IDEAL, "printed_kappa4_visc": L.LBE_VISC | L.LBE_PRINTED_INV | L.LBE_KAPPA4}[flags_name]
+    w = W.well_box(24, 3.0, 0.3, 0.5, 6.0, 1e-3, 5, 6)
+    w.body = [[1e-4, -2e-5, 0.0]]
+    banner(f"switches {flags_name}")
+    o, b = _pair(L, w, flags)
+    o.step(6)
+    b.step(6)
+    compare_state(o, b, 1, TOL, flags_name)
+
+
+def test_forces(L):
+    w = W.well_box(24, 4.0, 0.3, 0.5, 6.0, 1e-2, 8, 3)
+    banner("forces")
+    o, b = _pair(L, w, L.LBE_VISC)
+    o.step(3)
+    b.step(3)
+    cm, cv = o.forces(0)
+    assert rel_err(b.force(0, 0), cm) <= TOL
+    assert rel_err(b.force(0, 1), cv) <= TOL
+
+
+def test_channel_two_species(L):
+    """Reduced bottleneck channel: walls in y, solid constriction, M = 2,
+    sigma 4 and 6, body force along x."""
+    w = W.channel(nx=48, ny=24, nz=12, x0=20, x1=28, gap=10, force=1e-4, steps=8)
+    for a in range(2):
+        w.density[a] = w.density[a] * (1 + W.rng(60 + a).uniform(-1e-3, 1e-3, size=w.shape))
+    banner("channel M=2 48x24x12")
+    o, b = _pair(L, w, L.LBE_VISC)
+    o.step(8)
+    b.step(8)
+    compare_state(o, b, 2, TOL, "channel t=8")
+
+
+def test_three_species_ragged(L):
+    """Three species on a ragged box (edges not multiples of the block)."""
+    shape = (11, 13, 17)
+    sig = [2.0, 3.0, 1.0]
+    dens = [W.noisy_uniform(shape, 0.08 / s ** 3, 1e-2, 90 + i) for i, s in enumerate(sig)]
+    w = W.Workload("ragged3", 17, 13, 11, sig, density=dens, V=W.smooth_field(shape, 0.05, 3, 7),
+                   body=[[0, 0, 0]] * 3, periodic=7)
+    banner("three species ragged 17x13x11")
+    o, b = _pair(L, w, L.LBE_VISC)
+    o.step(4)
+    b.step(4)
+    compare_state(o, b, 3, TOL, "ragged t=4")
+
+
+def test_populations_roundtrip(L):
+    w = W.channel(nx=20, ny=12, nz=8, x0=8, x1=12, gap=4, sigma=(3.0, 2.0), steps=1)
+    banner("populations roundtrip")
+    b = L.box_from_workload(w, flags=L.LBE_VISC)
+    b.step(2)
+    for dist in (0, 1):
+        p = b.populations(1, dist)
+        b.set_populations(1, dist, p)
+        assert np.array_equal(b.populations(1, dist), p)
+
+
+def test_uniform_fixed_point(L):
+    L_ = 24
+    shape = (L_, L_, L_)
+    w = W.Workload("uni", L_, L_, L_, [4.0], density=[np.full(shape, 0.3 / 64)], V=np.zeros(shape),
+                   body=[[0, 0, 0]])
+    banner("uniform fixed point")
+    b = L.box_from_workload(w, flags=L.LBE_VISC)
+    b.step(20)
+    assert not np.any(b.velocity(-1))
+    n = b.density(0)
+    assert n.max() == n.min()
+    assert abs(n.max() - 0.3 / 64) <= 1e-14 * 0.3 / 64
+
+
+def test_mass_momentum_and_determinism(L):
+    w = W.well_box(32, 4.0, 0.3, 0.0, 1.0, 1e-2, 21, 1)
+    w.V = np.zeros(w.shape)
+    banner("mass/momentum/determinism")
+    b1 = L.box_from_workload(w, flags=L.LBE_VISC)
+    b2 = L.box_from_workload(w, flags=L.LBE_VISC)
+    d0 = b1.diagnostics()
+    b1.step(15)
+    b2.step(15)
+    d1 = b1.diagnostics()
+    m0, m1 = np.array(d0["mass"]), np.array(d1["mass"])
+    assert np.abs(m1 - m0).max() <= 1e-13 * m0.max()
+    scale = m0.sum() * math.sqrt(1 / 3)
+    assert np.abs(np.array(d1["gmom"]) - np.array(d0["gmom"])).max() <= 1e-13 * scale
+    for dist in (0, 1):
+        assert np.array_equal(b1.populations(0, dist), b2.populations(0, dist))
+
+
+def test_diagnostics_against_oracle(L):
+    w = W.well_box(24, 3.0, 0.3, 0.5, 6.0, 1e-3, 33, 5)
+    banner("diagnostics")
+    o, b = _pair(L, w, L.LBE_VISC)
+    o.step(5)
+    b.step(5)
+    do, dg = o.diagnostics(), b.diagnostics()
+    for k in ("umax", "err_n", "err_u", "err_J"):
+        assert abs(dg[k] - do[k]) <= 1e-11 * abs(do[k]), k
+    assert abs(dg["mass"][0] - do["mass"][0]) <= 1e-13 * do["mass"][0]
+
+
+def test_instability_is_reported(L):
+    L_ = 16
+    shape = (L_, L_, L_)
+    w = W.Workload("dense", L_, L_, L_, [4.0], density=[np.full(shape, 1.1 * 6 / (math.pi * 64))],
+                   V=np.zeros(shape), body=[[0, 0, 0]])
+    banner("instability flag")
+    b = L.box_from_workload(w, flags=L.LBE_VISC)
+    b.step(1)
+    assert b.diagnostics()["unstable"]
+    with pytest.raises(L.LBEError) as e:
+        b.step(1)
+    assert e.value.code == L.LBE_ERR_UNSTABLE
+    b.init_density(0, np.full(shape, 0.3 / 64))
+    b.step(1)
+    assert not b.diagnostics()["unstable"]
+
+
+def test_fp32_populations_report(L):
+    """FP32 population storage (FP64 arithmetic): reported, with a loose bar."""
+    w = W.c1_small_well()
+    banner("fp32 populations")
+    o, b = _pair(L, w, L.LBE_VISC, prec=L.LBE_FP32_POP)
+    o.step(10)
+    b.step(10)
+    en = rel_err(b.density(0), o.density(0))
+    eu = rel_err(b.velocity(-1), o.velocity(-1))
+    print(f"[fp32] n rel err {en:.3e} u rel err {eu:.3e}", flush=True)
+    assert en < 1e-5 and eu < 1e-3
