@@ -1,0 +1,206 @@
+#!/usr/bin/env python
+"""Throughput of the stabilized Lattice Boltzmann-Enskog step (DD-TR) on one
+MI355X: MLUPS per species and the HBM-roofline fraction of the dominant
+kernel, with the CPU oracle timed beside it.
+
+Workload (default): one-component hard spheres, D3Q19, 128^3 periodic box,
+sigma = 6, n sigma^3 = 0.4, cosine well of radius 24 and depth 2 kT at the
+centre, collisional viscous force on, FP64.  A "step" is one full DD-TR step
+(moments, contact values, force gather, collision, streaming) of the whole
+box.  Inputs are resident in HBM before the timed region starts.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def alg_bytes_collide(M, npairs, P, visc):
+    """Algorithmic bytes per node of the fused force + collision kernel:
+    pull of 2 x 19 populations per species, store of the same, one read of
+    each gathered field at the node (n, G, and J~ with C^visc), the external
+    force and the bounce-back mask."""
+    return M * (2 * 19 * P * 2) + 8 * M + 8 * npairs + (24 * M if visc else 0) + 24 + 4
+
+
+def alg_bytes_step(M, npairs, P, visc):
+    """Per node and step: populations read once and written once (the
+    minimum the method must move) plus one pass over the node fields."""
+    fields = 8 * M + 8 * M + 8 * npairs + 8 * npairs + 8  # n write+read, G write+read, V
+    if visc:
+        fields += 48 * M
+    return M * 2 * 38 * P + fields
+
+
+def run_gpu(w, prec, flags, steps, warmup, lbe, torch):
+    box = lbe.box_from_workload(w, prec=prec, flags=flags)
+    box.step(warmup)
+    box.synchronize()
+    log(f"warmup {warmup} steps done ({'fp64' if prec == lbe.LBE_FP64 else 'fp32-pop'})")
+    stream = box.stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for k in range(steps):
+        box.step_phase(0)
+        box.step_phase(1)
+        ev[k][0].record(stream)
+        box.step_phase(2)
+        ev[k][1].record(stream)
+    t1.record(stream)
+    t1.synchronize()
+    torch.cuda.synchronize()
+    total_ms = t0.elapsed_time(t1)
+    coll = sorted(a.elapsed_time(b) for a, b in ev)
+    coll_mean = sum(coll) / len(coll)
+    diag = box.diagnostics()
+    log(f"timed {steps} steps: {total_ms / steps:.3f} ms/step, collide {coll_mean:.3f} ms")
+    box.close()
+    return total_ms, coll_mean, coll[len(coll) // 2], diag
+
+
+def cpu_baseline(w, flags, budget_s):
+    """The oracle as it stands, on the host cores, over a bounded number of
+    steps of the same workload from its initial state."""
+    import oracle
+    if not oracle.LIB.exists():
+        oracle.build()
+    threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16")), 16)
+    oracle.set_threads(threads)
+    o = oracle.Oracle(w.nx, w.ny, w.nz, w.sigma, periodic=w.periodic, tau=w.tau, kT=w.kT, flags=flags)
+    if w.solid is not None:
+        o.set_solid(w.solid)
+    if w.V is not None:
+        o.set_potential(w.V)
+    for a, g in enumerate(w.body):
+        o.set_body_force(a, g)
+    for a, n in enumerate(w.density):
+        o.init_density(a, n)
+    steps = 0
+    t = time.perf_counter()
+    while True:
+        try:
+            o.step(1)
+        except oracle.OracleError as e:
+            log(f"cpu oracle stopped: {e}")
+            break
+        steps += 1
+        el = time.perf_counter() - t
+        log(f"cpu oracle step {steps}: {el:.1f} s")
+        if el > budget_s or steps >= 50:
+            break
+    el = time.perf_counter() - t
+    mlups = w.nodes * w.nspecies * steps / el / 1e6
+    o.close()
+    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} steps of the same {w.nx}x{w.ny}x{w.nz} workload from its initial "
+                      f"state ({el:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--fp32-steps", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "decomposition of the lattice is designed but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1202_3842_amd import lbe
+    from paper_1202_3842_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    w = W.c2_large_well()
+    # The library's default (derived) inversions make this start-up collapse
+    # within ~60 steps; the printed inversions of Sec. 4.2 keep it bounded for
+    # all 2000 steps.  The switch changes no memory traffic.
+    flags = lbe.LBE_VISC | lbe.LBE_PRINTED_INV
+    M = w.nspecies
+    npairs = M * (M + 1) // 2
+
+    total_ms, coll_ms, coll_med, diag = run_gpu(w, lbe.LBE_FP64, flags, args.steps, args.warmup, lbe, torch)
+    N = w.nodes
+    ms_step = total_ms / args.steps
+    mlups = N * M * args.steps / (total_ms / 1e3) / 1e6
+    bcoll = alg_bytes_collide(M, npairs, 8, True)
+    achieved = bcoll * N / (coll_ms / 1e3) / 1e9
+    balg = alg_bytes_step(M, npairs, 8, True)
+
+    fp32_steps = args.fp32_steps if args.fp32_steps is not None else max(args.steps // 4, 10)
+    t32, c32, _, diag32 = run_gpu(w, lbe.LBE_FP32_POP, flags, fp32_steps, args.warmup, lbe, torch)
+    mlups32 = N * M * fp32_steps / (t32 / 1e3) / 1e6
+    bcoll32 = alg_bytes_collide(M, npairs, 4, True)
+    ach32 = bcoll32 * N / (c32 / 1e3) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, flags, args.cpu_budget)
+
+    out = {
+        "metric": "MLUPS per species + % HBM roofline (FP64 & FP32); batched vs serial; adjoint/fwd",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name, "lattice": "D3Q19", "box": [w.nx, w.ny, w.nz], "periodic": "xyz",
+            "species": M, "sigma": w.sigma, "n_sigma3": 0.4, "well_radius": 24, "well_depth_kT": 2.0,
+            "tau": w.tau, "kT": w.kT, "collisional_viscous_force": True,
+            "inversion": "printed (Sec. 4.2)", "kappa": 2, "well_eps_kT": 1.0,
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": "k_collide (force gather + collision + store)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "alg_bytes_per_node": bcoll, "avg_launch_ms": round(coll_ms, 4),
+            "median_launch_ms": round(coll_med, 4),
+        },
+        "step_alg_frac": round(mlups * 1e6 * balg / (HBM_PEAK_GBS * 1e9), 4),
+        "step_alg_bytes_per_node": balg,
+        "fp32_pop": {
+            "value": round(mlups32, 2), "unit": "MLUPS", "steps": fp32_steps,
+            "ms_per_step": round(t32 / fp32_steps, 4),
+            "roofline": {"achieved": round(ach32, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(ach32 / HBM_PEAK_GBS, 4), "alg_bytes_per_node": bcoll32,
+                         "avg_launch_ms": round(c32, 4)},
+            "umax": diag32["umax"], "unstable": diag32["unstable"],
+        },
+        "state_after": {"umax": diag["umax"], "unstable": diag["unstable"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

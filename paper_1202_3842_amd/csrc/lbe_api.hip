@@ -193,6 +193,7 @@ struct lbe_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
   int cur = 0;             // ping-pong buffer holding the current state
+  int next_phase = 0;      // lbe_step_phase position inside a step
   bool poisoned = false;
   StepArgs args;
   Readout rd;
@@ -396,6 +397,23 @@ lbe_status lbe_init_density(lbe_ctx *c, int species, const double *n0, int where
   return clear_instability(c);
 }
 
+lbe_status lbe_step_phase(lbe_ctx *c, int phase) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  if (phase < 0 || phase > 2) return fail(LBE_ERR_ARG, "phase must be 0, 1 or 2");
+  if (c->poisoned) return fail(LBE_ERR_UNSTABLE, "context is unstable; reinitialise the state");
+  if (phase != c->next_phase) return fail(LBE_ERR_STATE, "phase %d expected", c->next_phase);
+  hipStream_t s = c->stream;
+  if (phase == 0) launch_moments(c->args, c->cfg.prec, c->pop(c->cur), s);
+  if (phase == 1) launch_contact(c->args, s);
+  if (phase == 2) {
+    launch_collide(c->args, c->cfg.prec, c->pop(c->cur), c->pop(c->cur ^ 1), s);
+    c->cur ^= 1;
+  }
+  LAUNCH_CHECK();
+  c->next_phase = (phase + 1) % 3;
+  return LBE_OK;
+}
+
 static lbe_status enqueue_step(lbe_ctx *c) {
   hipStream_t s = c->stream;
   launch_moments(c->args, c->cfg.prec, c->pop(c->cur), s);
@@ -410,6 +428,7 @@ lbe_status lbe_step(lbe_ctx *c, int nsteps) {
   if (!c) return fail(LBE_ERR_ARG, "null context");
   if (nsteps < 0) return fail(LBE_ERR_ARG, "nsteps < 0");
   if (c->poisoned) return fail(LBE_ERR_UNSTABLE, "context is unstable; reinitialise the state");
+  if (c->next_phase != 0) return fail(LBE_ERR_STATE, "a phased step is incomplete");
   for (int k = 0; k < nsteps; ++k) {
     lbe_status st = enqueue_step(c);
     if (st != LBE_OK) return st;

@@ -89,6 +89,7 @@ def lib() -> C.CDLL:
     L.lbe_set_body_force.argtypes = [P, C.c_int, C.POINTER(C.c_double)]
     L.lbe_init_density.argtypes = [P, C.c_int, P, C.c_int]
     L.lbe_step.argtypes = [P, C.c_int]
+    L.lbe_step_phase.argtypes = [P, C.c_int]
     L.lbe_get_density.argtypes = [P, C.c_int, P, C.c_int]
     L.lbe_get_velocity.argtypes = [P, C.c_int, P, C.c_int]
     L.lbe_get_force.argtypes = [P, C.c_int, C.c_int, P, C.c_int]
@@ -203,6 +204,9 @@ class Box:
 
     def step(self, n=1):
         _check(lib().lbe_step(self.h, int(n)))
+
+    def step_phase(self, phase):
+        _check(lib().lbe_step_phase(self.h, int(phase)))
 
     def synchronize(self):
         _check(lib().lbe_synchronize(self.h))

@@ -109,28 +109,35 @@ def packing_density(eta: float, sigma: float) -> float:
 # --------------------------------------------------------------------------
 # The workloads
 # --------------------------------------------------------------------------
-def well_box(L: int, sigma: float, nsig3: float, depth_kT: float, xi: float,
+def well_box(L: int, sigma: float, nsig3: float, eps_kT: float, xi: float,
              noise: float, seed: int, steps: int, name: str = "well") -> Workload:
     """One-component hard spheres in a periodic cube with a cosine well at
-    the centre: n = nsig3 / sigma^3 (1 + noise), well depth in kT units."""
+    the centre: n = nsig3 / sigma^3 (1 + noise); eps_kT is the amplitude eps
+    of eq. (extpotential) in kT units (the well is 2 eps deep)."""
     shape = (L, L, L)
     n0 = nsig3 / sigma ** 3
     return Workload(
         name=name, nx=L, ny=L, nz=L, sigma=[float(sigma)], steps=steps,
         density=[noisy_uniform(shape, n0, noise, seed)],
-        V=cosine_well(shape, xi, depth_kT * KT), body=[[0.0, 0.0, 0.0]])
+        V=cosine_well(shape, xi, eps_kT * KT), body=[[0.0, 0.0, 0.0]])
+
+
+def eps_for_depth(depth_kT: float) -> float:
+    """A well "depth D kT" read as the depth of the well, U(0) = -D kT,
+    i.e. eps = D/2 in eq. (extpotential)."""
+    return 0.5 * depth_kT
 
 
 def c1_small_well() -> Workload:
     """32^3 periodic, sigma = 4, n sigma^3 = 0.3 with +-1e-3 noise (seed 1202),
     well radius 8 and depth 1 kT, 50 steps."""
-    return well_box(32, 4.0, 0.3, 1.0, 8.0, 1e-3, 1202, 50, "well32_s4")
+    return well_box(32, 4.0, 0.3, eps_for_depth(1.0), 8.0, 1e-3, 1202, 50, "well32_s4")
 
 
 def c2_large_well() -> Workload:
     """128^3 periodic, sigma = 6, n sigma^3 = 0.4, well radius 24 and depth
     2 kT, 2000 steps (no noise)."""
-    return well_box(128, 6.0, 0.4, 2.0, 24.0, 0.0, 0, 2000, "well128_s6")
+    return well_box(128, 6.0, 0.4, eps_for_depth(2.0), 24.0, 0.0, 0, 2000, "well128_s6")
 
 
 def channel(nx=256, ny=64, nz=32, x0=112, x1=144, gap=24, sigma=(4.0, 6.0),
@@ -178,6 +185,6 @@ def c4_boxes(count: int = 96, seed: int = 3842, steps: int = 500,
         sigma = float(g.choice([3.0, 4.0, 6.0]))
         nsig3 = float(g.uniform(0.1, 0.45))
         depth = float(g.uniform(0.5, 3.0))
-        out.append(well_box(L, sigma, nsig3, depth, L / 4.0, 1e-3, seed + 1 + b,
+        out.append(well_box(L, sigma, nsig3, eps_for_depth(depth), L / 4.0, 1e-3, seed + 1 + b,
                             steps, name=f"box{b}"))
     return out
