@@ -30,12 +30,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def alg_bytes_collide(M, npairs, P, visc):
-    """Algorithmic bytes per node of the fused force + collision kernel:
-    pull of 2 x 19 populations per species, store of the same, one read of
-    each gathered field at the node (n, G, and J~ with C^visc), the external
-    force and the bounce-back mask."""
-    return M * (2 * 19 * P * 2) + 8 * M + 8 * npairs + (24 * M if visc else 0) + 24 + 4
+def alg_bytes_collide(M, P):
+    """Algorithmic bytes per node of the collision kernel: pull of 2 x 19
+    populations per species, store of the same, the per-particle forces
+    (6 doubles per species), the external force (3 doubles) and the
+    bounce-back mask (4 bytes)."""
+    return M * (2 * 19 * P * 2 + 48) + 24 + 4
+
+
+def alg_flops_force(pairs, visc):
+    """FP64 flops per node of the shell gather (FMA = 2): per +-e pair the
+    mean-field term costs 11 and the viscous term 28."""
+    return pairs * (11 + (28 if visc else 0))
 
 
 def alg_bytes_step(M, npairs, P, visc):
@@ -47,14 +53,57 @@ def alg_bytes_step(M, npairs, P, visc):
     return M * 2 * 38 * P + fields
 
 
+def shell_pairs(sigma):
+    """Number of +-e pairs in the lattice shell of radius sigma."""
+    K = int(sigma + 1.5)
+    n = 0
+    for z in range(-K, K + 1):
+        for y in range(-K, K + 1):
+            for x in range(-K, K + 1):
+                r2 = x * x + y * y + z * z
+                if r2 and (sigma - 0.5) ** 2 <= r2 < (sigma + 0.5) ** 2:
+                    n += 1
+    return n // 2
+
+
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
+
+
+def kernel_views(r, N, M, P, pairs):
+    """Per-kernel roofline views: the collision kernel against HBM, the force
+    gather against FP64 vector throughput."""
+    steps_ms = r["total_ms"]
+    bcoll = alg_bytes_collide(M, P)
+    coll_gbs = bcoll * N / (r["collide_ms"] / 1e3) / 1e9
+    fl = alg_flops_force(pairs, True) * M * M
+    force_tf = fl * N / (r["force_ms"] / 1e3) / 1e12
+    return {
+        "k_collide": {"bound": "hbm", "achieved": round(coll_gbs, 1), "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": round(coll_gbs / HBM_PEAK_GBS, 4),
+                      "alg_bytes_per_node": bcoll, "avg_launch_ms": round(r["collide_ms"], 4),
+                      "traffic": None},
+        "k_force": {"bound": "alu", "achieved": round(force_tf, 2), "peak": FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(force_tf / FP64_PEAK_TFLOPS, 4),
+                    "alg_flops_per_node": fl, "avg_launch_ms": round(r["force_ms"], 4),
+                    "traffic": None},
+    }
+
+
+def dominant(kv):
+    name = max(kv, key=lambda k: kv[k]["avg_launch_ms"])
+    d = dict(kv[name])
+    d["kernel"] = name
+    return d
+
+
 def run_gpu(w, prec, flags, steps, warmup, lbe, torch):
     box = lbe.box_from_workload(w, prec=prec, flags=flags)
     box.step(warmup)
     box.synchronize()
     log(f"warmup {warmup} steps done ({'fp64' if prec == lbe.LBE_FP64 else 'fp32-pop'})")
     stream = box.stream
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
+    mk = lambda: torch.cuda.Event(enable_timing=True)
+    ev = [(mk(), mk(), mk()) for _ in range(steps)]
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -65,16 +114,21 @@ def run_gpu(w, prec, flags, steps, warmup, lbe, torch):
         ev[k][0].record(stream)
         box.step_phase(2)
         ev[k][1].record(stream)
+        box.step_phase(3)
+        ev[k][2].record(stream)
     t1.record(stream)
     t1.synchronize()
     torch.cuda.synchronize()
     total_ms = t0.elapsed_time(t1)
-    coll = sorted(a.elapsed_time(b) for a, b in ev)
-    coll_mean = sum(coll) / len(coll)
+    force = [a.elapsed_time(b) for a, b, c in ev]
+    coll = [b.elapsed_time(c) for a, b, c in ev]
     diag = box.diagnostics()
-    log(f"timed {steps} steps: {total_ms / steps:.3f} ms/step, collide {coll_mean:.3f} ms")
+    res = {"total_ms": total_ms, "force_ms": sum(force) / steps, "collide_ms": sum(coll) / steps,
+           "diag": diag}
+    log(f"timed {steps} steps: {total_ms / steps:.3f} ms/step, force {res['force_ms']:.3f} ms, "
+        f"collide {res['collide_ms']:.3f} ms")
     box.close()
-    return total_ms, coll_mean, coll[len(coll) // 2], diag
+    return res
 
 
 def cpu_baseline(w, flags, budget_s):
@@ -142,19 +196,18 @@ def main():
     M = w.nspecies
     npairs = M * (M + 1) // 2
 
-    total_ms, coll_ms, coll_med, diag = run_gpu(w, lbe.LBE_FP64, flags, args.steps, args.warmup, lbe, torch)
+    r64 = run_gpu(w, lbe.LBE_FP64, flags, args.steps, args.warmup, lbe, torch)
     N = w.nodes
-    ms_step = total_ms / args.steps
-    mlups = N * M * args.steps / (total_ms / 1e3) / 1e6
-    bcoll = alg_bytes_collide(M, npairs, 8, True)
-    achieved = bcoll * N / (coll_ms / 1e3) / 1e9
+    ms_step = r64["total_ms"] / args.steps
+    mlups = N * M * args.steps / (r64["total_ms"] / 1e3) / 1e6
     balg = alg_bytes_step(M, npairs, 8, True)
+    pairs = shell_pairs(w.sigma[0])
+    kern64 = kernel_views(r64, N, M, 8, pairs)
 
     fp32_steps = args.fp32_steps if args.fp32_steps is not None else max(args.steps // 4, 10)
-    t32, c32, _, diag32 = run_gpu(w, lbe.LBE_FP32_POP, flags, fp32_steps, args.warmup, lbe, torch)
-    mlups32 = N * M * fp32_steps / (t32 / 1e3) / 1e6
-    bcoll32 = alg_bytes_collide(M, npairs, 4, True)
-    ach32 = bcoll32 * N / (c32 / 1e3) / 1e9
+    r32 = run_gpu(w, lbe.LBE_FP32_POP, flags, fp32_steps, args.warmup, lbe, torch)
+    mlups32 = N * M * fp32_steps / (r32["total_ms"] / 1e3) / 1e6
+    kern32 = kernel_views(r32, N, M, 4, pairs)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -179,24 +232,17 @@ def main():
             "tau": w.tau, "kT": w.kT, "collisional_viscous_force": True,
             "inversion": "printed (Sec. 4.2)", "kappa": 2, "well_eps_kT": 1.0,
         },
-        "roofline": {
-            "bound": "hbm", "kernel": "k_collide (force gather + collision + store)",
-            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "alg_bytes_per_node": bcoll, "avg_launch_ms": round(coll_ms, 4),
-            "median_launch_ms": round(coll_med, 4),
-        },
+        "roofline": dominant(kern64),
+        "kernels": kern64,
         "step_alg_frac": round(mlups * 1e6 * balg / (HBM_PEAK_GBS * 1e9), 4),
         "step_alg_bytes_per_node": balg,
         "fp32_pop": {
             "value": round(mlups32, 2), "unit": "MLUPS", "steps": fp32_steps,
-            "ms_per_step": round(t32 / fp32_steps, 4),
-            "roofline": {"achieved": round(ach32, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(ach32 / HBM_PEAK_GBS, 4), "alg_bytes_per_node": bcoll32,
-                         "avg_launch_ms": round(c32, 4)},
-            "umax": diag32["umax"], "unstable": diag32["unstable"],
+            "ms_per_step": round(r32["total_ms"] / fp32_steps, 4),
+            "roofline": dominant(kern32), "kernels": kern32,
+            "umax": r32["diag"]["umax"], "unstable": r32["diag"]["unstable"],
         },
-        "state_after": {"umax": diag["umax"], "unstable": diag["unstable"]},
+        "state_after": {"umax": r64["diag"]["umax"], "unstable": r64["diag"]["unstable"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -153,10 +153,11 @@ lbe_status lbe_init_density(lbe_ctx *ctx, int species, const double *n0,
  * next lbe_diagnostics or getter. */
 lbe_status lbe_step(lbe_ctx *ctx, int nsteps);
 
-/* One phase of lbe_step, for instrumentation (e.g. HIP events around the
- * collision kernel): phase 0 = moments, 1 = contact values, 2 = forces +
- * collision + buffer swap.  Calling phases 0, 1, 2 in order is exactly one
- * lbe_step; any other order is rejected with LBE_ERR_STATE. */
+/* One phase of lbe_step, for instrumentation (e.g. HIP events around one
+ * kernel): phase 0 = moments, 1 = contact values, 2 = nonlocal forces,
+ * 3 = collision + streaming store + buffer swap.  Calling phases 0..3 in
+ * order is exactly one lbe_step; any other order is rejected with
+ * LBE_ERR_STATE. */
 lbe_status lbe_step_phase(lbe_ctx *ctx, int phase);
 
 /* n^a = sum_p f~_p (Sec. 4.2), N values. */

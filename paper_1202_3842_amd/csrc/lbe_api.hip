@@ -41,11 +41,12 @@ lbe_status fail(lbe_status code, const char *fmt, ...) {
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 // Lattice shell of radius s: points e != 0 with s - 1/2 <= |e| < s + 1/2,
-// the half with the first nonzero component positive, and the uniform
-// weight 4 pi s / sum_e |e| that makes the weighted first moment
-// (4 pi/3) s delta_ij (Appendix integral over the unit sphere).
+// kept as the half S+ (e_z > 0, or e_z = 0 and e_y > 0, or e_z = e_y = 0 and
+// e_x > 0) grouped by e_z, with the uniform weight 4 pi s / sum_e |e| that
+// makes the weighted first moment (4 pi/3) s delta_ij (Appendix integral
+// over the unit sphere).
 struct HostShell {
-  std::vector<int> e;  // 3 per point of S+
+  std::vector<int> e;  // 3 per point of S+, ordered by e_z, then e_y, then e_x
   double weight = 0.0;
   int maxc = 0;
 };
@@ -57,19 +58,18 @@ HostShell make_shell(double s) {
   double lo = s - 0.5, hi = s + 0.5;
   double lo2 = lo * lo, hi2 = hi * hi;
   double sumlen = 0.0;
-  // z-major order keeps neighbouring offsets close in memory
   for (int z = -K; z <= K; ++z)
     for (int y = -K; y <= K; ++y)
       for (int x = -K; x <= K; ++x) {
         int r2 = x * x + y * y + z * z;
         if (r2 == 0 || (double)r2 < lo2 || (double)r2 >= hi2) continue;
         sumlen += sqrt((double)r2);
-        bool plus = x != 0 ? x > 0 : (y != 0 ? y > 0 : z > 0);
+        h.maxc = std::max(h.maxc, std::max(abs(x), std::max(abs(y), abs(z))));
+        bool plus = z != 0 ? z > 0 : (y != 0 ? y > 0 : x > 0);
         if (!plus) continue;
         h.e.push_back(x);
         h.e.push_back(y);
         h.e.push_back(z);
-        h.maxc = std::max(h.maxc, std::max(abs(x), std::max(abs(y), abs(z))));
       }
   h.weight = sumlen > 0 ? 4.0 * M_PI * s / sumlen : 0.0;
   return h;
@@ -100,9 +100,10 @@ struct Plan {
   std::vector<HostShell> shells;
   std::vector<std::vector<int>> balls;
   int nshell = 0, nball = 0;
-  size_t off_flag = 0, off_result = 0, off_shell_off = 0, off_shell_e = 0, off_ball = 0,
-         off_bb = 0, off_V = 0, off_F = 0, off_solid = 0, off_pop0 = 0, off_pop1 = 0,
-         off_n = 0, off_G = 0, off_J = 0, off_read = 0, off_part = 0, total = 0;
+  size_t off_flag = 0, off_result = 0, off_ring_ofs = 0, off_ring_off = 0, off_ring_e = 0,
+         off_ball = 0, off_bb = 0, off_V = 0, off_F = 0, off_solid = 0, off_pop0 = 0,
+         off_pop1 = 0, off_n = 0, off_G = 0, off_J = 0, off_force = 0, off_read = 0,
+         off_part = 0, total = 0;
   int nblocks = 0;
 };
 
@@ -117,9 +118,11 @@ lbe_status make_plan(const lbe_config *cfg, Plan &pl) {
   if (fabs(cfg->kT - 1.0 / 3.0) > 1e-12)
     return fail(LBE_ERR_ARG, "D3Q19 requires kT = v_T^2 = 1/3 (m = 1)");
   if (cfg->prec != LBE_FP64 && cfg->prec != LBE_FP32_POP) return fail(LBE_ERR_ARG, "bad precision");
-  for (int a = 0; a < cfg->nspecies; ++a)
-    if (!(cfg->sigma[a] >= 0.0) || cfg->sigma[a] > 16.0)
-      return fail(LBE_ERR_ARG, "sigma must lie in [0, 16]");
+  for (int a = 0; a < cfg->nspecies; ++a) {
+    if (!(cfg->sigma[a] >= 0.0)) return fail(LBE_ERR_ARG, "sigma must be >= 0");
+    if (cfg->sigma[a] > (double)RING_MAX)
+      return fail(LBE_ERR_UNSUPPORTED, "sigma above %d lattice units is not built", RING_MAX);
+  }
   pl.M = cfg->nspecies;
   pl.npairs = pl.M * (pl.M + 1) / 2;
   int R = 0;
@@ -166,8 +169,9 @@ lbe_status make_plan(const lbe_config *cfg, Plan &pl) {
   };
   pl.off_flag = take(64);
   pl.off_result = take(sizeof(double) * 16);
-  pl.off_shell_off = take(sizeof(int) * std::max(pl.nshell, 1));
-  pl.off_shell_e = take(sizeof(double) * 3 * std::max(pl.nshell, 1));
+  pl.off_ring_ofs = take(sizeof(int) * (RING_MAX + 2) * MAXPAIRS);
+  pl.off_ring_off = take(sizeof(int) * std::max(pl.nshell, 1));
+  pl.off_ring_e = take(sizeof(double) * 3 * std::max(pl.nshell, 1));
   pl.off_ball = take(sizeof(int) * std::max(pl.nball, 1));
   pl.off_bb = take(sizeof(uint32_t) * g.N);
   pl.off_V = take(sizeof(double) * g.N);
@@ -178,6 +182,7 @@ lbe_status make_plan(const lbe_config *cfg, Plan &pl) {
   pl.off_n = take(sizeof(double) * pl.M * g.Np);
   pl.off_G = take(sizeof(double) * pl.npairs * g.Np);
   pl.off_J = take(visc ? sizeof(double) * 3 * pl.M * g.Np : 0);
+  pl.off_force = take(sizeof(double) * 6 * pl.M * (size_t)g.N);
   pl.off_read = take(sizeof(double) * (10 * pl.M + 9) * (size_t)g.N);
   pl.off_part = take(sizeof(double) * DIAG_K * pl.nblocks);
   pl.total = o;
@@ -240,8 +245,8 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
   const Plan &P = c->pl;
   const Geom &g = P.g;
   // tables
-  std::vector<int> soff;
-  std::vector<double> seh;
+  std::vector<int> rofs((RING_MAX + 2) * MAXPAIRS, 0), roff;
+  std::vector<double> reh;
   StepArgs &a = c->args;
   memset(&a, 0, sizeof a);
   a.g = g;
@@ -258,20 +263,29 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
       const HostShell &h = P.shells[k];
       int idx = pair_index(P.M, pa, pb);
       double sab = 0.5 * (cfg->sigma[pa] + cfg->sigma[pb]);
-      a.t.pair_start[idx] = (int)soff.size();
-      a.t.pair_nplus[idx] = (int)h.e.size() / 3;
+      int R = h.maxc;
+      int W = FORCE_TX + 2 * R;
+      a.t.pair_R[idx] = R;
       a.t.pair_cmf[idx] = -cfg->kT * sab * sab * h.weight * 0.5;
       a.t.pair_cvisc[idx] = 2.0 * sab * sab * sqrt(cfg->kT / M_PI) * h.weight * 0.5;
       double ssum = cfg->sigma[pa] + cfg->sigma[pb];
       a.t.pair_d[idx] = ssum > 0.0 ? cfg->sigma[pa] * cfg->sigma[pb] / ssum : 0.0;
-      for (size_t j = 0; j < h.e.size(); j += 3) {
-        int ex = h.e[j], ey = h.e[j + 1], ez = h.e[j + 2];
-        soff.push_back(ex + g.PX * (ey + g.PY * ez));
-        double len = sqrt((double)(ex * ex + ey * ey + ez * ez));
-        seh.push_back(ex / len);
-        seh.push_back(ey / len);
-        seh.push_back(ez / len);
+      int *ofs = &rofs[idx * (RING_MAX + 2)];
+      size_t j = 0, np = h.e.size() / 3;
+      for (int ez = 0; ez <= R + 1 && ez <= RING_MAX + 1; ++ez) {
+        ofs[ez] = (int)roff.size();
+        while (j < np && h.e[3 * j + 2] == ez) {
+          int ex = h.e[3 * j], ey = h.e[3 * j + 1];
+          roff.push_back(ey * W + ex);
+          double len = sqrt((double)(ex * ex + ey * ey + ez * ez));
+          reh.push_back(ex / len);
+          reh.push_back(ey / len);
+          reh.push_back(ez / len);
+          ++j;
+        }
       }
+      for (int ez = R + 2; ez <= RING_MAX + 1; ++ez) ofs[ez] = (int)roff.size();
+      a.t.pair_nent[idx] = (int)np;
     }
   std::vector<int> boff;
   for (int s = 0; s < P.M; ++s) {
@@ -281,8 +295,10 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
     for (size_t j = 0; j < b.size(); j += 3) boff.push_back(b[j] + g.PX * (b[j + 1] + g.PY * b[j + 2]));
     a.t.sigma[s] = cfg->sigma[s];
   }
-  a.t.shell_off = c->at<int>(P.off_shell_off);
-  a.t.shell_ehat = c->at<double>(P.off_shell_e);
+  a.t.ring_ofs = c->at<int>(P.off_ring_ofs);
+  a.t.ring_off = c->at<int>(P.off_ring_off);
+  a.t.ring_e = c->at<double>(P.off_ring_e);
+  a.force = c->at<double>(P.off_force);
   a.t.ball_off = c->at<int>(P.off_ball);
   a.bb = c->at<uint32_t>(P.off_bb);
   a.Fext = c->at<double>(P.off_F);
@@ -308,8 +324,9 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
     return hipMemcpyAsync(c->ws + off, src, n, hipMemcpyHostToDevice, s) == hipSuccess;
   };
   if (hipMemsetAsync(c->ws, 0, P.total, s) != hipSuccess ||
-      !upload(P.off_shell_off, soff.data(), soff.size() * sizeof(int)) ||
-      !upload(P.off_shell_e, seh.data(), seh.size() * sizeof(double)) ||
+      !upload(P.off_ring_ofs, rofs.data(), rofs.size() * sizeof(int)) ||
+      !upload(P.off_ring_off, roff.data(), roff.size() * sizeof(int)) ||
+      !upload(P.off_ring_e, reh.data(), reh.size() * sizeof(double)) ||
       !upload(P.off_ball, boff.data(), boff.size() * sizeof(int)))
     rs = fail(LBE_ERR_HIP, "workspace initialisation failed");
   if (rs == LBE_OK) {
@@ -399,18 +416,19 @@ lbe_status lbe_init_density(lbe_ctx *c, int species, const double *n0, int where
 
 lbe_status lbe_step_phase(lbe_ctx *c, int phase) {
   if (!c) return fail(LBE_ERR_ARG, "null context");
-  if (phase < 0 || phase > 2) return fail(LBE_ERR_ARG, "phase must be 0, 1 or 2");
+  if (phase < 0 || phase > 3) return fail(LBE_ERR_ARG, "phase must be 0..3");
   if (c->poisoned) return fail(LBE_ERR_UNSTABLE, "context is unstable; reinitialise the state");
   if (phase != c->next_phase) return fail(LBE_ERR_STATE, "phase %d expected", c->next_phase);
   hipStream_t s = c->stream;
   if (phase == 0) launch_moments(c->args, c->cfg.prec, c->pop(c->cur), s);
   if (phase == 1) launch_contact(c->args, s);
-  if (phase == 2) {
+  if (phase == 2) launch_forces(c->args, s);
+  if (phase == 3) {
     launch_collide(c->args, c->cfg.prec, c->pop(c->cur), c->pop(c->cur ^ 1), s);
     c->cur ^= 1;
   }
   LAUNCH_CHECK();
-  c->next_phase = (phase + 1) % 3;
+  c->next_phase = (phase + 1) % 4;
   return LBE_OK;
 }
 
@@ -418,6 +436,7 @@ static lbe_status enqueue_step(lbe_ctx *c) {
   hipStream_t s = c->stream;
   launch_moments(c->args, c->cfg.prec, c->pop(c->cur), s);
   launch_contact(c->args, s);
+  launch_forces(c->args, s);
   launch_collide(c->args, c->cfg.prec, c->pop(c->cur), c->pop(c->cur ^ 1), s);
   LAUNCH_CHECK();
   c->cur ^= 1;
@@ -442,6 +461,7 @@ static lbe_status readout(lbe_ctx *c, bool *unstable) {
   hipStream_t s = c->stream;
   launch_moments(c->args, c->cfg.prec, c->pop(c->cur), s);
   launch_contact(c->args, s);
+  launch_forces(c->args, s);
   launch_readout(c->args, c->cfg.prec, c->pop(c->cur), c->rd, s);
   LAUNCH_CHECK();
   unsigned flag = 0;

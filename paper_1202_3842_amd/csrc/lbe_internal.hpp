@@ -37,13 +37,22 @@ __host__ __device__ inline long long padded_index(const Geom &g, int x, int y, i
   return (long long)(x + g.R) + (long long)g.PX * ((long long)(y + g.R) + (long long)g.PY * (z + g.R));
 }
 
-// Tables of the pair shells (half shells S+, as padded linear offsets and
-// unit vectors) and of the averaging balls.
+// Force-kernel tiling: a workgroup owns FORCE_TX x FORCE_TY output nodes and
+// marches over FORCE_ZC planes; shells reach at most RING_MAX nodes out.
+constexpr int FORCE_TX = 32, FORCE_TY = 8, FORCE_ZC = 8;
+constexpr int RING_MAX = 8;
+
+// Tables of the pair shells and of the averaging balls.  Each unordered pair
+// k has a half shell S+ (e_z > 0, or e_z = 0 with e_y > 0, or e_z = e_y = 0
+// with e_x > 0), stored ring by ring in e_z: entries ring_ofs[k][ez] ..
+// ring_ofs[k][ez+1]-1 hold the LDS offset e_y*W_k + e_x of the point in a
+// window of width W_k = FORCE_TX + 2 pair_R[k] and its unit vector.
 struct Tables {
-  const int *shell_off;       // all pairs' S+ offsets, concatenated
-  const double *shell_ehat;   // 3 doubles per offset
-  int pair_start[MAXPAIRS];
-  int pair_nplus[MAXPAIRS];
+  const int *ring_ofs;        // (RING_MAX + 2) per pair
+  const int *ring_off;        // one per S+ point, all pairs concatenated
+  const double *ring_e;       // 3 doubles per S+ point
+  int pair_R[MAXPAIRS];        // largest |component| of the pair's shell
+  int pair_nent[MAXPAIRS];     // points in the pair's half shell S+
   double pair_cmf[MAXPAIRS];   // -kT sigma_ab^2 w_ab / 2
   double pair_cvisc[MAXPAIRS]; //  2 sigma_ab^2 sqrt(kT/pi) w_ab / 2
   double pair_d[MAXPAIRS];     // sigma_a sigma_b / (sigma_a + sigma_b)
@@ -66,6 +75,7 @@ struct StepArgs {
   double *nfield;        // M * Np
   double *Gfield;        // npairs * Np
   double *Jfield;        // 3M * Np (only with LBE_VISC)
+  double *force;         // 6M * N: C^mf/n_a (3), C^visc/n_a (3) per species
   Tables t;
   unsigned *errflag;     // bit 0: packing fraction >= 1 or NaN
 };
@@ -83,6 +93,7 @@ void launch_zero_solid(const Geom &g, int M, int prec, void *pop, const uint32_t
                        long long stride, hipStream_t s);
 void launch_moments(const StepArgs &a, int prec, const void *pop, hipStream_t s);
 void launch_contact(const StepArgs &a, hipStream_t s);
+void launch_forces(const StepArgs &a, hipStream_t s);
 void launch_collide(const StepArgs &a, int prec, const void *pin, void *pout, hipStream_t s);
 void launch_readout(const StepArgs &a, int prec, const void *pin, const Readout &r, hipStream_t s);
 void launch_unstream(const Geom &g, int prec, const uint32_t *bb, const void *target_post,

@@ -13,8 +13,9 @@
 // Kernels per step
 //   k_moments  pull populations, n~ (and J~ with C^visc), write fields
 //   k_contact  ball-averaged densities -> BMCSL contact values G_ab
-//   k_collide  shell gather of C^mf (and C^visc), pull, inversion,
-//              equilibria, sources, trapezoidal BGK update, store
+//   k_force    LDS-tiled shell gather of C^mf (and C^visc) per species pair
+//   k_collide  pull, inversion, equilibria, sources, trapezoidal BGK
+//              update, store
 #include <math.h>
 
 #include "lbe_internal.hpp"
@@ -335,74 +336,201 @@ __global__ __launch_bounds__(BLOCK) void k_contact(StepArgs a) {
   for (int k = 0; k < NP; ++k) store_images(g, a.Gfield + (long long)k * g.Np, c, G[k]);
 }
 
-// Nonlocal forces at padded index P on the tilde moments:
-//   C^mf_a  = -kT n_a sum_b sigma_ab^2 w_ab sum_{e in S+} e^ [g(r,r+e) n_b(r+e)
-//                                                     - g(r,r-e) n_b(r-e)]
-//   C^visc_a = n_a sum_b 2 sigma_ab^2 sqrt(kT/pi) w_ab sum_e e^ (e^.(u_b(r+e)
-//                                              - u_b(r))) g(r,r+e) n_b(r+e)
-// with g(r,q) = (G(r) + G(q))/2 and n_b u_b = J~_b taken from the field.
-template <int M, bool VISC>
-__device__ inline void gather_forces(const StepArgs &a, long long P, double cmf[M][3],
-                                     double cvisc[M][3]) {
+// Nonlocal forces on the tilde moments, one directed species pair (a, b)
+// per launch, per particle of species a (the factor n_a(r) is applied by the
+// collision kernel):
+//   C^mf_a / n_a  += -kT sigma_ab^2 w_ab sum_{e in S+} e^ [g(r,r+e) n_b(r+e)
+//                                                    - g(r,r-e) n_b(r-e)]
+//   C^visc_a / n_a += 2 sigma_ab^2 sqrt(kT/pi) w_ab sum_e e^ (e^.(u_b(r+e)
+//                                      - u_b(r))) g(r,r+e) n_b(r+e)
+// with g(r,q) = (G_ab(r) + G_ab(q))/2 and n_b u_b = J~_b.
+//
+// Tiling: a workgroup owns an FTX x FTY tile of output nodes and marches
+// over FZC planes in z.  For each output plane it stages, per e_z = 0..R,
+// the two source planes z + e_z and z - e_z (with an R-wide halo in x and y)
+// in LDS and walks the ring of shell points with that e_z; the +e and -e
+// points of a pair sit in the two staged planes, so every pair is summed
+// together and a uniform state gives exactly zero.  LDS holds 2 planes of
+// n_b, G_ab (and J~_b with C^visc): 2 * NF * (FTX+2R)(FTY+2R) doubles.
+constexpr int FTX = FORCE_TX, FTY = FORCE_TY, FZC = FORCE_ZC;
+constexpr int FNT = FTX * FTY;
+
+// Read-only tables seen through the constant address space, so that loads
+// with a workgroup-uniform index become scalar loads.
+template <typename T>
+__device__ inline const __attribute__((address_space(4))) T *cptr(const T *p) {
+  return (const __attribute__((address_space(4))) T *)(p);
+}
+
+template <int R, bool VISC>
+__global__ __launch_bounds__(FNT) void k_force(StepArgs a, int alpha, int beta, int accumulate) {
+  extern __shared__ double lds[];
+  constexpr int NF = VISC ? 5 : 2;
+  constexpr int W = FTX + 2 * R, H = FTY + 2 * R, WH = W * H;
+  constexpr int SLOTS = (WH + FNT - 1) / FNT;   // window elements per thread and field
   const Geom &g = a.g;
-  for (int s = 0; s < M; ++s)
-    for (int k = 0; k < 3; ++k) cmf[s][k] = cvisc[s][k] = 0.0;
-  if (a.flags & LBE_IDEAL) return;
-  for (int s = 0; s < M; ++s) {
-    double ns = a.nfield[(long long)s * g.Np + P];
-    for (int b = 0; b < M; ++b) {
-      int k = pair_index(M, s, b);
-      int np = a.t.pair_nplus[k];
-      if (np == 0) continue;
-      const double *nb = a.nfield + (long long)b * g.Np + P;
-      const double *Gb = a.Gfield + (long long)k * g.Np + P;
-      const int *off = a.t.shell_off + a.t.pair_start[k];
-      const double *eh = a.t.shell_ehat + 3LL * a.t.pair_start[k];
-      double G0 = Gb[0];
-      double mx = 0.0, my = 0.0, mz = 0.0;
-      double vx = 0.0, vy = 0.0, vz = 0.0;
-      double u0x = 0.0, u0y = 0.0, u0z = 0.0;
-      const double *Jx = nullptr, *Jy = nullptr, *Jz = nullptr;
+  const int k = pair_index(a.M, alpha, beta);
+  const int t = threadIdx.x, tx = t % FTX, ty = t / FTX;
+  const int x0 = blockIdx.x * FTX, y0 = blockIdx.y * FTY;
+  const int x = x0 + tx, y = y0 + ty;
+  const bool valid = x < g.nx && y < g.ny;
+  const double *__restrict__ fld[5];
+  fld[0] = a.nfield + (long long)beta * g.Np;
+  fld[1] = a.Gfield + (long long)k * g.Np;
+  if (VISC) {
+    fld[2] = a.Jfield + (long long)(3 * beta) * g.Np;
+    fld[3] = fld[2] + g.Np;
+    fld[4] = fld[3] + g.Np;
+  }
+  const auto *ofs = cptr(a.t.ring_ofs + k * (RING_MAX + 2));
+  const auto *roff = cptr(a.t.ring_off);
+  const auto *re = cptr(a.t.ring_e);
+  const double cmf = a.t.pair_cmf[k], cvs = a.t.pair_cvisc[k];
+  const int base = (ty + R) * W + (tx + R);
+  // this thread's window slots: in-plane padded offset, or -1 outside the box
+  int soff[SLOTS];
+#pragma unroll
+  for (int q = 0; q < SLOTS; ++q) {
+    const int e = t + q * FNT;
+    const int c = e % W, r = e / W;
+    const int X = x0 - R + c + g.R, Y = y0 - R + r + g.R;
+    soff[q] = (e < WH && X < g.PX && Y < g.PY) ? X + g.PX * Y : -1;
+  }
+  // this pair's ring table, staged once in LDS behind the plane buffers as
+  // {e0, e1, e2, offset} per point, so the inner loop touches only LDS
+  int rofs[R + 2];
+#pragma unroll
+  for (int ez = 0; ez <= R + 1; ++ez) rofs[ez] = ofs[ez];
+  const int j0 = rofs[0], nent = rofs[R + 1] - rofs[0];
+  double *tab = lds + 2 * NF * WH;
+  for (int j = t; j < nent; j += FNT) {
+    tab[4 * j] = re[3 * (j0 + j)];
+    tab[4 * j + 1] = re[3 * (j0 + j) + 1];
+    tab[4 * j + 2] = re[3 * (j0 + j) + 2];
+    tab[4 * j + 3] = __longlong_as_double((long long)roff[j0 + j]);
+  }
+  const long long plane = (long long)g.PX * g.PY;
+  const int zb = blockIdx.z * FZC;
+  const int ze = zb + FZC < g.nz ? zb + FZC : g.nz;
+  const int rounds = (ze - zb) * (R + 1);
+  // planes of the next round, fetched while the current ring is computed:
+  // [plane b][field f][slot q]
+  double stage[2][NF][SLOTS];
+  auto fetch = [&](int rho) {
+    const int z = zb + rho / (R + 1), ez = rho % (R + 1);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const long long pz = (long long)((b ? z - ez : z + ez) + g.R) * plane;
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q)
+          stage[b][f][q] = (soff[q] >= 0 && (b == 0 || ez > 0)) ? fld[f][pz + soff[q]] : 0.0;
+    }
+  };
+  fetch(0);
+  double mx = 0.0, my = 0.0, mz = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
+  double G0 = 0.0, u0x = 0.0, u0y = 0.0, u0z = 0.0;
+  for (int rho = 0; rho < rounds; ++rho) {
+    const int z = zb + rho / (R + 1), ez = rho % (R + 1);
+    __syncthreads();  // previous round's readers are done with the buffers
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+          const int e = t + q * FNT;
+          if (q < SLOTS - 1 || e < WH) lds[(b * NF + f) * WH + e] = stage[b][f][q];
+        }
+    __syncthreads();
+    if (rho + 1 < rounds) fetch(rho + 1);
+    const double *Bp = lds;
+    const double *Bm = ez ? lds + NF * WH : lds;
+    if (ez == 0) {
+      mx = my = mz = vx = vy = vz = 0.0;
+      G0 = Bp[WH + base];
+      u0x = u0y = u0z = 0.0;
       if (VISC) {
-        Jx = a.Jfield + (long long)(3 * b) * g.Np + P;
-        Jy = Jx + g.Np;
-        Jz = Jy + g.Np;
-        double n0 = nb[0];
+        const double n0 = Bp[base];
         if (n0 != 0.0) {
-          u0x = Jx[0] / n0;
-          u0y = Jy[0] / n0;
-          u0z = Jz[0] / n0;
+          u0x = Bp[2 * WH + base] / n0;
+          u0y = Bp[3 * WH + base] / n0;
+          u0z = Bp[4 * WH + base] / n0;
         }
       }
-      for (int j = 0; j < np; ++j) {
-        int o = off[j];
-        double ex = eh[3 * j], ey = eh[3 * j + 1], ez = eh[3 * j + 2];
-        double npl = nb[o], nmi = nb[-o];
-        double gp = G0 + Gb[o], gm = G0 + Gb[-o];
-        double d = gp * npl - gm * nmi;
-        mx += ex * d;
-        my += ey * d;
-        mz += ez * d;
-        if (VISC) {
-          double eu = ex * u0x + ey * u0y + ez * u0z;
-          double tp = gp * (ex * Jx[o] + ey * Jy[o] + ez * Jz[o] - eu * npl);
-          double tm = gm * (ex * Jx[-o] + ey * Jy[-o] + ez * Jz[-o] - eu * nmi);
-          double t = tp + tm;
-          vx += ex * t;
-          vy += ey * t;
-          vz += ez * t;
-        }
-      }
-      double cm = a.t.pair_cmf[k] * ns;
-      cmf[s][0] += cm * mx;
-      cmf[s][1] += cm * my;
-      cmf[s][2] += cm * mz;
+    }
+    const int jbeg = rofs[ez] - j0, jend = rofs[ez + 1] - j0;
+    // one +-e pair: accumulate into (m, v)
+    auto pair = [&](int j, double &ax, double &ay, double &az, double &bx, double &by, double &bz) {
+      const double e0 = tab[4 * j], e1 = tab[4 * j + 1], e2 = tab[4 * j + 2];
+      const int o = (int)__double_as_longlong(tab[4 * j + 3]);
+      const int qa = base + o, qb = base - o;
+      const double npl = Bp[qa], nmi = Bm[qb];
+      const double gp = G0 + Bp[WH + qa], gm = G0 + Bm[WH + qb];
+      const double d = gp * npl - gm * nmi;
+      ax += e0 * d;
+      ay += e1 * d;
+      az += e2 * d;
       if (VISC) {
-        double cv = a.t.pair_cvisc[k] * ns;
-        cvisc[s][0] += cv * vx;
-        cvisc[s][1] += cv * vy;
-        cvisc[s][2] += cv * vz;
+        const double eu = e0 * u0x + e1 * u0y + e2 * u0z;
+        const double tp = gp * (e0 * Bp[2 * WH + qa] + e1 * Bp[3 * WH + qa] + e2 * Bp[4 * WH + qa] - eu * npl);
+        const double tm = gm * (e0 * Bm[2 * WH + qb] + e1 * Bm[3 * WH + qb] + e2 * Bm[4 * WH + qb] - eu * nmi);
+        const double tt = tp + tm;
+        bx += e0 * tt;
+        by += e1 * tt;
+        bz += e2 * tt;
       }
+    };
+    // two independent accumulator sets shorten the dependency chains; a
+    // pair's terms are still combined before they are accumulated, so a
+    // uniform state still sums to exactly zero
+    double mx2 = 0.0, my2 = 0.0, mz2 = 0.0, vx2 = 0.0, vy2 = 0.0, vz2 = 0.0;
+    int j = jbeg;
+    for (; j + 1 < jend; j += 2) {
+      pair(j, mx, my, mz, vx, vy, vz);
+      pair(j + 1, mx2, my2, mz2, vx2, vy2, vz2);
+    }
+    if (j < jend) pair(j, mx, my, mz, vx, vy, vz);
+    mx += mx2;
+    my += my2;
+    mz += mz2;
+    vx += vx2;
+    vy += vy2;
+    vz += vz2;
+    if (ez == R && valid) {
+      const long long N = g.N;
+      const long long i = x + (long long)g.nx * (y + (long long)g.ny * z);
+      double *F = a.force + 6LL * alpha * N + i;
+      if (accumulate) {
+        F[0] += cmf * mx;
+        F[N] += cmf * my;
+        F[2 * N] += cmf * mz;
+        F[3 * N] += cvs * vx;
+        F[4 * N] += cvs * vy;
+        F[5 * N] += cvs * vz;
+      } else {
+        F[0] = cmf * mx;
+        F[N] = cmf * my;
+        F[2 * N] = cmf * mz;
+        F[3 * N] = cvs * vx;
+        F[4 * N] = cvs * vy;
+        F[5 * N] = cvs * vz;
+      }
+    }
+  }
+}
+
+// per-particle forces of species s at node i, times n_s
+template <int M>
+__device__ inline void load_forces(const StepArgs &a, int i, const double n[M], double cmf[M][3],
+                                   double cvisc[M][3]) {
+  const long long N = a.g.N;
+  for (int s = 0; s < M; ++s) {
+    const double *F = a.force + 6LL * s * N + i;
+    for (int k = 0; k < 3; ++k) {
+      cmf[s][k] = n[s] * F[k * N];
+      cvisc[s][k] = n[s] * F[(3 + k) * N];
     }
   }
 }
@@ -508,7 +636,7 @@ __device__ inline void collide_all_p(const StepArgs &a, int s, const NodeMoments
   }
 }
 
-template <typename T, int M, bool VISC>
+template <typename T, int M>
 __global__ __launch_bounds__(BLOCK) void k_collide(StepArgs a, const T *__restrict__ pin,
                                                    T *__restrict__ pout) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -517,15 +645,15 @@ __global__ __launch_bounds__(BLOCK) void k_collide(StepArgs a, const T *__restri
   uint32_t m = a.bb[i];
   if (m & 1u) return;  // solid slots are never read
   Coord c = decode(g, i);
-  long long P = padded_index(g, c.x, c.y, c.z);
-  double cmf[M][3], cvisc[M][3];
-  gather_forces<M, VISC>(a, P, cmf, cvisc);
   long long Ns = pop_stride(g);
-  double ft[M][19], gt[M][19];
+  double ft[M][19], gt[M][19], n[M];
   for (int s = 0; s < M; ++s) {
     pull19(g, c, i, m, pin + (long long)s * Q * Ns, Ns, ft[s]);
     pull19(g, c, i, m, pin + (long long)(M + s) * Q * Ns, Ns, gt[s]);
+    moments0(ft[s], n[s]);
   }
+  double cmf[M][3], cvisc[M][3];
+  load_forces<M>(a, i, n, cmf, cvisc);
   NodeMoments<M> nm;
   invert<M>(a, ft, gt, cmf, cvisc, i, nm);
   for (int s = 0; s < M; ++s)
@@ -533,7 +661,7 @@ __global__ __launch_bounds__(BLOCK) void k_collide(StepArgs a, const T *__restri
                            pout + (long long)(M + s) * Q * Ns, Ns, i);
 }
 
-template <typename T, int M, bool VISC>
+template <typename T, int M>
 __global__ __launch_bounds__(BLOCK) void k_readout(StepArgs a, const T *__restrict__ pin, Readout r) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   const Geom &g = a.g;
@@ -557,15 +685,15 @@ __global__ __launch_bounds__(BLOCK) void k_readout(StepArgs a, const T *__restri
     return;
   }
   Coord c = decode(g, i);
-  long long P = padded_index(g, c.x, c.y, c.z);
-  double cmf[M][3], cvisc[M][3];
-  gather_forces<M, VISC>(a, P, cmf, cvisc);
   long long Ns = pop_stride(g);
-  double ft[M][19], gt[M][19];
+  double ft[M][19], gt[M][19], n[M];
   for (int s = 0; s < M; ++s) {
     pull19(g, c, i, m, pin + (long long)s * Q * Ns, Ns, ft[s]);
     pull19(g, c, i, m, pin + (long long)(M + s) * Q * Ns, Ns, gt[s]);
+    moments0(ft[s], n[s]);
   }
+  double cmf[M][3], cvisc[M][3];
+  load_forces<M>(a, i, n, cmf, cvisc);
   NodeMoments<M> nm;
   invert<M>(a, ft, gt, cmf, cvisc, i, nm);
   double jt[3] = {0.0, 0.0, 0.0}, js[3] = {0.0, 0.0, 0.0};
@@ -763,23 +891,60 @@ void launch_contact(const StepArgs &a, hipStream_t s) {
   }
 }
 
-template <typename T, int M>
-static void collide_dispatch(const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
-  bool visc = (a.flags & LBE_VISC) && !(a.flags & LBE_IDEAL);
-  dim3 gr = grid_for(a.g.N);
-  if (visc)
-    hipLaunchKernelGGL((k_collide<T, M, true>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, (T *)pout);
-  else
-    hipLaunchKernelGGL((k_collide<T, M, false>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, (T *)pout);
+template <int R, bool VISC>
+static void force_launch(const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
+  constexpr int NF = VISC ? 5 : 2;
+  const int k = pair_index(a.M, alpha, beta);
+  const size_t bytes = sizeof(double) * (2 * NF * (FTX + 2 * R) * (FTY + 2 * R) + 4 * a.t.pair_nent[k]);
+  static size_t attr = 0;
+  if (bytes > attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_force<R, VISC>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    attr = bytes;
+  }
+  dim3 gr((a.g.nx + FTX - 1) / FTX, (a.g.ny + FTY - 1) / FTY, (a.g.nz + FZC - 1) / FZC);
+  hipLaunchKernelGGL((k_force<R, VISC>), gr, dim3(FNT), bytes, s, a, alpha, beta, acc);
+}
+
+template <bool VISC>
+static void force_r(int R, const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
+  switch (R) {
+    case 1: force_launch<1, VISC>(a, alpha, beta, acc, s); break;
+    case 2: force_launch<2, VISC>(a, alpha, beta, acc, s); break;
+    case 3: force_launch<3, VISC>(a, alpha, beta, acc, s); break;
+    case 4: force_launch<4, VISC>(a, alpha, beta, acc, s); break;
+    case 5: force_launch<5, VISC>(a, alpha, beta, acc, s); break;
+    case 6: force_launch<6, VISC>(a, alpha, beta, acc, s); break;
+    case 7: force_launch<7, VISC>(a, alpha, beta, acc, s); break;
+    default: force_launch<8, VISC>(a, alpha, beta, acc, s); break;
+  }
+}
+
+void launch_forces(const StepArgs &a, hipStream_t s) {
+  if (a.flags & LBE_IDEAL) return;  // the force buffer stays zero
+  bool visc = (a.flags & LBE_VISC) != 0;
+  for (int al = 0; al < a.M; ++al) {
+    int written = 0;
+    for (int be = 0; be < a.M; ++be) {
+      int R = a.t.pair_R[pair_index(a.M, al, be)];
+      if (R == 0) continue;  // empty shell
+      if (visc)
+        force_r<true>(R, a, al, be, written, s);
+      else
+        force_r<false>(R, a, al, be, written, s);
+      written = 1;
+    }
+  }
 }
 
 template <typename T>
 static void collide_m(const StepArgs &a, const void *pin, void *pout, hipStream_t s) {
+  dim3 gr = grid_for(a.g.N);
   switch (a.M) {
-    case 1: collide_dispatch<T, 1>(a, pin, pout, s); break;
-    case 2: collide_dispatch<T, 2>(a, pin, pout, s); break;
-    case 3: collide_dispatch<T, 3>(a, pin, pout, s); break;
-    default: collide_dispatch<T, 4>(a, pin, pout, s); break;
+    case 1: hipLaunchKernelGGL((k_collide<T, 1>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, (T *)pout); break;
+    case 2: hipLaunchKernelGGL((k_collide<T, 2>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, (T *)pout); break;
+    case 3: hipLaunchKernelGGL((k_collide<T, 3>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, (T *)pout); break;
+    default: hipLaunchKernelGGL((k_collide<T, 4>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, (T *)pout); break;
   }
 }
 
@@ -790,23 +955,14 @@ void launch_collide(const StepArgs &a, int prec, const void *pin, void *pout, hi
     collide_m<float>(a, pin, pout, s);
 }
 
-template <typename T, int M>
-static void readout_dispatch(const StepArgs &a, const void *pin, const Readout &r, hipStream_t s) {
-  bool visc = (a.flags & LBE_VISC) && !(a.flags & LBE_IDEAL);
-  dim3 gr = grid_for(a.g.N);
-  if (visc)
-    hipLaunchKernelGGL((k_readout<T, M, true>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, r);
-  else
-    hipLaunchKernelGGL((k_readout<T, M, false>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, r);
-}
-
 template <typename T>
 static void readout_m(const StepArgs &a, const void *pin, const Readout &r, hipStream_t s) {
+  dim3 gr = grid_for(a.g.N);
   switch (a.M) {
-    case 1: readout_dispatch<T, 1>(a, pin, r, s); break;
-    case 2: readout_dispatch<T, 2>(a, pin, r, s); break;
-    case 3: readout_dispatch<T, 3>(a, pin, r, s); break;
-    default: readout_dispatch<T, 4>(a, pin, r, s); break;
+    case 1: hipLaunchKernelGGL((k_readout<T, 1>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, r); break;
+    case 2: hipLaunchKernelGGL((k_readout<T, 2>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, r); break;
+    case 3: hipLaunchKernelGGL((k_readout<T, 3>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, r); break;
+    default: hipLaunchKernelGGL((k_readout<T, 4>), gr, dim3(BLOCK), 0, s, a, (const T *)pin, r); break;
   }
 }
 
