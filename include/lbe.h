@@ -187,6 +187,38 @@ lbe_status lbe_diagnostics(lbe_ctx *ctx, lbe_diag *out);
 /* Block until all work queued by the context has finished. */
 lbe_status lbe_synchronize(lbe_ctx *ctx);
 
+/* z planes per workgroup of the force kernel (a tiling parameter: results
+ * do not depend on it; the autotuner sets it).  1 <= zchunk <= nz. */
+lbe_status lbe_set_force_zchunk(lbe_ctx *ctx, int zchunk);
+
+/* ---- batched boxes --------------------------------------------------------
+ * Many independent one-component boxes of different sizes and diameters
+ * stepped together: every phase of a step is one launch covering all boxes
+ * (one force launch per distinct shell range), and the launches of two
+ * steps are captured once in a HIP graph and replayed.  The results are
+ * bitwise those of stepping each box alone.  All boxes must have
+ * nspecies = 1 and share prec and flags. */
+typedef struct lbe_batch lbe_batch;
+
+/* Device workspace for a batch of nboxes configurations, or 0 if invalid. */
+size_t lbe_batch_workspace_bytes(const lbe_config *cfgs, int nboxes);
+
+/* Create the batch and its member contexts (see lbe_batch_box) in one
+ * caller-owned workspace, all on one HIP stream. */
+lbe_status lbe_batch_create(const lbe_config *cfgs, int nboxes, void *dev_workspace,
+                            size_t bytes, void *hip_stream, lbe_batch **out);
+
+/* The member context of box i (owned by the batch): use it with every
+ * single-box setter, getter and lbe_diagnostics. */
+lbe_ctx *lbe_batch_box(lbe_batch *batch, int box);
+
+/* Step every box nsteps times.  mode 0 = box after box with per-box
+ * launches (the reference serial schedule), 1 = batched launches,
+ * 2 = batched launches replayed from a captured HIP graph (default). */
+lbe_status lbe_batch_step(lbe_batch *batch, int nsteps, int mode);
+
+void lbe_batch_destroy(lbe_batch *batch);
+
 /* Thread-local text of the last failure (never NULL). */
 const char *lbe_last_error(void);
 

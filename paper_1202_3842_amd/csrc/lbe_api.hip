@@ -257,6 +257,9 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
   a.bcoef = 1.0 / (1.0 + 0.5 * omega);
   a.beta = 1.0 / cfg->kT;
   a.kappa = (cfg->flags & LBE_KAPPA4) ? 4.0 : 2.0;
+  a.zchunk = FORCE_ZC < g.nz ? FORCE_ZC : g.nz;
+  a.pop[0] = c->pop(0);
+  a.pop[1] = c->pop(1);
   int k = 0;
   for (int pa = 0; pa < P.M; ++pa)
     for (int pb = pa; pb < P.M; ++pb, ++k) {
@@ -582,10 +585,289 @@ lbe_status lbe_diagnostics(lbe_ctx *c, lbe_diag *out) {
   return LBE_OK;
 }
 
+lbe_status lbe_set_force_zchunk(lbe_ctx *c, int zchunk) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  if (zchunk < 1 || zchunk > c->pl.g.nz) return fail(LBE_ERR_ARG, "zchunk must lie in [1, nz]");
+  c->args.zchunk = zchunk;
+  return LBE_OK;
+}
+
 lbe_status lbe_synchronize(lbe_ctx *c) {
   if (!c) return fail(LBE_ERR_ARG, "null context");
   HIP_TRY(hipStreamSynchronize(c->stream));
   return LBE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched boxes.  Workspace: the device array of per-box parameter blocks,
+// the block -> box tables of the node-parallel kernels and of each force
+// group (boxes sharing a shell range), then every member box's workspace.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchPlan {
+  std::vector<size_t> box_bytes, box_off;
+  size_t off_args = 0, off_nodebox = 0, off_nodestart = 0, off_force = 0, total = 0;
+  int node_blocks = 0;
+  size_t force_bytes = 0;  // reserved for the force-group tables
+};
+
+// force-group tables are sized for the smallest zchunk (1), so that any
+// later zchunk choice fits
+size_t force_table_bytes(const std::vector<Plan> &plans) {
+  size_t blocks = 0;
+  for (const Plan &p : plans) blocks += force_blocks(p.g, 1);
+  return align256(sizeof(int) * blocks) * 1 + align256(sizeof(int) * plans.size()) * (RING_MAX + 1) +
+         align256(sizeof(int) * blocks) * RING_MAX;
+}
+
+lbe_status make_batch_plan(const lbe_config *cfgs, int nboxes, BatchPlan &bp) {
+  if (!cfgs || nboxes < 1) return fail(LBE_ERR_ARG, "need at least one box");
+  std::vector<Plan> plans(nboxes);
+  for (int b = 0; b < nboxes; ++b) {
+    lbe_status st = make_plan(&cfgs[b], plans[b]);
+    if (st != LBE_OK) return fail(st, "box %d: %s", b, g_err);
+    if (cfgs[b].nspecies != 1) return fail(LBE_ERR_UNSUPPORTED, "batched boxes must have one species");
+    if (cfgs[b].prec != cfgs[0].prec || cfgs[b].flags != cfgs[0].flags)
+      return fail(LBE_ERR_ARG, "batched boxes must share precision and flags");
+  }
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  bp.node_blocks = 0;
+  for (const Plan &p : plans) bp.node_blocks += node_blocks(p.g);
+  bp.off_args = take(sizeof(StepArgs) * nboxes);
+  bp.off_nodebox = take(sizeof(int) * bp.node_blocks);
+  bp.off_nodestart = take(sizeof(int) * nboxes);
+  bp.force_bytes = force_table_bytes(plans);
+  bp.off_force = take(bp.force_bytes);
+  for (const Plan &p : plans) {
+    bp.box_bytes.push_back(p.total);
+    bp.box_off.push_back(take(p.total));
+  }
+  bp.total = o;
+  return LBE_OK;
+}
+
+}  // namespace
+
+struct lbe_batch {
+  std::vector<lbe_ctx *> boxes;
+  BatchPlan bp;
+  char *ws = nullptr;
+  hipStream_t stream = nullptr;
+  int prec = 0;
+  bool visc = false;
+  struct Group {
+    int R, nblocks, entries;
+    int *blockbox, *blockstart;
+  };
+  std::vector<Group> groups;
+  std::vector<int> zchunks;          // the zchunk of each box the tables were built for
+  std::vector<StepArgs> uploaded;    // the parameter blocks last copied to the device
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+
+  void drop_graphs() {
+    for (auto &gx : graph)
+      if (gx) {
+        (void)hipGraphExecDestroy(gx);
+        gx = nullptr;
+      }
+  }
+};
+
+namespace {
+
+// (re)build the force-group block tables if any box's zchunk changed
+lbe_status batch_tables(lbe_batch *B) {
+  int n = (int)B->boxes.size();
+  bool same = (int)B->zchunks.size() == n;
+  for (int b = 0; same && b < n; ++b) same = B->zchunks[b] == B->boxes[b]->args.zchunk;
+  if (same) return LBE_OK;
+  B->drop_graphs();
+  B->groups.clear();
+  B->zchunks.assign(n, 0);
+  char *base = B->ws + B->bp.off_force;
+  size_t used = 0;
+  int maxR = 0, maxent = 0;
+  for (int R = 1; R <= RING_MAX; ++R) {
+    std::vector<int> box_of_block, start(n, 0);
+    int ent = 0;
+    for (int b = 0; b < n; ++b) {
+      const StepArgs &a = B->boxes[b]->args;
+      if (a.t.pair_R[0] != R) continue;
+      start[b] = (int)box_of_block.size();
+      int nb = force_blocks(a.g, a.zchunk);
+      box_of_block.insert(box_of_block.end(), nb, b);
+      ent = std::max(ent, a.t.pair_nent[0]);
+    }
+    if (box_of_block.empty()) continue;
+    lbe_batch::Group G;
+    G.R = R;
+    G.nblocks = (int)box_of_block.size();
+    G.entries = ent;
+    G.blockbox = (int *)(base + used);
+    used += align256(sizeof(int) * box_of_block.size());
+    G.blockstart = (int *)(base + used);
+    used += align256(sizeof(int) * n);
+    if (used > B->bp.force_bytes) return fail(LBE_ERR_OOM, "force tables exceed their reservation");
+    HIP_TRY(hipMemcpy(G.blockbox, box_of_block.data(), sizeof(int) * box_of_block.size(),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(G.blockstart, start.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+    B->groups.push_back(G);
+    maxR = std::max(maxR, R);
+    maxent = std::max(maxent, ent);
+  }
+  prepare_force_kernels(maxR, B->visc, maxent);
+  for (int b = 0; b < n; ++b) B->zchunks[b] = B->boxes[b]->args.zchunk;
+  return LBE_OK;
+}
+
+// copy the members' parameter blocks to the device when they changed
+lbe_status batch_upload(lbe_batch *B) {
+  int n = (int)B->boxes.size();
+  std::vector<StepArgs> now(n);
+  for (int b = 0; b < n; ++b) now[b] = B->boxes[b]->args;
+  if (B->uploaded.size() == now.size() &&
+      memcmp(B->uploaded.data(), now.data(), sizeof(StepArgs) * n) == 0)
+    return LBE_OK;
+  HIP_TRY(hipMemcpyAsync(B->ws + B->bp.off_args, now.data(), sizeof(StepArgs) * n,
+                         hipMemcpyHostToDevice, B->stream));
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  B->uploaded = now;
+  return LBE_OK;
+}
+
+void batch_launch_step(lbe_batch *B, int cur) {
+  BatchArgs ba;
+  ba.boxes = (const StepArgs *)(B->ws + B->bp.off_args);
+  ba.blockbox = (const int *)(B->ws + B->bp.off_nodebox);
+  ba.blockstart = (const int *)(B->ws + B->bp.off_nodestart);
+  ba.cur = cur;
+  launch_batch_moments(ba, B->bp.node_blocks, B->prec, B->visc, B->stream);
+  launch_batch_contact(ba, B->bp.node_blocks, B->stream);
+  for (const auto &G : B->groups) {
+    BatchArgs bf = ba;
+    bf.blockbox = G.blockbox;
+    bf.blockstart = G.blockstart;
+    launch_batch_force(bf, G.nblocks, G.R, B->visc, G.entries, B->stream);
+  }
+  launch_batch_collide(ba, B->bp.node_blocks, B->prec, B->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbe_batch_workspace_bytes(const lbe_config *cfgs, int nboxes) {
+  BatchPlan bp;
+  if (make_batch_plan(cfgs, nboxes, bp) != LBE_OK) return 0;
+  return bp.total;
+}
+
+lbe_status lbe_batch_create(const lbe_config *cfgs, int nboxes, void *ws, size_t bytes, void *stream,
+                            lbe_batch **out) {
+  if (!out) return fail(LBE_ERR_ARG, "null output pointer");
+  *out = nullptr;
+  BatchPlan bp;
+  lbe_status st = make_batch_plan(cfgs, nboxes, bp);
+  if (st != LBE_OK) return st;
+  if (!ws || ((uintptr_t)ws & 255u)) return fail(LBE_ERR_ARG, "workspace must be 256-byte aligned");
+  if (bytes < bp.total) return fail(LBE_ERR_OOM, "workspace of %zu bytes, %zu needed", bytes, bp.total);
+  lbe_batch *B = new (std::nothrow) lbe_batch();
+  if (!B) return fail(LBE_ERR_OOM, "host allocation failed");
+  B->bp = bp;
+  B->ws = (char *)ws;
+  B->stream = (hipStream_t)stream;
+  B->prec = cfgs[0].prec;
+  B->visc = (cfgs[0].flags & LBE_VISC) && !(cfgs[0].flags & LBE_IDEAL);
+  std::vector<int> nodebox, nodestart(nboxes);
+  for (int b = 0; b < nboxes; ++b) {
+    lbe_ctx *c = nullptr;
+    st = lbe_create(&cfgs[b], B->ws + bp.box_off[b], bp.box_bytes[b], stream, &c);
+    if (st != LBE_OK) {
+      lbe_batch_destroy(B);
+      return st;
+    }
+    B->boxes.push_back(c);
+    nodestart[b] = (int)nodebox.size();
+    nodebox.insert(nodebox.end(), node_blocks(c->pl.g), b);
+  }
+  if (hipMemcpy(B->ws + bp.off_nodebox, nodebox.data(), sizeof(int) * nodebox.size(),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(B->ws + bp.off_nodestart, nodestart.data(), sizeof(int) * nboxes,
+                hipMemcpyHostToDevice) != hipSuccess) {
+    lbe_batch_destroy(B);
+    return fail(LBE_ERR_HIP, "batch table upload failed");
+  }
+  *out = B;
+  return LBE_OK;
+}
+
+lbe_ctx *lbe_batch_box(lbe_batch *B, int box) {
+  if (!B || box < 0 || box >= (int)B->boxes.size()) {
+    fail(LBE_ERR_ARG, "bad box index");
+    return nullptr;
+  }
+  return B->boxes[box];
+}
+
+lbe_status lbe_batch_step(lbe_batch *B, int nsteps, int mode) {
+  if (!B) return fail(LBE_ERR_ARG, "null batch");
+  if (nsteps < 0 || mode < 0 || mode > 2) return fail(LBE_ERR_ARG, "bad nsteps or mode");
+  if (mode == 0) {
+    for (lbe_ctx *c : B->boxes) {
+      lbe_status st = lbe_step(c, nsteps);
+      if (st != LBE_OK) return st;
+    }
+    return LBE_OK;
+  }
+  int cur = B->boxes[0]->cur;
+  for (size_t b = 0; b < B->boxes.size(); ++b) {
+    lbe_ctx *c = B->boxes[b];
+    if (c->poisoned) return fail(LBE_ERR_UNSTABLE, "box %zu is unstable; reinitialise it", b);
+    if (c->next_phase != 0) return fail(LBE_ERR_STATE, "box %zu has an incomplete phased step", b);
+    if (c->cur != cur) return fail(LBE_ERR_STATE, "boxes are at different buffer parities");
+  }
+  lbe_status st = batch_tables(B);
+  if (st != LBE_OK) return st;
+  st = batch_upload(B);
+  if (st != LBE_OK) return st;
+  int left = nsteps;
+  if (mode == 2) {
+    if (left >= 2 && !B->graph[cur]) {
+      hipGraph_t gr = nullptr;
+      HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+      batch_launch_step(B, cur);
+      batch_launch_step(B, cur ^ 1);
+      HIP_TRY(hipStreamEndCapture(B->stream, &gr));
+      hipError_t e = hipGraphInstantiate(&B->graph[cur], gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      if (e != hipSuccess) return fail(LBE_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    for (; left >= 2; left -= 2) HIP_TRY(hipGraphLaunch(B->graph[cur], B->stream));
+  }
+  for (; left > 0; --left) {
+    batch_launch_step(B, cur);
+    cur ^= 1;
+  }
+  LAUNCH_CHECK();
+  if (nsteps & 1)
+    for (lbe_ctx *c : B->boxes) c->cur ^= 1;
+  return LBE_OK;
+}
+
+void lbe_batch_destroy(lbe_batch *B) {
+  if (!B) return;
+  (void)hipStreamSynchronize(B->stream);
+  B->drop_graphs();
+  for (lbe_ctx *c : B->boxes) lbe_destroy(c);
+  delete B;
 }
 
 }  // extern "C"

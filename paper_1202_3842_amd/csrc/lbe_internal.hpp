@@ -62,7 +62,7 @@ struct Tables {
   double sigma[MAXM];
 };
 
-struct StepArgs {
+struct alignas(8) StepArgs {
   Geom g;
   int M;
   unsigned flags;
@@ -76,8 +76,19 @@ struct StepArgs {
   double *Gfield;        // npairs * Np
   double *Jfield;        // 3M * Np (only with LBE_VISC)
   double *force;         // 6M * N: C^mf/n_a (3), C^visc/n_a (3) per species
+  void *pop[2];          // the two ping-pong population buffers
+  int zchunk;            // z planes per force-kernel workgroup
   Tables t;
   unsigned *errflag;     // bit 0: packing fraction >= 1 or NaN
+};
+
+// A batch launch: every block finds its box in blockbox and its first
+// block in blockstart; cur selects the ping-pong buffer holding the state.
+struct BatchArgs {
+  const StepArgs *boxes;
+  const int *blockbox;
+  const int *blockstart;
+  int cur;
 };
 
 // Per-node outputs of the read-out pass (component-major, N each):
@@ -111,6 +122,15 @@ void launch_diag_errn(const Geom &g, int M, const uint32_t *bb, const Readout &r
                       const double *V, double beta, const double *result, double *partials,
                       int nblocks, hipStream_t s);
 int diag_nblocks(const Geom &g);
+// blocks of the node-parallel kernels and of the force kernel for one box
+int node_blocks(const Geom &g);
+int force_blocks(const Geom &g, int zchunk);
+// batched launches (M = 1 boxes sharing precision and flags)
+void launch_batch_moments(const BatchArgs &b, int nblocks, int prec, bool visc, hipStream_t s);
+void launch_batch_contact(const BatchArgs &b, int nblocks, hipStream_t s);
+void launch_batch_force(const BatchArgs &b, int nblocks, int R, bool visc, int entries, hipStream_t s);
+void launch_batch_collide(const BatchArgs &b, int nblocks, int prec, hipStream_t s);
+void prepare_force_kernels(int maxR, bool visc, int max_entries);
 constexpr int DIAG_K = 12;  // reduced quantities per block
 
 }  // namespace lbe

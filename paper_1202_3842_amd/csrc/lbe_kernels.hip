@@ -38,6 +38,31 @@ __host__ __device__ constexpr double wgt(int p) {
   return p == 0 ? 1.0 / 3.0 : (p <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
 
+// Read-only tables seen through the constant address space, so that loads
+// with a workgroup-uniform index become scalar loads.
+template <typename T>
+__device__ inline const __attribute__((address_space(4))) T *cptr(const T *p) {
+  return (const __attribute__((address_space(4))) T *)(p);
+}
+
+// The lattice geometry as a local value (member-wise, so it also works when
+// the parameter block lives in the constant address space of a batch).
+template <class A>
+__device__ inline Geom geom_of(const A &a) {
+  Geom g;
+  g.nx = a.g.nx;
+  g.ny = a.g.ny;
+  g.nz = a.g.nz;
+  g.N = a.g.N;
+  g.R = a.g.R;
+  g.PX = a.g.PX;
+  g.PY = a.g.PY;
+  g.PZ = a.g.PZ;
+  g.Np = a.g.Np;
+  g.periodic = a.g.periodic;
+  return g;
+}
+
 template <typename T>
 __device__ inline double ld(const T *__restrict__ a, long long i) {
   return (double)a[i];
@@ -266,10 +291,9 @@ __global__ void k_pull(Geom g, const uint32_t *__restrict__ bb, const T *__restr
 // ------------------------------------------------------------------------
 // step kernels
 // ------------------------------------------------------------------------
-template <typename T, bool VISC>
-__global__ __launch_bounds__(BLOCK) void k_moments(StepArgs a, const T *__restrict__ pop) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const Geom &g = a.g;
+template <typename T, bool VISC, class A>
+__device__ inline void moments_body(const A &a, const T *__restrict__ pop, int i) {
+  const Geom g = geom_of(a);
   if (i >= g.N) return;
   Coord c = decode(g, i);
   uint32_t m = a.bb[i];
@@ -291,12 +315,16 @@ __global__ __launch_bounds__(BLOCK) void k_moments(StepArgs a, const T *__restri
   }
 }
 
+template <typename T, bool VISC>
+__global__ __launch_bounds__(BLOCK) void k_moments(StepArgs a, const T *__restrict__ pop) {
+  moments_body<T, VISC>(a, pop, blockIdx.x * BLOCK + threadIdx.x);
+}
+
 // Weighted densities (ball of radius sigma_b/2, normalised by its size) and
 // the BMCSL contact values G_ab(r) of every pair.
-template <int M>
-__global__ __launch_bounds__(BLOCK) void k_contact(StepArgs a) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const Geom &g = a.g;
+template <int M, class A>
+__device__ inline void contact_body(const A &a, int i) {
+  const Geom g = geom_of(a);
   if (i >= g.N) return;
   Coord c = decode(g, i);
   constexpr int NP = M * (M + 1) / 2;
@@ -336,6 +364,11 @@ __global__ __launch_bounds__(BLOCK) void k_contact(StepArgs a) {
   for (int k = 0; k < NP; ++k) store_images(g, a.Gfield + (long long)k * g.Np, c, G[k]);
 }
 
+template <int M>
+__global__ __launch_bounds__(BLOCK) void k_contact(StepArgs a) {
+  contact_body<M>(a, blockIdx.x * BLOCK + threadIdx.x);
+}
+
 // Nonlocal forces on the tilde moments, one directed species pair (a, b)
 // per launch, per particle of species a (the factor n_a(r) is applied by the
 // collision kernel):
@@ -346,32 +379,26 @@ __global__ __launch_bounds__(BLOCK) void k_contact(StepArgs a) {
 // with g(r,q) = (G_ab(r) + G_ab(q))/2 and n_b u_b = J~_b.
 //
 // Tiling: a workgroup owns an FTX x FTY tile of output nodes and marches
-// over FZC planes in z.  For each output plane it stages, per e_z = 0..R,
+// over zchunk planes in z.  For each output plane it stages, per e_z = 0..R,
 // the two source planes z + e_z and z - e_z (with an R-wide halo in x and y)
 // in LDS and walks the ring of shell points with that e_z; the +e and -e
 // points of a pair sit in the two staged planes, so every pair is summed
 // together and a uniform state gives exactly zero.  LDS holds 2 planes of
 // n_b, G_ab (and J~_b with C^visc): 2 * NF * (FTX+2R)(FTY+2R) doubles.
-constexpr int FTX = FORCE_TX, FTY = FORCE_TY, FZC = FORCE_ZC;
+constexpr int FTX = FORCE_TX, FTY = FORCE_TY;
 constexpr int FNT = FTX * FTY;
 
-// Read-only tables seen through the constant address space, so that loads
-// with a workgroup-uniform index become scalar loads.
-template <typename T>
-__device__ inline const __attribute__((address_space(4))) T *cptr(const T *p) {
-  return (const __attribute__((address_space(4))) T *)(p);
-}
 
-template <int R, bool VISC>
-__global__ __launch_bounds__(FNT) void k_force(StepArgs a, int alpha, int beta, int accumulate) {
-  extern __shared__ double lds[];
+template <int R, bool VISC, class A>
+__device__ inline void force_body(const A &a, int alpha, int beta, int accumulate, int bx,
+                                  int by, int bz, double *lds) {
   constexpr int NF = VISC ? 5 : 2;
   constexpr int W = FTX + 2 * R, H = FTY + 2 * R, WH = W * H;
   constexpr int SLOTS = (WH + FNT - 1) / FNT;   // window elements per thread and field
-  const Geom &g = a.g;
+  const Geom g = geom_of(a);
   const int k = pair_index(a.M, alpha, beta);
   const int t = threadIdx.x, tx = t % FTX, ty = t / FTX;
-  const int x0 = blockIdx.x * FTX, y0 = blockIdx.y * FTY;
+  const int x0 = bx * FTX, y0 = by * FTY;
   const int x = x0 + tx, y = y0 + ty;
   const bool valid = x < g.nx && y < g.ny;
   const double *__restrict__ fld[5];
@@ -410,8 +437,8 @@ __global__ __launch_bounds__(FNT) void k_force(StepArgs a, int alpha, int beta, 
     tab[4 * j + 3] = __longlong_as_double((long long)roff[j0 + j]);
   }
   const long long plane = (long long)g.PX * g.PY;
-  const int zb = blockIdx.z * FZC;
-  const int ze = zb + FZC < g.nz ? zb + FZC : g.nz;
+  const int zb = bz * a.zchunk;
+  const int ze = zb + a.zchunk < g.nz ? zb + a.zchunk : g.nz;
   const int rounds = (ze - zb) * (R + 1);
   // planes of the next round, fetched while the current ring is computed:
   // [plane b][field f][slot q]
@@ -521,9 +548,15 @@ __global__ __launch_bounds__(FNT) void k_force(StepArgs a, int alpha, int beta, 
   }
 }
 
+template <int R, bool VISC>
+__global__ __launch_bounds__(FNT) void k_force(StepArgs a, int alpha, int beta, int accumulate) {
+  extern __shared__ double lds[];
+  force_body<R, VISC>(a, alpha, beta, accumulate, blockIdx.x, blockIdx.y, blockIdx.z, lds);
+}
+
 // per-particle forces of species s at node i, times n_s
-template <int M>
-__device__ inline void load_forces(const StepArgs &a, int i, const double n[M], double cmf[M][3],
+template <int M, class A>
+__device__ inline void load_forces(const A &a, int i, const double n[M], double cmf[M][3],
                                    double cvisc[M][3]) {
   const long long N = a.g.N;
   for (int s = 0; s < M; ++s) {
@@ -550,8 +583,8 @@ struct NodeMoments {
   double u[3];
 };
 
-template <int M>
-__device__ inline void invert(const StepArgs &a, const double ft[M][19], const double gt[M][19],
+template <int M, class A>
+__device__ inline void invert(const A &a, const double ft[M][19], const double gt[M][19],
                               const double cmf[M][3], const double cvisc[M][3], int i,
                               NodeMoments<M> &nm) {
   const bool printed = a.flags & LBE_PRINTED_INV;
@@ -597,8 +630,8 @@ __device__ inline double cdot(const double v[3]) {
 
 template <int p>
 struct CollideP {
-  template <typename T, int M>
-  __device__ static inline void run(const StepArgs &a, int s, const NodeMoments<M> &nm,
+  template <typename T, int M, class A>
+  __device__ static inline void run(const A &a, int s, const NodeMoments<M> &nm,
                                     const double cm[3], const double ft, const double gt,
                                     T *__restrict__ fo, T *__restrict__ go) {
     const double w = wgt(p);
@@ -625,22 +658,21 @@ struct CollideP {
   }
 };
 
-template <typename T, int M, int p>
-__device__ inline void collide_all_p(const StepArgs &a, int s, const NodeMoments<M> &nm,
+template <typename T, int M, int p, class A>
+__device__ inline void collide_all_p(const A &a, int s, const NodeMoments<M> &nm,
                                      const double cm[3], const double ft[19], const double gt[19],
                                      T *__restrict__ fblk, T *__restrict__ gblk, long long Ns, int i) {
   if constexpr (p < Q) {
-    CollideP<p>::template run<T, M>(a, s, nm, cm, ft[p], gt[p], fblk + (long long)p * Ns + i,
+    CollideP<p>::template run<T, M, A>(a, s, nm, cm, ft[p], gt[p], fblk + (long long)p * Ns + i,
                                     gblk + (long long)p * Ns + i);
-    collide_all_p<T, M, p + 1>(a, s, nm, cm, ft, gt, fblk, gblk, Ns, i);
+    collide_all_p<T, M, p + 1, A>(a, s, nm, cm, ft, gt, fblk, gblk, Ns, i);
   }
 }
 
-template <typename T, int M>
-__global__ __launch_bounds__(BLOCK) void k_collide(StepArgs a, const T *__restrict__ pin,
-                                                   T *__restrict__ pout) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const Geom &g = a.g;
+template <typename T, int M, class A>
+__device__ inline void collide_body(const A &a, const T *__restrict__ pin, T *__restrict__ pout,
+                                    int i) {
+  const Geom g = geom_of(a);
   if (i >= g.N) return;
   uint32_t m = a.bb[i];
   if (m & 1u) return;  // solid slots are never read
@@ -662,9 +694,53 @@ __global__ __launch_bounds__(BLOCK) void k_collide(StepArgs a, const T *__restri
 }
 
 template <typename T, int M>
+__global__ __launch_bounds__(BLOCK) void k_collide(StepArgs a, const T *__restrict__ pin,
+                                                   T *__restrict__ pout) {
+  collide_body<T, M>(a, pin, pout, blockIdx.x * BLOCK + threadIdx.x);
+}
+
+// ------------------------------------------------------------------------
+// batched kernels: one launch covers every box of a batch.  Each block looks
+// up its box in a block -> box table and reads that box's parameter block
+// through scalar loads; the per-box bodies are the single-box ones.
+// ------------------------------------------------------------------------
+template <typename T, bool VISC>
+__global__ __launch_bounds__(BLOCK) void kb_moments(BatchArgs ba) {
+  const int b = cptr(ba.blockbox)[blockIdx.x];
+  const auto &a = *cptr(ba.boxes + b);
+  const int i = (blockIdx.x - cptr(ba.blockstart)[b]) * BLOCK + threadIdx.x;
+  moments_body<T, VISC>(a, (const T *)a.pop[ba.cur], i);
+}
+
+__global__ __launch_bounds__(BLOCK) void kb_contact(BatchArgs ba) {
+  const int b = cptr(ba.blockbox)[blockIdx.x];
+  const auto &a = *cptr(ba.boxes + b);
+  const int i = (blockIdx.x - cptr(ba.blockstart)[b]) * BLOCK + threadIdx.x;
+  contact_body<1>(a, i);
+}
+
+template <int R, bool VISC>
+__global__ __launch_bounds__(FNT) void kb_force(BatchArgs ba) {
+  extern __shared__ double lds[];
+  const int b = cptr(ba.blockbox)[blockIdx.x];
+  const auto &a = *cptr(ba.boxes + b);
+  const int local = blockIdx.x - cptr(ba.blockstart)[b];
+  const int nbx = (a.g.nx + FTX - 1) / FTX, nby = (a.g.ny + FTY - 1) / FTY;
+  force_body<R, VISC>(a, 0, 0, 0, local % nbx, (local / nbx) % nby, local / (nbx * nby), lds);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void kb_collide(BatchArgs ba) {
+  const int b = cptr(ba.blockbox)[blockIdx.x];
+  const auto &a = *cptr(ba.boxes + b);
+  const int i = (blockIdx.x - cptr(ba.blockstart)[b]) * BLOCK + threadIdx.x;
+  collide_body<T, 1>(a, (const T *)a.pop[ba.cur], (T *)a.pop[ba.cur ^ 1], i);
+}
+
+template <typename T, int M>
 __global__ __launch_bounds__(BLOCK) void k_readout(StepArgs a, const T *__restrict__ pin, Readout r) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const Geom &g = a.g;
+  const Geom g = geom_of(a);
   if (i >= g.N) return;
   uint32_t m = a.bb[i];
   const int N = g.N;
@@ -902,7 +978,7 @@ static void force_launch(const StepArgs &a, int alpha, int beta, int acc, hipStr
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     attr = bytes;
   }
-  dim3 gr((a.g.nx + FTX - 1) / FTX, (a.g.ny + FTY - 1) / FTY, (a.g.nz + FZC - 1) / FZC);
+  dim3 gr((a.g.nx + FTX - 1) / FTX, (a.g.ny + FTY - 1) / FTY, (a.g.nz + a.zchunk - 1) / a.zchunk);
   hipLaunchKernelGGL((k_force<R, VISC>), gr, dim3(FNT), bytes, s, a, alpha, beta, acc);
 }
 
@@ -971,6 +1047,76 @@ void launch_readout(const StepArgs &a, int prec, const void *pin, const Readout 
     readout_m<double>(a, pin, r, s);
   else
     readout_m<float>(a, pin, r, s);
+}
+
+int node_blocks(const Geom &g) { return (g.N + BLOCK - 1) / BLOCK; }
+
+int force_blocks(const Geom &g, int zchunk) {
+  return ((g.nx + FTX - 1) / FTX) * ((g.ny + FTY - 1) / FTY) * ((g.nz + zchunk - 1) / zchunk);
+}
+
+template <int R, bool VISC>
+static size_t force_lds_bytes(int entries) {
+  constexpr int NF = VISC ? 5 : 2;
+  return sizeof(double) * (2 * NF * (FTX + 2 * R) * (FTY + 2 * R) + 4 * (size_t)entries);
+}
+
+template <int R, bool VISC>
+static void prepare_one(int entries) {
+  const int bytes = (int)force_lds_bytes<R, VISC>(entries);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_force<R, VISC>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_force<R, VISC>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+// raise the dynamic-LDS limit of every force kernel up to shell range maxR
+// (done before a graph is captured)
+void prepare_force_kernels(int maxR, bool visc, int max_entries) {
+#define PREP(R)                                       \
+  if (maxR >= R) {                                    \
+    if (visc) prepare_one<R, true>(max_entries);      \
+    else prepare_one<R, false>(max_entries);          \
+  }
+  PREP(1) PREP(2) PREP(3) PREP(4) PREP(5) PREP(6) PREP(7) PREP(8)
+#undef PREP
+}
+
+void launch_batch_moments(const BatchArgs &b, int nblocks, int prec, bool visc, hipStream_t s) {
+  if (prec == LBE_FP64) {
+    if (visc) hipLaunchKernelGGL((kb_moments<double, true>), dim3(nblocks), dim3(BLOCK), 0, s, b);
+    else hipLaunchKernelGGL((kb_moments<double, false>), dim3(nblocks), dim3(BLOCK), 0, s, b);
+  } else {
+    if (visc) hipLaunchKernelGGL((kb_moments<float, true>), dim3(nblocks), dim3(BLOCK), 0, s, b);
+    else hipLaunchKernelGGL((kb_moments<float, false>), dim3(nblocks), dim3(BLOCK), 0, s, b);
+  }
+}
+
+void launch_batch_contact(const BatchArgs &b, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(kb_contact, dim3(nblocks), dim3(BLOCK), 0, s, b);
+}
+
+template <int R, bool VISC>
+static void batch_force_r(const BatchArgs &b, int nblocks, int entries, hipStream_t s) {
+  const size_t bytes = force_lds_bytes<R, VISC>(entries);
+  hipLaunchKernelGGL((kb_force<R, VISC>), dim3(nblocks), dim3(FNT), bytes, s, b);
+}
+
+void launch_batch_force(const BatchArgs &b, int nblocks, int R, bool visc, int entries, hipStream_t s) {
+#define BF(RR)                                                         \
+  case RR:                                                             \
+    if (visc) batch_force_r<RR, true>(b, nblocks, entries, s);         \
+    else batch_force_r<RR, false>(b, nblocks, entries, s);             \
+    break;
+  switch (R) { BF(1) BF(2) BF(3) BF(4) BF(5) BF(6) BF(7) BF(8) default: break; }
+#undef BF
+}
+
+void launch_batch_collide(const BatchArgs &b, int nblocks, int prec, hipStream_t s) {
+  if (prec == LBE_FP64)
+    hipLaunchKernelGGL(kb_collide<double>, dim3(nblocks), dim3(BLOCK), 0, s, b);
+  else
+    hipLaunchKernelGGL(kb_collide<float>, dim3(nblocks), dim3(BLOCK), 0, s, b);
 }
 
 int diag_nblocks(const Geom &g) {

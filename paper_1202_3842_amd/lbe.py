@@ -97,6 +97,15 @@ def lib() -> C.CDLL:
     L.lbe_set_populations.argtypes = [P, C.c_int, C.c_int, P, C.c_int]
     L.lbe_diagnostics.argtypes = [P, C.POINTER(lbe_diag)]
     L.lbe_synchronize.argtypes = [P]
+    L.lbe_set_force_zchunk.argtypes = [P, C.c_int]
+    L.lbe_batch_workspace_bytes.restype = C.c_size_t
+    L.lbe_batch_workspace_bytes.argtypes = [C.POINTER(lbe_config), C.c_int]
+    L.lbe_batch_create.argtypes = [C.POINTER(lbe_config), C.c_int, P, C.c_size_t, P, C.POINTER(P)]
+    L.lbe_batch_box.restype = P
+    L.lbe_batch_box.argtypes = [P, C.c_int]
+    L.lbe_batch_step.argtypes = [P, C.c_int, C.c_int]
+    L.lbe_batch_destroy.argtypes = [P]
+    L.lbe_batch_destroy.restype = None
     _lib = L
     return L
 
@@ -137,7 +146,7 @@ class Box:
     """
 
     def __init__(self, nx, ny, nz, sigma, periodic=7, tau=1.0, kT=1.0 / 3.0,
-                 prec=LBE_FP64, flags=LBE_VISC, stream=None):
+                 prec=LBE_FP64, flags=LBE_VISC, stream=None, _member=None):
         import torch
         self.torch = torch
         self.cfg = make_config(nx, ny, nz, sigma, periodic, tau, kT, prec, flags)
@@ -145,19 +154,24 @@ class Box:
         self.N = nx * ny * nz
         self.M = len(sigma)
         self.prec = prec
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        if _member is not None:  # a member context owned by a Batch
+            self.h = _member
+            self.owned = False
+            return
         nbytes = workspace_bytes(self.cfg)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
         _check(lib().lbe_create(C.byref(self.cfg), C.c_void_p(self.workspace.data_ptr()),
                                 nbytes, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
+        self.owned = True
 
     # ---- lifetime -------------------------------------------------------
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and getattr(self, "owned", False):
             lib().lbe_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -211,6 +225,9 @@ class Box:
     def synchronize(self):
         _check(lib().lbe_synchronize(self.h))
 
+    def set_force_zchunk(self, zchunk):
+        _check(lib().lbe_set_force_zchunk(self.h, int(zchunk)))
+
     def density(self, species=0, out=None):
         p, w, arr = self._dst(out, np.float64, self.N)
         _check(lib().lbe_get_density(self.h, int(species), p, w))
@@ -261,4 +278,74 @@ def box_from_workload(w, prec=LBE_FP64, flags=LBE_VISC) -> Box:
         b.set_body_force(a, g)
     for a, n in enumerate(w.density):
         b.init_density(a, n)
+    return b
+
+
+def load_workload(b: "Box", w) -> None:
+    """Load a paper_1202_3842_amd.workloads.Workload into an existing Box."""
+    if w.solid is not None:
+        b.set_solid(w.solid)
+    if w.V is not None:
+        b.set_potential(w.V)
+    for a, g in enumerate(w.body):
+        b.set_body_force(a, g)
+    for a, n in enumerate(w.density):
+        b.init_density(a, n)
+
+
+class Batch:
+    """Independent one-species boxes stepped together (lbe_batch_*).  Member
+    boxes are Box objects sharing the batch's workspace and stream."""
+
+    SERIAL, BATCHED, GRAPH = 0, 1, 2
+
+    def __init__(self, configs, stream=None):
+        import torch
+        self.torch = torch
+        n = len(configs)
+        arr = (lbe_config * n)(*configs)
+        self._cfgs = arr
+        nbytes = lib().lbe_batch_workspace_bytes(arr, n)
+        if nbytes == 0:
+            raise LBEError(LBE_ERR_ARG, lib().lbe_last_error().decode())
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        # graph capture needs a stream other than the null stream
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        torch.cuda.synchronize()
+        h = C.c_void_p()
+        _check(lib().lbe_batch_create(arr, n, C.c_void_p(self.workspace.data_ptr()), int(nbytes),
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.boxes = []
+        for i, c in enumerate(configs):
+            m = lib().lbe_batch_box(self.h, i)
+            sig = [c.sigma[k] for k in range(c.nspecies)]
+            self.boxes.append(Box(c.nx, c.ny, c.nz, sig, c.periodic, c.tau, c.kT, c.prec, c.flags,
+                                  stream=self.stream, _member=C.c_void_p(m)))
+
+    def step(self, n=1, mode=2):
+        _check(lib().lbe_batch_step(self.h, int(n), int(mode)))
+
+    def synchronize(self):
+        self.boxes[0].synchronize()
+
+    def close(self):
+        if getattr(self, "h", None):
+            for b in self.boxes:
+                b.h = None
+            lib().lbe_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_from_workloads(ws, prec=LBE_FP64, flags=LBE_VISC) -> Batch:
+    cfgs = [make_config(w.nx, w.ny, w.nz, w.sigma, w.periodic, w.tau, w.kT, prec, flags) for w in ws]
+    b = Batch(cfgs)
+    for box, w in zip(b.boxes, ws):
+        load_workload(box, w)
     return b
