@@ -97,7 +97,10 @@ def dominant(kv):
 
 
 def run_gpu(w, prec, flags, steps, warmup, lbe, torch):
+    from paper_1202_3842_amd import autotune
     box = lbe.box_from_workload(w, prec=prec, flags=flags)
+    z = autotune.tune_zchunk(box)
+    log(f"force-kernel zchunk {z}")
     box.step(warmup)
     box.synchronize()
     log(f"warmup {warmup} steps done ({'fp64' if prec == lbe.LBE_FP64 else 'fp32-pop'})")
@@ -129,6 +132,47 @@ def run_gpu(w, prec, flags, steps, warmup, lbe, torch):
         f"collide {res['collide_ms']:.3f} ms")
     box.close()
     return res
+
+
+def batch_leg(lbe, torch, W, flags, prec, steps, serial_steps, tune=True):
+    """96 independent boxes of uneven sizes and diameters: batched launches
+    replayed from a HIP graph against the same boxes stepped one after
+    another with per-box launches."""
+    from paper_1202_3842_amd import autotune
+    ws = W.c4_boxes()
+    nodes = sum(w.nodes for w in ws)
+    batch = lbe.batch_from_workloads(ws, prec=prec, flags=flags)
+    if tune:
+        for b in batch.boxes:
+            autotune.tune_zchunk(b)
+    st = batch.stream
+    batch.step(2, mode=2)
+    torch.cuda.synchronize()
+    e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+    e0.record(st)
+    batch.step(steps, mode=2)
+    e1.record(st)
+    e1.synchronize()
+    t_batch = e0.elapsed_time(e1) / steps
+    log(f"batched {len(ws)} boxes: {t_batch:.3f} ms/step")
+    e2.record(st)
+    batch.step(serial_steps, mode=0)
+    e3.record(st)
+    e3.synchronize()
+    t_serial = e2.elapsed_time(e3) / serial_steps
+    log(f"serial {len(ws)} boxes: {t_serial:.3f} ms/step")
+    unstable = sum(1 for b in batch.boxes if b.diagnostics()["unstable"])
+    batch.close()
+    return {
+        "workload": f"{len(ws)} one-component boxes, edge 24..96, sigma in {{3,4,6}}, "
+                    "n sigma^3 in [0.1,0.45], well depth 0.5..3 kT",
+        "nodes": nodes, "steps": steps, "serial_steps": serial_steps,
+        "ms_per_step": round(t_batch, 4), "serial_ms_per_step": round(t_serial, 4),
+        "value": round(nodes / (t_batch / 1e3) / 1e6, 2), "unit": "MLUPS",
+        "serial_value": round(nodes / (t_serial / 1e3) / 1e6, 2),
+        "batched_vs_serial": round(t_serial / t_batch, 3),
+        "boxes_flagged_unstable": unstable,
+    }
 
 
 def cpu_baseline(w, flags, budget_s):
@@ -177,6 +221,8 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -208,6 +254,14 @@ def main():
     r32 = run_gpu(w, lbe.LBE_FP32_POP, flags, fp32_steps, args.warmup, lbe, torch)
     mlups32 = N * M * fp32_steps / (r32["total_ms"] / 1e3) / 1e6
     kern32 = kernel_views(r32, N, M, 4, pairs)
+
+    batched = None
+    if not args.no_batch:
+        batched = {
+            "fp64": batch_leg(lbe, torch, W, flags, lbe.LBE_FP64, args.batch_steps, args.batch_steps),
+            "fp32_pop": batch_leg(lbe, torch, W, flags, lbe.LBE_FP32_POP, max(args.batch_steps // 5, 10),
+                                  max(args.batch_steps // 5, 10)),
+        }
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -243,6 +297,7 @@ def main():
             "umax": r32["diag"]["umax"], "unstable": r32["diag"]["unstable"],
         },
         "state_after": {"umax": r64["diag"]["umax"], "unstable": r64["diag"]["unstable"]},
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -1,0 +1,102 @@
+"""Autotuner for the force kernel's tiling.
+
+The force kernel's workgroup owns a 32 x 8 tile of nodes and marches over
+``zchunk`` planes in z; results do not depend on zchunk, its speed does (L2
+reuse of staged planes against the number of workgroups).  ``tune_zchunk``
+times the candidates on a scratch box of the same size class, diameter,
+precision and switches (the caller's state is never touched) and caches the
+winner in a JSON file (``$LBE_TUNE_CACHE`` or ``~/.cache/lbe_mi355x/tune.json``).
+"""
+from __future__ import annotations
+
+import json
+import os
+from pathlib import Path
+
+import numpy as np
+
+CANDIDATES = (1, 2, 4, 8, 16)
+
+
+def cache_path() -> Path:
+    p = os.environ.get("LBE_TUNE_CACHE")
+    return Path(p) if p else Path.home() / ".cache" / "lbe_mi355x" / "tune.json"
+
+
+def _load() -> dict:
+    try:
+        return json.loads(cache_path().read_text())
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(d: dict) -> None:
+    p = cache_path()
+    try:
+        p.parent.mkdir(parents=True, exist_ok=True)
+        p.write_text(json.dumps(d, indent=1, sort_keys=True))
+    except OSError:
+        pass
+
+
+def size_class(n: int) -> int:
+    """Edge length bucket: 32, 48, 64, 96, 128, 192, 256, ..."""
+    for c in (32, 48, 64, 96, 128, 192, 256, 384, 512):
+        if n <= c:
+            return c
+    return 1024
+
+
+def _key(box) -> str:
+    c = box.cfg
+    sig = ",".join(f"{c.sigma[k]:g}" for k in range(c.nspecies))
+    return (f"{size_class(c.nx)}x{size_class(c.ny)}x{size_class(c.nz)}|s{sig}|p{c.prec}|f{c.flags}")
+
+
+def _time_force(lbe, torch, cfg, zchunk, reps):
+    sig = [cfg.sigma[k] for k in range(cfg.nspecies)]
+    b = lbe.Box(cfg.nx, cfg.ny, cfg.nz, sig, cfg.periodic, cfg.tau, cfg.kT, cfg.prec, cfg.flags)
+    for a in range(cfg.nspecies):
+        s = max(sig[a], 1.0)
+        b.init_density(a, np.full(b.shape, 0.2 / s ** 3 / cfg.nspecies))
+    b.set_force_zchunk(zchunk)
+    st = b.stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    b.step(1)
+    for k in range(reps):
+        b.step_phase(0)
+        b.step_phase(1)
+        ev[k][0].record(st)
+        b.step_phase(2)
+        ev[k][1].record(st)
+        b.step_phase(3)
+    torch.cuda.synchronize()
+    t = min(e0.elapsed_time(e1) for e0, e1 in ev)
+    b.close()
+    return t
+
+
+def tune_zchunk(box, candidates=CANDIDATES, reps=3, use_cache=True) -> int:
+    """Pick and set the fastest zchunk for ``box`` (a paper_1202_3842_amd.lbe.Box)."""
+    import torch
+    from paper_1202_3842_amd import lbe
+    key = _key(box)
+    cache = _load() if use_cache else {}
+    if key in cache:
+        z = min(int(cache[key]), box.cfg.nz)
+        box.set_force_zchunk(z)
+        return z
+    best, best_t = None, None
+    for z in candidates:
+        if z > box.cfg.nz:
+            continue
+        t = _time_force(lbe, torch, box.cfg, z, reps)
+        if best_t is None or t < best_t:
+            best, best_t = z, t
+    box.set_force_zchunk(best)
+    if use_cache:
+        cache = _load()
+        cache[key] = best
+        _store(cache)
+    return best
