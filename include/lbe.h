@@ -168,6 +168,12 @@ lbe_status lbe_get_density(lbe_ctx *ctx, int species, double *out, int where);
  * zero on solid nodes. */
 lbe_status lbe_get_velocity(lbe_ctx *ctx, int species, double *out, int where);
 
+/* J^a = J~^a + (half-step force term) after the inversion (Sec. 4.2
+ * eq. mom-g, with the inversion selected by the flags), or the total
+ * sum_a J^a for species = -1; 3N values (component-major), zero on solid
+ * nodes. */
+lbe_status lbe_get_momentum(lbe_ctx *ctx, int species, double *out, int where);
+
 /* C^mf (which = 0) or C^visc (which = 1) of one species at the current
  * state, 3N values. */
 lbe_status lbe_get_force(lbe_ctx *ctx, int species, int which, double *out,
@@ -218,6 +224,52 @@ lbe_ctx *lbe_batch_box(lbe_batch *batch, int box);
 lbe_status lbe_batch_step(lbe_batch *batch, int nsteps, int mode);
 
 void lbe_batch_destroy(lbe_batch *batch);
+
+/* ---- adjoint with respect to the external potential ----------------------
+ * Reverse mode of nsteps steps of one box: the gradient dL/dV(r) of an
+ * objective L of the final state, where V is the potential of
+ * lbe_set_potential (the step's dependence on V runs through F = -grad_h V,
+ * Sec. 4.1).  The objective enters through its derivatives with respect to
+ * the read-outs of the final state: n^a (lbe_get_density), J^a
+ * (lbe_get_momentum) and the post-streaming populations
+ * (lbe_get_populations).  Supported: FP64 populations, the C^mf scheme
+ * with either inversion and either kappa (not LBE_VISC).  The forward
+ * keeps a copy of the state every `segment` steps; the backward recomputes
+ * one segment at a time from its copy, so device memory grows as
+ * (nsteps/segment + segment) states.  The context's potential, body forces
+ * and solid mask must not change between lbe_adjoint_forward and
+ * lbe_adjoint_backward. */
+typedef struct lbe_adjoint lbe_adjoint;
+
+/* Device workspace of an adjoint over nsteps steps checkpointed every
+ * `segment` steps, or 0 if unsupported or invalid (lbe_last_error says
+ * why). */
+size_t lbe_adjoint_workspace_bytes(const lbe_config *cfg, int nsteps, int segment);
+
+/* Attach an adjoint to a context, in a caller-owned device workspace (256-
+ * byte aligned) of lbe_adjoint_workspace_bytes bytes.  The context must
+ * outlive the adjoint. */
+lbe_status lbe_adjoint_create(lbe_ctx *ctx, int nsteps, int segment, void *dev_workspace,
+                              size_t bytes, lbe_adjoint **out);
+
+/* Advance the context nsteps steps from its current state (the t = 0 of the
+ * objective), keeping the checkpoints. */
+lbe_status lbe_adjoint_forward(lbe_adjoint *adj);
+
+/* dL/dV from the derivatives of L with respect to the final read-outs, any
+ * of which may be NULL (= 0): dL_dn M*N values (species-major), dL_dJ 3M*N
+ * ([species][component][node]), dL_dpop 2*M*19*N ([dist][species][p][node],
+ * post-streaming populations).  where: LBE_HOST or LBE_DEVICE for the three
+ * inputs; dL_dV: N values at where_out.  Synchronises. */
+lbe_status lbe_adjoint_backward(lbe_adjoint *adj, const double *dL_dn, const double *dL_dJ,
+                                const double *dL_dpop, int where, double *dL_dV, int where_out);
+
+/* After lbe_adjoint_backward: dL/d(post-streaming populations at t = 0) of
+ * one species and distribution, 19N values (zero on solid nodes). */
+lbe_status lbe_adjoint_state_grad(lbe_adjoint *adj, int species, int dist, double *out,
+                                  int where);
+
+void lbe_adjoint_destroy(lbe_adjoint *adj);
 
 /* Thread-local text of the last failure (never NULL). */
 const char *lbe_last_error(void);

@@ -8,48 +8,33 @@
 #include <algorithm>
 #include <vector>
 
-#include "lbe_internal.hpp"
+#include "lbe_host.hpp"
 
 using namespace lbe;
 
-namespace {
+namespace lbe {
 
+namespace {
 thread_local char g_err[512] = "";
+}
 
 lbe_status fail(lbe_status code, const char *fmt, ...) {
+  char buf[sizeof g_err];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
+  memcpy(g_err, buf, sizeof buf);
   return code;
 }
 
-#define HIP_TRY(expr)                                                              \
-  do {                                                                             \
-    hipError_t e_ = (expr);                                                        \
-    if (e_ != hipSuccess)                                                          \
-      return fail(LBE_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
-  } while (0)
+const char *error_text() { return g_err; }
 
-#define LAUNCH_CHECK()                                                             \
-  do {                                                                             \
-    hipError_t e_ = hipGetLastError();                                             \
-    if (e_ != hipSuccess)                                                          \
-      return fail(LBE_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
-  } while (0)
+void clear_error() { g_err[0] = 0; }
 
-size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+}  // namespace lbe
 
-// Lattice shell of radius s: points e != 0 with s - 1/2 <= |e| < s + 1/2,
-// kept as the half S+ (e_z > 0, or e_z = 0 and e_y > 0, or e_z = e_y = 0 and
-// e_x > 0) grouped by e_z, with the uniform weight 4 pi s / sum_e |e| that
-// makes the weighted first moment (4 pi/3) s delta_ij (Appendix integral
-// over the unit sphere).
-struct HostShell {
-  std::vector<int> e;  // 3 per point of S+, ordered by e_z, then e_y, then e_x
-  double weight = 0.0;
-  int maxc = 0;
-};
+namespace {
 
 HostShell make_shell(double s) {
   HostShell h;
@@ -92,20 +77,9 @@ std::vector<int> make_ball(double sigma, int *maxc) {
   return b;
 }
 
-struct Plan {
-  Geom g;
-  int M = 0, npairs = 0;
-  long long Ns = 0;
-  size_t pop_bytes = 0;  // one ping-pong buffer
-  std::vector<HostShell> shells;
-  std::vector<std::vector<int>> balls;
-  int nshell = 0, nball = 0;
-  size_t off_flag = 0, off_result = 0, off_ring_ofs = 0, off_ring_off = 0, off_ring_e = 0,
-         off_ball = 0, off_bb = 0, off_V = 0, off_F = 0, off_solid = 0, off_pop0 = 0,
-         off_pop1 = 0, off_n = 0, off_G = 0, off_J = 0, off_force = 0, off_read = 0,
-         off_part = 0, total = 0;
-  int nblocks = 0;
-};
+}  // namespace
+
+namespace lbe {
 
 lbe_status make_plan(const lbe_config *cfg, Plan &pl) {
   if (!cfg) return fail(LBE_ERR_ARG, "null config");
@@ -183,41 +157,17 @@ lbe_status make_plan(const lbe_config *cfg, Plan &pl) {
   pl.off_G = take(sizeof(double) * pl.npairs * g.Np);
   pl.off_J = take(visc ? sizeof(double) * 3 * pl.M * g.Np : 0);
   pl.off_force = take(sizeof(double) * 6 * pl.M * (size_t)g.N);
-  pl.off_read = take(sizeof(double) * (10 * pl.M + 9) * (size_t)g.N);
+  pl.off_read = take(sizeof(double) * (13 * pl.M + 9) * (size_t)g.N);
   pl.off_part = take(sizeof(double) * DIAG_K * pl.nblocks);
   pl.total = o;
   return LBE_OK;
 }
 
-}  // namespace
-
-struct lbe_ctx {
-  lbe_config cfg;
-  Plan pl;
-  char *ws = nullptr;
-  hipStream_t stream = nullptr;
-  int device = 0;
-  int cur = 0;             // ping-pong buffer holding the current state
-  int next_phase = 0;      // lbe_step_phase position inside a step
-  bool poisoned = false;
-  StepArgs args;
-  Readout rd;
-
-  template <typename T>
-  T *at(size_t off) const {
-    return reinterpret_cast<T *>(ws + off);
-  }
-  void *pop(int buf) const { return ws + (buf ? pl.off_pop1 : pl.off_pop0); }
-  size_t psize() const { return cfg.prec == LBE_FP64 ? 8 : 4; }
-  // one (dist, species) block of 19 populations in buffer buf
-  char *block(int buf, int dist, int s) const {
-    return (char *)pop(buf) + (size_t)(dist * pl.M + s) * Q * pl.Ns * psize();
-  }
-};
+}  // namespace lbe
 
 extern "C" {
 
-const char *lbe_last_error(void) { return g_err; }
+const char *lbe_last_error(void) { return lbe::error_text(); }
 
 size_t lbe_workspace_bytes(const lbe_config *cfg) {
   Plan pl;
@@ -320,6 +270,7 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
   c->rd.n = c->rd.cvisc + 3 * M * N;
   c->rd.jt = c->rd.n + M * N;
   c->rd.j = c->rd.jt + 3 * N;
+  c->rd.ja = c->rd.j + 3 * N;
   hipStream_t s = c->stream;
   lbe_status rs = LBE_OK;
   auto upload = [&](size_t off, const void *src, size_t n) -> bool {
@@ -344,7 +295,7 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
     return rs;
   }
   *out = c;
-  g_err[0] = 0;
+  clear_error();
   return LBE_OK;
 }
 
@@ -498,6 +449,19 @@ lbe_status lbe_get_velocity(lbe_ctx *c, int species, double *out, int where) {
   return bad ? fail(LBE_ERR_UNSTABLE, "packing fraction >= 1 or non-finite density") : LBE_OK;
 }
 
+lbe_status lbe_get_momentum(lbe_ctx *c, int species, double *out, int where) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  if (species < -1 || species >= c->pl.M) return fail(LBE_ERR_ARG, "bad species %d", species);
+  bool bad = false;
+  lbe_status st = readout(c, &bad);
+  if (st != LBE_OK) return st;
+  size_t N = c->pl.g.N;
+  const double *src = species < 0 ? c->rd.j : c->rd.ja + 3 * species * N;
+  st = copy_out(c, out, src, sizeof(double) * 3 * N, where);
+  if (st != LBE_OK) return st;
+  return bad ? fail(LBE_ERR_UNSTABLE, "packing fraction >= 1 or non-finite density") : LBE_OK;
+}
+
 lbe_status lbe_get_force(lbe_ctx *c, int species, int which, double *out, int where) {
   if (!c) return fail(LBE_ERR_ARG, "null context");
   if (species < 0 || species >= c->pl.M || which < 0 || which > 1)
@@ -628,7 +592,7 @@ lbe_status make_batch_plan(const lbe_config *cfgs, int nboxes, BatchPlan &bp) {
   std::vector<Plan> plans(nboxes);
   for (int b = 0; b < nboxes; ++b) {
     lbe_status st = make_plan(&cfgs[b], plans[b]);
-    if (st != LBE_OK) return fail(st, "box %d: %s", b, g_err);
+    if (st != LBE_OK) return fail(st, "box %d: %s", b, error_text());
     if (cfgs[b].nspecies != 1) return fail(LBE_ERR_UNSUPPORTED, "batched boxes must have one species");
     if (cfgs[b].prec != cfgs[0].prec || cfgs[b].flags != cfgs[0].flags)
       return fail(LBE_ERR_ARG, "batched boxes must share precision and flags");

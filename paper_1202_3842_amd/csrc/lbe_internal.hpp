@@ -92,9 +92,30 @@ struct BatchArgs {
 };
 
 // Per-node outputs of the read-out pass (component-major, N each):
-//   ua[M][3], u[3], cmf[M][3], cvisc[M][3], n[M], Jt_sum[3], J_sum[3]
+//   ua[M][3], u[3], cmf[M][3], cvisc[M][3], n[M], Jt_sum[3], J_sum[3], J[M][3]
 struct Readout {
-  double *ua, *u, *cmf, *cvisc, *n, *jt, *j;
+  double *ua, *u, *cmf, *cvisc, *n, *jt, *j, *ja;
+};
+
+// Buffers of the adjoint passes (FP64).  "bar" marks dL/d(quantity).  The
+// adjoint state of a step lives in the post-streaming frame: mu holds one
+// value per population (the population layout of a state buffer), nbar the
+// nonlocal part of the density adjoint (M*N); the adjoint of the stored
+// pre-streaming value at (r, q) is mu + nbar (f only) at the node that
+// pulls it.
+struct AdjArgs {
+  const double *PJ;        // 4M*N tilde moments of the state: Pi~ (M), J~ (3M)
+  const double *mu_in;     // adjoint state after the step
+  const double *nbar_in;
+  double *mu_out;          // adjoint state before the step
+  double *nbar_out;
+  double *phibar;          // 3M*Np padded: adjoint of the force per particle C^mf_a/n_a
+  double *Gbar;            // npairs*N: adjoint of the contact values
+  double *nbb;             // M*Np padded: adjoint of the ball-averaged densities
+  double *Fbar;            // 3N: accumulated adjoint of the external force -grad_h V
+  const double *dn;        // seeds of the read-out adjoint: dL/dn (M*N) or null
+  const double *dJ;        // dL/dJ (3M*N) or null
+  const double *dpop;      // dL/d(post-streaming populations) (2M*19*N) or null
 };
 
 // Launchers (lbe_kernels.hip)
@@ -131,6 +152,15 @@ void launch_batch_contact(const BatchArgs &b, int nblocks, hipStream_t s);
 void launch_batch_force(const BatchArgs &b, int nblocks, int R, bool visc, int entries, hipStream_t s);
 void launch_batch_collide(const BatchArgs &b, int nblocks, int prec, hipStream_t s);
 void prepare_force_kernels(int maxR, bool visc, int max_entries);
+// adjoint passes (FP64 populations, no C^visc)
+void launch_tape_moments(const StepArgs &a, const double *pop, double *PJ, hipStream_t s);
+void launch_adj_collide(const StepArgs &a, const AdjArgs &d, hipStream_t s);
+void launch_adj_readout(const StepArgs &a, const AdjArgs &d, hipStream_t s);
+void launch_adj_nonlocal(const StepArgs &a, const AdjArgs &d, hipStream_t s);
+void launch_adj_extforce(const Geom &g, const double *Fbar, double *Vbar, hipStream_t s);
+void launch_adj_state_grad(const Geom &g, int M, const uint32_t *bb, const double *mu,
+                           const double *nbar, int species, int dist, double *out, hipStream_t s);
+void launch_fill(double *p, long long n, double v, hipStream_t s);
 constexpr int DIAG_K = 12;  // reduced quantities per block
 
 }  // namespace lbe

@@ -389,10 +389,15 @@ constexpr int FTX = FORCE_TX, FTY = FORCE_TY;
 constexpr int FNT = FTX * FTY;
 
 
-template <int R, bool VISC, class A>
-__device__ inline void force_body(const A &a, int alpha, int beta, int accumulate, int bx,
-                                  int by, int bz, double *lds) {
-  constexpr int NF = VISC ? 5 : 2;
+// MODE 0: C^mf; MODE 1: C^mf and C^visc; MODE 2: the transpose of the C^mf
+// gather for the adjoint (fields n_b, G_ab and the adjoint force phi_a^bar,
+// see adjoint_force below).
+template <int R, int MODE, class A>
+__device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int beta, int accumulate,
+                                  int bx, int by, int bz, double *lds) {
+  constexpr bool VISC = MODE == 1;
+  constexpr bool ADJ = MODE == 2;
+  constexpr int NF = MODE == 0 ? 2 : 5;
   constexpr int W = FTX + 2 * R, H = FTY + 2 * R, WH = W * H;
   constexpr int SLOTS = (WH + FNT - 1) / FNT;   // window elements per thread and field
   const Geom g = geom_of(a);
@@ -406,6 +411,11 @@ __device__ inline void force_body(const A &a, int alpha, int beta, int accumulat
   fld[1] = a.Gfield + (long long)k * g.Np;
   if (VISC) {
     fld[2] = a.Jfield + (long long)(3 * beta) * g.Np;
+    fld[3] = fld[2] + g.Np;
+    fld[4] = fld[3] + g.Np;
+  }
+  if (ADJ) {
+    fld[2] = ad->phibar + (long long)(3 * alpha) * g.Np;
     fld[3] = fld[2] + g.Np;
     fld[4] = fld[3] + g.Np;
   }
@@ -457,7 +467,8 @@ __device__ inline void force_body(const A &a, int alpha, int beta, int accumulat
   };
   fetch(0);
   double mx = 0.0, my = 0.0, mz = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
-  double G0 = 0.0, u0x = 0.0, u0y = 0.0, u0z = 0.0;
+  // centre values: G_ab, and u_b (MODE 1) or n_b and phi_a^bar (MODE 2)
+  double G0 = 0.0, u0x = 0.0, u0y = 0.0, u0z = 0.0, n0 = 0.0;
   for (int rho = 0; rho < rounds; ++rho) {
     const int z = zb + rho / (R + 1), ez = rho % (R + 1);
     __syncthreads();  // previous round's readers are done with the buffers
@@ -478,13 +489,16 @@ __device__ inline void force_body(const A &a, int alpha, int beta, int accumulat
       mx = my = mz = vx = vy = vz = 0.0;
       G0 = Bp[WH + base];
       u0x = u0y = u0z = 0.0;
-      if (VISC) {
-        const double n0 = Bp[base];
-        if (n0 != 0.0) {
-          u0x = Bp[2 * WH + base] / n0;
-          u0y = Bp[3 * WH + base] / n0;
-          u0z = Bp[4 * WH + base] / n0;
-        }
+      n0 = Bp[base];
+      if (VISC && n0 != 0.0) {
+        u0x = Bp[2 * WH + base] / n0;
+        u0y = Bp[3 * WH + base] / n0;
+        u0z = Bp[4 * WH + base] / n0;
+      }
+      if (ADJ) {
+        u0x = Bp[2 * WH + base];
+        u0y = Bp[3 * WH + base];
+        u0z = Bp[4 * WH + base];
       }
     }
     const int jbeg = rofs[ez] - j0, jend = rofs[ez + 1] - j0;
@@ -494,19 +508,32 @@ __device__ inline void force_body(const A &a, int alpha, int beta, int accumulat
       const int o = (int)__double_as_longlong(tab[4 * j + 3]);
       const int qa = base + o, qb = base - o;
       const double npl = Bp[qa], nmi = Bm[qb];
-      const double gp = G0 + Bp[WH + qa], gm = G0 + Bm[WH + qb];
-      const double d = gp * npl - gm * nmi;
-      ax += e0 * d;
-      ay += e1 * d;
-      az += e2 * d;
-      if (VISC) {
-        const double eu = e0 * u0x + e1 * u0y + e2 * u0z;
-        const double tp = gp * (e0 * Bp[2 * WH + qa] + e1 * Bp[3 * WH + qa] + e2 * Bp[4 * WH + qa] - eu * npl);
-        const double tm = gm * (e0 * Bm[2 * WH + qb] + e1 * Bm[3 * WH + qb] + e2 * Bm[4 * WH + qb] - eu * nmi);
-        const double tt = tp + tm;
-        bx += e0 * tt;
-        by += e1 * tt;
-        bz += e2 * tt;
+      if (ADJ) {
+        // m: sum_S e^ n_b(r+e); v: sum_S e^.phibar(r+e) and
+        // sum_S (e^.phibar(r+e)) G(r+e), over both points of the pair
+        const double tp = e0 * Bp[2 * WH + qa] + e1 * Bp[3 * WH + qa] + e2 * Bp[4 * WH + qa];
+        const double tm = e0 * Bm[2 * WH + qb] + e1 * Bm[3 * WH + qb] + e2 * Bm[4 * WH + qb];
+        const double dn = npl - nmi;
+        ax += e0 * dn;
+        ay += e1 * dn;
+        az += e2 * dn;
+        bx += tp - tm;
+        by += tp * Bp[WH + qa] - tm * Bm[WH + qb];
+      } else {
+        const double gp = G0 + Bp[WH + qa], gm = G0 + Bm[WH + qb];
+        const double d = gp * npl - gm * nmi;
+        ax += e0 * d;
+        ay += e1 * d;
+        az += e2 * d;
+        if (VISC) {
+          const double eu = e0 * u0x + e1 * u0y + e2 * u0z;
+          const double tp = gp * (e0 * Bp[2 * WH + qa] + e1 * Bp[3 * WH + qa] + e2 * Bp[4 * WH + qa] - eu * npl);
+          const double tm = gm * (e0 * Bm[2 * WH + qb] + e1 * Bm[3 * WH + qb] + e2 * Bm[4 * WH + qb] - eu * nmi);
+          const double tt = tp + tm;
+          bx += e0 * tt;
+          by += e1 * tt;
+          bz += e2 * tt;
+        }
       }
     };
     // two independent accumulator sets shorten the dependency chains; a
@@ -528,21 +555,28 @@ __device__ inline void force_body(const A &a, int alpha, int beta, int accumulat
     if (ez == R && valid) {
       const long long N = g.N;
       const long long i = x + (long long)g.nx * (y + (long long)g.ny * z);
-      double *F = a.force + 6LL * alpha * N + i;
-      if (accumulate) {
-        F[0] += cmf * mx;
-        F[N] += cmf * my;
-        F[2 * N] += cmf * mz;
-        F[3 * N] += cvs * vx;
-        F[4 * N] += cvs * vy;
-        F[5 * N] += cvs * vz;
+      if (ADJ) {
+        // n_b^bar(r) += -c (sum (e^.phibar) G(r+e) + G(r) sum e^.phibar)
+        // G_ab^bar(r) += c (phibar(r).sum e^ n_b(r+e) - n_b(r) sum e^.phibar)
+        ad->nbar_out[beta * N + i] += -cmf * (vy + G0 * vx);
+        ad->Gbar[k * N + i] += cmf * (u0x * mx + u0y * my + u0z * mz - n0 * vx);
       } else {
-        F[0] = cmf * mx;
-        F[N] = cmf * my;
-        F[2 * N] = cmf * mz;
-        F[3 * N] = cvs * vx;
-        F[4 * N] = cvs * vy;
-        F[5 * N] = cvs * vz;
+        double *F = a.force + 6LL * alpha * N + i;
+        if (accumulate) {
+          F[0] += cmf * mx;
+          F[N] += cmf * my;
+          F[2 * N] += cmf * mz;
+          F[3 * N] += cvs * vx;
+          F[4 * N] += cvs * vy;
+          F[5 * N] += cvs * vz;
+        } else {
+          F[0] = cmf * mx;
+          F[N] = cmf * my;
+          F[2 * N] = cmf * mz;
+          F[3 * N] = cvs * vx;
+          F[4 * N] = cvs * vy;
+          F[5 * N] = cvs * vz;
+        }
       }
     }
   }
@@ -551,7 +585,7 @@ __device__ inline void force_body(const A &a, int alpha, int beta, int accumulat
 template <int R, bool VISC>
 __global__ __launch_bounds__(FNT) void k_force(StepArgs a, int alpha, int beta, int accumulate) {
   extern __shared__ double lds[];
-  force_body<R, VISC>(a, alpha, beta, accumulate, blockIdx.x, blockIdx.y, blockIdx.z, lds);
+  force_body<R, VISC ? 1 : 0>(a, nullptr, alpha, beta, accumulate, blockIdx.x, blockIdx.y, blockIdx.z, lds);
 }
 
 // per-particle forces of species s at node i, times n_s
@@ -726,7 +760,8 @@ __global__ __launch_bounds__(FNT) void kb_force(BatchArgs ba) {
   const auto &a = *cptr(ba.boxes + b);
   const int local = blockIdx.x - cptr(ba.blockstart)[b];
   const int nbx = (a.g.nx + FTX - 1) / FTX, nby = (a.g.ny + FTY - 1) / FTY;
-  force_body<R, VISC>(a, 0, 0, 0, local % nbx, (local / nbx) % nby, local / (nbx * nby), lds);
+  force_body<R, VISC ? 1 : 0>(a, nullptr, 0, 0, 0, local % nbx, (local / nbx) % nby, local / (nbx * nby),
+                              lds);
 }
 
 template <typename T>
@@ -751,6 +786,7 @@ __global__ __launch_bounds__(BLOCK) void k_readout(StepArgs a, const T *__restri
         r.ua[(long long)(3 * s + k) * N + i] = 0.0;
         r.cmf[(long long)(3 * s + k) * N + i] = 0.0;
         r.cvisc[(long long)(3 * s + k) * N + i] = 0.0;
+        r.ja[(long long)(3 * s + k) * N + i] = 0.0;
       }
     }
     for (int k = 0; k < 3; ++k) {
@@ -781,6 +817,7 @@ __global__ __launch_bounds__(BLOCK) void k_readout(StepArgs a, const T *__restri
       r.ua[(long long)(3 * s + k) * N + i] = nm.ua[s][k];
       r.cmf[(long long)(3 * s + k) * N + i] = cmf[s][k];
       r.cvisc[(long long)(3 * s + k) * N + i] = cvisc[s][k];
+      r.ja[(long long)(3 * s + k) * N + i] = nm.J[s][k];
       jt[k] += J1[k];
       js[k] += nm.J[s][k];
     }
@@ -884,6 +921,439 @@ __global__ __launch_bounds__(BLOCK) void k_diag_errn(Geom g, int M, const uint32
 }
 
 inline dim3 grid_for(int N) { return dim3((N + BLOCK - 1) / BLOCK); }
+
+// ------------------------------------------------------------------------
+// adjoint (reverse mode) of one step, for FP64 populations and the C^mf
+// scheme (no C^visc).  "bar" marks the adjoint dL/d(quantity).  The adjoint
+// state between steps is (mu, nbar) in the post-streaming frame (AdjArgs).
+// ------------------------------------------------------------------------
+
+// adjoint of the pre-streaming slot (r, q): the streaming map is a
+// permutation, so it is the adjoint of the one population that reads the
+// slot -- (r + c_q, q), or (r, opp q) when r + c_q is blocked -- plus the
+// nonlocal density adjoint of that node for f populations
+template <int q>
+__device__ inline double adj_slot(const Geom &g, const Coord &c, int i, uint32_t m,
+                                  const double *__restrict__ blk, long long Ns,
+                                  const double *__restrict__ nb) {
+  if (q == 0) return blk[i] + (nb ? nb[i] : 0.0);
+  if ((m >> opp(q)) & 1u) return blk[(long long)opp(q) * Ns + i] + (nb ? nb[i] : 0.0);
+  const int j = downstream(g, c, q);
+  return blk[(long long)q * Ns + j] + (nb ? nb[j] : 0.0);
+}
+
+// sum_q w_q v_q, sum_q w_q c_q v_q, sum_q w_q c_q c_q v_q (xx yy zz xy xz yz)
+struct WMoments {
+  double m0, m1[3], m2[6];
+};
+
+template <int q>
+__device__ inline void wacc(WMoments &b, double v) {
+  constexpr int cx = cvec(q, 0), cy = cvec(q, 1), cz = cvec(q, 2);
+  const double wv = wgt(q) * v;
+  b.m0 += wv;
+  if (cx) b.m1[0] += cx * wv;
+  if (cy) b.m1[1] += cy * wv;
+  if (cz) b.m1[2] += cz * wv;
+  if (cx) b.m2[0] += wv;
+  if (cy) b.m2[1] += wv;
+  if (cz) b.m2[2] += wv;
+  if (cx && cy) b.m2[3] += cx * cy * wv;
+  if (cx && cz) b.m2[4] += cx * cz * wv;
+  if (cy && cz) b.m2[5] += cy * cz * wv;
+}
+
+__device__ inline void wzero(WMoments &b) {
+  b.m0 = 0.0;
+  for (int k = 0; k < 3; ++k) b.m1[k] = 0.0;
+  for (int k = 0; k < 6; ++k) b.m2[k] = 0.0;
+}
+
+// symmetric 3x3 (xx yy zz xy xz yz) times a vector
+__device__ inline void symv(const double m[6], const double v[3], double o[3]) {
+  o[0] = m[0] * v[0] + m[3] * v[1] + m[4] * v[2];
+  o[1] = m[3] * v[0] + m[1] * v[1] + m[5] * v[2];
+  o[2] = m[4] * v[0] + m[5] * v[1] + m[2] * v[2];
+}
+
+__device__ inline double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+template <int q, int M>
+__device__ inline void adj_moments_all(const Geom &g, const Coord &c, int i, uint32_t m,
+                                       const AdjArgs &d, long long Ns, long long N,
+                                       WMoments bf[M], WMoments bg[M]) {
+  if constexpr (q < Q) {
+    for (int s = 0; s < M; ++s) {
+      wacc<q>(bf[s], adj_slot<q>(g, c, i, m, d.mu_in + (long long)s * Q * Ns, Ns, d.nbar_in + s * N));
+      wacc<q>(bg[s], adj_slot<q>(g, c, i, m, d.mu_in + (long long)(M + s) * Q * Ns, Ns, nullptr));
+    }
+    adj_moments_all<q + 1, M>(g, c, i, m, d, Ns, N, bf, bg);
+  }
+}
+
+// mu_out = (1 - a) (incoming adjoint) + the moment adjoints of the node
+template <int q, int M>
+__device__ inline void adj_store_all(const Geom &g, const Coord &c, int i, uint32_t m,
+                                     const AdjArgs &d, long long Ns, long long N, double keep,
+                                     const double nbar[M], const double Pibar[M],
+                                     const double Jbar[M][3]) {
+  if constexpr (q < Q) {
+    for (int s = 0; s < M; ++s) {
+      const double lf = adj_slot<q>(g, c, i, m, d.mu_in + (long long)s * Q * Ns, Ns, d.nbar_in + s * N);
+      const double lg = adj_slot<q>(g, c, i, m, d.mu_in + (long long)(M + s) * Q * Ns, Ns, nullptr);
+      d.mu_out[((long long)s * Q + q) * Ns + i] = keep * lf + nbar[s];
+      d.mu_out[((long long)(M + s) * Q + q) * Ns + i] = keep * lg + Pibar[s] + cdot<q>(Jbar[s]);
+    }
+    adj_store_all<q + 1, M>(g, c, i, m, d, Ns, N, keep, nbar, Pibar, Jbar);
+  }
+}
+
+__device__ inline void store_phibar(const Geom &g, const AdjArgs &d, const Coord &c, int s,
+                                    const double v[3]) {
+  for (int k = 0; k < 3; ++k) store_images(g, d.phibar + (long long)(3 * s + k) * g.Np, c, v[k]);
+}
+
+// Reverse of the collision of one node (inversion, equilibria, sources and
+// trapezoidal update, as in collide_body).  Inputs: the tilde moments of
+// the state (tape), n, the force per particle phi = C^mf/n and F; output
+// the adjoint before the step, phibar (for the shell-gather transpose) and
+// the external-force adjoint (accumulated).  Per species, with
+//   A = a (m_f + m_g), B = b m_f, D = b m_g  (weighted moments of the
+// incoming f- and g-adjoints),
+//   nbar  = A0 + 4.5 (2 u^a.A2.u - u.A2.u) - 1.5 (2 u^a.u - u.u) A0 - a m_g0
+//   Jbar  = 3 A1,  Pibar = a m_g0
+//   uabar = 9n A2.u - 3n A0 u + 9 B2.X - 3 B0 X + 4.5 kappa D2.C
+//           + (3 - 1.5 kappa) D0 C + 9 D2.Y - 3 D0 Y
+//   ubar += 9n A2.(u^a - u) - 3n A0 (u^a - u)
+//   Xbar  = 3 B1 + 9 B2.u^a - 3 B0 u^a
+//   Cbar  = 4.5 kappa D2.u^a + (3 - 1.5 kappa) D0 u^a
+//   Ybar  = 3 D1 + 9 D2.u^a - 3 D0 u^a
+// then back through Pi, u, u^a = J/n, J = J~ + (X or Y)/2, X = C + Y,
+// Y = n F and C = n phi.
+template <int M, class A>
+__device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
+  const Geom g = geom_of(a);
+  if (i >= g.N) return;
+  const uint32_t m = a.bb[i];
+  const Coord c = decode(g, i);
+  if (m & 1u) {
+    const double z[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < M; ++s) store_phibar(g, d, c, s, z);
+    return;
+  }
+  const long long Ns = pop_stride(g), N = g.N;
+  const long long P = padded_index(g, c.x, c.y, c.z);
+  const bool printed = a.flags & LBE_PRINTED_INV;
+  const double sgn = printed ? -1.0 : 1.0;
+  double n[M], phi[M][3], F[M][3], C[M][3], Y[M][3], X[M][3], ua[M][3], u[3];
+  double ntot = 0.0, Jtot[3] = {0.0, 0.0, 0.0};
+  for (int s = 0; s < M; ++s) {
+    n[s] = a.nfield[(long long)s * g.Np + P];
+    for (int k = 0; k < 3; ++k) {
+      phi[s][k] = a.force[6LL * s * N + k * N + i];
+      F[s][k] = a.Fext[(long long)k * N + i] + a.body[s][k];
+      C[s][k] = n[s] * phi[s][k];
+      Y[s][k] = n[s] * F[s][k];
+      X[s][k] = C[s][k] + Y[s][k];
+      const double J = d.PJ[(long long)(M + 3 * s + k) * N + i] + 0.5 * (printed ? X[s][k] : Y[s][k]);
+      ua[s][k] = n[s] != 0.0 ? J / n[s] : 0.0;
+      Jtot[k] += J;
+    }
+    ntot += n[s];
+  }
+  for (int k = 0; k < 3; ++k) u[k] = ntot != 0.0 ? Jtot[k] / ntot : 0.0;
+
+  WMoments bf[M], bg[M];
+  for (int s = 0; s < M; ++s) {
+    wzero(bf[s]);
+    wzero(bg[s]);
+  }
+  adj_moments_all<0, M>(g, c, i, m, d, Ns, N, bf, bg);
+
+  const double ac = a.acoef, bc = a.bcoef, kap = a.kappa, hb = 0.5 * a.beta;
+  double nbar[M], Pibar[M], Jbar[M][3], uabar[M][3], Cbar[M][3], Ybar[M][3], Xbar[M][3];
+  double ubar[3] = {0.0, 0.0, 0.0};
+  const double uu = dot3(u, u);
+  for (int s = 0; s < M; ++s) {
+    double A0 = ac * (bf[s].m0 + bg[s].m0), A1[3], A2[6], B2[6], D2[6];
+    for (int k = 0; k < 3; ++k) A1[k] = ac * (bf[s].m1[k] + bg[s].m1[k]);
+    for (int k = 0; k < 6; ++k) {
+      A2[k] = ac * (bf[s].m2[k] + bg[s].m2[k]);
+      B2[k] = bc * bf[s].m2[k];
+      D2[k] = bc * bg[s].m2[k];
+    }
+    const double B0 = bc * bf[s].m0, D0 = bc * bg[s].m0;
+    double A2u[3], A2ua[3], B2ua[3], D2ua[3], B2X[3], D2C[3], D2Y[3];
+    symv(A2, u, A2u);
+    symv(A2, ua[s], A2ua);
+    symv(B2, ua[s], B2ua);
+    symv(D2, ua[s], D2ua);
+    symv(B2, X[s], B2X);
+    symv(D2, C[s], D2C);
+    symv(D2, Y[s], D2Y);
+    const double uau = dot3(ua[s], u);
+    nbar[s] = A0 + 4.5 * (2.0 * dot3(ua[s], A2u) - dot3(u, A2u)) - 1.5 * (2.0 * uau - uu) * A0 -
+              ac * bg[s].m0;
+    Pibar[s] = ac * bg[s].m0;
+    const double ns = n[s];
+    for (int k = 0; k < 3; ++k) {
+      Jbar[s][k] = 3.0 * A1[k];
+      uabar[s][k] = 9.0 * ns * A2u[k] - 3.0 * ns * A0 * u[k] + 9.0 * B2X[k] - 3.0 * B0 * X[s][k] +
+                    4.5 * kap * D2C[k] + (3.0 - 1.5 * kap) * D0 * C[s][k] + 9.0 * D2Y[k] -
+                    3.0 * D0 * Y[s][k];
+      ubar[k] += 9.0 * ns * (A2ua[k] - A2u[k]) - 3.0 * ns * A0 * (ua[s][k] - u[k]);
+      Xbar[s][k] = 3.0 * bc * bf[s].m1[k] + 9.0 * B2ua[k] - 3.0 * B0 * ua[s][k];
+      Cbar[s][k] = 4.5 * kap * D2ua[k] + (3.0 - 1.5 * kap) * D0 * ua[s][k];
+      Ybar[s][k] = 3.0 * bc * bg[s].m1[k] + 9.0 * D2ua[k] - 3.0 * D0 * ua[s][k];
+      // Pi = Pi~ +- (beta/2) C.u^a
+      Cbar[s][k] += sgn * hb * Pibar[s] * ua[s][k];
+      uabar[s][k] += sgn * hb * Pibar[s] * C[s][k];
+    }
+  }
+  if (ntot != 0.0) {
+    const double ub = dot3(ubar, u) / ntot;
+    for (int s = 0; s < M; ++s) {
+      for (int k = 0; k < 3; ++k) Jbar[s][k] += ubar[k] / ntot;
+      nbar[s] -= ub;
+    }
+  }
+  double Fb[3] = {0.0, 0.0, 0.0};
+  for (int s = 0; s < M; ++s) {
+    if (n[s] != 0.0) {
+      for (int k = 0; k < 3; ++k) Jbar[s][k] += uabar[s][k] / n[s];
+      nbar[s] -= dot3(uabar[s], ua[s]) / n[s];
+    }
+    double pb[3];
+    for (int k = 0; k < 3; ++k) {
+      if (printed)
+        Xbar[s][k] += 0.5 * Jbar[s][k];
+      else
+        Ybar[s][k] += 0.5 * Jbar[s][k];
+      Cbar[s][k] += Xbar[s][k];
+      Ybar[s][k] += Xbar[s][k];
+      Fb[k] += n[s] * Ybar[s][k];
+      pb[k] = n[s] * Cbar[s][k];
+    }
+    nbar[s] += dot3(Ybar[s], F[s]) + dot3(Cbar[s], phi[s]);
+    store_phibar(g, d, c, s, pb);
+  }
+  for (int k = 0; k < 3; ++k) d.Fbar[(long long)k * N + i] += Fb[k];
+  adj_store_all<0, M>(g, c, i, m, d, Ns, N, 1.0 - ac, nbar, Pibar, Jbar);
+}
+
+template <int M>
+__global__ __launch_bounds__(BLOCK) void k_adj_collide(StepArgs a, AdjArgs d) {
+  adj_collide_body<M>(a, d, blockIdx.x * BLOCK + threadIdx.x);
+}
+
+// Reverse of the read-out of n^a and of the physical J^a = J~ + (X or Y)/2
+// (and of the post-streaming populations themselves): the adjoint state of
+// the final step from the seeds dn, dJ, dpop.
+template <int M>
+__global__ __launch_bounds__(BLOCK) void k_adj_readout(StepArgs a, AdjArgs d) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  const Geom g = a.g;
+  if (i >= g.N) return;
+  const uint32_t m = a.bb[i];
+  const Coord c = decode(g, i);
+  if (m & 1u) {
+    const double z[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < M; ++s) store_phibar(g, d, c, s, z);
+    return;
+  }
+  const long long Ns = pop_stride(g), N = g.N;
+  const long long P = padded_index(g, c.x, c.y, c.z);
+  const bool printed = a.flags & LBE_PRINTED_INV;
+  double Fb[3] = {0.0, 0.0, 0.0};
+  for (int s = 0; s < M; ++s) {
+    const double n = a.nfield[(long long)s * g.Np + P];
+    double Jb[3], pb[3], nb = d.dn ? d.dn[(long long)s * N + i] : 0.0;
+    for (int k = 0; k < 3; ++k) {
+      Jb[k] = d.dJ ? d.dJ[(long long)(3 * s + k) * N + i] : 0.0;
+      const double phi = a.force[6LL * s * N + k * N + i];
+      const double F = a.Fext[(long long)k * N + i] + a.body[s][k];
+      // J = J~ + (C + nF)/2 (printed) or J~ + nF/2
+      const double Yb = 0.5 * Jb[k];
+      const double Cb = printed ? 0.5 * Jb[k] : 0.0;
+      nb += Yb * F + Cb * phi;
+      Fb[k] += n * Yb;
+      pb[k] = n * Cb;
+    }
+    store_phibar(g, d, c, s, pb);
+    for (int q = 0; q < Q; ++q) {
+      const double df = d.dpop ? d.dpop[((long long)s * Q + q) * N + i] : 0.0;
+      const double dg = d.dpop ? d.dpop[((long long)(M + s) * Q + q) * N + i] : 0.0;
+      d.mu_out[((long long)s * Q + q) * Ns + i] = df + nb;
+      d.mu_out[((long long)(M + s) * Q + q) * Ns + i] =
+          dg + cvec(q, 0) * Jb[0] + cvec(q, 1) * Jb[1] + cvec(q, 2) * Jb[2];
+    }
+  }
+  for (int k = 0; k < 3; ++k) d.Fbar[(long long)k * N + i] += Fb[k];
+}
+
+// the tilde moments Pi~, J~ of a state (tape) and its densities n (padded
+// field, as k_moments writes them)
+template <int M>
+__global__ __launch_bounds__(BLOCK) void k_tape_moments(StepArgs a, const double *__restrict__ pop,
+                                                      double *__restrict__ PJ) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  const Geom g = a.g;
+  if (i >= g.N) return;
+  const uint32_t m = a.bb[i];
+  const Coord c = decode(g, i);
+  const long long Ns = pop_stride(g), N = g.N;
+  for (int s = 0; s < M; ++s) {
+    double n = 0.0, Pi = 0.0, J[3] = {0.0, 0.0, 0.0};
+    if (!(m & 1u)) {
+      double v[19];
+      pull19(g, c, i, m, pop + (long long)s * Q * Ns, Ns, v);
+      moments0(v, n);
+      pull19(g, c, i, m, pop + (long long)(M + s) * Q * Ns, Ns, v);
+      moments0(v, Pi);
+      moments1(v, J);
+    }
+    store_images(g, a.nfield + (long long)s * g.Np, c, n);
+    PJ[(long long)s * N + i] = Pi;
+    for (int k = 0; k < 3; ++k) PJ[(long long)(M + 3 * s + k) * N + i] = J[k];
+  }
+}
+
+// adjoint of the shell gather of one directed pair (alpha, beta), see
+// force_body MODE 2; accumulates into nbar_out and Gbar
+template <int R>
+__global__ __launch_bounds__(FNT) void k_adj_force(StepArgs a, AdjArgs d, int alpha, int beta) {
+  extern __shared__ double lds[];
+  force_body<R, 2>(a, &d, alpha, beta, 1, blockIdx.x, blockIdx.y, blockIdx.z, lds);
+}
+
+// Reverse of the contact values: G_ab = 1/(1-xi3) + 3 d xi2/(1-xi3)^2
+// + 2 d^2 xi2^2/(1-xi3)^3 with xi_k = (pi/6) sum_b sigma_b^k nbar_b, giving
+// the adjoint of each ball-averaged density (stored padded, with images)
+template <int M>
+__global__ __launch_bounds__(BLOCK) void k_adj_contact(StepArgs a, AdjArgs d) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  const Geom g = a.g;
+  if (i >= g.N) return;
+  const Coord c = decode(g, i);
+  if (a.bb[i] & 1u) {
+    for (int b = 0; b < M; ++b) store_images(g, d.nbb + (long long)b * g.Np, c, 0.0);
+    return;
+  }
+  const long long P = padded_index(g, c.x, c.y, c.z), N = g.N;
+  double xi2 = 0.0, xi3 = 0.0;
+  for (int b = 0; b < M; ++b) {
+    const double *nb = a.nfield + (long long)b * g.Np + P;
+    const int *off = a.t.ball_off + a.t.ball_start[b];
+    const int cnt = a.t.ball_n[b];
+    double s = 0.0;
+    for (int j = 0; j < cnt; ++j) s += nb[off[j]];
+    const double nbar = s / (double)cnt;
+    const double sg = a.t.sigma[b];
+    xi2 += sg * sg * nbar;
+    xi3 += sg * sg * sg * nbar;
+  }
+  xi2 *= M_PI / 6.0;
+  xi3 *= M_PI / 6.0;
+  const double i1 = 1.0 / (1.0 - xi3), i2 = i1 * i1, i3 = i2 * i1, i4 = i2 * i2;
+  double x2b = 0.0, x3b = 0.0;
+  for (int pa = 0; pa < M; ++pa)
+    for (int pb = pa; pb < M; ++pb) {
+      const int k = pair_index(M, pa, pb);
+      const double dd = a.t.pair_d[k];
+      const double Gb = d.Gbar[(long long)k * N + i];
+      x2b += Gb * (3.0 * dd * i2 + 4.0 * dd * dd * xi2 * i3);
+      x3b += Gb * (i2 + 6.0 * dd * xi2 * i3 + 6.0 * dd * dd * xi2 * xi2 * i4);
+    }
+  for (int b = 0; b < M; ++b) {
+    const double sg = a.t.sigma[b];
+    store_images(g, d.nbb + (long long)b * g.Np, c, (M_PI / 6.0) * (sg * sg * x2b + sg * sg * sg * x3b));
+  }
+}
+
+// transpose of the ball average (the ball is symmetric): nbar_out += the
+// ball average of nbb; zero on solid nodes
+template <int M>
+__global__ __launch_bounds__(BLOCK) void k_adj_ball(StepArgs a, AdjArgs d) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  const Geom g = a.g;
+  if (i >= g.N) return;
+  const long long N = g.N;
+  if (a.bb[i] & 1u) {
+    for (int b = 0; b < M; ++b) d.nbar_out[(long long)b * N + i] = 0.0;
+    return;
+  }
+  const Coord c = decode(g, i);
+  const long long P = padded_index(g, c.x, c.y, c.z);
+  for (int b = 0; b < M; ++b) {
+    const double *nb = d.nbb + (long long)b * g.Np + P;
+    const int *off = a.t.ball_off + a.t.ball_start[b];
+    const int cnt = a.t.ball_n[b];
+    double s = 0.0;
+    for (int j = 0; j < cnt; ++j) s += nb[off[j]];
+    d.nbar_out[(long long)b * N + i] += s / (double)cnt;
+  }
+}
+
+// Vbar = -(grad_h)^T Fbar: transpose of F(r) = -3 sum_p w_p c_p V(idx(r + c_p))
+// (idx wraps periodic directions and clamps the others), as a gather over
+// the nodes r with idx(r + c_p) = this node
+__device__ inline int adj_sources(int x, int n, int c, bool per, int out[2]) {
+  if (per) {
+    int X = x - c;
+    out[0] = X < 0 ? X + n : (X >= n ? X - n : X);
+    return 1;
+  }
+  int k = 0;
+  if (x - c >= 0 && x - c < n) out[k++] = x - c;
+  if (c == -1 && x == 0 && !(k == 1 && out[0] == 0)) out[k++] = 0;
+  if (c == 1 && x == n - 1 && !(k == 1 && out[0] == n - 1)) out[k++] = n - 1;
+  return k;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_adj_extforce(Geom g, const double *__restrict__ Fbar,
+                                                       double *__restrict__ Vbar) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= g.N) return;
+  const Coord c = decode(g, i);
+  const long long N = g.N;
+  double acc = 0.0;
+  for (int p = 1; p < Q; ++p) {
+    int xs[2], ys[2], zs[2];
+    const int kx = adj_sources(c.x, g.nx, cvec(p, 0), g.periodic & 1u, xs);
+    const int ky = adj_sources(c.y, g.ny, cvec(p, 1), g.periodic & 2u, ys);
+    const int kz = adj_sources(c.z, g.nz, cvec(p, 2), g.periodic & 4u, zs);
+    for (int a = 0; a < kz; ++a)
+      for (int b = 0; b < ky; ++b)
+        for (int e = 0; e < kx; ++e) {
+          const long long r = xs[e] + (long long)g.nx * (ys[b] + (long long)g.ny * zs[a]);
+          acc += wgt(p) * (cvec(p, 0) * Fbar[r] + cvec(p, 1) * Fbar[N + r] + cvec(p, 2) * Fbar[2 * N + r]);
+        }
+  }
+  Vbar[i] = -3.0 * acc;
+}
+
+// the adjoint of the post-streaming populations of one (species, dist)
+// block, compact 19N layout
+__global__ __launch_bounds__(BLOCK) void k_adj_state_grad(Geom g, int M, const uint32_t *__restrict__ bb,
+                                                         const double *__restrict__ mu,
+                                                         const double *__restrict__ nbar, int s,
+                                                         int dist, double *__restrict__ out) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= g.N) return;
+  const long long Ns = pop_stride(g), N = g.N;
+  const bool solid = bb[i] & 1u;
+  const double nb = dist == 0 ? nbar[(long long)s * N + i] : 0.0;
+  for (int q = 0; q < Q; ++q)
+    out[(long long)q * N + i] = solid ? 0.0 : mu[((long long)(dist * M + s) * Q + q) * Ns + i] + nb;
+}
+
+__global__ void k_fill(double *__restrict__ p, long long n, double v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
 
 }  // namespace
 
@@ -1139,5 +1609,88 @@ void launch_diag_errn(const Geom &g, int M, const uint32_t *bb, const Readout &r
   hipLaunchKernelGGL(k_diag_errn, dim3(nblocks), dim3(BLOCK), 0, s, g, M, bb, r, V, beta, result,
                      partials);
 }
+
+// ------------------------------------------------------------------------
+// adjoint launchers
+// ------------------------------------------------------------------------
+#define LBE_SWITCH_M(M_, CALL) \
+  switch (M_) {                \
+    case 1: { constexpr int MM = 1; CALL; } break; \
+    case 2: { constexpr int MM = 2; CALL; } break; \
+    case 3: { constexpr int MM = 3; CALL; } break; \
+    default: { constexpr int MM = 4; CALL; } break; \
+  }
+
+void launch_tape_moments(const StepArgs &a, const double *pop, double *PJ, hipStream_t s) {
+  const dim3 gr = grid_for(a.g.N);
+  LBE_SWITCH_M(a.M, hipLaunchKernelGGL(k_tape_moments<MM>, gr, dim3(BLOCK), 0, s, a, pop, PJ))
+}
+
+void launch_adj_collide(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
+  const dim3 gr = grid_for(a.g.N);
+  LBE_SWITCH_M(a.M, hipLaunchKernelGGL(k_adj_collide<MM>, gr, dim3(BLOCK), 0, s, a, d))
+}
+
+void launch_adj_readout(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
+  const dim3 gr = grid_for(a.g.N);
+  LBE_SWITCH_M(a.M, hipLaunchKernelGGL(k_adj_readout<MM>, gr, dim3(BLOCK), 0, s, a, d))
+}
+
+template <int R>
+static void adj_force_launch(const StepArgs &a, const AdjArgs &d, int alpha, int beta, hipStream_t s) {
+  const int k = pair_index(a.M, alpha, beta);
+  const size_t bytes = sizeof(double) * (2 * 5 * (FTX + 2 * R) * (FTY + 2 * R) + 4 * a.t.pair_nent[k]);
+  static size_t attr = 0;
+  if (bytes > attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_adj_force<R>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    attr = bytes;
+  }
+  dim3 gr((a.g.nx + FTX - 1) / FTX, (a.g.ny + FTY - 1) / FTY, (a.g.nz + a.zchunk - 1) / a.zchunk);
+  hipLaunchKernelGGL(k_adj_force<R>, gr, dim3(FNT), bytes, s, a, d, alpha, beta);
+}
+
+void launch_fill(double *p, long long n, double v, hipStream_t s) {
+  if (n <= 0) return;
+  long long blocks = (n + BLOCK - 1) / BLOCK;
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(BLOCK), 0, s, p, n, v);
+}
+
+void launch_adj_nonlocal(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
+  const long long N = a.g.N;
+  launch_fill(d.nbar_out, a.M * N, 0.0, s);
+  if (a.flags & LBE_IDEAL) return;  // no force: densities enter only locally
+  launch_fill(d.Gbar, (long long)(a.M * (a.M + 1) / 2) * N, 0.0, s);
+  for (int al = 0; al < a.M; ++al)
+    for (int be = 0; be < a.M; ++be) {
+      const int R = a.t.pair_R[pair_index(a.M, al, be)];
+      switch (R) {
+        case 0: break;  // empty shell
+        case 1: adj_force_launch<1>(a, d, al, be, s); break;
+        case 2: adj_force_launch<2>(a, d, al, be, s); break;
+        case 3: adj_force_launch<3>(a, d, al, be, s); break;
+        case 4: adj_force_launch<4>(a, d, al, be, s); break;
+        case 5: adj_force_launch<5>(a, d, al, be, s); break;
+        case 6: adj_force_launch<6>(a, d, al, be, s); break;
+        case 7: adj_force_launch<7>(a, d, al, be, s); break;
+        default: adj_force_launch<8>(a, d, al, be, s); break;
+      }
+    }
+  const dim3 gr = grid_for(a.g.N);
+  LBE_SWITCH_M(a.M, hipLaunchKernelGGL(k_adj_contact<MM>, gr, dim3(BLOCK), 0, s, a, d))
+  LBE_SWITCH_M(a.M, hipLaunchKernelGGL(k_adj_ball<MM>, gr, dim3(BLOCK), 0, s, a, d))
+}
+
+void launch_adj_extforce(const Geom &g, const double *Fbar, double *Vbar, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_extforce, grid_for(g.N), dim3(BLOCK), 0, s, g, Fbar, Vbar);
+}
+
+void launch_adj_state_grad(const Geom &g, int M, const uint32_t *bb, const double *mu,
+                           const double *nbar, int species, int dist, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_state_grad, grid_for(g.N), dim3(BLOCK), 0, s, g, M, bb, mu, nbar, species,
+                     dist, out);
+}
+
+#undef LBE_SWITCH_M
 
 }  // namespace lbe

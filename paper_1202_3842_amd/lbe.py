@@ -93,6 +93,7 @@ def lib() -> C.CDLL:
     L.lbe_get_density.argtypes = [P, C.c_int, P, C.c_int]
     L.lbe_get_velocity.argtypes = [P, C.c_int, P, C.c_int]
     L.lbe_get_force.argtypes = [P, C.c_int, C.c_int, P, C.c_int]
+    L.lbe_get_momentum.argtypes = [P, C.c_int, P, C.c_int]
     L.lbe_get_populations.argtypes = [P, C.c_int, C.c_int, P, C.c_int]
     L.lbe_set_populations.argtypes = [P, C.c_int, C.c_int, P, C.c_int]
     L.lbe_diagnostics.argtypes = [P, C.POINTER(lbe_diag)]
@@ -106,6 +107,14 @@ def lib() -> C.CDLL:
     L.lbe_batch_step.argtypes = [P, C.c_int, C.c_int]
     L.lbe_batch_destroy.argtypes = [P]
     L.lbe_batch_destroy.restype = None
+    L.lbe_adjoint_workspace_bytes.restype = C.c_size_t
+    L.lbe_adjoint_workspace_bytes.argtypes = [C.POINTER(lbe_config), C.c_int, C.c_int]
+    L.lbe_adjoint_create.argtypes = [P, C.c_int, C.c_int, P, C.c_size_t, C.POINTER(P)]
+    L.lbe_adjoint_forward.argtypes = [P]
+    L.lbe_adjoint_backward.argtypes = [P, P, P, P, C.c_int, P, C.c_int]
+    L.lbe_adjoint_state_grad.argtypes = [P, C.c_int, C.c_int, P, C.c_int]
+    L.lbe_adjoint_destroy.argtypes = [P]
+    L.lbe_adjoint_destroy.restype = None
     _lib = L
     return L
 
@@ -238,6 +247,11 @@ class Box:
         _check(lib().lbe_get_velocity(self.h, int(species), p, w))
         return arr.reshape((3,) + self.shape) if out is None else arr
 
+    def momentum(self, species=-1, out=None):
+        p, w, arr = self._dst(out, np.float64, 3 * self.N)
+        _check(lib().lbe_get_momentum(self.h, int(species), p, w))
+        return arr.reshape((3,) + self.shape) if out is None else arr
+
     def force(self, species=0, which=0, out=None):
         p, w, arr = self._dst(out, np.float64, 3 * self.N)
         _check(lib().lbe_get_force(self.h, int(species), int(which), p, w))
@@ -349,3 +363,129 @@ def batch_from_workloads(ws, prec=LBE_FP64, flags=LBE_VISC) -> Batch:
     for box, w in zip(b.boxes, ws):
         load_workload(box, w)
     return b
+
+
+class Adjoint:
+    """Reverse mode of `nsteps` steps of a Box with respect to its potential
+    V (lbe_adjoint_*), checkpointed every `segment` steps.
+
+    forward() advances the box from its current state; backward(dn, dJ, dpop)
+    takes dL/d(final n^a), dL/d(final J^a) and dL/d(final populations) (any
+    may be None; numpy arrays or torch CUDA tensors shaped (M, nz, ny, nx),
+    (M, 3, nz, ny, nx) and (2, M, 19, nz, ny, nx)) and returns dL/dV.
+    """
+
+    def __init__(self, box: Box, nsteps: int, segment: int = 20):
+        torch = box.torch
+        self.box = box
+        self.nsteps = int(nsteps)
+        self.segment = int(segment)
+        n = lib().lbe_adjoint_workspace_bytes(C.byref(box.cfg), self.nsteps, self.segment)
+        if n == 0:
+            raise LBEError(LBE_ERR_UNSUPPORTED, lib().lbe_last_error().decode())
+        self.workspace = torch.empty(int(n), dtype=torch.uint8, device="cuda")
+        h = C.c_void_p()
+        _check(lib().lbe_adjoint_create(box.h, self.nsteps, self.segment,
+                                        C.c_void_p(self.workspace.data_ptr()), int(n), C.byref(h)))
+        self.h = h
+
+    def forward(self):
+        _check(lib().lbe_adjoint_forward(self.h))
+
+    def backward(self, dn=None, dJ=None, dpop=None, out=None):
+        b = self.box
+        M, N = b.M, b.N
+        t = b.torch
+        dev = any(isinstance(a, t.Tensor) and a.is_cuda for a in (dn, dJ, dpop) if a is not None)
+        ptrs, keep = [], []
+        for a, count in ((dn, M * N), (dJ, 3 * M * N), (dpop, 2 * M * 19 * N)):
+            if a is None:
+                ptrs.append(None)
+                continue
+            if dev:
+                a = t.as_tensor(a, dtype=t.float64, device="cuda").contiguous().reshape(-1)
+                ptrs.append(C.c_void_p(a.data_ptr()))
+            else:
+                a = np.ascontiguousarray(np.asarray(a), dtype=np.float64).reshape(-1)
+                ptrs.append(C.c_void_p(a.ctypes.data))
+            assert a.numel() == count if dev else a.size == count
+            keep.append(a)
+        where = LBE_DEVICE if dev else LBE_HOST
+        p, w, arr = b._dst(out, np.float64, N)
+        _check(lib().lbe_adjoint_backward(self.h, ptrs[0], ptrs[1], ptrs[2], where, p, w))
+        return arr.reshape(b.shape) if out is None else arr
+
+    def state_grad(self, species=0, dist=0, out=None):
+        b = self.box
+        p, w, arr = b._dst(out, np.float64, 19 * b.N)
+        _check(lib().lbe_adjoint_state_grad(self.h, int(species), int(dist), p, w))
+        return arr.reshape((19,) + b.shape) if out is None else arr
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbe_adjoint_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def potential_to_state(V, adjoint: Adjoint, reset):
+    """Differentiable map V -> (n, J) of the final state, for torch autograd.
+
+    V: float64 torch tensor (nz, ny, nx) on the GPU; reset(box) puts the box
+    into the initial state (called before each forward).  Returns n shaped
+    (M, nz, ny, nx) and J shaped (M, 3, nz, ny, nx), CUDA float64; their
+    gradients flow back to V through lbe_adjoint_backward.
+    """
+    return _PotentialToState.apply(V, adjoint, reset)
+
+
+def _autograd_function():
+    import torch
+
+    class PotentialToState(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, V, adjoint, reset):
+            b = adjoint.box
+            Vd = V.detach().to(device="cuda", dtype=torch.float64).contiguous()
+            b.set_potential(Vd)
+            reset(b)
+            adjoint.forward()
+            n = torch.empty((b.M,) + b.shape, dtype=torch.float64, device="cuda")
+            J = torch.empty((b.M, 3) + b.shape, dtype=torch.float64, device="cuda")
+            for a in range(b.M):
+                b.density(a, out=n[a].view(-1))
+                b.momentum(a, out=J[a].view(-1))
+            ctx.adjoint = adjoint
+            ctx.V_device = V.device
+            return n, J
+
+        @staticmethod
+        def backward(ctx, gn, gJ):
+            adj = ctx.adjoint
+            b = adj.box
+            out = torch.empty(b.shape, dtype=torch.float64, device="cuda")
+            gn = None if gn is None else gn.to(device="cuda", dtype=torch.float64).contiguous()
+            gJ = None if gJ is None else gJ.to(device="cuda", dtype=torch.float64).contiguous()
+            if gn is None and gJ is None:
+                return torch.zeros(b.shape, dtype=torch.float64, device=ctx.V_device), None, None
+            adj.backward(gn, gJ, None, out=out.view(-1))
+            return out.to(ctx.V_device), None, None
+
+    return PotentialToState
+
+
+class _Lazy:
+    fn = None
+
+    def apply(self, *args):
+        if _Lazy.fn is None:
+            _Lazy.fn = _autograd_function()
+        return _Lazy.fn.apply(*args)
+
+
+_PotentialToState = _Lazy()

@@ -188,3 +188,31 @@ def c4_boxes(count: int = 96, seed: int = 3842, steps: int = 500,
         out.append(well_box(L, sigma, nsig3, eps_for_depth(depth), L / 4.0, 1e-3, seed + 1 + b,
                             steps, name=f"box{b}"))
     return out
+
+
+# --------------------------------------------------------------------------
+# The gradient check on the channel: an objective of the final state whose
+# gradient with respect to the potential V(r) the adjoint computes.
+# --------------------------------------------------------------------------
+FLUX_PLANE_X = 48
+
+
+def c5_objective(w: Workload):
+    """Inputs of the objective on the 96x32x32 channel after w.steps steps,
+        L = sum_{fluid r} (n_A(r) - n_t(r))^2 + sum_{r in plane} sum_a J_x^a(r),
+    with the target n_t = n_A0 (1 + 0.05 s(r)), s a 4-mode smooth field of
+    unit amplitude (seed 1204), and the plane the fluid nodes of x = 48 (the
+    middle of the constriction).  Returns (n_t, fluid_mask, plane_mask)."""
+    s = smooth_field(w.shape, 1.0, 4, 1204)
+    n_t = w.density[0] * (1.0 + 0.05 * s)
+    fluid = (w.solid == 0) if w.solid is not None else np.ones(w.shape, dtype=bool)
+    plane = np.zeros(w.shape, dtype=bool)
+    plane[:, :, FLUX_PLANE_X] = True
+    return n_t, fluid, plane & fluid
+
+
+def sample_fluid_nodes(w: Workload, count: int = 32, seed: int = 1205) -> np.ndarray:
+    """Flat indices of `count` distinct fluid nodes drawn with a fixed seed."""
+    fluid = np.flatnonzero((w.solid.reshape(-1) == 0) if w.solid is not None
+                           else np.ones(w.nodes, dtype=bool))
+    return np.sort(rng(seed).choice(fluid, size=count, replace=False))

@@ -1,0 +1,80 @@
+"""Central finite differences of the channel objective with respect to V.
+
+Writes ``channel96_fd_grad.json``: dL/dV at 32 seeded fluid nodes of the
+96x32x32 two-species channel (C^mf only, derived inversions, 400 steps), each
+from two runs of the oracle with V(r_i) moved by +-h.  The objective is the
+one described in ``paper_1202_3842_amd.workloads.c5_objective``.  Only the
+oracle computes anything here; the GPU adjoint is compared with these values
+by tests/test_gpu_adjoint.py.
+
+    python tests/golden/make_channel_fd.py [--threads 8]   (about 80 min on 8 cores)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parents[2]
+sys.path.insert(0, str(ROOT))
+
+import oracle  # noqa: E402
+from paper_1202_3842_amd import workloads as W  # noqa: E402
+
+H = 1e-6
+OUT = Path(__file__).resolve().parent / "channel96_fd_grad.json"
+
+
+def objective(w, V, flags, steps):
+    o = oracle.Oracle(w.nx, w.ny, w.nz, w.sigma, w.periodic, w.tau, w.kT, flags=flags)
+    o.set_solid(w.solid)
+    o.set_potential(V)
+    for a in range(w.nspecies):
+        o.init_density(a, w.density[a])
+        o.set_body_force(a, w.body[a])
+    o.step(steps)
+    n_t, fluid, plane = W.c5_objective(w)
+    nA = o.density(0)
+    dens = float(np.sum(((nA - n_t) ** 2)[fluid]))
+    flux = 0.0
+    for a in range(w.nspecies):
+        J = o.density(a) * o.velocity(a)[0]
+        flux += float(np.sum(J[plane]))
+    o.close()
+    return dens + flux, dens, flux
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--threads", type=int, default=8)
+    ap.add_argument("--count", type=int, default=32)
+    args = ap.parse_args()
+    oracle.set_threads(args.threads)
+    w = W.c5_channel()
+    flags = 0
+    nodes = W.sample_fluid_nodes(w, args.count)
+    t0 = time.time()
+    L0, d0, f0 = objective(w, w.V, flags, w.steps)
+    print(f"L0 = {L0:.17g} (density {d0:.6g}, flux {f0:.6g}) {time.time() - t0:.0f}s", flush=True)
+    rows = []
+    for k, i in enumerate(nodes):
+        V = w.V.copy().reshape(-1)
+        V[i] += H
+        Lp = objective(w, V.reshape(w.shape), flags, w.steps)[0]
+        V[i] -= 2 * H
+        Lm = objective(w, V.reshape(w.shape), flags, w.steps)[0]
+        g = (Lp - Lm) / (2 * H)
+        rows.append({"node": int(i), "Lp": Lp, "Lm": Lm, "grad": g})
+        print(f"{k + 1}/{len(nodes)} node {i}: dL/dV = {g:.10e} {time.time() - t0:.0f}s", flush=True)
+        OUT.write_text(json.dumps({
+            "workload": w.name, "steps": w.steps, "flags": flags, "h": H, "L0": L0,
+            "rows": rows}, indent=1))
+    print("wrote", OUT)
+
+
+if __name__ == "__main__":
+    main()

@@ -38,7 +38,25 @@ def test_workspace_size_and_validation(L):
     bad = lbe.make_config(32, 32, 32, [4.0], kT=0.5)
     with pytest.raises(lbe.LBEError):
         lbe.workspace_bytes(bad)
-    small = lbe.make_config(4, 32, 32, [12.0])  # periodic edge shorter than the range
+    small = lbe.make_config(4, 32, 32, [6.0])  # periodic edge shorter than the range
     with pytest.raises(lbe.LBEError):
         lbe.workspace_bytes(small)
-    assert b"kT" in L.lbe_last_error() or b"range" in L.lbe_last_error()
+    assert b"range" in L.lbe_last_error()
+    huge = lbe.make_config(32, 32, 32, [12.0])
+    with pytest.raises(lbe.LBEError):
+        lbe.workspace_bytes(huge)
+    assert b"sigma" in L.lbe_last_error()
+
+
+def test_adjoint_workspace_and_scope(L):
+    cfg = lbe.make_config(32, 32, 32, [4.0], flags=0)
+    n1 = L.lbe_adjoint_workspace_bytes(C.byref(cfg), 100, 10)
+    n2 = L.lbe_adjoint_workspace_bytes(C.byref(cfg), 100, 50)
+    pop = 2 * 19 * 32 ** 3 * 8
+    # 11 checkpoints + 10 tape slots vs 3 checkpoints + 50 tape slots
+    assert n1 >= 11 * pop and n2 > n1
+    for bad in (lbe.make_config(32, 32, 32, [4.0], flags=lbe.LBE_VISC),
+                lbe.make_config(32, 32, 32, [4.0], prec=lbe.LBE_FP32_POP, flags=0)):
+        assert L.lbe_adjoint_workspace_bytes(C.byref(bad), 10, 5) == 0
+    assert b"adjoint" in L.lbe_last_error()
+    assert L.lbe_adjoint_workspace_bytes(C.byref(cfg), 0, 5) == 0

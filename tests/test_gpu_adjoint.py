@@ -1,0 +1,149 @@
+"""GPU adjoint (lbe_adjoint_*) against the reference gradient of
+oracle/autograd_ref.py (autograd of the step re-expressed in torch, CPU
+FP64), and on the 96x32x32 channel against central finite differences of
+the C oracle (tests/golden/channel96_fd_grad.json)."""
+import json
+from pathlib import Path
+
+import numpy as np
+import pytest
+import torch
+
+from adjoint_util import small_channel, objective_terms, pop_weights
+from paper_1202_3842_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = Path(__file__).resolve().parent / "golden" / "channel96_fd_grad.json"
+
+
+def reference(w, flags, T, pw):
+    from oracle import autograd_ref as AR
+    n_t, fluid, plane = objective_terms(w)
+    geo = AR.Geometry(w.nx, w.ny, w.nz, w.periodic,
+                      (w.solid if w.solid is not None else np.zeros(w.shape)).astype(bool))
+    st = AR.Stepper(geo, w.sigma, w.tau, w.kT, flags, w.body)
+    V = torch.tensor(w.V.reshape(-1), requires_grad=True)
+    f0, g0 = st.rest_state(np.stack(w.density))
+    f0.requires_grad_(True)
+    g0.requires_grad_(True)
+    f, g = st.run(f0, g0, V, T)
+    n, J = st.readout(f, g, V)
+    L = ((n[0] - torch.tensor(n_t.reshape(-1))) ** 2 * torch.tensor(fluid.reshape(-1), dtype=torch.float64)).sum()
+    L = L + (J[:, 0, :] * torch.tensor(plane.reshape(-1), dtype=torch.float64)).sum()
+    if pw is not None:
+        pwt = torch.tensor(pw.reshape(2, w.nspecies, 19, -1))
+        L = L + (pwt[0] * f).sum() + (pwt[1] * g).sum()
+    L.backward()
+    return V.grad.numpy().reshape(w.shape), f0.grad.numpy(), g0.grad.numpy()
+
+
+def gpu_gradient(w, flags, T, segment, pw):
+    from paper_1202_3842_amd import lbe
+    box = lbe.box_from_workload(w, flags=flags)
+    adj = lbe.Adjoint(box, T, segment)
+    adj.forward()
+    n_t, fluid, plane = objective_terms(w)
+    M = w.nspecies
+    dn = np.zeros((M,) + w.shape)
+    dn[0] = 2.0 * (box.density(0) - n_t) * fluid
+    dJ = np.zeros((M, 3) + w.shape)
+    for a in range(M):
+        dJ[a, 0] = plane
+    gV = adj.backward(dn, dJ, pw)
+    gf = np.stack([adj.state_grad(a, 0).reshape(19, -1) for a in range(M)])
+    gg = np.stack([adj.state_grad(a, 1).reshape(19, -1) for a in range(M)])
+    adj.close()
+    box.close()
+    return gV, gf, gg
+
+
+def assert_close(got, ref, rtol, what):
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref).max()
+    print(f"{what}: max|ref| {scale:.3e} max err {err:.3e}", flush=True)
+    assert err <= rtol * scale, (what, err, scale)
+
+
+@pytest.mark.parametrize("flags,T,segment", [
+    (0, 6, 6), (0, 6, 4), (0, 7, 1), (2, 6, 3), (4, 5, 2), (2 | 4, 5, 5)])
+def test_adjoint_matches_reference(flags, T, segment):
+    w = small_channel()
+    pw = pop_weights(w) * 1e-3
+    print(f"small channel flags {flags} T {T} segment {segment}", flush=True)
+    rV, rf, rg = reference(w, flags, T, pw)
+    gV, gf, gg = gpu_gradient(w, flags, T, segment, pw)
+    assert_close(gV, rV, 1e-10, "dL/dV")
+    assert_close(gf, rf, 1e-10, "dL/df0")
+    assert_close(gg, rg, 1e-10, "dL/dg0")
+
+
+def test_adjoint_one_species_periodic_well():
+    w = W.well_box(16, 3.0, 0.3, W.eps_for_depth(1.0), 5.0, 1e-2, 31, 5, "well16_s3")
+    w.V = w.V + W.smooth_field(w.shape, 0.02, 3, 32)
+    w.solid = np.zeros(w.shape, dtype=np.uint8)
+    pw = pop_weights(w, 6) * 1e-3
+    print("well16 sigma 3 one species", flush=True)
+    rV, rf, rg = reference(w, 0, 5, pw)
+    gV, gf, gg = gpu_gradient(w, 0, 5, 2, pw)
+    assert_close(gV, rV, 1e-10, "dL/dV")
+    assert_close(gf, rf, 1e-10, "dL/df0")
+
+
+def test_autograd_function_matches_adjoint():
+    from paper_1202_3842_amd import lbe
+    w = small_channel()
+    n_t, fluid, plane = objective_terms(w)
+    box = lbe.box_from_workload(w, flags=0)
+    adj = lbe.Adjoint(box, 5, 2)
+    n0 = [torch.tensor(d, device="cuda") for d in w.density]
+
+    def reset(b):
+        for a, d in enumerate(n0):
+            b.init_density(a, d.reshape(-1))
+
+    V = torch.tensor(w.V, device="cuda", requires_grad=True)
+    n, J = lbe.potential_to_state(V, adj, reset)
+    nt = torch.tensor(n_t, device="cuda")
+    fl = torch.tensor(fluid, device="cuda", dtype=torch.float64)
+    pl = torch.tensor(plane, device="cuda", dtype=torch.float64)
+    L = (((n[0] - nt) ** 2) * fl).sum() + (J[:, 0] * pl).sum()
+    L.backward()
+    rV, _, _ = reference(w, 0, 5, None)
+    assert_close(V.grad.cpu().numpy(), rV, 1e-10, "autograd dL/dV")
+
+
+@pytest.mark.skipif(not GOLDEN.exists(), reason="finite-difference golden file not generated")
+def test_channel96_gradient_against_oracle_fd():
+    from paper_1202_3842_amd import lbe
+    gold = json.loads(GOLDEN.read_text())
+    w = W.c5_channel()
+    assert gold["workload"] == w.name and gold["steps"] == w.steps
+    n_t, fluid, plane = W.c5_objective(w)
+    box = lbe.box_from_workload(w, flags=gold["flags"])
+    adj = lbe.Adjoint(box, w.steps, 20)
+    adj.forward()
+    nA = box.density(0)
+    d = box.diagnostics()
+    assert not d["unstable"]
+    M = w.nspecies
+    dn = np.zeros((M,) + w.shape)
+    dn[0] = 2.0 * (nA - n_t) * fluid
+    dJ = np.zeros((M, 3) + w.shape)
+    for a in range(M):
+        dJ[a, 0] = plane
+    L = float(np.sum(((nA - n_t) ** 2)[fluid])) + sum(
+        float(np.sum(box.momentum(a)[0][plane])) for a in range(M))
+    assert abs(L - gold["L0"]) <= 1e-9 * abs(gold["L0"])
+    gV = adj.backward(dn, dJ).reshape(-1)
+    rows = gold["rows"]
+    scale = max(abs(r["grad"]) for r in rows)
+    # central differences carry ~eps |L| / h of rounding noise
+    noise = 2.2e-16 * abs(gold["L0"]) / gold["h"]
+    worst = 0.0
+    for r in rows:
+        err = abs(gV[r["node"]] - r["grad"])
+        worst = max(worst, err)
+        assert err <= 1e-6 * scale + 10 * noise, (r["node"], gV[r["node"]], r["grad"])
+    print(f"channel96: {len(rows)} nodes, max|grad| {scale:.3e}, worst err {worst:.3e}, "
+          f"fd noise {noise:.1e}", flush=True)
