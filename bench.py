@@ -175,6 +175,66 @@ def batch_leg(lbe, torch, W, flags, prec, steps, serial_steps, tune=True):
     }
 
 
+def adjoint_leg(lbe, torch, W, segment=20):
+    """dL/dV on the 96x32x32 two-species channel (C^mf scheme, 400 steps):
+    the forward with a checkpoint every `segment` steps and the backward
+    (segment recompute + adjoint steps) against 400 plain forward steps."""
+    from paper_1202_3842_amd import autotune
+    import numpy as np
+    w = W.c5_channel()
+    T = w.steps
+    n_t, fluid, plane = W.c5_objective(w)
+    box = lbe.box_from_workload(w, flags=0)
+    autotune.tune_zchunk(box)
+    st = box.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    box.step(10)
+    lbe.load_workload(box, w)
+    torch.cuda.synchronize()
+    ev[0].record(st)
+    box.step(T)
+    ev[1].record(st)
+    ev[1].synchronize()
+    t_plain = ev[0].elapsed_time(ev[1])
+    adj = lbe.Adjoint(box, T, segment)
+    lbe.load_workload(box, w)
+    torch.cuda.synchronize()
+    ev[2].record(st)
+    adj.forward()
+    ev[3].record(st)
+    ev[3].synchronize()
+    t_fwd = ev[2].elapsed_time(ev[3])
+    M = w.nspecies
+    nA = box.density(0)
+    dn = np.zeros((M,) + w.shape)
+    dn[0] = 2.0 * (nA - n_t) * fluid
+    dJ = np.zeros((M, 3) + w.shape)
+    for a in range(M):
+        dJ[a, 0] = plane
+    dn_d = torch.tensor(dn, device="cuda")
+    dJ_d = torch.tensor(dJ, device="cuda")
+    out = torch.empty(w.nodes, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    ev[4].record(st)
+    adj.backward(dn_d, dJ_d, None, out=out)
+    ev[5].record(st)
+    ev[5].synchronize()
+    t_bwd = ev[4].elapsed_time(ev[5])
+    gnorm = float(out.abs().max())
+    adj.close()
+    box.close()
+    log(f"adjoint: plain forward {t_plain:.1f} ms, checkpointed forward {t_fwd:.1f} ms, "
+        f"backward {t_bwd:.1f} ms ({T} steps)")
+    return {
+        "workload": w.name, "steps": T, "segment": segment, "species": M, "sigma": w.sigma,
+        "scheme": "C^mf, derived inversion",
+        "forward_ms": round(t_plain, 3), "forward_checkpointed_ms": round(t_fwd, 3),
+        "backward_ms": round(t_bwd, 3),
+        "adjoint_vs_forward": round(t_bwd / t_plain, 3),
+        "max_abs_dL_dV": gnorm,
+    }
+
+
 def cpu_baseline(w, flags, budget_s):
     """The oracle as it stands, on the host cores, over a bounded number of
     steps of the same workload from its initial state."""
@@ -223,6 +283,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint leg and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -234,6 +297,9 @@ def main():
     from paper_1202_3842_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_leg(lbe, torch, W)}), flush=True)
+        return
     w = W.c2_large_well()
     # The library's default (derived) inversions make this start-up collapse
     # within ~60 steps; the printed inversions of Sec. 4.2 keep it bounded for
@@ -262,6 +328,8 @@ def main():
             "fp32_pop": batch_leg(lbe, torch, W, flags, lbe.LBE_FP32_POP, max(args.batch_steps // 5, 10),
                                   max(args.batch_steps // 5, 10)),
         }
+
+    adjoint = None if args.no_adjoint else adjoint_leg(lbe, torch, W)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -298,6 +366,7 @@ def main():
         },
         "state_after": {"umax": r64["diag"]["umax"], "unstable": r64["diag"]["unstable"]},
         "batched": batched,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

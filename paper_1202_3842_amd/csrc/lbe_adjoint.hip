@@ -25,8 +25,8 @@ struct AdjPlan {
   Plan pl;
   int T = 0, S = 0, nseg = 0;
   size_t slot_bytes = 0, mu_bytes = 0, total = 0;
-  size_t off_cp = 0, off_roll = 0, off_tape = 0, off_mu = 0, off_nbar = 0, off_phibar = 0,
-         off_Gbar = 0, off_nbb = 0, off_Fbar = 0, off_Vbar = 0, off_stage = 0;
+  size_t off_cp = 0, off_roll = 0, off_tape = 0, off_mu = 0, off_node = 0, off_nbar = 0,
+         off_phibar = 0, off_Gbar = 0, off_nbb = 0, off_Fbar = 0, off_Vbar = 0, off_stage = 0;
   // inside a tape slot
   size_t so_n = 0, so_G = 0, so_force = 0, so_PJ = 0;
 };
@@ -59,7 +59,8 @@ lbe_status make_adj_plan(const lbe_config *cfg, int nsteps, int segment, AdjPlan
   ap.off_roll = take(P.pop_bytes * 2);
   ap.off_tape = take(ap.slot_bytes * (size_t)ap.S);
   ap.off_mu = take(ap.mu_bytes * 2);
-  ap.off_nbar = take(sizeof(double) * 2 * M * N);
+  ap.off_node = take(sizeof(double) * 5 * M * N);
+  ap.off_nbar = take(sizeof(double) * M * N);
   ap.off_phibar = take(sizeof(double) * 3 * M * Np);
   ap.off_Gbar = take(sizeof(double) * npairs * N);
   ap.off_nbb = take(sizeof(double) * M * Np);
@@ -76,16 +77,13 @@ struct lbe_adjoint {
   lbe_ctx *c = nullptr;
   AdjPlan ap;
   char *ws = nullptr;
-  int cur = 0;              // mu/nbar buffer holding the adjoint state
+  int cur = 0;              // mu buffer holding the adjoint state
   bool forward_done = false, backward_done = false;
 
   char *cp(int k) const { return ws + ap.off_cp + (size_t)k * ap.pl.pop_bytes; }
   char *roll(int k) const { return ws + ap.off_roll + (size_t)k * ap.pl.pop_bytes; }
   char *slot(int j) const { return ws + ap.off_tape + (size_t)j * ap.slot_bytes; }
   double *mu(int k) const { return (double *)(ws + ap.off_mu + (size_t)k * ap.mu_bytes); }
-  double *nbar(int k) const {
-    return (double *)(ws + ap.off_nbar) + (size_t)k * ap.pl.M * ap.pl.g.N;
-  }
   double *at(size_t off) const { return (double *)(ws + off); }
 
   // the box's parameter block with the fields of tape slot j
@@ -102,6 +100,8 @@ struct lbe_adjoint {
   AdjArgs base_args() const {
     AdjArgs d;
     memset(&d, 0, sizeof d);
+    d.node = at(ap.off_node);
+    d.nbar = at(ap.off_nbar);
     d.phibar = at(ap.off_phibar);
     d.Gbar = at(ap.off_Gbar);
     d.nbb = at(ap.off_nbb);
@@ -206,9 +206,9 @@ lbe_status lbe_adjoint_backward(lbe_adjoint *A, const double *dL_dn, const doubl
     AdjArgs e = d;
     e.PJ = A->slot_PJ(0);
     e.mu_out = A->mu(0);
-    e.nbar_out = A->nbar(0);
     launch_adj_readout(a, e, s);
     launch_adj_nonlocal(a, e, s);
+    launch_adj_stream(a, e, true, s);
   }
   if (where == LBE_HOST) HIP_TRY(hipStreamSynchronize(s));  // host seeds may go away
   int cur = 0;
@@ -224,12 +224,11 @@ lbe_status lbe_adjoint_backward(lbe_adjoint *A, const double *dL_dn, const doubl
       e.dpop = e.dn = e.dJ = nullptr;
       e.PJ = A->slot_PJ(j);
       e.mu_in = A->mu(cur);
-      e.nbar_in = A->nbar(cur);
       e.mu_out = A->mu(cur ^ 1);
-      e.nbar_out = A->nbar(cur ^ 1);
       const StepArgs a = A->slot_args(j);
       launch_adj_collide(a, e, s);
       launch_adj_nonlocal(a, e, s);
+      launch_adj_stream(a, e, false, s);
       cur ^= 1;
     }
   }
@@ -254,8 +253,7 @@ lbe_status lbe_adjoint_state_grad(lbe_adjoint *A, int species, int dist, double 
   if (where != LBE_HOST && where != LBE_DEVICE) return fail(LBE_ERR_ARG, "bad 'where'");
   hipStream_t s = A->c->stream;
   double *stage = A->at(ap.off_stage);
-  launch_adj_state_grad(ap.pl.g, ap.pl.M, A->c->args.bb, A->mu(A->cur), A->nbar(A->cur), species, dist,
-                        stage, s);
+  launch_adj_state_grad(ap.pl.g, ap.pl.M, A->c->args.bb, A->mu(A->cur), species, dist, stage, s);
   LAUNCH_CHECK();
   HIP_TRY(hipMemcpyAsync(out, stage, sizeof(double) * Q * ap.pl.g.N,
                          where == LBE_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));

@@ -98,17 +98,16 @@ struct Readout {
 };
 
 // Buffers of the adjoint passes (FP64).  "bar" marks dL/d(quantity).  The
-// adjoint state of a step lives in the post-streaming frame: mu holds one
-// value per population (the population layout of a state buffer), nbar the
-// nonlocal part of the density adjoint (M*N); the adjoint of the stored
-// pre-streaming value at (r, q) is mu + nbar (f only) at the node that
-// pulls it.
+// adjoint state of a step is mu: one value per population in the
+// post-streaming frame (the population layout of a state buffer), i.e. the
+// adjoint of f~_p(r), g~_p(r); the adjoint of the stored pre-streaming value
+// at (r, q) is mu at the node that pulls it.
 struct AdjArgs {
   const double *PJ;        // 4M*N tilde moments of the state: Pi~ (M), J~ (3M)
   const double *mu_in;     // adjoint state after the step
-  const double *nbar_in;
   double *mu_out;          // adjoint state before the step
-  double *nbar_out;
+  double *node;            // 5M*N node adjoints of the collision: nbar (M), Pi~bar (M), J~bar (3M)
+  double *nbar;            // M*N: the nonlocal part of the density adjoint
   double *phibar;          // 3M*Np padded: adjoint of the force per particle C^mf_a/n_a
   double *Gbar;            // npairs*N: adjoint of the contact values
   double *nbb;             // M*Np padded: adjoint of the ball-averaged densities
@@ -156,10 +155,13 @@ void prepare_force_kernels(int maxR, bool visc, int max_entries);
 void launch_tape_moments(const StepArgs &a, const double *pop, double *PJ, hipStream_t s);
 void launch_adj_collide(const StepArgs &a, const AdjArgs &d, hipStream_t s);
 void launch_adj_readout(const StepArgs &a, const AdjArgs &d, hipStream_t s);
+// mu_out from the node adjoints, nbar and the incoming state (or the seed
+// dpop at the final step)
+void launch_adj_stream(const StepArgs &a, const AdjArgs &d, bool terminal, hipStream_t s);
 void launch_adj_nonlocal(const StepArgs &a, const AdjArgs &d, hipStream_t s);
 void launch_adj_extforce(const Geom &g, const double *Fbar, double *Vbar, hipStream_t s);
-void launch_adj_state_grad(const Geom &g, int M, const uint32_t *bb, const double *mu,
-                           const double *nbar, int species, int dist, double *out, hipStream_t s);
+void launch_adj_state_grad(const Geom &g, int M, const uint32_t *bb, const double *mu, int species,
+                           int dist, double *out, hipStream_t s);
 void launch_fill(double *p, long long n, double v, hipStream_t s);
 constexpr int DIAG_K = 12;  // reduced quantities per block
 

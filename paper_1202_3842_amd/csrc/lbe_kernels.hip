@@ -558,8 +558,11 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
       if (ADJ) {
         // n_b^bar(r) += -c (sum (e^.phibar) G(r+e) + G(r) sum e^.phibar)
         // G_ab^bar(r) += c (phibar(r).sum e^ n_b(r+e) - n_b(r) sum e^.phibar)
-        ad->nbar_out[beta * N + i] += -cmf * (vy + G0 * vx);
-        ad->Gbar[k * N + i] += cmf * (u0x * mx + u0y * my + u0z * mz - n0 * vx);
+        const double vn = -cmf * (vy + G0 * vx);
+        const double vg = cmf * (u0x * mx + u0y * my + u0z * mz - n0 * vx);
+        double *pn = ad->nbar + beta * N + i, *pg = ad->Gbar + k * N + i;
+        *pn = (accumulate & 1) ? *pn + vn : vn;
+        *pg = (accumulate & 2) ? *pg + vg : vg;
       } else {
         double *F = a.force + 6LL * alpha * N + i;
         if (accumulate) {
@@ -930,16 +933,13 @@ inline dim3 grid_for(int N) { return dim3((N + BLOCK - 1) / BLOCK); }
 
 // adjoint of the pre-streaming slot (r, q): the streaming map is a
 // permutation, so it is the adjoint of the one population that reads the
-// slot -- (r + c_q, q), or (r, opp q) when r + c_q is blocked -- plus the
-// nonlocal density adjoint of that node for f populations
+// slot -- (r + c_q, q), or (r, opp q) when r + c_q is blocked
 template <int q>
 __device__ inline double adj_slot(const Geom &g, const Coord &c, int i, uint32_t m,
-                                  const double *__restrict__ blk, long long Ns,
-                                  const double *__restrict__ nb) {
-  if (q == 0) return blk[i] + (nb ? nb[i] : 0.0);
-  if ((m >> opp(q)) & 1u) return blk[(long long)opp(q) * Ns + i] + (nb ? nb[i] : 0.0);
-  const int j = downstream(g, c, q);
-  return blk[(long long)q * Ns + j] + (nb ? nb[j] : 0.0);
+                                  const double *__restrict__ blk, long long Ns) {
+  if (q == 0) return blk[i];
+  if ((m >> opp(q)) & 1u) return blk[(long long)opp(q) * Ns + i];
+  return blk[(long long)q * Ns + downstream(g, c, q)];
 }
 
 // sum_q w_q v_q, sum_q w_q c_q v_q, sum_q w_q c_q c_q v_q (xx yy zz xy xz yz)
@@ -982,32 +982,22 @@ __device__ inline double dot3(const double a[3], const double b[3]) {
 
 template <int q, int M>
 __device__ inline void adj_moments_all(const Geom &g, const Coord &c, int i, uint32_t m,
-                                       const AdjArgs &d, long long Ns, long long N,
-                                       WMoments bf[M], WMoments bg[M]) {
+                                       const AdjArgs &d, long long Ns, WMoments bf[M], WMoments bg[M]) {
   if constexpr (q < Q) {
     for (int s = 0; s < M; ++s) {
-      wacc<q>(bf[s], adj_slot<q>(g, c, i, m, d.mu_in + (long long)s * Q * Ns, Ns, d.nbar_in + s * N));
-      wacc<q>(bg[s], adj_slot<q>(g, c, i, m, d.mu_in + (long long)(M + s) * Q * Ns, Ns, nullptr));
+      wacc<q>(bf[s], adj_slot<q>(g, c, i, m, d.mu_in + (long long)s * Q * Ns, Ns));
+      wacc<q>(bg[s], adj_slot<q>(g, c, i, m, d.mu_in + (long long)(M + s) * Q * Ns, Ns));
     }
-    adj_moments_all<q + 1, M>(g, c, i, m, d, Ns, N, bf, bg);
+    adj_moments_all<q + 1, M>(g, c, i, m, d, Ns, bf, bg);
   }
 }
 
-// mu_out = (1 - a) (incoming adjoint) + the moment adjoints of the node
-template <int q, int M>
-__device__ inline void adj_store_all(const Geom &g, const Coord &c, int i, uint32_t m,
-                                     const AdjArgs &d, long long Ns, long long N, double keep,
-                                     const double nbar[M], const double Pibar[M],
-                                     const double Jbar[M][3]) {
-  if constexpr (q < Q) {
-    for (int s = 0; s < M; ++s) {
-      const double lf = adj_slot<q>(g, c, i, m, d.mu_in + (long long)s * Q * Ns, Ns, d.nbar_in + s * N);
-      const double lg = adj_slot<q>(g, c, i, m, d.mu_in + (long long)(M + s) * Q * Ns, Ns, nullptr);
-      d.mu_out[((long long)s * Q + q) * Ns + i] = keep * lf + nbar[s];
-      d.mu_out[((long long)(M + s) * Q + q) * Ns + i] = keep * lg + Pibar[s] + cdot<q>(Jbar[s]);
-    }
-    adj_store_all<q + 1, M>(g, c, i, m, d, Ns, N, keep, nbar, Pibar, Jbar);
-  }
+// node adjoints of species s: nbar (local part), Pi~bar, J~bar
+__device__ inline void store_node(const AdjArgs &d, int M, long long N, int i, int s, double nb,
+                                  double Pib, const double Jb[3]) {
+  d.node[(long long)s * N + i] = nb;
+  d.node[(long long)(M + s) * N + i] = Pib;
+  for (int k = 0; k < 3; ++k) d.node[(long long)(2 * M + 3 * s + k) * N + i] = Jb[k];
 }
 
 __device__ inline void store_phibar(const Geom &g, const AdjArgs &d, const Coord &c, int s,
@@ -1017,9 +1007,10 @@ __device__ inline void store_phibar(const Geom &g, const AdjArgs &d, const Coord
 
 // Reverse of the collision of one node (inversion, equilibria, sources and
 // trapezoidal update, as in collide_body).  Inputs: the tilde moments of
-// the state (tape), n, the force per particle phi = C^mf/n and F; output
-// the adjoint before the step, phibar (for the shell-gather transpose) and
-// the external-force adjoint (accumulated).  Per species, with
+// the state (tape), n, the force per particle phi = C^mf/n and F; outputs
+// the node adjoints of n, Pi~ and J~ (k_adj_stream turns them into the
+// adjoint state), phibar (for the shell-gather transpose) and the
+// external-force adjoint (accumulated).  Per species, with
 //   A = a (m_f + m_g), B = b m_f, D = b m_g  (weighted moments of the
 // incoming f- and g-adjoints),
 //   nbar  = A0 + 4.5 (2 u^a.A2.u - u.A2.u) - 1.5 (2 u^a.u - u.u) A0 - a m_g0
@@ -1070,7 +1061,7 @@ __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
     wzero(bf[s]);
     wzero(bg[s]);
   }
-  adj_moments_all<0, M>(g, c, i, m, d, Ns, N, bf, bg);
+  adj_moments_all<0, M>(g, c, i, m, d, Ns, bf, bg);
 
   const double ac = a.acoef, bc = a.bcoef, kap = a.kappa, hb = 0.5 * a.beta;
   double nbar[M], Pibar[M], Jbar[M][3], uabar[M][3], Cbar[M][3], Ybar[M][3], Xbar[M][3];
@@ -1138,9 +1129,9 @@ __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
     }
     nbar[s] += dot3(Ybar[s], F[s]) + dot3(Cbar[s], phi[s]);
     store_phibar(g, d, c, s, pb);
+    store_node(d, M, N, i, s, nbar[s], Pibar[s], Jbar[s]);
   }
   for (int k = 0; k < 3; ++k) d.Fbar[(long long)k * N + i] += Fb[k];
-  adj_store_all<0, M>(g, c, i, m, d, Ns, N, 1.0 - ac, nbar, Pibar, Jbar);
 }
 
 template <int M>
@@ -1148,9 +1139,9 @@ __global__ __launch_bounds__(BLOCK) void k_adj_collide(StepArgs a, AdjArgs d) {
   adj_collide_body<M>(a, d, blockIdx.x * BLOCK + threadIdx.x);
 }
 
-// Reverse of the read-out of n^a and of the physical J^a = J~ + (X or Y)/2
-// (and of the post-streaming populations themselves): the adjoint state of
-// the final step from the seeds dn, dJ, dpop.
+// Reverse of the read-out of n^a and of the physical J^a = J~ + (X or Y)/2:
+// node adjoints of the final state from the seeds dn, dJ (the seed dpop of
+// the populations themselves enters in k_adj_stream).
 template <int M>
 __global__ __launch_bounds__(BLOCK) void k_adj_readout(StepArgs a, AdjArgs d) {
   const int i = blockIdx.x * BLOCK + threadIdx.x;
@@ -1163,7 +1154,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_readout(StepArgs a, AdjArgs d) {
     for (int s = 0; s < M; ++s) store_phibar(g, d, c, s, z);
     return;
   }
-  const long long Ns = pop_stride(g), N = g.N;
+  const long long N = g.N;
   const long long P = padded_index(g, c.x, c.y, c.z);
   const bool printed = a.flags & LBE_PRINTED_INV;
   double Fb[3] = {0.0, 0.0, 0.0};
@@ -1182,15 +1173,56 @@ __global__ __launch_bounds__(BLOCK) void k_adj_readout(StepArgs a, AdjArgs d) {
       pb[k] = n * Cb;
     }
     store_phibar(g, d, c, s, pb);
-    for (int q = 0; q < Q; ++q) {
-      const double df = d.dpop ? d.dpop[((long long)s * Q + q) * N + i] : 0.0;
-      const double dg = d.dpop ? d.dpop[((long long)(M + s) * Q + q) * N + i] : 0.0;
-      d.mu_out[((long long)s * Q + q) * Ns + i] = df + nb;
-      d.mu_out[((long long)(M + s) * Q + q) * Ns + i] =
-          dg + cvec(q, 0) * Jb[0] + cvec(q, 1) * Jb[1] + cvec(q, 2) * Jb[2];
-    }
+    store_node(d, M, N, i, s, nb, 0.0, Jb);
   }
   for (int k = 0; k < 3; ++k) d.Fbar[(long long)k * N + i] += Fb[k];
+}
+
+// The adjoint state before the step, per node r and population q:
+//   mu_f = (1 - a) lambda_f + nbar_loc + nbar,  mu_g = (1 - a) lambda_g + Pi~bar + c_q.J~bar
+// with lambda the adjoint of the pre-streaming slots (the streaming
+// transpose of mu_in) -- or, at the final step, lambda the seed dpop and no
+// (1 - a) (the read-out does not collide).
+template <int q, int M, bool TERMINAL>
+__device__ inline void adj_stream_q(const Geom &g, const Coord &c, int i, uint32_t m,
+                                    const AdjArgs &d, long long Ns, long long N, double keep,
+                                    const double nb[M], const double Pib[M], const double Jb[M][3]) {
+  if constexpr (q < Q) {
+    for (int s = 0; s < M; ++s) {
+      double lf, lg;
+      if (TERMINAL) {
+        lf = d.dpop ? d.dpop[((long long)s * Q + q) * N + i] : 0.0;
+        lg = d.dpop ? d.dpop[((long long)(M + s) * Q + q) * N + i] : 0.0;
+      } else {
+        lf = keep * adj_slot<q>(g, c, i, m, d.mu_in + (long long)s * Q * Ns, Ns);
+        lg = keep * adj_slot<q>(g, c, i, m, d.mu_in + (long long)(M + s) * Q * Ns, Ns);
+      }
+      d.mu_out[((long long)s * Q + q) * Ns + i] = lf + nb[s];
+      d.mu_out[((long long)(M + s) * Q + q) * Ns + i] = lg + Pib[s] + cdot<q>(Jb[s]);
+    }
+    adj_stream_q<q + 1, M, TERMINAL>(g, c, i, m, d, Ns, N, keep, nb, Pib, Jb);
+  }
+}
+
+template <int M, bool TERMINAL>
+__global__ __launch_bounds__(BLOCK) void k_adj_stream(StepArgs a, AdjArgs d) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  const Geom g = a.g;
+  if (i >= g.N) return;
+  const uint32_t m = a.bb[i];
+  const long long Ns = pop_stride(g), N = g.N;
+  if (m & 1u) {
+    for (int k = 0; k < 2 * M * Q; ++k) d.mu_out[(long long)k * Ns + i] = 0.0;
+    return;
+  }
+  const Coord c = decode(g, i);
+  double nb[M], Pib[M], Jb[M][3];
+  for (int s = 0; s < M; ++s) {
+    nb[s] = d.node[(long long)s * N + i] + d.nbar[(long long)s * N + i];
+    Pib[s] = d.node[(long long)(M + s) * N + i];
+    for (int k = 0; k < 3; ++k) Jb[s][k] = d.node[(long long)(2 * M + 3 * s + k) * N + i];
+  }
+  adj_stream_q<0, M, TERMINAL>(g, c, i, m, d, Ns, N, 1.0 - a.acoef, nb, Pib, Jb);
 }
 
 // the tilde moments Pi~, J~ of a state (tape) and its densities n (padded
@@ -1221,11 +1253,12 @@ __global__ __launch_bounds__(BLOCK) void k_tape_moments(StepArgs a, const double
 }
 
 // adjoint of the shell gather of one directed pair (alpha, beta), see
-// force_body MODE 2; accumulates into nbar_out and Gbar
+// force_body MODE 2: writes or (acc bit 0) accumulates into nbar, writes or
+// (acc bit 1) accumulates into Gbar
 template <int R>
-__global__ __launch_bounds__(FNT) void k_adj_force(StepArgs a, AdjArgs d, int alpha, int beta) {
+__global__ __launch_bounds__(FNT) void k_adj_force(StepArgs a, AdjArgs d, int alpha, int beta, int acc) {
   extern __shared__ double lds[];
-  force_body<R, 2>(a, &d, alpha, beta, 1, blockIdx.x, blockIdx.y, blockIdx.z, lds);
+  force_body<R, 2>(a, &d, alpha, beta, acc, blockIdx.x, blockIdx.y, blockIdx.z, lds);
 }
 
 // Reverse of the contact values: G_ab = 1/(1-xi3) + 3 d xi2/(1-xi3)^2
@@ -1272,8 +1305,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj_contact(StepArgs a, AdjArgs d) {
   }
 }
 
-// transpose of the ball average (the ball is symmetric): nbar_out += the
-// ball average of nbb; zero on solid nodes
+// transpose of the ball average (the ball is symmetric): nbar += the ball
+// average of nbb; zero on solid nodes
 template <int M>
 __global__ __launch_bounds__(BLOCK) void k_adj_ball(StepArgs a, AdjArgs d) {
   const int i = blockIdx.x * BLOCK + threadIdx.x;
@@ -1281,7 +1314,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_ball(StepArgs a, AdjArgs d) {
   if (i >= g.N) return;
   const long long N = g.N;
   if (a.bb[i] & 1u) {
-    for (int b = 0; b < M; ++b) d.nbar_out[(long long)b * N + i] = 0.0;
+    for (int b = 0; b < M; ++b) d.nbar[(long long)b * N + i] = 0.0;
     return;
   }
   const Coord c = decode(g, i);
@@ -1292,7 +1325,7 @@ __global__ __launch_bounds__(BLOCK) void k_adj_ball(StepArgs a, AdjArgs d) {
     const int cnt = a.t.ball_n[b];
     double s = 0.0;
     for (int j = 0; j < cnt; ++j) s += nb[off[j]];
-    d.nbar_out[(long long)b * N + i] += s / (double)cnt;
+    d.nbar[(long long)b * N + i] += s / (double)cnt;
   }
 }
 
@@ -1337,16 +1370,14 @@ __global__ __launch_bounds__(BLOCK) void k_adj_extforce(Geom g, const double *__
 // the adjoint of the post-streaming populations of one (species, dist)
 // block, compact 19N layout
 __global__ __launch_bounds__(BLOCK) void k_adj_state_grad(Geom g, int M, const uint32_t *__restrict__ bb,
-                                                         const double *__restrict__ mu,
-                                                         const double *__restrict__ nbar, int s,
-                                                         int dist, double *__restrict__ out) {
+                                                         const double *__restrict__ mu, int s, int dist,
+                                                         double *__restrict__ out) {
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   if (i >= g.N) return;
   const long long Ns = pop_stride(g), N = g.N;
   const bool solid = bb[i] & 1u;
-  const double nb = dist == 0 ? nbar[(long long)s * N + i] : 0.0;
   for (int q = 0; q < Q; ++q)
-    out[(long long)q * N + i] = solid ? 0.0 : mu[((long long)(dist * M + s) * Q + q) * Ns + i] + nb;
+    out[(long long)q * N + i] = solid ? 0.0 : mu[((long long)(dist * M + s) * Q + q) * Ns + i];
 }
 
 __global__ void k_fill(double *__restrict__ p, long long n, double v) {
@@ -1636,8 +1667,18 @@ void launch_adj_readout(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
   LBE_SWITCH_M(a.M, hipLaunchKernelGGL(k_adj_readout<MM>, gr, dim3(BLOCK), 0, s, a, d))
 }
 
+void launch_adj_stream(const StepArgs &a, const AdjArgs &d, bool terminal, hipStream_t s) {
+  const dim3 gr = grid_for(a.g.N);
+  if (terminal) {
+    LBE_SWITCH_M(a.M, hipLaunchKernelGGL((k_adj_stream<MM, true>), gr, dim3(BLOCK), 0, s, a, d))
+  } else {
+    LBE_SWITCH_M(a.M, hipLaunchKernelGGL((k_adj_stream<MM, false>), gr, dim3(BLOCK), 0, s, a, d))
+  }
+}
+
 template <int R>
-static void adj_force_launch(const StepArgs &a, const AdjArgs &d, int alpha, int beta, hipStream_t s) {
+static void adj_force_launch(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
+                             hipStream_t s) {
   const int k = pair_index(a.M, alpha, beta);
   const size_t bytes = sizeof(double) * (2 * 5 * (FTX + 2 * R) * (FTY + 2 * R) + 4 * a.t.pair_nent[k]);
   static size_t attr = 0;
@@ -1647,7 +1688,7 @@ static void adj_force_launch(const StepArgs &a, const AdjArgs &d, int alpha, int
     attr = bytes;
   }
   dim3 gr((a.g.nx + FTX - 1) / FTX, (a.g.ny + FTY - 1) / FTY, (a.g.nz + a.zchunk - 1) / a.zchunk);
-  hipLaunchKernelGGL(k_adj_force<R>, gr, dim3(FNT), bytes, s, a, d, alpha, beta);
+  hipLaunchKernelGGL(k_adj_force<R>, gr, dim3(FNT), bytes, s, a, d, alpha, beta, acc);
 }
 
 void launch_fill(double *p, long long n, double v, hipStream_t s) {
@@ -1656,26 +1697,39 @@ void launch_fill(double *p, long long n, double v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(BLOCK), 0, s, p, n, v);
 }
 
+// nbar of the step: the transposes of the shell gathers (every directed
+// pair) and of the contact values and ball averages.  The first launch that
+// reaches an output writes it, later ones accumulate.
 void launch_adj_nonlocal(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
   const long long N = a.g.N;
-  launch_fill(d.nbar_out, a.M * N, 0.0, s);
-  if (a.flags & LBE_IDEAL) return;  // no force: densities enter only locally
-  launch_fill(d.Gbar, (long long)(a.M * (a.M + 1) / 2) * N, 0.0, s);
-  for (int al = 0; al < a.M; ++al)
-    for (int be = 0; be < a.M; ++be) {
-      const int R = a.t.pair_R[pair_index(a.M, al, be)];
+  const int M = a.M, npairs = M * (M + 1) / 2;
+  if (a.flags & LBE_IDEAL) {  // no force: densities enter only locally
+    launch_fill(d.nbar, M * N, 0.0, s);
+    return;
+  }
+  bool wn[MAXM] = {false, false, false, false}, wg[MAXPAIRS] = {};
+  for (int al = 0; al < M; ++al)
+    for (int be = 0; be < M; ++be) {
+      const int k = pair_index(M, al, be);
+      const int R = a.t.pair_R[k];
+      if (R == 0) continue;  // empty shell
+      const int acc = (wn[be] ? 1 : 0) | (wg[k] ? 2 : 0);
+      wn[be] = wg[k] = true;
       switch (R) {
-        case 0: break;  // empty shell
-        case 1: adj_force_launch<1>(a, d, al, be, s); break;
-        case 2: adj_force_launch<2>(a, d, al, be, s); break;
-        case 3: adj_force_launch<3>(a, d, al, be, s); break;
-        case 4: adj_force_launch<4>(a, d, al, be, s); break;
-        case 5: adj_force_launch<5>(a, d, al, be, s); break;
-        case 6: adj_force_launch<6>(a, d, al, be, s); break;
-        case 7: adj_force_launch<7>(a, d, al, be, s); break;
-        default: adj_force_launch<8>(a, d, al, be, s); break;
+        case 1: adj_force_launch<1>(a, d, al, be, acc, s); break;
+        case 2: adj_force_launch<2>(a, d, al, be, acc, s); break;
+        case 3: adj_force_launch<3>(a, d, al, be, acc, s); break;
+        case 4: adj_force_launch<4>(a, d, al, be, acc, s); break;
+        case 5: adj_force_launch<5>(a, d, al, be, acc, s); break;
+        case 6: adj_force_launch<6>(a, d, al, be, acc, s); break;
+        case 7: adj_force_launch<7>(a, d, al, be, acc, s); break;
+        default: adj_force_launch<8>(a, d, al, be, acc, s); break;
       }
     }
+  for (int b = 0; b < M; ++b)
+    if (!wn[b]) launch_fill(d.nbar + b * N, N, 0.0, s);
+  for (int k = 0; k < npairs; ++k)
+    if (!wg[k]) launch_fill(d.Gbar + k * N, N, 0.0, s);
   const dim3 gr = grid_for(a.g.N);
   LBE_SWITCH_M(a.M, hipLaunchKernelGGL(k_adj_contact<MM>, gr, dim3(BLOCK), 0, s, a, d))
   LBE_SWITCH_M(a.M, hipLaunchKernelGGL(k_adj_ball<MM>, gr, dim3(BLOCK), 0, s, a, d))
@@ -1685,10 +1739,10 @@ void launch_adj_extforce(const Geom &g, const double *Fbar, double *Vbar, hipStr
   hipLaunchKernelGGL(k_adj_extforce, grid_for(g.N), dim3(BLOCK), 0, s, g, Fbar, Vbar);
 }
 
-void launch_adj_state_grad(const Geom &g, int M, const uint32_t *bb, const double *mu,
-                           const double *nbar, int species, int dist, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_state_grad, grid_for(g.N), dim3(BLOCK), 0, s, g, M, bb, mu, nbar, species,
-                     dist, out);
+void launch_adj_state_grad(const Geom &g, int M, const uint32_t *bb, const double *mu, int species,
+                           int dist, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_state_grad, grid_for(g.N), dim3(BLOCK), 0, s, g, M, bb, mu, species, dist,
+                     out);
 }
 
 #undef LBE_SWITCH_M
