@@ -100,7 +100,7 @@ def run_gpu(w, prec, flags, steps, warmup, lbe, torch):
     from paper_1202_3842_amd import autotune
     box = lbe.box_from_workload(w, prec=prec, flags=flags)
     z = autotune.tune_zchunk(box)
-    log(f"force-kernel zchunk {z}")
+    log(f"force-kernel tiling (zchunk, order) {getattr(box, 'tiling', (z, None))}")
     box.step(warmup)
     box.synchronize()
     log(f"warmup {warmup} steps done ({'fp64' if prec == lbe.LBE_FP64 else 'fp32-pop'})")
@@ -284,6 +284,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-MiB device buffer 5 times (a plain copy kernel of "
+                         "known traffic, to scale HBM counters)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint leg and print its JSON (for profiling)")
     args = ap.parse_args()
@@ -297,6 +300,15 @@ def main():
     from paper_1202_3842_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "copies": 5}), flush=True)
+        return
     if args.adjoint_only:
         print(json.dumps({"adjoint": adjoint_leg(lbe, torch, W)}), flush=True)
         return

@@ -197,6 +197,14 @@ lbe_status lbe_synchronize(lbe_ctx *ctx);
  * do not depend on it; the autotuner sets it).  1 <= zchunk <= nz. */
 lbe_status lbe_set_force_zchunk(lbe_ctx *ctx, int zchunk);
 
+/* zchunk as above; the order in which the force kernel's tiles are handed
+ * out: 0 = hardware order (default), 1 = each of the 8 XCDs (one L2 each)
+ * gets a contiguous range of tiles, x fastest, 2 = the same with z fastest;
+ * shape of the output tile: 0 = 32 x 8, 256 threads (default), 1 = 32 x 16,
+ * 256 threads with two rows each, 2 = 32 x 16, 512 threads.  Tiling
+ * parameters only: results do not depend on them. */
+lbe_status lbe_set_force_tiling(lbe_ctx *ctx, int zchunk, int order, int shape);
+
 /* ---- batched boxes --------------------------------------------------------
  * Many independent one-component boxes of different sizes and diameters
  * stepped together: every phase of a step is one launch covering all boxes

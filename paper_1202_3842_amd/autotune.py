@@ -1,11 +1,14 @@
 """Autotuner for the force kernel's tiling.
 
-The force kernel's workgroup owns a 32 x 8 tile of nodes and marches over
-``zchunk`` planes in z; results do not depend on zchunk, its speed does (L2
-reuse of staged planes against the number of workgroups).  ``tune_zchunk``
-times the candidates on a scratch box of the same size class, diameter,
-precision and switches (the caller's state is never touched) and caches the
-winner in a JSON file (``$LBE_TUNE_CACHE`` or ``~/.cache/lbe_mi355x/tune.json``).
+The force kernel's workgroup owns a 32 x 8 or 32 x 16 tile of nodes (the
+``shape``: 256 threads with one or two rows each, or 512 threads) and marches
+over ``zchunk`` planes in z; the tiles
+are handed to the XCDs in one of three orders (hardware round-robin, or one
+contiguous range per XCD with x or z fastest).  Results do not depend on either knob, the speed does (L2 reuse of
+staged planes against the number of workgroups).  ``tune_zchunk`` times the
+candidates on a scratch box of the same size class, diameter, precision and
+switches (the caller's state is never touched) and caches the winner in a
+JSON file (``$LBE_TUNE_CACHE`` or ``~/.cache/lbe_mi355x/tune.json``).
 """
 from __future__ import annotations
 
@@ -15,7 +18,9 @@ from pathlib import Path
 
 import numpy as np
 
-CANDIDATES = (1, 2, 4, 8, 16)
+CANDIDATES = (1, 2, 4, 8)
+ORDERS = (0, 1)
+SHAPES = (0, 1, 2)
 
 
 def cache_path() -> Path:
@@ -50,16 +55,16 @@ def size_class(n: int) -> int:
 def _key(box) -> str:
     c = box.cfg
     sig = ",".join(f"{c.sigma[k]:g}" for k in range(c.nspecies))
-    return (f"{size_class(c.nx)}x{size_class(c.ny)}x{size_class(c.nz)}|s{sig}|p{c.prec}|f{c.flags}")
+    return (f"{size_class(c.nx)}x{size_class(c.ny)}x{size_class(c.nz)}|s{sig}|p{c.prec}|f{c.flags}|v4")
 
 
-def _time_force(lbe, torch, cfg, zchunk, reps):
+def _time_force(lbe, torch, cfg, zchunk, order, rows, reps):
     sig = [cfg.sigma[k] for k in range(cfg.nspecies)]
     b = lbe.Box(cfg.nx, cfg.ny, cfg.nz, sig, cfg.periodic, cfg.tau, cfg.kT, cfg.prec, cfg.flags)
     for a in range(cfg.nspecies):
         s = max(sig[a], 1.0)
         b.init_density(a, np.full(b.shape, 0.2 / s ** 3 / cfg.nspecies))
-    b.set_force_zchunk(zchunk)
+    b.set_force_tiling(zchunk, order, rows)
     st = b.stream
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(reps)]
@@ -77,26 +82,32 @@ def _time_force(lbe, torch, cfg, zchunk, reps):
     return t
 
 
-def tune_zchunk(box, candidates=CANDIDATES, reps=3, use_cache=True) -> int:
-    """Pick and set the fastest zchunk for ``box`` (a paper_1202_3842_amd.lbe.Box)."""
+def tune_zchunk(box, candidates=CANDIDATES, orders=ORDERS, rows=SHAPES, reps=3, use_cache=True) -> int:
+    """Pick and set the fastest (zchunk, order, shape) for ``box`` (a
+    paper_1202_3842_amd.lbe.Box); returns zchunk."""
     import torch
     from paper_1202_3842_amd import lbe
     key = _key(box)
     cache = _load() if use_cache else {}
     if key in cache:
-        z = min(int(cache[key]), box.cfg.nz)
-        box.set_force_zchunk(z)
+        z, o, r = cache[key]
+        z = min(int(z), box.cfg.nz)
+        box.set_force_tiling(z, int(o), int(r))
+        box.tiling = (z, int(o), int(r))
         return z
     best, best_t = None, None
     for z in candidates:
         if z > box.cfg.nz:
             continue
-        t = _time_force(lbe, torch, box.cfg, z, reps)
-        if best_t is None or t < best_t:
-            best, best_t = z, t
-    box.set_force_zchunk(best)
+        for o in orders:
+            for r in rows:
+                t = _time_force(lbe, torch, box.cfg, z, o, r, reps)
+                if best_t is None or t < best_t:
+                    best, best_t = (z, o, r), t
+    box.set_force_tiling(*best)
+    box.tiling = best
     if use_cache:
         cache = _load()
-        cache[key] = best
+        cache[key] = list(best)
         _store(cache)
-    return best
+    return best[0]

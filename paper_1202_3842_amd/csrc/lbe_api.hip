@@ -146,7 +146,7 @@ lbe_status make_plan(const lbe_config *cfg, Plan &pl) {
   pl.off_ring_ofs = take(sizeof(int) * (RING_MAX + 2) * MAXPAIRS);
   pl.off_ring_off = take(sizeof(int) * std::max(pl.nshell, 1));
   pl.off_ring_e = take(sizeof(double) * 3 * std::max(pl.nshell, 1));
-  pl.off_ball = take(sizeof(int) * std::max(pl.nball, 1));
+  pl.off_ball = take(sizeof(int) * 2 * std::max(pl.nball, 1));
   pl.off_bb = take(sizeof(uint32_t) * g.N);
   pl.off_V = take(sizeof(double) * g.N);
   pl.off_F = take(sizeof(double) * 3 * g.N);
@@ -208,6 +208,8 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
   a.beta = 1.0 / cfg->kT;
   a.kappa = (cfg->flags & LBE_KAPPA4) ? 4.0 : 2.0;
   a.zchunk = FORCE_ZC < g.nz ? FORCE_ZC : g.nz;
+  a.order = 0;
+  a.rows = 0;
   a.pop[0] = c->pop(0);
   a.pop[1] = c->pop(1);
   int k = 0;
@@ -240,19 +242,31 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
       for (int ez = R + 2; ez <= RING_MAX + 1; ++ez) ofs[ez] = (int)roff.size();
       a.t.pair_nent[idx] = (int)np;
     }
-  std::vector<int> boff;
+  std::vector<int> boff, bloff;
+  int bR = 0;
+  for (int s = 0; s < P.M; ++s)
+    for (size_t j = 0; j < P.balls[s].size(); ++j) bR = std::max(bR, abs(P.balls[s][j]));
+  a.t.ball_R = bR;
+  // LDS block of the ball kernels (see ball_block in lbe_kernels.hip)
+  const int BW = FORCE_TX + 2 * bR, BH = FORCE_TY + 2 * bR;
   for (int s = 0; s < P.M; ++s) {
     a.t.ball_start[s] = (int)boff.size();
     const std::vector<int> &b = P.balls[s];
     a.t.ball_n[s] = (int)b.size() / 3;
-    for (size_t j = 0; j < b.size(); j += 3) boff.push_back(b[j] + g.PX * (b[j + 1] + g.PY * b[j + 2]));
+    for (size_t j = 0; j < b.size(); j += 3) {
+      boff.push_back(b[j] + g.PX * (b[j + 1] + g.PY * b[j + 2]));
+      bloff.push_back(b[j] + BW * (b[j + 1] + BH * b[j + 2]));
+    }
     a.t.sigma[s] = cfg->sigma[s];
   }
+  a.t.ball_total = (int)boff.size();
+  boff.insert(boff.end(), bloff.begin(), bloff.end());
   a.t.ring_ofs = c->at<int>(P.off_ring_ofs);
   a.t.ring_off = c->at<int>(P.off_ring_off);
   a.t.ring_e = c->at<double>(P.off_ring_e);
   a.force = c->at<double>(P.off_force);
   a.t.ball_off = c->at<int>(P.off_ball);
+  a.t.ball_loff = a.t.ball_off + a.t.ball_total;
   a.bb = c->at<uint32_t>(P.off_bb);
   a.Fext = c->at<double>(P.off_F);
   a.nfield = c->at<double>(P.off_n);
@@ -551,8 +565,17 @@ lbe_status lbe_diagnostics(lbe_ctx *c, lbe_diag *out) {
 
 lbe_status lbe_set_force_zchunk(lbe_ctx *c, int zchunk) {
   if (!c) return fail(LBE_ERR_ARG, "null context");
+  return lbe_set_force_tiling(c, zchunk, c->args.order, c->args.rows);
+}
+
+lbe_status lbe_set_force_tiling(lbe_ctx *c, int zchunk, int order, int shape) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
   if (zchunk < 1 || zchunk > c->pl.g.nz) return fail(LBE_ERR_ARG, "zchunk must lie in [1, nz]");
+  if (order < 0 || order > 2) return fail(LBE_ERR_ARG, "order must be 0, 1 or 2");
+  if (shape < 0 || shape > 2) return fail(LBE_ERR_ARG, "shape must be 0, 1 or 2");
   c->args.zchunk = zchunk;
+  c->args.order = order;
+  c->args.rows = shape;
   return LBE_OK;
 }
 

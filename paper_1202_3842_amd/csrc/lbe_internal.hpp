@@ -56,7 +56,10 @@ struct Tables {
   double pair_cmf[MAXPAIRS];   // -kT sigma_ab^2 w_ab / 2
   double pair_cvisc[MAXPAIRS]; //  2 sigma_ab^2 sqrt(kT/pi) w_ab / 2
   double pair_d[MAXPAIRS];     // sigma_a sigma_b / (sigma_a + sigma_b)
-  const int *ball_off;        // all species' balls, concatenated
+  const int *ball_off;        // all species' balls, concatenated (padded-field offsets)
+  const int *ball_loff;       // the same points as offsets in a ball-kernel LDS block
+  int ball_R;                 // largest reach of any species' ball
+  int ball_total;             // points of all balls
   int ball_start[MAXM];
   int ball_n[MAXM];
   double sigma[MAXM];
@@ -78,6 +81,10 @@ struct alignas(8) StepArgs {
   double *force;         // 6M * N: C^mf/n_a (3), C^visc/n_a (3) per species
   void *pop[2];          // the two ping-pong population buffers
   int zchunk;            // z planes per force-kernel workgroup
+  int order;             // force-kernel tile order: 0 hardware order, 1 and 2
+                         // XCD-grouped with x or z fastest
+  int rows;              // force-kernel tile shape: 0 32x8, 1 32x16 (two rows
+                         // per thread), 2 32x16 (512 threads)
   Tables t;
   unsigned *errflag;     // bit 0: packing fraction >= 1 or NaN
 };
@@ -124,6 +131,8 @@ void launch_zero_solid(const Geom &g, int M, int prec, void *pop, const uint32_t
                        long long stride, hipStream_t s);
 void launch_moments(const StepArgs &a, int prec, const void *pop, hipStream_t s);
 void launch_contact(const StepArgs &a, hipStream_t s);
+// LDS block of the ball kernels: (FORCE_TX + 2R) x (FORCE_TY + 2R) x (zc + 2R)
+int ball_block_zc(const Geom &g);
 void launch_forces(const StepArgs &a, hipStream_t s);
 void launch_collide(const StepArgs &a, int prec, const void *pin, void *pout, hipStream_t s);
 void launch_readout(const StepArgs &a, int prec, const void *pin, const Readout &r, hipStream_t s);
@@ -144,7 +153,7 @@ void launch_diag_errn(const Geom &g, int M, const uint32_t *bb, const Readout &r
 int diag_nblocks(const Geom &g);
 // blocks of the node-parallel kernels and of the force kernel for one box
 int node_blocks(const Geom &g);
-int force_blocks(const Geom &g, int zchunk);
+int force_blocks(const Geom &g, int zchunk, int ty = FORCE_TY);
 // batched launches (M = 1 boxes sharing precision and flags)
 void launch_batch_moments(const BatchArgs &b, int nblocks, int prec, bool visc, hipStream_t s);
 void launch_batch_contact(const BatchArgs &b, int nblocks, hipStream_t s);

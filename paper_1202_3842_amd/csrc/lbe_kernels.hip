@@ -17,6 +17,7 @@
 //   k_collide  pull, inversion, equilibria, sources, trapezoidal BGK
 //              update, store
 #include <math.h>
+#include <string.h>
 
 #include "lbe_internal.hpp"
 
@@ -24,6 +25,9 @@ namespace lbe {
 namespace {
 
 constexpr int BLOCK = 256;
+// tiles of the LDS-tiled gathers: FTX x FTY nodes per workgroup of FNT threads
+constexpr int FTX = FORCE_TX, FTY = FORCE_TY;
+constexpr int FNT = FTX * FTY;
 
 // D3Q19 velocities (order documented in lbe.h) and weights
 __host__ __device__ constexpr int cvec(int p, int k) {
@@ -364,9 +368,118 @@ __device__ inline void contact_body(const A &a, int i) {
   for (int k = 0; k < NP; ++k) store_images(g, a.Gfield + (long long)k * g.Np, c, G[k]);
 }
 
-template <int M>
-__global__ __launch_bounds__(BLOCK) void k_contact(StepArgs a) {
-  contact_body<M>(a, blockIdx.x * BLOCK + threadIdx.x);
+
+// ------------------------------------------------------------------------
+// LDS-tiled ball gathers.  A workgroup owns FTX x FTY x ZC nodes; for each
+// species it stages the (FTX + 2R) x (FTY + 2R) x (ZC + 2R) block of the
+// padded field (R = the largest ball reach) in LDS and every thread sums
+// the ball of each of its ZC nodes, one ball point for all ZC nodes at a
+// time.  Each node's sum runs over the ball in table order, so results are
+// bitwise those of the direct gather (contact_body).
+//   MODE 0: ball averages of n -> BMCSL contact values G (forward)
+//   MODE 1: ball averages of n and Gbar -> adjoint of the ball averages
+//   MODE 2: ball averages of that adjoint, added into nbar (the transpose)
+// ------------------------------------------------------------------------
+template <int M, int MODE, int ZC>
+__global__ __launch_bounds__(BLOCK) void k_ball(StepArgs a, AdjArgs d) {
+  extern __shared__ double lds[];
+  const Geom g = a.g;
+  const int Rb = a.t.ball_R;
+  const int BW = FTX + 2 * Rb, BH = FTY + 2 * Rb, BZ = ZC + 2 * Rb, BP = BW * BH, BV = BP * BZ;
+  int *loff = (int *)(lds + BV);
+  const int nbx = (g.nx + FTX - 1) / FTX, nby = (g.ny + FTY - 1) / FTY;
+  const int b = blockIdx.x;
+  const int x0 = (b % nbx) * FTX, y0 = ((b / nbx) % nby) * FTY, z0 = (b / (nbx * nby)) * ZC;
+  const int t = threadIdx.x, tx = t % FTX, ty = t / FTX;
+  const int base = (ty + Rb) * BW + (tx + Rb) + Rb * BP;
+  for (int j = t; j < a.t.ball_total; j += BLOCK) loff[j] = a.t.ball_loff[j];
+  double nb[M][ZC];
+  for (int sp = 0; sp < M; ++sp) {
+    const double *src = (MODE == 2 ? d.nbb : a.nfield) + (long long)sp * g.Np;
+    __syncthreads();  // the previous species' readers are done with the block
+    for (int e = t; e < BV; e += BLOCK) {
+      const int cx = e % BW, cy = (e / BW) % BH, cz = e / BP;
+      const int X = x0 - Rb + cx + g.R, Y = y0 - Rb + cy + g.R, Z = z0 - Rb + cz + g.R;
+      lds[e] = (X < g.PX && Y < g.PY && Z < g.PZ) ? src[X + (long long)g.PX * (Y + (long long)g.PY * Z)] : 0.0;
+    }
+    __syncthreads();
+    double s[ZC];
+#pragma unroll
+    for (int zz = 0; zz < ZC; ++zz) s[zz] = 0.0;
+    const int j0 = a.t.ball_start[sp], cnt = a.t.ball_n[sp];
+    for (int j = 0; j < cnt; ++j) {
+      const double *p = lds + base + loff[j0 + j];
+#pragma unroll
+      for (int zz = 0; zz < ZC; ++zz) s[zz] += p[zz * BP];
+    }
+#pragma unroll
+    for (int zz = 0; zz < ZC; ++zz) nb[sp][zz] = s[zz] / (double)cnt;
+  }
+  const int x = x0 + tx, y = y0 + ty;
+  if (x >= g.nx || y >= g.ny) return;
+#pragma unroll
+  for (int zz = 0; zz < ZC; ++zz) {
+    const int z = z0 + zz;
+    if (z >= g.nz) break;
+    const int i = x + g.nx * (y + g.ny * z);
+    const bool solid = a.bb[i] & 1u;
+    const Coord c = decode(g, i);
+    if (MODE == 2) {
+      for (int sp = 0; sp < M; ++sp) {
+        double *o = d.nbar + (long long)sp * g.N + i;
+        *o = solid ? 0.0 : *o + nb[sp][zz];
+      }
+      continue;
+    }
+    constexpr int NP = M * (M + 1) / 2;
+    double xi2 = 0.0, xi3 = 0.0;
+    bool finite = true;
+    for (int sp = 0; sp < M; ++sp) {
+      const double sg = a.t.sigma[sp];
+      finite &= isfinite(nb[sp][zz]);
+      xi2 += sg * sg * nb[sp][zz];
+      xi3 += sg * sg * sg * nb[sp][zz];
+    }
+    xi2 *= M_PI / 6.0;
+    xi3 *= M_PI / 6.0;
+    if (MODE == 0) {
+      double G[NP];
+      if (solid) {
+        for (int k = 0; k < NP; ++k) G[k] = 0.0;
+      } else {
+        if (!(xi3 < 1.0) || !finite) atomicOr(a.errflag, 1u);
+        const double one = 1.0 - xi3;
+        const double i1 = 1.0 / one;
+        const double i2 = i1 * i1;
+        const double i3 = i2 * i1;
+        for (int pa = 0; pa < M; ++pa)
+          for (int pb = pa; pb < M; ++pb) {
+            const int k = pair_index(M, pa, pb);
+            const double dd = a.t.pair_d[k];
+            G[k] = i1 + 3.0 * dd * xi2 * i2 + 2.0 * dd * dd * xi2 * xi2 * i3;
+          }
+      }
+      for (int k = 0; k < NP; ++k) store_images(g, a.Gfield + (long long)k * g.Np, c, G[k]);
+    } else {
+      double x2b = 0.0, x3b = 0.0;
+      if (!solid) {
+        const double i1 = 1.0 / (1.0 - xi3), i2 = i1 * i1, i3 = i2 * i1, i4 = i2 * i2;
+        for (int pa = 0; pa < M; ++pa)
+          for (int pb = pa; pb < M; ++pb) {
+            const int k = pair_index(M, pa, pb);
+            const double dd = a.t.pair_d[k];
+            const double Gb = d.Gbar[(long long)k * g.N + i];
+            x2b += Gb * (3.0 * dd * i2 + 4.0 * dd * dd * xi2 * i3);
+            x3b += Gb * (i2 + 6.0 * dd * xi2 * i3 + 6.0 * dd * dd * xi2 * xi2 * i4);
+          }
+      }
+      for (int sp = 0; sp < M; ++sp) {
+        const double sg = a.t.sigma[sp];
+        store_images(g, d.nbb + (long long)sp * g.Np, c,
+                     solid ? 0.0 : (M_PI / 6.0) * (sg * sg * x2b + sg * sg * sg * x3b));
+      }
+    }
+  }
 }
 
 // Nonlocal forces on the tilde moments, one directed species pair (a, b)
@@ -385,27 +498,31 @@ __global__ __launch_bounds__(BLOCK) void k_contact(StepArgs a) {
 // points of a pair sit in the two staged planes, so every pair is summed
 // together and a uniform state gives exactly zero.  LDS holds 2 planes of
 // n_b, G_ab (and J~_b with C^visc): 2 * NF * (FTX+2R)(FTY+2R) doubles.
-constexpr int FTX = FORCE_TX, FTY = FORCE_TY;
-constexpr int FNT = FTX * FTY;
 
 
 // MODE 0: C^mf; MODE 1: C^mf and C^visc; MODE 2: the transpose of the C^mf
 // gather for the adjoint (fields n_b, G_ab and the adjoint force phi_a^bar,
-// see adjoint_force below).
-template <int R, int MODE, class A>
+// see k_adj_force).  NT threads in rows of FTX; NY = output rows per thread:
+// the tile is FTX x (NT/FTX NY) and thread (tx, ty) owns rows ty,
+// ty + NT/FTX, ...; one ring-table read and one address then serve NY nodes.
+// Taller tiles shrink the staged window per node.
+template <int R, int MODE, int NY, int NT, class A>
 __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int beta, int accumulate,
                                   int bx, int by, int bz, double *lds) {
   constexpr bool VISC = MODE == 1;
   constexpr bool ADJ = MODE == 2;
   constexpr int NF = MODE == 0 ? 2 : 5;
-  constexpr int W = FTX + 2 * R, H = FTY + 2 * R, WH = W * H;
-  constexpr int SLOTS = (WH + FNT - 1) / FNT;   // window elements per thread and field
+  constexpr int RY = NT / FTX;                  // thread rows of the workgroup
+  constexpr int TY = RY * NY;
+  constexpr int W = FTX + 2 * R, H = TY + 2 * R, WH = W * H;
+  constexpr int SLOTS = (WH + NT - 1) / NT;     // window elements per thread and field
+  constexpr int ROW = RY * W;                   // LDS distance between a thread's rows
+  constexpr int NS = NY == 1 ? 2 : 1;           // accumulator sets per row (ILP)
   const Geom g = geom_of(a);
   const int k = pair_index(a.M, alpha, beta);
   const int t = threadIdx.x, tx = t % FTX, ty = t / FTX;
-  const int x0 = bx * FTX, y0 = by * FTY;
-  const int x = x0 + tx, y = y0 + ty;
-  const bool valid = x < g.nx && y < g.ny;
+  const int x0 = bx * FTX, y0 = by * TY;
+  const int x = x0 + tx;
   const double *__restrict__ fld[5];
   fld[0] = a.nfield + (long long)beta * g.Np;
   fld[1] = a.Gfield + (long long)k * g.Np;
@@ -428,19 +545,20 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   int soff[SLOTS];
 #pragma unroll
   for (int q = 0; q < SLOTS; ++q) {
-    const int e = t + q * FNT;
+    const int e = t + q * NT;
     const int c = e % W, r = e / W;
     const int X = x0 - R + c + g.R, Y = y0 - R + r + g.R;
     soff[q] = (e < WH && X < g.PX && Y < g.PY) ? X + g.PX * Y : -1;
   }
   // this pair's ring table, staged once in LDS behind the plane buffers as
-  // {e0, e1, e2, offset} per point, so the inner loop touches only LDS
+  // {e0, e1, e2, offset} per point (the ring offsets are e_y*W_k + e_x for a
+  // window of FORCE_TX + 2R columns), so the inner loop touches only LDS
   int rofs[R + 2];
 #pragma unroll
   for (int ez = 0; ez <= R + 1; ++ez) rofs[ez] = ofs[ez];
   const int j0 = rofs[0], nent = rofs[R + 1] - rofs[0];
   double *tab = lds + 2 * NF * WH;
-  for (int j = t; j < nent; j += FNT) {
+  for (int j = t; j < nent; j += NT) {
     tab[4 * j] = re[3 * (j0 + j)];
     tab[4 * j + 1] = re[3 * (j0 + j) + 1];
     tab[4 * j + 2] = re[3 * (j0 + j) + 2];
@@ -466,9 +584,11 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
     }
   };
   fetch(0);
-  double mx = 0.0, my = 0.0, mz = 0.0, vx = 0.0, vy = 0.0, vz = 0.0;
-  // centre values: G_ab, and u_b (MODE 1) or n_b and phi_a^bar (MODE 2)
-  double G0 = 0.0, u0x = 0.0, u0y = 0.0, u0z = 0.0, n0 = 0.0;
+  // accumulators [row][set]: m (C^mf, or sum e^ n_b(r+e) for the adjoint)
+  // and v (C^visc, or the two adjoint sums)
+  double mx[NY][NS], my[NY][NS], mz[NY][NS], vx[NY][NS], vy[NY][NS], vz[NY][NS];
+  // centre values of each row: G_ab, and u_b (MODE 1) or n_b and phibar_a (MODE 2)
+  double G0[NY], n0[NY], u0x[NY], u0y[NY], u0z[NY];
   for (int rho = 0; rho < rounds; ++rho) {
     const int z = zb + rho / (R + 1), ez = rho % (R + 1);
     __syncthreads();  // previous round's readers are done with the buffers
@@ -478,7 +598,7 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
       for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int q = 0; q < SLOTS; ++q) {
-          const int e = t + q * FNT;
+          const int e = t + q * NT;
           if (q < SLOTS - 1 || e < WH) lds[(b * NF + f) * WH + e] = stage[b][f][q];
         }
     __syncthreads();
@@ -486,109 +606,158 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
     const double *Bp = lds;
     const double *Bm = ez ? lds + NF * WH : lds;
     if (ez == 0) {
-      mx = my = mz = vx = vy = vz = 0.0;
-      G0 = Bp[WH + base];
-      u0x = u0y = u0z = 0.0;
-      n0 = Bp[base];
-      if (VISC && n0 != 0.0) {
-        u0x = Bp[2 * WH + base] / n0;
-        u0y = Bp[3 * WH + base] / n0;
-        u0z = Bp[4 * WH + base] / n0;
-      }
-      if (ADJ) {
-        u0x = Bp[2 * WH + base];
-        u0y = Bp[3 * WH + base];
-        u0z = Bp[4 * WH + base];
+#pragma unroll
+      for (int jn = 0; jn < NY; ++jn) {
+#pragma unroll
+        for (int c = 0; c < NS; ++c) mx[jn][c] = my[jn][c] = mz[jn][c] = vx[jn][c] = vy[jn][c] = vz[jn][c] = 0.0;
+        const int bj = base + jn * ROW;
+        G0[jn] = Bp[WH + bj];
+        n0[jn] = Bp[bj];
+        u0x[jn] = u0y[jn] = u0z[jn] = 0.0;
+        if (VISC && n0[jn] != 0.0) {
+          u0x[jn] = Bp[2 * WH + bj] / n0[jn];
+          u0y[jn] = Bp[3 * WH + bj] / n0[jn];
+          u0z[jn] = Bp[4 * WH + bj] / n0[jn];
+        }
+        if (ADJ) {
+          u0x[jn] = Bp[2 * WH + bj];
+          u0y[jn] = Bp[3 * WH + bj];
+          u0z[jn] = Bp[4 * WH + bj];
+        }
       }
     }
     const int jbeg = rofs[ez] - j0, jend = rofs[ez + 1] - j0;
-    // one +-e pair: accumulate into (m, v)
-    auto pair = [&](int j, double &ax, double &ay, double &az, double &bx, double &by, double &bz) {
+    // one +-e pair for every row of the thread, into accumulator set c
+    auto pair = [&](int j, int c) {
       const double e0 = tab[4 * j], e1 = tab[4 * j + 1], e2 = tab[4 * j + 2];
       const int o = (int)__double_as_longlong(tab[4 * j + 3]);
-      const int qa = base + o, qb = base - o;
-      const double npl = Bp[qa], nmi = Bm[qb];
-      if (ADJ) {
-        // m: sum_S e^ n_b(r+e); v: sum_S e^.phibar(r+e) and
-        // sum_S (e^.phibar(r+e)) G(r+e), over both points of the pair
-        const double tp = e0 * Bp[2 * WH + qa] + e1 * Bp[3 * WH + qa] + e2 * Bp[4 * WH + qa];
-        const double tm = e0 * Bm[2 * WH + qb] + e1 * Bm[3 * WH + qb] + e2 * Bm[4 * WH + qb];
-        const double dn = npl - nmi;
-        ax += e0 * dn;
-        ay += e1 * dn;
-        az += e2 * dn;
-        bx += tp - tm;
-        by += tp * Bp[WH + qa] - tm * Bm[WH + qb];
-      } else {
-        const double gp = G0 + Bp[WH + qa], gm = G0 + Bm[WH + qb];
-        const double d = gp * npl - gm * nmi;
-        ax += e0 * d;
-        ay += e1 * d;
-        az += e2 * d;
-        if (VISC) {
-          const double eu = e0 * u0x + e1 * u0y + e2 * u0z;
-          const double tp = gp * (e0 * Bp[2 * WH + qa] + e1 * Bp[3 * WH + qa] + e2 * Bp[4 * WH + qa] - eu * npl);
-          const double tm = gm * (e0 * Bm[2 * WH + qb] + e1 * Bm[3 * WH + qb] + e2 * Bm[4 * WH + qb] - eu * nmi);
-          const double tt = tp + tm;
-          bx += e0 * tt;
-          by += e1 * tt;
-          bz += e2 * tt;
+#pragma unroll
+      for (int jn = 0; jn < NY; ++jn) {
+        const int qa = base + jn * ROW + o, qb = base + jn * ROW - o;
+        const double npl = Bp[qa], nmi = Bm[qb];
+        if (ADJ) {
+          // m: sum_S e^ n_b(r+e); v: sum_S e^.phibar(r+e) and
+          // sum_S (e^.phibar(r+e)) G(r+e), over both points of the pair
+          const double tp = e0 * Bp[2 * WH + qa] + e1 * Bp[3 * WH + qa] + e2 * Bp[4 * WH + qa];
+          const double tm = e0 * Bm[2 * WH + qb] + e1 * Bm[3 * WH + qb] + e2 * Bm[4 * WH + qb];
+          const double dn = npl - nmi;
+          mx[jn][c] += e0 * dn;
+          my[jn][c] += e1 * dn;
+          mz[jn][c] += e2 * dn;
+          vx[jn][c] += tp - tm;
+          vy[jn][c] += tp * Bp[WH + qa] - tm * Bm[WH + qb];
+        } else {
+          const double gp = G0[jn] + Bp[WH + qa], gm = G0[jn] + Bm[WH + qb];
+          const double d = gp * npl - gm * nmi;
+          mx[jn][c] += e0 * d;
+          my[jn][c] += e1 * d;
+          mz[jn][c] += e2 * d;
+          if (VISC) {
+            const double eu = e0 * u0x[jn] + e1 * u0y[jn] + e2 * u0z[jn];
+            const double tp = gp * (e0 * Bp[2 * WH + qa] + e1 * Bp[3 * WH + qa] + e2 * Bp[4 * WH + qa] - eu * npl);
+            const double tm = gm * (e0 * Bm[2 * WH + qb] + e1 * Bm[3 * WH + qb] + e2 * Bm[4 * WH + qb] - eu * nmi);
+            const double tt = tp + tm;
+            vx[jn][c] += e0 * tt;
+            vy[jn][c] += e1 * tt;
+            vz[jn][c] += e2 * tt;
+          }
         }
       }
     };
-    // two independent accumulator sets shorten the dependency chains; a
-    // pair's terms are still combined before they are accumulated, so a
-    // uniform state still sums to exactly zero
-    double mx2 = 0.0, my2 = 0.0, mz2 = 0.0, vx2 = 0.0, vy2 = 0.0, vz2 = 0.0;
+    // a pair's terms are combined before they are accumulated, so a uniform
+    // state still sums to exactly zero
     int j = jbeg;
-    for (; j + 1 < jend; j += 2) {
-      pair(j, mx, my, mz, vx, vy, vz);
-      pair(j + 1, mx2, my2, mz2, vx2, vy2, vz2);
+    if (NS == 2) {
+      for (; j + 1 < jend; j += 2) {
+        pair(j, 0);
+        pair(j + 1, NS - 1);
+      }
     }
-    if (j < jend) pair(j, mx, my, mz, vx, vy, vz);
-    mx += mx2;
-    my += my2;
-    mz += mz2;
-    vx += vx2;
-    vy += vy2;
-    vz += vz2;
-    if (ez == R && valid) {
+    for (; j < jend; ++j) pair(j, 0);
+    if (ez == R) {
       const long long N = g.N;
-      const long long i = x + (long long)g.nx * (y + (long long)g.ny * z);
-      if (ADJ) {
-        // n_b^bar(r) += -c (sum (e^.phibar) G(r+e) + G(r) sum e^.phibar)
-        // G_ab^bar(r) += c (phibar(r).sum e^ n_b(r+e) - n_b(r) sum e^.phibar)
-        const double vn = -cmf * (vy + G0 * vx);
-        const double vg = cmf * (u0x * mx + u0y * my + u0z * mz - n0 * vx);
-        double *pn = ad->nbar + beta * N + i, *pg = ad->Gbar + k * N + i;
-        *pn = (accumulate & 1) ? *pn + vn : vn;
-        *pg = (accumulate & 2) ? *pg + vg : vg;
-      } else {
-        double *F = a.force + 6LL * alpha * N + i;
-        if (accumulate) {
-          F[0] += cmf * mx;
-          F[N] += cmf * my;
-          F[2 * N] += cmf * mz;
-          F[3 * N] += cvs * vx;
-          F[4 * N] += cvs * vy;
-          F[5 * N] += cvs * vz;
+#pragma unroll
+      for (int jn = 0; jn < NY; ++jn) {
+        const int y = y0 + ty + jn * RY;
+        if (!(x < g.nx && y < g.ny)) continue;
+        double Mx = mx[jn][0], My = my[jn][0], Mz = mz[jn][0];
+        double Vx = vx[jn][0], Vy = vy[jn][0], Vz = vz[jn][0];
+        if (NS == 2) {
+          Mx += mx[jn][NS - 1];
+          My += my[jn][NS - 1];
+          Mz += mz[jn][NS - 1];
+          Vx += vx[jn][NS - 1];
+          Vy += vy[jn][NS - 1];
+          Vz += vz[jn][NS - 1];
+        }
+        const long long i = x + (long long)g.nx * (y + (long long)g.ny * z);
+        if (ADJ) {
+          // n_b^bar(r) += -c (sum (e^.phibar) G(r+e) + G(r) sum e^.phibar)
+          // G_ab^bar(r) += c (phibar(r).sum e^ n_b(r+e) - n_b(r) sum e^.phibar)
+          const double vn = -cmf * (Vy + G0[jn] * Vx);
+          const double vg = cmf * (u0x[jn] * Mx + u0y[jn] * My + u0z[jn] * Mz - n0[jn] * Vx);
+          double *pn = ad->nbar + beta * N + i, *pg = ad->Gbar + k * N + i;
+          *pn = (accumulate & 1) ? *pn + vn : vn;
+          *pg = (accumulate & 2) ? *pg + vg : vg;
         } else {
-          F[0] = cmf * mx;
-          F[N] = cmf * my;
-          F[2 * N] = cmf * mz;
-          F[3 * N] = cvs * vx;
-          F[4 * N] = cvs * vy;
-          F[5 * N] = cvs * vz;
+          double *F = a.force + 6LL * alpha * N + i;
+          if (accumulate) {
+            F[0] += cmf * Mx;
+            F[N] += cmf * My;
+            F[2 * N] += cmf * Mz;
+            F[3 * N] += cvs * Vx;
+            F[4 * N] += cvs * Vy;
+            F[5 * N] += cvs * Vz;
+          } else {
+            F[0] = cmf * Mx;
+            F[N] = cmf * My;
+            F[2 * N] = cmf * Mz;
+            F[3 * N] = cvs * Vx;
+            F[4 * N] = cvs * Vy;
+            F[5 * N] = cvs * Vz;
+          }
         }
       }
     }
   }
 }
 
-template <int R, bool VISC>
-__global__ __launch_bounds__(FNT) void k_force(StepArgs a, int alpha, int beta, int accumulate) {
+// The tile (bx, by, bz) of this workgroup.  Workgroups are handed to the 8
+// XCDs round-robin (workgroup b to XCD b mod 8), each with its own L2; with
+// order 1 or 2 the tiles are renumbered so that each XCD gets one
+// contiguous range of tiles (x fastest, or z fastest), which keeps the
+// halo planes that neighbouring tiles share in one L2.
+constexpr int NXCD = 8;
+
+struct Tile {
+  int bx, by, bz;
+};
+
+__device__ inline Tile force_tile(const Geom &g, int zchunk, int order, int ty) {
+  const int nbx = (g.nx + FTX - 1) / FTX, nby = (g.ny + ty - 1) / ty;
+  const int nbz = (g.nz + zchunk - 1) / zchunk;
+  const int b = blockIdx.x;
+  const int nb = nbx * nby * nbz, q = nb / NXCD, r = nb % NXCD;
+  const int k = b % NXCD, j = b / NXCD;
+  const int t = order == 0 ? b : (k < r ? k * (q + 1) + j : r * (q + 1) + (k - r) * q + j);
+  Tile T;
+  if (order == 2) {
+    T.bz = t % nbz;
+    T.bx = (t / nbz) % nbx;
+    T.by = t / (nbz * nbx);
+  } else {
+    T.bx = t % nbx;
+    T.by = (t / nbx) % nby;
+    T.bz = t / (nbx * nby);
+  }
+  return T;
+}
+
+template <int R, bool VISC, int NY, int NT>
+__global__ __launch_bounds__(NT) void k_force(StepArgs a, int alpha, int beta, int accumulate) {
   extern __shared__ double lds[];
-  force_body<R, VISC ? 1 : 0>(a, nullptr, alpha, beta, accumulate, blockIdx.x, blockIdx.y, blockIdx.z, lds);
+  const Tile T = force_tile(a.g, a.zchunk, a.order, NT / FTX * NY);
+  force_body<R, VISC ? 1 : 0, NY, NT>(a, nullptr, alpha, beta, accumulate, T.bx, T.by, T.bz, lds);
 }
 
 // per-particle forces of species s at node i, times n_s
@@ -763,8 +932,8 @@ __global__ __launch_bounds__(FNT) void kb_force(BatchArgs ba) {
   const auto &a = *cptr(ba.boxes + b);
   const int local = blockIdx.x - cptr(ba.blockstart)[b];
   const int nbx = (a.g.nx + FTX - 1) / FTX, nby = (a.g.ny + FTY - 1) / FTY;
-  force_body<R, VISC ? 1 : 0>(a, nullptr, 0, 0, 0, local % nbx, (local / nbx) % nby, local / (nbx * nby),
-                              lds);
+  force_body<R, VISC ? 1 : 0, 1, FNT>(a, nullptr, 0, 0, 0, local % nbx, (local / nbx) % nby,
+                                      local / (nbx * nby), lds);
 }
 
 template <typename T>
@@ -1255,78 +1424,11 @@ __global__ __launch_bounds__(BLOCK) void k_tape_moments(StepArgs a, const double
 // adjoint of the shell gather of one directed pair (alpha, beta), see
 // force_body MODE 2: writes or (acc bit 0) accumulates into nbar, writes or
 // (acc bit 1) accumulates into Gbar
-template <int R>
-__global__ __launch_bounds__(FNT) void k_adj_force(StepArgs a, AdjArgs d, int alpha, int beta, int acc) {
+template <int R, int NY, int NT>
+__global__ __launch_bounds__(NT) void k_adj_force(StepArgs a, AdjArgs d, int alpha, int beta, int acc) {
   extern __shared__ double lds[];
-  force_body<R, 2>(a, &d, alpha, beta, acc, blockIdx.x, blockIdx.y, blockIdx.z, lds);
-}
-
-// Reverse of the contact values: G_ab = 1/(1-xi3) + 3 d xi2/(1-xi3)^2
-// + 2 d^2 xi2^2/(1-xi3)^3 with xi_k = (pi/6) sum_b sigma_b^k nbar_b, giving
-// the adjoint of each ball-averaged density (stored padded, with images)
-template <int M>
-__global__ __launch_bounds__(BLOCK) void k_adj_contact(StepArgs a, AdjArgs d) {
-  const int i = blockIdx.x * BLOCK + threadIdx.x;
-  const Geom g = a.g;
-  if (i >= g.N) return;
-  const Coord c = decode(g, i);
-  if (a.bb[i] & 1u) {
-    for (int b = 0; b < M; ++b) store_images(g, d.nbb + (long long)b * g.Np, c, 0.0);
-    return;
-  }
-  const long long P = padded_index(g, c.x, c.y, c.z), N = g.N;
-  double xi2 = 0.0, xi3 = 0.0;
-  for (int b = 0; b < M; ++b) {
-    const double *nb = a.nfield + (long long)b * g.Np + P;
-    const int *off = a.t.ball_off + a.t.ball_start[b];
-    const int cnt = a.t.ball_n[b];
-    double s = 0.0;
-    for (int j = 0; j < cnt; ++j) s += nb[off[j]];
-    const double nbar = s / (double)cnt;
-    const double sg = a.t.sigma[b];
-    xi2 += sg * sg * nbar;
-    xi3 += sg * sg * sg * nbar;
-  }
-  xi2 *= M_PI / 6.0;
-  xi3 *= M_PI / 6.0;
-  const double i1 = 1.0 / (1.0 - xi3), i2 = i1 * i1, i3 = i2 * i1, i4 = i2 * i2;
-  double x2b = 0.0, x3b = 0.0;
-  for (int pa = 0; pa < M; ++pa)
-    for (int pb = pa; pb < M; ++pb) {
-      const int k = pair_index(M, pa, pb);
-      const double dd = a.t.pair_d[k];
-      const double Gb = d.Gbar[(long long)k * N + i];
-      x2b += Gb * (3.0 * dd * i2 + 4.0 * dd * dd * xi2 * i3);
-      x3b += Gb * (i2 + 6.0 * dd * xi2 * i3 + 6.0 * dd * dd * xi2 * xi2 * i4);
-    }
-  for (int b = 0; b < M; ++b) {
-    const double sg = a.t.sigma[b];
-    store_images(g, d.nbb + (long long)b * g.Np, c, (M_PI / 6.0) * (sg * sg * x2b + sg * sg * sg * x3b));
-  }
-}
-
-// transpose of the ball average (the ball is symmetric): nbar += the ball
-// average of nbb; zero on solid nodes
-template <int M>
-__global__ __launch_bounds__(BLOCK) void k_adj_ball(StepArgs a, AdjArgs d) {
-  const int i = blockIdx.x * BLOCK + threadIdx.x;
-  const Geom g = a.g;
-  if (i >= g.N) return;
-  const long long N = g.N;
-  if (a.bb[i] & 1u) {
-    for (int b = 0; b < M; ++b) d.nbar[(long long)b * N + i] = 0.0;
-    return;
-  }
-  const Coord c = decode(g, i);
-  const long long P = padded_index(g, c.x, c.y, c.z);
-  for (int b = 0; b < M; ++b) {
-    const double *nb = d.nbb + (long long)b * g.Np + P;
-    const int *off = a.t.ball_off + a.t.ball_start[b];
-    const int cnt = a.t.ball_n[b];
-    double s = 0.0;
-    for (int j = 0; j < cnt; ++j) s += nb[off[j]];
-    d.nbar[(long long)b * N + i] += s / (double)cnt;
-  }
+  const Tile T = force_tile(a.g, a.zchunk, a.order, NT / FTX * NY);
+  force_body<R, 2, NY, NT>(a, &d, alpha, beta, acc, T.bx, T.by, T.bz, lds);
 }
 
 // Vbar = -(grad_h)^T Fbar: transpose of F(r) = -3 sum_p w_p c_p V(idx(r + c_p))
@@ -1458,29 +1560,87 @@ void launch_moments(const StepArgs &a, int prec, const void *pop, hipStream_t s)
   }
 }
 
-void launch_contact(const StepArgs &a, hipStream_t s) {
-  dim3 gr = grid_for(a.g.N);
-  switch (a.M) {
-    case 1: hipLaunchKernelGGL(k_contact<1>, gr, dim3(BLOCK), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_contact<2>, gr, dim3(BLOCK), 0, s, a); break;
-    case 3: hipLaunchKernelGGL(k_contact<3>, gr, dim3(BLOCK), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_contact<4>, gr, dim3(BLOCK), 0, s, a); break;
+// z depth of a ball-kernel workgroup: the largest of 8, 4, 2 that still
+// gives at least 1024 workgroups, else 1
+int ball_block_zc(const Geom &g) {
+  const long long tiles = (long long)((g.nx + FTX - 1) / FTX) * ((g.ny + FTY - 1) / FTY);
+  for (int zc = 8; zc > 1; zc /= 2)
+    if (tiles * ((g.nz + zc - 1) / zc) >= 1024) return zc;
+  return 1;
+}
+
+template <int M, int MODE, int ZC>
+static void ball_launch_zc(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
+  const Geom &g = a.g;
+  const int Rb = a.t.ball_R;
+  const size_t bytes = sizeof(double) * (size_t)(FTX + 2 * Rb) * (FTY + 2 * Rb) * (ZC + 2 * Rb) +
+                       sizeof(int) * (size_t)a.t.ball_total;
+  static size_t attr = 0;
+  if (bytes > attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ball<M, MODE, ZC>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    attr = bytes;
   }
+  const int blocks = ((g.nx + FTX - 1) / FTX) * ((g.ny + FTY - 1) / FTY) * ((g.nz + ZC - 1) / ZC);
+  hipLaunchKernelGGL((k_ball<M, MODE, ZC>), dim3(blocks), dim3(BLOCK), bytes, s, a, d);
+}
+
+template <int M, int MODE>
+static void ball_launch_m(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
+  switch (ball_block_zc(a.g)) {
+    case 8: ball_launch_zc<M, MODE, 8>(a, d, s); break;
+    case 4: ball_launch_zc<M, MODE, 4>(a, d, s); break;
+    case 2: ball_launch_zc<M, MODE, 2>(a, d, s); break;
+    default: ball_launch_zc<M, MODE, 1>(a, d, s); break;
+  }
+}
+
+template <int MODE>
+static void ball_launch(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
+  switch (a.M) {
+    case 1: ball_launch_m<1, MODE>(a, d, s); break;
+    case 2: ball_launch_m<2, MODE>(a, d, s); break;
+    case 3: ball_launch_m<3, MODE>(a, d, s); break;
+    default: ball_launch_m<4, MODE>(a, d, s); break;
+  }
+}
+
+void launch_contact(const StepArgs &a, hipStream_t s) {
+  AdjArgs none;
+  memset(&none, 0, sizeof none);
+  ball_launch<0>(a, none, s);
+}
+
+// the force kernel's tile shapes (lbe_set_force_tiling): 0 = 256 threads,
+// one row each (32 x 8); 1 = 256 threads, two rows each (32 x 16);
+// 2 = 512 threads, one row each (32 x 16)
+constexpr int shape_ny(int shape) { return shape == 1 ? 2 : 1; }
+constexpr int shape_nt(int shape) { return shape == 2 ? 512 : 256; }
+constexpr int shape_ty(int shape) { return shape_nt(shape) / FTX * shape_ny(shape); }
+
+template <int R, bool VISC, int SHAPE>
+static void force_launch_shape(const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
+  constexpr int NF = VISC ? 5 : 2, NY = shape_ny(SHAPE), NT = shape_nt(SHAPE), TY = shape_ty(SHAPE);
+  const int k = pair_index(a.M, alpha, beta);
+  const size_t bytes = sizeof(double) * (2 * NF * (FTX + 2 * R) * (TY + 2 * R) + 4 * a.t.pair_nent[k]);
+  static size_t attr = 0;
+  if (bytes > attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_force<R, VISC, NY, NT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    attr = bytes;
+  }
+  const dim3 gr(force_blocks(a.g, a.zchunk, TY));
+  hipLaunchKernelGGL((k_force<R, VISC, NY, NT>), gr, dim3(NT), bytes, s, a, alpha, beta, acc);
 }
 
 template <int R, bool VISC>
 static void force_launch(const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
-  constexpr int NF = VISC ? 5 : 2;
-  const int k = pair_index(a.M, alpha, beta);
-  const size_t bytes = sizeof(double) * (2 * NF * (FTX + 2 * R) * (FTY + 2 * R) + 4 * a.t.pair_nent[k]);
-  static size_t attr = 0;
-  if (bytes > attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_force<R, VISC>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    attr = bytes;
-  }
-  dim3 gr((a.g.nx + FTX - 1) / FTX, (a.g.ny + FTY - 1) / FTY, (a.g.nz + a.zchunk - 1) / a.zchunk);
-  hipLaunchKernelGGL((k_force<R, VISC>), gr, dim3(FNT), bytes, s, a, alpha, beta, acc);
+  if (a.rows == 1)
+    force_launch_shape<R, VISC, 1>(a, alpha, beta, acc, s);
+  else if (a.rows == 2)
+    force_launch_shape<R, VISC, 2>(a, alpha, beta, acc, s);
+  else
+    force_launch_shape<R, VISC, 0>(a, alpha, beta, acc, s);
 }
 
 template <bool VISC>
@@ -1552,8 +1712,8 @@ void launch_readout(const StepArgs &a, int prec, const void *pin, const Readout 
 
 int node_blocks(const Geom &g) { return (g.N + BLOCK - 1) / BLOCK; }
 
-int force_blocks(const Geom &g, int zchunk) {
-  return ((g.nx + FTX - 1) / FTX) * ((g.ny + FTY - 1) / FTY) * ((g.nz + zchunk - 1) / zchunk);
+int force_blocks(const Geom &g, int zchunk, int ty) {
+  return ((g.nx + FTX - 1) / FTX) * ((g.ny + ty - 1) / ty) * ((g.nz + zchunk - 1) / zchunk);
 }
 
 template <int R, bool VISC>
@@ -1565,8 +1725,6 @@ static size_t force_lds_bytes(int entries) {
 template <int R, bool VISC>
 static void prepare_one(int entries) {
   const int bytes = (int)force_lds_bytes<R, VISC>(entries);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_force<R, VISC>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_force<R, VISC>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
@@ -1676,19 +1834,31 @@ void launch_adj_stream(const StepArgs &a, const AdjArgs &d, bool terminal, hipSt
   }
 }
 
-template <int R>
-static void adj_force_launch(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
-                             hipStream_t s) {
+template <int R, int SHAPE>
+static void adj_force_launch_shape(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
+                                   hipStream_t s) {
+  constexpr int NY = shape_ny(SHAPE), NT = shape_nt(SHAPE), TY = shape_ty(SHAPE);
   const int k = pair_index(a.M, alpha, beta);
-  const size_t bytes = sizeof(double) * (2 * 5 * (FTX + 2 * R) * (FTY + 2 * R) + 4 * a.t.pair_nent[k]);
+  const size_t bytes = sizeof(double) * (2 * 5 * (FTX + 2 * R) * (TY + 2 * R) + 4 * a.t.pair_nent[k]);
   static size_t attr = 0;
   if (bytes > attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_adj_force<R>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_adj_force<R, NY, NT>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     attr = bytes;
   }
-  dim3 gr((a.g.nx + FTX - 1) / FTX, (a.g.ny + FTY - 1) / FTY, (a.g.nz + a.zchunk - 1) / a.zchunk);
-  hipLaunchKernelGGL(k_adj_force<R>, gr, dim3(FNT), bytes, s, a, d, alpha, beta, acc);
+  const dim3 gr(force_blocks(a.g, a.zchunk, TY));
+  hipLaunchKernelGGL((k_adj_force<R, NY, NT>), gr, dim3(NT), bytes, s, a, d, alpha, beta, acc);
+}
+
+template <int R>
+static void adj_force_launch(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
+                             hipStream_t s) {
+  if (a.rows == 1)
+    adj_force_launch_shape<R, 1>(a, d, alpha, beta, acc, s);
+  else if (a.rows == 2)
+    adj_force_launch_shape<R, 2>(a, d, alpha, beta, acc, s);
+  else
+    adj_force_launch_shape<R, 0>(a, d, alpha, beta, acc, s);
 }
 
 void launch_fill(double *p, long long n, double v, hipStream_t s) {
@@ -1730,9 +1900,8 @@ void launch_adj_nonlocal(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
     if (!wn[b]) launch_fill(d.nbar + b * N, N, 0.0, s);
   for (int k = 0; k < npairs; ++k)
     if (!wg[k]) launch_fill(d.Gbar + k * N, N, 0.0, s);
-  const dim3 gr = grid_for(a.g.N);
-  LBE_SWITCH_M(a.M, hipLaunchKernelGGL(k_adj_contact<MM>, gr, dim3(BLOCK), 0, s, a, d))
-  LBE_SWITCH_M(a.M, hipLaunchKernelGGL(k_adj_ball<MM>, gr, dim3(BLOCK), 0, s, a, d))
+  ball_launch<1>(a, d, s);
+  ball_launch<2>(a, d, s);
 }
 
 void launch_adj_extforce(const Geom &g, const double *Fbar, double *Vbar, hipStream_t s) {

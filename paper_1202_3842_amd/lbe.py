@@ -99,6 +99,7 @@ def lib() -> C.CDLL:
     L.lbe_diagnostics.argtypes = [P, C.POINTER(lbe_diag)]
     L.lbe_synchronize.argtypes = [P]
     L.lbe_set_force_zchunk.argtypes = [P, C.c_int]
+    L.lbe_set_force_tiling.argtypes = [P, C.c_int, C.c_int, C.c_int]
     L.lbe_batch_workspace_bytes.restype = C.c_size_t
     L.lbe_batch_workspace_bytes.argtypes = [C.POINTER(lbe_config), C.c_int]
     L.lbe_batch_create.argtypes = [C.POINTER(lbe_config), C.c_int, P, C.c_size_t, P, C.POINTER(P)]
@@ -236,6 +237,9 @@ class Box:
 
     def set_force_zchunk(self, zchunk):
         _check(lib().lbe_set_force_zchunk(self.h, int(zchunk)))
+
+    def set_force_tiling(self, zchunk, order=0, shape=0):
+        _check(lib().lbe_set_force_tiling(self.h, int(zchunk), int(order), int(shape)))
 
     def density(self, species=0, out=None):
         p, w, arr = self._dst(out, np.float64, self.N)
