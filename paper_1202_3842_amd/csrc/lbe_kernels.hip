@@ -517,7 +517,10 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   constexpr int W = FTX + 2 * R, H = TY + 2 * R, WH = W * H;
   constexpr int SLOTS = (WH + NT - 1) / NT;     // window elements per thread and field
   constexpr int ROW = RY * W;                   // LDS distance between a thread's rows
-  constexpr int NS = NY == 1 ? 2 : 1;           // accumulator sets per row (ILP)
+  // two accumulator sets per row, alternating over the pairs of a ring (and
+  // summed at the end): shorter dependency chains, and the same summation
+  // order for every tile shape, so results do not depend on the tiling
+  constexpr int NS = 2;
   const Geom g = geom_of(a);
   const int k = pair_index(a.M, alpha, beta);
   const int t = threadIdx.x, tx = t % FTX, ty = t / FTX;
@@ -667,29 +670,19 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
     // a pair's terms are combined before they are accumulated, so a uniform
     // state still sums to exactly zero
     int j = jbeg;
-    if (NS == 2) {
-      for (; j + 1 < jend; j += 2) {
-        pair(j, 0);
-        pair(j + 1, NS - 1);
-      }
+    for (; j + 1 < jend; j += 2) {
+      pair(j, 0);
+      pair(j + 1, 1);
     }
-    for (; j < jend; ++j) pair(j, 0);
+    if (j < jend) pair(j, 0);
     if (ez == R) {
       const long long N = g.N;
 #pragma unroll
       for (int jn = 0; jn < NY; ++jn) {
         const int y = y0 + ty + jn * RY;
         if (!(x < g.nx && y < g.ny)) continue;
-        double Mx = mx[jn][0], My = my[jn][0], Mz = mz[jn][0];
-        double Vx = vx[jn][0], Vy = vy[jn][0], Vz = vz[jn][0];
-        if (NS == 2) {
-          Mx += mx[jn][NS - 1];
-          My += my[jn][NS - 1];
-          Mz += mz[jn][NS - 1];
-          Vx += vx[jn][NS - 1];
-          Vy += vy[jn][NS - 1];
-          Vz += vz[jn][NS - 1];
-        }
+        const double Mx = mx[jn][0] + mx[jn][1], My = my[jn][0] + my[jn][1], Mz = mz[jn][0] + mz[jn][1];
+        const double Vx = vx[jn][0] + vx[jn][1], Vy = vy[jn][0] + vy[jn][1], Vz = vz[jn][0] + vz[jn][1];
         const long long i = x + (long long)g.nx * (y + (long long)g.ny * z);
         if (ADJ) {
           // n_b^bar(r) += -c (sum (e^.phibar) G(r+e) + G(r) sum e^.phibar)

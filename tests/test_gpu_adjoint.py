@@ -147,3 +147,26 @@ def test_channel96_gradient_against_oracle_fd():
         assert err <= 1e-6 * scale + 10 * noise, (r["node"], gV[r["node"]], r["grad"])
     print(f"channel96: {len(rows)} nodes, max|grad| {scale:.3e}, worst err {worst:.3e}, "
           f"fd noise {noise:.1e}", flush=True)
+
+
+def test_adjoint_tiling_does_not_change_gradient():
+    """The adjoint shell-gather transposes under every force tiling."""
+    from paper_1202_3842_amd import lbe
+    w = small_channel()
+    n_t, fluid, plane = objective_terms(w)
+    ref = None
+    for zc, order, shape in ((1, 0, 0), (3, 1, 1), (8, 2, 2), (2, 0, 1)):
+        print(f"adjoint tiling zchunk {zc} order {order} shape {shape}", flush=True)
+        box = lbe.box_from_workload(w, flags=0)
+        box.set_force_tiling(zc, order, shape)
+        adj = lbe.Adjoint(box, 4, 2)
+        adj.forward()
+        dn = np.zeros((2,) + w.shape)
+        dn[0] = 2.0 * (box.density(0) - n_t) * fluid
+        g = adj.backward(dn, None, None)
+        adj.close()
+        box.close()
+        if ref is None:
+            ref = g
+        else:
+            assert np.array_equal(g, ref), (zc, order, shape)
