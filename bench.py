@@ -67,25 +67,66 @@ def shell_pairs(sigma):
 
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_well128_s6.json")
 
 
-def kernel_views(r, N, M, P, pairs):
+def measured_traffic(kernel, grid):
+    """HBM bytes per launch of `kernel` launched with `grid` threads, from the
+    committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary (scaled by a plain
+    copy), or None when that launch was not measured."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            table = json.load(f)["kernels"]
+    except (OSError, ValueError, KeyError):
+        return None
+    v = table.get(f"{kernel}|{grid}")
+    return None if v is None else int(round(v))
+
+
+def force_launch(box, sigma, visc):
+    """(kernel name, grid threads) of the force kernel for the box's tiling."""
+    z, order, shape = getattr(box, "tiling", (2, 0, 0))
+    nt = 512 if shape == 2 else 256
+    ny = 2 if shape == 1 else 1
+    ty = nt // 32 * ny
+    R = int(sigma + 0.5)
+    c = box.cfg
+    blocks = -(-c.nx // 32) * -(-c.ny // ty) * -(-c.nz // z)
+    return f"k_force<{R}, {'true' if visc else 'false'}, {ny}, {nt}>", blocks * nt
+
+
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12   # 256 CUs x 128 B/clk x 2.4 GHz = 78.6 TB/s
+
+
+def lds_bytes_force(pairs, visc):
+    """LDS bytes read per node by the force gather: per +-e pair, n and G at
+    both points (and J~ with C^visc), 8 bytes each."""
+    return pairs * 8 * (2 * (5 if visc else 2))
+
+
+def kernel_views(r, N, M, P, pairs, prec_name):
     """Per-kernel roofline views: the collision kernel against HBM, the force
-    gather against FP64 vector throughput."""
-    steps_ms = r["total_ms"]
+    gather against FP64 vector throughput (and, beside it, LDS bandwidth)."""
     bcoll = alg_bytes_collide(M, P)
     coll_gbs = bcoll * N / (r["collide_ms"] / 1e3) / 1e9
     fl = alg_flops_force(pairs, True) * M * M
     force_tf = fl * N / (r["force_ms"] / 1e3) / 1e12
+    lds = lds_bytes_force(pairs, True) * M * M
+    lds_tbs = lds * N / (r["force_ms"] / 1e3) / 1e12
+    fname, fgrid = r["force_launch"]
     return {
         "k_collide": {"bound": "hbm", "achieved": round(coll_gbs, 1), "peak": HBM_PEAK_GBS,
                       "unit": "GB/s", "frac": round(coll_gbs / HBM_PEAK_GBS, 4),
                       "alg_bytes_per_node": bcoll, "avg_launch_ms": round(r["collide_ms"], 4),
-                      "traffic": None},
+                      "traffic": measured_traffic(f"k_collide<{prec_name}, {M}>", N)},
         "k_force": {"bound": "alu", "achieved": round(force_tf, 2), "peak": FP64_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(force_tf / FP64_PEAK_TFLOPS, 4),
                     "alg_flops_per_node": fl, "avg_launch_ms": round(r["force_ms"], 4),
-                    "traffic": None},
+                    "traffic": measured_traffic(fname, fgrid), "launch": fname, "grid": fgrid,
+                    "tiling": r["tiling"],
+                    "lds_view": {"achieved": round(lds_tbs, 2), "peak": round(LDS_PEAK_TBS, 1),
+                                 "unit": "TB/s", "frac": round(lds_tbs / LDS_PEAK_TBS, 4),
+                                 "lds_bytes_per_node": lds}},
     }
 
 
@@ -100,7 +141,7 @@ def run_gpu(w, prec, flags, steps, warmup, lbe, torch):
     from paper_1202_3842_amd import autotune
     box = lbe.box_from_workload(w, prec=prec, flags=flags)
     z = autotune.tune_zchunk(box)
-    log(f"force-kernel tiling (zchunk, order) {getattr(box, 'tiling', (z, None))}")
+    log(f"force-kernel tiling (zchunk, order, shape) {getattr(box, 'tiling', (z, None, None))}")
     box.step(warmup)
     box.synchronize()
     log(f"warmup {warmup} steps done ({'fp64' if prec == lbe.LBE_FP64 else 'fp32-pop'})")
@@ -127,7 +168,8 @@ def run_gpu(w, prec, flags, steps, warmup, lbe, torch):
     coll = [b.elapsed_time(c) for a, b, c in ev]
     diag = box.diagnostics()
     res = {"total_ms": total_ms, "force_ms": sum(force) / steps, "collide_ms": sum(coll) / steps,
-           "diag": diag}
+           "diag": diag, "force_launch": force_launch(box, w.sigma[0], bool(flags & lbe.LBE_VISC)),
+           "tiling": list(getattr(box, "tiling", ()))}
     log(f"timed {steps} steps: {total_ms / steps:.3f} ms/step, force {res['force_ms']:.3f} ms, "
         f"collide {res['collide_ms']:.3f} ms")
     box.close()
@@ -326,12 +368,12 @@ def main():
     mlups = N * M * args.steps / (r64["total_ms"] / 1e3) / 1e6
     balg = alg_bytes_step(M, npairs, 8, True)
     pairs = shell_pairs(w.sigma[0])
-    kern64 = kernel_views(r64, N, M, 8, pairs)
+    kern64 = kernel_views(r64, N, M, 8, pairs, "double")
 
     fp32_steps = args.fp32_steps if args.fp32_steps is not None else max(args.steps // 4, 10)
     r32 = run_gpu(w, lbe.LBE_FP32_POP, flags, fp32_steps, args.warmup, lbe, torch)
     mlups32 = N * M * fp32_steps / (r32["total_ms"] / 1e3) / 1e6
-    kern32 = kernel_views(r32, N, M, 4, pairs)
+    kern32 = kernel_views(r32, N, M, 4, pairs, "float")
 
     batched = None
     if not args.no_batch:

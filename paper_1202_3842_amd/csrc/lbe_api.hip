@@ -589,15 +589,21 @@ lbe_status lbe_synchronize(lbe_ctx *c) {
 
 // ---------------------------------------------------------------------------
 // Batched boxes.  Workspace: the device array of per-box parameter blocks,
-// the block -> box tables of the node-parallel kernels and of each force
-// group (boxes sharing a shell range), then every member box's workspace.
+// the block -> box tables of the node-parallel kernels, of the ball kernel
+// and of each force group (boxes sharing a shell range), then every member
+// box's workspace.
 // ---------------------------------------------------------------------------
 namespace {
 
+// z depth of the batched ball kernel's workgroups (every box)
+constexpr int BATCH_BALL_ZC = 8;
+
 struct BatchPlan {
   std::vector<size_t> box_bytes, box_off;
-  size_t off_args = 0, off_nodebox = 0, off_nodestart = 0, off_force = 0, total = 0;
-  int node_blocks = 0;
+  size_t off_args = 0, off_nodebox = 0, off_nodestart = 0, off_force = 0, off_ballbox = 0,
+         off_ballstart = 0, total = 0;
+  int node_blocks = 0, ball_blocks = 0;
+  size_t ball_lds = 0;     // LDS bytes of the batched ball kernel
   size_t force_bytes = 0;  // reserved for the force-group tables
 };
 
@@ -627,10 +633,21 @@ lbe_status make_batch_plan(const lbe_config *cfgs, int nboxes, BatchPlan &bp) {
     return at;
   };
   bp.node_blocks = 0;
-  for (const Plan &p : plans) bp.node_blocks += node_blocks(p.g);
+  bp.ball_blocks = 0;
+  bp.ball_lds = 0;
+  for (const Plan &p : plans) {
+    bp.node_blocks += node_blocks(p.g);
+    bp.ball_blocks += ball_blocks(p.g, BATCH_BALL_ZC);
+    int bR = 0;
+    for (const auto &ball : p.balls)
+      for (int v : ball) bR = std::max(bR, abs(v));
+    bp.ball_lds = std::max(bp.ball_lds, ball_lds_bytes(bR, p.nball, BATCH_BALL_ZC));
+  }
   bp.off_args = take(sizeof(StepArgs) * nboxes);
   bp.off_nodebox = take(sizeof(int) * bp.node_blocks);
   bp.off_nodestart = take(sizeof(int) * nboxes);
+  bp.off_ballbox = take(sizeof(int) * bp.ball_blocks);
+  bp.off_ballstart = take(sizeof(int) * nboxes);
   bp.force_bytes = force_table_bytes(plans);
   bp.off_force = take(bp.force_bytes);
   for (const Plan &p : plans) {
@@ -737,7 +754,12 @@ void batch_launch_step(lbe_batch *B, int cur) {
   ba.blockstart = (const int *)(B->ws + B->bp.off_nodestart);
   ba.cur = cur;
   launch_batch_moments(ba, B->bp.node_blocks, B->prec, B->visc, B->stream);
-  launch_batch_contact(ba, B->bp.node_blocks, B->stream);
+  {
+    BatchArgs bb = ba;
+    bb.blockbox = (const int *)(B->ws + B->bp.off_ballbox);
+    bb.blockstart = (const int *)(B->ws + B->bp.off_ballstart);
+    launch_batch_ball(bb, B->bp.ball_blocks, BATCH_BALL_ZC, B->bp.ball_lds, B->stream);
+  }
   for (const auto &G : B->groups) {
     BatchArgs bf = ba;
     bf.blockbox = G.blockbox;
@@ -773,7 +795,7 @@ lbe_status lbe_batch_create(const lbe_config *cfgs, int nboxes, void *ws, size_t
   B->stream = (hipStream_t)stream;
   B->prec = cfgs[0].prec;
   B->visc = (cfgs[0].flags & LBE_VISC) && !(cfgs[0].flags & LBE_IDEAL);
-  std::vector<int> nodebox, nodestart(nboxes);
+  std::vector<int> nodebox, nodestart(nboxes), ballbox, ballstart(nboxes);
   for (int b = 0; b < nboxes; ++b) {
     lbe_ctx *c = nullptr;
     st = lbe_create(&cfgs[b], B->ws + bp.box_off[b], bp.box_bytes[b], stream, &c);
@@ -784,10 +806,16 @@ lbe_status lbe_batch_create(const lbe_config *cfgs, int nboxes, void *ws, size_t
     B->boxes.push_back(c);
     nodestart[b] = (int)nodebox.size();
     nodebox.insert(nodebox.end(), node_blocks(c->pl.g), b);
+    ballstart[b] = (int)ballbox.size();
+    ballbox.insert(ballbox.end(), ball_blocks(c->pl.g, BATCH_BALL_ZC), b);
   }
   if (hipMemcpy(B->ws + bp.off_nodebox, nodebox.data(), sizeof(int) * nodebox.size(),
                 hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(B->ws + bp.off_nodestart, nodestart.data(), sizeof(int) * nboxes,
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(B->ws + bp.off_ballbox, ballbox.data(), sizeof(int) * ballbox.size(),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(B->ws + bp.off_ballstart, ballstart.data(), sizeof(int) * nboxes,
                 hipMemcpyHostToDevice) != hipSuccess) {
     lbe_batch_destroy(B);
     return fail(LBE_ERR_HIP, "batch table upload failed");

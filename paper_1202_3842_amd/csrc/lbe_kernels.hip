@@ -12,10 +12,12 @@
 //
 // Kernels per step
 //   k_moments  pull populations, n~ (and J~ with C^visc), write fields
-//   k_contact  ball-averaged densities -> BMCSL contact values G_ab
+//   k_ball     LDS-tiled ball-averaged densities -> BMCSL contact values G_ab
 //   k_force    LDS-tiled shell gather of C^mf (and C^visc) per species pair
 //   k_collide  pull, inversion, equilibria, sources, trapezoidal BGK
 //              update, store
+// and, for the adjoint with respect to V, their reverse passes (k_adj_*,
+// k_ball modes 1 and 2, k_tape_moments).
 #include <math.h>
 #include <string.h>
 
@@ -324,71 +326,24 @@ __global__ __launch_bounds__(BLOCK) void k_moments(StepArgs a, const T *__restri
   moments_body<T, VISC>(a, pop, blockIdx.x * BLOCK + threadIdx.x);
 }
 
-// Weighted densities (ball of radius sigma_b/2, normalised by its size) and
-// the BMCSL contact values G_ab(r) of every pair.
-template <int M, class A>
-__device__ inline void contact_body(const A &a, int i) {
-  const Geom g = geom_of(a);
-  if (i >= g.N) return;
-  Coord c = decode(g, i);
-  constexpr int NP = M * (M + 1) / 2;
-  double G[NP];
-  if (a.bb[i] & 1u) {
-    for (int k = 0; k < NP; ++k) G[k] = 0.0;
-  } else {
-    long long P = padded_index(g, c.x, c.y, c.z);
-    double xi2 = 0.0, xi3 = 0.0;
-    bool finite = true;
-    for (int b = 0; b < M; ++b) {
-      const double *nb = a.nfield + (long long)b * g.Np + P;
-      const int *off = a.t.ball_off + a.t.ball_start[b];
-      int cnt = a.t.ball_n[b];
-      double s = 0.0;
-      for (int j = 0; j < cnt; ++j) s += nb[off[j]];
-      double nbar = s / (double)cnt;
-      finite &= isfinite(nbar);
-      double sg = a.t.sigma[b];
-      xi2 += sg * sg * nbar;
-      xi3 += sg * sg * sg * nbar;
-    }
-    xi2 *= M_PI / 6.0;
-    xi3 *= M_PI / 6.0;
-    if (!(xi3 < 1.0) || !finite) atomicOr(a.errflag, 1u);
-    double one = 1.0 - xi3;
-    double i1 = 1.0 / one;
-    double i2 = i1 * i1;
-    double i3 = i2 * i1;
-    for (int pa = 0; pa < M; ++pa)
-      for (int pb = pa; pb < M; ++pb) {
-        int k = pair_index(M, pa, pb);
-        double d = a.t.pair_d[k];
-        G[k] = i1 + 3.0 * d * xi2 * i2 + 2.0 * d * d * xi2 * xi2 * i3;
-      }
-  }
-  for (int k = 0; k < NP; ++k) store_images(g, a.Gfield + (long long)k * g.Np, c, G[k]);
-}
-
-
 // ------------------------------------------------------------------------
 // LDS-tiled ball gathers.  A workgroup owns FTX x FTY x ZC nodes; for each
 // species it stages the (FTX + 2R) x (FTY + 2R) x (ZC + 2R) block of the
 // padded field (R = the largest ball reach) in LDS and every thread sums
 // the ball of each of its ZC nodes, one ball point for all ZC nodes at a
-// time.  Each node's sum runs over the ball in table order, so results are
-// bitwise those of the direct gather (contact_body).
+// time.  Each node's sum runs over the ball in table order (normalised by
+// the full ball size), so the result does not depend on ZC.
 //   MODE 0: ball averages of n -> BMCSL contact values G (forward)
 //   MODE 1: ball averages of n and Gbar -> adjoint of the ball averages
 //   MODE 2: ball averages of that adjoint, added into nbar (the transpose)
 // ------------------------------------------------------------------------
-template <int M, int MODE, int ZC>
-__global__ __launch_bounds__(BLOCK) void k_ball(StepArgs a, AdjArgs d) {
-  extern __shared__ double lds[];
-  const Geom g = a.g;
+template <int M, int MODE, int ZC, class A>
+__device__ inline void ball_body(const A &a, const AdjArgs &d, int b, double *lds) {
+  const Geom g = geom_of(a);
   const int Rb = a.t.ball_R;
   const int BW = FTX + 2 * Rb, BH = FTY + 2 * Rb, BZ = ZC + 2 * Rb, BP = BW * BH, BV = BP * BZ;
   int *loff = (int *)(lds + BV);
   const int nbx = (g.nx + FTX - 1) / FTX, nby = (g.ny + FTY - 1) / FTY;
-  const int b = blockIdx.x;
   const int x0 = (b % nbx) * FTX, y0 = ((b / nbx) % nby) * FTY, z0 = (b / (nbx * nby)) * ZC;
   const int t = threadIdx.x, tx = t % FTX, ty = t / FTX;
   const int base = (ty + Rb) * BW + (tx + Rb) + Rb * BP;
@@ -480,6 +435,12 @@ __global__ __launch_bounds__(BLOCK) void k_ball(StepArgs a, AdjArgs d) {
       }
     }
   }
+}
+
+template <int M, int MODE, int ZC>
+__global__ __launch_bounds__(BLOCK) void k_ball(StepArgs a, AdjArgs d) {
+  extern __shared__ double lds[];
+  ball_body<M, MODE, ZC>(a, d, blockIdx.x, lds);
 }
 
 // Nonlocal forces on the tilde moments, one directed species pair (a, b)
@@ -911,11 +872,15 @@ __global__ __launch_bounds__(BLOCK) void kb_moments(BatchArgs ba) {
   moments_body<T, VISC>(a, (const T *)a.pop[ba.cur], i);
 }
 
-__global__ __launch_bounds__(BLOCK) void kb_contact(BatchArgs ba) {
+// one-species boxes of one ball z depth ZC; blockbox/blockstart index
+// ball tiles here
+template <int ZC>
+__global__ __launch_bounds__(BLOCK) void kb_ball(BatchArgs ba) {
+  extern __shared__ double lds[];
   const int b = cptr(ba.blockbox)[blockIdx.x];
   const auto &a = *cptr(ba.boxes + b);
-  const int i = (blockIdx.x - cptr(ba.blockstart)[b]) * BLOCK + threadIdx.x;
-  contact_body<1>(a, i);
+  const AdjArgs none{};
+  ball_body<1, 0, ZC>(a, none, blockIdx.x - cptr(ba.blockstart)[b], lds);
 }
 
 template <int R, bool VISC>
@@ -1565,9 +1530,7 @@ int ball_block_zc(const Geom &g) {
 template <int M, int MODE, int ZC>
 static void ball_launch_zc(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
   const Geom &g = a.g;
-  const int Rb = a.t.ball_R;
-  const size_t bytes = sizeof(double) * (size_t)(FTX + 2 * Rb) * (FTY + 2 * Rb) * (ZC + 2 * Rb) +
-                       sizeof(int) * (size_t)a.t.ball_total;
+  const size_t bytes = ball_lds_bytes(a.t.ball_R, a.t.ball_total, ZC);
   static size_t attr = 0;
   if (bytes > attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_ball<M, MODE, ZC>),
@@ -1744,8 +1707,33 @@ void launch_batch_moments(const BatchArgs &b, int nblocks, int prec, bool visc, 
   }
 }
 
-void launch_batch_contact(const BatchArgs &b, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(kb_contact, dim3(nblocks), dim3(BLOCK), 0, s, b);
+template <int ZC>
+static void batch_ball_zc(const BatchArgs &b, int nblocks, size_t bytes, hipStream_t s) {
+  static size_t attr = 0;
+  if (bytes > attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_ball<ZC>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    attr = bytes;
+  }
+  hipLaunchKernelGGL(kb_ball<ZC>, dim3(nblocks), dim3(BLOCK), bytes, s, b);
+}
+
+void launch_batch_ball(const BatchArgs &b, int nblocks, int zc, size_t lds_bytes, hipStream_t s) {
+  switch (zc) {
+    case 8: batch_ball_zc<8>(b, nblocks, lds_bytes, s); break;
+    case 4: batch_ball_zc<4>(b, nblocks, lds_bytes, s); break;
+    case 2: batch_ball_zc<2>(b, nblocks, lds_bytes, s); break;
+    default: batch_ball_zc<1>(b, nblocks, lds_bytes, s); break;
+  }
+}
+
+size_t ball_lds_bytes(int ball_R, int ball_total, int zc) {
+  return sizeof(double) * (size_t)(FTX + 2 * ball_R) * (FTY + 2 * ball_R) * (zc + 2 * ball_R) +
+         sizeof(int) * (size_t)ball_total;
+}
+
+int ball_blocks(const Geom &g, int zc) {
+  return ((g.nx + FTX - 1) / FTX) * ((g.ny + FTY - 1) / FTY) * ((g.nz + zc - 1) / zc);
 }
 
 template <int R, bool VISC>
@@ -1843,15 +1831,12 @@ static void adj_force_launch_shape(const StepArgs &a, const AdjArgs &d, int alph
   hipLaunchKernelGGL((k_adj_force<R, NY, NT>), gr, dim3(NT), bytes, s, a, d, alpha, beta, acc);
 }
 
+// the adjoint gather stages five fields, like C^visc, for which the 32 x 8
+// shape is the fast one; zchunk and the tile order follow the box's tiling
 template <int R>
 static void adj_force_launch(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
                              hipStream_t s) {
-  if (a.rows == 1)
-    adj_force_launch_shape<R, 1>(a, d, alpha, beta, acc, s);
-  else if (a.rows == 2)
-    adj_force_launch_shape<R, 2>(a, d, alpha, beta, acc, s);
-  else
-    adj_force_launch_shape<R, 0>(a, d, alpha, beta, acc, s);
+  adj_force_launch_shape<R, 0>(a, d, alpha, beta, acc, s);
 }
 
 void launch_fill(double *p, long long n, double v, hipStream_t s) {
