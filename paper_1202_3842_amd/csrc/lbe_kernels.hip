@@ -69,9 +69,11 @@ __device__ inline Geom geom_of(const A &a) {
   return g;
 }
 
+// population loads and stores are streamed once per pass: non-temporal, so
+// that they do not evict the gathered fields from the caches
 template <typename T>
 __device__ inline double ld(const T *__restrict__ a, long long i) {
-  return (double)a[i];
+  return (double)__builtin_nontemporal_load(a + i);
 }
 
 struct Coord {
@@ -813,8 +815,8 @@ struct CollideP {
     const double Sf = w * (3.0 * cX + 9.0 * cX * cua - 3.0 * Xua);
     const double Sg = w * (4.5 * a.kappa * cC * cua + (3.0 - 1.5 * a.kappa) * Cua + 3.0 * cY +
                            9.0 * cY * cua - 3.0 * Yua);
-    *fo = T(ft + a.acoef * (feq - ft) + a.bcoef * Sf);
-    *go = T(gt + a.acoef * (geq - gt) + a.bcoef * Sg);
+    __builtin_nontemporal_store(T(ft + a.acoef * (feq - ft) + a.bcoef * Sf), fo);
+    __builtin_nontemporal_store(T(gt + a.acoef * (geq - gt) + a.bcoef * Sg), go);
   }
 };
 
