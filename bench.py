@@ -217,6 +217,23 @@ def batch_leg(lbe, torch, W, flags, prec, steps, serial_steps, tune=True):
     }
 
 
+def variants_leg(lbe, torch, w, base_flags, steps, warmup):
+    """The other schemes of Sec. 4 on the same workload and precision (FP64):
+    DD-EU, SD-TR and SD-EU (SD streams and collides f only)."""
+    out = {}
+    N, M = w.nodes, w.nspecies
+    for name, fl in (("DD-EU", lbe.LBE_EULER), ("SD-TR", lbe.LBE_SINGLE),
+                     ("SD-EU", lbe.LBE_SINGLE | lbe.LBE_EULER)):
+        r = run_gpu(w, lbe.LBE_FP64, base_flags | fl, steps, warmup, lbe, torch)
+        out[name] = {
+            "value": round(N * M * steps / (r["total_ms"] / 1e3) / 1e6, 2), "unit": "MLUPS",
+            "steps": steps, "ms_per_step": round(r["total_ms"] / steps, 4),
+            "force_ms": round(r["force_ms"], 4), "collide_ms": round(r["collide_ms"], 4),
+            "umax": r["diag"]["umax"], "unstable": r["diag"]["unstable"],
+        }
+    return out
+
+
 def adjoint_leg(lbe, torch, W, segment=20):
     """dL/dV on the 96x32x32 two-species channel (C^mf scheme, 400 steps):
     the forward with a checkpoint every `segment` steps and the backward
@@ -326,6 +343,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--variant-steps", type=int, default=300)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (a plain copy kernel of "
                          "known traffic, to scale HBM counters)")
@@ -383,6 +402,9 @@ def main():
                                   max(args.batch_steps // 5, 10)),
         }
 
+    variants = None if args.no_variants else variants_leg(lbe, torch, w, flags, args.variant_steps,
+                                                             args.warmup)
+
     adjoint = None if args.no_adjoint else adjoint_leg(lbe, torch, W)
 
     cpu = None
@@ -420,6 +442,7 @@ def main():
         },
         "state_after": {"umax": r64["diag"]["umax"], "unstable": r64["diag"]["unstable"]},
         "batched": batched,
+        "variants": variants,
         "adjoint": adjoint,
         "cpu_baseline": cpu,
     }

@@ -85,12 +85,23 @@ enum { LBE_HOST = 0, LBE_DEVICE = 1 };   /* the 'where' of user pointers    */
  *                   Pi = Pi~ + (beta/2) C^mf.u^a.
  *  LBE_KAPPA4       the printed coefficient 4 on H2.u^a in the C^mf part of
  *                   S_g (Sec. 4.2); default is 2, the Hermite projection.
- *  LBE_IDEAL        C = 0: the ideal fluid of Sec. 4.1.                     */
+ *  LBE_IDEAL        C = 0: the ideal fluid of Sec. 4.1.
+ * Scheme variants compared in Sec. 4 (default DD-TR: double distribution,
+ * trapezoidal rule):
+ *  LBE_EULER        Euler integration (EU): f* = f + omega (f_eq - f) + S_f
+ *                   (and g), moments without half-step terms.
+ *  LBE_SINGLE       single distribution (SD): only f evolves; its moments
+ *                   give n and J (J = J~ + X/2 with the trapezoidal rule,
+ *                   X the first moment of S_f); the g populations are not
+ *                   read or written (their getters return unspecified
+ *                   values).                                                */
 enum {
   LBE_VISC = 1u << 0,
   LBE_PRINTED_INV = 1u << 1,
   LBE_KAPPA4 = 1u << 2,
-  LBE_IDEAL = 1u << 3
+  LBE_IDEAL = 1u << 3,
+  LBE_EULER = 1u << 4,
+  LBE_SINGLE = 1u << 5
 };
 
 #define LBE_MAX_SPECIES 4

@@ -26,6 +26,8 @@ LBEO_VISC = 1 << 0
 LBEO_PRINTED_INV = 1 << 1
 LBEO_KAPPA4 = 1 << 2
 LBEO_IDEAL = 1 << 3
+LBEO_EULER = 1 << 4
+LBEO_SINGLE = 1 << 5
 
 Q = 19
 

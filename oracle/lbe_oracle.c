@@ -525,9 +525,11 @@ static void node_moments(const double *fp, const double *gp, double *n,
 
 static void compute_moments(lbeo_ctx *c) {
   long N = c->N;
+  /* single distribution: the current is carried by f */
+  int single = (c->cfg.flags & LBEO_SINGLE) != 0;
   for (int a = 0; a < c->M; ++a) {
     const double *fa = c->f + (long)a * Q * N;
-    const double *ga = c->g + (long)a * Q * N;
+    const double *ga = single ? fa : c->g + (long)a * Q * N;
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) {
       double fp[Q], gp[Q], n = 0, Pi = 0, J[3] = {0, 0, 0};
@@ -708,6 +710,9 @@ static void compute_forces(lbeo_ctx *c) {
 /* Trapezoidal update (Sec. 4.1):                                           */
 /*   f~* = f~ + (w h/(1 + w h/2)) (f_eq - f~) + (h/(1 + w h/2)) S_f         */
 /* and the same for g~.                                                     */
+/* Variants of Sec. 4: EULER updates f* = f + w h (f_eq - f) + h S_f (and g)*/
+/* with J = sum c g, Pi = sum g and no half-step terms; SINGLE takes the    */
+/* current from f (J = J~ + h X/2 for TR), Pi = n, and evolves no g.        */
 /* ------------------------------------------------------------------------ */
 static void hermite_tables(double vT2, hermite_t *t) {
   for (int p = 0; p < Q; ++p)
@@ -743,8 +748,11 @@ static int collide_node_tab(const hermite_t *tab, int M, double tau,
                             double *fpost, double *gpost, double *mom) {
   const double h = 1.0;
   double vT2 = kT, beta = 1.0 / kT, omega = 1.0 / tau;
-  double acoef = omega * h / (1.0 + 0.5 * omega * h);
-  double bcoef = h / (1.0 + 0.5 * omega * h);
+  int euler = (flags & LBEO_EULER) != 0;
+  int single = (flags & LBEO_SINGLE) != 0;
+  /* trapezoidal update of the tilde populations (Sec. 4.1), or Euler */
+  double acoef = euler ? omega * h : omega * h / (1.0 + 0.5 * omega * h);
+  double bcoef = euler ? h : h / (1.0 + 0.5 * omega * h);
   double kappa = (flags & LBEO_KAPPA4) ? 4.0 : 2.0;
   int printed = (flags & LBEO_PRINTED_INV) != 0;
   const double(*H1)[3] = tab->H1;
@@ -754,17 +762,23 @@ static int collide_node_tab(const hermite_t *tab, int M, double tau,
   double X[MAXM][3], Y[MAXM][3];
   double ntot = 0.0, Jtot[3] = {0, 0, 0};
   for (int a = 0; a < M; ++a) {
-    node_moments(ft + a * Q, gt + a * Q, &n[a], &Pit[a], Jt[a]);
+    /* the current from g (DD) or from f itself (SD) */
+    node_moments(ft + a * Q, single ? ft + a * Q : gt + a * Q, &n[a], &Pit[a], Jt[a]);
     for (int k = 0; k < 3; ++k) {
       double nF = n[a] * F[a * 3 + k];
       X[a][k] = cmf[a * 3 + k] + cvisc[a * 3 + k] + nF;
       Y[a][k] = cvisc[a * 3 + k] + nF;
-      J[a][k] = Jt[a][k] + 0.5 * h * (printed ? X[a][k] : Y[a][k]);
+      /* EU: no half-step terms; SD-TR: the f inversion J~ + h X/2 */
+      double half = euler ? 0.0 : 0.5 * h * ((printed || single) ? X[a][k] : Y[a][k]);
+      J[a][k] = Jt[a][k] + half;
       ua[a][k] = n[a] != 0.0 ? J[a][k] / n[a] : 0.0;
     }
     double cu = 0.0;
     for (int k = 0; k < 3; ++k) cu += cmf[a * 3 + k] * ua[a][k];
-    Pi[a] = printed ? Pit[a] - 0.5 * h * beta * cu : Pit[a] + 0.5 * h * beta * cu;
+    if (euler || single)
+      Pi[a] = Pit[a];
+    else
+      Pi[a] = printed ? Pit[a] - 0.5 * h * beta * cu : Pit[a] + 0.5 * h * beta * cu;
     ntot += n[a];
     for (int k = 0; k < 3; ++k) Jtot[k] += J[a][k];
   }
@@ -798,7 +812,7 @@ static int collide_node_tab(const hermite_t *tab, int M, double tau,
       sg *= w;
       double fo = ft[a * Q + p], go = gt[a * Q + p];
       fpost[a * Q + p] = fo + acoef * (feq - fo) + bcoef * sf;
-      gpost[a * Q + p] = go + acoef * (geq - go) + bcoef * sg;
+      gpost[a * Q + p] = single ? 0.0 : go + acoef * (geq - go) + bcoef * sg;
     }
   }
   if (mom) {

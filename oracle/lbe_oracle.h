@@ -51,12 +51,22 @@ enum {
  *               instead of the ones derived from eq. (invertmoments).
  *  KAPPA4       use the printed coefficient 4 on H2.u^a in the C^mf part of
  *               S_g (Sec. 4.2, eq. kernel-g-1) instead of the projected 2.
- *  IDEAL        switch the collisional kernel off (C = 0, Sec. 4.1).     */
+ *  IDEAL        switch the collisional kernel off (C = 0, Sec. 4.1).
+ * Scheme variants compared in Sec. 4 (default: DD-TR):
+ *  EULER        Euler integration (EU, Sec. 4.1): f* = f + omega h (f_eq -
+ *               f) + h S on the populations themselves, moments without
+ *               half-step corrections.
+ *  SINGLE       single distribution (SD): only f evolves (eqs.
+ *               boltzoriginal and bolt2); its moments give n and J, and the
+ *               trapezoidal inversion is J = J~ + h X/2 with X the first
+ *               moment of S_f; g is not used (it is set to zero).          */
 enum {
   LBEO_VISC = 1u << 0,
   LBEO_PRINTED_INV = 1u << 1,
   LBEO_KAPPA4 = 1u << 2,
-  LBEO_IDEAL = 1u << 3
+  LBEO_IDEAL = 1u << 3,
+  LBEO_EULER = 1u << 4,
+  LBEO_SINGLE = 1u << 5
 };
 
 typedef struct {

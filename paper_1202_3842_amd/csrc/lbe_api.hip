@@ -203,8 +203,9 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
   a.M = P.M;
   a.flags = cfg->flags;
   double omega = 1.0 / cfg->tau;
-  a.acoef = omega / (1.0 + 0.5 * omega);
-  a.bcoef = 1.0 / (1.0 + 0.5 * omega);
+  const bool euler = cfg->flags & LBE_EULER;
+  a.acoef = euler ? omega : omega / (1.0 + 0.5 * omega);
+  a.bcoef = euler ? 1.0 : 1.0 / (1.0 + 0.5 * omega);
   a.beta = 1.0 / cfg->kT;
   a.kappa = (cfg->flags & LBE_KAPPA4) ? 4.0 : 2.0;
   a.zchunk = FORCE_ZC < g.nz ? FORCE_ZC : g.nz;

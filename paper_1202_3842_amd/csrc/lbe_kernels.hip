@@ -313,7 +313,8 @@ __device__ inline void moments_body(const A &a, const T *__restrict__ pop, int i
       pull19(g, c, i, m, pop + (long long)s * Q * Ns, Ns, v);
       moments0(v, n);
       if (VISC) {
-        pull19(g, c, i, m, pop + (long long)(a.M + s) * Q * Ns, Ns, v);
+        // the current of C^visc: from g, or from f with a single distribution
+        if (!(a.flags & LBE_SINGLE)) pull19(g, c, i, m, pop + (long long)(a.M + s) * Q * Ns, Ns, v);
         moments1(v, J);
       }
     }
@@ -374,6 +375,7 @@ __device__ inline void ball_body(const A &a, const AdjArgs &d, int b, double *ld
   }
   const int x = x0 + tx, y = y0 + ty;
   if (x >= g.nx || y >= g.ny) return;
+  bool bad = false;  // packing fraction >= 1 or a non-finite density here
 #pragma unroll
   for (int zz = 0; zz < ZC; ++zz) {
     const int z = z0 + zz;
@@ -404,7 +406,7 @@ __device__ inline void ball_body(const A &a, const AdjArgs &d, int b, double *ld
       if (solid) {
         for (int k = 0; k < NP; ++k) G[k] = 0.0;
       } else {
-        if (!(xi3 < 1.0) || !finite) atomicOr(a.errflag, 1u);
+        bad |= !(xi3 < 1.0) || !finite;
         const double one = 1.0 - xi3;
         const double i1 = 1.0 / one;
         const double i2 = i1 * i1;
@@ -436,6 +438,12 @@ __device__ inline void ball_body(const A &a, const AdjArgs &d, int b, double *ld
                      solid ? 0.0 : (M_PI / 6.0) * (sg * sg * x2b + sg * sg * sg * x3b));
       }
     }
+  }
+  // one atomic per wave that saw a bad node (an unstable state would
+  // otherwise issue one per node)
+  if (MODE == 0) {
+    const unsigned long long m = __ballot(bad);
+    if (m != 0ull && (int)(threadIdx.x & 63u) == __ffsll((long long)m) - 1) atomicOr(a.errflag, 1u);
   }
 }
 
@@ -733,6 +741,7 @@ __device__ inline void load_forces(const A &a, int i, const double n[M], double 
 // Inversions, equilibria, sources and the trapezoidal update of one node.
 //  J = J~ + Y/2 (or + X/2 printed), u^a = J/n,
 //  Pi = Pi~ + (beta/2) C^mf.u^a (or - printed), u = sum J / sum n,
+//  (Euler: J = J~, Pi = Pi~; single distribution: J~ from f, J = J~ + X/2)
 //  f_eq = w [n + 3 c.J + 4.5 n (2 (c.u^a)(c.u) - (c.u)^2) - 1.5 n (2 u^a.u - u.u)]
 //  g_eq = f_eq + w (Pi - n)
 //  S_f  = w [3 c.X + 9 (c.X)(c.u^a) - 3 X.u^a]
@@ -750,6 +759,7 @@ __device__ inline void invert(const A &a, const double ft[M][19], const double g
                               const double cmf[M][3], const double cvisc[M][3], int i,
                               NodeMoments<M> &nm) {
   const bool printed = a.flags & LBE_PRINTED_INV;
+  const bool euler = a.flags & LBE_EULER, single = a.flags & LBE_SINGLE;
   double ntot = 0.0, Jt0 = 0.0, Jt1 = 0.0, Jt2 = 0.0;
   for (int s = 0; s < M; ++s) {
     double n, Pit, Jt[3];
@@ -762,12 +772,13 @@ __device__ inline void invert(const A &a, const double ft[M][19], const double g
       double nF = n * F;
       nm.X[s][k] = cmf[s][k] + cvisc[s][k] + nF;
       nm.Y[s][k] = cvisc[s][k] + nF;
-      nm.J[s][k] = Jt[k] + 0.5 * (printed ? nm.X[s][k] : nm.Y[s][k]);
+      // EU: no half-step term; SD: the f inversion with X
+      nm.J[s][k] = euler ? Jt[k] : Jt[k] + 0.5 * ((printed || single) ? nm.X[s][k] : nm.Y[s][k]);
       nm.ua[s][k] = n != 0.0 ? nm.J[s][k] / n : 0.0;
       cu += cmf[s][k] * nm.ua[s][k];
     }
     nm.n[s] = n;
-    nm.Pi[s] = printed ? Pit - 0.5 * a.beta * cu : Pit + 0.5 * a.beta * cu;
+    nm.Pi[s] = (euler || single) ? Pit : (printed ? Pit - 0.5 * a.beta * cu : Pit + 0.5 * a.beta * cu);
     ntot += n;
     Jt0 += nm.J[s][0];
     Jt1 += nm.J[s][1];
@@ -816,7 +827,7 @@ struct CollideP {
     const double Sg = w * (4.5 * a.kappa * cC * cua + (3.0 - 1.5 * a.kappa) * Cua + 3.0 * cY +
                            9.0 * cY * cua - 3.0 * Yua);
     __builtin_nontemporal_store(T(ft + a.acoef * (feq - ft) + a.bcoef * Sf), fo);
-    __builtin_nontemporal_store(T(gt + a.acoef * (geq - gt) + a.bcoef * Sg), go);
+    if (go) __builtin_nontemporal_store(T(gt + a.acoef * (geq - gt) + a.bcoef * Sg), go);
   }
 };
 
@@ -826,7 +837,7 @@ __device__ inline void collide_all_p(const A &a, int s, const NodeMoments<M> &nm
                                      T *__restrict__ fblk, T *__restrict__ gblk, long long Ns, int i) {
   if constexpr (p < Q) {
     CollideP<p>::template run<T, M, A>(a, s, nm, cm, ft[p], gt[p], fblk + (long long)p * Ns + i,
-                                    gblk + (long long)p * Ns + i);
+                                    gblk ? gblk + (long long)p * Ns + i : nullptr);
     collide_all_p<T, M, p + 1, A>(a, s, nm, cm, ft, gt, fblk, gblk, Ns, i);
   }
 }
@@ -840,19 +851,20 @@ __device__ inline void collide_body(const A &a, const T *__restrict__ pin, T *__
   if (m & 1u) return;  // solid slots are never read
   Coord c = decode(g, i);
   long long Ns = pop_stride(g);
+  const bool single = a.flags & LBE_SINGLE;
   double ft[M][19], gt[M][19], n[M];
   for (int s = 0; s < M; ++s) {
     pull19(g, c, i, m, pin + (long long)s * Q * Ns, Ns, ft[s]);
-    pull19(g, c, i, m, pin + (long long)(M + s) * Q * Ns, Ns, gt[s]);
+    if (!single) pull19(g, c, i, m, pin + (long long)(M + s) * Q * Ns, Ns, gt[s]);
     moments0(ft[s], n[s]);
   }
   double cmf[M][3], cvisc[M][3];
   load_forces<M>(a, i, n, cmf, cvisc);
   NodeMoments<M> nm;
-  invert<M>(a, ft, gt, cmf, cvisc, i, nm);
+  invert<M>(a, ft, single ? ft : gt, cmf, cvisc, i, nm);
   for (int s = 0; s < M; ++s)
-    collide_all_p<T, M, 0>(a, s, nm, cmf[s], ft[s], gt[s], pout + (long long)s * Q * Ns,
-                           pout + (long long)(M + s) * Q * Ns, Ns, i);
+    collide_all_p<T, M, 0>(a, s, nm, cmf[s], ft[s], single ? ft[s] : gt[s], pout + (long long)s * Q * Ns,
+                           single ? nullptr : pout + (long long)(M + s) * Q * Ns, Ns, i);
 }
 
 template <typename T, int M>
@@ -930,20 +942,21 @@ __global__ __launch_bounds__(BLOCK) void k_readout(StepArgs a, const T *__restri
   }
   Coord c = decode(g, i);
   long long Ns = pop_stride(g);
+  const bool single = a.flags & LBE_SINGLE;
   double ft[M][19], gt[M][19], n[M];
   for (int s = 0; s < M; ++s) {
     pull19(g, c, i, m, pin + (long long)s * Q * Ns, Ns, ft[s]);
-    pull19(g, c, i, m, pin + (long long)(M + s) * Q * Ns, Ns, gt[s]);
+    if (!single) pull19(g, c, i, m, pin + (long long)(M + s) * Q * Ns, Ns, gt[s]);
     moments0(ft[s], n[s]);
   }
   double cmf[M][3], cvisc[M][3];
   load_forces<M>(a, i, n, cmf, cvisc);
   NodeMoments<M> nm;
-  invert<M>(a, ft, gt, cmf, cvisc, i, nm);
+  invert<M>(a, ft, single ? ft : gt, cmf, cvisc, i, nm);
   double jt[3] = {0.0, 0.0, 0.0}, js[3] = {0.0, 0.0, 0.0};
   for (int s = 0; s < M; ++s) {
     double J1[3];
-    moments1(gt[s], J1);
+    moments1(single ? ft[s] : gt[s], J1);
     r.n[(long long)s * N + i] = nm.n[s];
     for (int k = 0; k < 3; ++k) {
       r.ua[(long long)(3 * s + k) * N + i] = nm.ua[s][k];

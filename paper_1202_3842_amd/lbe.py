@@ -35,6 +35,8 @@ LBE_VISC = 1 << 0
 LBE_PRINTED_INV = 1 << 1
 LBE_KAPPA4 = 1 << 2
 LBE_IDEAL = 1 << 3
+LBE_EULER = 1 << 4
+LBE_SINGLE = 1 << 5
 
 
 class lbe_config(C.Structure):

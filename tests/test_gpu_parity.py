@@ -49,11 +49,19 @@ def test_small_well_fp64(L):
         assert rel_err(b.populations(0, dist), o.populations(0, dist)) <= TOL
 
 
-@pytest.mark.parametrize("flags_name", ["none", "printed", "kappa4", "ideal", "printed_kappa4_visc"])
+SWITCHES = ["none", "printed", "kappa4", "ideal", "printed_kappa4_visc",
+            "dd_eu_visc", "sd_tr_visc", "sd_eu_visc", "sd_tr_ideal", "dd_eu_printed"]
+
+
+@pytest.mark.parametrize("flags_name", SWITCHES)
 def test_scheme_switches(L, flags_name):
     import oracle
     flags = {"none": 0, "printed": L.LBE_PRINTED_INV | L.LBE_VISC, "kappa4": L.LBE_KAPPA4 | L.LBE_VISC,
-             "ideal": L.LBE_IDEAL, "printed_kappa4_visc": L.LBE_VISC | L.LBE_PRINTED_INV | L.LBE_KAPPA4}[flags_name]
+             "ideal": L.LBE_IDEAL, "printed_kappa4_visc": L.LBE_VISC | L.LBE_PRINTED_INV | L.LBE_KAPPA4,
+             "dd_eu_visc": L.LBE_EULER | L.LBE_VISC, "sd_tr_visc": L.LBE_SINGLE | L.LBE_VISC,
+             "sd_eu_visc": L.LBE_SINGLE | L.LBE_EULER | L.LBE_VISC,
+             "sd_tr_ideal": L.LBE_SINGLE | L.LBE_IDEAL,
+             "dd_eu_printed": L.LBE_EULER | L.LBE_PRINTED_INV}[flags_name]
     w = W.well_box(24, 3.0, 0.3, 0.5, 6.0, 1e-3, 5, 6)
     w.body = [[1e-4, -2e-5, 0.0]]
     banner(f"switches {flags_name}")
@@ -61,6 +69,23 @@ def test_scheme_switches(L, flags_name):
     o.step(6)
     b.step(6)
     compare_state(o, b, 1, TOL, flags_name)
+
+
+@pytest.mark.parametrize("variant", ["sd_tr", "dd_eu", "sd_eu"])
+def test_scheme_variants_channel(L, variant):
+    """Sec. 4 variants on the two-species channel with walls and C^visc."""
+    flags = L.LBE_VISC | {"sd_tr": L.LBE_SINGLE, "dd_eu": L.LBE_EULER,
+                          "sd_eu": L.LBE_SINGLE | L.LBE_EULER}[variant]
+    w = W.channel(nx=48, ny=24, nz=16, x0=20, x1=28, gap=10, sigma=(4.0, 6.0), steps=5, name="channel48")
+    banner(f"variant {variant} channel")
+    o, b = _pair(L, w, flags)
+    o.step(5)
+    b.step(5)
+    compare_state(o, b, 2, TOL, variant)
+    for a in range(2):
+        assert rel_err(b.populations(a, 0), o.populations(a, 0)) <= TOL
+        if not (flags & L.LBE_SINGLE):
+            assert rel_err(b.populations(a, 1), o.populations(a, 1)) <= TOL
 
 
 def test_forces(L):
