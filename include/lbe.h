@@ -94,14 +94,20 @@ enum { LBE_HOST = 0, LBE_DEVICE = 1 };   /* the 'where' of user pointers    */
  *                   give n and J (J = J~ + X/2 with the trapezoidal rule,
  *                   X the first moment of S_f); the g populations are not
  *                   read or written (their getters return unspecified
- *                   values).                                                */
+ *                   values).
+ *  LBE_DRAG         add the interspecies drag (Appendix, eq. dragforce2),
+ *                   C^drag_a = -n_a sum_b 2 sigma_ab^2 sqrt(kT/pi) (4pi/3)
+ *                   G_ab n_b (u~_a - u~_b) with u~ = J~/n, to the
+ *                   dissipative forces (with C^visc in X, Y and
+ *                   lbe_get_force(which = 1)); zero for one species.       */
 enum {
   LBE_VISC = 1u << 0,
   LBE_PRINTED_INV = 1u << 1,
   LBE_KAPPA4 = 1u << 2,
   LBE_IDEAL = 1u << 3,
   LBE_EULER = 1u << 4,
-  LBE_SINGLE = 1u << 5
+  LBE_SINGLE = 1u << 5,
+  LBE_DRAG = 1u << 6
 };
 
 #define LBE_MAX_SPECIES 4

@@ -28,6 +28,7 @@ LBEO_KAPPA4 = 1 << 2
 LBEO_IDEAL = 1 << 3
 LBEO_EULER = 1 << 4
 LBEO_SINGLE = 1 << 5
+LBEO_DRAG = 1 << 6
 
 Q = 19
 

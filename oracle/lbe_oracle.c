@@ -619,6 +619,7 @@ static void compute_forces(lbeo_ctx *c) {
   int M = c->M;
   int visc = (c->cfg.flags & LBEO_VISC) != 0;
   int ideal = (c->cfg.flags & LBEO_IDEAL) != 0;
+  int drag = (c->cfg.flags & LBEO_DRAG) != 0;
   double kT = c->cfg.kT;
   double cvpref = 2.0 * sqrt(kT / M_PI);
   for (int a = 0; a < M; ++a) {
@@ -678,6 +679,18 @@ static void compute_forces(lbeo_ctx *c) {
               for (int k = 0; k < 3; ++k) {
                 mf[k] += -kT * na * sab * sab * s->weight * smf[k];
                 vs[k] += na * cvpref * sab * sab * s->weight * svs[k];
+              }
+            }
+            /* interspecies drag (Appendix, eq. dragforce2), local */
+            if (drag) {
+              double na = c->n[(long)a * N + i];
+              for (int b = 0; b < M; ++b) {
+                double sab = 0.5 * (c->cfg.sigma[a] + c->cfg.sigma[b]);
+                /* 2 sigma_ab^2 sqrt(kT/pi) (4 pi/3), cvpref = 2 sqrt(kT/pi) */
+                double gam = sab * sab * cvpref * (4.0 * M_PI / 3.0);
+                double coef = -na * gam * c->G[((long)a * M + b) * N + i] * c->n[(long)b * N + i];
+                for (int k = 0; k < 3; ++k)
+                  vs[k] += coef * (c->ut[((long)a * 3 + k) * N + i] - c->ut[((long)b * 3 + k) * N + i]);
               }
             }
           }

@@ -59,14 +59,21 @@ enum {
  *  SINGLE       single distribution (SD): only f evolves (eqs.
  *               boltzoriginal and bolt2); its moments give n and J, and the
  *               trapezoidal inversion is J = J~ + h X/2 with X the first
- *               moment of S_f; g is not used (it is set to zero).          */
+ *               moment of S_f; g is not used (it is set to zero).
+ *  DRAG         add the interspecies drag C^drag (Appendix, eq.
+ *               dragforce2) to the dissipative forces: with u~_b = J~_b/n_b
+ *               and the contact values G_ab(r),
+ *               C^drag_a = -n_a sum_b 2 sigma_ab^2 sqrt(kT/pi) (4 pi/3)
+ *                          G_ab n_b (u~_a - u~_b).
+ *               It enters X and Y like C^visc (and is reported with it). */
 enum {
   LBEO_VISC = 1u << 0,
   LBEO_PRINTED_INV = 1u << 1,
   LBEO_KAPPA4 = 1u << 2,
   LBEO_IDEAL = 1u << 3,
   LBEO_EULER = 1u << 4,
-  LBEO_SINGLE = 1u << 5
+  LBEO_SINGLE = 1u << 5,
+  LBEO_DRAG = 1u << 6
 };
 
 typedef struct {

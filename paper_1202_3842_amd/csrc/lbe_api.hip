@@ -133,7 +133,9 @@ lbe_status make_plan(const lbe_config *cfg, Plan &pl) {
   pl.Ns = ((long long)g.N + 63) / 64 * 64;
   size_t P = cfg->prec == LBE_FP64 ? 8 : 4;
   pl.pop_bytes = (size_t)2 * pl.M * Q * pl.Ns * P;
-  bool visc = (cfg->flags & LBE_VISC) && !(cfg->flags & LBE_IDEAL);
+  // the current fields J~: C^visc, or the drag of a mixture
+  bool visc = ((cfg->flags & LBE_VISC) || ((cfg->flags & LBE_DRAG) && pl.M > 1)) &&
+              !(cfg->flags & LBE_IDEAL);
   pl.nblocks = diag_nblocks(g);
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -224,6 +226,7 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
       a.t.pair_R[idx] = R;
       a.t.pair_cmf[idx] = -cfg->kT * sab * sab * h.weight * 0.5;
       a.t.pair_cvisc[idx] = 2.0 * sab * sab * sqrt(cfg->kT / M_PI) * h.weight * 0.5;
+      a.t.pair_drag[idx] = 2.0 * sab * sab * sqrt(cfg->kT / M_PI) * (4.0 * M_PI / 3.0);
       double ssum = cfg->sigma[pa] + cfg->sigma[pb];
       a.t.pair_d[idx] = ssum > 0.0 ? cfg->sigma[pa] * cfg->sigma[pb] / ssum : 0.0;
       int *ofs = &rofs[idx * (RING_MAX + 2)];
@@ -272,8 +275,9 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
   a.Fext = c->at<double>(P.off_F);
   a.nfield = c->at<double>(P.off_n);
   a.Gfield = c->at<double>(P.off_G);
-  a.Jfield = P.off_J ? c->at<double>(P.off_J) : nullptr;
-  if (!((cfg->flags & LBE_VISC) && !(cfg->flags & LBE_IDEAL))) a.Jfield = nullptr;
+  const bool currents = ((cfg->flags & LBE_VISC) || ((cfg->flags & LBE_DRAG) && P.M > 1)) &&
+                        !(cfg->flags & LBE_IDEAL);
+  a.Jfield = currents ? c->at<double>(P.off_J) : nullptr;
   a.errflag = c->at<unsigned>(P.off_flag);
   double *rb = c->at<double>(P.off_read);
   size_t N = g.N;

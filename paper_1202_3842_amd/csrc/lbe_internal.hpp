@@ -56,6 +56,7 @@ struct Tables {
   double pair_cmf[MAXPAIRS];   // -kT sigma_ab^2 w_ab / 2
   double pair_cvisc[MAXPAIRS]; //  2 sigma_ab^2 sqrt(kT/pi) w_ab / 2
   double pair_d[MAXPAIRS];     // sigma_a sigma_b / (sigma_a + sigma_b)
+  double pair_drag[MAXPAIRS];  // 2 sigma_ab^2 sqrt(kT/pi) 4 pi/3 (interspecies drag)
   const int *ball_off;        // all species' balls, concatenated (padded-field offsets)
   const int *ball_loff;       // the same points as offsets in a ball-kernel LDS block
   int ball_R;                 // largest reach of any species' ball
@@ -77,7 +78,7 @@ struct alignas(8) StepArgs {
   double body[MAXM][3];
   double *nfield;        // M * Np
   double *Gfield;        // npairs * Np
-  double *Jfield;        // 3M * Np (only with LBE_VISC)
+  double *Jfield;        // 3M * Np (only with LBE_VISC, or LBE_DRAG and M > 1)
   double *force;         // 6M * N: C^mf/n_a (3), C^visc/n_a (3) per species
   void *pop[2];          // the two ping-pong population buffers
   int zchunk;            // z planes per force-kernel workgroup

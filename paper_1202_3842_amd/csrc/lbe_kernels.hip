@@ -726,8 +726,8 @@ __global__ __launch_bounds__(NT) void k_force(StepArgs a, int alpha, int beta, i
 
 // per-particle forces of species s at node i, times n_s
 template <int M, class A>
-__device__ inline void load_forces(const A &a, int i, const double n[M], double cmf[M][3],
-                                   double cvisc[M][3]) {
+__device__ inline void load_forces(const A &a, int i, const Coord &c, const double n[M],
+                                   double cmf[M][3], double cvisc[M][3]) {
   const long long N = a.g.N;
   for (int s = 0; s < M; ++s) {
     const double *F = a.force + 6LL * s * N + i;
@@ -735,6 +735,24 @@ __device__ inline void load_forces(const A &a, int i, const double n[M], double 
       cmf[s][k] = n[s] * F[k * N];
       cvisc[s][k] = n[s] * F[(3 + k) * N];
     }
+  }
+  // interspecies drag (Appendix, eq. dragforce2), local, with the same
+  // velocities u~ = J~/n as C^visc: C^drag_a = -n_a sum_b gamma_ab G_ab
+  // n_b (u~_a - u~_b), added to the dissipative forces
+  if (M > 1 && (a.flags & LBE_DRAG) && !(a.flags & LBE_IDEAL)) {
+    const Geom g = geom_of(a);
+    const long long P = padded_index(g, c.x, c.y, c.z);
+    double u[M][3];
+    for (int b = 0; b < M; ++b)
+      for (int k = 0; k < 3; ++k)
+        u[b][k] = n[b] != 0.0 ? a.Jfield[(long long)(3 * b + k) * g.Np + P] / n[b] : 0.0;
+    for (int s = 0; s < M; ++s)
+      for (int b = 0; b < M; ++b) {
+        if (b == s) continue;
+        const int k = pair_index(M, s, b);
+        const double coef = -n[s] * a.t.pair_drag[k] * a.Gfield[(long long)k * g.Np + P] * n[b];
+        for (int d = 0; d < 3; ++d) cvisc[s][d] += coef * (u[s][d] - u[b][d]);
+      }
   }
 }
 
@@ -859,7 +877,7 @@ __device__ inline void collide_body(const A &a, const T *__restrict__ pin, T *__
     moments0(ft[s], n[s]);
   }
   double cmf[M][3], cvisc[M][3];
-  load_forces<M>(a, i, n, cmf, cvisc);
+  load_forces<M>(a, i, c, n, cmf, cvisc);
   NodeMoments<M> nm;
   invert<M>(a, ft, single ? ft : gt, cmf, cvisc, i, nm);
   for (int s = 0; s < M; ++s)
@@ -950,7 +968,7 @@ __global__ __launch_bounds__(BLOCK) void k_readout(StepArgs a, const T *__restri
     moments0(ft[s], n[s]);
   }
   double cmf[M][3], cvisc[M][3];
-  load_forces<M>(a, i, n, cmf, cvisc);
+  load_forces<M>(a, i, c, n, cmf, cvisc);
   NodeMoments<M> nm;
   invert<M>(a, ft, single ? ft : gt, cmf, cvisc, i, nm);
   double jt[3] = {0.0, 0.0, 0.0}, js[3] = {0.0, 0.0, 0.0};
@@ -1518,7 +1536,8 @@ void launch_pull(const Geom &g, int prec, const uint32_t *bb, const void *pre, v
 }
 
 void launch_moments(const StepArgs &a, int prec, const void *pop, hipStream_t s) {
-  bool visc = (a.flags & LBE_VISC) && !(a.flags & LBE_IDEAL);
+  // the currents J~ are needed by C^visc and by the interspecies drag
+  bool visc = a.Jfield != nullptr;
   dim3 gr = grid_for(a.g.N);
   if (prec == LBE_FP64) {
     if (visc)

@@ -37,6 +37,7 @@ LBE_KAPPA4 = 1 << 2
 LBE_IDEAL = 1 << 3
 LBE_EULER = 1 << 4
 LBE_SINGLE = 1 << 5
+LBE_DRAG = 1 << 6
 
 
 class lbe_config(C.Structure):

@@ -71,11 +71,14 @@ def test_scheme_switches(L, flags_name):
     compare_state(o, b, 1, TOL, flags_name)
 
 
-@pytest.mark.parametrize("variant", ["sd_tr", "dd_eu", "sd_eu"])
+@pytest.mark.parametrize("variant", ["sd_tr", "dd_eu", "sd_eu", "drag", "drag_visc", "drag_sd_tr"])
 def test_scheme_variants_channel(L, variant):
-    """Sec. 4 variants on the two-species channel with walls and C^visc."""
-    flags = L.LBE_VISC | {"sd_tr": L.LBE_SINGLE, "dd_eu": L.LBE_EULER,
-                          "sd_eu": L.LBE_SINGLE | L.LBE_EULER}[variant]
+    """Sec. 4 variants and the interspecies drag on the two-species channel
+    with walls (C^visc on unless the name says otherwise)."""
+    flags = {"sd_tr": L.LBE_SINGLE | L.LBE_VISC, "dd_eu": L.LBE_EULER | L.LBE_VISC,
+             "sd_eu": L.LBE_SINGLE | L.LBE_EULER | L.LBE_VISC, "drag": L.LBE_DRAG,
+             "drag_visc": L.LBE_DRAG | L.LBE_VISC,
+             "drag_sd_tr": L.LBE_DRAG | L.LBE_SINGLE | L.LBE_VISC}[variant]
     w = W.channel(nx=48, ny=24, nz=16, x0=20, x1=28, gap=10, sigma=(4.0, 6.0), steps=5, name="channel48")
     banner(f"variant {variant} channel")
     o, b = _pair(L, w, flags)
