@@ -70,22 +70,24 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_well128_s6.json")
 
 
-def measured_traffic(kernel, grid):
-    """HBM bytes per launch of `kernel` launched with `grid` threads, from the
-    committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary (scaled by a plain
-    copy), or None when that launch was not measured."""
+def measured_traffic(kernel, grid, order=None):
+    """HBM bytes per launch of `kernel` launched with `grid` threads (and, for
+    the force kernel, tile order `order`), from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary scaled by a plain copy, or None when that
+    launch was not measured."""
     try:
         with open(TRAFFIC_FILE) as f:
             table = json.load(f)["kernels"]
     except (OSError, ValueError, KeyError):
         return None
-    v = table.get(f"{kernel}|{grid}")
+    key = f"{kernel}|{grid}" + ("" if order is None else f"|order{order}")
+    v = table.get(key)
     return None if v is None else int(round(v))
 
 
 def force_launch(box, sigma, visc):
     """(kernel name, grid threads) of the force kernel for the box's tiling."""
-    z, order, shape = getattr(box, "tiling", (2, 0, 0))
+    z, order, shape = getattr(box, "tiling", (2, 1, 0))
     nt = 512 if shape == 2 else 256
     ny = 2 if shape == 1 else 1
     ty = nt // 32 * ny
@@ -122,7 +124,8 @@ def kernel_views(r, N, M, P, pairs, prec_name):
         "k_force": {"bound": "alu", "achieved": round(force_tf, 2), "peak": FP64_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(force_tf / FP64_PEAK_TFLOPS, 4),
                     "alg_flops_per_node": fl, "avg_launch_ms": round(r["force_ms"], 4),
-                    "traffic": measured_traffic(fname, fgrid), "launch": fname, "grid": fgrid,
+                    "traffic": measured_traffic(fname, fgrid, r["tiling"][1] if r["tiling"] else None),
+                    "launch": fname, "grid": fgrid,
                     "tiling": r["tiling"],
                     "lds_view": {"achieved": round(lds_tbs, 2), "peak": round(LDS_PEAK_TBS, 1),
                                  "unit": "TB/s", "frac": round(lds_tbs / LDS_PEAK_TBS, 4),

@@ -215,8 +215,9 @@ lbe_status lbe_synchronize(lbe_ctx *ctx);
 lbe_status lbe_set_force_zchunk(lbe_ctx *ctx, int zchunk);
 
 /* zchunk as above; the order in which the force kernel's tiles are handed
- * out: 0 = hardware order (default), 1 = each of the 8 XCDs (one L2 each)
- * gets a contiguous range of tiles, x fastest, 2 = the same with z fastest;
+ * out: 0 = hardware order, 1 = each of the 8 XCDs (one L2 each) gets a
+ * contiguous range of tiles, x fastest (default: same speed, about half the
+ * L2 -> fabric traffic), 2 = the same with z fastest;
  * shape of the output tile: 0 = 32 x 8, 256 threads (default), 1 = 32 x 16,
  * 256 threads with two rows each, 2 = 32 x 16, 512 threads.  Tiling
  * parameters only: results do not depend on them. */

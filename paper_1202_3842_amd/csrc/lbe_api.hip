@@ -211,7 +211,7 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
   a.beta = 1.0 / cfg->kT;
   a.kappa = (cfg->flags & LBE_KAPPA4) ? 4.0 : 2.0;
   a.zchunk = FORCE_ZC < g.nz ? FORCE_ZC : g.nz;
-  a.order = 0;
+  a.order = 1;
   a.rows = 0;
   a.pop[0] = c->pop(0);
   a.pop[1] = c->pop(1);
