@@ -203,6 +203,41 @@ lbe_status lbe_get_populations(lbe_ctx *ctx, int species, int dist, void *out,
 lbe_status lbe_set_populations(lbe_ctx *ctx, int species, int dist,
                                const void *in, int where);
 
+/* ---- quasi-pressure (Sec. 2, eq. quasipressure) ----------------------------
+ * Pi^a(r) = n^a(r) - beta * Phi^a(r), Phi^a the line integral of v^a from an
+ * origin r0 to r, evaluated with the trapezoidal rule on unit lattice steps
+ * (as the paper does): along x from r0 to (x, y0, z0), then along y to
+ * (x, y, z0), then along z to r; no step crosses a periodic face.  The
+ * paper fixes no path.  Its equation integrates v^a = C^{a,mf} + n^a F^a;
+ * the discrete g source of Sec. 4.2 keeps n^a F^a as a force, so the Pi
+ * that the discrete scheme carries at rest is the integral of C^{a,mf}
+ * alone.  That is the default (mode 0); mode LBE_QP_WITH_FEXT adds
+ * n^a F^a (F^a = -grad_h U + body force) as printed.  v = 0 on solid nodes.
+ * Both calls evaluate C^mf and n at the current state.  Errors:
+ * LBE_ERR_ARG for a null pointer, an origin outside the box or on a solid
+ * node, or unknown mode bits; LBE_ERR_UNSTABLE if the state has a packing
+ * fraction >= 1 or a non-finite density. */
+enum { LBE_QP_WITH_FEXT = 1u };
+
+/* Pi of one species, N values (0 on solid nodes); origin = {x0, y0, z0}.
+ * Blocks until the result is in out.  Uses the context's second population
+ * buffer as scratch (the state is not changed). */
+lbe_status lbe_get_quasipressure(lbe_ctx *ctx, int species, const int origin[3],
+                                 unsigned mode, double *out, int where);
+
+/* Initialiser for a non-uniform start (for example a density profile set by
+ * lbe_init_density): for every species, sets the zeroth moment of the
+ * post-streaming g~ to Pi~, the tilde value of the quasi-pressure above,
+ * by adding w_p (Pi~ - sum_q g~_q) to each g~_p on fluid nodes.  f~ and the
+ * first moment of g~ are unchanged.  Pi~ follows from Pi by the inversion
+ * of Sec. 4.2 at the current u^a: Pi~ = Pi - (beta/2) C^mf.u^a (derived
+ * reading), Pi + (beta/2) C^mf.u^a (LBE_PRINTED_INV), Pi (LBE_EULER).  The
+ * integration constant (the value at r0) does not enter the evolution.
+ * Asynchronous after the moment evaluation.  Errors as above, plus
+ * LBE_ERR_ARG with LBE_SINGLE (no g) and LBE_ERR_STATE inside a phased
+ * step. */
+lbe_status lbe_init_quasipressure(lbe_ctx *ctx, const int origin[3], unsigned mode);
+
 /* Mass, g-momentum, spurious-current and Sec. 4.1 error measures of the
  * current state; synchronises. */
 lbe_status lbe_diagnostics(lbe_ctx *ctx, lbe_diag *out);

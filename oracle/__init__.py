@@ -29,6 +29,7 @@ LBEO_IDEAL = 1 << 3
 LBEO_EULER = 1 << 4
 LBEO_SINGLE = 1 << 5
 LBEO_DRAG = 1 << 6
+LBEO_QP_WITH_FEXT = 1
 
 Q = 19
 
@@ -96,6 +97,8 @@ def lib() -> C.CDLL:
         L.lbeo_get_weighted_density.argtypes = [P, C.c_int, dp]
         L.lbeo_get_external_force.argtypes = [P, C.c_int, dp]
         L.lbeo_stream.argtypes = [P, dp, dp]
+        L.lbeo_quasipressure.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.c_uint, dp]
+        L.lbeo_init_quasipressure.argtypes = [P, C.POINTER(C.c_int), C.c_uint]
         L.lbeo_shell.argtypes = [C.c_double, C.c_int, C.POINTER(C.c_int), dp]
         L.lbeo_ball.argtypes = [C.c_double, C.c_int, C.POINTER(C.c_int)]
         L.lbeo_bmcsl.argtypes = [C.c_int, dp, dp, C.c_int, C.c_int]
@@ -292,3 +295,15 @@ class Oracle:
         out = np.zeros_like(p)
         _check(lib().lbeo_stream(self.h, _dp(p), _dp(out)))
         return out.reshape((19,) + self.shape)
+
+    def quasipressure(self, species=0, origin=(0, 0, 0), mode=0):
+        """Pi of eq. quasipressure by the trapezoidal path integral; origin
+        is (x, y, z)."""
+        o = (C.c_int * 3)(*[int(v) for v in origin])
+        out = np.zeros(self.N)
+        _check(lib().lbeo_quasipressure(self.h, species, o, mode, _dp(out)))
+        return out.reshape(self.shape)
+
+    def init_quasipressure(self, origin=(0, 0, 0), mode=0):
+        o = (C.c_int * 3)(*[int(v) for v in origin])
+        _check(lib().lbeo_init_quasipressure(self.h, o, mode))

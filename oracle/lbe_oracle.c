@@ -1021,6 +1021,129 @@ int lbeo_get_external_force(lbeo_ctx *c, int a, double *F) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Quasi-pressure (Sec. 2, eq. quasipressure).  Pi^a is n^a minus beta     */
+/* times the line integral of C^{a,mf} + n^a F^a/m from an origin, taken by */
+/* the trapezoidal rule on the lattice (the paper says so).  The paper      */
+/* fixes neither origin nor path; ours (a reading): from r0 along x to      */
+/* (x, y0, z0), then along y to (x, y, z0), then along z, in unit steps     */
+/* that never cross a periodic face.  The integrand is zero on solid nodes. */
+/*                                                                          */
+/* Integrand (a reading): the discrete g source of Sec. 4.2 keeps n F as a  */
+/* force in its first moment and C^mf only in its zeroth, so the Pi that    */
+/* the discrete scheme carries obeys grad Pi = grad n - beta C^mf; that is  */
+/* the default.  LBEO_QP_WITH_FEXT adds n F as in the printed equation.     */
+/* ------------------------------------------------------------------------ */
+static double qp_integrand(const lbeo_ctx *c, int a, unsigned mode, int k,
+                           const int r[3]) {
+  long i = IDX(c, r[0], r[1], r[2]);
+  if (c->solid[i]) return 0.0;
+  double v = c->cmf[((long)a * 3 + k) * c->N + i];
+  if (mode & LBEO_QP_WITH_FEXT) v += c->n[(long)a * c->N + i] * ext_force(c, a, k, i);
+  return v;
+}
+
+/* integral of v_k along axis k from r (updated in place) to coordinate end */
+static double qp_leg(const lbeo_ctx *c, int a, unsigned mode, int k, int r[3],
+                     int end) {
+  double acc = 0.0;
+  int dir = end > r[k] ? 1 : -1;
+  while (r[k] != end) {
+    double va = qp_integrand(c, a, mode, k, r);
+    r[k] += dir;
+    double vb = qp_integrand(c, a, mode, k, r);
+    acc += dir * 0.5 * (va + vb);
+  }
+  return acc;
+}
+
+static int qp_check(lbeo_ctx *c, const int origin[3], unsigned mode) {
+  if (!c || !origin) return fail(LBEO_ERR_ARG, "null argument");
+  if (mode & ~LBEO_QP_WITH_FEXT) return fail(LBEO_ERR_ARG, "bad mode");
+  if (origin[0] < 0 || origin[0] >= c->nx || origin[1] < 0 ||
+      origin[1] >= c->ny || origin[2] < 0 || origin[2] >= c->nz)
+    return fail(LBEO_ERR_ARG, "origin outside the box");
+  if (c->solid[IDX(c, origin[0], origin[1], origin[2])])
+    return fail(LBEO_ERR_ARG, "origin is a solid node");
+  return LBEO_OK;
+}
+
+/* Pi of species a at every node, from the current forces and densities */
+static void qp_field(const lbeo_ctx *c, int a, const int origin[3],
+                     unsigned mode, double *out) {
+  double beta = 1.0 / c->cfg.kT;
+#pragma omp parallel for schedule(static)
+  for (int z = 0; z < c->nz; ++z)
+    for (int y = 0; y < c->ny; ++y)
+      for (int x = 0; x < c->nx; ++x) {
+        long i = IDX(c, x, y, z);
+        if (c->solid[i]) {
+          out[i] = 0.0;
+          continue;
+        }
+        int r[3] = {origin[0], origin[1], origin[2]};
+        double phi = qp_leg(c, a, mode, 0, r, x);
+        phi += qp_leg(c, a, mode, 1, r, y);
+        phi += qp_leg(c, a, mode, 2, r, z);
+        out[i] = c->n[(long)a * c->N + i] - beta * phi;
+      }
+}
+
+int lbeo_quasipressure(lbeo_ctx *c, int a, const int origin[3], unsigned mode,
+                       double *out) {
+  int st = qp_check(c, origin, mode);
+  if (st != LBEO_OK) return st;
+  if (!out) return fail(LBEO_ERR_ARG, "null argument");
+  if (!check_species(c, a)) return fail(LBEO_ERR_ARG, "bad species");
+  st = prepare(c);
+  if (st != LBEO_OK) return st;
+  qp_field(c, a, origin, mode, out);
+  return LBEO_OK;
+}
+
+/* The zeroth moment of g~ is Pi~, related to Pi by the inversion of        */
+/* Sec. 4.2 at the node's current velocity u^a: Pi~ = Pi - (beta/2)         */
+/* C^mf.u^a (derived reading), Pi + (beta/2) C^mf.u^a (printed inversion),  */
+/* Pi~ = Pi for the Euler scheme.  Each g~_p gains w_p (Pi~ - sum_q g~_q),  */
+/* which leaves sum_p c_p g~_p unchanged.                                   */
+int lbeo_init_quasipressure(lbeo_ctx *c, const int origin[3], unsigned mode) {
+  int st = qp_check(c, origin, mode);
+  if (st != LBEO_OK) return st;
+  if (c->cfg.flags & LBEO_SINGLE)
+    return fail(LBEO_ERR_ARG, "the single-distribution scheme has no g");
+  st = prepare(c);
+  if (st != LBEO_OK) return st;
+  long N = c->N;
+  int M = c->M;
+  double *pi = malloc(sizeof(double) * (size_t)M * (size_t)N);
+  if (!pi) return fail(LBEO_ERR_OOM, "out of memory");
+  for (int a = 0; a < M; ++a) qp_field(c, a, origin, mode, pi + (long)a * N);
+  double beta = 1.0 / c->cfg.kT;
+  int euler = (c->cfg.flags & LBEO_EULER) != 0;
+  int printed = (c->cfg.flags & LBEO_PRINTED_INV) != 0;
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < N; ++i) {
+    double ft[MAXM * Q], gt[MAXM * Q], fo[MAXM * Q], go[MAXM * Q];
+    double cm[MAXM * 3], cv[MAXM * 3], F[MAXM * 3], mom[8 * MAXM + 3];
+    if (c->solid[i]) continue;
+    node_inputs(c, i, ft, gt, cm, cv, F);
+    collide_node_tab(&c->herm, M, c->cfg.tau, c->cfg.kT, c->cfg.flags, ft, gt,
+                     cm, cv, F, fo, go, mom);
+    for (int a = 0; a < M; ++a) {
+      double cu = 0.0;
+      for (int k = 0; k < 3; ++k) cu += cm[a * 3 + k] * mom[8 * a + 5 + k];
+      double target = pi[(long)a * N + i];
+      if (!euler) target += (printed ? 0.5 : -0.5) * beta * cu;
+      double sum = 0.0;
+      for (int p = 0; p < Q; ++p) sum += gt[a * Q + p];
+      for (int p = 0; p < Q; ++p)
+        c->g[((long)a * Q + p) * N + i] = gt[a * Q + p] + WEIGHT(p) * (target - sum);
+    }
+  }
+  free(pi);
+  return LBEO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Diagnostics.  Error measures of Sec. 4.1:                                */
 /*   Err(n) = max |n - n_eq| / n_0,  Err(u) = max |u| / v_T,                */
 /*   Err(J) = max |J| / (n_0 v_T),                                          */

@@ -113,6 +113,20 @@ int lbeo_get_populations(lbeo_ctx *ctx, int species, int dist, double *out); /* 
 int lbeo_set_populations(lbeo_ctx *ctx, int species, int dist, const double *in);
 int lbeo_diagnostics(lbeo_ctx *ctx, lbeo_diag *out);
 
+/* ---- quasi-pressure (Sec. 2, eq. quasipressure) --------------------------- */
+/* Pi^a(r) = n^a(r) - beta * (path integral from r0 to r of v^a . dr') with  */
+/* v^a = C^{a,mf}, or C^{a,mf} + n^a F^a (the form printed in the equation)  */
+/* with LBEO_QP_WITH_FEXT.  Trapezoidal rule on unit lattice steps along x,  */
+/* then y, then z from the origin r0, which must be a fluid node; no step    */
+/* crosses a periodic face.  Pi = 0 on solid nodes.                          */
+#define LBEO_QP_WITH_FEXT 1u
+int lbeo_quasipressure(lbeo_ctx *ctx, int species, const int origin[3],
+                       unsigned mode, double *out);                 /* N */
+/* Sets the zeroth moment of every species' g~ to Pi~, the tilde value of    */
+/* the quasi-pressure above at the current state, leaving f~ and the first   */
+/* moment of g~ unchanged.  Not available with LBEO_SINGLE (no g).          */
+int lbeo_init_quasipressure(lbeo_ctx *ctx, const int origin[3], unsigned mode);
+
 /* ---- inspection entry points used by the pins ---------------------------- */
 /* C^mf and C^visc of one species at the current state (3N each). */
 int lbeo_get_forces(lbeo_ctx *ctx, int species, double *cmf, double *cvisc);

@@ -532,6 +532,61 @@ lbe_status lbe_set_populations(lbe_ctx *c, int species, int dist, const void *in
   return clear_instability(c);
 }
 
+// Quasi-pressure of every species at the current state into the scratch
+// area at the start of the second population buffer (M*N doubles, well inside
+// its f~ blocks, so the g~ blocks of that buffer stay free as a stage).
+static lbe_status qp_prepare(lbe_ctx *c, const int origin[3], unsigned mode, double **phi) {
+  if (!origin) return fail(LBE_ERR_ARG, "null origin");
+  if (mode & ~(unsigned)LBE_QP_WITH_FEXT) return fail(LBE_ERR_ARG, "unknown mode bits 0x%x", mode);
+  const Geom &g = c->pl.g;
+  if (origin[0] < 0 || origin[0] >= g.nx || origin[1] < 0 || origin[1] >= g.ny || origin[2] < 0 ||
+      origin[2] >= g.nz)
+    return fail(LBE_ERR_ARG, "origin (%d, %d, %d) outside the %dx%dx%d box", origin[0], origin[1],
+                origin[2], g.nx, g.ny, g.nz);
+  const long long io = origin[0] + (long long)g.nx * (origin[1] + (long long)g.ny * origin[2]);
+  uint32_t m = 0;
+  HIP_TRY(hipMemcpyAsync(&m, c->args.bb + io, sizeof m, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (m & 1u) return fail(LBE_ERR_ARG, "origin is a solid node");
+  bool bad = false;
+  lbe_status st = readout(c, &bad);
+  if (st != LBE_OK) return st;
+  if (bad) return fail(LBE_ERR_UNSTABLE, "packing fraction >= 1 or non-finite density");
+  *phi = reinterpret_cast<double *>(c->pop(c->cur ^ 1));
+  launch_quasipressure(c->args, c->rd, origin, (mode & LBE_QP_WITH_FEXT) != 0, *phi, c->stream);
+  LAUNCH_CHECK();
+  return LBE_OK;
+}
+
+lbe_status lbe_get_quasipressure(lbe_ctx *c, int species, const int origin[3], unsigned mode, double *out,
+                                 int where) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  if (species < 0 || species >= c->pl.M) return fail(LBE_ERR_ARG, "bad species %d", species);
+  if (!out) return fail(LBE_ERR_ARG, "null output");
+  double *phi = nullptr;
+  lbe_status st = qp_prepare(c, origin, mode, &phi);
+  if (st != LBE_OK) return st;
+  size_t N = c->pl.g.N;
+  return copy_out(c, out, phi + species * N, sizeof(double) * N, where);
+}
+
+lbe_status lbe_init_quasipressure(lbe_ctx *c, const int origin[3], unsigned mode) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  if (c->cfg.flags & LBE_SINGLE) return fail(LBE_ERR_ARG, "the single-distribution scheme has no g");
+  if (c->next_phase != 0) return fail(LBE_ERR_STATE, "a phased step is incomplete");
+  double *phi = nullptr;
+  lbe_status st = qp_prepare(c, origin, mode, &phi);
+  if (st != LBE_OK) return st;
+  for (int s = 0; s < c->pl.M; ++s) {
+    char *stage = c->block(c->cur ^ 1, 1, s);
+    launch_pull(c->pl.g, c->cfg.prec, c->args.bb, c->block(c->cur, 1, s), stage, c->stream);
+    launch_qp_apply(c->args, c->rd, phi, s, c->cfg.prec, stage, c->stream);
+    launch_unstream(c->pl.g, c->cfg.prec, c->args.bb, stage, c->block(c->cur, 1, s), c->stream);
+  }
+  LAUNCH_CHECK();
+  return LBE_OK;
+}
+
 lbe_status lbe_diagnostics(lbe_ctx *c, lbe_diag *out) {
   if (!c || !out) return fail(LBE_ERR_ARG, "null argument");
   memset(out, 0, sizeof *out);

@@ -1479,6 +1479,115 @@ __global__ void k_fill(double *__restrict__ p, long long n, double v) {
     p[i] = v;
 }
 
+
+// ------------------------------------------------------------------------
+// quasi-pressure (Sec. 2, eq. quasipressure): Pi^a = n^a - beta Phi^a, Phi
+// the line integral of v^a = C^{a,mf} (+ n^a F^a) from the origin by the
+// trapezoidal rule on unit lattice steps, along x, then y, then z, never
+// across a periodic face; v = 0 on solid nodes.  One launch per axis.  A
+// workgroup holds QP_LANES lines of the axis, adjacent in memory so that the
+// walks along the lines are coalesced across lanes, and cuts each line into
+// QP_SEG segments.  With P(e) = sum_{k<e} (v(k) + v(k+1))/2 along a line,
+// Phi(e) = Phi(o) + P(e) - P(o) for the line's origin coordinate o; Phi(o)
+// comes from the previous axis (zero on the first), and the last axis
+// writes Pi itself.
+constexpr int QP_LANES = 64, QP_SEG = 8;
+
+struct QpPass {
+  int axis;                       // 0 x, 1 y, 2 z
+  int L;                          // nodes on a line
+  int o;                          // origin coordinate along the line
+  int nlines;
+  long long b0, lstride, estride; // node of element e of line l: b0 + l lstride + e estride
+  int first, last, fext;
+};
+
+__device__ inline double qp_v(const StepArgs &a, const Readout &r, int s, const QpPass &q,
+                              long long i) {
+  if (a.bb[i] & 1u) return 0.0;
+  const long long N = a.g.N;
+  double v = r.cmf[(3LL * s + q.axis) * N + i];
+  if (q.fext) v += r.n[(long long)s * N + i] * (a.Fext[(long long)q.axis * N + i] + a.body[s][q.axis]);
+  return v;
+}
+
+__global__ __launch_bounds__(QP_LANES *QP_SEG) void k_qp_pass(StepArgs a, Readout r, QpPass q,
+                                                              double *phi) {
+  __shared__ double segsum[QP_SEG][QP_LANES];
+  __shared__ double porigin[QP_LANES];
+  const int lane = threadIdx.x % QP_LANES, sg = threadIdx.x / QP_LANES;
+  const int s = blockIdx.y;
+  const int l = blockIdx.x * QP_LANES + lane;
+  const bool live = l < q.nlines;
+  const int Ls = (q.L + QP_SEG - 1) / QP_SEG;
+  const int e0 = min(sg * Ls, q.L), e1 = min(e0 + Ls, q.L);
+  const long long N = a.g.N;
+  const long long base = q.b0 + (long long)(live ? l : 0) * q.lstride;
+  double *ph = phi + (long long)s * N;
+  // Phi at the origin of the line, read before any thread of the line writes
+  const double phio = (live && !q.first) ? ph[base + (long long)q.o * q.estride] : 0.0;
+  double run = 0.0;
+  if (live && e0 < e1) {
+    double vk = qp_v(a, r, s, q, base + (long long)e0 * q.estride);
+    for (int e = e0; e < e1; ++e) {
+      if (e == q.o) porigin[lane] = run;
+      if (e + 1 < q.L) {
+        const double vn = qp_v(a, r, s, q, base + (long long)(e + 1) * q.estride);
+        run += 0.5 * (vk + vn);
+        vk = vn;
+      }
+    }
+  }
+  segsum[sg][lane] = run;
+  __syncthreads();
+  if (!live || e0 >= e1) return;
+  const int so = q.o / Ls;
+  double off = 0.0, po = 0.0;
+  for (int t = 0; t < QP_SEG; ++t) {
+    if (t < sg) off += segsum[t][lane];
+    if (t < so) po += segsum[t][lane];
+  }
+  po += porigin[lane];
+  double run2 = off;
+  double vk = qp_v(a, r, s, q, base + (long long)e0 * q.estride);
+  for (int e = e0; e < e1; ++e) {
+    const long long i = base + (long long)e * q.estride;
+    double val = phio + (run2 - po);
+    if (q.last) val = (a.bb[i] & 1u) ? 0.0 : r.n[(long long)s * N + i] - a.beta * val;
+    ph[i] = val;
+    if (e + 1 < q.L) {
+      const double vn = qp_v(a, r, s, q, base + (long long)(e + 1) * q.estride);
+      run2 += 0.5 * (vk + vn);
+      vk = vn;
+    }
+  }
+}
+
+// g~_p += w_p (Pi~ - sum_q g~_q) on the post-streaming g~ of species s, with
+// Pi~ from Pi by the inversion of Sec. 4.2 at the node's current u^a
+template <typename T>
+__global__ __launch_bounds__(BLOCK) void k_qp_apply(StepArgs a, Readout r, const double *__restrict__ pi,
+                                                     int s, T *__restrict__ gst, long long Ns) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  const long long N = a.g.N;
+  if (i >= N || (a.bb[i] & 1u)) return;
+  double target = pi[(long long)s * N + i];
+  if (!(a.flags & LBE_EULER)) {
+    double cu = 0.0;
+    for (int k = 0; k < 3; ++k) cu += r.cmf[(3LL * s + k) * N + i] * r.ua[(3LL * s + k) * N + i];
+    target += ((a.flags & LBE_PRINTED_INV) ? 0.5 : -0.5) * a.beta * cu;
+  }
+  double v[Q], sum = 0.0;
+#pragma unroll
+  for (int p = 0; p < Q; ++p) {
+    v[p] = (double)gst[(long long)p * Ns + i];
+    sum += v[p];
+  }
+  const double d = target - sum;
+#pragma unroll
+  for (int p = 0; p < Q; ++p) gst[(long long)p * Ns + i] = T(v[p] + wgt(p) * d);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------
@@ -1924,6 +2033,33 @@ void launch_adj_state_grad(const Geom &g, int M, const uint32_t *bb, const doubl
                            int dist, double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_state_grad, grid_for(g.N), dim3(BLOCK), 0, s, g, M, bb, mu, species, dist,
                      out);
+}
+
+
+void launch_quasipressure(const StepArgs &a, const Readout &r, const int o[3], bool fext, double *phi,
+                          hipStream_t s) {
+  const Geom &g = a.g;
+  const long long plane = (long long)g.nx * g.ny;
+  const dim3 blk(QP_LANES * QP_SEG);
+  // x: the line (y0, z0); y: one line per x on the plane z0; z: one line per (x, y)
+  QpPass qx = {0, g.nx, o[0], 1, (long long)g.nx * (o[1] + (long long)g.ny * o[2]), 0, 1, 1, 0, fext};
+  QpPass qy = {1, g.ny, o[1], g.nx, plane * o[2], 1, g.nx, 0, 0, fext};
+  QpPass qz = {2, g.nz, o[2], (int)plane, 0, 1, plane, 0, 1, fext};
+  hipLaunchKernelGGL(k_qp_pass, dim3(1, a.M), blk, 0, s, a, r, qx, phi);
+  hipLaunchKernelGGL(k_qp_pass, dim3((g.nx + QP_LANES - 1) / QP_LANES, a.M), blk, 0, s, a, r, qy, phi);
+  hipLaunchKernelGGL(k_qp_pass, dim3((unsigned)((plane + QP_LANES - 1) / QP_LANES), a.M), blk, 0, s, a, r,
+                     qz, phi);
+}
+
+void launch_qp_apply(const StepArgs &a, const Readout &r, const double *pi, int species, int prec,
+                     void *gstage, hipStream_t s) {
+  const long long Ns = ((long long)a.g.N + 63) / 64 * 64;
+  if (prec == LBE_FP64)
+    hipLaunchKernelGGL(k_qp_apply<double>, grid_for(a.g.N), dim3(BLOCK), 0, s, a, r, pi, species,
+                       (double *)gstage, Ns);
+  else
+    hipLaunchKernelGGL(k_qp_apply<float>, grid_for(a.g.N), dim3(BLOCK), 0, s, a, r, pi, species,
+                       (float *)gstage, Ns);
 }
 
 #undef LBE_SWITCH_M

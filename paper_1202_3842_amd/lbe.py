@@ -38,6 +38,7 @@ LBE_IDEAL = 1 << 3
 LBE_EULER = 1 << 4
 LBE_SINGLE = 1 << 5
 LBE_DRAG = 1 << 6
+LBE_QP_WITH_FEXT = 1
 
 
 class lbe_config(C.Structure):
@@ -99,6 +100,8 @@ def lib() -> C.CDLL:
     L.lbe_get_momentum.argtypes = [P, C.c_int, P, C.c_int]
     L.lbe_get_populations.argtypes = [P, C.c_int, C.c_int, P, C.c_int]
     L.lbe_set_populations.argtypes = [P, C.c_int, C.c_int, P, C.c_int]
+    L.lbe_get_quasipressure.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.c_uint, P, C.c_int]
+    L.lbe_init_quasipressure.argtypes = [P, C.POINTER(C.c_int), C.c_uint]
     L.lbe_diagnostics.argtypes = [P, C.POINTER(lbe_diag)]
     L.lbe_synchronize.argtypes = [P]
     L.lbe_set_force_zchunk.argtypes = [P, C.c_int]
@@ -276,6 +279,25 @@ class Box:
     def set_populations(self, species, dist, pops):
         p, w, keep = self._src(pops, self.pop_dtype, 19 * self.N)
         _check(lib().lbe_set_populations(self.h, int(species), int(dist), p, w))
+
+    def _origin(self, origin):
+        if origin is None:
+            nz, ny, nx = self.shape
+            origin = (nx // 2, ny // 2, nz // 2)
+        return (C.c_int * 3)(*[int(v) for v in origin])
+
+    def quasipressure(self, species=0, origin=None, mode=0, out=None):
+        """Pi of eq. quasipressure (trapezoidal path integral from origin =
+        (x, y, z), the box centre by default); mode LBE_QP_WITH_FEXT adds
+        n F to the integrand as printed."""
+        p, w, arr = self._dst(out, np.float64, self.N)
+        _check(lib().lbe_get_quasipressure(self.h, int(species), self._origin(origin), int(mode), p, w))
+        return arr.reshape(self.shape) if out is None else arr
+
+    def init_quasipressure(self, origin=None, mode=0):
+        """Set the zeroth moment of every species' g~ to the quasi-pressure
+        of the current state (for a start from a non-uniform profile)."""
+        _check(lib().lbe_init_quasipressure(self.h, self._origin(origin), int(mode)))
 
     def diagnostics(self):
         d = lbe_diag()
