@@ -297,6 +297,40 @@ def adjoint_leg(lbe, torch, W, segment=20):
     }
 
 
+def quasipressure_leg(lbe, torch, w, flags, reps=20):
+    """The quasi-pressure initialiser of Sec. 2 (eq. quasipressure) on the
+    benchmark box after 10 steps: wall time per call of a plain read-out
+    (moments, contact values, forces, read-out pass), of Pi into device memory,
+    and of the g~ initialiser; each call synchronises.  The path integral
+    itself adds three line-scan launches to the read-out, the initialiser a
+    pull, a zeroth-moment shift and an unstream per species."""
+    box = lbe.box_from_workload(w, flags=flags)
+    box.step(10)
+    origin = (w.nx // 2, w.ny // 2, w.nz // 2)
+    out = torch.empty(w.nodes, dtype=torch.float64, device="cuda")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    t_read = timed(lambda: box.density(0, out=out))
+    t_pi = timed(lambda: box.quasipressure(0, origin, 0, out=out))
+    t_init = timed(lambda: box.init_quasipressure(origin, 0))
+    box.close()
+    log(f"quasipressure: read-out {t_read:.3f} ms, Pi {t_pi:.3f} ms, initialiser {t_init:.3f} ms")
+    return {
+        "workload": w.name, "origin": list(origin), "calls": reps,
+        "readout_ms": round(t_read, 4), "quasipressure_ms": round(t_pi, 4),
+        "init_ms": round(t_init, 4),
+        "path_integral_extra_ms": round(t_pi - t_read, 4),
+    }
+
+
 def cpu_baseline(w, flags, budget_s):
     """The oracle as it stands, on the host cores, over a bounded number of
     steps of the same workload from its initial state."""
@@ -347,6 +381,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-quasipressure", action="store_true")
+    ap.add_argument("--quasipressure-only", action="store_true",
+                    help="run only the quasi-pressure leg and print its JSON (for profiling)")
     ap.add_argument("--variant-steps", type=int, default=300)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (a plain copy kernel of "
@@ -377,6 +414,10 @@ def main():
         print(json.dumps({"adjoint": adjoint_leg(lbe, torch, W)}), flush=True)
         return
     w = W.c2_large_well()
+    if args.quasipressure_only:
+        qflags = lbe.LBE_VISC | lbe.LBE_PRINTED_INV
+        print(json.dumps({"quasipressure": quasipressure_leg(lbe, torch, w, qflags)}), flush=True)
+        return
     # The library's default (derived) inversions make this start-up collapse
     # within ~60 steps; the printed inversions of Sec. 4.2 keep it bounded for
     # all 2000 steps.  The switch changes no memory traffic.
@@ -409,6 +450,8 @@ def main():
                                                              args.warmup)
 
     adjoint = None if args.no_adjoint else adjoint_leg(lbe, torch, W)
+
+    qp = None if args.no_quasipressure else quasipressure_leg(lbe, torch, w, flags)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -447,6 +490,7 @@ def main():
         "batched": batched,
         "variants": variants,
         "adjoint": adjoint,
+        "quasipressure": qp,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -1491,7 +1491,7 @@ __global__ void k_fill(double *__restrict__ p, long long n, double v) {
 // Phi(e) = Phi(o) + P(e) - P(o) for the line's origin coordinate o; Phi(o)
 // comes from the previous axis (zero on the first), and the last axis
 // writes Pi itself.
-constexpr int QP_LANES = 64, QP_SEG = 8;
+constexpr int QP_LANES = 64, QP_SEG = 16;
 
 struct QpPass {
   int axis;                       // 0 x, 1 y, 2 z
