@@ -471,6 +471,16 @@ __global__ __launch_bounds__(BLOCK) void k_ball(StepArgs a, AdjArgs d) {
 // n_b, G_ab (and J~_b with C^visc): 2 * NF * (FTX+2R)(FTY+2R) doubles.
 
 
+// where force_body reads its ring table from (see there): scalar loads for
+// C^visc and for the adjoint gather, LDS for C^mf alone
+__host__ __device__ constexpr bool table_in_smem(int mode) { return mode != 0; }
+// dynamic LDS of force_body: two planes of NF fields, then the ring table
+// when it is staged in LDS
+__host__ __device__ constexpr size_t force_lds(int mode, int R, int ty, int entries) {
+  return sizeof(double) * ((size_t)2 * (mode == 0 ? 2 : 5) * (FTX + 2 * R) * (ty + 2 * R) +
+                           (table_in_smem(mode) ? 0 : 4 * (size_t)entries));
+}
+
 // MODE 0: C^mf; MODE 1: C^mf and C^visc; MODE 2: the transpose of the C^mf
 // gather for the adjoint (fields n_b, G_ab and the adjoint force phi_a^bar,
 // see k_adj_force).  NT threads in rows of FTX; NY = output rows per thread:
@@ -524,19 +534,28 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
     const int X = x0 - R + c + g.R, Y = y0 - R + r + g.R;
     soff[q] = (e < WH && X < g.PX && Y < g.PY) ? X + g.PX * Y : -1;
   }
-  // this pair's ring table, staged once in LDS behind the plane buffers as
-  // {e0, e1, e2, offset} per point (the ring offsets are e_y*W_k + e_x for a
-  // window of FORCE_TX + 2R columns), so the inner loop touches only LDS
+  // this pair's ring table ({e^, offset} per point; the ring offsets are
+  // e_y*W_k + e_x for a window of FORCE_TX + 2R columns).  The point index is
+  // the same in every lane.  With C^visc and in the adjoint (ten gathers per
+  // pair) the entries come in through scalar loads into SGPRs and cost no LDS
+  // bandwidth (a broadcast LDS read of the 32-byte entry costs as much LDS
+  // return bandwidth as four gathers of one field).  For C^mf alone (four
+  // gathers per pair) the wait on each scalar load is exposed, so the table
+  // is staged once in LDS behind the plane buffers instead.
+  constexpr bool STAB = table_in_smem(MODE);
   int rofs[R + 2];
 #pragma unroll
   for (int ez = 0; ez <= R + 1; ++ez) rofs[ez] = ofs[ez];
-  const int j0 = rofs[0], nent = rofs[R + 1] - rofs[0];
+  const int j0 = rofs[0];
   double *tab = lds + 2 * NF * WH;
-  for (int j = t; j < nent; j += NT) {
-    tab[4 * j] = re[3 * (j0 + j)];
-    tab[4 * j + 1] = re[3 * (j0 + j) + 1];
-    tab[4 * j + 2] = re[3 * (j0 + j) + 2];
-    tab[4 * j + 3] = __longlong_as_double((long long)roff[j0 + j]);
+  if (!STAB) {
+    const int nent = rofs[R + 1] - rofs[0];
+    for (int j = t; j < nent; j += NT) {
+      tab[4 * j] = re[3 * (j0 + j)];
+      tab[4 * j + 1] = re[3 * (j0 + j) + 1];
+      tab[4 * j + 2] = re[3 * (j0 + j) + 2];
+      tab[4 * j + 3] = __longlong_as_double((long long)roff[j0 + j]);
+    }
   }
   const long long plane = (long long)g.PX * g.PY;
   const int zb = bz * a.zchunk;
@@ -603,8 +622,19 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
     const int jbeg = rofs[ez] - j0, jend = rofs[ez + 1] - j0;
     // one +-e pair for every row of the thread, into accumulator set c
     auto pair = [&](int j, int c) {
-      const double e0 = tab[4 * j], e1 = tab[4 * j + 1], e2 = tab[4 * j + 2];
-      const int o = (int)__double_as_longlong(tab[4 * j + 3]);
+      double e0, e1, e2;
+      int o;
+      if (STAB) {
+        e0 = re[3 * (j0 + j)];
+        e1 = re[3 * (j0 + j) + 1];
+        e2 = re[3 * (j0 + j) + 2];
+        o = roff[j0 + j];
+      } else {
+        e0 = tab[4 * j];
+        e1 = tab[4 * j + 1];
+        e2 = tab[4 * j + 2];
+        o = (int)__double_as_longlong(tab[4 * j + 3]);
+      }
 #pragma unroll
       for (int jn = 0; jn < NY; ++jn) {
         const int qa = base + jn * ROW + o, qb = base + jn * ROW - o;
@@ -1719,9 +1749,9 @@ constexpr int shape_ty(int shape) { return shape_nt(shape) / FTX * shape_ny(shap
 
 template <int R, bool VISC, int SHAPE>
 static void force_launch_shape(const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
-  constexpr int NF = VISC ? 5 : 2, NY = shape_ny(SHAPE), NT = shape_nt(SHAPE), TY = shape_ty(SHAPE);
+  constexpr int NY = shape_ny(SHAPE), NT = shape_nt(SHAPE), TY = shape_ty(SHAPE);
   const int k = pair_index(a.M, alpha, beta);
-  const size_t bytes = sizeof(double) * (2 * NF * (FTX + 2 * R) * (TY + 2 * R) + 4 * a.t.pair_nent[k]);
+  const size_t bytes = force_lds(VISC ? 1 : 0, R, TY, a.t.pair_nent[k]);
   static size_t attr = 0;
   if (bytes > attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_force<R, VISC, NY, NT>),
@@ -1817,8 +1847,7 @@ int force_blocks(const Geom &g, int zchunk, int ty) {
 
 template <int R, bool VISC>
 static size_t force_lds_bytes(int entries) {
-  constexpr int NF = VISC ? 5 : 2;
-  return sizeof(double) * (2 * NF * (FTX + 2 * R) * (FTY + 2 * R) + 4 * (size_t)entries);
+  return force_lds(VISC ? 1 : 0, R, FTY, entries);
 }
 
 template <int R, bool VISC>
@@ -1963,7 +1992,7 @@ static void adj_force_launch_shape(const StepArgs &a, const AdjArgs &d, int alph
                                    hipStream_t s) {
   constexpr int NY = shape_ny(SHAPE), NT = shape_nt(SHAPE), TY = shape_ty(SHAPE);
   const int k = pair_index(a.M, alpha, beta);
-  const size_t bytes = sizeof(double) * (2 * 5 * (FTX + 2 * R) * (TY + 2 * R) + 4 * a.t.pair_nent[k]);
+  const size_t bytes = force_lds(2, R, TY, a.t.pair_nent[k]);
   static size_t attr = 0;
   if (bytes > attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_adj_force<R, NY, NT>),
