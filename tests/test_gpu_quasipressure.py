@@ -217,3 +217,32 @@ def test_argument_and_state_errors(L):
     assert e.value.code == L.LBE_ERR_ARG
     s.quasipressure(0, (1, 1, 1), 0)      # Pi itself is defined for SD too
     s.close()
+
+
+def test_initialiser_on_batch_members(L):
+    """Members of a batched set share the batch's buffers: the initialiser on
+    two of them, then batched steps (graph replay), equal bitwise a standalone
+    box that does the same."""
+    spec = [(24, 3.0, 0.3, 0.5), (30, 4.0, 0.25, 1.0), (17, 3.0, 0.2, 0.3)]
+    ws = [W.well_box(n, s, ns3, eps, n / 4.0, 1e-3, 700 + i, 6, name=f"q{i}")
+          for i, (n, s, ns3, eps) in enumerate(spec)]
+    banner("quasipressure init on batch members")
+    batch = L.batch_from_workloads(ws, flags=L.LBE_VISC)
+    singles = [L.box_from_workload(w, flags=L.LBE_VISC) for w in ws]
+    batch.step(3)
+    for b in singles:
+        b.step(3)
+    for i in (0, 2):
+        o = (ws[i].nx // 3, ws[i].ny // 2, 1)
+        batch.boxes[i].init_quasipressure(o, 0)
+        singles[i].init_quasipressure(o, 0)
+        assert np.array_equal(batch.boxes[i].quasipressure(0, o), singles[i].quasipressure(0, o))
+    batch.step(5)
+    for b in singles:
+        b.step(5)
+    for bb, bs in zip(batch.boxes, singles):
+        for dist in (0, 1):
+            assert np.array_equal(bb.populations(0, dist), bs.populations(0, dist))
+    for b in singles:
+        b.close()
+    batch.close()
