@@ -298,10 +298,11 @@ def adjoint_leg(lbe, torch, W, segment=20):
 
 
 def quasipressure_leg(lbe, torch, w, flags, reps=20):
-    """The quasi-pressure initialiser of Sec. 2 (eq. quasipressure) on the
-    benchmark box after 10 steps: wall time per call of a plain read-out
-    (moments, contact values, forces, read-out pass), of Pi into device memory,
-    and of the g~ initialiser; each call synchronises.  The path integral
+    """The quasi-pressure initialiser of Sec. 2 (eq. quasipressure) and the
+    divergence diagnostic of Sec. 4.3 on the benchmark box after 10 steps:
+    wall time per call of a plain read-out (moments, contact values, forces,
+    read-out pass), of Pi into device memory, of the g~ initialiser and of D;
+    each call synchronises.  The path integral
     itself adds three line-scan launches to the read-out, the initialiser a
     pull, a zeroth-moment shift and an unstream per species."""
     box = lbe.box_from_workload(w, flags=flags)
@@ -321,13 +322,16 @@ def quasipressure_leg(lbe, torch, w, flags, reps=20):
     t_read = timed(lambda: box.density(0, out=out))
     t_pi = timed(lambda: box.quasipressure(0, origin, 0, out=out))
     t_init = timed(lambda: box.init_quasipressure(origin, 0))
+    t_div = timed(lambda: box.divergence(out=out))
     box.close()
-    log(f"quasipressure: read-out {t_read:.3f} ms, Pi {t_pi:.3f} ms, initialiser {t_init:.3f} ms")
+    log(f"quasipressure: read-out {t_read:.3f} ms, Pi {t_pi:.3f} ms, initialiser {t_init:.3f} ms, "
+        f"divergence {t_div:.3f} ms")
     return {
         "workload": w.name, "origin": list(origin), "calls": reps,
         "readout_ms": round(t_read, 4), "quasipressure_ms": round(t_pi, 4),
         "init_ms": round(t_init, 4),
         "path_integral_extra_ms": round(t_pi - t_read, 4),
+        "divergence_ms": round(t_div, 4),
     }
 
 

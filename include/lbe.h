@@ -203,6 +203,14 @@ lbe_status lbe_get_populations(lbe_ctx *ctx, int species, int dist, void *out,
 lbe_status lbe_set_populations(lbe_ctx *ctx, int species, int dist,
                                const void *in, int where);
 
+/* Divergence of the barycentric velocity, D = div u / (v_T/dx) (Sec. 4.3,
+ * the quantity of the channel validation), N values.  The derivative is the
+ * isotropic D3Q19 one, (1/v_T^2) sum_p w_p c_p . u(r + c_p) (a central
+ * difference along each axis); u = 0 on solid nodes and beyond non-periodic
+ * faces; D = 0 on solid nodes.  Uses the second population buffer as
+ * scratch (the state is not changed); blocks until out is written. */
+lbe_status lbe_get_divergence(lbe_ctx *ctx, double *out, int where);
+
 /* ---- quasi-pressure (Sec. 2, eq. quasipressure) ----------------------------
  * Pi^a(r) = n^a(r) - beta * Phi^a(r), Phi^a the line integral of v^a from an
  * origin r0 to r, evaluated with the trapezoidal rule on unit lattice steps

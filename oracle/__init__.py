@@ -99,6 +99,7 @@ def lib() -> C.CDLL:
         L.lbeo_stream.argtypes = [P, dp, dp]
         L.lbeo_quasipressure.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.c_uint, dp]
         L.lbeo_init_quasipressure.argtypes = [P, C.POINTER(C.c_int), C.c_uint]
+        L.lbeo_get_divergence.argtypes = [P, dp]
         L.lbeo_shell.argtypes = [C.c_double, C.c_int, C.POINTER(C.c_int), dp]
         L.lbeo_ball.argtypes = [C.c_double, C.c_int, C.POINTER(C.c_int)]
         L.lbeo_bmcsl.argtypes = [C.c_int, dp, dp, C.c_int, C.c_int]
@@ -307,3 +308,9 @@ class Oracle:
     def init_quasipressure(self, origin=(0, 0, 0), mode=0):
         o = (C.c_int * 3)(*[int(v) for v in origin])
         _check(lib().lbeo_init_quasipressure(self.h, o, mode))
+
+    def divergence(self):
+        """D = div_h u / (v_T / dx) of the barycentric velocity."""
+        out = np.zeros(self.N)
+        _check(lib().lbeo_get_divergence(self.h, _dp(out)))
+        return out.reshape(self.shape)

@@ -1144,6 +1144,52 @@ int lbeo_init_quasipressure(lbeo_ctx *c, const int origin[3], unsigned mode) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Divergence of the velocity field (Sec. 4.3, the quantity D of the        */
+/* channel validation): D = div u / (v_T / dx), dx = 1.  The paper does not */
+/* say how the derivative is taken; our reading uses the isotropic D3Q19    */
+/* gradient of the external force, div_h u = (1/v_T^2) sum_p w_p c_p .      */
+/* u(r + c_p), with u = 0 on solid nodes (no-slip) and beyond non-periodic  */
+/* faces (the walls).                                                       */
+/* ------------------------------------------------------------------------ */
+int lbeo_get_divergence(lbeo_ctx *c, double *out) {
+  if (!c || !out) return fail(LBEO_ERR_ARG, "null argument");
+  long N = c->N;
+  double *u = malloc(sizeof(double) * 3 * (size_t)N);
+  if (!u) return fail(LBEO_ERR_OOM, "out of memory");
+  int st = lbeo_get_velocity(c, -1, u);
+  if (st != LBEO_OK) {
+    free(u);
+    return st;
+  }
+  double vT = sqrt(c->vT2);
+#pragma omp parallel for schedule(static)
+  for (int z = 0; z < c->nz; ++z)
+    for (int y = 0; y < c->ny; ++y)
+      for (int x = 0; x < c->nx; ++x) {
+        long i = IDX(c, x, y, z);
+        if (c->solid[i]) {
+          out[i] = 0.0;
+          continue;
+        }
+        double div = 0.0;
+        for (int p = 1; p < Q; ++p) {
+          int X = x + CV[p][0], Y = y + CV[p][1], Z = z + CV[p][2];
+          if (!wrap1(&X, c->nx, c->cfg.periodic & 1u) ||
+              !wrap1(&Y, c->ny, c->cfg.periodic & 2u) ||
+              !wrap1(&Z, c->nz, c->cfg.periodic & 4u))
+            continue; /* beyond a wall: u = 0 */
+          long j = IDX(c, X, Y, Z);
+          double cu = 0.0;
+          for (int k = 0; k < 3; ++k) cu += CV[p][k] * u[(long)k * N + j];
+          div += WEIGHT(p) * cu;
+        }
+        out[i] = div / c->vT2 / vT;
+      }
+  free(u);
+  return LBEO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Diagnostics.  Error measures of Sec. 4.1:                                */
 /*   Err(n) = max |n - n_eq| / n_0,  Err(u) = max |u| / v_T,                */
 /*   Err(J) = max |J| / (n_0 v_T),                                          */

@@ -127,6 +127,12 @@ int lbeo_quasipressure(lbeo_ctx *ctx, int species, const int origin[3],
 /* moment of g~ unchanged.  Not available with LBEO_SINGLE (no g).          */
 int lbeo_init_quasipressure(lbeo_ctx *ctx, const int origin[3], unsigned mode);
 
+/* ---- velocity divergence (Sec. 4.3, the D of the channel validation) ------ */
+/* D = div_h u / (v_T / dx) of the barycentric velocity u, with the isotropic */
+/* D3Q19 divergence (1/v_T^2) sum_p w_p c_p . u(r + c_p); u = 0 on solid     */
+/* nodes and beyond non-periodic faces; D = 0 on solid nodes (N values).     */
+int lbeo_get_divergence(lbeo_ctx *ctx, double *out);
+
 /* ---- inspection entry points used by the pins ---------------------------- */
 /* C^mf and C^visc of one species at the current state (3N each). */
 int lbeo_get_forces(lbeo_ctx *ctx, int species, double *cmf, double *cvisc);

@@ -532,6 +532,20 @@ lbe_status lbe_set_populations(lbe_ctx *c, int species, int dist, const void *in
   return clear_instability(c);
 }
 
+lbe_status lbe_get_divergence(lbe_ctx *c, double *out, int where) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  if (!out) return fail(LBE_ERR_ARG, "null output");
+  bool bad = false;
+  lbe_status st = readout(c, &bad);
+  if (st != LBE_OK) return st;
+  double *d = reinterpret_cast<double *>(c->pop(c->cur ^ 1));
+  launch_divergence(c->pl.g, c->args.bb, c->rd.u, c->cfg.kT, d, c->stream);
+  LAUNCH_CHECK();
+  st = copy_out(c, out, d, sizeof(double) * c->pl.g.N, where);
+  if (st != LBE_OK) return st;
+  return bad ? fail(LBE_ERR_UNSTABLE, "packing fraction >= 1 or non-finite density") : LBE_OK;
+}
+
 // Quasi-pressure of every species at the current state into the scratch
 // area at the start of the second population buffer (M*N doubles, well inside
 // its f~ blocks, so the g~ blocks of that buffer stay free as a stage).

@@ -176,6 +176,8 @@ void launch_adj_extforce(const Geom &g, const double *Fbar, double *Vbar, hipStr
 void launch_adj_state_grad(const Geom &g, int M, const uint32_t *bb, const double *mu, int species,
                            int dist, double *out, hipStream_t s);
 void launch_fill(double *p, long long n, double v, hipStream_t s);
+void launch_divergence(const Geom &g, const uint32_t *bb, const double *u, double kT, double *out,
+                       hipStream_t s);
 // quasi-pressure: Pi of every species into phi (M*N) from the read-out
 // fields; then, per species, the zeroth-moment shift of a pulled g~ stage
 void launch_quasipressure(const StepArgs &a, const Readout &r, const int origin[3], bool fext,

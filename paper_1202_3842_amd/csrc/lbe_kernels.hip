@@ -1511,6 +1511,40 @@ __global__ void k_fill(double *__restrict__ p, long long n, double v) {
 
 
 // ------------------------------------------------------------------------
+// velocity divergence D = div_h u / (v_T/dx) of the barycentric velocity,
+// with the isotropic D3Q19 divergence (1/v_T^2) sum_p w_p c_p . u(r + c_p);
+// u = 0 on solid nodes and beyond non-periodic faces, D = 0 on solid nodes
+__global__ __launch_bounds__(BLOCK) void k_divergence(Geom g, const uint32_t *__restrict__ bb,
+                                                       const double *__restrict__ u, double scale,
+                                                       double *__restrict__ out) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= g.N) return;
+  if (bb[i] & 1u) {
+    out[i] = 0.0;
+    return;
+  }
+  const Coord c = decode(g, i);
+  const bool px = g.periodic & 1u, py = g.periodic & 2u, pz = g.periodic & 4u;
+  const long long N = g.N;
+  double div = 0.0;
+#pragma unroll
+  for (int p = 1; p < Q; ++p) {
+    const int cx = cvec(p, 0), cy = cvec(p, 1), cz = cvec(p, 2);
+    if ((cx < 0 && c.x == 0 && !px) || (cx > 0 && c.x == g.nx - 1 && !px) ||
+        (cy < 0 && c.y == 0 && !py) || (cy > 0 && c.y == g.ny - 1 && !py) ||
+        (cz < 0 && c.z == 0 && !pz) || (cz > 0 && c.z == g.nz - 1 && !pz))
+      continue;
+    const long long j = downstream(g, c, p);
+    double cu = 0.0;
+    if (cx) cu += cx * u[j];
+    if (cy) cu += cy * u[N + j];
+    if (cz) cu += cz * u[2 * N + j];
+    div += wgt(p) * cu;
+  }
+  out[i] = div * scale;
+}
+
+// ------------------------------------------------------------------------
 // quasi-pressure (Sec. 2, eq. quasipressure): Pi^a = n^a - beta Phi^a, Phi
 // the line integral of v^a = C^{a,mf} (+ n^a F^a) from the origin by the
 // trapezoidal rule on unit lattice steps, along x, then y, then z, never
@@ -2064,6 +2098,13 @@ void launch_adj_state_grad(const Geom &g, int M, const uint32_t *bb, const doubl
                      out);
 }
 
+
+void launch_divergence(const Geom &g, const uint32_t *bb, const double *u, double kT, double *out,
+                       hipStream_t s) {
+  // 1/v_T^2 of the stencil times 1/v_T of the normalisation (dx = 1)
+  const double scale = 1.0 / (kT * sqrt(kT));
+  hipLaunchKernelGGL(k_divergence, grid_for(g.N), dim3(BLOCK), 0, s, g, bb, u, scale, out);
+}
 
 void launch_quasipressure(const StepArgs &a, const Readout &r, const int o[3], bool fext, double *phi,
                           hipStream_t s) {

@@ -100,6 +100,7 @@ def lib() -> C.CDLL:
     L.lbe_get_momentum.argtypes = [P, C.c_int, P, C.c_int]
     L.lbe_get_populations.argtypes = [P, C.c_int, C.c_int, P, C.c_int]
     L.lbe_set_populations.argtypes = [P, C.c_int, C.c_int, P, C.c_int]
+    L.lbe_get_divergence.argtypes = [P, P, C.c_int]
     L.lbe_get_quasipressure.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.c_uint, P, C.c_int]
     L.lbe_init_quasipressure.argtypes = [P, C.POINTER(C.c_int), C.c_uint]
     L.lbe_diagnostics.argtypes = [P, C.POINTER(lbe_diag)]
@@ -279,6 +280,12 @@ class Box:
     def set_populations(self, species, dist, pops):
         p, w, keep = self._src(pops, self.pop_dtype, 19 * self.N)
         _check(lib().lbe_set_populations(self.h, int(species), int(dist), p, w))
+
+    def divergence(self, out=None):
+        """D = div_h u / (v_T/dx) of the barycentric velocity."""
+        p, w, arr = self._dst(out, np.float64, self.N)
+        _check(lib().lbe_get_divergence(self.h, p, w))
+        return arr.reshape(self.shape) if out is None else arr
 
     def _origin(self, origin):
         if origin is None:
