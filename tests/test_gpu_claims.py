@@ -1,0 +1,40 @@
+"""GPU checks of the paper's quantitative comparison of its schemes (Sec. 4.3,
+hard spheres in the cosine well): the spurious velocity of DD-TR lies far
+below that of SD-EU.  The paper reports a factor of about 50; the library
+measures about 90 on this workload."""
+import numpy as np
+import pytest
+
+from paper_1202_3842_amd import workloads as W
+from tests.parity_util import banner
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1202_3842_amd import lbe
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    lbe.lib()
+    return lbe
+
+
+def test_dd_tr_spurious_velocity_far_below_sd_eu(L):
+    """32^3 periodic well, sigma = 4, n sigma^3 = 0.3 (eta 0.157), depth 1 kT,
+    C^visc on, 3000 steps: max |u| of DD-TR at least 20x below SD-EU's, and
+    SD-TR in between."""
+    w = W.c1_small_well()
+    banner("spurious velocity DD-TR / SD-TR / SD-EU, 32^3 well")
+    umax = {}
+    for name, fl in (("DD-TR", L.LBE_VISC), ("SD-TR", L.LBE_VISC | L.LBE_SINGLE),
+                     ("SD-EU", L.LBE_VISC | L.LBE_SINGLE | L.LBE_EULER)):
+        b = L.box_from_workload(w, flags=fl)
+        b.step(3000)
+        d = b.diagnostics()
+        assert not d["unstable"], name
+        umax[name] = d["umax"]
+        b.close()
+    print(f"[claim] max |u|: {umax}, SD-EU / DD-TR {umax['SD-EU'] / umax['DD-TR']:.3g}", flush=True)
+    assert umax["SD-EU"] > 20.0 * umax["DD-TR"]
+    assert umax["DD-TR"] < umax["SD-TR"] < umax["SD-EU"]
