@@ -471,6 +471,8 @@ __global__ __launch_bounds__(BLOCK) void k_ball(StepArgs a, AdjArgs d) {
 // n_b, G_ab (and J~_b with C^visc): 2 * NF * (FTX+2R)(FTY+2R) doubles.
 
 
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
 // where force_body reads its ring table from (see there): scalar loads for
 // C^visc and for the adjoint gather, LDS for C^mf alone
 __host__ __device__ constexpr bool table_in_smem(int mode) { return mode != 0; }
@@ -502,6 +504,15 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   // summed at the end): shorter dependency chains, and the same summation
   // order for every tile shape, so results do not depend on the tiling
   constexpr int NS = 2;
+  // LDS layout of a staged plane.  PAIRED: n and G interleaved, then the x and
+  // y components of the vector field interleaved, then its z component, so a
+  // point's n and G come in with one 16-byte read; otherwise one array per
+  // field.  The separate arrays are faster with C^visc, the interleaved ones
+  // for C^mf alone and for the adjoint gather (measured).
+  constexpr bool PAIRED = MODE != 1;
+  auto at = [&](int f, int e) {
+    return PAIRED ? (f < 2 ? 2 * e + f : (f < 4 ? 2 * WH + 2 * e + (f - 2) : 4 * WH + e)) : f * WH + e;
+  };
   const Geom g = geom_of(a);
   const int k = pair_index(a.M, alpha, beta);
   const int t = threadIdx.x, tx = t % FTX, ty = t / FTX;
@@ -588,12 +599,22 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int f = 0; f < NF; ++f)
+      for (int q = 0; q < SLOTS; ++q) {
+        const int e = t + q * NT;
+        if (q < SLOTS - 1 || e < WH) {
+          double *P = lds + b * NF * WH;
+          if (PAIRED) {
+            *reinterpret_cast<dbl2 *>(P + 2 * e) = dbl2{stage[b][0][q], stage[b][1][q]};
+            if (NF == 5) {
+              *reinterpret_cast<dbl2 *>(P + 2 * WH + 2 * e) = dbl2{stage[b][2 % NF][q], stage[b][3 % NF][q]};
+              P[4 * WH + e] = stage[b][4 % NF][q];
+            }
+          } else {
 #pragma unroll
-        for (int q = 0; q < SLOTS; ++q) {
-          const int e = t + q * NT;
-          if (q < SLOTS - 1 || e < WH) lds[(b * NF + f) * WH + e] = stage[b][f][q];
+            for (int f = 0; f < NF; ++f) P[f * WH + e] = stage[b][f][q];
+          }
         }
+      }
     __syncthreads();
     if (rho + 1 < rounds) fetch(rho + 1);
     const double *Bp = lds;
@@ -604,18 +625,18 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
 #pragma unroll
         for (int c = 0; c < NS; ++c) mx[jn][c] = my[jn][c] = mz[jn][c] = vx[jn][c] = vy[jn][c] = vz[jn][c] = 0.0;
         const int bj = base + jn * ROW;
-        G0[jn] = Bp[WH + bj];
-        n0[jn] = Bp[bj];
+        G0[jn] = Bp[at(1, bj)];
+        n0[jn] = Bp[at(0, bj)];
         u0x[jn] = u0y[jn] = u0z[jn] = 0.0;
         if (VISC && n0[jn] != 0.0) {
-          u0x[jn] = Bp[2 * WH + bj] / n0[jn];
-          u0y[jn] = Bp[3 * WH + bj] / n0[jn];
-          u0z[jn] = Bp[4 * WH + bj] / n0[jn];
+          u0x[jn] = Bp[at(2, bj)] / n0[jn];
+          u0y[jn] = Bp[at(3, bj)] / n0[jn];
+          u0z[jn] = Bp[at(4, bj)] / n0[jn];
         }
         if (ADJ) {
-          u0x[jn] = Bp[2 * WH + bj];
-          u0y[jn] = Bp[3 * WH + bj];
-          u0z[jn] = Bp[4 * WH + bj];
+          u0x[jn] = Bp[at(2, bj)];
+          u0y[jn] = Bp[at(3, bj)];
+          u0z[jn] = Bp[at(4, bj)];
         }
       }
     }
@@ -638,28 +659,49 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
 #pragma unroll
       for (int jn = 0; jn < NY; ++jn) {
         const int qa = base + jn * ROW + o, qb = base + jn * ROW - o;
-        const double npl = Bp[qa], nmi = Bm[qb];
+        dbl2 ap, am, vp = {0.0, 0.0}, vm = {0.0, 0.0};
+        double vpz = 0.0, vmz = 0.0;
+        if (PAIRED) {
+          ap = *reinterpret_cast<const dbl2 *>(Bp + 2 * qa);
+          am = *reinterpret_cast<const dbl2 *>(Bm + 2 * qb);
+          if (NF == 5) {
+            vp = *reinterpret_cast<const dbl2 *>(Bp + 2 * WH + 2 * qa);
+            vm = *reinterpret_cast<const dbl2 *>(Bm + 2 * WH + 2 * qb);
+          }
+        } else {
+          ap = dbl2{Bp[qa], Bp[WH + qa]};
+          am = dbl2{Bm[qb], Bm[WH + qb]};
+          if (NF == 5) {
+            vp = dbl2{Bp[2 * WH + qa], Bp[3 * WH + qa]};
+            vm = dbl2{Bm[2 * WH + qb], Bm[3 * WH + qb]};
+          }
+        }
+        if (NF == 5) {
+          vpz = Bp[4 * WH + qa];
+          vmz = Bm[4 * WH + qb];
+        }
+        const double npl = ap.x, nmi = am.x;
         if (ADJ) {
           // m: sum_S e^ n_b(r+e); v: sum_S e^.phibar(r+e) and
           // sum_S (e^.phibar(r+e)) G(r+e), over both points of the pair
-          const double tp = e0 * Bp[2 * WH + qa] + e1 * Bp[3 * WH + qa] + e2 * Bp[4 * WH + qa];
-          const double tm = e0 * Bm[2 * WH + qb] + e1 * Bm[3 * WH + qb] + e2 * Bm[4 * WH + qb];
+          const double tp = e0 * vp.x + e1 * vp.y + e2 * vpz;
+          const double tm = e0 * vm.x + e1 * vm.y + e2 * vmz;
           const double dn = npl - nmi;
           mx[jn][c] += e0 * dn;
           my[jn][c] += e1 * dn;
           mz[jn][c] += e2 * dn;
           vx[jn][c] += tp - tm;
-          vy[jn][c] += tp * Bp[WH + qa] - tm * Bm[WH + qb];
+          vy[jn][c] += tp * ap.y - tm * am.y;
         } else {
-          const double gp = G0[jn] + Bp[WH + qa], gm = G0[jn] + Bm[WH + qb];
+          const double gp = G0[jn] + ap.y, gm = G0[jn] + am.y;
           const double d = gp * npl - gm * nmi;
           mx[jn][c] += e0 * d;
           my[jn][c] += e1 * d;
           mz[jn][c] += e2 * d;
           if (VISC) {
             const double eu = e0 * u0x[jn] + e1 * u0y[jn] + e2 * u0z[jn];
-            const double tp = gp * (e0 * Bp[2 * WH + qa] + e1 * Bp[3 * WH + qa] + e2 * Bp[4 * WH + qa] - eu * npl);
-            const double tm = gm * (e0 * Bm[2 * WH + qb] + e1 * Bm[3 * WH + qb] + e2 * Bm[4 * WH + qb] - eu * nmi);
+            const double tp = gp * (e0 * vp.x + e1 * vp.y + e2 * vpz - eu * npl);
+            const double tm = gm * (e0 * vm.x + e1 * vm.y + e2 * vmz - eu * nmi);
             const double tt = tp + tm;
             vx[jn][c] += e0 * tt;
             vy[jn][c] += e1 * tt;
