@@ -1,0 +1,81 @@
+"""GPU parity on seeded random small configurations: odd and thin boxes,
+mixed periodicity, one to three species with unequal diameters, random
+relaxation times, solid obstacles, smooth potentials, body forces and every
+scheme switch.  Each case runs 3 steps in the library and in the FP64 oracle
+and compares n and u of every species and the barycentric u (bar 1e-11)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1202_3842_amd import workloads as W
+from tests.parity_util import banner, compare_state, oracle_from_workload
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+KT = 1.0 / 3.0
+NCASES = 16
+
+
+@pytest.fixture(scope="module")
+def L():
+    import oracle
+    if not oracle.LIB.exists():
+        oracle.build()
+    oracle.set_threads(8)
+    from paper_1202_3842_amd import lbe
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    lbe.lib()
+    return lbe
+
+
+def _case(L, i):
+    g = W.rng(9000 + i)
+    M = int(g.integers(1, 4))
+    sigma = [float(g.choice([1.0, 2.0, 2.5, 3.0, 4.0, 5.0])) for _ in range(M)]
+    reach = int(math.ceil(max(sigma))) + 1
+    dims = [int(g.integers(max(reach, 5), 29)) for _ in range(3)]
+    periodic = int(g.integers(0, 8))
+    for k in range(3):                       # a periodic edge must cover the interaction range
+        if dims[k] < reach + 2:
+            periodic |= 1 << k
+            dims[k] = max(dims[k], reach + 2)
+    nx, ny, nz = dims
+    shape = (nz, ny, nx)
+    choices = [0, L.LBE_VISC, L.LBE_VISC | L.LBE_PRINTED_INV, L.LBE_KAPPA4 | L.LBE_VISC,
+               L.LBE_VISC | L.LBE_EULER, L.LBE_VISC | L.LBE_SINGLE, L.LBE_SINGLE | L.LBE_EULER,
+               L.LBE_IDEAL, L.LBE_VISC | L.LBE_PRINTED_INV | L.LBE_KAPPA4]
+    if M > 1:
+        choices += [L.LBE_DRAG, L.LBE_DRAG | L.LBE_VISC]
+    flags = int(choices[int(g.integers(0, len(choices)))])
+    tau = float(g.choice([0.6, 1.0, 1.7]))
+    eta = float(g.uniform(0.05, 0.22))
+    frac = g.dirichlet(np.ones(M))
+    density = [W.noisy_uniform(shape, W.packing_density(eta * frac[a], sigma[a]) if sigma[a] > 0 else 0.01,
+                               0.02, 9100 + 10 * i + a) for a in range(M)]
+    solid = None
+    if g.uniform() < 0.5:                    # one cuboid obstacle, away from being the whole box
+        lo = [int(g.integers(0, d // 2)) for d in dims]
+        hi = [lo[k] + int(g.integers(1, max(2, dims[k] // 3))) for k in range(3)]
+        z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+        solid = ((x >= lo[0]) & (x < hi[0]) & (y >= lo[1]) & (y < hi[1]) &
+                 (z >= lo[2]) & (z < hi[2])).astype(np.uint8)
+    w = W.Workload(name=f"random{i}", nx=nx, ny=ny, nz=nz, sigma=sigma, periodic=periodic, tau=tau,
+                   steps=3, density=density, V=W.smooth_field(shape, 0.3 * KT, 3, 9200 + i), solid=solid,
+                   body=[list(g.uniform(-2e-4, 2e-4, 3)) for _ in range(M)])
+    return w, flags
+
+
+@pytest.mark.parametrize("i", range(NCASES))
+def test_random_configuration(L, i):
+    w, flags = _case(L, i)
+    banner(f"random case {i}: {w.nx}x{w.ny}x{w.nz} periodic={w.periodic} sigma={w.sigma} "
+           f"tau={w.tau} flags={flags} solid={w.solid is not None}")
+    o = oracle_from_workload(w, flags)
+    b = L.box_from_workload(w, flags=flags)
+    o.step(w.steps)
+    b.step(w.steps)
+    compare_state(o, b, w.nspecies, TOL, f"random {i}")
+    b.close()
