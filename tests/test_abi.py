@@ -60,3 +60,37 @@ def test_adjoint_workspace_and_scope(L):
         assert L.lbe_adjoint_workspace_bytes(C.byref(bad), 10, 5) == 0
     assert b"adjoint" in L.lbe_last_error()
     assert L.lbe_adjoint_workspace_bytes(C.byref(cfg), 0, 5) == 0
+
+
+def test_null_handles_are_rejected_without_touching_the_device(L):
+    """Every entry point that takes a context, batch or adjoint handle returns
+    LBE_ERR_ARG for a null handle (and the destroy calls accept one) before
+    any HIP call, so this runs on a machine with no GPU."""
+    o3 = (C.c_int * 3)(1, 1, 1)
+    g3 = (C.c_double * 3)(0.0, 0.0, 0.0)
+    calls = {
+        "lbe_set_solid": (None, None, 0), "lbe_set_potential": (None, None, 0),
+        "lbe_set_body_force": (None, 0, g3), "lbe_init_density": (None, 0, None, 0),
+        "lbe_step": (None, 1), "lbe_step_phase": (None, 0), "lbe_get_density": (None, 0, None, 0),
+        "lbe_get_velocity": (None, 0, None, 0), "lbe_get_momentum": (None, 0, None, 0),
+        "lbe_get_force": (None, 0, 0, None, 0), "lbe_get_populations": (None, 0, 0, None, 0),
+        "lbe_set_populations": (None, 0, 0, None, 0), "lbe_get_divergence": (None, None, 0),
+        "lbe_get_quasipressure": (None, 0, o3, 0, None, 0), "lbe_init_quasipressure": (None, o3, 0),
+        "lbe_diagnostics": (None, None), "lbe_synchronize": (None,),
+        "lbe_set_force_zchunk": (None, 1), "lbe_set_force_tiling": (None, 1, 0, 0),
+        "lbe_batch_step": (None, 1, 2), "lbe_adjoint_forward": (None,),
+        "lbe_adjoint_backward": (None, None, None, None, 0, None, 0),
+        "lbe_adjoint_state_grad": (None, 0, 0, None, 0),
+        "lbe_adjoint_create": (None, 10, 5, None, 0, C.byref(C.c_void_p())),
+        "lbe_create": (None, None, 0, None, C.byref(C.c_void_p())),
+    }
+    for name, args in calls.items():
+        assert getattr(L, name)(*args) == lbe.LBE_ERR_ARG, name
+    assert L.lbe_batch_box(None, 0) is None
+    L.lbe_destroy(None)
+    L.lbe_batch_destroy(None)
+    L.lbe_adjoint_destroy(None)
+    covered = set(calls) | {"lbe_batch_box", "lbe_destroy", "lbe_batch_destroy", "lbe_adjoint_destroy",
+                            "lbe_workspace_bytes", "lbe_batch_workspace_bytes",
+                            "lbe_adjoint_workspace_bytes", "lbe_last_error", "lbe_batch_create"}
+    assert not set(lbe.declared_symbols()) - covered, set(lbe.declared_symbols()) - covered
