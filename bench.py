@@ -335,9 +335,11 @@ def quasipressure_leg(lbe, torch, w, flags, reps=20):
     }
 
 
-def cpu_baseline(w, flags, budget_s):
+def cpu_baseline(w, flags, budget_s, compare=None):
     """The oracle as it stands, on the host cores, over a bounded number of
-    steps of the same workload from its initial state."""
+    steps of the same workload from its initial state.  After the timing,
+    compare(oracle, steps) may check GPU runs of the same steps against the
+    oracle's state; its result is returned alongside."""
     import oracle
     if not oracle.LIB.exists():
         oracle.build()
@@ -367,10 +369,36 @@ def cpu_baseline(w, flags, budget_s):
             break
     el = time.perf_counter() - t
     mlups = w.nodes * w.nspecies * steps / el / 1e6
+    checked = compare(o, steps) if compare is not None and steps > 0 else None
     o.close()
     return {"value": round(mlups, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"{steps} steps of the same {w.nx}x{w.ny}x{w.nz} workload from its initial "
-                      f"state ({el:.1f} s wall)"}
+                      f"state ({el:.1f} s wall)"}, checked
+
+
+def oracle_comparison(lbe, w, flags):
+    """GPU runs in FP64 and with FP32 populations, from the same initial
+    state and for as many steps as the oracle took, against the oracle:
+    max-norm relative error of n and of the barycentric u, and max |u|."""
+    import numpy as np
+
+    def compare(o, steps):
+        n_ref, u_ref = o.density(0), o.velocity(-1)
+        out = {"steps": steps}
+        for name, prec in (("fp64", lbe.LBE_FP64), ("fp32_pop", lbe.LBE_FP32_POP)):
+            box = lbe.box_from_workload(w, prec=prec, flags=flags)
+            box.step(steps)
+            n, u = box.density(0), box.velocity(-1)
+            box.close()
+            out[name] = {"n_rel_err": float(np.abs(n - n_ref).max() / np.abs(n_ref).max()),
+                         "u_rel_err": float(np.abs(u - u_ref).max() / np.abs(u_ref).max()),
+                         "umax": float(np.sqrt((u ** 2).sum(axis=0)).max())}
+        out["oracle_umax"] = float(np.sqrt((u_ref ** 2).sum(axis=0)).max())
+        log(f"against the oracle after {steps} steps: fp64 n {out['fp64']['n_rel_err']:.2e} "
+            f"u {out['fp64']['u_rel_err']:.2e}; fp32 n {out['fp32_pop']['n_rel_err']:.2e} "
+            f"u {out['fp32_pop']['u_rel_err']:.2e}")
+        return out
+    return compare
 
 
 def main():
@@ -458,8 +486,9 @@ def main():
     qp = None if args.no_quasipressure else quasipressure_leg(lbe, torch, w, flags)
 
     cpu = None
+    parity = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, flags, args.cpu_budget)
+        cpu, parity = cpu_baseline(w, flags, args.cpu_budget, oracle_comparison(lbe, w, flags))
 
     out = {
         "metric": "MLUPS per species + % HBM roofline (FP64 & FP32); batched vs serial; adjoint/fwd",
@@ -489,7 +518,10 @@ def main():
             "ms_per_step": round(r32["total_ms"] / fp32_steps, 4),
             "roofline": dominant(kern32), "kernels": kern32,
             "umax": r32["diag"]["umax"], "unstable": r32["diag"]["unstable"],
+            "vs_oracle": parity and {"steps": parity["steps"], **parity["fp32_pop"]},
         },
+        "vs_oracle": parity and {"steps": parity["steps"], "oracle_umax": parity["oracle_umax"],
+                                 **parity["fp64"]},
         "state_after": {"umax": r64["diag"]["umax"], "unstable": r64["diag"]["unstable"]},
         "batched": batched,
         "variants": variants,
