@@ -179,12 +179,13 @@ def run_gpu(w, prec, flags, steps, warmup, lbe, torch):
     return res
 
 
-def batch_leg(lbe, torch, W, flags, prec, steps, serial_steps, tune=True):
+def batch_leg(lbe, torch, W, flags, prec, steps, serial_steps, tune=True, Lmin=24, Lmax=96):
     """96 independent boxes of uneven sizes and diameters: batched launches
     replayed from a HIP graph against the same boxes stepped one after
-    another with per-box launches."""
+    another with per-box launches.  The specified set has edges 24..96; with
+    smaller edges the per-box launch cost dominates the serial schedule."""
     from paper_1202_3842_amd import autotune
-    ws = W.c4_boxes()
+    ws = W.c4_boxes(Lmin=Lmin, Lmax=Lmax)
     nodes = sum(w.nodes for w in ws)
     batch = lbe.batch_from_workloads(ws, prec=prec, flags=flags)
     if tune:
@@ -209,7 +210,7 @@ def batch_leg(lbe, torch, W, flags, prec, steps, serial_steps, tune=True):
     unstable = sum(1 for b in batch.boxes if b.diagnostics()["unstable"])
     batch.close()
     return {
-        "workload": f"{len(ws)} one-component boxes, edge 24..96, sigma in {{3,4,6}}, "
+        "workload": f"{len(ws)} one-component boxes, edge {Lmin}..{Lmax}, sigma in {{3,4,6}}, "
                     "n sigma^3 in [0.1,0.45], well depth 0.5..3 kT",
         "nodes": nodes, "steps": steps, "serial_steps": serial_steps,
         "ms_per_step": round(t_batch, 4), "serial_ms_per_step": round(t_serial, 4),
@@ -476,6 +477,8 @@ def main():
             "fp64": batch_leg(lbe, torch, W, flags, lbe.LBE_FP64, args.batch_steps, args.batch_steps),
             "fp32_pop": batch_leg(lbe, torch, W, flags, lbe.LBE_FP32_POP, max(args.batch_steps // 5, 10),
                                   max(args.batch_steps // 5, 10)),
+            "fp64_small_boxes": batch_leg(lbe, torch, W, flags, lbe.LBE_FP64, args.batch_steps,
+                                          args.batch_steps, Lmin=8, Lmax=24),
         }
 
     variants = None if args.no_variants else variants_leg(lbe, torch, w, flags, args.variant_steps,
