@@ -54,6 +54,7 @@ class lbeo_config(C.Structure):
         ("periodic", C.c_uint), ("nspecies", C.c_int),
         ("sigma", C.c_double * 4), ("tau", C.c_double), ("kT", C.c_double),
         ("prec", C.c_int), ("flags", C.c_uint),
+        ("att_eps", (C.c_double * 4) * 4), ("att_rc", C.c_double),
     ]
 
 
@@ -187,7 +188,7 @@ class Oracle:
     x + nx*(y + ny*z); numpy arrays shaped (nz, ny, nx) are accepted."""
 
     def __init__(self, nx, ny, nz, sigma, periodic=7, tau=1.0, kT=1.0 / 3.0,
-                 flags=LBEO_VISC):
+                 flags=LBEO_VISC, att_eps=None, att_rc=0.0):
         self.shape = (nz, ny, nx)
         self.N = nx * ny * nz
         self.M = len(sigma)
@@ -201,6 +202,12 @@ class Oracle:
         cfg.kT = kT
         cfg.prec = 0
         cfg.flags = flags
+        if att_eps is not None:
+            e = np.asarray(att_eps, dtype=float)
+            for a in range(self.M):
+                for b in range(self.M):
+                    cfg.att_eps[a][b] = float(e[a, b]) if e.ndim == 2 else float(e)
+        cfg.att_rc = float(att_rc)
         self.cfg = cfg
         h = C.c_void_p()
         _check(lib().lbeo_create(C.byref(cfg), C.byref(h)))

@@ -106,6 +106,56 @@ typedef struct {
   int (*off)[3];
 } ball_t;
 
+/* ------------------------------------------------------------------------ */
+/* Attractive molecular field (Appendix: G^{ab} = -int dr' n_b(r')          */
+/* g_ab(r,r') grad U^{ab}(r - r')).  The paper leaves U^{ab} open; our      */
+/* choice is the attractive r^-6 tail U = -eps (sigma_ab/r)^6 for           */
+/* sigma_ab <= r < rc (0 elsewhere) with g_ab = 1 there (mean field).  On   */
+/* the lattice (dx^3 = 1) with r' = r + e:                                   */
+/*   G^{ab}(r) = sum_e U'(|e|) e^ n_b(r + e),  U'(r) = 6 eps sigma^6 r^-7,   */
+/* over the thick shell sigma_ab <= |e| < rc, summed as +-e pairs over the  */
+/* half S+ so that a uniform state gives exactly zero.                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int nplus;       /* points of S+                                        */
+  int (*off)[3];
+  double (*K)[3];  /* U'(|e|) e^                                           */
+} att_t;
+
+static int build_att(double sab, double eps, double rc, att_t *t) {
+  memset(t, 0, sizeof *t);
+  if (!(eps > 0.0) || !(sab > 0.0) || !(rc > sab)) return 0;
+  int K = (int)ceil(rc);
+  int cap = (2 * K + 1) * (2 * K + 1) * (2 * K + 1);
+  t->off = malloc(sizeof(int[3]) * (size_t)cap);
+  t->K = malloc(sizeof(double[3]) * (size_t)cap);
+  if (!t->off || !t->K) return 1;
+  double s6 = pow(sab, 6.0);
+  for (int z = -K; z <= K; ++z)
+    for (int y = -K; y <= K; ++y)
+      for (int x = -K; x <= K; ++x) {
+        int plus = z != 0 ? z > 0 : (y != 0 ? y > 0 : x > 0);
+        if (!plus) continue;
+        double r = sqrt((double)(x * x + y * y + z * z));
+        if (r < sab || r >= rc) continue;
+        double dU = 6.0 * eps * s6 / pow(r, 7.0);
+        t->off[t->nplus][0] = x;
+        t->off[t->nplus][1] = y;
+        t->off[t->nplus][2] = z;
+        t->K[t->nplus][0] = dU * x / r;
+        t->K[t->nplus][1] = dU * y / r;
+        t->K[t->nplus][2] = dU * z / r;
+        t->nplus++;
+      }
+  return 0;
+}
+
+static void free_att(att_t *t) {
+  free(t->off);
+  free(t->K);
+  memset(t, 0, sizeof *t);
+}
+
 static int in_shell(double sigma, int ex, int ey, int ez) {
   if (ex == 0 && ey == 0 && ez == 0) return 0;
   double r2 = (double)(ex * ex + ey * ey + ez * ez);
@@ -267,6 +317,7 @@ struct lbeo_ctx {
   double *G;                   /* [M][M][N], symmetric                    */
   double *cmf, *cvisc;         /* [M][3][N]                               */
   shell_t shell[MAXM][MAXM];   /* symmetric, [a][b] built for a <= b      */
+  att_t att[MAXM][MAXM];       /* attractive tails, [a][b] for a <= b     */
   hermite_t herm;
   ball_t ball[MAXM];
   int unstable;
@@ -319,7 +370,10 @@ static void free_ctx(lbeo_ctx *c) {
   free(c->cmf);
   free(c->cvisc);
   for (int a = 0; a < MAXM; ++a) {
-    for (int b = a; b < MAXM; ++b) free_shell(&c->shell[a][b]);
+    for (int b = a; b < MAXM; ++b) {
+      free_shell(&c->shell[a][b]);
+      free_att(&c->att[a][b]);
+    }
     free(c->ball[a].off);
   }
   free(c);
@@ -342,6 +396,15 @@ int lbeo_create(const lbeo_config *cfg, lbeo_ctx **out) {
   for (int a = 0; a < cfg->nspecies; ++a)
     if (!(cfg->sigma[a] >= 0.0))
       return fail(LBEO_ERR_ARG, "sigma must be >= 0");
+  for (int a = 0; a < cfg->nspecies; ++a)
+    for (int b = 0; b < cfg->nspecies; ++b) {
+      double e = cfg->att_eps[a][b];
+      if (!(e >= 0.0) || e != cfg->att_eps[b][a])
+        return fail(LBEO_ERR_ARG, "att_eps must be symmetric and >= 0");
+      double sab = 0.5 * (cfg->sigma[a] + cfg->sigma[b]);
+      if (e > 0.0 && !(sab > 0.0 && cfg->att_rc > sab))
+        return fail(LBEO_ERR_ARG, "an attractive pair needs sigma_ab > 0 and att_rc > sigma_ab");
+    }
   lbeo_ctx *c = calloc(1, sizeof *c);
   if (!c) return fail(LBEO_ERR_OOM, "out of memory");
   c->cfg = *cfg;
@@ -379,7 +442,8 @@ int lbeo_create(const lbeo_config *cfg, lbeo_ctx **out) {
   for (int a = 0; a < M; ++a) {
     for (int b = a; b < M; ++b) {
       double sab = 0.5 * (cfg->sigma[a] + cfg->sigma[b]);
-      if (build_shell(sab, &c->shell[a][b])) {
+      if (build_shell(sab, &c->shell[a][b]) ||
+          build_att(sab, cfg->att_eps[a][b], cfg->att_rc, &c->att[a][b])) {
         free_ctx(c);
         return fail(LBEO_ERR_OOM, "out of memory");
       }
@@ -680,6 +744,22 @@ static void compute_forces(lbeo_ctx *c) {
                 mf[k] += -kT * na * sab * sab * s->weight * smf[k];
                 vs[k] += na * cvpref * sab * sab * s->weight * svs[k];
               }
+            }
+            /* attractive molecular field, part of C^mf (Appendix) */
+            for (int b = 0; b < M; ++b) {
+              const att_t *t = a <= b ? &c->att[a][b] : &c->att[b][a];
+              if (t->nplus == 0) continue;
+              const double *nb = c->n + (long)b * N;
+              double Gv[3] = {0, 0, 0};
+              for (int j = 0; j < t->nplus; ++j) {
+                const int *e = t->off[j];
+                long ip = neighbour(c, x, y, z, e[0], e[1], e[2]);
+                long im = neighbour(c, x, y, z, -e[0], -e[1], -e[2]);
+                double d = (is_fluid(c, ip) ? nb[ip] : 0.0) - (is_fluid(c, im) ? nb[im] : 0.0);
+                for (int k = 0; k < 3; ++k) Gv[k] += t->K[j][k] * d;
+              }
+              double na = c->n[(long)a * N + i];
+              for (int k = 0; k < 3; ++k) mf[k] += na * Gv[k];
             }
             /* interspecies drag (Appendix, eq. dragforce2), local */
             if (drag) {

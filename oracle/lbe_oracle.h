@@ -85,6 +85,11 @@ typedef struct {
   double kT;           /* k_B T with m = 1; D3Q19 needs kT = v_T^2 = 1/3     */
   int prec;            /* ignored: the oracle is FP64 throughout             */
   unsigned flags;      /* LBEO_* switches above                              */
+  /* attractive molecular field G^{ab} (Appendix; our choice of U, which the */
+  /* paper leaves open): U^{ab}(r) = -att_eps[a][b] (sigma_ab/r)^6 for        */
+  /* sigma_ab <= r < att_rc, else 0; att_eps symmetric, >= 0 (0 = none)      */
+  double att_eps[4][4];
+  double att_rc;
 } lbeo_config;
 
 typedef struct {
