@@ -336,6 +336,34 @@ def quasipressure_leg(lbe, torch, w, flags, reps=20):
     }
 
 
+def attraction_leg(lbe, torch, w, flags, steps, warmup, base_force_ms):
+    """The benchmark box with the attractive molecular field of the Appendix
+    switched on (the r^-6 tail, eps = kT/4, rc = 8: the thick shell
+    6 <= |e| < 8): step time, and the cost of the extra gather against its
+    LDS and FP64 work (two 8-byte LDS reads and 7 flops per +-e pair and node)."""
+    import copy
+    import numpy as np
+    wa = copy.copy(w)
+    wa.att_eps, wa.att_rc = [[0.25 * w.kT]], 8.0
+    r = run_gpu(wa, lbe.LBE_FP64, flags, steps, warmup, lbe, torch)
+    K = 8
+    g = np.arange(-K, K + 1)
+    d = np.sqrt(g[:, None, None] ** 2 + g[None, :, None] ** 2 + g[None, None, :] ** 2)
+    pairs = int(((d >= w.sigma[0]) & (d < wa.att_rc)).sum()) // 2
+    extra = r["force_ms"] - base_force_ms
+    N = w.nodes
+    out = {"eps_kT": 0.25, "rc": wa.att_rc, "pairs_per_node": pairs, "steps": steps,
+           "ms_per_step": round(r["total_ms"] / steps, 4),
+           "value": round(N * w.nspecies * steps / (r["total_ms"] / 1e3) / 1e6, 2), "unit": "MLUPS",
+           "force_phase_ms": round(r["force_ms"], 4), "attraction_ms": round(extra, 4),
+           "umax": r["diag"]["umax"], "unstable": r["diag"]["unstable"]}
+    if extra > 0:
+        out["attraction_lds_TBps"] = round(N * pairs * 16 / (extra * 1e-3) / 1e12, 2)
+        out["attraction_TFLOPs"] = round(N * pairs * 7 / (extra * 1e-3) / 1e12, 2)
+    log(f"attraction: {out['ms_per_step']:.3f} ms/step, gather {extra:.3f} ms ({pairs} pairs/node)")
+    return out
+
+
 def cpu_baseline(w, flags, budget_s, compare=None):
     """The oracle as it stands, on the host cores, over a bounded number of
     steps of the same workload from its initial state.  After the timing,
@@ -415,6 +443,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-quasipressure", action="store_true")
+    ap.add_argument("--no-attraction", action="store_true")
     ap.add_argument("--quasipressure-only", action="store_true",
                     help="run only the quasi-pressure leg and print its JSON (for profiling)")
     ap.add_argument("--variant-steps", type=int, default=300)
@@ -488,6 +517,9 @@ def main():
 
     qp = None if args.no_quasipressure else quasipressure_leg(lbe, torch, w, flags)
 
+    att = None if args.no_attraction else attraction_leg(lbe, torch, w, flags, args.variant_steps,
+                                                          args.warmup, r64["force_ms"])
+
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
@@ -530,6 +562,7 @@ def main():
         "variants": variants,
         "adjoint": adjoint,
         "quasipressure": qp,
+        "attraction": att,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

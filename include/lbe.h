@@ -122,6 +122,18 @@ typedef struct {
   double kT;              /* must be 1/3 (v_T^2 of D3Q19, m = 1)             */
   lbe_precision prec;     /* population storage                              */
   unsigned flags;         /* LBE_* switches                                  */
+  /* Attractive molecular field G^{ab} of the Appendix (the last term of
+   * C^{a,mf}).  The paper leaves U^{ab} open; this library takes the
+   * attractive r^-6 tail U^{ab}(r) = -att_eps[a][b] (sigma_ab/r)^6 on
+   * sigma_ab <= r < att_rc (0 elsewhere) with g_ab = 1 there, so that
+   * G^{ab}(r) = sum_e U'(|e|) e^ n_b(r + e) over the lattice points of that
+   * range, and C^{a,mf} gains n_a sum_b G^{ab}.  att_eps in energy units
+   * (kT = 1/3), symmetric, >= 0; all zero = no attraction.  A pair with
+   * att_eps > 0 needs sigma_ab > 0 and sigma_ab < att_rc, and the points
+   * must reach at most 8 nodes per axis (att_rc <= 9).  Not with LBE_IDEAL
+   * (which drops every nonlocal force), batched boxes or the adjoint. */
+  double att_eps[4][4];
+  double att_rc;
 } lbe_config;
 
 typedef struct {

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "lbe_host.hpp"
@@ -77,6 +78,31 @@ std::vector<int> make_ball(double sigma, int *maxc) {
   return b;
 }
 
+// attractive tail of one pair (see HostAtt): U'(r) = 6 eps sigma^6 r^-7
+HostAtt make_att(double sab, double eps, double rc) {
+  HostAtt h;
+  if (!(eps > 0.0) || !(sab > 0.0) || !(rc > sab)) return h;
+  int K = (int)ceil(rc);
+  double s6 = pow(sab, 6.0);
+  for (int z = -K; z <= K; ++z)
+    for (int y = -K; y <= K; ++y)
+      for (int x = -K; x <= K; ++x) {
+        bool plus = z != 0 ? z > 0 : (y != 0 ? y > 0 : x > 0);
+        if (!plus) continue;
+        double r = sqrt((double)(x * x + y * y + z * z));
+        if (r < sab || r >= rc) continue;
+        double dU = 6.0 * eps * s6 / pow(r, 7.0);
+        h.maxc = std::max(h.maxc, std::max(abs(x), std::max(abs(y), abs(z))));
+        h.e.push_back(x);
+        h.e.push_back(y);
+        h.e.push_back(z);
+        h.K.push_back(dU * x / r);
+        h.K.push_back(dU * y / r);
+        h.K.push_back(dU * z / r);
+      }
+  return h;
+}
+
 }  // namespace
 
 namespace lbe {
@@ -97,18 +123,38 @@ lbe_status make_plan(const lbe_config *cfg, Plan &pl) {
     if (cfg->sigma[a] > (double)RING_MAX)
       return fail(LBE_ERR_UNSUPPORTED, "sigma above %d lattice units is not built", RING_MAX);
   }
+  for (int a = 0; a < cfg->nspecies; ++a)
+    for (int b = 0; b < cfg->nspecies; ++b) {
+      const double e = cfg->att_eps[a][b];
+      if (!(e >= 0.0) || e != cfg->att_eps[b][a] || !std::isfinite(e))
+        return fail(LBE_ERR_ARG, "att_eps must be symmetric, finite and >= 0");
+      const double sab = 0.5 * (cfg->sigma[a] + cfg->sigma[b]);
+      if (e > 0.0 && !(sab > 0.0 && cfg->att_rc > sab))
+        return fail(LBE_ERR_ARG, "an attractive pair needs sigma_ab > 0 and att_rc > sigma_ab");
+      if (e > 0.0 && (cfg->flags & LBE_IDEAL))
+        return fail(LBE_ERR_ARG, "LBE_IDEAL drops the attractive field");
+    }
   pl.M = cfg->nspecies;
   pl.npairs = pl.M * (pl.M + 1) / 2;
   int R = 0;
   pl.shells.clear();
+  pl.atts.clear();
   pl.balls.clear();
-  pl.nshell = pl.nball = 0;
+  pl.nshell = pl.nball = pl.natt = 0;
   for (int a = 0; a < pl.M; ++a)
     for (int b = a; b < pl.M; ++b) {
-      HostShell h = make_shell(0.5 * (cfg->sigma[a] + cfg->sigma[b]));
+      const double sab = 0.5 * (cfg->sigma[a] + cfg->sigma[b]);
+      HostShell h = make_shell(sab);
       R = std::max(R, h.maxc);
       pl.nshell += (int)h.e.size() / 3;
       pl.shells.push_back(std::move(h));
+      HostAtt t = make_att(sab, cfg->att_eps[a][b], cfg->att_rc);
+      if (t.maxc > RING_MAX)
+        return fail(LBE_ERR_UNSUPPORTED, "att_rc reaches %d nodes per axis; at most %d are built", t.maxc,
+                    RING_MAX);
+      R = std::max(R, t.maxc);
+      pl.natt += (int)t.e.size() / 3;
+      pl.atts.push_back(std::move(t));
     }
   for (int a = 0; a < pl.M; ++a) {
     int mc = 0;
@@ -146,8 +192,9 @@ lbe_status make_plan(const lbe_config *cfg, Plan &pl) {
   pl.off_flag = take(64);
   pl.off_result = take(sizeof(double) * 16);
   pl.off_ring_ofs = take(sizeof(int) * (RING_MAX + 2) * MAXPAIRS);
-  pl.off_ring_off = take(sizeof(int) * std::max(pl.nshell, 1));
-  pl.off_ring_e = take(sizeof(double) * 3 * std::max(pl.nshell, 1));
+  pl.off_ring_off = take(sizeof(int) * std::max(pl.nshell + pl.natt, 1));
+  pl.off_ring_e = take(sizeof(double) * 3 * std::max(pl.nshell + pl.natt, 1));
+  pl.off_att_ofs = take(sizeof(int) * (RING_MAX + 2) * MAXPAIRS);
   pl.off_ball = take(sizeof(int) * 2 * std::max(pl.nball, 1));
   pl.off_bb = take(sizeof(uint32_t) * g.N);
   pl.off_V = take(sizeof(double) * g.N);
@@ -246,6 +293,31 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
       for (int ez = R + 2; ez <= RING_MAX + 1; ++ez) ofs[ez] = (int)roff.size();
       a.t.pair_nent[idx] = (int)np;
     }
+  // the attractive tails, after all shells, in the same ring layout
+  std::vector<int> arofs((RING_MAX + 2) * MAXPAIRS, 0);
+  k = 0;
+  for (int pa = 0; pa < P.M; ++pa)
+    for (int pb = pa; pb < P.M; ++pb, ++k) {
+      const HostAtt &h = P.atts[k];
+      int idx = pair_index(P.M, pa, pb);
+      int R = h.maxc;
+      int W = FORCE_TX + 2 * R;
+      size_t np = h.e.size() / 3;
+      a.t.att_R[idx] = np ? R : 0;
+      a.t.att_nent[idx] = (int)np;
+      int *ofs = &arofs[idx * (RING_MAX + 2)];
+      size_t j = 0;
+      for (int ez = 0; ez <= RING_MAX + 1; ++ez) {
+        ofs[ez] = (int)roff.size();
+        while (j < np && h.e[3 * j + 2] == ez) {
+          roff.push_back(h.e[3 * j + 1] * W + h.e[3 * j]);
+          reh.push_back(h.K[3 * j]);
+          reh.push_back(h.K[3 * j + 1]);
+          reh.push_back(h.K[3 * j + 2]);
+          ++j;
+        }
+      }
+    }
   std::vector<int> boff, bloff;
   int bR = 0;
   for (int s = 0; s < P.M; ++s)
@@ -268,6 +340,7 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
   a.t.ring_ofs = c->at<int>(P.off_ring_ofs);
   a.t.ring_off = c->at<int>(P.off_ring_off);
   a.t.ring_e = c->at<double>(P.off_ring_e);
+  a.t.att_ring_ofs = c->at<int>(P.off_att_ofs);
   a.force = c->at<double>(P.off_force);
   a.t.ball_off = c->at<int>(P.off_ball);
   a.t.ball_loff = a.t.ball_off + a.t.ball_total;
@@ -300,6 +373,7 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
       !upload(P.off_ring_ofs, rofs.data(), rofs.size() * sizeof(int)) ||
       !upload(P.off_ring_off, roff.data(), roff.size() * sizeof(int)) ||
       !upload(P.off_ring_e, reh.data(), reh.size() * sizeof(double)) ||
+      !upload(P.off_att_ofs, arofs.data(), arofs.size() * sizeof(int)) ||
       !upload(P.off_ball, boff.data(), boff.size() * sizeof(int)))
     rs = fail(LBE_ERR_HIP, "workspace initialisation failed");
   if (rs == LBE_OK) {
@@ -697,6 +771,8 @@ lbe_status make_batch_plan(const lbe_config *cfgs, int nboxes, BatchPlan &bp) {
     lbe_status st = make_plan(&cfgs[b], plans[b]);
     if (st != LBE_OK) return fail(st, "box %d: %s", b, error_text());
     if (cfgs[b].nspecies != 1) return fail(LBE_ERR_UNSUPPORTED, "batched boxes must have one species");
+    if (cfgs[b].att_eps[0][0] > 0.0)
+      return fail(LBE_ERR_UNSUPPORTED, "batched boxes do not take the attractive field");
     if (cfgs[b].prec != cfgs[0].prec || cfgs[b].flags != cfgs[0].flags)
       return fail(LBE_ERR_ARG, "batched boxes must share precision and flags");
   }

@@ -44,18 +44,28 @@ struct HostShell {
   int maxc = 0;
 };
 
+// Attractive tail of a pair: the half S+ of the thick shell sigma_ab <= |e|
+// < rc, grouped by e_z, with K = U'(|e|) e^ per point for U = -eps
+// (sigma_ab/r)^6.
+struct HostAtt {
+  std::vector<int> e;     // 3 per point of S+, ordered by e_z, then e_y, then e_x
+  std::vector<double> K;  // 3 per point
+  int maxc = 0;
+};
+
 struct Plan {
   Geom g;
   int M = 0, npairs = 0;
   long long Ns = 0;
   size_t pop_bytes = 0;  // one ping-pong buffer
   std::vector<HostShell> shells;
+  std::vector<HostAtt> atts;  // one per unordered pair, empty without attraction
   std::vector<std::vector<int>> balls;
-  int nshell = 0, nball = 0;
+  int nshell = 0, nball = 0, natt = 0;
   size_t off_flag = 0, off_result = 0, off_ring_ofs = 0, off_ring_off = 0, off_ring_e = 0,
          off_ball = 0, off_bb = 0, off_V = 0, off_F = 0, off_solid = 0, off_pop0 = 0,
          off_pop1 = 0, off_n = 0, off_G = 0, off_J = 0, off_force = 0, off_read = 0,
-         off_part = 0, total = 0;
+         off_part = 0, off_att_ofs = 0, total = 0;
   int nblocks = 0;
 };
 

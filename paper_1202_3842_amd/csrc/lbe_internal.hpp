@@ -64,6 +64,13 @@ struct Tables {
   int ball_start[MAXM];
   int ball_n[MAXM];
   double sigma[MAXM];
+  // attractive tails: per pair, the half thick shell sigma_ab <= |e| < rc in
+  // the same ring layout (offsets for a window of FORCE_TX + 2 att_R[k]
+  // columns) inside ring_off / ring_e, whose 3 doubles per point are here
+  // U'(|e|) e^ instead of a unit vector
+  const int *att_ring_ofs;     // (RING_MAX + 2) per pair
+  int att_R[MAXPAIRS];         // 0 = no attraction for the pair
+  int att_nent[MAXPAIRS];
 };
 
 struct alignas(8) StepArgs {

@@ -474,18 +474,22 @@ __global__ __launch_bounds__(BLOCK) void k_ball(StepArgs a, AdjArgs d) {
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 // where force_body reads its ring table from (see there): scalar loads for
-// C^visc and for the adjoint gather, LDS for C^mf alone
-__host__ __device__ constexpr bool table_in_smem(int mode) { return mode != 0; }
+// C^visc and for the adjoint gather, LDS for C^mf alone and the attraction
+__host__ __device__ constexpr bool table_in_smem(int mode) { return mode == 1 || mode == 2; }
+// fields staged per plane by force_body
+__host__ __device__ constexpr int force_fields(int mode) { return mode == 0 ? 2 : (mode == 3 ? 1 : 5); }
 // dynamic LDS of force_body: two planes of NF fields, then the ring table
 // when it is staged in LDS
 __host__ __device__ constexpr size_t force_lds(int mode, int R, int ty, int entries) {
-  return sizeof(double) * ((size_t)2 * (mode == 0 ? 2 : 5) * (FTX + 2 * R) * (ty + 2 * R) +
+  return sizeof(double) * ((size_t)2 * force_fields(mode) * (FTX + 2 * R) * (ty + 2 * R) +
                            (table_in_smem(mode) ? 0 : 4 * (size_t)entries));
 }
 
 // MODE 0: C^mf; MODE 1: C^mf and C^visc; MODE 2: the transpose of the C^mf
 // gather for the adjoint (fields n_b, G_ab and the adjoint force phi_a^bar,
-// see k_adj_force).  NT threads in rows of FTX; NY = output rows per thread:
+// see k_adj_force); MODE 3: the attractive field G^{ab} = sum_e U'(|e|) e^
+// n_b(r + e) over the pair's thick shell (field n_b; the table holds
+// U'(|e|) e^), added to C^mf/n_a.  NT threads in rows of FTX; NY = output rows per thread:
 // the tile is FTX x (NT/FTX NY) and thread (tx, ty) owns rows ty,
 // ty + NT/FTX, ...; one ring-table read and one address then serve NY nodes.
 // Taller tiles shrink the staged window per node.
@@ -494,7 +498,8 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
                                   int bx, int by, int bz, double *lds) {
   constexpr bool VISC = MODE == 1;
   constexpr bool ADJ = MODE == 2;
-  constexpr int NF = MODE == 0 ? 2 : 5;
+  constexpr bool ATT = MODE == 3;
+  constexpr int NF = force_fields(MODE);
   constexpr int RY = NT / FTX;                  // thread rows of the workgroup
   constexpr int TY = RY * NY;
   constexpr int W = FTX + 2 * R, H = TY + 2 * R, WH = W * H;
@@ -509,7 +514,7 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   // point's n and G come in with one 16-byte read; otherwise one array per
   // field.  The separate arrays are faster with C^visc, the interleaved ones
   // for C^mf alone and for the adjoint gather (measured).
-  constexpr bool PAIRED = MODE != 1;
+  constexpr bool PAIRED = MODE == 0 || MODE == 2;
   auto at = [&](int f, int e) {
     return PAIRED ? (f < 2 ? 2 * e + f : (f < 4 ? 2 * WH + 2 * e + (f - 2) : 4 * WH + e)) : f * WH + e;
   };
@@ -531,7 +536,7 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
     fld[3] = fld[2] + g.Np;
     fld[4] = fld[3] + g.Np;
   }
-  const auto *ofs = cptr(a.t.ring_ofs + k * (RING_MAX + 2));
+  const auto *ofs = cptr((ATT ? a.t.att_ring_ofs : a.t.ring_ofs) + k * (RING_MAX + 2));
   const auto *roff = cptr(a.t.ring_off);
   const auto *re = cptr(a.t.ring_e);
   const double cmf = a.t.pair_cmf[k], cvs = a.t.pair_cvisc[k];
@@ -625,7 +630,7 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
 #pragma unroll
         for (int c = 0; c < NS; ++c) mx[jn][c] = my[jn][c] = mz[jn][c] = vx[jn][c] = vy[jn][c] = vz[jn][c] = 0.0;
         const int bj = base + jn * ROW;
-        G0[jn] = Bp[at(1, bj)];
+        G0[jn] = ATT ? 0.0 : Bp[at(1, bj)];
         n0[jn] = Bp[at(0, bj)];
         u0x[jn] = u0y[jn] = u0z[jn] = 0.0;
         if (VISC && n0[jn] != 0.0) {
@@ -668,6 +673,9 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
             vp = *reinterpret_cast<const dbl2 *>(Bp + 2 * WH + 2 * qa);
             vm = *reinterpret_cast<const dbl2 *>(Bm + 2 * WH + 2 * qb);
           }
+        } else if (ATT) {
+          ap = dbl2{Bp[qa], 0.0};
+          am = dbl2{Bm[qb], 0.0};
         } else {
           ap = dbl2{Bp[qa], Bp[WH + qa]};
           am = dbl2{Bm[qb], Bm[WH + qb]};
@@ -681,7 +689,13 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
           vmz = Bm[4 * WH + qb];
         }
         const double npl = ap.x, nmi = am.x;
-        if (ADJ) {
+        if (ATT) {
+          // the table holds U'(|e|) e^; the pair adds K.(n_b(r+e) - n_b(r-e))
+          const double dn = npl - nmi;
+          mx[jn][c] += e0 * dn;
+          my[jn][c] += e1 * dn;
+          mz[jn][c] += e2 * dn;
+        } else if (ADJ) {
           // m: sum_S e^ n_b(r+e); v: sum_S e^.phibar(r+e) and
           // sum_S (e^.phibar(r+e)) G(r+e), over both points of the pair
           const double tp = e0 * vp.x + e1 * vp.y + e2 * vpz;
@@ -735,6 +749,21 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
           double *pn = ad->nbar + beta * N + i, *pg = ad->Gbar + k * N + i;
           *pn = (accumulate & 1) ? *pn + vn : vn;
           *pg = (accumulate & 2) ? *pg + vg : vg;
+        } else if (ATT) {
+          // G^{ab} is a force per particle of species a: into C^mf/n_a
+          double *F = a.force + 6LL * alpha * N + i;
+          if (accumulate) {
+            F[0] += Mx;
+            F[N] += My;
+            F[2 * N] += Mz;
+          } else {
+            F[0] = Mx;
+            F[N] = My;
+            F[2 * N] = Mz;
+            F[3 * N] = 0.0;
+            F[4 * N] = 0.0;
+            F[5 * N] = 0.0;
+          }
         } else {
           double *F = a.force + 6LL * alpha * N + i;
           if (accumulate) {
@@ -794,6 +823,14 @@ __global__ __launch_bounds__(NT) void k_force(StepArgs a, int alpha, int beta, i
   extern __shared__ double lds[];
   const Tile T = force_tile(a.g, a.zchunk, a.order, NT / FTX * NY);
   force_body<R, VISC ? 1 : 0, NY, NT>(a, nullptr, alpha, beta, accumulate, T.bx, T.by, T.bz, lds);
+}
+
+// the attractive field of the directed pair (alpha, beta), added to C^mf/n_alpha
+template <int R>
+__global__ __launch_bounds__(FNT) void k_force_att(StepArgs a, int alpha, int beta, int accumulate) {
+  extern __shared__ double lds[];
+  const Tile T = force_tile(a.g, a.zchunk, a.order, FTY);
+  force_body<R, 3, 1, FNT>(a, nullptr, alpha, beta, accumulate, T.bx, T.by, T.bz, lds);
 }
 
 // per-particle forces of species s at node i, times n_s
@@ -1862,6 +1899,33 @@ static void force_r(int R, const StepArgs &a, int alpha, int beta, int acc, hipS
   }
 }
 
+template <int R>
+static void att_launch(const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
+  const int k = pair_index(a.M, alpha, beta);
+  const size_t bytes = force_lds(3, R, FTY, a.t.att_nent[k]);
+  static size_t attr = 0;
+  if (bytes > attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_force_att<R>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    attr = bytes;
+  }
+  hipLaunchKernelGGL((k_force_att<R>), dim3(force_blocks(a.g, a.zchunk, FTY)), dim3(FNT), bytes, s, a, alpha,
+                     beta, acc);
+}
+
+static void att_r(int R, const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
+  switch (R) {
+    case 1: att_launch<1>(a, alpha, beta, acc, s); break;
+    case 2: att_launch<2>(a, alpha, beta, acc, s); break;
+    case 3: att_launch<3>(a, alpha, beta, acc, s); break;
+    case 4: att_launch<4>(a, alpha, beta, acc, s); break;
+    case 5: att_launch<5>(a, alpha, beta, acc, s); break;
+    case 6: att_launch<6>(a, alpha, beta, acc, s); break;
+    case 7: att_launch<7>(a, alpha, beta, acc, s); break;
+    default: att_launch<8>(a, alpha, beta, acc, s); break;
+  }
+}
+
 void launch_forces(const StepArgs &a, hipStream_t s) {
   if (a.flags & LBE_IDEAL) return;  // the force buffer stays zero
   bool visc = (a.flags & LBE_VISC) != 0;
@@ -1874,6 +1938,13 @@ void launch_forces(const StepArgs &a, hipStream_t s) {
         force_r<true>(R, a, al, be, written, s);
       else
         force_r<false>(R, a, al, be, written, s);
+      written = 1;
+    }
+    // the attractive field of every pair with one (Appendix, part of C^mf)
+    for (int be = 0; be < a.M; ++be) {
+      int R = a.t.att_R[pair_index(a.M, al, be)];
+      if (R == 0) continue;
+      att_r(R, a, al, be, written, s);
       written = 1;
     }
   }

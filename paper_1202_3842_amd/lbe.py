@@ -47,6 +47,7 @@ class lbe_config(C.Structure):
         ("periodic", C.c_uint), ("nspecies", C.c_int),
         ("sigma", C.c_double * 4), ("tau", C.c_double), ("kT", C.c_double),
         ("prec", C.c_int), ("flags", C.c_uint),
+        ("att_eps", (C.c_double * 4) * 4), ("att_rc", C.c_double),
     ]
 
 
@@ -133,7 +134,9 @@ def _check(st: int):
 
 
 def make_config(nx, ny, nz, sigma: Sequence[float], periodic=7, tau=1.0, kT=1.0 / 3.0,
-                prec=LBE_FP64, flags=LBE_VISC) -> lbe_config:
+                prec=LBE_FP64, flags=LBE_VISC, att_eps=None, att_rc=0.0) -> lbe_config:
+    """att_eps: M x M symmetric depths of the attractive tail (a scalar is
+    taken for every pair), att_rc: its cutoff; see lbe_config in lbe.h."""
     cfg = lbe_config()
     cfg.nx, cfg.ny, cfg.nz = int(nx), int(ny), int(nz)
     cfg.periodic = int(periodic)
@@ -144,6 +147,12 @@ def make_config(nx, ny, nz, sigma: Sequence[float], periodic=7, tau=1.0, kT=1.0 
     cfg.kT = float(kT)
     cfg.prec = int(prec)
     cfg.flags = int(flags)
+    if att_eps is not None:
+        e = np.asarray(att_eps, dtype=float)
+        for a in range(len(sigma)):
+            for b in range(len(sigma)):
+                cfg.att_eps[a][b] = float(e[a, b]) if e.ndim == 2 else float(e)
+    cfg.att_rc = float(att_rc)
     return cfg
 
 
@@ -163,10 +172,10 @@ class Box:
     """
 
     def __init__(self, nx, ny, nz, sigma, periodic=7, tau=1.0, kT=1.0 / 3.0,
-                 prec=LBE_FP64, flags=LBE_VISC, stream=None, _member=None):
+                 prec=LBE_FP64, flags=LBE_VISC, stream=None, _member=None, att_eps=None, att_rc=0.0):
         import torch
         self.torch = torch
-        self.cfg = make_config(nx, ny, nz, sigma, periodic, tau, kT, prec, flags)
+        self.cfg = make_config(nx, ny, nz, sigma, periodic, tau, kT, prec, flags, att_eps, att_rc)
         self.shape = (nz, ny, nx)
         self.N = nx * ny * nz
         self.M = len(sigma)
@@ -319,7 +328,7 @@ class Box:
 def box_from_workload(w, prec=LBE_FP64, flags=LBE_VISC) -> Box:
     """Create a Box and load a paper_1202_3842_amd.workloads.Workload into it."""
     b = Box(w.nx, w.ny, w.nz, w.sigma, periodic=w.periodic, tau=w.tau, kT=w.kT,
-            prec=prec, flags=flags)
+            prec=prec, flags=flags, att_eps=getattr(w, "att_eps", None), att_rc=getattr(w, "att_rc", 0.0))
     if w.solid is not None:
         b.set_solid(w.solid)
     if w.V is not None:

@@ -37,6 +37,8 @@ class Workload:
     V: Optional[np.ndarray] = None
     solid: Optional[np.ndarray] = None
     body: List[List[float]] = field(default_factory=list)
+    att_eps: Optional[list] = None      # attractive tail depths (M x M), None = none
+    att_rc: float = 0.0                 # its cutoff
 
     @property
     def shape(self):

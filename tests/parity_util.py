@@ -16,7 +16,8 @@ def banner(msg: str) -> None:
 
 def oracle_from_workload(w: W.Workload, flags: int):
     import oracle
-    o = oracle.Oracle(w.nx, w.ny, w.nz, w.sigma, periodic=w.periodic, tau=w.tau, kT=w.kT, flags=flags)
+    o = oracle.Oracle(w.nx, w.ny, w.nz, w.sigma, periodic=w.periodic, tau=w.tau, kT=w.kT, flags=flags,
+                      att_eps=w.att_eps, att_rc=w.att_rc)
     if w.solid is not None:
         o.set_solid(w.solid)
     if w.V is not None:

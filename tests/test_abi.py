@@ -94,3 +94,29 @@ def test_null_handles_are_rejected_without_touching_the_device(L):
                             "lbe_workspace_bytes", "lbe_batch_workspace_bytes",
                             "lbe_adjoint_workspace_bytes", "lbe_last_error", "lbe_batch_create"}
     assert not set(lbe.declared_symbols()) - covered, set(lbe.declared_symbols()) - covered
+
+
+def test_attraction_configuration_is_validated(L):
+    """The attractive tail's parameters (lbe_config.att_eps, att_rc): the
+    interaction range grows with att_rc, and bad values are refused before
+    any device work."""
+    base = lbe.workspace_bytes(lbe.make_config(32, 32, 32, [4.0]))
+    with_att = lbe.workspace_bytes(lbe.make_config(32, 32, 32, [4.0], att_eps=0.2, att_rc=8.0))
+    assert with_att > base                     # wider ghost layers of the fields
+    bad = [
+        (lbe.make_config(16, 16, 16, [2.0, 3.0], att_eps=[[0.1, 0.2], [0.1, 0.1]], att_rc=5.0), b"symmetric"),
+        (lbe.make_config(16, 16, 16, [2.0], att_eps=-0.1, att_rc=5.0), b"symmetric"),
+        (lbe.make_config(16, 16, 16, [4.0], att_eps=0.1, att_rc=4.0), b"att_rc"),
+        (lbe.make_config(32, 32, 32, [4.0], att_eps=0.1, att_rc=9.5), b"att_rc"),
+        (lbe.make_config(16, 16, 16, [2.0], att_eps=0.1, att_rc=5.0, flags=lbe.LBE_IDEAL), b"IDEAL"),
+    ]
+    for cfg, word in bad:
+        with pytest.raises(lbe.LBEError):
+            lbe.workspace_bytes(cfg)
+        assert word in L.lbe_last_error(), L.lbe_last_error()
+    ok = lbe.make_config(16, 16, 16, [2.0], att_eps=0.1, att_rc=5.0, flags=0)
+    assert L.lbe_adjoint_workspace_bytes(C.byref(ok), 10, 5) == 0
+    assert b"attractive" in L.lbe_last_error()
+    arr = (lbe.lbe_config * 1)(ok)
+    assert L.lbe_batch_workspace_bytes(arr, 1) == 0
+    assert b"attractive" in L.lbe_last_error()
