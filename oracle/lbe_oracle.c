@@ -404,6 +404,8 @@ int lbeo_create(const lbeo_config *cfg, lbeo_ctx **out) {
       double sab = 0.5 * (cfg->sigma[a] + cfg->sigma[b]);
       if (e > 0.0 && !(sab > 0.0 && cfg->att_rc > sab))
         return fail(LBEO_ERR_ARG, "an attractive pair needs sigma_ab > 0 and att_rc > sigma_ab");
+      if (e > 0.0 && (cfg->flags & LBEO_IDEAL))
+        return fail(LBEO_ERR_ARG, "LBEO_IDEAL drops the attractive field");
     }
   lbeo_ctx *c = calloc(1, sizeof *c);
   if (!c) return fail(LBEO_ERR_OOM, "out of memory");

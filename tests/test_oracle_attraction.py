@@ -123,3 +123,5 @@ def test_attraction_arguments(oracle_lib):
         _oracle(oracle_lib, (8, 8, 8), [2.0], [[-0.1]], 5.0)                      # negative
     with pytest.raises(oracle_lib.OracleError):
         _oracle(oracle_lib, (8, 8, 8), [4.0], [[0.1]], 3.0)                       # rc <= sigma
+    with pytest.raises(oracle_lib.OracleError):
+        _oracle(oracle_lib, (8, 8, 8), [2.0], [[0.1]], 5.0, flags=oracle_lib.LBEO_IDEAL)
