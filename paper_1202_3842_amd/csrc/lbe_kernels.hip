@@ -474,8 +474,9 @@ __global__ __launch_bounds__(BLOCK) void k_ball(StepArgs a, AdjArgs d) {
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 // where force_body reads its ring table from (see there): scalar loads for
-// C^visc and for the adjoint gather, LDS for C^mf alone and the attraction
-__host__ __device__ constexpr bool table_in_smem(int mode) { return mode == 1 || mode == 2; }
+// C^visc, the adjoint gather and the attraction (two rows per thread), LDS
+// for C^mf alone
+__host__ __device__ constexpr bool table_in_smem(int mode) { return mode != 0; }
 // fields staged per plane by force_body
 __host__ __device__ constexpr int force_fields(int mode) { return mode == 0 ? 2 : (mode == 3 ? 1 : 5); }
 // dynamic LDS of force_body: two planes of NF fields, then the ring table
@@ -553,11 +554,12 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   // this pair's ring table ({e^, offset} per point; the ring offsets are
   // e_y*W_k + e_x for a window of FORCE_TX + 2R columns).  The point index is
   // the same in every lane.  With C^visc and in the adjoint (ten gathers per
-  // pair) the entries come in through scalar loads into SGPRs and cost no LDS
-  // bandwidth (a broadcast LDS read of the 32-byte entry costs as much LDS
-  // return bandwidth as four gathers of one field).  For C^mf alone (four
-  // gathers per pair) the wait on each scalar load is exposed, so the table
-  // is staged once in LDS behind the plane buffers instead.
+  // pair), and for the attraction (two rows of two gathers), the entries come
+  // in through scalar loads into SGPRs and cost no LDS bandwidth (a broadcast
+  // LDS read of the 32-byte entry costs as much LDS return bandwidth as four
+  // gathers of one field).  For C^mf alone (four gathers per pair) the wait
+  // on each scalar load is exposed, so the table is staged once in LDS
+  // behind the plane buffers instead.
   constexpr bool STAB = table_in_smem(MODE);
   int rofs[R + 2];
 #pragma unroll
@@ -825,12 +827,18 @@ __global__ __launch_bounds__(NT) void k_force(StepArgs a, int alpha, int beta, i
   force_body<R, VISC ? 1 : 0, NY, NT>(a, nullptr, alpha, beta, accumulate, T.bx, T.by, T.bz, lds);
 }
 
-// the attractive field of the directed pair (alpha, beta), added to C^mf/n_alpha
+// the attractive field of the directed pair (alpha, beta), added to C^mf/n_alpha.
+// Two gathers per pair and row: the table entry comes through scalar loads
+// (no LDS traffic), and two output rows per thread (a 32 x 16 tile) give each
+// entry four gathers to hide its load behind.  At 128^3 with 604 pairs per
+// node: 0.755 ms with an LDS table and one row, 0.59 ms with two rows, 0.35 ms
+// with two rows and scalar loads.
+constexpr int ATT_NY = 2, ATT_TY = FNT / FTX * ATT_NY;
 template <int R>
 __global__ __launch_bounds__(FNT) void k_force_att(StepArgs a, int alpha, int beta, int accumulate) {
   extern __shared__ double lds[];
-  const Tile T = force_tile(a.g, a.zchunk, a.order, FTY);
-  force_body<R, 3, 1, FNT>(a, nullptr, alpha, beta, accumulate, T.bx, T.by, T.bz, lds);
+  const Tile T = force_tile(a.g, a.zchunk, a.order, ATT_TY);
+  force_body<R, 3, ATT_NY, FNT>(a, nullptr, alpha, beta, accumulate, T.bx, T.by, T.bz, lds);
 }
 
 // per-particle forces of species s at node i, times n_s
@@ -1902,15 +1910,15 @@ static void force_r(int R, const StepArgs &a, int alpha, int beta, int acc, hipS
 template <int R>
 static void att_launch(const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
   const int k = pair_index(a.M, alpha, beta);
-  const size_t bytes = force_lds(3, R, FTY, a.t.att_nent[k]);
+  const size_t bytes = force_lds(3, R, ATT_TY, a.t.att_nent[k]);
   static size_t attr = 0;
   if (bytes > attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_force_att<R>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     attr = bytes;
   }
-  hipLaunchKernelGGL((k_force_att<R>), dim3(force_blocks(a.g, a.zchunk, FTY)), dim3(FNT), bytes, s, a, alpha,
-                     beta, acc);
+  hipLaunchKernelGGL((k_force_att<R>), dim3(force_blocks(a.g, a.zchunk, ATT_TY)), dim3(FNT), bytes, s, a,
+                     alpha, beta, acc);
 }
 
 static void att_r(int R, const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
