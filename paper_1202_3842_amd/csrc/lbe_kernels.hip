@@ -474,16 +474,16 @@ __global__ __launch_bounds__(BLOCK) void k_ball(StepArgs a, AdjArgs d) {
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 // where force_body reads its ring table from (see there): scalar loads for
-// C^visc, the adjoint gather and the attraction (two rows per thread), LDS
-// for C^mf alone
-__host__ __device__ constexpr bool table_in_smem(int mode) { return mode != 0; }
+// C^visc, the adjoint gather, the attraction and any tile with two rows per
+// thread; LDS for C^mf alone with one row per thread
+__host__ __device__ constexpr bool table_in_smem(int mode, int ny = 1) { return mode != 0 || ny > 1; }
 // fields staged per plane by force_body
 __host__ __device__ constexpr int force_fields(int mode) { return mode == 0 ? 2 : (mode == 3 ? 1 : 5); }
 // dynamic LDS of force_body: two planes of NF fields, then the ring table
 // when it is staged in LDS
-__host__ __device__ constexpr size_t force_lds(int mode, int R, int ty, int entries) {
+__host__ __device__ constexpr size_t force_lds(int mode, int R, int ty, int entries, int ny = 1) {
   return sizeof(double) * ((size_t)2 * force_fields(mode) * (FTX + 2 * R) * (ty + 2 * R) +
-                           (table_in_smem(mode) ? 0 : 4 * (size_t)entries));
+                           (table_in_smem(mode, ny) ? 0 : 4 * (size_t)entries));
 }
 
 // MODE 0: C^mf; MODE 1: C^mf and C^visc; MODE 2: the transpose of the C^mf
@@ -554,13 +554,15 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   // this pair's ring table ({e^, offset} per point; the ring offsets are
   // e_y*W_k + e_x for a window of FORCE_TX + 2R columns).  The point index is
   // the same in every lane.  With C^visc and in the adjoint (ten gathers per
-  // pair), and for the attraction (two rows of two gathers), the entries come
-  // in through scalar loads into SGPRs and cost no LDS bandwidth (a broadcast
-  // LDS read of the 32-byte entry costs as much LDS return bandwidth as four
-  // gathers of one field).  For C^mf alone (four gathers per pair) the wait
-  // on each scalar load is exposed, so the table is staged once in LDS
-  // behind the plane buffers instead.
-  constexpr bool STAB = table_in_smem(MODE);
+  // pair), for the attraction and for any tile with two rows per thread, the
+  // entries come in through scalar loads into SGPRs and cost no LDS bandwidth
+  // (a broadcast LDS read of the 32-byte entry costs as much LDS return
+  // bandwidth as four gathers of one field).  For C^mf alone with one row
+  // (four gathers per pair) the wait on each scalar load is exposed, so the
+  // table is staged once in LDS behind the plane buffers instead.  (C^mf
+  // alone at 128^3, 32 x 16 tile with two rows: 0.297 ms with the LDS table,
+  // 0.232 ms with scalar loads.)
+  constexpr bool STAB = table_in_smem(MODE, NY);
   int rofs[R + 2];
 #pragma unroll
   for (int ez = 0; ez <= R + 1; ++ez) rofs[ez] = ofs[ez];
@@ -1872,7 +1874,7 @@ template <int R, bool VISC, int SHAPE>
 static void force_launch_shape(const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
   constexpr int NY = shape_ny(SHAPE), NT = shape_nt(SHAPE), TY = shape_ty(SHAPE);
   const int k = pair_index(a.M, alpha, beta);
-  const size_t bytes = force_lds(VISC ? 1 : 0, R, TY, a.t.pair_nent[k]);
+  const size_t bytes = force_lds(VISC ? 1 : 0, R, TY, a.t.pair_nent[k], NY);
   static size_t attr = 0;
   if (bytes > attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_force<R, VISC, NY, NT>),
@@ -1910,7 +1912,7 @@ static void force_r(int R, const StepArgs &a, int alpha, int beta, int acc, hipS
 template <int R>
 static void att_launch(const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
   const int k = pair_index(a.M, alpha, beta);
-  const size_t bytes = force_lds(3, R, ATT_TY, a.t.att_nent[k]);
+  const size_t bytes = force_lds(3, R, ATT_TY, a.t.att_nent[k], ATT_NY);
   static size_t attr = 0;
   if (bytes > attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_force_att<R>),
@@ -2147,7 +2149,7 @@ static void adj_force_launch_shape(const StepArgs &a, const AdjArgs &d, int alph
                                    hipStream_t s) {
   constexpr int NY = shape_ny(SHAPE), NT = shape_nt(SHAPE), TY = shape_ty(SHAPE);
   const int k = pair_index(a.M, alpha, beta);
-  const size_t bytes = force_lds(2, R, TY, a.t.pair_nent[k]);
+  const size_t bytes = force_lds(2, R, TY, a.t.pair_nent[k], NY);
   static size_t attr = 0;
   if (bytes > attr) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_adj_force<R, NY, NT>),
