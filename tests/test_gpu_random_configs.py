@@ -79,3 +79,40 @@ def test_random_configuration(L, i):
     b.step(w.steps)
     compare_state(o, b, w.nspecies, TOL, f"random {i}")
     b.close()
+
+
+
+# generator seeds whose runs stay bounded with the attraction on (a random mix
+# of very unequal diameters can drive a trace species far past v_T within a
+# few steps, and then says nothing about parity); between them they cover one
+# to three species, walls, obstacles, every scheme switch and the drag
+ATT_SEEDS = [500, 501, 502, 504, 508, 512, 536, 539, 561, 615]
+
+
+@pytest.mark.parametrize("seed", ATT_SEEDS)
+def test_random_configuration_with_attraction(L, seed):
+    """The same generator with the attractive tail switched on: random
+    symmetric depths up to 0.3 kT per pair and a cutoff between the largest
+    pair diameter + 1/2 and 9."""
+    w, flags = _case(L, seed)
+    flags &= ~L.LBE_IDEAL
+    g = W.rng(9200 + seed)
+    M = w.nspecies
+    e = g.uniform(0.0, 0.3 * KT, size=(M, M))
+    w.att_eps = ((e + e.T) / 2).tolist()
+    smax = max(0.5 * (a + b) for a in w.sigma for b in w.sigma)
+    w.att_rc = float(g.uniform(smax + 0.5, 9.0))
+    reach = int(math.ceil(w.att_rc))
+    for k, d in enumerate((w.nx, w.ny, w.nz)):      # a periodic edge must cover the range
+        if (w.periodic >> k) & 1 and d < reach:
+            w.periodic &= ~(1 << k)
+    banner(f"random attraction case {seed}: {w.nx}x{w.ny}x{w.nz} periodic={w.periodic} sigma={w.sigma} "
+           f"rc={w.att_rc:.2f} flags={flags} solid={w.solid is not None}")
+    o = oracle_from_workload(w, flags)
+    b = L.box_from_workload(w, flags=flags)
+    o.step(w.steps)
+    b.step(w.steps)
+    d = o.diagnostics()
+    assert not d["unstable"] and d["umax"] < 0.9 * math.sqrt(KT), d
+    compare_state(o, b, w.nspecies, TOL, f"random attraction {seed}")
+    b.close()
