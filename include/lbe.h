@@ -131,7 +131,7 @@ typedef struct {
    * (kT = 1/3), symmetric, >= 0; all zero = no attraction.  A pair with
    * att_eps > 0 needs sigma_ab > 0 and sigma_ab < att_rc, and the points
    * must reach at most 8 nodes per axis (att_rc <= 9).  Not with LBE_IDEAL
-   * (which drops every nonlocal force), batched boxes or the adjoint. */
+   * (which drops every nonlocal force) or batched boxes. */
   double att_eps[4][4];
   double att_rc;
 } lbe_config;
@@ -314,7 +314,8 @@ void lbe_batch_destroy(lbe_batch *batch);
  * the read-outs of the final state: n^a (lbe_get_density), J^a
  * (lbe_get_momentum) and the post-streaming populations
  * (lbe_get_populations).  Supported: FP64 populations, the C^mf scheme
- * with either inversion and either kappa (not LBE_VISC).  The forward
+ * with either inversion and either kappa, with or without the attractive
+ * field (not LBE_VISC).  The forward
  * keeps a copy of the state every `segment` steps; the backward recomputes
  * one segment at a time from its copy, so device memory grows as
  * (nsteps/segment + segment) states.  The context's potential, body forces

@@ -23,7 +23,10 @@ post-streaming populations f~, g~:
     the kappa of the C^mf part of S_g;
   * trapezoidal update f~* = f~ + a (f_eq - f~) + b S_f (Sec. 4.1) and the
     pull streaming with mid-point bounce-back (Sec. 4.3).
-Only the C^mf scheme (no C^visc) is expressed.  Neighbour access uses index
+Only the C^mf scheme (no C^visc) is expressed, optionally with the
+attractive molecular field of the Appendix (the r^-6 tail U = -eps (sigma/r)^6
+for sigma_ab <= r < rc, g = 1 there), which adds
+n_a sum_b sum_e U'(|e|) e^ n_b(r+e) to C^mf_a.  Neighbour access uses index
 tables built once per geometry; an index of N points at a zero.
 """
 from __future__ import annotations
@@ -63,6 +66,18 @@ def lattice_shell(s: float):
     e = np.array([p[:3] for p in pts], dtype=np.int64)
     r = np.array([p[3] for p in pts])
     return e, e / r[:, None], 4 * math.pi * s / r.sum()
+
+
+def attraction_offsets(sab: float, eps: float, rc: float):
+    """Offsets e with sigma_ab <= |e| < rc and U'(|e|) e^ for
+    U = -eps (sigma_ab/r)^6, so U' = 6 eps sigma_ab^6 / r^7."""
+    K = int(math.ceil(rc))
+    e = np.array([(x, y, z) for z in range(-K, K + 1) for y in range(-K, K + 1) for x in range(-K, K + 1)],
+                 dtype=np.int64)
+    r = np.sqrt((e ** 2).sum(1).astype(float))
+    keep = (r >= sab) & (r < rc)
+    e, r = e[keep], r[keep]
+    return e, (6.0 * eps * sab ** 6 / r ** 7 / r)[:, None] * e
 
 
 def lattice_ball(sigma: float):
@@ -112,7 +127,8 @@ class Geometry:
 class Stepper:
     """One configuration: geometry, species diameters, tau, flags, body forces."""
 
-    def __init__(self, geom: Geometry, sigma, tau=1.0, kT=1.0 / 3.0, flags=0, body=None):
+    def __init__(self, geom: Geometry, sigma, tau=1.0, kT=1.0 / 3.0, flags=0, body=None,
+                 att_eps=None, att_rc=0.0):
         self.g = geom
         self.M = len(sigma)
         self.sigma = [float(s) for s in sigma]
@@ -149,6 +165,15 @@ class Stepper:
                 e, eh, w = lattice_shell(s) if s >= 0.5 else (np.zeros((0, 3), np.int64), np.zeros((0, 3)), 0.0)
                 idx = np.stack([geom.shifted(v) for v in e]) if len(e) else np.zeros((0, N), np.int64)
                 self.shell[a, b] = (torch.tensor(idx), torch.tensor(eh), s, w)
+        # attractive tails of every ordered pair with a positive depth
+        self.att = {}
+        for a in range(self.M):
+            for b in range(self.M):
+                eps = 0.0 if att_eps is None else float(att_eps[a][b])
+                if eps > 0.0:
+                    s = 0.5 * (self.sigma[a] + self.sigma[b])
+                    e, K = attraction_offsets(s, eps, att_rc)
+                    self.att[a, b] = (torch.tensor(np.stack([geom.shifted(v) for v in e])), torch.tensor(K))
         self.ball = []
         for b in range(self.M):
             d = lattice_ball(self.sigma[b])
@@ -201,7 +226,12 @@ class Stepper:
                 Gab = G[a, b]
                 pair = 0.5 * (Gab[None, :] + self._ext(Gab)[idx]) * self._ext(n[b])[idx]   # (E, N)
                 acc = acc + s * s * w * (eh.T @ pair)
-            out.append(-self.kT * n[a][None, :] * acc)
+            Ca = -self.kT * n[a][None, :] * acc
+            for b in range(self.M):
+                if (a, b) in self.att:
+                    idx, K = self.att[a, b]
+                    Ca = Ca + n[a][None, :] * (K.T @ self._ext(n[b])[idx])
+            out.append(Ca)
         return torch.stack(out)
 
     def invert(self, f, g, n, Cmf, F):

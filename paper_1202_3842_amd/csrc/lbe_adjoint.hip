@@ -41,10 +41,6 @@ lbe_status make_adj_plan(const lbe_config *cfg, int nsteps, int segment, AdjPlan
     return fail(LBE_ERR_UNSUPPORTED, "the adjoint covers the DD-TR scheme only");
   if ((cfg->flags & LBE_DRAG) && cfg->nspecies > 1 && !(cfg->flags & LBE_IDEAL))
     return fail(LBE_ERR_UNSUPPORTED, "the adjoint does not cover the interspecies drag");
-  for (int x = 0; x < cfg->nspecies; ++x)
-    for (int y = 0; y < cfg->nspecies; ++y)
-      if (cfg->att_eps[x][y] > 0.0)
-        return fail(LBE_ERR_UNSUPPORTED, "the adjoint does not cover the attractive field");
   if (nsteps < 1 || segment < 1) return fail(LBE_ERR_ARG, "nsteps and segment must be >= 1");
   const Plan &P = ap.pl;
   const size_t N = P.g.N, Np = P.g.Np, M = P.M, npairs = P.npairs;

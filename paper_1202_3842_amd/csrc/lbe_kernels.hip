@@ -478,7 +478,9 @@ typedef double dbl2 __attribute__((ext_vector_type(2)));
 // thread; LDS for C^mf alone with one row per thread
 __host__ __device__ constexpr bool table_in_smem(int mode, int ny = 1) { return mode != 0 || ny > 1; }
 // fields staged per plane by force_body
-__host__ __device__ constexpr int force_fields(int mode) { return mode == 0 ? 2 : (mode == 3 ? 1 : 5); }
+__host__ __device__ constexpr int force_fields(int mode) {
+  return mode == 0 ? 2 : (mode == 3 ? 1 : (mode == 4 ? 3 : 5));
+}
 // dynamic LDS of force_body: two planes of NF fields, then the ring table
 // when it is staged in LDS
 __host__ __device__ constexpr size_t force_lds(int mode, int R, int ty, int entries, int ny = 1) {
@@ -490,7 +492,9 @@ __host__ __device__ constexpr size_t force_lds(int mode, int R, int ty, int entr
 // gather for the adjoint (fields n_b, G_ab and the adjoint force phi_a^bar,
 // see k_adj_force); MODE 3: the attractive field G^{ab} = sum_e U'(|e|) e^
 // n_b(r + e) over the pair's thick shell (field n_b; the table holds
-// U'(|e|) e^), added to C^mf/n_a.  NT threads in rows of FTX; NY = output rows per thread:
+// U'(|e|) e^), added to C^mf/n_a; MODE 4: the transpose of MODE 3 for the
+// adjoint, n_b^bar(r) -= sum_e U'(|e|) e^.phibar_a(r + e) (field phibar_a, the
+// same table).  NT threads in rows of FTX; NY = output rows per thread:
 // the tile is FTX x (NT/FTX NY) and thread (tx, ty) owns rows ty,
 // ty + NT/FTX, ...; one ring-table read and one address then serve NY nodes.
 // Taller tiles shrink the staged window per node.
@@ -500,6 +504,7 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   constexpr bool VISC = MODE == 1;
   constexpr bool ADJ = MODE == 2;
   constexpr bool ATT = MODE == 3;
+  constexpr bool AADJ = MODE == 4;
   constexpr int NF = force_fields(MODE);
   constexpr int RY = NT / FTX;                  // thread rows of the workgroup
   constexpr int TY = RY * NY;
@@ -537,7 +542,12 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
     fld[3] = fld[2] + g.Np;
     fld[4] = fld[3] + g.Np;
   }
-  const auto *ofs = cptr((ATT ? a.t.att_ring_ofs : a.t.ring_ofs) + k * (RING_MAX + 2));
+  if (AADJ) {
+    fld[0] = ad->phibar + (long long)(3 * alpha) * g.Np;
+    fld[1] = fld[0] + g.Np;
+    fld[2] = fld[1] + g.Np;
+  }
+  const auto *ofs = cptr((ATT || AADJ ? a.t.att_ring_ofs : a.t.ring_ofs) + k * (RING_MAX + 2));
   const auto *roff = cptr(a.t.ring_off);
   const auto *re = cptr(a.t.ring_e);
   const double cmf = a.t.pair_cmf[k], cvs = a.t.pair_cvisc[k];
@@ -634,8 +644,8 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
 #pragma unroll
         for (int c = 0; c < NS; ++c) mx[jn][c] = my[jn][c] = mz[jn][c] = vx[jn][c] = vy[jn][c] = vz[jn][c] = 0.0;
         const int bj = base + jn * ROW;
-        G0[jn] = ATT ? 0.0 : Bp[at(1, bj)];
-        n0[jn] = Bp[at(0, bj)];
+        G0[jn] = ATT || AADJ ? 0.0 : Bp[at(1, bj)];
+        n0[jn] = AADJ ? 0.0 : Bp[at(0, bj)];
         u0x[jn] = u0y[jn] = u0z[jn] = 0.0;
         if (VISC && n0[jn] != 0.0) {
           u0x[jn] = Bp[at(2, bj)] / n0[jn];
@@ -680,6 +690,11 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
         } else if (ATT) {
           ap = dbl2{Bp[qa], 0.0};
           am = dbl2{Bm[qb], 0.0};
+        } else if (AADJ) {
+          ap = dbl2{Bp[qa], Bp[WH + qa]};
+          am = dbl2{Bm[qb], Bm[WH + qb]};
+          vpz = Bp[2 * WH + qa];
+          vmz = Bm[2 * WH + qb];
         } else {
           ap = dbl2{Bp[qa], Bp[WH + qa]};
           am = dbl2{Bm[qb], Bm[WH + qb]};
@@ -693,7 +708,10 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
           vmz = Bm[4 * WH + qb];
         }
         const double npl = ap.x, nmi = am.x;
-        if (ATT) {
+        if (AADJ) {
+          // K(-e) = -K(e): the pair adds K.(phibar(r+e) - phibar(r-e))
+          mx[jn][c] += e0 * (ap.x - am.x) + e1 * (ap.y - am.y) + e2 * (vpz - vmz);
+        } else if (ATT) {
           // the table holds U'(|e|) e^; the pair adds K.(n_b(r+e) - n_b(r-e))
           const double dn = npl - nmi;
           mx[jn][c] += e0 * dn;
@@ -753,6 +771,9 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
           double *pn = ad->nbar + beta * N + i, *pg = ad->Gbar + k * N + i;
           *pn = (accumulate & 1) ? *pn + vn : vn;
           *pg = (accumulate & 2) ? *pg + vg : vg;
+        } else if (AADJ) {
+          double *pn = ad->nbar + beta * N + i;
+          *pn = (accumulate & 1) ? *pn - Mx : -Mx;
         } else if (ATT) {
           // G^{ab} is a force per particle of species a: into C^mf/n_a
           double *F = a.force + 6LL * alpha * N + i;
@@ -1541,6 +1562,16 @@ __global__ __launch_bounds__(NT) void k_adj_force(StepArgs a, AdjArgs d, int alp
   force_body<R, 2, NY, NT>(a, &d, alpha, beta, acc, T.bx, T.by, T.bz, lds);
 }
 
+// adjoint of the attractive field of the directed pair (alpha, beta), see
+// force_body MODE 4: writes or (acc bit 0) accumulates into nbar; the tile
+// shape of the forward attraction gather
+template <int R>
+__global__ __launch_bounds__(FNT) void k_adj_att(StepArgs a, AdjArgs d, int alpha, int beta, int acc) {
+  extern __shared__ double lds[];
+  const Tile T = force_tile(a.g, a.zchunk, a.order, ATT_TY);
+  force_body<R, 4, ATT_NY, FNT>(a, &d, alpha, beta, acc, T.bx, T.by, T.bz, lds);
+}
+
 // Vbar = -(grad_h)^T Fbar: transpose of F(r) = -3 sum_p w_p c_p V(idx(r + c_p))
 // (idx wraps periodic directions and clamps the others), as a gather over
 // the nodes r with idx(r + c_p) = this node
@@ -2168,6 +2199,35 @@ static void adj_force_launch(const StepArgs &a, const AdjArgs &d, int alpha, int
   adj_force_launch_shape<R, 0>(a, d, alpha, beta, acc, s);
 }
 
+template <int R>
+static void adj_att_launch(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
+                           hipStream_t s) {
+  const int k = pair_index(a.M, alpha, beta);
+  const size_t bytes = force_lds(4, R, ATT_TY, a.t.att_nent[k], ATT_NY);
+  static size_t attr = 0;
+  if (bytes > attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_adj_att<R>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    attr = bytes;
+  }
+  hipLaunchKernelGGL((k_adj_att<R>), dim3(force_blocks(a.g, a.zchunk, ATT_TY)), dim3(FNT), bytes, s, a, d,
+                     alpha, beta, acc);
+}
+
+static void adj_att_r(int R, const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
+                      hipStream_t s) {
+  switch (R) {
+    case 1: adj_att_launch<1>(a, d, alpha, beta, acc, s); break;
+    case 2: adj_att_launch<2>(a, d, alpha, beta, acc, s); break;
+    case 3: adj_att_launch<3>(a, d, alpha, beta, acc, s); break;
+    case 4: adj_att_launch<4>(a, d, alpha, beta, acc, s); break;
+    case 5: adj_att_launch<5>(a, d, alpha, beta, acc, s); break;
+    case 6: adj_att_launch<6>(a, d, alpha, beta, acc, s); break;
+    case 7: adj_att_launch<7>(a, d, alpha, beta, acc, s); break;
+    default: adj_att_launch<8>(a, d, alpha, beta, acc, s); break;
+  }
+}
+
 void launch_fill(double *p, long long n, double v, hipStream_t s) {
   if (n <= 0) return;
   long long blocks = (n + BLOCK - 1) / BLOCK;
@@ -2175,7 +2235,7 @@ void launch_fill(double *p, long long n, double v, hipStream_t s) {
 }
 
 // nbar of the step: the transposes of the shell gathers (every directed
-// pair) and of the contact values and ball averages.  The first launch that
+// pair), of the attractive tails and of the contact values and ball averages.  The first launch that
 // reaches an output writes it, later ones accumulate.
 void launch_adj_nonlocal(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
   const long long N = a.g.N;
@@ -2202,6 +2262,14 @@ void launch_adj_nonlocal(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
         case 7: adj_force_launch<7>(a, d, al, be, acc, s); break;
         default: adj_force_launch<8>(a, d, al, be, acc, s); break;
       }
+    }
+  // the attractive tails: phibar_a gathered back onto n_b
+  for (int al = 0; al < M; ++al)
+    for (int be = 0; be < M; ++be) {
+      const int R = a.t.att_R[pair_index(M, al, be)];
+      if (R == 0) continue;
+      adj_att_r(R, a, d, al, be, wn[be] ? 1 : 0, s);
+      wn[be] = true;
     }
   for (int b = 0; b < M; ++b)
     if (!wn[b]) launch_fill(d.nbar + b * N, N, 0.0, s);

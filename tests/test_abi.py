@@ -115,8 +115,7 @@ def test_attraction_configuration_is_validated(L):
             lbe.workspace_bytes(cfg)
         assert word in L.lbe_last_error(), L.lbe_last_error()
     ok = lbe.make_config(16, 16, 16, [2.0], att_eps=0.1, att_rc=5.0, flags=0)
-    assert L.lbe_adjoint_workspace_bytes(C.byref(ok), 10, 5) == 0
-    assert b"attractive" in L.lbe_last_error()
+    assert L.lbe_adjoint_workspace_bytes(C.byref(ok), 10, 5) > 0      # the adjoint covers it
     arr = (lbe.lbe_config * 1)(ok)
     assert L.lbe_batch_workspace_bytes(arr, 1) == 0
     assert b"attractive" in L.lbe_last_error()

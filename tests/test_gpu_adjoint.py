@@ -22,7 +22,7 @@ def reference(w, flags, T, pw):
     n_t, fluid, plane = objective_terms(w)
     geo = AR.Geometry(w.nx, w.ny, w.nz, w.periodic,
                       (w.solid if w.solid is not None else np.zeros(w.shape)).astype(bool))
-    st = AR.Stepper(geo, w.sigma, w.tau, w.kT, flags, w.body)
+    st = AR.Stepper(geo, w.sigma, w.tau, w.kT, flags, w.body, att_eps=w.att_eps, att_rc=w.att_rc)
     V = torch.tensor(w.V.reshape(-1), requires_grad=True)
     f0, g0 = st.rest_state(np.stack(w.density))
     f0.requires_grad_(True)
@@ -76,6 +76,38 @@ def test_adjoint_matches_reference(flags, T, segment):
     assert_close(gV, rV, 1e-10, "dL/dV")
     assert_close(gf, rf, 1e-10, "dL/df0")
     assert_close(gg, rg, 1e-10, "dL/dg0")
+
+
+@pytest.mark.parametrize("flags,T,segment", [(0, 6, 6), (0, 7, 3), (2 | 4, 5, 2)])
+def test_adjoint_with_attraction_matches_reference(flags, T, segment):
+    """The two-species channel with the attractive tails on (depths 0.2 to
+    0.3 kT, cutoff 5): the transpose of the attraction gather joins the
+    adjoint of the density."""
+    w = small_channel()
+    w.att_eps = [[0.3 * W.KT, 0.2 * W.KT], [0.2 * W.KT, 0.25 * W.KT]]
+    w.att_rc = 5.0
+    pw = pop_weights(w) * 1e-3
+    print(f"small channel with attraction flags {flags} T {T} segment {segment}", flush=True)
+    rV, rf, rg = reference(w, flags, T, pw)
+    gV, gf, gg = gpu_gradient(w, flags, T, segment, pw)
+    assert_close(gV, rV, 1e-10, "dL/dV")
+    assert_close(gf, rf, 1e-10, "dL/df0")
+    assert_close(gg, rg, 1e-10, "dL/dg0")
+
+
+def test_adjoint_attraction_one_species_periodic():
+    """One species, periodic box, a cutoff of 7.5 (the widest transpose
+    window, 7 nodes per axis) and a potential well."""
+    w = W.well_box(18, 3.0, 0.25, W.eps_for_depth(1.0), 5.0, 1e-2, 41, 5, "well18_s3_att")
+    w.V = w.V + W.smooth_field(w.shape, 0.02, 3, 42)
+    w.solid = np.zeros(w.shape, dtype=np.uint8)
+    w.att_eps, w.att_rc = [[0.3 * W.KT]], 7.5
+    pw = pop_weights(w, 7) * 1e-3
+    print("well18 sigma 3 one species with attraction", flush=True)
+    rV, rf, rg = reference(w, 0, 4, pw)
+    gV, gf, gg = gpu_gradient(w, 0, 4, 2, pw)
+    assert_close(gV, rV, 1e-10, "dL/dV")
+    assert_close(gf, rf, 1e-10, "dL/df0")
 
 
 def test_adjoint_one_species_periodic_well():
@@ -149,14 +181,18 @@ def test_channel96_gradient_against_oracle_fd():
           f"fd noise {noise:.1e}", flush=True)
 
 
-def test_adjoint_tiling_does_not_change_gradient():
-    """The adjoint shell-gather transposes under every force tiling."""
+@pytest.mark.parametrize("att", [False, True])
+def test_adjoint_tiling_does_not_change_gradient(att):
+    """The adjoint shell-gather transposes (and those of the attraction)
+    under every force tiling."""
     from paper_1202_3842_amd import lbe
     w = small_channel()
+    if att:
+        w.att_eps, w.att_rc = [[0.3 * W.KT, 0.2 * W.KT], [0.2 * W.KT, 0.25 * W.KT]], 5.0
     n_t, fluid, plane = objective_terms(w)
     ref = None
     for zc, order, shape in ((1, 0, 0), (3, 1, 1), (8, 2, 2), (2, 0, 1)):
-        print(f"adjoint tiling zchunk {zc} order {order} shape {shape}", flush=True)
+        print(f"adjoint tiling att {att} zchunk {zc} order {order} shape {shape}", flush=True)
         box = lbe.box_from_workload(w, flags=0)
         box.set_force_tiling(zc, order, shape)
         adj = lbe.Adjoint(box, 4, 2)

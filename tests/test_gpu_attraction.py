@@ -115,9 +115,3 @@ def test_attraction_is_refused_where_not_built(L):
     with pytest.raises(L.LBEError) as e:
         L.Batch([cfg])
     assert e.value.code in (L.LBE_ERR_UNSUPPORTED, L.LBE_ERR_ARG)
-    b = L.Box(16, 16, 16, [2.0], flags=0, att_eps=0.1, att_rc=5.0)
-    b.init_density(0, np.full((16, 16, 16), 0.02))
-    with pytest.raises(L.LBEError) as e:
-        L.Adjoint(b, 10, 5)
-    assert e.value.code in (L.LBE_ERR_UNSUPPORTED, L.LBE_ERR_ARG)
-    b.close()

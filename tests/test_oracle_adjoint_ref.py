@@ -13,8 +13,14 @@ from paper_1202_3842_amd import workloads as W
 T = 4
 
 
-def c_oracle(w, flags, V=None):
-    o = oracle.Oracle(w.nx, w.ny, w.nz, w.sigma, w.periodic, w.tau, w.kT, flags=flags)
+# attractive tails for the two-species channel (sigma 2 and 3)
+ATT_EPS = [[0.3 * W.KT, 0.2 * W.KT], [0.2 * W.KT, 0.25 * W.KT]]
+ATT_RC = 5.0
+
+
+def c_oracle(w, flags, V=None, att=False):
+    o = oracle.Oracle(w.nx, w.ny, w.nz, w.sigma, w.periodic, w.tau, w.kT, flags=flags,
+                      att_eps=ATT_EPS if att else None, att_rc=ATT_RC if att else 0.0)
     o.set_solid(w.solid)
     o.set_potential(w.V if V is None else V)
     for a in range(w.nspecies):
@@ -23,9 +29,10 @@ def c_oracle(w, flags, V=None):
     return o
 
 
-def stepper(w, flags):
+def stepper(w, flags, att=False):
     geo = AR.Geometry(w.nx, w.ny, w.nz, w.periodic, w.solid.astype(bool))
-    return AR.Stepper(geo, w.sigma, w.tau, w.kT, flags, w.body)
+    return AR.Stepper(geo, w.sigma, w.tau, w.kT, flags, w.body,
+                      att_eps=ATT_EPS if att else None, att_rc=ATT_RC if att else 0.0)
 
 
 def torch_loss(st, w, f, g, V, n_t, fluid, plane, pw=None):
@@ -38,12 +45,13 @@ def torch_loss(st, w, f, g, V, n_t, fluid, plane, pw=None):
     return L
 
 
-@pytest.mark.parametrize("flags", [0, AR.PRINTED_INV, AR.KAPPA4])
-def test_forward_equals_c_oracle(flags):
+@pytest.mark.parametrize("flags,att", [(0, False), (AR.PRINTED_INV, False), (AR.KAPPA4, False),
+                                       (0, True), (AR.PRINTED_INV | AR.KAPPA4, True)])
+def test_forward_equals_c_oracle(flags, att):
     w = small_channel()
-    o = c_oracle(w, flags)
+    o = c_oracle(w, flags, att=att)
     o.step(5)
-    st = stepper(w, flags)
+    st = stepper(w, flags, att)
     f, g = st.rest_state(np.stack(w.density))
     f, g = st.run(f, g, torch.tensor(w.V), 5)
     for a in range(w.nspecies):
@@ -57,12 +65,12 @@ def test_forward_equals_c_oracle(flags):
         assert np.abs(J[a].numpy() - Jo).max() <= 1e-13 * np.abs(Jo).max()
 
 
-@pytest.mark.parametrize("flags", [0, AR.PRINTED_INV])
-def test_gradient_equals_oracle_fd(flags):
+@pytest.mark.parametrize("flags,att", [(0, False), (AR.PRINTED_INV, False), (0, True)])
+def test_gradient_equals_oracle_fd(flags, att):
     w = small_channel()
     n_t, fluid, plane = objective_terms(w)
     pw = pop_weights(w) * 1e-3
-    st = stepper(w, flags)
+    st = stepper(w, flags, att)
     V = torch.tensor(w.V.reshape(-1), requires_grad=True)
     f0, g0 = st.rest_state(np.stack(w.density))
     f0.requires_grad_(True)
@@ -74,7 +82,7 @@ def test_gradient_equals_oracle_fd(flags):
     gf = f0.grad.numpy()
 
     def oracle_loss(Vx=None, pop=None):
-        o = c_oracle(w, flags, Vx)
+        o = c_oracle(w, flags, Vx, att)
         if pop is not None:
             a, p, i, h = pop
             f_in = o.populations(a, 0).reshape(19, -1).copy()
