@@ -238,13 +238,17 @@ def variants_leg(lbe, torch, w, base_flags, steps, warmup):
     return out
 
 
-def adjoint_leg(lbe, torch, W, segment=20):
+def adjoint_leg(lbe, torch, W, segment=20, att=False):
     """dL/dV on the 96x32x32 two-species channel (C^mf scheme, 400 steps):
     the forward with a checkpoint every `segment` steps and the backward
-    (segment recompute + adjoint steps) against 400 plain forward steps."""
+    (segment recompute + adjoint steps) against 400 plain forward steps.
+    With att, the attractive tails are on (eps = kT/4 for every pair,
+    rc = 8)."""
     from paper_1202_3842_amd import autotune
     import numpy as np
     w = W.c5_channel()
+    if att:
+        w.att_eps, w.att_rc = [[0.25 * W.KT] * w.nspecies] * w.nspecies, 8.0
     T = w.steps
     n_t, fluid, plane = W.c5_objective(w)
     box = lbe.box_from_workload(w, flags=0)
@@ -286,11 +290,11 @@ def adjoint_leg(lbe, torch, W, segment=20):
     gnorm = float(out.abs().max())
     adj.close()
     box.close()
-    log(f"adjoint: plain forward {t_plain:.1f} ms, checkpointed forward {t_fwd:.1f} ms, "
-        f"backward {t_bwd:.1f} ms ({T} steps)")
+    log(f"adjoint{' with attraction' if att else ''}: plain forward {t_plain:.1f} ms, "
+        f"checkpointed forward {t_fwd:.1f} ms, backward {t_bwd:.1f} ms ({T} steps)")
     return {
         "workload": w.name, "steps": T, "segment": segment, "species": M, "sigma": w.sigma,
-        "scheme": "C^mf, derived inversion",
+        "scheme": "C^mf, derived inversion" + (", attraction eps = kT/4, rc = 8" if att else ""),
         "forward_ms": round(t_plain, 3), "forward_checkpointed_ms": round(t_fwd, 3),
         "backward_ms": round(t_bwd, 3),
         "adjoint_vs_forward": round(t_bwd / t_plain, 3),
@@ -473,7 +477,9 @@ def main():
         print(json.dumps({"copy_bytes": nbytes, "copies": 5}), flush=True)
         return
     if args.adjoint_only:
-        print(json.dumps({"adjoint": adjoint_leg(lbe, torch, W)}), flush=True)
+        adj = adjoint_leg(lbe, torch, W)
+        adj["with_attraction"] = adjoint_leg(lbe, torch, W, att=True)
+        print(json.dumps({"adjoint": adj}), flush=True)
         return
     w = W.c2_large_well()
     if args.quasipressure_only:
@@ -513,7 +519,10 @@ def main():
     variants = None if args.no_variants else variants_leg(lbe, torch, w, flags, args.variant_steps,
                                                              args.warmup)
 
-    adjoint = None if args.no_adjoint else adjoint_leg(lbe, torch, W)
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = adjoint_leg(lbe, torch, W)
+        adjoint["with_attraction"] = adjoint_leg(lbe, torch, W, att=True)
 
     qp = None if args.no_quasipressure else quasipressure_leg(lbe, torch, w, flags)
 

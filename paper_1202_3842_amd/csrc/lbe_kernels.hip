@@ -855,13 +855,23 @@ __global__ __launch_bounds__(NT) void k_force(StepArgs a, int alpha, int beta, i
 // (no LDS traffic), and two output rows per thread (a 32 x 16 tile) give each
 // entry four gathers to hide its load behind.  At 128^3 with 604 pairs per
 // node: 0.755 ms with an LDS table and one row, 0.59 ms with two rows, 0.35 ms
-// with two rows and scalar loads.
-constexpr int ATT_NY = 2, ATT_TY = FNT / FTX * ATT_NY;
-template <int R>
+// with two rows and scalar loads.  A box that gives fewer than two such
+// tiles per CU takes one row per thread (a 32 x 8 tile, twice the
+// workgroups): on the 96 x 32 x 32 channel, 192 workgroups of 32 x 16 leave a
+// quarter of the 256 CUs idle, and the 32 x 8 tile makes the four gathers
+// 0.58 -> 0.53 ms; at 128^3 the 32 x 16 tile stays faster (1.15 against
+// 1.32 ms).  Both give the same sums bit for bit.
+template <int R, int NY>
 __global__ __launch_bounds__(FNT) void k_force_att(StepArgs a, int alpha, int beta, int accumulate) {
   extern __shared__ double lds[];
-  const Tile T = force_tile(a.g, a.zchunk, a.order, ATT_TY);
-  force_body<R, 3, ATT_NY, FNT>(a, nullptr, alpha, beta, accumulate, T.bx, T.by, T.bz, lds);
+  const Tile T = force_tile(a.g, a.zchunk, a.order, FNT / FTX * NY);
+  force_body<R, 3, NY, FNT>(a, nullptr, alpha, beta, accumulate, T.bx, T.by, T.bz, lds);
+}
+
+// output rows per thread of the attraction gathers (forward and transpose)
+constexpr int NCU = 256;
+static int att_rows(const StepArgs &a) {
+  return force_blocks(a.g, a.zchunk, FNT / FTX * 2) < 2 * NCU ? 1 : 2;
 }
 
 // per-particle forces of species s at node i, times n_s
@@ -1564,12 +1574,12 @@ __global__ __launch_bounds__(NT) void k_adj_force(StepArgs a, AdjArgs d, int alp
 
 // adjoint of the attractive field of the directed pair (alpha, beta), see
 // force_body MODE 4: writes or (acc bit 0) accumulates into nbar; the tile
-// shape of the forward attraction gather
-template <int R>
+// shapes of the forward attraction gather
+template <int R, int NY>
 __global__ __launch_bounds__(FNT) void k_adj_att(StepArgs a, AdjArgs d, int alpha, int beta, int acc) {
   extern __shared__ double lds[];
-  const Tile T = force_tile(a.g, a.zchunk, a.order, ATT_TY);
-  force_body<R, 4, ATT_NY, FNT>(a, &d, alpha, beta, acc, T.bx, T.by, T.bz, lds);
+  const Tile T = force_tile(a.g, a.zchunk, a.order, FNT / FTX * NY);
+  force_body<R, 4, NY, FNT>(a, &d, alpha, beta, acc, T.bx, T.by, T.bz, lds);
 }
 
 // Vbar = -(grad_h)^T Fbar: transpose of F(r) = -3 sum_p w_p c_p V(idx(r + c_p))
@@ -1940,18 +1950,27 @@ static void force_r(int R, const StepArgs &a, int alpha, int beta, int acc, hipS
   }
 }
 
-template <int R>
-static void att_launch(const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
+template <int R, int NY>
+static void att_launch_rows(const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
+  constexpr int TY = FNT / FTX * NY;
   const int k = pair_index(a.M, alpha, beta);
-  const size_t bytes = force_lds(3, R, ATT_TY, a.t.att_nent[k], ATT_NY);
+  const size_t bytes = force_lds(3, R, TY, a.t.att_nent[k], NY);
   static size_t attr = 0;
   if (bytes > attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_force_att<R>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_force_att<R, NY>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     attr = bytes;
   }
-  hipLaunchKernelGGL((k_force_att<R>), dim3(force_blocks(a.g, a.zchunk, ATT_TY)), dim3(FNT), bytes, s, a,
+  hipLaunchKernelGGL((k_force_att<R, NY>), dim3(force_blocks(a.g, a.zchunk, TY)), dim3(FNT), bytes, s, a,
                      alpha, beta, acc);
+}
+
+template <int R>
+static void att_launch(const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
+  if (att_rows(a) == 1)
+    att_launch_rows<R, 1>(a, alpha, beta, acc, s);
+  else
+    att_launch_rows<R, 2>(a, alpha, beta, acc, s);
 }
 
 static void att_r(int R, const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
@@ -2199,19 +2218,29 @@ static void adj_force_launch(const StepArgs &a, const AdjArgs &d, int alpha, int
   adj_force_launch_shape<R, 0>(a, d, alpha, beta, acc, s);
 }
 
-template <int R>
-static void adj_att_launch(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
-                           hipStream_t s) {
+template <int R, int NY>
+static void adj_att_launch_rows(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
+                                hipStream_t s) {
+  constexpr int TY = FNT / FTX * NY;
   const int k = pair_index(a.M, alpha, beta);
-  const size_t bytes = force_lds(4, R, ATT_TY, a.t.att_nent[k], ATT_NY);
+  const size_t bytes = force_lds(4, R, TY, a.t.att_nent[k], NY);
   static size_t attr = 0;
   if (bytes > attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_adj_att<R>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_adj_att<R, NY>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     attr = bytes;
   }
-  hipLaunchKernelGGL((k_adj_att<R>), dim3(force_blocks(a.g, a.zchunk, ATT_TY)), dim3(FNT), bytes, s, a, d,
+  hipLaunchKernelGGL((k_adj_att<R, NY>), dim3(force_blocks(a.g, a.zchunk, TY)), dim3(FNT), bytes, s, a, d,
                      alpha, beta, acc);
+}
+
+template <int R>
+static void adj_att_launch(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
+                           hipStream_t s) {
+  if (att_rows(a) == 1)
+    adj_att_launch_rows<R, 1>(a, d, alpha, beta, acc, s);
+  else
+    adj_att_launch_rows<R, 2>(a, d, alpha, beta, acc, s);
 }
 
 static void adj_att_r(int R, const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
