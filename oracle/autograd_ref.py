@@ -24,6 +24,9 @@ post-streaming populations f~, g~:
   * trapezoidal update f~* = f~ + a (f_eq - f~) + b S_f (Sec. 4.1) and the
     pull streaming with mid-point bounce-back (Sec. 4.3).
 Only the C^mf scheme (no C^visc) is expressed, optionally with the
+interspecies drag of the Appendix (eq. dragforce2: the local force
+-n_a sum_b gamma_ab G_ab n_b (u~_a - u~_b), u~ = J~/n, gamma_ab =
+sigma_ab^2 2 sqrt(kT/pi) 4 pi/3, which joins C^visc in the sources) and the
 attractive molecular field of the Appendix (the r^-6 tail U = -eps (sigma/r)^6
 for sigma_ab <= r < rc, g = 1 there), which adds
 n_a sum_b sum_e U'(|e|) e^ n_b(r+e) to C^mf_a.  Neighbour access uses index
@@ -49,6 +52,7 @@ OPP = np.array([int(np.flatnonzero((C_VEL == -c).all(1))[0]) for c in C_VEL])
 
 PRINTED_INV = 1 << 1
 KAPPA4 = 1 << 2
+DRAG = 1 << 6
 
 
 def lattice_shell(s: float):
@@ -140,6 +144,11 @@ class Stepper:
         self.b = 1.0 / (1 + 0.5 * omega)
         self.printed = bool(flags & PRINTED_INV)
         self.kappa = 4.0 if flags & KAPPA4 else 2.0
+        self.drag = bool(flags & DRAG) and self.M > 1
+        # drag coefficients: the collision integral of C^visc over the unit
+        # sphere, 2 sigma_ab^2 sqrt(kT/pi) (4 pi/3)
+        self.gamma = [[(0.5 * (sa + sb)) ** 2 * 2.0 * math.sqrt(kT / math.pi) * (4.0 * math.pi / 3.0)
+                       for sb in self.sigma] for sa in self.sigma]
         self.body = torch.tensor(np.zeros((self.M, 3)) if body is None else np.asarray(body, float),
                                  dtype=torch.float64)
         N = geom.N
@@ -234,13 +243,26 @@ class Stepper:
             out.append(Ca)
         return torch.stack(out)
 
-    def invert(self, f, g, n, Cmf, F):
+    def drag_force(self, n, G, Jt):
+        """C^drag of every species, (M, 3, N), from u~ = J~/n."""
+        pos = n > 0
+        ut = Jt / torch.where(pos, n, torch.ones_like(n))[:, None, :] * pos[:, None, :]
+        out = []
+        for a in range(self.M):
+            acc = n.new_zeros(3, n.shape[1])
+            for b in range(self.M):
+                if b != a:
+                    acc = acc + (self.gamma[a][b] * G[a, b] * n[b])[None, :] * (ut[a] - ut[b])
+            out.append(-n[a][None, :] * acc)
+        return torch.stack(out)
+
+    def invert(self, f, g, n, Cmf, F, G):
         """Physical moments: J, u^a, Pi, u (Sec. 4.2 with the chosen inversion)."""
         Pit = g.sum(1)                                               # (M, N)
         Jt = torch.einsum("pk,mpn->mkn", self.c, g)                  # (M, 3, N)
         nF = n[:, None, :] * F
-        X = Cmf + nF
-        Y = nF
+        Y = nF + self.drag_force(n, G, Jt) if self.drag else nF
+        X = Cmf + Y
         J = Jt + 0.5 * (X if self.printed else Y)
         pos = n > 0
         nsafe = torch.where(pos, n, torch.ones_like(n))
@@ -262,7 +284,7 @@ class Stepper:
     def step(self, f, g, V):
         """One step on post-streaming populations (M, Q, N) -> next ones."""
         n, G, Cmf, F = self.fields(f, V)
-        J, ua, Pi, u, X, Y = self.invert(f, g, n, Cmf, F)
+        J, ua, Pi, u, X, Y = self.invert(f, g, n, Cmf, F, G)
         w = self.w[None, :, None]
         # Hermite contractions, (M, Q, N)
         JH1 = torch.einsum("mkn,pk->mpn", J, self.H1)
@@ -287,7 +309,7 @@ class Stepper:
 
     def readout(self, f, g, V):
         n, G, Cmf, F = self.fields(f, V)
-        J, ua, Pi, u, X, Y = self.invert(f, g, n, Cmf, F)
+        J, ua, Pi, u, X, Y = self.invert(f, g, n, Cmf, F, G)
         return n, J * self.fluid
 
     def rest_state(self, n0):

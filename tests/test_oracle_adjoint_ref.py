@@ -46,7 +46,8 @@ def torch_loss(st, w, f, g, V, n_t, fluid, plane, pw=None):
 
 
 @pytest.mark.parametrize("flags,att", [(0, False), (AR.PRINTED_INV, False), (AR.KAPPA4, False),
-                                       (0, True), (AR.PRINTED_INV | AR.KAPPA4, True)])
+                                       (0, True), (AR.PRINTED_INV | AR.KAPPA4, True),
+                                       (AR.DRAG, False), (AR.DRAG | AR.PRINTED_INV, True)])
 def test_forward_equals_c_oracle(flags, att):
     w = small_channel()
     o = c_oracle(w, flags, att=att)
@@ -65,7 +66,8 @@ def test_forward_equals_c_oracle(flags, att):
         assert np.abs(J[a].numpy() - Jo).max() <= 1e-13 * np.abs(Jo).max()
 
 
-@pytest.mark.parametrize("flags,att", [(0, False), (AR.PRINTED_INV, False), (0, True)])
+@pytest.mark.parametrize("flags,att", [(0, False), (AR.PRINTED_INV, False), (0, True),
+                                       (AR.DRAG, False), (AR.DRAG | AR.PRINTED_INV, False)])
 def test_gradient_equals_oracle_fd(flags, att):
     w = small_channel()
     n_t, fluid, plane = objective_terms(w)
