@@ -6,7 +6,8 @@
 // Backward: the adjoint of the read-out seeds the adjoint state at the final
 // step; then, segment by segment from the last, the segment's states are
 // recomputed from its checkpoint while a tape keeps, per step, the fields
-// the adjoint needs (n, G, C^mf/n and the tilde moments Pi~, J~), and the
+// the adjoint needs (n, G, C^mf/n, the tilde moments Pi~, J~, and J~ as a
+// padded field when the interspecies drag is on), and the
 // adjoint steps run in reverse over the tape.  The adjoint of the external
 // force is accumulated over all steps and turned into dL/dV by the transpose
 // of -grad_h at the end.
@@ -28,7 +29,8 @@ struct AdjPlan {
   size_t off_cp = 0, off_roll = 0, off_tape = 0, off_mu = 0, off_node = 0, off_nbar = 0,
          off_phibar = 0, off_Gbar = 0, off_nbb = 0, off_Fbar = 0, off_Vbar = 0, off_stage = 0;
   // inside a tape slot
-  size_t so_n = 0, so_G = 0, so_force = 0, so_PJ = 0;
+  size_t so_n = 0, so_G = 0, so_force = 0, so_PJ = 0, so_J = 0;
+  bool drag = false;
 };
 
 lbe_status make_adj_plan(const lbe_config *cfg, int nsteps, int segment, AdjPlan &ap) {
@@ -39,8 +41,6 @@ lbe_status make_adj_plan(const lbe_config *cfg, int nsteps, int segment, AdjPlan
     return fail(LBE_ERR_UNSUPPORTED, "the adjoint covers the C^mf scheme only (no LBE_VISC)");
   if (cfg->flags & (LBE_EULER | LBE_SINGLE))
     return fail(LBE_ERR_UNSUPPORTED, "the adjoint covers the DD-TR scheme only");
-  if ((cfg->flags & LBE_DRAG) && cfg->nspecies > 1 && !(cfg->flags & LBE_IDEAL))
-    return fail(LBE_ERR_UNSUPPORTED, "the adjoint does not cover the interspecies drag");
   if (nsteps < 1 || segment < 1) return fail(LBE_ERR_ARG, "nsteps and segment must be >= 1");
   const Plan &P = ap.pl;
   const size_t N = P.g.N, Np = P.g.Np, M = P.M, npairs = P.npairs;
@@ -57,7 +57,10 @@ lbe_status make_adj_plan(const lbe_config *cfg, int nsteps, int segment, AdjPlan
   ap.so_G = align256(sizeof(double) * M * Np);
   ap.so_force = ap.so_G + align256(sizeof(double) * npairs * Np);
   ap.so_PJ = ap.so_force + align256(sizeof(double) * 6 * M * N);
-  ap.slot_bytes = ap.so_PJ + align256(sizeof(double) * 4 * M * N);
+  ap.so_J = ap.so_PJ + align256(sizeof(double) * 4 * M * N);
+  // the drag of the recomputed steps reads J~ as a padded field
+  ap.drag = M > 1 && (cfg->flags & LBE_DRAG) && !(cfg->flags & LBE_IDEAL);
+  ap.slot_bytes = ap.so_J + (ap.drag ? align256(sizeof(double) * 3 * M * Np) : 0);
   ap.mu_bytes = P.pop_bytes;  // same layout as a state buffer, FP64
   ap.off_cp = take(P.pop_bytes * (size_t)(ap.nseg + 1));
   ap.off_roll = take(P.pop_bytes * 2);
@@ -96,7 +99,7 @@ struct lbe_adjoint {
     a.nfield = (double *)(slot(j) + ap.so_n);
     a.Gfield = (double *)(slot(j) + ap.so_G);
     a.force = (double *)(slot(j) + ap.so_force);
-    a.Jfield = nullptr;
+    a.Jfield = ap.drag ? (double *)(slot(j) + ap.so_J) : nullptr;
     return a;
   }
   double *slot_PJ(int j) const { return (double *)(slot(j) + ap.so_PJ); }

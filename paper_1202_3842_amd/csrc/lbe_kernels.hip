@@ -1237,7 +1237,8 @@ inline dim3 grid_for(int N) { return dim3((N + BLOCK - 1) / BLOCK); }
 
 // ------------------------------------------------------------------------
 // adjoint (reverse mode) of one step, for FP64 populations and the C^mf
-// scheme (no C^visc).  "bar" marks the adjoint dL/d(quantity).  The adjoint
+// scheme (no C^visc; with or without the interspecies drag).  "bar" marks
+// the adjoint dL/d(quantity).  The adjoint
 // state between steps is (mu, nbar) in the post-streaming frame (AdjArgs).
 // ------------------------------------------------------------------------
 
@@ -1315,6 +1316,77 @@ __device__ inline void store_phibar(const Geom &g, const AdjArgs &d, const Coord
   for (int k = 0; k < 3; ++k) store_images(g, d.phibar + (long long)(3 * s + k) * g.Np, c, v[k]);
 }
 
+// the interspecies drag is on (see load_forces)
+template <class A>
+__device__ inline bool drag_on(const A &a) {
+  return a.M > 1 && (a.flags & LBE_DRAG) && !(a.flags & LBE_IDEAL);
+}
+
+// u~ = J~/n of every species at node i from the tape's tilde moments
+template <int M>
+__device__ inline void tape_ut(const AdjArgs &d, long long N, int i, const double n[M], double ut[M][3]) {
+  for (int s = 0; s < M; ++s)
+    for (int k = 0; k < 3; ++k) ut[s][k] = n[s] != 0.0 ? d.PJ[(long long)(M + 3 * s + k) * N + i] / n[s] : 0.0;
+}
+
+// the drag force of every species at node P / i, as load_forces adds it
+template <int M, class A>
+__device__ inline void drag_force(const A &a, long long P, const double n[M], const double ut[M][3],
+                                  double D[M][3]) {
+  const long long Np = a.g.Np;
+  for (int s = 0; s < M; ++s) {
+    for (int k = 0; k < 3; ++k) D[s][k] = 0.0;
+    for (int b = 0; b < M; ++b) {
+      if (b == s) continue;
+      const int k = pair_index(M, s, b);
+      const double coef = -n[s] * a.t.pair_drag[k] * a.Gfield[(long long)k * Np + P] * n[b];
+      for (int x = 0; x < 3; ++x) D[s][x] += coef * (ut[s][x] - ut[b][x]);
+    }
+  }
+}
+
+// Reverse of the drag C^drag_s = -n_s sum_b gamma_sb G_sb n_b (u~_s - u~_b),
+// u~ = J~/n, given Db = dL/dC^drag: adds to nbar and J~bar and writes Gbar
+// of every pair at node i (the shell and ball transposes accumulate on it).
+template <int M, class A>
+__device__ inline void adj_drag(const A &a, const AdjArgs &d, long long P, int i, const double n[M],
+                                const double ut[M][3], const double Db[M][3], double nbar[M],
+                                double Jbar[M][3]) {
+  const long long N = a.g.N, Np = a.g.Np;
+  double utb[M][3], Gb[M * (M + 1) / 2];
+  for (int k = 0; k < M * (M + 1) / 2; ++k) Gb[k] = 0.0;
+  for (int s = 0; s < M; ++s)
+    for (int k = 0; k < 3; ++k) utb[s][k] = 0.0;
+  for (int s = 0; s < M; ++s)
+    for (int b = 0; b < M; ++b) {
+      if (b == s) continue;
+      const int k = pair_index(M, s, b);
+      const double gam = a.t.pair_drag[k], G = a.Gfield[(long long)k * Np + P];
+      const double coef = -n[s] * gam * G * n[b];
+      double cb = 0.0;
+      for (int x = 0; x < 3; ++x) {
+        cb += Db[s][x] * (ut[s][x] - ut[b][x]);
+        utb[s][x] += coef * Db[s][x];
+        utb[b][x] -= coef * Db[s][x];
+      }
+      nbar[s] -= gam * G * n[b] * cb;
+      nbar[b] -= gam * G * n[s] * cb;
+      Gb[k] -= gam * n[s] * n[b] * cb;
+    }
+  for (int s = 0; s < M; ++s)
+    if (n[s] != 0.0) {
+      for (int k = 0; k < 3; ++k) Jbar[s][k] += utb[s][k] / n[s];
+      nbar[s] -= dot3(utb[s], ut[s]) / n[s];
+    }
+  for (int k = 0; k < M * (M + 1) / 2; ++k) d.Gbar[(long long)k * N + i] = Gb[k];
+}
+
+// Gbar of every pair at a solid node (with the drag)
+template <int M>
+__device__ inline void zero_Gbar(const AdjArgs &d, long long N, int i) {
+  for (int k = 0; k < M * (M + 1) / 2; ++k) d.Gbar[(long long)k * N + i] = 0.0;
+}
+
 // Reverse of the collision of one node (inversion, equilibria, sources and
 // trapezoidal update, as in collide_body).  Inputs: the tilde moments of
 // the state (tape), n, the force per particle phi = C^mf/n and F; outputs
@@ -1339,9 +1411,11 @@ __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
   if (i >= g.N) return;
   const uint32_t m = a.bb[i];
   const Coord c = decode(g, i);
+  const bool drag = drag_on(a);
   if (m & 1u) {
     const double z[3] = {0.0, 0.0, 0.0};
     for (int s = 0; s < M; ++s) store_phibar(g, d, c, s, z);
+    if (drag) zero_Gbar<M>(d, g.N, i);
     return;
   }
   const long long Ns = pop_stride(g), N = g.N;
@@ -1349,14 +1423,19 @@ __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
   const bool printed = a.flags & LBE_PRINTED_INV;
   const double sgn = printed ? -1.0 : 1.0;
   double n[M], phi[M][3], F[M][3], C[M][3], Y[M][3], X[M][3], ua[M][3], u[3];
+  double ut[M][3], Dr[M][3];
   double ntot = 0.0, Jtot[3] = {0.0, 0.0, 0.0};
+  for (int s = 0; s < M; ++s) n[s] = a.nfield[(long long)s * g.Np + P];
+  if (drag) {
+    tape_ut<M>(d, N, i, n, ut);
+    drag_force<M>(a, P, n, ut, Dr);
+  }
   for (int s = 0; s < M; ++s) {
-    n[s] = a.nfield[(long long)s * g.Np + P];
     for (int k = 0; k < 3; ++k) {
       phi[s][k] = a.force[6LL * s * N + k * N + i];
       F[s][k] = a.Fext[(long long)k * N + i] + a.body[s][k];
       C[s][k] = n[s] * phi[s][k];
-      Y[s][k] = n[s] * F[s][k];
+      Y[s][k] = drag ? Dr[s][k] + n[s] * F[s][k] : n[s] * F[s][k];
       X[s][k] = C[s][k] + Y[s][k];
       const double J = d.PJ[(long long)(M + 3 * s + k) * N + i] + 0.5 * (printed ? X[s][k] : Y[s][k]);
       ua[s][k] = n[s] != 0.0 ? J / n[s] : 0.0;
@@ -1439,8 +1518,10 @@ __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
     }
     nbar[s] += dot3(Ybar[s], F[s]) + dot3(Cbar[s], phi[s]);
     store_phibar(g, d, c, s, pb);
-    store_node(d, M, N, i, s, nbar[s], Pibar[s], Jbar[s]);
   }
+  // Y = n F + C^drag: Ybar is also the adjoint of the drag force
+  if (drag) adj_drag<M>(a, d, P, i, n, ut, Ybar, nbar, Jbar);
+  for (int s = 0; s < M; ++s) store_node(d, M, N, i, s, nbar[s], Pibar[s], Jbar[s]);
   for (int k = 0; k < 3; ++k) d.Fbar[(long long)k * N + i] += Fb[k];
 }
 
@@ -1459,32 +1540,41 @@ __global__ __launch_bounds__(BLOCK) void k_adj_readout(StepArgs a, AdjArgs d) {
   if (i >= g.N) return;
   const uint32_t m = a.bb[i];
   const Coord c = decode(g, i);
+  const bool drag = drag_on(a);
   if (m & 1u) {
     const double z[3] = {0.0, 0.0, 0.0};
     for (int s = 0; s < M; ++s) store_phibar(g, d, c, s, z);
+    if (drag) zero_Gbar<M>(d, g.N, i);
     return;
   }
   const long long N = g.N;
   const long long P = padded_index(g, c.x, c.y, c.z);
   const bool printed = a.flags & LBE_PRINTED_INV;
   double Fb[3] = {0.0, 0.0, 0.0};
+  double n[M], nb[M], Jb[M][3], Yb[M][3];
   for (int s = 0; s < M; ++s) {
-    const double n = a.nfield[(long long)s * g.Np + P];
-    double Jb[3], pb[3], nb = d.dn ? d.dn[(long long)s * N + i] : 0.0;
+    n[s] = a.nfield[(long long)s * g.Np + P];
+    nb[s] = d.dn ? d.dn[(long long)s * N + i] : 0.0;
+    double pb[3];
     for (int k = 0; k < 3; ++k) {
-      Jb[k] = d.dJ ? d.dJ[(long long)(3 * s + k) * N + i] : 0.0;
+      Jb[s][k] = d.dJ ? d.dJ[(long long)(3 * s + k) * N + i] : 0.0;
       const double phi = a.force[6LL * s * N + k * N + i];
       const double F = a.Fext[(long long)k * N + i] + a.body[s][k];
-      // J = J~ + (C + nF)/2 (printed) or J~ + nF/2
-      const double Yb = 0.5 * Jb[k];
-      const double Cb = printed ? 0.5 * Jb[k] : 0.0;
-      nb += Yb * F + Cb * phi;
-      Fb[k] += n * Yb;
-      pb[k] = n * Cb;
+      // J = J~ + (C + Y)/2 (printed) or J~ + Y/2, Y = nF (+ C^drag)
+      Yb[s][k] = 0.5 * Jb[s][k];
+      const double Cb = printed ? 0.5 * Jb[s][k] : 0.0;
+      nb[s] += Yb[s][k] * F + Cb * phi;
+      Fb[k] += n[s] * Yb[s][k];
+      pb[k] = n[s] * Cb;
     }
     store_phibar(g, d, c, s, pb);
-    store_node(d, M, N, i, s, nb, 0.0, Jb);
   }
+  if (drag) {
+    double ut[M][3];
+    tape_ut<M>(d, N, i, n, ut);
+    adj_drag<M>(a, d, P, i, n, ut, Yb, nb, Jb);
+  }
+  for (int s = 0; s < M; ++s) store_node(d, M, N, i, s, nb[s], 0.0, Jb[s]);
   for (int k = 0; k < 3; ++k) d.Fbar[(long long)k * N + i] += Fb[k];
 }
 
@@ -1536,7 +1626,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj_stream(StepArgs a, AdjArgs d) {
 }
 
 // the tilde moments Pi~, J~ of a state (tape) and its densities n (padded
-// field, as k_moments writes them)
+// field, as k_moments writes them), and J~ padded as well when the tape has
+// a field for it
 template <int M>
 __global__ __launch_bounds__(BLOCK) void k_tape_moments(StepArgs a, const double *__restrict__ pop,
                                                       double *__restrict__ PJ) {
@@ -1559,6 +1650,8 @@ __global__ __launch_bounds__(BLOCK) void k_tape_moments(StepArgs a, const double
     store_images(g, a.nfield + (long long)s * g.Np, c, n);
     PJ[(long long)s * N + i] = Pi;
     for (int k = 0; k < 3; ++k) PJ[(long long)(M + 3 * s + k) * N + i] = J[k];
+    if (a.Jfield)  // the drag of the recomputed step reads J~ there
+      for (int k = 0; k < 3; ++k) store_images(g, a.Jfield + (long long)(3 * s + k) * g.Np, c, J[k]);
   }
 }
 
@@ -2274,6 +2367,9 @@ void launch_adj_nonlocal(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
     return;
   }
   bool wn[MAXM] = {false, false, false, false}, wg[MAXPAIRS] = {};
+  // with the drag, the collision (or read-out) adjoint has written Gbar
+  if (M > 1 && (a.flags & LBE_DRAG))
+    for (int k = 0; k < npairs; ++k) wg[k] = true;
   for (int al = 0; al < M; ++al)
     for (int be = 0; be < M; ++be) {
       const int k = pair_index(M, al, be);

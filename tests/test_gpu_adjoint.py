@@ -95,6 +95,24 @@ def test_adjoint_with_attraction_matches_reference(flags, T, segment):
     assert_close(gg, rg, 1e-10, "dL/dg0")
 
 
+@pytest.mark.parametrize("flags,att,T,segment", [(64, False, 6, 3), (64 | 2, False, 5, 5),
+                                                 (64 | 4, True, 6, 2)])
+def test_adjoint_with_drag_matches_reference(flags, att, T, segment):
+    """The two-species channel with the interspecies drag (flag 64): its
+    reverse joins the collision and read-out adjoints (n, J~ and the contact
+    values), with either inversion, and with the attractive tails on too."""
+    w = small_channel()
+    if att:
+        w.att_eps, w.att_rc = [[0.3 * W.KT, 0.2 * W.KT], [0.2 * W.KT, 0.25 * W.KT]], 5.0
+    pw = pop_weights(w) * 1e-3
+    print(f"small channel with drag flags {flags} att {att} T {T} segment {segment}", flush=True)
+    rV, rf, rg = reference(w, flags, T, pw)
+    gV, gf, gg = gpu_gradient(w, flags, T, segment, pw)
+    assert_close(gV, rV, 1e-10, "dL/dV")
+    assert_close(gf, rf, 1e-10, "dL/df0")
+    assert_close(gg, rg, 1e-10, "dL/dg0")
+
+
 def test_adjoint_attraction_one_species_periodic():
     """One species, periodic box, a cutoff of 7.5 (the widest transpose
     window, 7 nodes per axis) and a potential well."""
