@@ -52,6 +52,8 @@ OPP = np.array([int(np.flatnonzero((C_VEL == -c).all(1))[0]) for c in C_VEL])
 
 PRINTED_INV = 1 << 1
 KAPPA4 = 1 << 2
+EULER = 1 << 4
+SINGLE = 1 << 5
 DRAG = 1 << 6
 
 
@@ -140,8 +142,13 @@ class Stepper:
         self.vT2 = kT
         self.beta = 1.0 / kT
         omega = 1.0 / tau
-        self.a = omega / (1 + 0.5 * omega)
-        self.b = 1.0 / (1 + 0.5 * omega)
+        # the scheme variants of Sec. 4: Euler (f* = f + omega (f_eq - f) + S)
+        # or the trapezoidal rule; one distribution (f carries the current,
+        # no g) or two
+        self.euler = bool(flags & EULER)
+        self.single = bool(flags & SINGLE)
+        self.a = omega if self.euler else omega / (1 + 0.5 * omega)
+        self.b = 1.0 if self.euler else 1.0 / (1 + 0.5 * omega)
         self.printed = bool(flags & PRINTED_INV)
         self.kappa = 4.0 if flags & KAPPA4 else 2.0
         self.drag = bool(flags & DRAG) and self.M > 1
@@ -259,16 +266,22 @@ class Stepper:
     def invert(self, f, g, n, Cmf, F, G):
         """Physical moments: J, u^a, Pi, u (Sec. 4.2 with the chosen inversion)."""
         Pit = g.sum(1)                                               # (M, N)
-        Jt = torch.einsum("pk,mpn->mkn", self.c, g)                  # (M, 3, N)
+        Jt = torch.einsum("pk,mpn->mkn", self.c, f if self.single else g)   # (M, 3, N)
         nF = n[:, None, :] * F
         Y = nF + self.drag_force(n, G, Jt) if self.drag else nF
         X = Cmf + Y
-        J = Jt + 0.5 * (X if self.printed else Y)
+        if self.euler:                      # no half-step terms
+            J = Jt
+        else:                               # SD-TR takes the f inversion, with X
+            J = Jt + 0.5 * (X if (self.printed or self.single) else Y)
         pos = n > 0
         nsafe = torch.where(pos, n, torch.ones_like(n))
         ua = J / nsafe[:, None, :] * pos[:, None, :]
         Cu = (Cmf * ua).sum(1)
-        Pi = Pit - 0.5 * self.beta * Cu if self.printed else Pit + 0.5 * self.beta * Cu
+        if self.euler or self.single:
+            Pi = Pit
+        else:
+            Pi = Pit - 0.5 * self.beta * Cu if self.printed else Pit + 0.5 * self.beta * Cu
         ntot = n.sum(0)
         tpos = ntot > 0
         u = J.sum(0) / torch.where(tpos, ntot, torch.ones_like(ntot)) * tpos
@@ -298,6 +311,8 @@ class Stepper:
         sg = w * ((Cmf[:, None, :, :] * (ua[:, None, :, :] / self.vT2 + self.kappa * h2ua)).sum(2)
                   + (Y[:, None, :, :] * (H1b + 2 * h2ua)).sum(2))
         fs = (f + self.a * (feq - f) + self.b * sf) * self.fluid
+        if self.single:                     # no g is evolved
+            return self.stream(fs), torch.zeros_like(g)
         gs = (g + self.a * (geq - g) + self.b * sg) * self.fluid
         return self.stream(fs), self.stream(gs)
 

@@ -47,7 +47,9 @@ def torch_loss(st, w, f, g, V, n_t, fluid, plane, pw=None):
 
 @pytest.mark.parametrize("flags,att", [(0, False), (AR.PRINTED_INV, False), (AR.KAPPA4, False),
                                        (0, True), (AR.PRINTED_INV | AR.KAPPA4, True),
-                                       (AR.DRAG, False), (AR.DRAG | AR.PRINTED_INV, True)])
+                                       (AR.DRAG, False), (AR.DRAG | AR.PRINTED_INV, True),
+                                       (AR.EULER, False), (AR.SINGLE, True),
+                                       (AR.SINGLE | AR.EULER | AR.DRAG, False)])
 def test_forward_equals_c_oracle(flags, att):
     w = small_channel()
     o = c_oracle(w, flags, att=att)
@@ -67,7 +69,9 @@ def test_forward_equals_c_oracle(flags, att):
 
 
 @pytest.mark.parametrize("flags,att", [(0, False), (AR.PRINTED_INV, False), (0, True),
-                                       (AR.DRAG, False), (AR.DRAG | AR.PRINTED_INV, False)])
+                                       (AR.DRAG, False), (AR.DRAG | AR.PRINTED_INV, False),
+                                       (AR.EULER, False), (AR.SINGLE, False),
+                                       (AR.SINGLE | AR.EULER, False)])
 def test_gradient_equals_oracle_fd(flags, att):
     w = small_channel()
     n_t, fluid, plane = objective_terms(w)
