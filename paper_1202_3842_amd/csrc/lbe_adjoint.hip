@@ -39,8 +39,6 @@ lbe_status make_adj_plan(const lbe_config *cfg, int nsteps, int segment, AdjPlan
   if (cfg->prec != LBE_FP64) return fail(LBE_ERR_UNSUPPORTED, "the adjoint needs FP64 populations");
   if ((cfg->flags & LBE_VISC) && !(cfg->flags & LBE_IDEAL))
     return fail(LBE_ERR_UNSUPPORTED, "the adjoint covers the C^mf scheme only (no LBE_VISC)");
-  if (cfg->flags & (LBE_EULER | LBE_SINGLE))
-    return fail(LBE_ERR_UNSUPPORTED, "the adjoint covers the DD-TR scheme only");
   if (nsteps < 1 || segment < 1) return fail(LBE_ERR_ARG, "nsteps and segment must be >= 1");
   const Plan &P = ap.pl;
   const size_t N = P.g.N, Np = P.g.Np, M = P.M, npairs = P.npairs;

@@ -1237,7 +1237,8 @@ inline dim3 grid_for(int N) { return dim3((N + BLOCK - 1) / BLOCK); }
 
 // ------------------------------------------------------------------------
 // adjoint (reverse mode) of one step, for FP64 populations and the C^mf
-// scheme (no C^visc; with or without the interspecies drag).  "bar" marks
+// scheme (no C^visc; with or without the interspecies drag; trapezoidal or
+// Euler, two distributions or one).  "bar" marks
 // the adjoint dL/d(quantity).  The adjoint
 // state between steps is (mu, nbar) in the post-streaming frame (AdjArgs).
 // ------------------------------------------------------------------------
@@ -1421,6 +1422,10 @@ __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
   const long long Ns = pop_stride(g), N = g.N;
   const long long P = padded_index(g, c.x, c.y, c.z);
   const bool printed = a.flags & LBE_PRINTED_INV;
+  const bool euler = a.flags & LBE_EULER, single = a.flags & LBE_SINGLE;
+  // the inversion J = J~ + h (X or Y): h = 0 for Euler; X for SD-TR
+  const double half = euler ? 0.0 : 0.5;
+  const bool withX = printed || single, shiftPi = !(euler || single);
   const double sgn = printed ? -1.0 : 1.0;
   double n[M], phi[M][3], F[M][3], C[M][3], Y[M][3], X[M][3], ua[M][3], u[3];
   double ut[M][3], Dr[M][3];
@@ -1437,7 +1442,7 @@ __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
       C[s][k] = n[s] * phi[s][k];
       Y[s][k] = drag ? Dr[s][k] + n[s] * F[s][k] : n[s] * F[s][k];
       X[s][k] = C[s][k] + Y[s][k];
-      const double J = d.PJ[(long long)(M + 3 * s + k) * N + i] + 0.5 * (printed ? X[s][k] : Y[s][k]);
+      const double J = d.PJ[(long long)(M + 3 * s + k) * N + i] + half * (withX ? X[s][k] : Y[s][k]);
       ua[s][k] = n[s] != 0.0 ? J / n[s] : 0.0;
       Jtot[k] += J;
     }
@@ -1487,9 +1492,11 @@ __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
       Xbar[s][k] = 3.0 * bc * bf[s].m1[k] + 9.0 * B2ua[k] - 3.0 * B0 * ua[s][k];
       Cbar[s][k] = 4.5 * kap * D2ua[k] + (3.0 - 1.5 * kap) * D0 * ua[s][k];
       Ybar[s][k] = 3.0 * bc * bg[s].m1[k] + 9.0 * D2ua[k] - 3.0 * D0 * ua[s][k];
-      // Pi = Pi~ +- (beta/2) C.u^a
-      Cbar[s][k] += sgn * hb * Pibar[s] * ua[s][k];
-      uabar[s][k] += sgn * hb * Pibar[s] * C[s][k];
+      // Pi = Pi~ +- (beta/2) C.u^a (Pi = Pi~ for Euler and SD)
+      if (shiftPi) {
+        Cbar[s][k] += sgn * hb * Pibar[s] * ua[s][k];
+        uabar[s][k] += sgn * hb * Pibar[s] * C[s][k];
+      }
     }
   }
   if (ntot != 0.0) {
@@ -1507,10 +1514,10 @@ __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
     }
     double pb[3];
     for (int k = 0; k < 3; ++k) {
-      if (printed)
-        Xbar[s][k] += 0.5 * Jbar[s][k];
+      if (withX)
+        Xbar[s][k] += half * Jbar[s][k];
       else
-        Ybar[s][k] += 0.5 * Jbar[s][k];
+        Ybar[s][k] += half * Jbar[s][k];
       Cbar[s][k] += Xbar[s][k];
       Ybar[s][k] += Xbar[s][k];
       Fb[k] += n[s] * Ybar[s][k];
@@ -1550,6 +1557,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj_readout(StepArgs a, AdjArgs d) {
   const long long N = g.N;
   const long long P = padded_index(g, c.x, c.y, c.z);
   const bool printed = a.flags & LBE_PRINTED_INV;
+  const double half = (a.flags & LBE_EULER) ? 0.0 : 0.5;
+  const bool withX = printed || (a.flags & LBE_SINGLE);
   double Fb[3] = {0.0, 0.0, 0.0};
   double n[M], nb[M], Jb[M][3], Yb[M][3];
   for (int s = 0; s < M; ++s) {
@@ -1560,9 +1569,10 @@ __global__ __launch_bounds__(BLOCK) void k_adj_readout(StepArgs a, AdjArgs d) {
       Jb[s][k] = d.dJ ? d.dJ[(long long)(3 * s + k) * N + i] : 0.0;
       const double phi = a.force[6LL * s * N + k * N + i];
       const double F = a.Fext[(long long)k * N + i] + a.body[s][k];
-      // J = J~ + (C + Y)/2 (printed) or J~ + Y/2, Y = nF (+ C^drag)
-      Yb[s][k] = 0.5 * Jb[s][k];
-      const double Cb = printed ? 0.5 * Jb[s][k] : 0.0;
+      // J = J~ + (C + Y)/2 (printed, SD-TR) or J~ + Y/2, Y = nF (+ C^drag);
+      // J = J~ for Euler
+      Yb[s][k] = half * Jb[s][k];
+      const double Cb = withX ? half * Jb[s][k] : 0.0;
       nb[s] += Yb[s][k] * F + Cb * phi;
       Fb[k] += n[s] * Yb[s][k];
       pb[k] = n[s] * Cb;
@@ -1580,12 +1590,13 @@ __global__ __launch_bounds__(BLOCK) void k_adj_readout(StepArgs a, AdjArgs d) {
 
 // The adjoint state before the step, per node r and population q:
 //   mu_f = (1 - a) lambda_f + nbar_loc + nbar,  mu_g = (1 - a) lambda_g + Pi~bar + c_q.J~bar
+// (one distribution: mu_f = (1 - a) lambda_f + nbar_loc + nbar + c_q.J~bar, mu_g = 0)
 // with lambda the adjoint of the pre-streaming slots (the streaming
 // transpose of mu_in) -- or, at the final step, lambda the seed dpop and no
 // (1 - a) (the read-out does not collide).
 template <int q, int M, bool TERMINAL>
 __device__ inline void adj_stream_q(const Geom &g, const Coord &c, int i, uint32_t m,
-                                    const AdjArgs &d, long long Ns, long long N, double keep,
+                                    const AdjArgs &d, long long Ns, long long N, double keep, bool single,
                                     const double nb[M], const double Pib[M], const double Jb[M][3]) {
   if constexpr (q < Q) {
     for (int s = 0; s < M; ++s) {
@@ -1597,10 +1608,15 @@ __device__ inline void adj_stream_q(const Geom &g, const Coord &c, int i, uint32
         lf = keep * adj_slot<q>(g, c, i, m, d.mu_in + (long long)s * Q * Ns, Ns);
         lg = keep * adj_slot<q>(g, c, i, m, d.mu_in + (long long)(M + s) * Q * Ns, Ns);
       }
-      d.mu_out[((long long)s * Q + q) * Ns + i] = lf + nb[s];
-      d.mu_out[((long long)(M + s) * Q + q) * Ns + i] = lg + Pib[s] + cdot<q>(Jb[s]);
+      if (single) {  // f carries the current; no g
+        d.mu_out[((long long)s * Q + q) * Ns + i] = lf + nb[s] + cdot<q>(Jb[s]);
+        d.mu_out[((long long)(M + s) * Q + q) * Ns + i] = 0.0;
+      } else {
+        d.mu_out[((long long)s * Q + q) * Ns + i] = lf + nb[s];
+        d.mu_out[((long long)(M + s) * Q + q) * Ns + i] = lg + Pib[s] + cdot<q>(Jb[s]);
+      }
     }
-    adj_stream_q<q + 1, M, TERMINAL>(g, c, i, m, d, Ns, N, keep, nb, Pib, Jb);
+    adj_stream_q<q + 1, M, TERMINAL>(g, c, i, m, d, Ns, N, keep, single, nb, Pib, Jb);
   }
 }
 
@@ -1622,7 +1638,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj_stream(StepArgs a, AdjArgs d) {
     Pib[s] = d.node[(long long)(M + s) * N + i];
     for (int k = 0; k < 3; ++k) Jb[s][k] = d.node[(long long)(2 * M + 3 * s + k) * N + i];
   }
-  adj_stream_q<0, M, TERMINAL>(g, c, i, m, d, Ns, N, 1.0 - a.acoef, nb, Pib, Jb);
+  adj_stream_q<0, M, TERMINAL>(g, c, i, m, d, Ns, N, 1.0 - a.acoef, (a.flags & LBE_SINGLE) != 0, nb, Pib,
+                               Jb);
 }
 
 // the tilde moments Pi~, J~ of a state (tape) and its densities n (padded
@@ -1643,8 +1660,11 @@ __global__ __launch_bounds__(BLOCK) void k_tape_moments(StepArgs a, const double
       double v[19];
       pull19(g, c, i, m, pop + (long long)s * Q * Ns, Ns, v);
       moments0(v, n);
-      pull19(g, c, i, m, pop + (long long)(M + s) * Q * Ns, Ns, v);
-      moments0(v, Pi);
+      // one distribution: f carries the current and there is no Pi~
+      if (!(a.flags & LBE_SINGLE)) {
+        pull19(g, c, i, m, pop + (long long)(M + s) * Q * Ns, Ns, v);
+        moments0(v, Pi);
+      }
       moments1(v, J);
     }
     store_images(g, a.nfield + (long long)s * g.Np, c, n);

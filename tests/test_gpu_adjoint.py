@@ -35,7 +35,9 @@ def reference(w, flags, T, pw):
         pwt = torch.tensor(pw.reshape(2, w.nspecies, 19, -1))
         L = L + (pwt[0] * f).sum() + (pwt[1] * g).sum()
     L.backward()
-    return V.grad.numpy().reshape(w.shape), f0.grad.numpy(), g0.grad.numpy()
+    # with one distribution g0 takes no part in L
+    rg = g0.grad.numpy() if g0.grad is not None else np.zeros(tuple(g0.shape))
+    return V.grad.numpy().reshape(w.shape), f0.grad.numpy(), rg
 
 
 def gpu_gradient(w, flags, T, segment, pw):
@@ -111,6 +113,29 @@ def test_adjoint_with_drag_matches_reference(flags, att, T, segment):
     assert_close(gV, rV, 1e-10, "dL/dV")
     assert_close(gf, rf, 1e-10, "dL/df0")
     assert_close(gg, rg, 1e-10, "dL/dg0")
+
+
+@pytest.mark.parametrize("flags,T,segment", [(16, 6, 3), (16 | 2 | 64, 5, 5), (32, 6, 2),
+                                               (32 | 16, 5, 3), (32 | 64, 6, 6)])
+def test_adjoint_scheme_variants_match_reference(flags, T, segment):
+    """The scheme variants of Sec. 4 on the two-species channel: DD-EU
+    (flag 16; with the printed inversion and the drag too), SD-TR (32),
+    SD-EU and SD-TR with the drag.  With one distribution there is no g: the
+    g part of the seed is zero and the g gradient is zero."""
+    w = small_channel()
+    pw = pop_weights(w) * 1e-3
+    single = bool(flags & 32)
+    if single:
+        pw[1] = 0.0
+    print(f"small channel scheme variant flags {flags} T {T} segment {segment}", flush=True)
+    rV, rf, rg = reference(w, flags, T, pw)
+    gV, gf, gg = gpu_gradient(w, flags, T, segment, pw)
+    assert_close(gV, rV, 1e-10, "dL/dV")
+    assert_close(gf, rf, 1e-10, "dL/df0")
+    if single:
+        assert not gg.any() and not rg.any()
+    else:
+        assert_close(gg, rg, 1e-10, "dL/dg0")
 
 
 def test_adjoint_attraction_one_species_periodic():
