@@ -23,8 +23,10 @@ post-streaming populations f~, g~:
     the kappa of the C^mf part of S_g;
   * trapezoidal update f~* = f~ + a (f_eq - f~) + b S_f (Sec. 4.1) and the
     pull streaming with mid-point bounce-back (Sec. 4.3).
-Only the C^mf scheme (no C^visc) is expressed, optionally with the
-interspecies drag of the Appendix (eq. dragforce2: the local force
+The C^mf scheme is expressed, optionally with the collisional viscous
+force of the Appendix (C^visc_a = n_a sum_b 2 sigma_ab^2 sqrt(kT/pi) w_ab
+sum_{e in shell} e^ [e^.(u~_b(r+e) - u~_b(r))] g(r, r+e) n_b(r+e), u~ =
+J~/n), the interspecies drag of the Appendix (eq. dragforce2: the local force
 -n_a sum_b gamma_ab G_ab n_b (u~_a - u~_b), u~ = J~/n, gamma_ab =
 sigma_ab^2 2 sqrt(kT/pi) 4 pi/3, which joins C^visc in the sources) and the
 attractive molecular field of the Appendix (the r^-6 tail U = -eps (sigma/r)^6
@@ -50,6 +52,7 @@ C_VEL = np.array([
 W_VEL = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
 OPP = np.array([int(np.flatnonzero((C_VEL == -c).all(1))[0]) for c in C_VEL])
 
+VISC = 1 << 0
 PRINTED_INV = 1 << 1
 KAPPA4 = 1 << 2
 EULER = 1 << 4
@@ -152,6 +155,7 @@ class Stepper:
         self.printed = bool(flags & PRINTED_INV)
         self.kappa = 4.0 if flags & KAPPA4 else 2.0
         self.drag = bool(flags & DRAG) and self.M > 1
+        self.visc = bool(flags & VISC)
         # drag coefficients: the collision integral of C^visc over the unit
         # sphere, 2 sigma_ab^2 sqrt(kT/pi) (4 pi/3)
         self.gamma = [[(0.5 * (sa + sb)) ** 2 * 2.0 * math.sqrt(kT / math.pi) * (4.0 * math.pi / 3.0)
@@ -250,6 +254,26 @@ class Stepper:
             out.append(Ca)
         return torch.stack(out)
 
+    def visc_force(self, n, G, Jt):
+        """C^visc of every species, (M, 3, N), over the same shells as C^mf."""
+        pos = n > 0
+        ut = Jt / torch.where(pos, n, torch.ones_like(n))[:, None, :] * pos[:, None, :]
+        pref = 2.0 * math.sqrt(self.kT / math.pi)
+        out = []
+        for a in range(self.M):
+            acc = n.new_zeros(3, n.shape[1])
+            for b in range(self.M):
+                idx, eh, s, w = self.shell[a, b]
+                if idx.shape[0] == 0:
+                    continue
+                ub = ut[b]
+                ue = torch.stack([self._ext(ub[k])[idx] for k in range(3)])        # (3, E, N)
+                kdu = (eh.T[:, :, None] * (ue - ub[:, None, :])).sum(0)            # (E, N)
+                g = 0.5 * (G[a, b][None, :] + self._ext(G[a, b])[idx])
+                acc = acc + s * s * w * (eh.T @ (kdu * g * self._ext(n[b])[idx]))
+            out.append(pref * n[a][None, :] * acc)
+        return torch.stack(out)
+
     def drag_force(self, n, G, Jt):
         """C^drag of every species, (M, 3, N), from u~ = J~/n."""
         pos = n > 0
@@ -269,6 +293,8 @@ class Stepper:
         Jt = torch.einsum("pk,mpn->mkn", self.c, f if self.single else g)   # (M, 3, N)
         nF = n[:, None, :] * F
         Y = nF + self.drag_force(n, G, Jt) if self.drag else nF
+        if self.visc:
+            Y = Y + self.visc_force(n, G, Jt)
         X = Cmf + Y
         if self.euler:                      # no half-step terms
             J = Jt

@@ -49,7 +49,9 @@ def torch_loss(st, w, f, g, V, n_t, fluid, plane, pw=None):
                                        (0, True), (AR.PRINTED_INV | AR.KAPPA4, True),
                                        (AR.DRAG, False), (AR.DRAG | AR.PRINTED_INV, True),
                                        (AR.EULER, False), (AR.SINGLE, True),
-                                       (AR.SINGLE | AR.EULER | AR.DRAG, False)])
+                                       (AR.SINGLE | AR.EULER | AR.DRAG, False),
+                                       (AR.VISC, False), (AR.VISC | AR.PRINTED_INV | AR.DRAG, True),
+                                       (AR.VISC | AR.SINGLE, False)])
 def test_forward_equals_c_oracle(flags, att):
     w = small_channel()
     o = c_oracle(w, flags, att=att)
@@ -71,7 +73,8 @@ def test_forward_equals_c_oracle(flags, att):
 @pytest.mark.parametrize("flags,att", [(0, False), (AR.PRINTED_INV, False), (0, True),
                                        (AR.DRAG, False), (AR.DRAG | AR.PRINTED_INV, False),
                                        (AR.EULER, False), (AR.SINGLE, False),
-                                       (AR.SINGLE | AR.EULER, False)])
+                                       (AR.SINGLE | AR.EULER, False),
+                                       (AR.VISC, False), (AR.VISC | AR.PRINTED_INV | AR.DRAG, False)])
 def test_gradient_equals_oracle_fd(flags, att):
     w = small_channel()
     n_t, fluid, plane = objective_terms(w)
