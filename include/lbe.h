@@ -313,10 +313,10 @@ void lbe_batch_destroy(lbe_batch *batch);
  * Sec. 4.1).  The objective enters through its derivatives with respect to
  * the read-outs of the final state: n^a (lbe_get_density), J^a
  * (lbe_get_momentum) and the post-streaming populations
- * (lbe_get_populations).  Supported: FP64 populations, the C^mf scheme
- * with either inversion and either kappa, with or without the attractive
- * field and the interspecies drag, in every scheme variant (LBE_EULER,
- * LBE_SINGLE; not LBE_VISC).  Under LBE_SINGLE the scheme has no g, so the
+ * (lbe_get_populations).  Supported: FP64 populations, with every force
+ * (C^mf, C^visc, the attractive field, the interspecies drag), either
+ * inversion and either kappa, in every scheme variant (LBE_EULER,
+ * LBE_SINGLE).  Under LBE_SINGLE the scheme has no g, so the
  * g part of dL_dpop is ignored and the g gradient is zero.  The forward
  * keeps a copy of the state every `segment` steps; the backward recomputes
  * one segment at a time from its copy, so device memory grows as

@@ -6,8 +6,8 @@
 // Backward: the adjoint of the read-out seeds the adjoint state at the final
 // step; then, segment by segment from the last, the segment's states are
 // recomputed from its checkpoint while a tape keeps, per step, the fields
-// the adjoint needs (n, G, C^mf/n, the tilde moments Pi~, J~, and J~ as a
-// padded field when the interspecies drag is on), and the
+// the adjoint needs (n, G, the forces per particle, the tilde moments Pi~,
+// J~, and J~ as a padded field with C^visc or the interspecies drag), and the
 // adjoint steps run in reverse over the tape.  The adjoint of the external
 // force is accumulated over all steps and turned into dL/dV by the transpose
 // of -grad_h at the end.
@@ -28,17 +28,16 @@ struct AdjPlan {
   size_t slot_bytes = 0, mu_bytes = 0, total = 0;
   size_t off_cp = 0, off_roll = 0, off_tape = 0, off_mu = 0, off_node = 0, off_nbar = 0,
          off_phibar = 0, off_Gbar = 0, off_nbb = 0, off_Fbar = 0, off_Vbar = 0, off_stage = 0;
+  size_t off_psibar = 0, off_ut = 0, off_Jnl = 0;  // with C^visc
   // inside a tape slot
   size_t so_n = 0, so_G = 0, so_force = 0, so_PJ = 0, so_J = 0;
-  bool drag = false;
+  bool drag = false, visc = false;
 };
 
 lbe_status make_adj_plan(const lbe_config *cfg, int nsteps, int segment, AdjPlan &ap) {
   lbe_status st = make_plan(cfg, ap.pl);
   if (st != LBE_OK) return st;
   if (cfg->prec != LBE_FP64) return fail(LBE_ERR_UNSUPPORTED, "the adjoint needs FP64 populations");
-  if ((cfg->flags & LBE_VISC) && !(cfg->flags & LBE_IDEAL))
-    return fail(LBE_ERR_UNSUPPORTED, "the adjoint covers the C^mf scheme only (no LBE_VISC)");
   if (nsteps < 1 || segment < 1) return fail(LBE_ERR_ARG, "nsteps and segment must be >= 1");
   const Plan &P = ap.pl;
   const size_t N = P.g.N, Np = P.g.Np, M = P.M, npairs = P.npairs;
@@ -56,9 +55,10 @@ lbe_status make_adj_plan(const lbe_config *cfg, int nsteps, int segment, AdjPlan
   ap.so_force = ap.so_G + align256(sizeof(double) * npairs * Np);
   ap.so_PJ = ap.so_force + align256(sizeof(double) * 6 * M * N);
   ap.so_J = ap.so_PJ + align256(sizeof(double) * 4 * M * N);
-  // the drag of the recomputed steps reads J~ as a padded field
+  // C^visc and the drag of the recomputed steps read J~ as a padded field
   ap.drag = M > 1 && (cfg->flags & LBE_DRAG) && !(cfg->flags & LBE_IDEAL);
-  ap.slot_bytes = ap.so_J + (ap.drag ? align256(sizeof(double) * 3 * M * Np) : 0);
+  ap.visc = (cfg->flags & LBE_VISC) && !(cfg->flags & LBE_IDEAL);
+  ap.slot_bytes = ap.so_J + (ap.drag || ap.visc ? align256(sizeof(double) * 3 * M * Np) : 0);
   ap.mu_bytes = P.pop_bytes;  // same layout as a state buffer, FP64
   ap.off_cp = take(P.pop_bytes * (size_t)(ap.nseg + 1));
   ap.off_roll = take(P.pop_bytes * 2);
@@ -72,6 +72,11 @@ lbe_status make_adj_plan(const lbe_config *cfg, int nsteps, int segment, AdjPlan
   ap.off_Fbar = take(sizeof(double) * 3 * N);
   ap.off_Vbar = take(sizeof(double) * N);
   ap.off_stage = take(sizeof(double) * (2 * M * Q + 4 * M) * N);
+  if (ap.visc) {
+    ap.off_psibar = take(sizeof(double) * 3 * M * Np);
+    ap.off_ut = take(sizeof(double) * 3 * M * Np);
+    ap.off_Jnl = take(sizeof(double) * 3 * M * N);
+  }
   ap.total = o;
   return LBE_OK;
 }
@@ -97,7 +102,7 @@ struct lbe_adjoint {
     a.nfield = (double *)(slot(j) + ap.so_n);
     a.Gfield = (double *)(slot(j) + ap.so_G);
     a.force = (double *)(slot(j) + ap.so_force);
-    a.Jfield = ap.drag ? (double *)(slot(j) + ap.so_J) : nullptr;
+    a.Jfield = ap.drag || ap.visc ? (double *)(slot(j) + ap.so_J) : nullptr;
     return a;
   }
   double *slot_PJ(int j) const { return (double *)(slot(j) + ap.so_PJ); }
@@ -111,6 +116,11 @@ struct lbe_adjoint {
     d.Gbar = at(ap.off_Gbar);
     d.nbb = at(ap.off_nbb);
     d.Fbar = at(ap.off_Fbar);
+    if (ap.visc) {
+      d.psibar = at(ap.off_psibar);
+      d.ut = at(ap.off_ut);
+      d.Jnl = at(ap.off_Jnl);
+    }
     return d;
   }
 

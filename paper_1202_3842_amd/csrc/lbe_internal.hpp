@@ -130,6 +130,10 @@ struct AdjArgs {
   const double *dn;        // seeds of the read-out adjoint: dL/dn (M*N) or null
   const double *dJ;        // dL/dJ (3M*N) or null
   const double *dpop;      // dL/d(post-streaming populations) (2M*19*N) or null
+  // with C^visc (null otherwise)
+  double *psibar;          // 3M*Np padded: adjoint of the viscous force per particle C^visc_a/n_a
+  double *ut;              // 3M*Np padded: u~ = J~/n of the step
+  double *Jnl;             // 3M*N: the nonlocal part of the J~ adjoint
 };
 
 // Launchers (lbe_kernels.hip)

@@ -479,7 +479,7 @@ typedef double dbl2 __attribute__((ext_vector_type(2)));
 __host__ __device__ constexpr bool table_in_smem(int mode, int ny = 1) { return mode != 0 || ny > 1; }
 // fields staged per plane by force_body
 __host__ __device__ constexpr int force_fields(int mode) {
-  return mode == 0 ? 2 : (mode == 3 ? 1 : (mode == 4 ? 3 : 5));
+  return mode == 0 ? 2 : (mode == 3 ? 1 : (mode == 4 ? 3 : (mode == 5 ? 7 : 5)));
 }
 // dynamic LDS of force_body: two planes of NF fields, then the ring table
 // when it is staged in LDS
@@ -494,7 +494,10 @@ __host__ __device__ constexpr size_t force_lds(int mode, int R, int ty, int entr
 // n_b(r + e) over the pair's thick shell (field n_b; the table holds
 // U'(|e|) e^), added to C^mf/n_a; MODE 4: the transpose of MODE 3 for the
 // adjoint, n_b^bar(r) -= sum_e U'(|e|) e^.phibar_a(r + e) (field phibar_a, the
-// same table).  NT threads in rows of FTX; NY = output rows per thread:
+// same table); MODES 5 and 6: the transpose of the C^visc gather for the
+// adjoint (see k_adj_visc), MODE 5 over the fields phibar'_a (the adjoint of
+// C^visc/n_a), G_ab and u~_b, MODE 6 over n_b, G_ab and J~_b with the centre
+// phibar'_a.  NT threads in rows of FTX; NY = output rows per thread:
 // the tile is FTX x (NT/FTX NY) and thread (tx, ty) owns rows ty,
 // ty + NT/FTX, ...; one ring-table read and one address then serve NY nodes.
 // Taller tiles shrink the staged window per node.
@@ -505,6 +508,7 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   constexpr bool ADJ = MODE == 2;
   constexpr bool ATT = MODE == 3;
   constexpr bool AADJ = MODE == 4;
+  constexpr bool VT1 = MODE == 5, VT2 = MODE == 6;
   constexpr int NF = force_fields(MODE);
   constexpr int RY = NT / FTX;                  // thread rows of the workgroup
   constexpr int TY = RY * NY;
@@ -529,10 +533,19 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   const int t = threadIdx.x, tx = t % FTX, ty = t / FTX;
   const int x0 = bx * FTX, y0 = by * TY;
   const int x = x0 + tx;
-  const double *__restrict__ fld[5];
+  const double *__restrict__ fld[7];
   fld[0] = a.nfield + (long long)beta * g.Np;
   fld[1] = a.Gfield + (long long)k * g.Np;
-  if (VISC) {
+  if (VT1) {
+    fld[0] = ad->psibar + (long long)(3 * alpha) * g.Np;
+    fld[1] = fld[0] + g.Np;
+    fld[2] = fld[1] + g.Np;
+    fld[3] = a.Gfield + (long long)k * g.Np;
+    fld[4] = ad->ut + (long long)(3 * beta) * g.Np;
+    fld[5] = fld[4] + g.Np;
+    fld[6] = fld[5] + g.Np;
+  }
+  if (VISC || VT2) {
     fld[2] = a.Jfield + (long long)(3 * beta) * g.Np;
     fld[3] = fld[2] + g.Np;
     fld[4] = fld[3] + g.Np;
@@ -610,8 +623,10 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   // accumulators [row][set]: m (C^mf, or sum e^ n_b(r+e) for the adjoint)
   // and v (C^visc, or the two adjoint sums)
   double mx[NY][NS], my[NY][NS], mz[NY][NS], vx[NY][NS], vy[NY][NS], vz[NY][NS];
-  // centre values of each row: G_ab, and u_b (MODE 1) or n_b and phibar_a (MODE 2)
-  double G0[NY], n0[NY], u0x[NY], u0y[NY], u0z[NY];
+  double ox[NY][NS], oy[NY][NS];  // MODE 5 only
+  // centre values of each row: G_ab, and u_b (MODES 1, 6) or n_b and
+  // phibar_a (MODE 2); phibar'_a (MODE 6)
+  double G0[NY], n0[NY], u0x[NY], u0y[NY], u0z[NY], p0x[NY], p0y[NY], p0z[NY];
   for (int rho = 0; rho < rounds; ++rho) {
     const int z = zb + rho / (R + 1), ez = rho % (R + 1);
     __syncthreads();  // previous round's readers are done with the buffers
@@ -642,12 +657,26 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
 #pragma unroll
       for (int jn = 0; jn < NY; ++jn) {
 #pragma unroll
-        for (int c = 0; c < NS; ++c) mx[jn][c] = my[jn][c] = mz[jn][c] = vx[jn][c] = vy[jn][c] = vz[jn][c] = 0.0;
+        for (int c = 0; c < NS; ++c) {
+          mx[jn][c] = my[jn][c] = mz[jn][c] = vx[jn][c] = vy[jn][c] = vz[jn][c] = 0.0;
+          ox[jn][c] = oy[jn][c] = 0.0;
+        }
         const int bj = base + jn * ROW;
-        G0[jn] = ATT || AADJ ? 0.0 : Bp[at(1, bj)];
-        n0[jn] = AADJ ? 0.0 : Bp[at(0, bj)];
+        G0[jn] = ATT || AADJ ? 0.0 : (VT1 ? Bp[3 * WH + bj] : Bp[at(1, bj)]);
+        n0[jn] = AADJ || VT1 ? 0.0 : Bp[at(0, bj)];
         u0x[jn] = u0y[jn] = u0z[jn] = 0.0;
-        if (VISC && n0[jn] != 0.0) {
+        p0x[jn] = p0y[jn] = p0z[jn] = 0.0;
+        if (VT2) {  // phibar'_a at the output node, from the padded field
+          const int y = y0 + ty + jn * RY;
+          if (x < g.nx && y < g.ny) {
+            const long long Pc = (x + g.R) + (long long)g.PX * ((y + g.R) + (long long)g.PY * (z + g.R));
+            const double *pb = ad->psibar + (long long)(3 * alpha) * g.Np + Pc;
+            p0x[jn] = pb[0];
+            p0y[jn] = pb[g.Np];
+            p0z[jn] = pb[2 * g.Np];
+          }
+        }
+        if ((VISC || VT2) && n0[jn] != 0.0) {
           u0x[jn] = Bp[at(2, bj)] / n0[jn];
           u0y[jn] = Bp[at(3, bj)] / n0[jn];
           u0z[jn] = Bp[at(4, bj)] / n0[jn];
@@ -678,6 +707,26 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
 #pragma unroll
       for (int jn = 0; jn < NY; ++jn) {
         const int qa = base + jn * ROW + o, qb = base + jn * ROW - o;
+        if constexpr (VT1) {
+          // e^.phibar' and e^.u~ at r+e and r-e (the -e terms carry the
+          // same signs: (-e^)(-e^.v) = e^(e^.v)); G at both points
+          const double pp = e0 * Bp[qa] + e1 * Bp[WH + qa] + e2 * Bp[2 * WH + qa];
+          const double pm = e0 * Bm[qb] + e1 * Bm[WH + qb] + e2 * Bm[2 * WH + qb];
+          const double Gp = Bp[3 * WH + qa], Gm = Bm[3 * WH + qb];
+          const double up = e0 * Bp[4 * WH + qa] + e1 * Bp[5 * WH + qa] + e2 * Bp[6 * WH + qa];
+          const double um = e0 * Bm[4 * WH + qb] + e1 * Bm[5 * WH + qb] + e2 * Bm[6 * WH + qb];
+          const double s1 = pp + pm, s2 = pp * Gp + pm * Gm;
+          mx[jn][c] += e0 * s1;
+          my[jn][c] += e1 * s1;
+          mz[jn][c] += e2 * s1;
+          vx[jn][c] += e0 * s2;
+          vy[jn][c] += e1 * s2;
+          vz[jn][c] += e2 * s2;
+          const double bp = pp * up, bm = pm * um;
+          ox[jn][c] += bp + bm;
+          oy[jn][c] += bp * Gp + bm * Gm;
+          continue;
+        }
         dbl2 ap, am, vp = {0.0, 0.0}, vm = {0.0, 0.0};
         double vpz = 0.0, vmz = 0.0;
         if (PAIRED) {
@@ -728,6 +777,18 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
           mz[jn][c] += e2 * dn;
           vx[jn][c] += tp - tm;
           vy[jn][c] += tp * ap.y - tm * am.y;
+        } else if (VT2) {
+          // m: sum_S e^ (e^.phibar'(r)) n_b(r+e) (G(r) + G(r+e));
+          // v: sum_S (e^.phibar'(r)) (e^.J~(r+e) - (e^.u~(r)) n_b(r+e))
+          const double gp = G0[jn] + ap.y, gm = G0[jn] + am.y;
+          const double ep = e0 * p0x[jn] + e1 * p0y[jn] + e2 * p0z[jn];
+          const double eu = e0 * u0x[jn] + e1 * u0y[jn] + e2 * u0z[jn];
+          const double s1 = ep * (npl * gp + nmi * gm);
+          mx[jn][c] += e0 * s1;
+          my[jn][c] += e1 * s1;
+          mz[jn][c] += e2 * s1;
+          const double jp = e0 * vp.x + e1 * vp.y + e2 * vpz, jm = e0 * vm.x + e1 * vm.y + e2 * vmz;
+          vx[jn][c] += ep * (jp + jm - eu * (npl + nmi));
         } else {
           const double gp = G0[jn] + ap.y, gm = G0[jn] + am.y;
           const double d = gp * npl - gm * nmi;
@@ -774,6 +835,39 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
         } else if (AADJ) {
           double *pn = ad->nbar + beta * N + i;
           *pn = (accumulate & 1) ? *pn - Mx : -Mx;
+        } else if (VT1 || VT2) {
+          // with c = pair_cvisc (C^visc/n_a = c sum_S e^ [e^.J~(r+e) -
+          // (e^.u~(r)) n_b(r+e)] (G(r) + G(r+e))):
+          // MODE 5: J~_b^bar(r) += c (sum e^(e^.pb(r+e)) G(r+e) + G(r) sum e^(e^.pb(r+e)))
+          //         n_b^bar(r)  -= c (sum (e^.pb)(e^.u~)(r+e) G(r+e) + G(r) sum (e^.pb)(e^.u~)(r+e))
+          //         G^bar(r)    += c (J~_b(r).sum e^(e^.pb(r+e)) - n_b(r) sum (e^.pb)(e^.u~)(r+e))
+          // MODE 6: u~^bar(r) = -c sum e^(e^.pb(r)) n_b(r+e)(G(r) + G(r+e)), into
+          //         J~_b^bar += u~^bar/n_b, n_b^bar -= u~^bar.u~/n_b;
+          //         G^bar(r) += c sum (e^.pb(r)) (e^.J~(r+e) - (e^.u~(r)) n_b(r+e))
+          double jb[3], vn, vg;
+          if (VT1) {
+            const double Ox = ox[jn][0] + ox[jn][1], Oy = oy[jn][0] + oy[jn][1];
+            const long long Pc = (x + g.R) + (long long)g.PX * ((y + g.R) + (long long)g.PY * (z + g.R));
+            const double *Jc = a.Jfield + (long long)(3 * beta) * g.Np + Pc;
+            const double nc = a.nfield[(long long)beta * g.Np + Pc];
+            jb[0] = cvs * (Vx + G0[jn] * Mx);
+            jb[1] = cvs * (Vy + G0[jn] * My);
+            jb[2] = cvs * (Vz + G0[jn] * Mz);
+            vn = -cvs * (Oy + G0[jn] * Ox);
+            vg = cvs * (Jc[0] * Mx + Jc[g.Np] * My + Jc[2 * g.Np] * Mz - nc * Ox);
+          } else {
+            const double ub0 = -cvs * Mx, ub1 = -cvs * My, ub2 = -cvs * Mz;
+            const double inv = n0[jn] != 0.0 ? 1.0 / n0[jn] : 0.0;
+            jb[0] = ub0 * inv;
+            jb[1] = ub1 * inv;
+            jb[2] = ub2 * inv;
+            vn = -(ub0 * u0x[jn] + ub1 * u0y[jn] + ub2 * u0z[jn]) * inv;
+            vg = cvs * Vx;
+          }
+          double *pn = ad->nbar + beta * N + i, *pg = ad->Gbar + k * N + i, *pj = ad->Jnl + 3 * beta * N + i;
+          *pn = (accumulate & 1) ? *pn + vn : vn;
+          *pg = (accumulate & 2) ? *pg + vg : vg;
+          for (int q = 0; q < 3; ++q) pj[q * N] = (accumulate & 4) ? pj[q * N] + jb[q] : jb[q];
         } else if (ATT) {
           // G^{ab} is a force per particle of species a: into C^mf/n_a
           double *F = a.force + 6LL * alpha * N + i;
@@ -1382,6 +1476,15 @@ __device__ inline void adj_drag(const A &a, const AdjArgs &d, long long P, int i
   for (int k = 0; k < M * (M + 1) / 2; ++k) d.Gbar[(long long)k * N + i] = Gb[k];
 }
 
+// the C^visc adjoint fields of species s at node c: phibar' = n Ybar and u~
+__device__ inline void store_visc_fields(const Geom &g, const AdjArgs &d, const Coord &c, int s,
+                                         const double pb[3], const double ut[3]) {
+  for (int k = 0; k < 3; ++k) {
+    store_images(g, d.psibar + (long long)(3 * s + k) * g.Np, c, pb[k]);
+    store_images(g, d.ut + (long long)(3 * s + k) * g.Np, c, ut[k]);
+  }
+}
+
 // Gbar of every pair at a solid node (with the drag)
 template <int M>
 __device__ inline void zero_Gbar(const AdjArgs &d, long long N, int i) {
@@ -1413,9 +1516,13 @@ __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
   const uint32_t m = a.bb[i];
   const Coord c = decode(g, i);
   const bool drag = drag_on(a);
+  const bool visc = d.psibar != nullptr;  // C^visc (its force per particle in slots 3..5)
   if (m & 1u) {
     const double z[3] = {0.0, 0.0, 0.0};
-    for (int s = 0; s < M; ++s) store_phibar(g, d, c, s, z);
+    for (int s = 0; s < M; ++s) {
+      store_phibar(g, d, c, s, z);
+      if (visc) store_visc_fields(g, d, c, s, z, z);
+    }
     if (drag) zero_Gbar<M>(d, g.N, i);
     return;
   }
@@ -1428,19 +1535,21 @@ __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
   const bool withX = printed || single, shiftPi = !(euler || single);
   const double sgn = printed ? -1.0 : 1.0;
   double n[M], phi[M][3], F[M][3], C[M][3], Y[M][3], X[M][3], ua[M][3], u[3];
-  double ut[M][3], Dr[M][3];
+  double ut[M][3], Dr[M][3], psi[M][3];
   double ntot = 0.0, Jtot[3] = {0.0, 0.0, 0.0};
   for (int s = 0; s < M; ++s) n[s] = a.nfield[(long long)s * g.Np + P];
-  if (drag) {
-    tape_ut<M>(d, N, i, n, ut);
-    drag_force<M>(a, P, n, ut, Dr);
-  }
+  if (drag || visc) tape_ut<M>(d, N, i, n, ut);
+  if (drag) drag_force<M>(a, P, n, ut, Dr);
+  for (int s = 0; s < M; ++s)
+    for (int k = 0; k < 3; ++k) psi[s][k] = visc ? a.force[6LL * s * N + (3 + k) * N + i] : 0.0;
   for (int s = 0; s < M; ++s) {
     for (int k = 0; k < 3; ++k) {
       phi[s][k] = a.force[6LL * s * N + k * N + i];
       F[s][k] = a.Fext[(long long)k * N + i] + a.body[s][k];
       C[s][k] = n[s] * phi[s][k];
-      Y[s][k] = drag ? Dr[s][k] + n[s] * F[s][k] : n[s] * F[s][k];
+      // Y = C^visc (+ C^drag) + n F, in the order of the forward step
+      const double cv = n[s] * psi[s][k] + (drag ? Dr[s][k] : 0.0);
+      Y[s][k] = cv + n[s] * F[s][k];
       X[s][k] = C[s][k] + Y[s][k];
       const double J = d.PJ[(long long)(M + 3 * s + k) * N + i] + half * (withX ? X[s][k] : Y[s][k]);
       ua[s][k] = n[s] != 0.0 ? J / n[s] : 0.0;
@@ -1525,6 +1634,12 @@ __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
     }
     nbar[s] += dot3(Ybar[s], F[s]) + dot3(Cbar[s], phi[s]);
     store_phibar(g, d, c, s, pb);
+    if (visc) {  // C^visc = n psi: phibar' = n Ybar
+      double pv[3];
+      for (int k = 0; k < 3; ++k) pv[k] = n[s] * Ybar[s][k];
+      nbar[s] += dot3(Ybar[s], psi[s]);
+      store_visc_fields(g, d, c, s, pv, ut[s]);
+    }
   }
   // Y = n F + C^drag: Ybar is also the adjoint of the drag force
   if (drag) adj_drag<M>(a, d, P, i, n, ut, Ybar, nbar, Jbar);
@@ -1548,9 +1663,13 @@ __global__ __launch_bounds__(BLOCK) void k_adj_readout(StepArgs a, AdjArgs d) {
   const uint32_t m = a.bb[i];
   const Coord c = decode(g, i);
   const bool drag = drag_on(a);
+  const bool visc = d.psibar != nullptr;
   if (m & 1u) {
     const double z[3] = {0.0, 0.0, 0.0};
-    for (int s = 0; s < M; ++s) store_phibar(g, d, c, s, z);
+    for (int s = 0; s < M; ++s) {
+      store_phibar(g, d, c, s, z);
+      if (visc) store_visc_fields(g, d, c, s, z, z);
+    }
     if (drag) zero_Gbar<M>(d, g.N, i);
     return;
   }
@@ -1579,11 +1698,19 @@ __global__ __launch_bounds__(BLOCK) void k_adj_readout(StepArgs a, AdjArgs d) {
     }
     store_phibar(g, d, c, s, pb);
   }
-  if (drag) {
-    double ut[M][3];
-    tape_ut<M>(d, N, i, n, ut);
-    adj_drag<M>(a, d, P, i, n, ut, Yb, nb, Jb);
-  }
+  double ut[M][3];
+  if (drag || visc) tape_ut<M>(d, N, i, n, ut);
+  if (visc)  // Y holds C^visc = n psi too
+    for (int s = 0; s < M; ++s) {
+      double pv[3], psi[3];
+      for (int k = 0; k < 3; ++k) {
+        psi[k] = a.force[6LL * s * N + (3 + k) * N + i];
+        pv[k] = n[s] * Yb[s][k];
+      }
+      nb[s] += dot3(Yb[s], psi);
+      store_visc_fields(g, d, c, s, pv, ut[s]);
+    }
+  if (drag) adj_drag<M>(a, d, P, i, n, ut, Yb, nb, Jb);
   for (int s = 0; s < M; ++s) store_node(d, M, N, i, s, nb[s], 0.0, Jb[s]);
   for (int k = 0; k < 3; ++k) d.Fbar[(long long)k * N + i] += Fb[k];
 }
@@ -1636,7 +1763,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj_stream(StepArgs a, AdjArgs d) {
   for (int s = 0; s < M; ++s) {
     nb[s] = d.node[(long long)s * N + i] + d.nbar[(long long)s * N + i];
     Pib[s] = d.node[(long long)(M + s) * N + i];
-    for (int k = 0; k < 3; ++k) Jb[s][k] = d.node[(long long)(2 * M + 3 * s + k) * N + i];
+    for (int k = 0; k < 3; ++k)
+      Jb[s][k] = d.node[(long long)(2 * M + 3 * s + k) * N + i] + (d.Jnl ? d.Jnl[(3LL * s + k) * N + i] : 0.0);
   }
   adj_stream_q<0, M, TERMINAL>(g, c, i, m, d, Ns, N, 1.0 - a.acoef, (a.flags & LBE_SINGLE) != 0, nb, Pib,
                                Jb);
@@ -1693,6 +1821,17 @@ __global__ __launch_bounds__(FNT) void k_adj_att(StepArgs a, AdjArgs d, int alph
   extern __shared__ double lds[];
   const Tile T = force_tile(a.g, a.zchunk, a.order, FNT / FTX * NY);
   force_body<R, 4, NY, FNT>(a, &d, alpha, beta, acc, T.bx, T.by, T.bz, lds);
+}
+
+// adjoint of the C^visc gather of the directed pair (alpha, beta), force_body
+// MODE 5 or 6 (see there): writes or accumulates into nbar (acc bit 0),
+// Gbar (bit 1) and Jnl (bit 2); 32 x 8 tiles, the ring table through scalar
+// loads
+template <int R, int MODE>
+__global__ __launch_bounds__(FNT) void k_adj_visc(StepArgs a, AdjArgs d, int alpha, int beta, int acc) {
+  extern __shared__ double lds[];
+  const Tile T = force_tile(a.g, a.zchunk, a.order, FTY);
+  force_body<R, MODE, 1, FNT>(a, &d, alpha, beta, acc, T.bx, T.by, T.bz, lds);
 }
 
 // Vbar = -(grad_h)^T Fbar: transpose of F(r) = -3 sum_p w_p c_p V(idx(r + c_p))
@@ -2370,6 +2509,36 @@ static void adj_att_r(int R, const StepArgs &a, const AdjArgs &d, int alpha, int
   }
 }
 
+template <int R, int MODE>
+static void adj_visc_launch(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
+                            hipStream_t s) {
+  const int k = pair_index(a.M, alpha, beta);
+  const size_t bytes = force_lds(MODE, R, FTY, a.t.pair_nent[k], 1);
+  static size_t attr = 0;
+  if (bytes > attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_adj_visc<R, MODE>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    attr = bytes;
+  }
+  hipLaunchKernelGGL((k_adj_visc<R, MODE>), dim3(force_blocks(a.g, a.zchunk, FTY)), dim3(FNT), bytes, s, a,
+                     d, alpha, beta, acc);
+}
+
+template <int MODE>
+static void adj_visc_r(int R, const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
+                       hipStream_t s) {
+  switch (R) {
+    case 1: adj_visc_launch<1, MODE>(a, d, alpha, beta, acc, s); break;
+    case 2: adj_visc_launch<2, MODE>(a, d, alpha, beta, acc, s); break;
+    case 3: adj_visc_launch<3, MODE>(a, d, alpha, beta, acc, s); break;
+    case 4: adj_visc_launch<4, MODE>(a, d, alpha, beta, acc, s); break;
+    case 5: adj_visc_launch<5, MODE>(a, d, alpha, beta, acc, s); break;
+    case 6: adj_visc_launch<6, MODE>(a, d, alpha, beta, acc, s); break;
+    case 7: adj_visc_launch<7, MODE>(a, d, alpha, beta, acc, s); break;
+    default: adj_visc_launch<8, MODE>(a, d, alpha, beta, acc, s); break;
+  }
+}
+
 void launch_fill(double *p, long long n, double v, hipStream_t s) {
   if (n <= 0) return;
   long long blocks = (n + BLOCK - 1) / BLOCK;
@@ -2408,6 +2577,21 @@ void launch_adj_nonlocal(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
         default: adj_force_launch<8>(a, d, al, be, acc, s); break;
       }
     }
+  // C^visc: its two transposes per directed pair, into nbar, Gbar and Jnl
+  if ((a.flags & LBE_VISC) && d.Jnl) {
+    bool wj[MAXM] = {false, false, false, false};
+    for (int al = 0; al < M; ++al)
+      for (int be = 0; be < M; ++be) {
+        const int k = pair_index(M, al, be);
+        const int R = a.t.pair_R[k];
+        if (R == 0) continue;
+        adj_visc_r<5>(R, a, d, al, be, (wn[be] ? 1 : 0) | (wg[k] ? 2 : 0) | (wj[be] ? 4 : 0), s);
+        wn[be] = wg[k] = wj[be] = true;
+        adj_visc_r<6>(R, a, d, al, be, 7, s);
+      }
+    for (int b = 0; b < M; ++b)
+      if (!wj[b]) launch_fill(d.Jnl + 3 * b * N, 3 * N, 0.0, s);
+  }
   // the attractive tails: phibar_a gathered back onto n_b
   for (int al = 0; al < M; ++al)
     for (int be = 0; be < M; ++be) {

@@ -138,6 +138,45 @@ def test_adjoint_scheme_variants_match_reference(flags, T, segment):
         assert_close(gg, rg, 1e-10, "dL/dg0")
 
 
+@pytest.mark.parametrize("flags,att,T,segment", [(1, False, 6, 3), (1 | 2, False, 5, 5), (1 | 4, False, 6, 1),
+                                                 (1 | 64, False, 6, 2), (1 | 32, False, 5, 5),
+                                                 (1 | 2 | 64, True, 5, 2)])
+def test_adjoint_with_visc_matches_reference(flags, att, T, segment):
+    """C^visc (flag 1) on the two-species channel: its two transposes per
+    directed pair (MODE 5 over phibar', G and u~; MODE 6 over n, G and J~
+    with the centre phibar') with either inversion, kappa = 4, the drag,
+    one distribution, and the drag and attractive tails together."""
+    w = small_channel()
+    if att:
+        w.att_eps, w.att_rc = [[0.3 * W.KT, 0.2 * W.KT], [0.2 * W.KT, 0.25 * W.KT]], 5.0
+    pw = pop_weights(w) * 1e-3
+    single = bool(flags & 32)
+    if single:
+        pw[1] = 0.0
+    print(f"small channel with C^visc flags {flags} att {att} T {T} segment {segment}", flush=True)
+    rV, rf, rg = reference(w, flags, T, pw)
+    gV, gf, gg = gpu_gradient(w, flags, T, segment, pw)
+    assert_close(gV, rV, 1e-10, "dL/dV")
+    assert_close(gf, rf, 1e-10, "dL/df0")
+    if not single:
+        assert_close(gg, rg, 1e-10, "dL/dg0")
+
+
+def test_adjoint_visc_one_species_periodic_well():
+    """One species, sigma = 3, periodic, C^visc on, printed inversions (the
+    scheme of the 128^3 benchmark box)."""
+    w = W.well_box(16, 3.0, 0.3, W.eps_for_depth(1.0), 5.0, 1e-2, 33, 5, "well16_s3_visc")
+    w.V = w.V + W.smooth_field(w.shape, 0.02, 3, 34)
+    w.solid = np.zeros(w.shape, dtype=np.uint8)
+    pw = pop_weights(w, 8) * 1e-3
+    print("well16 sigma 3 one species with C^visc", flush=True)
+    rV, rf, rg = reference(w, 1 | 2, 5, pw)
+    gV, gf, gg = gpu_gradient(w, 1 | 2, 5, 2, pw)
+    assert_close(gV, rV, 1e-10, "dL/dV")
+    assert_close(gf, rf, 1e-10, "dL/df0")
+    assert_close(gg, rg, 1e-10, "dL/dg0")
+
+
 def test_adjoint_attraction_one_species_periodic():
     """One species, periodic box, a cutoff of 7.5 (the widest transpose
     window, 7 nodes per axis) and a potential well."""
@@ -224,10 +263,10 @@ def test_channel96_gradient_against_oracle_fd():
           f"fd noise {noise:.1e}", flush=True)
 
 
-@pytest.mark.parametrize("att", [False, True])
-def test_adjoint_tiling_does_not_change_gradient(att):
-    """The adjoint shell-gather transposes (and those of the attraction)
-    under every force tiling."""
+@pytest.mark.parametrize("att,flags", [(False, 0), (True, 0), (False, 1)])
+def test_adjoint_tiling_does_not_change_gradient(att, flags):
+    """The adjoint shell-gather transposes (and those of the attraction and
+    of C^visc) under every force tiling."""
     from paper_1202_3842_amd import lbe
     w = small_channel()
     if att:
@@ -235,8 +274,8 @@ def test_adjoint_tiling_does_not_change_gradient(att):
     n_t, fluid, plane = objective_terms(w)
     ref = None
     for zc, order, shape in ((1, 0, 0), (3, 1, 1), (8, 2, 2), (2, 0, 1)):
-        print(f"adjoint tiling att {att} zchunk {zc} order {order} shape {shape}", flush=True)
-        box = lbe.box_from_workload(w, flags=0)
+        print(f"adjoint tiling att {att} flags {flags} zchunk {zc} order {order} shape {shape}", flush=True)
+        box = lbe.box_from_workload(w, flags=flags)
         box.set_force_tiling(zc, order, shape)
         adj = lbe.Adjoint(box, 4, 2)
         adj.forward()
