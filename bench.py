@@ -302,6 +302,51 @@ def adjoint_leg(lbe, torch, W, segment=20, att=False):
     }
 
 
+def adjoint_box_leg(lbe, torch, W, flags, T=40, segment=10):
+    """dL/dV on the 128^3 benchmark box with its own scheme (C^visc on,
+    printed inversions), T steps checkpointed every `segment`: forward,
+    checkpointed forward and backward times, L = sum of n^2 at the end."""
+    from paper_1202_3842_amd import autotune
+    w = W.c2_large_well()
+    box = lbe.box_from_workload(w, flags=flags)
+    autotune.tune_zchunk(box)
+    st = box.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    box.step(5)
+    lbe.load_workload(box, w)
+    torch.cuda.synchronize()
+    ev[0].record(st)
+    box.step(T)
+    ev[1].record(st)
+    ev[1].synchronize()
+    t_plain = ev[0].elapsed_time(ev[1])
+    adj = lbe.Adjoint(box, T, segment)
+    lbe.load_workload(box, w)
+    torch.cuda.synchronize()
+    ev[2].record(st)
+    adj.forward()
+    ev[3].record(st)
+    ev[3].synchronize()
+    t_fwd = ev[2].elapsed_time(ev[3])
+    dn = torch.tensor(2.0 * box.density(0)[None], device="cuda")
+    out = torch.empty(w.nodes, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    ev[4].record(st)
+    adj.backward(dn, None, None, out=out)
+    ev[5].record(st)
+    ev[5].synchronize()
+    t_bwd = ev[4].elapsed_time(ev[5])
+    adj.close()
+    box.close()
+    log(f"adjoint on {w.name}: plain forward {t_plain:.1f} ms, checkpointed forward {t_fwd:.1f} ms, "
+        f"backward {t_bwd:.1f} ms ({T} steps)")
+    return {"workload": w.name, "steps": T, "segment": segment,
+            "scheme": "C^mf + C^visc, printed inversions",
+            "forward_ms": round(t_plain, 3), "forward_checkpointed_ms": round(t_fwd, 3),
+            "backward_ms": round(t_bwd, 3), "adjoint_vs_forward": round(t_bwd / t_plain, 3),
+            "max_abs_dL_dV": float(out.abs().max())}
+
+
 def quasipressure_leg(lbe, torch, w, flags, reps=20):
     """The quasi-pressure initialiser of Sec. 2 (eq. quasipressure) and the
     divergence diagnostic of Sec. 4.3 on the benchmark box after 10 steps:
@@ -479,6 +524,7 @@ def main():
     if args.adjoint_only:
         adj = adjoint_leg(lbe, torch, W)
         adj["with_attraction"] = adjoint_leg(lbe, torch, W, att=True)
+        adj["benchmark_box"] = adjoint_box_leg(lbe, torch, W, lbe.LBE_VISC | lbe.LBE_PRINTED_INV)
         print(json.dumps({"adjoint": adj}), flush=True)
         return
     w = W.c2_large_well()
@@ -523,6 +569,7 @@ def main():
     if not args.no_adjoint:
         adjoint = adjoint_leg(lbe, torch, W)
         adjoint["with_attraction"] = adjoint_leg(lbe, torch, W, att=True)
+        adjoint["benchmark_box"] = adjoint_box_leg(lbe, torch, W, flags)
 
     qp = None if args.no_quasipressure else quasipressure_leg(lbe, torch, w, flags)
 

@@ -319,3 +319,43 @@ def test_adjoint_attraction_tile_rows_agree():
     assert np.array_equal(dens[0], dens[1])
     assert np.abs(grads[0]).max() > 0
     assert np.array_equal(grads[0], grads[1])
+
+
+def test_adjoint_full_size_directional_derivative():
+    """The 128^3 benchmark box (sigma = 6, C^visc, printed inversions) in the
+    launch configuration bench.py times, 3 steps: the adjoint's dL/dV along
+    a smooth direction dV equals the central difference of L along dV (the
+    library's own forward at V +- h dV), for L = sum_r c(r) n(r, T) with
+    seeded weights c.  A property that holds at any size; the reference
+    gradient covers the small boxes."""
+    from paper_1202_3842_amd import lbe, autotune
+    w = W.c2_large_well()
+    flags = lbe.LBE_VISC | lbe.LBE_PRINTED_INV
+    T = 3
+    c = W.rng(61).uniform(-1.0, 1.0, size=w.shape)
+    dV = W.smooth_field(w.shape, 0.1 * W.KT, 4, 62)
+    box = lbe.box_from_workload(w, flags=flags)
+    autotune.tune_zchunk(box)
+    print(f"full size adjoint, tiling {getattr(box, 'tiling', None)}", flush=True)
+    adj = lbe.Adjoint(box, T, T)
+    lbe.load_workload(box, w)
+    adj.forward()
+    gV = adj.backward(c[None], None, None)
+    adj.close()
+    ana = float(np.sum(gV * dV))
+
+    def loss(V):
+        lbe.load_workload(box, w)
+        box.set_potential(np.ascontiguousarray(V))
+        box.step(T)
+        return float(np.sum(c * box.density(0)))
+
+    h = 1e-4
+    L0 = loss(w.V)
+    fd = (loss(w.V + h * dV) - loss(w.V - h * dV)) / (2 * h)
+    box.close()
+    noise = 2.2e-16 * np.abs(c).sum() * float(w.density[0].max()) / h
+    print(f"full size: adjoint {ana:.9e}, central difference {fd:.9e}, L {L0:.6e}, noise {noise:.1e}",
+          flush=True)
+    assert abs(ana) > 100 * noise
+    assert abs(ana - fd) <= 1e-6 * abs(ana) + 10 * noise
