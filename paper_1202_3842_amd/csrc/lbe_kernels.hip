@@ -1827,11 +1827,11 @@ __global__ __launch_bounds__(FNT) void k_adj_att(StepArgs a, AdjArgs d, int alph
 // MODE 5 or 6 (see there): writes or accumulates into nbar (acc bit 0),
 // Gbar (bit 1) and Jnl (bit 2); 32 x 8 tiles, the ring table through scalar
 // loads
-template <int R, int MODE>
-__global__ __launch_bounds__(FNT) void k_adj_visc(StepArgs a, AdjArgs d, int alpha, int beta, int acc) {
+template <int R, int MODE, int NT>
+__global__ __launch_bounds__(NT) void k_adj_visc(StepArgs a, AdjArgs d, int alpha, int beta, int acc) {
   extern __shared__ double lds[];
-  const Tile T = force_tile(a.g, a.zchunk, a.order, FTY);
-  force_body<R, MODE, 1, FNT>(a, &d, alpha, beta, acc, T.bx, T.by, T.bz, lds);
+  const Tile T = force_tile(a.g, a.zchunk, a.order, NT / FTX);
+  force_body<R, MODE, 1, NT>(a, &d, alpha, beta, acc, T.bx, T.by, T.bz, lds);
 }
 
 // Vbar = -(grad_h)^T Fbar: transpose of F(r) = -3 sum_p w_p c_p V(idx(r + c_p))
@@ -2509,19 +2509,31 @@ static void adj_att_r(int R, const StepArgs &a, const AdjArgs &d, int alpha, int
   }
 }
 
-template <int R, int MODE>
-static void adj_visc_launch(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
-                            hipStream_t s) {
+template <int R, int MODE, int NT>
+static void adj_visc_launch_nt(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
+                               hipStream_t s) {
+  constexpr int TY = NT / FTX;
   const int k = pair_index(a.M, alpha, beta);
-  const size_t bytes = force_lds(MODE, R, FTY, a.t.pair_nent[k], 1);
+  const size_t bytes = force_lds(MODE, R, TY, a.t.pair_nent[k], 1);
   static size_t attr = 0;
   if (bytes > attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_adj_visc<R, MODE>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_adj_visc<R, MODE, NT>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     attr = bytes;
   }
-  hipLaunchKernelGGL((k_adj_visc<R, MODE>), dim3(force_blocks(a.g, a.zchunk, FTY)), dim3(FNT), bytes, s, a,
-                     d, alpha, beta, acc);
+  hipLaunchKernelGGL((k_adj_visc<R, MODE, NT>), dim3(force_blocks(a.g, a.zchunk, TY)), dim3(NT), bytes, s,
+                     a, d, alpha, beta, acc);
+}
+
+// 512-thread 32 x 16 tiles where their two planes fit in LDS (fewer window
+// slots per thread and less halo per output), else 32 x 8
+template <int R, int MODE>
+static void adj_visc_launch(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
+                            hipStream_t s) {
+  if (force_lds(MODE, R, 16, 0, 1) <= 160 * 1024)
+    adj_visc_launch_nt<R, MODE, 512>(a, d, alpha, beta, acc, s);
+  else
+    adj_visc_launch_nt<R, MODE, 256>(a, d, alpha, beta, acc, s);
 }
 
 template <int MODE>
