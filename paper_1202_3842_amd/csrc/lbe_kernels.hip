@@ -2446,6 +2446,13 @@ void launch_adj_stream(const StepArgs &a, const AdjArgs &d, bool terminal, hipSt
   }
 }
 
+// tiles of the adjoint gathers of C^visc: 512-thread 32 x 16 tiles
+// where their two planes fit in LDS (fewer window slots per thread and less
+// halo per output) and the box still gives two such tiles per CU, else 32 x 8
+static bool wide_tiles(const StepArgs &a, int mode, int R) {
+  return force_lds(mode, R, 16, 0, 1) <= 160 * 1024 && force_blocks(a.g, a.zchunk, 16) >= 2 * NCU;
+}
+
 template <int R, int SHAPE>
 static void adj_force_launch_shape(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
                                    hipStream_t s) {
@@ -2463,7 +2470,8 @@ static void adj_force_launch_shape(const StepArgs &a, const AdjArgs &d, int alph
 }
 
 // the adjoint gather stages five fields, like C^visc, for which the 32 x 8
-// shape is the fast one; zchunk and the tile order follow the box's tiling
+// shape is the fast one (also at 128^3: 32 x 16 tiles of 512 threads gave
+// the same time); zchunk and the tile order follow the box's tiling
 template <int R>
 static void adj_force_launch(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
                              hipStream_t s) {
@@ -2525,12 +2533,10 @@ static void adj_visc_launch_nt(const StepArgs &a, const AdjArgs &d, int alpha, i
                      a, d, alpha, beta, acc);
 }
 
-// 512-thread 32 x 16 tiles where their two planes fit in LDS (fewer window
-// slots per thread and less halo per output), else 32 x 8
 template <int R, int MODE>
 static void adj_visc_launch(const StepArgs &a, const AdjArgs &d, int alpha, int beta, int acc,
                             hipStream_t s) {
-  if (force_lds(MODE, R, 16, 0, 1) <= 160 * 1024)
+  if (wide_tiles(a, MODE, R))
     adj_visc_launch_nt<R, MODE, 512>(a, d, alpha, beta, acc, s);
   else
     adj_visc_launch_nt<R, MODE, 256>(a, d, alpha, beta, acc, s);
