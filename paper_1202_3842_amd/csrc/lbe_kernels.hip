@@ -2446,11 +2446,15 @@ void launch_adj_stream(const StepArgs &a, const AdjArgs &d, bool terminal, hipSt
   }
 }
 
-// tiles of the adjoint gathers of C^visc: 512-thread 32 x 16 tiles
-// where their two planes fit in LDS (fewer window slots per thread and less
-// halo per output) and the box still gives two such tiles per CU, else 32 x 8
+// tiles of the adjoint gathers of C^visc: MODE 5 (seven staged fields)
+// takes 512-thread 32 x 16 tiles where its two planes fit in LDS (fewer
+// window slots per thread and less halo per output) and the box still gives
+// two such tiles per CU, else 32 x 8.  At 128^3: MODE 5 1.58 -> 1.03 ms;
+// MODE 6 (five fields) 0.86 ms with 32 x 8 and 0.89 ms with 32 x 16, so it
+// keeps 32 x 8.
 static bool wide_tiles(const StepArgs &a, int mode, int R) {
-  return force_lds(mode, R, 16, 0, 1) <= 160 * 1024 && force_blocks(a.g, a.zchunk, 16) >= 2 * NCU;
+  return mode == 5 && force_lds(mode, R, 16, 0, 1) <= 160 * 1024 &&
+         force_blocks(a.g, a.zchunk, 16) >= 2 * NCU;
 }
 
 template <int R, int SHAPE>
