@@ -2,12 +2,16 @@
 
 Writes ``channel96_fd_grad.json``: dL/dV at 32 seeded fluid nodes of the
 96x32x32 two-species channel (C^mf only, derived inversions, 400 steps), each
-from two runs of the oracle with V(r_i) moved by +-h.  The objective is the
+from two runs of the oracle with V(r_i) moved by +-h.  With ``--flags 3
+--steps 40 --out channel96_visc_fd_grad.json`` the same for the scheme with
+C^visc and the printed inversions over 40 steps (the channel collapses with
+C^visc well before 400 steps).  The objective is the
 one described in ``paper_1202_3842_amd.workloads.c5_objective``.  Only the
 oracle computes anything here; the GPU adjoint is compared with these values
 by tests/test_gpu_adjoint.py.
 
     python tests/golden/make_channel_fd.py [--threads 8]   (about 80 min on 8 cores)
+    python tests/golden/make_channel_fd.py --flags 3 --steps 40 --out channel96_visc_fd_grad.json
 """
 from __future__ import annotations
 
@@ -26,7 +30,7 @@ import oracle  # noqa: E402
 from paper_1202_3842_amd import workloads as W  # noqa: E402
 
 H = 1e-6
-OUT = Path(__file__).resolve().parent / "channel96_fd_grad.json"
+HERE = Path(__file__).resolve().parent
 
 
 def objective(w, V, flags, steps):
@@ -52,10 +56,16 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=8)
     ap.add_argument("--count", type=int, default=32)
+    ap.add_argument("--flags", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=0, help="0: the workload's 400")
+    ap.add_argument("--out", default="channel96_fd_grad.json")
     args = ap.parse_args()
     oracle.set_threads(args.threads)
     w = W.c5_channel()
-    flags = 0
+    if args.steps:
+        w.steps = args.steps
+    flags = args.flags
+    OUT = HERE / args.out
     nodes = W.sample_fluid_nodes(w, args.count)
     t0 = time.time()
     L0, d0, f0 = objective(w, w.V, flags, w.steps)

@@ -15,6 +15,7 @@ from paper_1202_3842_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 GOLDEN = Path(__file__).resolve().parent / "golden" / "channel96_fd_grad.json"
+GOLDEN_VISC = Path(__file__).resolve().parent / "golden" / "channel96_visc_fd_grad.json"
 
 
 def reference(w, flags, T, pw):
@@ -227,15 +228,22 @@ def test_autograd_function_matches_adjoint():
     assert_close(V.grad.cpu().numpy(), rV, 1e-10, "autograd dL/dV")
 
 
-@pytest.mark.skipif(not GOLDEN.exists(), reason="finite-difference golden file not generated")
-def test_channel96_gradient_against_oracle_fd():
+@pytest.mark.parametrize("golden,steps,segment", [(GOLDEN, 400, 20), (GOLDEN_VISC, 40, 10)],
+                         ids=["cmf_400", "visc_printed_40"])
+def test_channel96_gradient_against_oracle_fd(golden, steps, segment):
+    """dL/dV on the 96x32x32 channel against central differences of the
+    oracle: C^mf with the derived inversions over 400 steps, and C^visc with
+    the printed inversions over 40 steps."""
     from paper_1202_3842_amd import lbe
-    gold = json.loads(GOLDEN.read_text())
+    if not golden.exists():
+        pytest.skip(f"finite-difference golden file {golden.name} not generated")
+    gold = json.loads(golden.read_text())
     w = W.c5_channel()
+    w.steps = steps
     assert gold["workload"] == w.name and gold["steps"] == w.steps
     n_t, fluid, plane = W.c5_objective(w)
     box = lbe.box_from_workload(w, flags=gold["flags"])
-    adj = lbe.Adjoint(box, w.steps, 20)
+    adj = lbe.Adjoint(box, w.steps, segment)
     adj.forward()
     nA = box.density(0)
     d = box.diagnostics()
