@@ -131,7 +131,8 @@ typedef struct {
    * (kT = 1/3), symmetric, >= 0; all zero = no attraction.  A pair with
    * att_eps > 0 needs sigma_ab > 0 and sigma_ab < att_rc, and the points
    * must reach at most 8 nodes per axis (att_rc <= 9).  Not with LBE_IDEAL
-   * (which drops every nonlocal force) or batched boxes. */
+   * (which drops every nonlocal force).  In a batch, a box with the field
+   * needs a non-empty hard-sphere shell (sigma >= 1/2). */
   double att_eps[4][4];
   double att_rc;
 } lbe_config;

@@ -771,8 +771,9 @@ lbe_status make_batch_plan(const lbe_config *cfgs, int nboxes, BatchPlan &bp) {
     lbe_status st = make_plan(&cfgs[b], plans[b]);
     if (st != LBE_OK) return fail(st, "box %d: %s", b, error_text());
     if (cfgs[b].nspecies != 1) return fail(LBE_ERR_UNSUPPORTED, "batched boxes must have one species");
-    if (cfgs[b].att_eps[0][0] > 0.0)
-      return fail(LBE_ERR_UNSUPPORTED, "batched boxes do not take the attractive field");
+    // the attraction adds to the hard-sphere force, which must have written it
+    if (cfgs[b].att_eps[0][0] > 0.0 && plans[b].shells[0].e.empty())
+      return fail(LBE_ERR_UNSUPPORTED, "box %d: the attractive field in a batch needs a hard-sphere shell", b);
     if (cfgs[b].prec != cfgs[0].prec || cfgs[b].flags != cfgs[0].flags)
       return fail(LBE_ERR_ARG, "batched boxes must share precision and flags");
   }
@@ -798,7 +799,8 @@ lbe_status make_batch_plan(const lbe_config *cfgs, int nboxes, BatchPlan &bp) {
   bp.off_nodestart = take(sizeof(int) * nboxes);
   bp.off_ballbox = take(sizeof(int) * bp.ball_blocks);
   bp.off_ballstart = take(sizeof(int) * nboxes);
-  bp.force_bytes = force_table_bytes(plans);
+  // block tables of the force groups, then of the attraction groups
+  bp.force_bytes = 2 * force_table_bytes(plans);
   bp.off_force = take(bp.force_bytes);
   for (const Plan &p : plans) {
     bp.box_bytes.push_back(p.total);
@@ -821,7 +823,7 @@ struct lbe_batch {
     int R, nblocks, entries;
     int *blockbox, *blockstart;
   };
-  std::vector<Group> groups;
+  std::vector<Group> groups, att_groups;
   std::vector<int> zchunks;          // the zchunk of each box the tables were built for
   std::vector<StepArgs> uploaded;    // the parameter blocks last copied to the device
   hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -845,6 +847,7 @@ lbe_status batch_tables(lbe_batch *B) {
   if (same) return LBE_OK;
   B->drop_graphs();
   B->groups.clear();
+  B->att_groups.clear();
   B->zchunks.assign(n, 0);
   char *base = B->ws + B->bp.off_force;
   size_t used = 0;
@@ -876,6 +879,31 @@ lbe_status batch_tables(lbe_batch *B) {
     B->groups.push_back(G);
     maxR = std::max(maxR, R);
     maxent = std::max(maxent, ent);
+  }
+  // boxes with the attractive field, grouped by the tail's reach (32 x 8
+  // tiles, the same block count as the force groups)
+  for (int R = 1; R <= RING_MAX; ++R) {
+    std::vector<int> box_of_block, start(n, 0);
+    for (int b = 0; b < n; ++b) {
+      const StepArgs &a = B->boxes[b]->args;
+      if (a.t.att_R[0] != R) continue;
+      start[b] = (int)box_of_block.size();
+      box_of_block.insert(box_of_block.end(), force_blocks(a.g, a.zchunk), b);
+    }
+    if (box_of_block.empty()) continue;
+    lbe_batch::Group G;
+    G.R = R;
+    G.nblocks = (int)box_of_block.size();
+    G.entries = 0;
+    G.blockbox = (int *)(base + used);
+    used += align256(sizeof(int) * box_of_block.size());
+    G.blockstart = (int *)(base + used);
+    used += align256(sizeof(int) * n);
+    if (used > B->bp.force_bytes) return fail(LBE_ERR_OOM, "force tables exceed their reservation");
+    HIP_TRY(hipMemcpy(G.blockbox, box_of_block.data(), sizeof(int) * box_of_block.size(),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(G.blockstart, start.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+    B->att_groups.push_back(G);
   }
   prepare_force_kernels(maxR, B->visc, maxent);
   for (int b = 0; b < n; ++b) B->zchunks[b] = B->boxes[b]->args.zchunk;
@@ -915,6 +943,12 @@ void batch_launch_step(lbe_batch *B, int cur) {
     bf.blockbox = G.blockbox;
     bf.blockstart = G.blockstart;
     launch_batch_force(bf, G.nblocks, G.R, B->visc, G.entries, B->stream);
+  }
+  for (const auto &G : B->att_groups) {
+    BatchArgs bf = ba;
+    bf.blockbox = G.blockbox;
+    bf.blockstart = G.blockstart;
+    launch_batch_att(bf, G.nblocks, G.R, B->stream);
   }
   launch_batch_collide(ba, B->bp.node_blocks, B->prec, B->stream);
 }

@@ -170,6 +170,8 @@ int force_blocks(const Geom &g, int zchunk, int ty = FORCE_TY);
 void launch_batch_moments(const BatchArgs &b, int nblocks, int prec, bool visc, hipStream_t s);
 // ball kernels of a batch: one launch per ball z depth zc
 void launch_batch_ball(const BatchArgs &b, int nblocks, int zc, size_t lds_bytes, hipStream_t s);
+// the attractive field of the boxes of one tail reach R (after the force groups)
+void launch_batch_att(const BatchArgs &b, int nblocks, int R, hipStream_t s);
 size_t ball_lds_bytes(int ball_R, int ball_total, int zc);
 int ball_blocks(const Geom &g, int zc);
 void launch_batch_force(const BatchArgs &b, int nblocks, int R, bool visc, int entries, hipStream_t s);

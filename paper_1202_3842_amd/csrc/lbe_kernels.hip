@@ -1170,6 +1170,19 @@ __global__ __launch_bounds__(FNT) void kb_force(BatchArgs ba) {
                                       local / (nbx * nby), lds);
 }
 
+// the attractive field of every box of one tail reach R (one species, so the
+// pair (0, 0)), added to C^mf/n after the hard-sphere gathers; 32 x 8 tiles
+template <int R>
+__global__ __launch_bounds__(FNT) void kb_force_att(BatchArgs ba) {
+  extern __shared__ double lds[];
+  const int b = cptr(ba.blockbox)[blockIdx.x];
+  const auto &a = *cptr(ba.boxes + b);
+  const int local = blockIdx.x - cptr(ba.blockstart)[b];
+  const int nbx = (a.g.nx + FTX - 1) / FTX, nby = (a.g.ny + FTY - 1) / FTY;
+  force_body<R, 3, 1, FNT>(a, nullptr, 0, 0, 1, local % nbx, (local / nbx) % nby, local / (nbx * nby),
+                           lds);
+}
+
 template <typename T>
 __global__ __launch_bounds__(BLOCK) void kb_collide(BatchArgs ba) {
   const int b = cptr(ba.blockbox)[blockIdx.x];
@@ -2381,6 +2394,26 @@ void launch_batch_force(const BatchArgs &b, int nblocks, int R, bool visc, int e
     break;
   switch (R) { BF(1) BF(2) BF(3) BF(4) BF(5) BF(6) BF(7) BF(8) default: break; }
 #undef BF
+}
+
+template <int R>
+static void batch_att_r(const BatchArgs &b, int nblocks, hipStream_t s) {
+  // one staged field and the table through scalar loads: at most 18 KB
+  const size_t bytes = force_lds(3, R, FTY, 0, 1);
+  hipLaunchKernelGGL((kb_force_att<R>), dim3(nblocks), dim3(FNT), bytes, s, b);
+}
+
+void launch_batch_att(const BatchArgs &b, int nblocks, int R, hipStream_t s) {
+  switch (R) {
+    case 1: batch_att_r<1>(b, nblocks, s); break;
+    case 2: batch_att_r<2>(b, nblocks, s); break;
+    case 3: batch_att_r<3>(b, nblocks, s); break;
+    case 4: batch_att_r<4>(b, nblocks, s); break;
+    case 5: batch_att_r<5>(b, nblocks, s); break;
+    case 6: batch_att_r<6>(b, nblocks, s); break;
+    case 7: batch_att_r<7>(b, nblocks, s); break;
+    default: batch_att_r<8>(b, nblocks, s); break;
+  }
 }
 
 void launch_batch_collide(const BatchArgs &b, int nblocks, int prec, hipStream_t s) {

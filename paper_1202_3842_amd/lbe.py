@@ -403,7 +403,8 @@ class Batch:
 
 
 def batch_from_workloads(ws, prec=LBE_FP64, flags=LBE_VISC) -> Batch:
-    cfgs = [make_config(w.nx, w.ny, w.nz, w.sigma, w.periodic, w.tau, w.kT, prec, flags) for w in ws]
+    cfgs = [make_config(w.nx, w.ny, w.nz, w.sigma, w.periodic, w.tau, w.kT, prec, flags,
+                        att_eps=getattr(w, "att_eps", None), att_rc=getattr(w, "att_rc", 0.0)) for w in ws]
     b = Batch(cfgs)
     for box, w in zip(b.boxes, ws):
         load_workload(box, w)

@@ -119,5 +119,8 @@ def test_attraction_configuration_is_validated(L):
     ok = lbe.make_config(16, 16, 16, [2.0], att_eps=0.1, att_rc=5.0, flags=0)
     assert L.lbe_adjoint_workspace_bytes(C.byref(ok), 10, 5) > 0      # the adjoint covers it
     arr = (lbe.lbe_config * 1)(ok)
-    assert L.lbe_batch_workspace_bytes(arr, 1) == 0
-    assert b"attractive" in L.lbe_last_error()
+    assert L.lbe_batch_workspace_bytes(arr, 1) > 0              # batches take it
+    # ... but a batched box with it needs a hard-sphere shell to add to
+    thin = (lbe.lbe_config * 1)(lbe.make_config(16, 16, 16, [0.4], att_eps=0.1, att_rc=3.0, flags=0))
+    assert L.lbe_batch_workspace_bytes(thin, 1) == 0
+    assert b"hard-sphere shell" in L.lbe_last_error()

@@ -110,8 +110,49 @@ def test_attraction_full_size_well128(L):
     o.close()
 
 
-def test_attraction_is_refused_where_not_built(L):
-    cfg = L.make_config(16, 16, 16, [2.0], att_eps=0.1, att_rc=5.0, flags=0)
-    with pytest.raises(L.LBEError) as e:
-        L.Batch([cfg])
-    assert e.value.code in (L.LBE_ERR_UNSUPPORTED, L.LBE_ERR_ARG)
+def test_attraction_fp32_storage(L):
+    """FP32 population storage with the attractive field (FP64 arithmetic):
+    the same loose bar as the plain FP32 check, after 10 steps."""
+    w = _well(0.5 * KT, 6.0)
+    banner("attraction fp32 populations")
+    o = oracle_from_workload(w, L.LBE_VISC)
+    b = L.box_from_workload(w, prec=L.LBE_FP32_POP, flags=L.LBE_VISC)
+    o.step(10)
+    b.step(10)
+    en = rel_err(b.density(0), o.density(0))
+    eu = rel_err(b.velocity(-1), o.velocity(-1))
+    print(f"[fp32] attraction n rel err {en:.3e} u rel err {eu:.3e}", flush=True)
+    assert en < 1e-5 and eu < 1e-3
+    b.close()
+
+
+def test_attraction_in_batched_boxes(L):
+    """Uneven boxes, some with the attractive field (different depths and
+    cutoffs, so three tail reaches), stepped as a batch from graph replays and
+    batched launches: bitwise equal to the same boxes stepped alone, and one
+    of them equal to the oracle to 1e-11."""
+    spec = [(20, 3.0, 0.3, 0.25 * KT, 5.5), (27, 4.0, 0.25, 0.0, 0.0), (17, 3.0, 0.2, 0.4 * KT, 7.5),
+            (24, 6.0, 0.3, 0.2 * KT, 8.0)]
+    ws = []
+    for i, (n, sg, ns3, eps, rc) in enumerate(spec):
+        w = W.well_box(n, sg, ns3, 0.5, n / 4.0, 1e-3, 800 + i, 6, name=f"att_batch{i}")
+        if eps > 0:
+            w.att_eps, w.att_rc = [[eps]], rc
+        ws.append(w)
+    flags = L.LBE_VISC
+    banner("attraction in batched boxes")
+    batch = L.batch_from_workloads(ws, flags=flags)
+    singles = [L.box_from_workload(w, flags=flags) for w in ws]
+    batch.step(5, mode=2)   # graph replays (odd: plus one batched step)
+    batch.step(2, mode=1)   # batched launches
+    for b in singles:
+        b.step(7)
+    for i, (bb, bs) in enumerate(zip(batch.boxes, singles)):
+        for dist in (0, 1):
+            assert np.array_equal(bb.populations(0, dist), bs.populations(0, dist)), (i, dist)
+    o = oracle_from_workload(ws[2], flags)
+    o.step(7)
+    compare_state(o, batch.boxes[2], 1, TOL, "batched box with attraction")
+    for b in singles:
+        b.close()
+    batch.close()
