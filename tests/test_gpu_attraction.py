@@ -128,7 +128,7 @@ def test_attraction_fp32_storage(L):
 
 def test_attraction_in_batched_boxes(L):
     """Uneven boxes, some with the attractive field (different depths and
-    cutoffs, so three tail reaches), stepped as a batch from graph replays and
+    cutoffs: tail reaches of 5 and 7 nodes), stepped as a batch from graph replays and
     batched launches: bitwise equal to the same boxes stepped alone, and one
     of them equal to the oracle to 1e-11."""
     spec = [(20, 3.0, 0.3, 0.25 * KT, 5.5), (27, 4.0, 0.25, 0.0, 0.0), (17, 3.0, 0.2, 0.4 * KT, 7.5),
