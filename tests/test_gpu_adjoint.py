@@ -329,15 +329,19 @@ def test_adjoint_attraction_tile_rows_agree():
     assert np.array_equal(grads[0], grads[1])
 
 
-def test_adjoint_full_size_directional_derivative():
+@pytest.mark.parametrize("att", [False, True], ids=["visc", "visc_attraction"])
+def test_adjoint_full_size_directional_derivative(att):
     """The 128^3 benchmark box (sigma = 6, C^visc, printed inversions) in the
     launch configuration bench.py times, 3 steps: the adjoint's dL/dV along
     a smooth direction dV equals the central difference of L along dV (the
     library's own forward at V +- h dV), for L = sum_r c(r) n(r, T) with
-    seeded weights c.  A property that holds at any size; the reference
-    gradient covers the small boxes."""
+    seeded weights c.  Also with the attractive tail (eps = kT/4, rc = 8),
+    whose transpose takes its two-row tiles at this size.  A property that
+    holds at any size; the reference gradient covers the small boxes."""
     from paper_1202_3842_amd import lbe, autotune
     w = W.c2_large_well()
+    if att:
+        w.att_eps, w.att_rc = [[0.25 * W.KT]], 8.0
     flags = lbe.LBE_VISC | lbe.LBE_PRINTED_INV
     T = 3
     c = W.rng(61).uniform(-1.0, 1.0, size=w.shape)
