@@ -1343,11 +1343,11 @@ __global__ __launch_bounds__(BLOCK) void k_diag_errn(Geom g, int M, const uint32
 inline dim3 grid_for(int N) { return dim3((N + BLOCK - 1) / BLOCK); }
 
 // ------------------------------------------------------------------------
-// adjoint (reverse mode) of one step, for FP64 populations and the C^mf
-// scheme (no C^visc; with or without the interspecies drag; trapezoidal or
-// Euler, two distributions or one).  "bar" marks
-// the adjoint dL/d(quantity).  The adjoint
-// state between steps is (mu, nbar) in the post-streaming frame (AdjArgs).
+// adjoint (reverse mode) of one step, for FP64 populations: C^mf, with or
+// without C^visc, the interspecies drag and the attractive field;
+// trapezoidal or Euler, two distributions or one.  "bar" marks the adjoint
+// dL/d(quantity).  The adjoint state between steps is (mu, nbar) in the
+// post-streaming frame (AdjArgs).
 // ------------------------------------------------------------------------
 
 // adjoint of the pre-streaming slot (r, q): the streaming map is a
@@ -1520,8 +1520,10 @@ __device__ inline void zero_Gbar(const AdjArgs &d, long long N, int i) {
 //   Xbar  = 3 B1 + 9 B2.u^a - 3 B0 u^a
 //   Cbar  = 4.5 kappa D2.u^a + (3 - 1.5 kappa) D0 u^a
 //   Ybar  = 3 D1 + 9 D2.u^a - 3 D0 u^a
-// then back through Pi, u, u^a = J/n, J = J~ + (X or Y)/2, X = C + Y,
-// Y = n F and C = n phi.
+// then back through Pi, u, u^a = J/n, J = J~ + (X or Y)/2 (J~ for Euler),
+// X = C + Y, Y = n F (+ n psi with C^visc, + C^drag) and C = n phi.  With
+// C^visc it also writes psibar = n Ybar and u~ = J~/n (padded) for the
+// C^visc transposes.
 template <int M, class A>
 __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
   const Geom g = geom_of(a);
@@ -1838,8 +1840,8 @@ __global__ __launch_bounds__(FNT) void k_adj_att(StepArgs a, AdjArgs d, int alph
 
 // adjoint of the C^visc gather of the directed pair (alpha, beta), force_body
 // MODE 5 or 6 (see there): writes or accumulates into nbar (acc bit 0),
-// Gbar (bit 1) and Jnl (bit 2); 32 x 8 tiles, the ring table through scalar
-// loads
+// Gbar (bit 1) and Jnl (bit 2); 32 x (NT/32) tiles, the ring table through
+// scalar loads
 template <int R, int MODE, int NT>
 __global__ __launch_bounds__(NT) void k_adj_visc(StepArgs a, AdjArgs d, int alpha, int beta, int acc) {
   extern __shared__ double lds[];
