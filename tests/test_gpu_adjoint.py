@@ -371,3 +371,36 @@ def test_adjoint_full_size_directional_derivative(att):
           flush=True)
     assert abs(ana) > 100 * noise
     assert abs(ana - fd) <= 1e-6 * abs(ana) + 10 * noise
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_adjoint_random_configurations(seed):
+    """Seeded random channels (sizes, diameters, C^visc, printed inversion,
+    kappa = 4, Euler, one distribution, drag and the attractive tails each
+    switched on at random; random horizon and segment) against the reference
+    gradient."""
+    import math
+    g = W.rng(7000 + seed)
+    sig = [(2.0, 3.0), (3.0, 2.0), (2.0, 2.0), (1.0, 3.0)][int(g.integers(0, 4))]
+    w = small_channel(nx=int(g.integers(10, 16)), ny=10, nz=int(g.integers(7, 12)), sigma=sig, seed=100 + seed)
+    flags = 0
+    for bit in (1, 2, 4, 16, 32, 64):
+        if g.uniform() < 0.4:
+            flags |= bit
+    att = g.uniform() < 0.4
+    if att:
+        w.att_eps, w.att_rc = [[0.3 * W.KT, 0.2 * W.KT], [0.2 * W.KT, 0.25 * W.KT]], float(g.uniform(4.0, 6.0))
+        for k, d in enumerate((w.nx, w.ny, w.nz)):
+            if (w.periodic >> k) & 1 and d < math.ceil(w.att_rc):
+                w.periodic &= ~(1 << k)
+    T = int(g.integers(3, 7))
+    seg = int(g.integers(1, T + 1))
+    print(f"random adjoint {seed}: {w.nx}x{w.ny}x{w.nz} sigma {sig} flags {flags} att {att} T {T} "
+          f"segment {seg}", flush=True)
+    pw = pop_weights(w) * 1e-3
+    if flags & 32:
+        pw[1] = 0.0
+    rV, rf, rg = reference(w, flags, T, pw)
+    gV, gf, gg = gpu_gradient(w, flags, T, seg, pw)
+    assert_close(gV, rV, 1e-10, "dL/dV")
+    assert_close(gf, rf, 1e-10, "dL/df0")
