@@ -314,10 +314,13 @@ void lbe_batch_destroy(lbe_batch *batch);
  * Sec. 4.1).  The objective enters through its derivatives with respect to
  * the read-outs of the final state: n^a (lbe_get_density), J^a
  * (lbe_get_momentum) and the post-streaming populations
- * (lbe_get_populations).  Supported: FP64 populations, with every force
+ * (lbe_get_populations).  Supported: every force
  * (C^mf, C^visc, the attractive field, the interspecies drag), either
  * inversion and either kappa, in every scheme variant (LBE_EULER,
- * LBE_SINGLE).  Under LBE_SINGLE the scheme has no g, so the
+ * LBE_SINGLE), and either storage.  With LBE_FP32_POP the result is the
+ * reverse of the FP64 step along the trajectory of the stored FP32
+ * populations (the rounding to storage is taken as the identity), with
+ * the adjoint state in FP64.  Under LBE_SINGLE the scheme has no g, so the
  * g part of dL_dpop is ignored and the g gradient is zero.  The forward
  * keeps a copy of the state every `segment` steps; the backward recomputes
  * one segment at a time from its copy, so device memory grows as

@@ -37,7 +37,6 @@ struct AdjPlan {
 lbe_status make_adj_plan(const lbe_config *cfg, int nsteps, int segment, AdjPlan &ap) {
   lbe_status st = make_plan(cfg, ap.pl);
   if (st != LBE_OK) return st;
-  if (cfg->prec != LBE_FP64) return fail(LBE_ERR_UNSUPPORTED, "the adjoint needs FP64 populations");
   if (nsteps < 1 || segment < 1) return fail(LBE_ERR_ARG, "nsteps and segment must be >= 1");
   const Plan &P = ap.pl;
   const size_t N = P.g.N, Np = P.g.Np, M = P.M, npairs = P.npairs;
@@ -59,7 +58,8 @@ lbe_status make_adj_plan(const lbe_config *cfg, int nsteps, int segment, AdjPlan
   ap.drag = M > 1 && (cfg->flags & LBE_DRAG) && !(cfg->flags & LBE_IDEAL);
   ap.visc = (cfg->flags & LBE_VISC) && !(cfg->flags & LBE_IDEAL);
   ap.slot_bytes = ap.so_J + (ap.drag || ap.visc ? align256(sizeof(double) * 3 * M * Np) : 0);
-  ap.mu_bytes = P.pop_bytes;  // same layout as a state buffer, FP64
+  // the adjoint state: the layout of a state buffer, always FP64
+  ap.mu_bytes = (size_t)2 * M * Q * P.Ns * sizeof(double);
   ap.off_cp = take(P.pop_bytes * (size_t)(ap.nseg + 1));
   ap.off_roll = take(P.pop_bytes * 2);
   ap.off_tape = take(ap.slot_bytes * (size_t)ap.S);
@@ -127,7 +127,7 @@ struct lbe_adjoint {
   // fields of state `pop` into slot j: n (padded) and Pi~, J~, then G and C^mf/n
   void fields(int j, const void *pop) const {
     StepArgs a = slot_args(j);
-    launch_tape_moments(a, (const double *)pop, slot_PJ(j), c->stream);
+    launch_tape_moments(a, c->cfg.prec, pop, slot_PJ(j), c->stream);
     launch_contact(a, c->stream);
     launch_forces(a, c->stream);
   }
@@ -232,7 +232,8 @@ lbe_status lbe_adjoint_backward(lbe_adjoint *A, const double *dL_dn, const doubl
     HIP_TRY(hipMemcpyAsync(A->roll(0), A->cp(k), ap.pl.pop_bytes, hipMemcpyDeviceToDevice, s));
     for (int j = 0; j < len; ++j) {
       A->fields(j, A->roll(j & 1));
-      if (j + 1 < len) launch_collide(A->slot_args(j), LBE_FP64, A->roll(j & 1), A->roll((j + 1) & 1), s);
+      if (j + 1 < len)
+        launch_collide(A->slot_args(j), c->cfg.prec, A->roll(j & 1), A->roll((j + 1) & 1), s);
     }
     for (int j = len - 1; j >= 0; --j) {
       AdjArgs e = d;

@@ -178,7 +178,7 @@ void launch_batch_force(const BatchArgs &b, int nblocks, int R, bool visc, int e
 void launch_batch_collide(const BatchArgs &b, int nblocks, int prec, hipStream_t s);
 void prepare_force_kernels(int maxR, bool visc, int max_entries);
 // adjoint passes (FP64 populations, no C^visc)
-void launch_tape_moments(const StepArgs &a, const double *pop, double *PJ, hipStream_t s);
+void launch_tape_moments(const StepArgs &a, int prec, const void *pop, double *PJ, hipStream_t s);
 void launch_adj_collide(const StepArgs &a, const AdjArgs &d, hipStream_t s);
 void launch_adj_readout(const StepArgs &a, const AdjArgs &d, hipStream_t s);
 // mu_out from the node adjoints, nbar and the incoming state (or the seed

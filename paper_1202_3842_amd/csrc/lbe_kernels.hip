@@ -1788,8 +1788,8 @@ __global__ __launch_bounds__(BLOCK) void k_adj_stream(StepArgs a, AdjArgs d) {
 // the tilde moments Pi~, J~ of a state (tape) and its densities n (padded
 // field, as k_moments writes them), and J~ padded as well when the tape has
 // a field for it
-template <int M>
-__global__ __launch_bounds__(BLOCK) void k_tape_moments(StepArgs a, const double *__restrict__ pop,
+template <typename T, int M>
+__global__ __launch_bounds__(BLOCK) void k_tape_moments(StepArgs a, const T *__restrict__ pop,
                                                       double *__restrict__ PJ) {
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   const Geom g = a.g;
@@ -2457,9 +2457,14 @@ void launch_diag_errn(const Geom &g, int M, const uint32_t *bb, const Readout &r
     default: { constexpr int MM = 4; CALL; } break; \
   }
 
-void launch_tape_moments(const StepArgs &a, const double *pop, double *PJ, hipStream_t s) {
+void launch_tape_moments(const StepArgs &a, int prec, const void *pop, double *PJ, hipStream_t s) {
   const dim3 gr = grid_for(a.g.N);
-  LBE_SWITCH_M(a.M, hipLaunchKernelGGL(k_tape_moments<MM>, gr, dim3(BLOCK), 0, s, a, pop, PJ))
+  if (prec == LBE_FP64)
+    LBE_SWITCH_M(a.M, hipLaunchKernelGGL((k_tape_moments<double, MM>), gr, dim3(BLOCK), 0, s, a,
+                                         (const double *)pop, PJ))
+  else
+    LBE_SWITCH_M(a.M, hipLaunchKernelGGL((k_tape_moments<float, MM>), gr, dim3(BLOCK), 0, s, a,
+                                         (const float *)pop, PJ))
 }
 
 void launch_adj_collide(const StepArgs &a, const AdjArgs &d, hipStream_t s) {

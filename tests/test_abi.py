@@ -55,9 +55,12 @@ def test_adjoint_workspace_and_scope(L):
     pop = 2 * 19 * 32 ** 3 * 8
     # 11 checkpoints + 10 tape slots vs 3 checkpoints + 50 tape slots
     assert n1 >= 11 * pop and n2 > n1
-    bad = lbe.make_config(32, 32, 32, [4.0], prec=lbe.LBE_FP32_POP, flags=0)
-    assert L.lbe_adjoint_workspace_bytes(C.byref(bad), 10, 5) == 0
-    assert b"adjoint" in L.lbe_last_error()
+    bad = lbe.make_config(32, 32, 32, [4.0], flags=0)
+    assert L.lbe_adjoint_workspace_bytes(C.byref(bad), 10, 0) == 0
+    assert b"segment" in L.lbe_last_error()
+    # FP32 storage: checkpoints and tape states at half size, the adjoint state in FP64
+    f32 = lbe.make_config(32, 32, 32, [4.0], prec=lbe.LBE_FP32_POP, flags=0)
+    assert 0 < L.lbe_adjoint_workspace_bytes(C.byref(f32), 100, 10) < n1
     # C^visc adds the padded J~ field to every tape slot and its adjoint fields
     visc = lbe.make_config(32, 32, 32, [4.0], flags=lbe.LBE_VISC)
     assert L.lbe_adjoint_workspace_bytes(C.byref(visc), 100, 10) > n1

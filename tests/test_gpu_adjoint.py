@@ -41,9 +41,9 @@ def reference(w, flags, T, pw):
     return V.grad.numpy().reshape(w.shape), f0.grad.numpy(), rg
 
 
-def gpu_gradient(w, flags, T, segment, pw):
+def gpu_gradient(w, flags, T, segment, pw, prec=0):
     from paper_1202_3842_amd import lbe
-    box = lbe.box_from_workload(w, flags=flags)
+    box = lbe.box_from_workload(w, prec=prec, flags=flags)
     adj = lbe.Adjoint(box, T, segment)
     adj.forward()
     n_t, fluid, plane = objective_terms(w)
@@ -404,3 +404,19 @@ def test_adjoint_random_configurations(seed):
     gV, gf, gg = gpu_gradient(w, flags, T, seg, pw)
     assert_close(gV, rV, 1e-10, "dL/dV")
     assert_close(gf, rf, 1e-10, "dL/df0")
+
+
+@pytest.mark.parametrize("flags", [1 | 2, 0, 1 | 64])
+def test_adjoint_fp32_storage(flags):
+    """FP32 population storage: the reverse of the FP64 step along the FP32
+    trajectory.  It differs from the FP64 gradient by the storage rounding
+    only (bar 1e-5 of the max-norm; the forward's FP32 error is ~5e-8)."""
+    from paper_1202_3842_amd import lbe
+    w = small_channel()
+    pw = pop_weights(w) * 1e-3
+    print(f"small channel FP32 storage flags {flags}", flush=True)
+    rV, rf, rg = reference(w, flags, 5, pw)
+    gV, gf, gg = gpu_gradient(w, flags, 5, 2, pw, prec=lbe.LBE_FP32_POP)
+    assert_close(gV, rV, 1e-5, "dL/dV (fp32 storage)")
+    assert_close(gf, rf, 1e-5, "dL/df0 (fp32 storage)")
+    assert_close(gg, rg, 1e-5, "dL/dg0 (fp32 storage)")
