@@ -289,6 +289,28 @@ def adjoint_leg(lbe, torch, W, segment=20, att=False):
     t_bwd = ev[4].elapsed_time(ev[5])
     gnorm = float(out.abs().max())
     adj.close()
+    # the same with one segment: the forward records the whole tape
+    # (T + 1 slots) and the backward recomputes nothing
+    one = None
+    if not att:
+        adj = lbe.Adjoint(box, T, T)
+        lbe.load_workload(box, w)
+        torch.cuda.synchronize()
+        ev[2].record(st)
+        adj.forward()
+        ev[3].record(st)
+        ev[3].synchronize()
+        t_fwd1 = ev[2].elapsed_time(ev[3])
+        torch.cuda.synchronize()
+        ev[4].record(st)
+        adj.backward(dn_d, dJ_d, None, out=out)
+        ev[5].record(st)
+        ev[5].synchronize()
+        t_bwd1 = ev[4].elapsed_time(ev[5])
+        adj.close()
+        one = {"forward_taped_ms": round(t_fwd1, 3), "backward_ms": round(t_bwd1, 3),
+               "adjoint_vs_forward": round(t_bwd1 / t_plain, 3)}
+        log(f"adjoint, one segment: taped forward {t_fwd1:.1f} ms, backward {t_bwd1:.1f} ms")
     box.close()
     log(f"adjoint{' with attraction' if att else ''}: plain forward {t_plain:.1f} ms, "
         f"checkpointed forward {t_fwd:.1f} ms, backward {t_bwd:.1f} ms ({T} steps)")
@@ -299,13 +321,15 @@ def adjoint_leg(lbe, torch, W, segment=20, att=False):
         "backward_ms": round(t_bwd, 3),
         "adjoint_vs_forward": round(t_bwd / t_plain, 3),
         "max_abs_dL_dV": gnorm,
+        "one_segment": one,
     }
 
 
-def adjoint_box_leg(lbe, torch, W, flags, T=40, segment=10):
+def adjoint_box_leg(lbe, torch, W, flags, T=40, segment=40):
     """dL/dV on the 128^3 benchmark box with its own scheme (C^visc on,
-    printed inversions), T steps checkpointed every `segment`: forward,
-    checkpointed forward and backward times, L = sum of n^2 at the end."""
+    printed inversions), T steps in one segment (the forward records the
+    tape, 41 slots of about 0.27 GB, and the backward recomputes nothing):
+    forward, taped forward and backward times, L = sum of n^2 at the end."""
     from paper_1202_3842_amd import autotune
     w = W.c2_large_well()
     box = lbe.box_from_workload(w, flags=flags)

@@ -320,7 +320,9 @@ void lbe_batch_destroy(lbe_batch *batch);
  * LBE_SINGLE), and either storage.  With LBE_FP32_POP the result is the
  * reverse of the FP64 step along the trajectory of the stored FP32
  * populations (the rounding to storage is taken as the identity), with
- * the adjoint state in FP64.  Under LBE_SINGLE the scheme has no g, so the
+ * the adjoint state in FP64.  With segment >= nsteps the forward itself
+ * records what the backward needs (nsteps + 1 tape slots) and the backward
+ * recomputes nothing.  Under LBE_SINGLE the scheme has no g, so the
  * g part of dL_dpop is ignored and the g gradient is zero.  The forward
  * keeps a copy of the state every `segment` steps; the backward recomputes
  * one segment at a time from its copy, so device memory grows as

@@ -10,7 +10,10 @@
 // J~, and J~ as a padded field with C^visc or the interspecies drag), and the
 // adjoint steps run in reverse over the tape.  The adjoint of the external
 // force is accumulated over all steps and turned into dL/dV by the transpose
-// of -grad_h at the end.
+// of -grad_h at the end.  When the whole horizon is one segment (segment
+// >= nsteps), the forward itself fills the tape as it steps, and the
+// backward recomputes nothing.  The read-out adjoint has a tape slot of its
+// own.
 #include <string.h>
 
 #include <algorithm>
@@ -62,7 +65,7 @@ lbe_status make_adj_plan(const lbe_config *cfg, int nsteps, int segment, AdjPlan
   ap.mu_bytes = (size_t)2 * M * Q * P.Ns * sizeof(double);
   ap.off_cp = take(P.pop_bytes * (size_t)(ap.nseg + 1));
   ap.off_roll = take(P.pop_bytes * 2);
-  ap.off_tape = take(ap.slot_bytes * (size_t)ap.S);
+  ap.off_tape = take(ap.slot_bytes * (size_t)(ap.S + 1));  // S steps + the read-out
   ap.off_mu = take(ap.mu_bytes * 2);
   ap.off_node = take(sizeof(double) * 5 * M * N);
   ap.off_nbar = take(sizeof(double) * M * N);
@@ -89,6 +92,7 @@ struct lbe_adjoint {
   char *ws = nullptr;
   int cur = 0;              // mu buffer holding the adjoint state
   bool forward_done = false, backward_done = false;
+  bool taped = false;       // the forward filled the tape (one segment)
 
   char *cp(int k) const { return ws + ap.off_cp + (size_t)k * ap.pl.pop_bytes; }
   char *roll(int k) const { return ws + ap.off_roll + (size_t)k * ap.pl.pop_bytes; }
@@ -172,13 +176,26 @@ lbe_status lbe_adjoint_forward(lbe_adjoint *A) {
   if (c->poisoned) return fail(LBE_ERR_UNSTABLE, "context is unstable; reinitialise the state");
   if (c->next_phase != 0) return fail(LBE_ERR_STATE, "a phased step is incomplete");
   const AdjPlan &ap = A->ap;
-  A->forward_done = A->backward_done = false;
-  for (int t = 0; t < ap.T; ++t) {
-    if (t % ap.S == 0)
-      HIP_TRY(hipMemcpyAsync(A->cp(t / ap.S), c->pop(c->cur), ap.pl.pop_bytes, hipMemcpyDeviceToDevice,
-                             c->stream));
-    lbe_status st = lbe_step(c, 1);
-    if (st != LBE_OK) return st;
+  A->forward_done = A->backward_done = A->taped = false;
+  if (ap.nseg == 1) {
+    // one segment: each step's fields go to its tape slot, and the
+    // collision reads them there (the kernels of lbe_step, on the tape)
+    HIP_TRY(hipMemcpyAsync(A->cp(0), c->pop(c->cur), ap.pl.pop_bytes, hipMemcpyDeviceToDevice, c->stream));
+    for (int t = 0; t < ap.T; ++t) {
+      A->fields(t, c->pop(c->cur));
+      launch_collide(A->slot_args(t), c->cfg.prec, c->pop(c->cur), c->pop(c->cur ^ 1), c->stream);
+      LAUNCH_CHECK();
+      c->cur ^= 1;
+    }
+    A->taped = true;
+  } else {
+    for (int t = 0; t < ap.T; ++t) {
+      if (t % ap.S == 0)
+        HIP_TRY(hipMemcpyAsync(A->cp(t / ap.S), c->pop(c->cur), ap.pl.pop_bytes, hipMemcpyDeviceToDevice,
+                               c->stream));
+      lbe_status st = lbe_step(c, 1);
+      if (st != LBE_OK) return st;
+    }
   }
   HIP_TRY(hipMemcpyAsync(A->cp(ap.nseg), c->pop(c->cur), ap.pl.pop_bytes, hipMemcpyDeviceToDevice,
                          c->stream));
@@ -214,12 +231,13 @@ lbe_status lbe_adjoint_backward(lbe_adjoint *A, const double *dL_dn, const doubl
   if ((dL_dpop && !d.dpop) || (dL_dn && !d.dn) || (dL_dJ && !d.dJ))
     return fail(LBE_ERR_HIP, "seed upload failed");
   launch_fill(d.Fbar, 3 * (long long)N, 0.0, s);
-  // adjoint of the read-out of the final state
-  A->fields(0, A->cp(ap.nseg));
+  // adjoint of the read-out of the final state, in the tape's last slot
+  const int term = ap.S;
+  A->fields(term, A->cp(ap.nseg));
   {
-    StepArgs a = A->slot_args(0);
+    StepArgs a = A->slot_args(term);
     AdjArgs e = d;
-    e.PJ = A->slot_PJ(0);
+    e.PJ = A->slot_PJ(term);
     e.mu_out = A->mu(0);
     launch_adj_readout(a, e, s);
     launch_adj_nonlocal(a, e, s);
@@ -229,11 +247,13 @@ lbe_status lbe_adjoint_backward(lbe_adjoint *A, const double *dL_dn, const doubl
   int cur = 0;
   for (int k = ap.nseg - 1; k >= 0; --k) {
     const int t0 = k * ap.S, len = std::min(ap.S, ap.T - t0);
-    HIP_TRY(hipMemcpyAsync(A->roll(0), A->cp(k), ap.pl.pop_bytes, hipMemcpyDeviceToDevice, s));
-    for (int j = 0; j < len; ++j) {
-      A->fields(j, A->roll(j & 1));
-      if (j + 1 < len)
-        launch_collide(A->slot_args(j), c->cfg.prec, A->roll(j & 1), A->roll((j + 1) & 1), s);
+    if (!A->taped) {  // recompute the segment's tape from its checkpoint
+      HIP_TRY(hipMemcpyAsync(A->roll(0), A->cp(k), ap.pl.pop_bytes, hipMemcpyDeviceToDevice, s));
+      for (int j = 0; j < len; ++j) {
+        A->fields(j, A->roll(j & 1));
+        if (j + 1 < len)
+          launch_collide(A->slot_args(j), c->cfg.prec, A->roll(j & 1), A->roll((j + 1) & 1), s);
+      }
     }
     for (int j = len - 1; j >= 0; --j) {
       AdjArgs e = d;

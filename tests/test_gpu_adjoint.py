@@ -420,3 +420,31 @@ def test_adjoint_fp32_storage(flags):
     assert_close(gV, rV, 1e-5, "dL/dV (fp32 storage)")
     assert_close(gf, rf, 1e-5, "dL/df0 (fp32 storage)")
     assert_close(gg, rg, 1e-5, "dL/dg0 (fp32 storage)")
+
+
+@pytest.mark.parametrize("flags", [0, 1 | 2 | 64])
+def test_taped_forward_equals_checkpointed(flags):
+    """With one segment the forward records the tape and the backward does
+    no recompute: the final state equals plain stepping and the gradient
+    equals the checkpointed one, bit for bit."""
+    from paper_1202_3842_amd import lbe
+    w = small_channel()
+    n_t, fluid, plane = objective_terms(w)
+    T = 6
+    plain = lbe.box_from_workload(w, flags=flags)
+    plain.step(T)
+    grads = []
+    for seg in (T, 2):
+        box = lbe.box_from_workload(w, flags=flags)
+        adj = lbe.Adjoint(box, T, seg)
+        adj.forward()
+        for dist in (0, 1):
+            assert np.array_equal(box.populations(0, dist), plain.populations(0, dist)), (seg, dist)
+        dn = np.zeros((2,) + w.shape)
+        dn[0] = 2.0 * (box.density(0) - n_t) * fluid
+        grads.append(adj.backward(dn, None, None))
+        adj.close()
+        box.close()
+    plain.close()
+    assert np.abs(grads[0]).max() > 0
+    assert np.array_equal(grads[0], grads[1])
