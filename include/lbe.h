@@ -320,15 +320,16 @@ void lbe_batch_destroy(lbe_batch *batch);
  * LBE_SINGLE), and either storage.  With LBE_FP32_POP the result is the
  * reverse of the FP64 step along the trajectory of the stored FP32
  * populations (the rounding to storage is taken as the identity), with
- * the adjoint state in FP64.  With segment >= nsteps the forward itself
- * records what the backward needs (nsteps + 1 tape slots) and the backward
- * recomputes nothing.  Under LBE_SINGLE the scheme has no g, so the
- * g part of dL_dpop is ignored and the g gradient is zero.  The forward
- * keeps a copy of the state every `segment` steps; the backward recomputes
- * one segment at a time from its copy, so device memory grows as
- * (nsteps/segment + segment) states.  The context's potential, body forces
- * and solid mask must not change between lbe_adjoint_forward and
- * lbe_adjoint_backward. */
+ * the adjoint state in FP64.  Under LBE_SINGLE the scheme has no g, so the
+ * g part of dL_dpop is ignored and the g gradient is zero.
+ * Memory: the forward keeps a copy of the state every `segment` steps, and
+ * the backward recomputes one segment at a time from its copy into a tape
+ * of segment + 1 slots (each slot holds one step's fields: n, G, forces,
+ * tilde moments), so device memory grows as nsteps/segment states plus
+ * segment slots.  With segment >= nsteps the forward itself fills the tape
+ * (nsteps + 1 slots) and the backward recomputes nothing.  The context's
+ * potential, body forces and solid mask must not change between
+ * lbe_adjoint_forward and lbe_adjoint_backward. */
 typedef struct lbe_adjoint lbe_adjoint;
 
 /* Device workspace of an adjoint over nsteps steps checkpointed every
@@ -343,7 +344,7 @@ lbe_status lbe_adjoint_create(lbe_ctx *ctx, int nsteps, int segment, void *dev_w
                               size_t bytes, lbe_adjoint **out);
 
 /* Advance the context nsteps steps from its current state (the t = 0 of the
- * objective), keeping the checkpoints. */
+ * objective), keeping the checkpoints (or, in one segment, the tape). */
 lbe_status lbe_adjoint_forward(lbe_adjoint *adj);
 
 /* dL/dV from the derivatives of L with respect to the final read-outs, any
