@@ -280,12 +280,13 @@ lbe_status lbe_set_force_zchunk(lbe_ctx *ctx, int zchunk);
 lbe_status lbe_set_force_tiling(lbe_ctx *ctx, int zchunk, int order, int shape);
 
 /* ---- batched boxes --------------------------------------------------------
- * Many independent one-component boxes of different sizes and diameters
- * stepped together: every phase of a step is one launch covering all boxes
- * (one force launch per distinct shell range), and the launches of two
- * steps are captured once in a HIP graph and replayed.  The results are
- * bitwise those of stepping each box alone.  All boxes must have
- * nspecies = 1 and share prec and flags. */
+ * Many independent boxes of different sizes and diameters stepped
+ * together: every phase of a step is one launch covering all boxes (one
+ * force launch per directed species pair and distinct shell range), and the
+ * launches of two steps are captured once in a HIP graph and replayed.  The
+ * results are bitwise those of stepping each box alone.  All boxes must
+ * share nspecies, prec and flags; with several species every pair's shell
+ * must be non-empty (sigma_ab >= 1/2). */
 typedef struct lbe_batch lbe_batch;
 
 /* Device workspace for a batch of nboxes configurations, or 0 if invalid. */

@@ -770,7 +770,14 @@ lbe_status make_batch_plan(const lbe_config *cfgs, int nboxes, BatchPlan &bp) {
   for (int b = 0; b < nboxes; ++b) {
     lbe_status st = make_plan(&cfgs[b], plans[b]);
     if (st != LBE_OK) return fail(st, "box %d: %s", b, error_text());
-    if (cfgs[b].nspecies != 1) return fail(LBE_ERR_UNSUPPORTED, "batched boxes must have one species");
+    if (cfgs[b].nspecies != cfgs[0].nspecies)
+      return fail(LBE_ERR_ARG, "batched boxes must have the same number of species");
+    // with several species the pair gathers of one species add up, the first
+    // writing: every pair's shell must be there to write in every box
+    for (const HostShell &h : plans[b].shells)
+      if (cfgs[b].nspecies > 1 && h.e.empty() && !(cfgs[b].flags & LBE_IDEAL))
+        return fail(LBE_ERR_UNSUPPORTED, "box %d: a batched mixture needs every pair's shell (sigma_ab >= 1/2)",
+                    b);
     // the attraction adds to the hard-sphere force, which must have written it
     if (cfgs[b].att_eps[0][0] > 0.0 && plans[b].shells[0].e.empty())
       return fail(LBE_ERR_UNSUPPORTED, "box %d: the attractive field in a batch needs a hard-sphere shell", b);
@@ -799,8 +806,10 @@ lbe_status make_batch_plan(const lbe_config *cfgs, int nboxes, BatchPlan &bp) {
   bp.off_nodestart = take(sizeof(int) * nboxes);
   bp.off_ballbox = take(sizeof(int) * bp.ball_blocks);
   bp.off_ballstart = take(sizeof(int) * nboxes);
-  // block tables of the force groups, then of the attraction groups
-  bp.force_bytes = 2 * force_table_bytes(plans);
+  // block tables of the force groups, then of the attraction groups, per
+  // directed species pair
+  const size_t M = (size_t)cfgs[0].nspecies;
+  bp.force_bytes = 2 * M * M * force_table_bytes(plans);
   bp.off_force = take(bp.force_bytes);
   for (const Plan &p : plans) {
     bp.box_bytes.push_back(p.total);
@@ -819,8 +828,11 @@ struct lbe_batch {
   hipStream_t stream = nullptr;
   int prec = 0;
   bool visc = false;
+  int M = 1;
+  bool currents = false;             // the moments keep J~ (C^visc or the drag)
+  bool ideal = false;                // no nonlocal forces: no force groups
   struct Group {
-    int R, nblocks, entries;
+    int R, nblocks, entries, alpha, beta;
     int *blockbox, *blockstart;
   };
   std::vector<Group> groups, att_groups;
@@ -852,58 +864,53 @@ lbe_status batch_tables(lbe_batch *B) {
   char *base = B->ws + B->bp.off_force;
   size_t used = 0;
   int maxR = 0, maxent = 0;
-  for (int R = 1; R <= RING_MAX; ++R) {
-    std::vector<int> box_of_block, start(n, 0);
-    int ent = 0;
-    for (int b = 0; b < n; ++b) {
-      const StepArgs &a = B->boxes[b]->args;
-      if (a.t.pair_R[0] != R) continue;
-      start[b] = (int)box_of_block.size();
-      int nb = force_blocks(a.g, a.zchunk);
-      box_of_block.insert(box_of_block.end(), nb, b);
-      ent = std::max(ent, a.t.pair_nent[0]);
-    }
-    if (box_of_block.empty()) continue;
-    lbe_batch::Group G;
-    G.R = R;
-    G.nblocks = (int)box_of_block.size();
-    G.entries = ent;
-    G.blockbox = (int *)(base + used);
-    used += align256(sizeof(int) * box_of_block.size());
-    G.blockstart = (int *)(base + used);
-    used += align256(sizeof(int) * n);
-    if (used > B->bp.force_bytes) return fail(LBE_ERR_OOM, "force tables exceed their reservation");
-    HIP_TRY(hipMemcpy(G.blockbox, box_of_block.data(), sizeof(int) * box_of_block.size(),
-                      hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(G.blockstart, start.data(), sizeof(int) * n, hipMemcpyHostToDevice));
-    B->groups.push_back(G);
-    maxR = std::max(maxR, R);
-    maxent = std::max(maxent, ent);
-  }
-  // boxes with the attractive field, grouped by the tail's reach (32 x 8
-  // tiles, the same block count as the force groups)
-  for (int R = 1; R <= RING_MAX; ++R) {
-    std::vector<int> box_of_block, start(n, 0);
-    for (int b = 0; b < n; ++b) {
-      const StepArgs &a = B->boxes[b]->args;
-      if (a.t.att_R[0] != R) continue;
-      start[b] = (int)box_of_block.size();
-      box_of_block.insert(box_of_block.end(), force_blocks(a.g, a.zchunk), b);
-    }
-    if (box_of_block.empty()) continue;
-    lbe_batch::Group G;
-    G.R = R;
-    G.nblocks = (int)box_of_block.size();
-    G.entries = 0;
-    G.blockbox = (int *)(base + used);
-    used += align256(sizeof(int) * box_of_block.size());
-    G.blockstart = (int *)(base + used);
-    used += align256(sizeof(int) * n);
-    if (used > B->bp.force_bytes) return fail(LBE_ERR_OOM, "force tables exceed their reservation");
-    HIP_TRY(hipMemcpy(G.blockbox, box_of_block.data(), sizeof(int) * box_of_block.size(),
-                      hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(G.blockstart, start.data(), sizeof(int) * n, hipMemcpyHostToDevice));
-    B->att_groups.push_back(G);
+  // one group per directed species pair (alpha, beta) and reach R: the boxes
+  // whose pair reaches R nodes (its shell, or with att its attractive
+  // tail), in the order alpha, beta, R, so that for every box the pairs of
+  // one species follow each other as in a single box
+  auto build = [&](bool att, std::vector<lbe_batch::Group> &out) -> lbe_status {
+    for (int al = 0; al < B->M; ++al)
+      for (int be = 0; be < B->M; ++be) {
+        const int k = pair_index(B->M, al, be);
+        for (int R = 1; R <= RING_MAX; ++R) {
+          std::vector<int> box_of_block, start(n, 0);
+          int ent = 0;
+          for (int b = 0; b < n; ++b) {
+            const StepArgs &a = B->boxes[b]->args;
+            if ((att ? a.t.att_R[k] : a.t.pair_R[k]) != R) continue;
+            start[b] = (int)box_of_block.size();
+            box_of_block.insert(box_of_block.end(), force_blocks(a.g, a.zchunk), b);
+            if (!att) ent = std::max(ent, a.t.pair_nent[k]);
+          }
+          if (box_of_block.empty()) continue;
+          lbe_batch::Group G;
+          G.R = R;
+          G.nblocks = (int)box_of_block.size();
+          G.entries = ent;
+          G.alpha = al;
+          G.beta = be;
+          G.blockbox = (int *)(base + used);
+          used += align256(sizeof(int) * box_of_block.size());
+          G.blockstart = (int *)(base + used);
+          used += align256(sizeof(int) * n);
+          if (used > B->bp.force_bytes) return fail(LBE_ERR_OOM, "force tables exceed their reservation");
+          HIP_TRY(hipMemcpy(G.blockbox, box_of_block.data(), sizeof(int) * box_of_block.size(),
+                            hipMemcpyHostToDevice));
+          HIP_TRY(hipMemcpy(G.blockstart, start.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+          out.push_back(G);
+          if (!att) {
+            maxR = std::max(maxR, R);
+            maxent = std::max(maxent, ent);
+          }
+        }
+      }
+    return LBE_OK;
+  };
+  if (!B->ideal) {  // the ideal gas keeps its force buffers at zero
+    lbe_status st = build(false, B->groups);
+    if (st != LBE_OK) return st;
+    st = build(true, B->att_groups);  // added after all hard-sphere gathers
+    if (st != LBE_OK) return st;
   }
   prepare_force_kernels(maxR, B->visc, maxent);
   for (int b = 0; b < n; ++b) B->zchunks[b] = B->boxes[b]->args.zchunk;
@@ -931,26 +938,28 @@ void batch_launch_step(lbe_batch *B, int cur) {
   ba.blockbox = (const int *)(B->ws + B->bp.off_nodebox);
   ba.blockstart = (const int *)(B->ws + B->bp.off_nodestart);
   ba.cur = cur;
-  launch_batch_moments(ba, B->bp.node_blocks, B->prec, B->visc, B->stream);
+  launch_batch_moments(ba, B->bp.node_blocks, B->prec, B->currents, B->stream);
   {
     BatchArgs bb = ba;
     bb.blockbox = (const int *)(B->ws + B->bp.off_ballbox);
     bb.blockstart = (const int *)(B->ws + B->bp.off_ballstart);
-    launch_batch_ball(bb, B->bp.ball_blocks, BATCH_BALL_ZC, B->bp.ball_lds, B->stream);
+    launch_batch_ball(bb, B->bp.ball_blocks, BATCH_BALL_ZC, B->bp.ball_lds, B->M, B->stream);
   }
   for (const auto &G : B->groups) {
     BatchArgs bf = ba;
     bf.blockbox = G.blockbox;
     bf.blockstart = G.blockstart;
-    launch_batch_force(bf, G.nblocks, G.R, B->visc, G.entries, B->stream);
+    // the first pair of a species writes its force, later pairs add
+    launch_batch_force(bf, G.nblocks, G.R, B->visc, G.entries, G.alpha, G.beta, G.beta > 0 ? 1 : 0,
+                       B->stream);
   }
   for (const auto &G : B->att_groups) {
     BatchArgs bf = ba;
     bf.blockbox = G.blockbox;
     bf.blockstart = G.blockstart;
-    launch_batch_att(bf, G.nblocks, G.R, B->stream);
+    launch_batch_att(bf, G.nblocks, G.R, G.alpha, G.beta, B->stream);
   }
-  launch_batch_collide(ba, B->bp.node_blocks, B->prec, B->stream);
+  launch_batch_collide(ba, B->bp.node_blocks, B->prec, B->M, B->stream);
 }
 
 }  // namespace
@@ -979,6 +988,10 @@ lbe_status lbe_batch_create(const lbe_config *cfgs, int nboxes, void *ws, size_t
   B->stream = (hipStream_t)stream;
   B->prec = cfgs[0].prec;
   B->visc = (cfgs[0].flags & LBE_VISC) && !(cfgs[0].flags & LBE_IDEAL);
+  B->M = cfgs[0].nspecies;
+  B->ideal = (cfgs[0].flags & LBE_IDEAL) != 0;
+  B->currents = ((cfgs[0].flags & LBE_VISC) || ((cfgs[0].flags & LBE_DRAG) && B->M > 1)) &&
+                !(cfgs[0].flags & LBE_IDEAL);
   std::vector<int> nodebox, nodestart(nboxes), ballbox, ballstart(nboxes);
   for (int b = 0; b < nboxes; ++b) {
     lbe_ctx *c = nullptr;

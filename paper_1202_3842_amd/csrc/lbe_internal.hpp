@@ -169,13 +169,14 @@ int force_blocks(const Geom &g, int zchunk, int ty = FORCE_TY);
 // batched launches (M = 1 boxes sharing precision and flags)
 void launch_batch_moments(const BatchArgs &b, int nblocks, int prec, bool visc, hipStream_t s);
 // ball kernels of a batch: one launch per ball z depth zc
-void launch_batch_ball(const BatchArgs &b, int nblocks, int zc, size_t lds_bytes, hipStream_t s);
+void launch_batch_ball(const BatchArgs &b, int nblocks, int zc, size_t lds_bytes, int M, hipStream_t s);
 // the attractive field of the boxes of one tail reach R (after the force groups)
-void launch_batch_att(const BatchArgs &b, int nblocks, int R, hipStream_t s);
+void launch_batch_att(const BatchArgs &b, int nblocks, int R, int alpha, int beta, hipStream_t s);
 size_t ball_lds_bytes(int ball_R, int ball_total, int zc);
 int ball_blocks(const Geom &g, int zc);
-void launch_batch_force(const BatchArgs &b, int nblocks, int R, bool visc, int entries, hipStream_t s);
-void launch_batch_collide(const BatchArgs &b, int nblocks, int prec, hipStream_t s);
+void launch_batch_force(const BatchArgs &b, int nblocks, int R, bool visc, int entries, int alpha, int beta,
+                        int acc, hipStream_t s);
+void launch_batch_collide(const BatchArgs &b, int nblocks, int prec, int M, hipStream_t s);
 void prepare_force_kernels(int maxR, bool visc, int max_entries);
 // adjoint passes (FP64 populations, no C^visc)
 void launch_tape_moments(const StepArgs &a, int prec, const void *pop, double *PJ, hipStream_t s);

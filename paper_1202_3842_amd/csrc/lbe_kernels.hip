@@ -1148,47 +1148,50 @@ __global__ __launch_bounds__(BLOCK) void kb_moments(BatchArgs ba) {
   moments_body<T, VISC>(a, (const T *)a.pop[ba.cur], i);
 }
 
-// one-species boxes of one ball z depth ZC; blockbox/blockstart index
+// boxes of M species and one ball z depth ZC; blockbox/blockstart index
 // ball tiles here
-template <int ZC>
+template <int M, int ZC>
 __global__ __launch_bounds__(BLOCK) void kb_ball(BatchArgs ba) {
   extern __shared__ double lds[];
   const int b = cptr(ba.blockbox)[blockIdx.x];
   const auto &a = *cptr(ba.boxes + b);
   const AdjArgs none{};
-  ball_body<1, 0, ZC>(a, none, blockIdx.x - cptr(ba.blockstart)[b], lds);
+  ball_body<M, 0, ZC>(a, none, blockIdx.x - cptr(ba.blockstart)[b], lds);
 }
 
+// the shell gather of the directed pair (alpha, beta) for every box of one
+// shell reach R; acc: add to the force of species alpha (later pairs)
 template <int R, bool VISC>
-__global__ __launch_bounds__(FNT) void kb_force(BatchArgs ba) {
+__global__ __launch_bounds__(FNT) void kb_force(BatchArgs ba, int alpha, int beta, int acc) {
   extern __shared__ double lds[];
   const int b = cptr(ba.blockbox)[blockIdx.x];
   const auto &a = *cptr(ba.boxes + b);
   const int local = blockIdx.x - cptr(ba.blockstart)[b];
   const int nbx = (a.g.nx + FTX - 1) / FTX, nby = (a.g.ny + FTY - 1) / FTY;
-  force_body<R, VISC ? 1 : 0, 1, FNT>(a, nullptr, 0, 0, 0, local % nbx, (local / nbx) % nby,
+  force_body<R, VISC ? 1 : 0, 1, FNT>(a, nullptr, alpha, beta, acc, local % nbx, (local / nbx) % nby,
                                       local / (nbx * nby), lds);
 }
 
-// the attractive field of every box of one tail reach R (one species, so the
-// pair (0, 0)), added to C^mf/n after the hard-sphere gathers; 32 x 8 tiles
+// the attractive field of the directed pair (alpha, beta) for every box of
+// one tail reach R, added to C^mf/n_alpha after the hard-sphere gathers;
+// 32 x 8 tiles
 template <int R>
-__global__ __launch_bounds__(FNT) void kb_force_att(BatchArgs ba) {
+__global__ __launch_bounds__(FNT) void kb_force_att(BatchArgs ba, int alpha, int beta) {
   extern __shared__ double lds[];
   const int b = cptr(ba.blockbox)[blockIdx.x];
   const auto &a = *cptr(ba.boxes + b);
   const int local = blockIdx.x - cptr(ba.blockstart)[b];
   const int nbx = (a.g.nx + FTX - 1) / FTX, nby = (a.g.ny + FTY - 1) / FTY;
-  force_body<R, 3, 1, FNT>(a, nullptr, 0, 0, 1, local % nbx, (local / nbx) % nby, local / (nbx * nby),
-                           lds);
+  force_body<R, 3, 1, FNT>(a, nullptr, alpha, beta, 1, local % nbx, (local / nbx) % nby,
+                           local / (nbx * nby), lds);
 }
 
-template <typename T>
+template <typename T, int M>
 __global__ __launch_bounds__(BLOCK) void kb_collide(BatchArgs ba) {
   const int b = cptr(ba.blockbox)[blockIdx.x];
   const auto &a = *cptr(ba.boxes + b);
   const int i = (blockIdx.x - cptr(ba.blockstart)[b]) * BLOCK + threadIdx.x;
-  collide_body<T, 1>(a, (const T *)a.pop[ba.cur], (T *)a.pop[ba.cur ^ 1], i);
+  collide_body<T, M>(a, (const T *)a.pop[ba.cur], (T *)a.pop[ba.cur ^ 1], i);
 }
 
 template <typename T, int M>
@@ -2343,6 +2346,15 @@ void prepare_force_kernels(int maxR, bool visc, int max_entries) {
 #undef PREP
 }
 
+// a runtime species count as the template argument MM of CALL
+#define LBE_SWITCH_M(M_, CALL) \
+  switch (M_) {                \
+    case 1: { constexpr int MM = 1; CALL; } break; \
+    case 2: { constexpr int MM = 2; CALL; } break; \
+    case 3: { constexpr int MM = 3; CALL; } break; \
+    default: { constexpr int MM = 4; CALL; } break; \
+  }
+
 void launch_batch_moments(const BatchArgs &b, int nblocks, int prec, bool visc, hipStream_t s) {
   if (prec == LBE_FP64) {
     if (visc) hipLaunchKernelGGL((kb_moments<double, true>), dim3(nblocks), dim3(BLOCK), 0, s, b);
@@ -2353,23 +2365,23 @@ void launch_batch_moments(const BatchArgs &b, int nblocks, int prec, bool visc, 
   }
 }
 
-template <int ZC>
+template <int M, int ZC>
 static void batch_ball_zc(const BatchArgs &b, int nblocks, size_t bytes, hipStream_t s) {
   static size_t attr = 0;
   if (bytes > attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_ball<ZC>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_ball<M, ZC>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     attr = bytes;
   }
-  hipLaunchKernelGGL(kb_ball<ZC>, dim3(nblocks), dim3(BLOCK), bytes, s, b);
+  hipLaunchKernelGGL((kb_ball<M, ZC>), dim3(nblocks), dim3(BLOCK), bytes, s, b);
 }
 
-void launch_batch_ball(const BatchArgs &b, int nblocks, int zc, size_t lds_bytes, hipStream_t s) {
+void launch_batch_ball(const BatchArgs &b, int nblocks, int zc, size_t lds_bytes, int M, hipStream_t s) {
   switch (zc) {
-    case 8: batch_ball_zc<8>(b, nblocks, lds_bytes, s); break;
-    case 4: batch_ball_zc<4>(b, nblocks, lds_bytes, s); break;
-    case 2: batch_ball_zc<2>(b, nblocks, lds_bytes, s); break;
-    default: batch_ball_zc<1>(b, nblocks, lds_bytes, s); break;
+    case 8: LBE_SWITCH_M(M, (batch_ball_zc<MM, 8>(b, nblocks, lds_bytes, s))) break;
+    case 4: LBE_SWITCH_M(M, (batch_ball_zc<MM, 4>(b, nblocks, lds_bytes, s))) break;
+    case 2: LBE_SWITCH_M(M, (batch_ball_zc<MM, 2>(b, nblocks, lds_bytes, s))) break;
+    default: LBE_SWITCH_M(M, (batch_ball_zc<MM, 1>(b, nblocks, lds_bytes, s))) break;
   }
 }
 
@@ -2383,46 +2395,48 @@ int ball_blocks(const Geom &g, int zc) {
 }
 
 template <int R, bool VISC>
-static void batch_force_r(const BatchArgs &b, int nblocks, int entries, hipStream_t s) {
+static void batch_force_r(const BatchArgs &b, int nblocks, int entries, int alpha, int beta, int acc,
+                          hipStream_t s) {
   const size_t bytes = force_lds_bytes<R, VISC>(entries);
-  hipLaunchKernelGGL((kb_force<R, VISC>), dim3(nblocks), dim3(FNT), bytes, s, b);
+  hipLaunchKernelGGL((kb_force<R, VISC>), dim3(nblocks), dim3(FNT), bytes, s, b, alpha, beta, acc);
 }
 
-void launch_batch_force(const BatchArgs &b, int nblocks, int R, bool visc, int entries, hipStream_t s) {
-#define BF(RR)                                                         \
-  case RR:                                                             \
-    if (visc) batch_force_r<RR, true>(b, nblocks, entries, s);         \
-    else batch_force_r<RR, false>(b, nblocks, entries, s);             \
+void launch_batch_force(const BatchArgs &b, int nblocks, int R, bool visc, int entries, int alpha, int beta,
+                        int acc, hipStream_t s) {
+#define BF(RR)                                                                      \
+  case RR:                                                                          \
+    if (visc) batch_force_r<RR, true>(b, nblocks, entries, alpha, beta, acc, s);    \
+    else batch_force_r<RR, false>(b, nblocks, entries, alpha, beta, acc, s);        \
     break;
   switch (R) { BF(1) BF(2) BF(3) BF(4) BF(5) BF(6) BF(7) BF(8) default: break; }
 #undef BF
 }
 
 template <int R>
-static void batch_att_r(const BatchArgs &b, int nblocks, hipStream_t s) {
+static void batch_att_r(const BatchArgs &b, int nblocks, int alpha, int beta, hipStream_t s) {
   // one staged field and the table through scalar loads: at most 18 KB
   const size_t bytes = force_lds(3, R, FTY, 0, 1);
-  hipLaunchKernelGGL((kb_force_att<R>), dim3(nblocks), dim3(FNT), bytes, s, b);
+  hipLaunchKernelGGL((kb_force_att<R>), dim3(nblocks), dim3(FNT), bytes, s, b, alpha, beta);
 }
 
-void launch_batch_att(const BatchArgs &b, int nblocks, int R, hipStream_t s) {
+void launch_batch_att(const BatchArgs &b, int nblocks, int R, int alpha, int beta, hipStream_t s) {
   switch (R) {
-    case 1: batch_att_r<1>(b, nblocks, s); break;
-    case 2: batch_att_r<2>(b, nblocks, s); break;
-    case 3: batch_att_r<3>(b, nblocks, s); break;
-    case 4: batch_att_r<4>(b, nblocks, s); break;
-    case 5: batch_att_r<5>(b, nblocks, s); break;
-    case 6: batch_att_r<6>(b, nblocks, s); break;
-    case 7: batch_att_r<7>(b, nblocks, s); break;
-    default: batch_att_r<8>(b, nblocks, s); break;
+    case 1: batch_att_r<1>(b, nblocks, alpha, beta, s); break;
+    case 2: batch_att_r<2>(b, nblocks, alpha, beta, s); break;
+    case 3: batch_att_r<3>(b, nblocks, alpha, beta, s); break;
+    case 4: batch_att_r<4>(b, nblocks, alpha, beta, s); break;
+    case 5: batch_att_r<5>(b, nblocks, alpha, beta, s); break;
+    case 6: batch_att_r<6>(b, nblocks, alpha, beta, s); break;
+    case 7: batch_att_r<7>(b, nblocks, alpha, beta, s); break;
+    default: batch_att_r<8>(b, nblocks, alpha, beta, s); break;
   }
 }
 
-void launch_batch_collide(const BatchArgs &b, int nblocks, int prec, hipStream_t s) {
+void launch_batch_collide(const BatchArgs &b, int nblocks, int prec, int M, hipStream_t s) {
   if (prec == LBE_FP64)
-    hipLaunchKernelGGL(kb_collide<double>, dim3(nblocks), dim3(BLOCK), 0, s, b);
+    LBE_SWITCH_M(M, hipLaunchKernelGGL((kb_collide<double, MM>), dim3(nblocks), dim3(BLOCK), 0, s, b))
   else
-    hipLaunchKernelGGL(kb_collide<float>, dim3(nblocks), dim3(BLOCK), 0, s, b);
+    LBE_SWITCH_M(M, hipLaunchKernelGGL((kb_collide<float, MM>), dim3(nblocks), dim3(BLOCK), 0, s, b))
 }
 
 int diag_nblocks(const Geom &g) {
@@ -2449,13 +2463,6 @@ void launch_diag_errn(const Geom &g, int M, const uint32_t *bb, const Readout &r
 // ------------------------------------------------------------------------
 // adjoint launchers
 // ------------------------------------------------------------------------
-#define LBE_SWITCH_M(M_, CALL) \
-  switch (M_) {                \
-    case 1: { constexpr int MM = 1; CALL; } break; \
-    case 2: { constexpr int MM = 2; CALL; } break; \
-    case 3: { constexpr int MM = 3; CALL; } break; \
-    default: { constexpr int MM = 4; CALL; } break; \
-  }
 
 void launch_tape_moments(const StepArgs &a, int prec, const void *pop, double *PJ, hipStream_t s) {
   const dim3 gr = grid_for(a.g.N);

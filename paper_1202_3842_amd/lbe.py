@@ -353,7 +353,7 @@ def load_workload(b: "Box", w) -> None:
 
 
 class Batch:
-    """Independent one-species boxes stepped together (lbe_batch_*).  Member
+    """Independent boxes (same species count) stepped together (lbe_batch_*).  Member
     boxes are Box objects sharing the batch's workspace and stream."""
 
     SERIAL, BATCHED, GRAPH = 0, 1, 2

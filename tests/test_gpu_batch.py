@@ -59,3 +59,62 @@ def test_batch_member_setters_and_diagnostics(L):
     single.set_body_force(0, [1e-4, 0, 0])
     single.step(4)
     assert np.array_equal(batch.boxes[1].populations(0, 1), single.populations(0, 1))
+
+
+def _mixtures(seed=900):
+    """Uneven two-species boxes: cosine wells, diameters 2-6, a channel with
+    walls and an obstacle among them."""
+    out = []
+    spec = [(18, (3.0, 2.0)), (25, (4.0, 6.0)), (21, (2.0, 2.0))]
+    for i, (n, sg) in enumerate(spec):
+        shape = (n, n, n)
+        dens = [W.noisy_uniform(shape, W.packing_density(0.12, s), 1e-2, seed + 10 * i + a) for a, s in enumerate(sg)]
+        out.append(W.Workload(name=f"mix{i}", nx=n, ny=n, nz=n, sigma=list(sg), steps=6, density=dens,
+                              V=W.smooth_field(shape, 0.2 * W.KT, 3, seed + i),
+                              body=[[1e-4, 0.0, 0.0], [0.0, -1e-4, 0.0]]))
+    ch = W.channel(nx=40, ny=20, nz=12, x0=16, x1=22, gap=8, steps=6, name="mixchannel")
+    ch.V = W.smooth_field(ch.shape, 0.1 * W.KT, 3, seed + 9)
+    out.append(ch)
+    return out
+
+
+@pytest.mark.parametrize("flags", ["visc", "visc_drag_printed", "drag_single", "ideal"])
+def test_batched_mixtures_equal_single_boxes(L, flags):
+    """Two-species boxes in a batch: one force launch per directed pair and
+    shell range (the first pair of a species writes, later ones add), the
+    two-species ball and collision bodies; bitwise the boxes stepped alone,
+    from graph replays, batched launches and the serial schedule."""
+    f = {"visc": L.LBE_VISC, "visc_drag_printed": L.LBE_VISC | L.LBE_DRAG | L.LBE_PRINTED_INV,
+         "drag_single": L.LBE_DRAG | L.LBE_SINGLE, "ideal": L.LBE_IDEAL}[flags]
+    ws = _mixtures()
+    banner(f"batched mixtures {flags}")
+    batch = L.batch_from_workloads(ws, flags=f)
+    singles = [L.box_from_workload(w, flags=f) for w in ws]
+    batch.step(5, mode=2)
+    batch.step(2, mode=1)
+    batch.step(1, mode=0)
+    for b in singles:
+        b.step(8)
+    for i, (bb, bs) in enumerate(zip(batch.boxes, singles)):
+        for a in range(2):
+            for dist in ((0,) if f & L.LBE_SINGLE else (0, 1)):
+                assert np.array_equal(bb.populations(a, dist), bs.populations(a, dist)), (i, a, dist)
+    for b in singles:
+        b.close()
+    batch.close()
+
+
+def test_batched_mixture_against_oracle(L):
+    """One two-species box of the batch against the oracle, to 1e-11."""
+    import oracle
+    from tests.parity_util import compare_state, oracle_from_workload
+    if not oracle.LIB.exists():
+        oracle.build()
+    ws = _mixtures()
+    banner("batched mixture vs oracle")
+    batch = L.batch_from_workloads(ws, flags=L.LBE_VISC)
+    batch.step(6)
+    o = oracle_from_workload(ws[1], L.LBE_VISC)
+    o.step(6)
+    compare_state(o, batch.boxes[1], 2, 1e-11, "batched mixture")
+    batch.close()
