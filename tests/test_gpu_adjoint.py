@@ -448,3 +448,24 @@ def test_taped_forward_equals_checkpointed(flags):
     plain.close()
     assert np.abs(grads[0]).max() > 0
     assert np.array_equal(grads[0], grads[1])
+
+
+@pytest.mark.parametrize("flags,att", [(1 | 64, True), (2 | 4, False)])
+def test_adjoint_three_species(flags, att):
+    """Three species (sigma 2, 3 and 2.5) on the small channel: every
+    directed pair's transposes, the drag between three species and the
+    attractive tails of six pairs, against the reference gradient."""
+    w = small_channel()
+    w.sigma = [2.0, 3.0, 2.5]
+    w.density = w.density + [W.noisy_uniform(w.shape, float(w.density[0].mean()) * 0.5, 1e-2, 431)]
+    w.body = w.body + [[-5e-5, 1e-5, 0.0]]
+    if att:
+        e = np.array([[0.3, 0.2, 0.25], [0.2, 0.25, 0.15], [0.25, 0.15, 0.2]]) * W.KT
+        w.att_eps, w.att_rc = e.tolist(), 5.0
+    pw = pop_weights(w) * 1e-3
+    print(f"small channel three species flags {flags} att {att}", flush=True)
+    rV, rf, rg = reference(w, flags, 5, pw)
+    gV, gf, gg = gpu_gradient(w, flags, 5, 2, pw)
+    assert_close(gV, rV, 1e-10, "dL/dV")
+    assert_close(gf, rf, 1e-10, "dL/df0")
+    assert_close(gg, rg, 1e-10, "dL/dg0")
