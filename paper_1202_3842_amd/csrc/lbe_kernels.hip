@@ -479,7 +479,7 @@ typedef double dbl2 __attribute__((ext_vector_type(2)));
 __host__ __device__ constexpr bool table_in_smem(int mode, int ny = 1) { return mode != 0 || ny > 1; }
 // fields staged per plane by force_body
 __host__ __device__ constexpr int force_fields(int mode) {
-  return mode == 0 ? 2 : (mode == 3 ? 1 : (mode == 4 ? 3 : (mode == 5 ? 7 : 5)));
+  return mode == 0 ? 2 : (mode == 3 ? 1 : (mode == 4 ? 3 : (mode == 5 ? 8 : 5)));
 }
 // dynamic LDS of force_body: two planes of NF fields, then the ring table
 // when it is staged in LDS
@@ -494,10 +494,9 @@ __host__ __device__ constexpr size_t force_lds(int mode, int R, int ty, int entr
 // n_b(r + e) over the pair's thick shell (field n_b; the table holds
 // U'(|e|) e^), added to C^mf/n_a; MODE 4: the transpose of MODE 3 for the
 // adjoint, n_b^bar(r) -= sum_e U'(|e|) e^.phibar_a(r + e) (field phibar_a, the
-// same table); MODES 5 and 6: the transpose of the C^visc gather for the
-// adjoint (see k_adj_visc), MODE 5 over the fields phibar'_a (the adjoint of
-// C^visc/n_a), G_ab and u~_b, MODE 6 over n_b, G_ab and J~_b with the centre
-// phibar'_a.  NT threads in rows of FTX; NY = output rows per thread:
+// same table); MODE 5: the transpose of the C^visc gather for the adjoint
+// (see k_adj_visc), over the fields phibar'_a (the adjoint of C^visc/n_a),
+// G_ab, u~_b and n_b.  NT threads in rows of FTX; NY = output rows per thread:
 // the tile is FTX x (NT/FTX NY) and thread (tx, ty) owns rows ty,
 // ty + NT/FTX, ...; one ring-table read and one address then serve NY nodes.
 // Taller tiles shrink the staged window per node.
@@ -508,7 +507,7 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   constexpr bool ADJ = MODE == 2;
   constexpr bool ATT = MODE == 3;
   constexpr bool AADJ = MODE == 4;
-  constexpr bool VT1 = MODE == 5, VT2 = MODE == 6;
+  constexpr bool VTF = MODE == 5;
   constexpr int NF = force_fields(MODE);
   constexpr int RY = NT / FTX;                  // thread rows of the workgroup
   constexpr int TY = RY * NY;
@@ -533,10 +532,10 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   const int t = threadIdx.x, tx = t % FTX, ty = t / FTX;
   const int x0 = bx * FTX, y0 = by * TY;
   const int x = x0 + tx;
-  const double *__restrict__ fld[7];
+  const double *__restrict__ fld[8];
   fld[0] = a.nfield + (long long)beta * g.Np;
   fld[1] = a.Gfield + (long long)k * g.Np;
-  if (VT1) {
+  if (VTF) {
     fld[0] = ad->psibar + (long long)(3 * alpha) * g.Np;
     fld[1] = fld[0] + g.Np;
     fld[2] = fld[1] + g.Np;
@@ -544,8 +543,9 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
     fld[4] = ad->ut + (long long)(3 * beta) * g.Np;
     fld[5] = fld[4] + g.Np;
     fld[6] = fld[5] + g.Np;
+    fld[7] = a.nfield + (long long)beta * g.Np;
   }
-  if (VISC || VT2) {
+  if (VISC) {
     fld[2] = a.Jfield + (long long)(3 * beta) * g.Np;
     fld[3] = fld[2] + g.Np;
     fld[4] = fld[3] + g.Np;
@@ -623,9 +623,9 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   // accumulators [row][set]: m (C^mf, or sum e^ n_b(r+e) for the adjoint)
   // and v (C^visc, or the two adjoint sums)
   double mx[NY][NS], my[NY][NS], mz[NY][NS], vx[NY][NS], vy[NY][NS], vz[NY][NS];
-  double ox[NY][NS], oy[NY][NS];  // MODE 5 only
+  double ox[NY][NS], oy[NY][NS], wx[NY][NS], wy[NY][NS], wz[NY][NS], we[NY][NS];  // MODE 5
   // centre values of each row: G_ab, and u_b (MODES 1, 6) or n_b and
-  // phibar_a (MODE 2); phibar'_a (MODE 6)
+  // phibar_a (MODE 2); phibar'_a and u~_b (MODE 5)
   double G0[NY], n0[NY], u0x[NY], u0y[NY], u0z[NY], p0x[NY], p0y[NY], p0z[NY];
   for (int rho = 0; rho < rounds; ++rho) {
     const int z = zb + rho / (R + 1), ez = rho % (R + 1);
@@ -660,23 +660,22 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
         for (int c = 0; c < NS; ++c) {
           mx[jn][c] = my[jn][c] = mz[jn][c] = vx[jn][c] = vy[jn][c] = vz[jn][c] = 0.0;
           ox[jn][c] = oy[jn][c] = 0.0;
+          wx[jn][c] = wy[jn][c] = wz[jn][c] = we[jn][c] = 0.0;
         }
         const int bj = base + jn * ROW;
-        G0[jn] = ATT || AADJ ? 0.0 : (VT1 ? Bp[3 * WH + bj] : Bp[at(1, bj)]);
-        n0[jn] = AADJ || VT1 ? 0.0 : Bp[at(0, bj)];
+        G0[jn] = ATT || AADJ ? 0.0 : (VTF ? Bp[3 * WH + bj] : Bp[at(1, bj)]);
+        n0[jn] = AADJ ? 0.0 : (VTF ? Bp[7 * WH + bj] : Bp[at(0, bj)]);
         u0x[jn] = u0y[jn] = u0z[jn] = 0.0;
         p0x[jn] = p0y[jn] = p0z[jn] = 0.0;
-        if (VT2) {  // phibar'_a at the output node, from the padded field
-          const int y = y0 + ty + jn * RY;
-          if (x < g.nx && y < g.ny) {
-            const long long Pc = (x + g.R) + (long long)g.PX * ((y + g.R) + (long long)g.PY * (z + g.R));
-            const double *pb = ad->psibar + (long long)(3 * alpha) * g.Np + Pc;
-            p0x[jn] = pb[0];
-            p0y[jn] = pb[g.Np];
-            p0z[jn] = pb[2 * g.Np];
-          }
+        if (VTF) {  // phibar'_a and u~_b at the output node, staged
+          p0x[jn] = Bp[bj];
+          p0y[jn] = Bp[WH + bj];
+          p0z[jn] = Bp[2 * WH + bj];
+          u0x[jn] = Bp[4 * WH + bj];
+          u0y[jn] = Bp[5 * WH + bj];
+          u0z[jn] = Bp[6 * WH + bj];
         }
-        if ((VISC || VT2) && n0[jn] != 0.0) {
+        if (VISC && n0[jn] != 0.0) {
           u0x[jn] = Bp[at(2, bj)] / n0[jn];
           u0y[jn] = Bp[at(3, bj)] / n0[jn];
           u0z[jn] = Bp[at(4, bj)] / n0[jn];
@@ -707,14 +706,15 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
 #pragma unroll
       for (int jn = 0; jn < NY; ++jn) {
         const int qa = base + jn * ROW + o, qb = base + jn * ROW - o;
-        if constexpr (VT1) {
-          // e^.phibar' and e^.u~ at r+e and r-e (the -e terms carry the
-          // same signs: (-e^)(-e^.v) = e^(e^.v)); G at both points
+        if constexpr (VTF) {
+          // e^.phibar', e^.u~, G and n at r+e and r-e (the -e terms carry the
+          // same signs: (-e^)(-e^.v) = e^(e^.v)); e^.J~ = n (e^.u~) there
           const double pp = e0 * Bp[qa] + e1 * Bp[WH + qa] + e2 * Bp[2 * WH + qa];
           const double pm = e0 * Bm[qb] + e1 * Bm[WH + qb] + e2 * Bm[2 * WH + qb];
           const double Gp = Bp[3 * WH + qa], Gm = Bm[3 * WH + qb];
           const double up = e0 * Bp[4 * WH + qa] + e1 * Bp[5 * WH + qa] + e2 * Bp[6 * WH + qa];
           const double um = e0 * Bm[4 * WH + qb] + e1 * Bm[5 * WH + qb] + e2 * Bm[6 * WH + qb];
+          const double npl = Bp[7 * WH + qa], nmi = Bm[7 * WH + qb];
           const double s1 = pp + pm, s2 = pp * Gp + pm * Gm;
           mx[jn][c] += e0 * s1;
           my[jn][c] += e1 * s1;
@@ -725,6 +725,13 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
           const double bp = pp * up, bm = pm * um;
           ox[jn][c] += bp + bm;
           oy[jn][c] += bp * Gp + bm * Gm;
+          const double ep = e0 * p0x[jn] + e1 * p0y[jn] + e2 * p0z[jn];
+          const double eu = e0 * u0x[jn] + e1 * u0y[jn] + e2 * u0z[jn];
+          const double t1 = ep * (npl * (G0[jn] + Gp) + nmi * (G0[jn] + Gm));
+          wx[jn][c] += e0 * t1;
+          wy[jn][c] += e1 * t1;
+          wz[jn][c] += e2 * t1;
+          we[jn][c] += ep * (npl * (up - eu) + nmi * (um - eu));
           continue;
         }
         dbl2 ap, am, vp = {0.0, 0.0}, vm = {0.0, 0.0};
@@ -777,18 +784,6 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
           mz[jn][c] += e2 * dn;
           vx[jn][c] += tp - tm;
           vy[jn][c] += tp * ap.y - tm * am.y;
-        } else if (VT2) {
-          // m: sum_S e^ (e^.phibar'(r)) n_b(r+e) (G(r) + G(r+e));
-          // v: sum_S (e^.phibar'(r)) (e^.J~(r+e) - (e^.u~(r)) n_b(r+e))
-          const double gp = G0[jn] + ap.y, gm = G0[jn] + am.y;
-          const double ep = e0 * p0x[jn] + e1 * p0y[jn] + e2 * p0z[jn];
-          const double eu = e0 * u0x[jn] + e1 * u0y[jn] + e2 * u0z[jn];
-          const double s1 = ep * (npl * gp + nmi * gm);
-          mx[jn][c] += e0 * s1;
-          my[jn][c] += e1 * s1;
-          mz[jn][c] += e2 * s1;
-          const double jp = e0 * vp.x + e1 * vp.y + e2 * vpz, jm = e0 * vm.x + e1 * vm.y + e2 * vmz;
-          vx[jn][c] += ep * (jp + jm - eu * (npl + nmi));
         } else {
           const double gp = G0[jn] + ap.y, gm = G0[jn] + am.y;
           const double d = gp * npl - gm * nmi;
@@ -835,35 +830,29 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
         } else if (AADJ) {
           double *pn = ad->nbar + beta * N + i;
           *pn = (accumulate & 1) ? *pn - Mx : -Mx;
-        } else if (VT1 || VT2) {
+        } else if (VTF) {
           // with c = pair_cvisc (C^visc/n_a = c sum_S e^ [e^.J~(r+e) -
-          // (e^.u~(r)) n_b(r+e)] (G(r) + G(r+e))):
-          // MODE 5: J~_b^bar(r) += c (sum e^(e^.pb(r+e)) G(r+e) + G(r) sum e^(e^.pb(r+e)))
-          //         n_b^bar(r)  -= c (sum (e^.pb)(e^.u~)(r+e) G(r+e) + G(r) sum (e^.pb)(e^.u~)(r+e))
-          //         G^bar(r)    += c (J~_b(r).sum e^(e^.pb(r+e)) - n_b(r) sum (e^.pb)(e^.u~)(r+e))
-          // MODE 6: u~^bar(r) = -c sum e^(e^.pb(r)) n_b(r+e)(G(r) + G(r+e)), into
-          //         J~_b^bar += u~^bar/n_b, n_b^bar -= u~^bar.u~/n_b;
-          //         G^bar(r) += c sum (e^.pb(r)) (e^.J~(r+e) - (e^.u~(r)) n_b(r+e))
-          double jb[3], vn, vg;
-          if (VT1) {
-            const double Ox = ox[jn][0] + ox[jn][1], Oy = oy[jn][0] + oy[jn][1];
-            const long long Pc = (x + g.R) + (long long)g.PX * ((y + g.R) + (long long)g.PY * (z + g.R));
-            const double *Jc = a.Jfield + (long long)(3 * beta) * g.Np + Pc;
-            const double nc = a.nfield[(long long)beta * g.Np + Pc];
-            jb[0] = cvs * (Vx + G0[jn] * Mx);
-            jb[1] = cvs * (Vy + G0[jn] * My);
-            jb[2] = cvs * (Vz + G0[jn] * Mz);
-            vn = -cvs * (Oy + G0[jn] * Ox);
-            vg = cvs * (Jc[0] * Mx + Jc[g.Np] * My + Jc[2 * g.Np] * Mz - nc * Ox);
-          } else {
-            const double ub0 = -cvs * Mx, ub1 = -cvs * My, ub2 = -cvs * Mz;
-            const double inv = n0[jn] != 0.0 ? 1.0 / n0[jn] : 0.0;
-            jb[0] = ub0 * inv;
-            jb[1] = ub1 * inv;
-            jb[2] = ub2 * inv;
-            vn = -(ub0 * u0x[jn] + ub1 * u0y[jn] + ub2 * u0z[jn]) * inv;
-            vg = cvs * Vx;
-          }
+          // (e^.u~(r)) n_b(r+e)] (G(r) + G(r+e))) and pb = phibar'_a:
+          //   J~_b^bar(r) += c (sum e^(e^.pb(r+e)) G(r+e) + G(r) sum e^(e^.pb(r+e)))
+          //   n_b^bar(r)  -= c (sum (e^.pb)(e^.u~)(r+e) G(r+e) + G(r) sum (e^.pb)(e^.u~)(r+e))
+          //   G^bar(r)    += c (J~_b(r).sum e^(e^.pb(r+e)) - n_b(r) sum (e^.pb)(e^.u~)(r+e))
+          // from the neighbours' terms, and from the node's own u~_b(r) and G(r):
+          //   u~^bar(r) = -c sum e^(e^.pb(r)) n_b(r+e)(G(r) + G(r+e)), into
+          //     J~_b^bar += u~^bar/n_b, n_b^bar -= u~^bar.u~/n_b,
+          //   G^bar(r) += c sum (e^.pb(r)) (e^.J~(r+e) - (e^.u~(r)) n_b(r+e))
+          const double Ox = ox[jn][0] + ox[jn][1], Oy = oy[jn][0] + oy[jn][1];
+          const double Wx = wx[jn][0] + wx[jn][1], Wy = wy[jn][0] + wy[jn][1], Wz = wz[jn][0] + wz[jn][1];
+          const double We = we[jn][0] + we[jn][1];
+          const long long Pc = (x + g.R) + (long long)g.PX * ((y + g.R) + (long long)g.PY * (z + g.R));
+          const double *Jc = a.Jfield + (long long)(3 * beta) * g.Np + Pc;
+          const double inv = n0[jn] != 0.0 ? 1.0 / n0[jn] : 0.0;
+          const double ub0 = -cvs * Wx, ub1 = -cvs * Wy, ub2 = -cvs * Wz;
+          double jb[3];
+          jb[0] = cvs * (Vx + G0[jn] * Mx) + ub0 * inv;
+          jb[1] = cvs * (Vy + G0[jn] * My) + ub1 * inv;
+          jb[2] = cvs * (Vz + G0[jn] * Mz) + ub2 * inv;
+          const double vn = -cvs * (Oy + G0[jn] * Ox) - (ub0 * u0x[jn] + ub1 * u0y[jn] + ub2 * u0z[jn]) * inv;
+          const double vg = cvs * (Jc[0] * Mx + Jc[g.Np] * My + Jc[2 * g.Np] * Mz - n0[jn] * Ox + We);
           double *pn = ad->nbar + beta * N + i, *pg = ad->Gbar + k * N + i, *pj = ad->Jnl + 3 * beta * N + i;
           *pn = (accumulate & 1) ? *pn + vn : vn;
           *pg = (accumulate & 2) ? *pg + vg : vg;
@@ -1842,7 +1831,7 @@ __global__ __launch_bounds__(FNT) void k_adj_att(StepArgs a, AdjArgs d, int alph
 }
 
 // adjoint of the C^visc gather of the directed pair (alpha, beta), force_body
-// MODE 5 or 6 (see there): writes or accumulates into nbar (acc bit 0),
+// MODE 5 (see there): writes or accumulates into nbar (acc bit 0),
 // Gbar (bit 1) and Jnl (bit 2); 32 x (NT/32) tiles, the ring table through
 // scalar loads
 template <int R, int MODE, int NT>
@@ -2493,12 +2482,13 @@ void launch_adj_stream(const StepArgs &a, const AdjArgs &d, bool terminal, hipSt
   }
 }
 
-// tiles of the adjoint gathers of C^visc: MODE 5 (seven staged fields)
-// takes 512-thread 32 x 16 tiles where its two planes fit in LDS (fewer
-// window slots per thread and less halo per output) and the box still gives
-// two such tiles per CU, else 32 x 8.  At 128^3: MODE 5 1.58 -> 1.03 ms;
-// MODE 6 (five fields) 0.86 ms with 32 x 8 and 0.89 ms with 32 x 16, so it
-// keeps 32 x 8.
+// tiles of the adjoint gather of C^visc (MODE 5, eight staged fields):
+// 512-thread 32 x 16 tiles where its two planes fit in LDS (reach up to 6;
+// fewer window slots per thread and less halo per output) and the box still
+// gives two such tiles per CU, else 32 x 8 (its planes fit for every reach).
+// The sums do not depend on the tile.  An earlier split into two gathers
+// (seven and five staged fields) took 1.03 + 0.86 ms at 128^3; the fused one
+// saves 2% of the backward.
 static bool wide_tiles(const StepArgs &a, int mode, int R) {
   return mode == 5 && force_lds(mode, R, 16, 0, 1) <= 160 * 1024 &&
          force_blocks(a.g, a.zchunk, 16) >= 2 * NCU;
@@ -2646,7 +2636,7 @@ void launch_adj_nonlocal(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
         default: adj_force_launch<8>(a, d, al, be, acc, s); break;
       }
     }
-  // C^visc: its two transposes per directed pair, into nbar, Gbar and Jnl
+  // C^visc: its transpose per directed pair, into nbar, Gbar and Jnl
   if ((a.flags & LBE_VISC) && d.Jnl) {
     bool wj[MAXM] = {false, false, false, false};
     for (int al = 0; al < M; ++al)
@@ -2656,7 +2646,6 @@ void launch_adj_nonlocal(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
         if (R == 0) continue;
         adj_visc_r<5>(R, a, d, al, be, (wn[be] ? 1 : 0) | (wg[k] ? 2 : 0) | (wj[be] ? 4 : 0), s);
         wn[be] = wg[k] = wj[be] = true;
-        adj_visc_r<6>(R, a, d, al, be, 7, s);
       }
     for (int b = 0; b < M; ++b)
       if (!wj[b]) launch_fill(d.Jnl + 3 * b * N, 3 * N, 0.0, s);
