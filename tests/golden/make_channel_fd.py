@@ -5,7 +5,9 @@ Writes ``channel96_fd_grad.json``: dL/dV at 32 seeded fluid nodes of the
 from two runs of the oracle with V(r_i) moved by +-h.  With ``--flags 3
 --steps 40 --out channel96_visc_fd_grad.json`` the same for the scheme with
 C^visc and the printed inversions over 40 steps (the channel collapses with
-C^visc well before 400 steps).  The objective is the
+C^visc well before 400 steps); ``--flags 67 --steps 40 --att-eps 0.25
+--att-rc 7 --out channel96_all_fd_grad.json`` the scheme with every force
+(C^visc, the drag and the attractive tails, printed inversions).  The objective is the
 one described in ``paper_1202_3842_amd.workloads.c5_objective``.  Only the
 oracle computes anything here; the GPU adjoint is compared with these values
 by tests/test_gpu_adjoint.py.
@@ -34,7 +36,8 @@ HERE = Path(__file__).resolve().parent
 
 
 def objective(w, V, flags, steps):
-    o = oracle.Oracle(w.nx, w.ny, w.nz, w.sigma, w.periodic, w.tau, w.kT, flags=flags)
+    o = oracle.Oracle(w.nx, w.ny, w.nz, w.sigma, w.periodic, w.tau, w.kT, flags=flags,
+                      att_eps=w.att_eps, att_rc=w.att_rc)
     o.set_solid(w.solid)
     o.set_potential(V)
     for a in range(w.nspecies):
@@ -59,11 +62,16 @@ def main():
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--steps", type=int, default=0, help="0: the workload's 400")
     ap.add_argument("--out", default="channel96_fd_grad.json")
+    ap.add_argument("--att-eps", type=float, default=0.0, help="attractive depth for every pair, in kT")
+    ap.add_argument("--att-rc", type=float, default=0.0)
     args = ap.parse_args()
     oracle.set_threads(args.threads)
     w = W.c5_channel()
     if args.steps:
         w.steps = args.steps
+    if args.att_eps > 0:
+        w.att_eps = [[args.att_eps * w.kT] * w.nspecies] * w.nspecies
+        w.att_rc = args.att_rc
     flags = args.flags
     OUT = HERE / args.out
     nodes = W.sample_fluid_nodes(w, args.count)
@@ -82,7 +90,7 @@ def main():
         print(f"{k + 1}/{len(nodes)} node {i}: dL/dV = {g:.10e} {time.time() - t0:.0f}s", flush=True)
         OUT.write_text(json.dumps({
             "workload": w.name, "steps": w.steps, "flags": flags, "h": H, "L0": L0,
-            "rows": rows}, indent=1))
+            "att_eps_kT": args.att_eps, "att_rc": args.att_rc, "rows": rows}, indent=1))
     print("wrote", OUT)
 
 

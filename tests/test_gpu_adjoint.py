@@ -16,6 +16,7 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = Path(__file__).resolve().parent / "golden" / "channel96_fd_grad.json"
 GOLDEN_VISC = Path(__file__).resolve().parent / "golden" / "channel96_visc_fd_grad.json"
+GOLDEN_ALL = Path(__file__).resolve().parent / "golden" / "channel96_all_fd_grad.json"
 
 
 def reference(w, flags, T, pw):
@@ -228,18 +229,23 @@ def test_autograd_function_matches_adjoint():
     assert_close(V.grad.cpu().numpy(), rV, 1e-10, "autograd dL/dV")
 
 
-@pytest.mark.parametrize("golden,steps,segment", [(GOLDEN, 400, 20), (GOLDEN_VISC, 40, 10)],
-                         ids=["cmf_400", "visc_printed_40"])
+@pytest.mark.parametrize("golden,steps,segment", [(GOLDEN, 400, 20), (GOLDEN_VISC, 40, 10), (GOLDEN_ALL, 40, 40)],
+                         ids=["cmf_400", "visc_printed_40", "all_forces_40"])
 def test_channel96_gradient_against_oracle_fd(golden, steps, segment):
     """dL/dV on the 96x32x32 channel against central differences of the
-    oracle: C^mf with the derived inversions over 400 steps, and C^visc with
-    the printed inversions over 40 steps."""
+    oracle: C^mf with the derived inversions over 400 steps; C^visc with
+    the printed inversions over 40 steps; and every force (C^visc, the drag
+    and the attractive tails, printed inversions) over 40 steps in one
+    segment."""
     from paper_1202_3842_amd import lbe
     if not golden.exists():
         pytest.skip(f"finite-difference golden file {golden.name} not generated")
     gold = json.loads(golden.read_text())
     w = W.c5_channel()
     w.steps = steps
+    if gold.get("att_eps_kT", 0.0) > 0:
+        w.att_eps = [[gold["att_eps_kT"] * w.kT] * w.nspecies] * w.nspecies
+        w.att_rc = gold["att_rc"]
     assert gold["workload"] == w.name and gold["steps"] == w.steps
     n_t, fluid, plane = W.c5_objective(w)
     box = lbe.box_from_workload(w, flags=gold["flags"])
