@@ -517,7 +517,9 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   // two accumulator sets per row, alternating over the pairs of a ring (and
   // summed at the end): shorter dependency chains, and the same summation
   // order for every tile shape, so results do not depend on the tiling
-  constexpr int NS = 2;
+  // (four sets for C^mf + C^visc: 0.789 -> 0.762 ms at 128^3, sigma = 6; three
+  // or six were no faster than two)
+  constexpr int NS = MODE == 1 ? 4 : 2;
   // LDS layout of a staged plane.  PAIRED: n and G interleaved, then the x and
   // y components of the vector field interleaved, then its z component, so a
   // point's n and G come in with one 16-byte read; otherwise one array per
@@ -805,19 +807,26 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
     // a pair's terms are combined before they are accumulated, so a uniform
     // state still sums to exactly zero
     int j = jbeg;
-    for (; j + 1 < jend; j += 2) {
-      pair(j, 0);
-      pair(j + 1, 1);
+    for (; j + NS - 1 < jend; j += NS) {
+#pragma unroll
+      for (int c = 0; c < NS; ++c) pair(j + c, c);
     }
-    if (j < jend) pair(j, 0);
+    for (int c = 0; j < jend; ++j, ++c) pair(j, c);
     if (ez == R) {
       const long long N = g.N;
 #pragma unroll
       for (int jn = 0; jn < NY; ++jn) {
         const int y = y0 + ty + jn * RY;
         if (!(x < g.nx && y < g.ny)) continue;
-        const double Mx = mx[jn][0] + mx[jn][1], My = my[jn][0] + my[jn][1], Mz = mz[jn][0] + mz[jn][1];
-        const double Vx = vx[jn][0] + vx[jn][1], Vy = vy[jn][0] + vy[jn][1], Vz = vz[jn][0] + vz[jn][1];
+        // the sets summed in order
+        auto sets = [&](const double (&v)[NY][NS]) {
+          double r = v[jn][0];
+#pragma unroll
+          for (int c = 1; c < NS; ++c) r += v[jn][c];
+          return r;
+        };
+        const double Mx = sets(mx), My = sets(my), Mz = sets(mz);
+        const double Vx = sets(vx), Vy = sets(vy), Vz = sets(vz);
         const long long i = x + (long long)g.nx * (y + (long long)g.ny * z);
         if (ADJ) {
           // n_b^bar(r) += -c (sum (e^.phibar) G(r+e) + G(r) sum e^.phibar)
@@ -840,9 +849,9 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
           //   u~^bar(r) = -c sum e^(e^.pb(r)) n_b(r+e)(G(r) + G(r+e)), into
           //     J~_b^bar += u~^bar/n_b, n_b^bar -= u~^bar.u~/n_b,
           //   G^bar(r) += c sum (e^.pb(r)) (e^.J~(r+e) - (e^.u~(r)) n_b(r+e))
-          const double Ox = ox[jn][0] + ox[jn][1], Oy = oy[jn][0] + oy[jn][1];
-          const double Wx = wx[jn][0] + wx[jn][1], Wy = wy[jn][0] + wy[jn][1], Wz = wz[jn][0] + wz[jn][1];
-          const double We = we[jn][0] + we[jn][1];
+          const double Ox = sets(ox), Oy = sets(oy);
+          const double Wx = sets(wx), Wy = sets(wy), Wz = sets(wz);
+          const double We = sets(we);
           const long long Pc = (x + g.R) + (long long)g.PX * ((y + g.R) + (long long)g.PY * (z + g.R));
           const double *Jc = a.Jfield + (long long)(3 * beta) * g.Np + Pc;
           const double inv = n0[jn] != 0.0 ? 1.0 / n0[jn] : 0.0;
