@@ -517,9 +517,12 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   // two accumulator sets per row, alternating over the pairs of a ring (and
   // summed at the end): shorter dependency chains, and the same summation
   // order for every tile shape, so results do not depend on the tiling
-  // (four sets for C^mf + C^visc: 0.789 -> 0.762 ms at 128^3, sigma = 6; three
-  // or six were no faster than two)
-  constexpr int NS = MODE == 1 ? 4 : 2;
+  // (four sets for C^mf + C^visc: 0.789 -> 0.762 ms at 128^3, sigma = 6, where
+  // three or six were no faster than two; four also for the attraction and
+  // the C^mf and attraction transposes, a few per cent each; two for C^mf
+  // alone, whose two-row tiles slowed from 0.245 to 0.269 ms with four, and
+  // for the C^visc transpose, already at 256 VGPRs)
+  constexpr int NS = (MODE == 0 || MODE == 5) ? 2 : 4;
   // LDS layout of a staged plane.  PAIRED: n and G interleaved, then the x and
   // y components of the vector field interleaved, then its z component, so a
   // point's n and G come in with one 16-byte read; otherwise one array per
