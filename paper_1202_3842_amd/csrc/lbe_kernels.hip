@@ -810,6 +810,13 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
     // a pair's terms are combined before they are accumulated, so a uniform
     // state still sums to exactly zero
     int j = jbeg;
+    // C^mf + C^visc: eight pairs per iteration, the same sets in the same
+    // order (bitwise the same sums; 0.766 -> 0.761 ms at 128^3)
+    if (MODE == 1)
+      for (; j + 2 * NS - 1 < jend; j += 2 * NS) {
+#pragma unroll
+        for (int c = 0; c < 2 * NS; ++c) pair(j + c, c % NS);
+      }
     for (; j + NS - 1 < jend; j += NS) {
 #pragma unroll
       for (int c = 0; c < NS; ++c) pair(j + c, c);
