@@ -514,10 +514,10 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
   constexpr int W = FTX + 2 * R, H = TY + 2 * R, WH = W * H;
   constexpr int SLOTS = (WH + NT - 1) / NT;     // window elements per thread and field
   constexpr int ROW = RY * W;                   // LDS distance between a thread's rows
-  // two accumulator sets per row, alternating over the pairs of a ring (and
-  // summed at the end): shorter dependency chains, and the same summation
-  // order for every tile shape, so results do not depend on the tiling
-  // (four sets for C^mf + C^visc: 0.789 -> 0.762 ms at 128^3, sigma = 6, where
+  // NS accumulator sets per row, taking the pairs of a ring in turn (and
+  // summed in order at the end): shorter dependency chains, and the same
+  // summation order for every tile shape, so results do not depend on the
+  // tiling (four sets for C^mf + C^visc: 0.789 -> 0.762 ms at 128^3, sigma = 6, where
   // three or six were no faster than two; four also for the attraction and
   // the C^mf and attraction transposes, a few per cent each; two for C^mf
   // alone, whose two-row tiles slowed from 0.245 to 0.269 ms with four, and
