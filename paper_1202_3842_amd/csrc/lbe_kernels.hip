@@ -811,7 +811,8 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
     // state still sums to exactly zero
     int j = jbeg;
     // C^mf + C^visc: eight pairs per iteration, the same sets in the same
-    // order (bitwise the same sums; 0.766 -> 0.761 ms at 128^3)
+    // order (bitwise the same sums; 0.766 -> 0.761 ms at 128^3).  For the
+    // other gathers it made no consistent difference.
     if (MODE == 1)
       for (; j + 2 * NS - 1 < jend; j += 2 * NS) {
 #pragma unroll
