@@ -29,7 +29,10 @@ LBEO_IDEAL = 1 << 3
 LBEO_EULER = 1 << 4
 LBEO_SINGLE = 1 << 5
 LBEO_DRAG = 1 << 6
+LBEO_PI_CARRIED = 1 << 7
+LBEO_BALL_FLUID = 1 << 8
 LBEO_QP_WITH_FEXT = 1
+LBEO_QP_SYMMETRIC = 2
 
 Q = 19
 
@@ -100,6 +103,7 @@ def lib() -> C.CDLL:
         L.lbeo_stream.argtypes = [P, dp, dp]
         L.lbeo_quasipressure.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.c_uint, dp]
         L.lbeo_init_quasipressure.argtypes = [P, C.POINTER(C.c_int), C.c_uint]
+        L.lbeo_set_quasipressure_route.argtypes = [P, C.POINTER(C.c_int), C.c_uint]
         L.lbeo_get_divergence.argtypes = [P, dp]
         L.lbeo_shell.argtypes = [C.c_double, C.c_int, C.POINTER(C.c_int), dp]
         L.lbeo_ball.argtypes = [C.c_double, C.c_int, C.POINTER(C.c_int)]
@@ -315,6 +319,12 @@ class Oracle:
     def init_quasipressure(self, origin=(0, 0, 0), mode=0):
         o = (C.c_int * 3)(*[int(v) for v in origin])
         _check(lib().lbeo_init_quasipressure(self.h, o, mode))
+
+    def set_quasipressure_route(self, origin=(0, 0, 0), mode=LBEO_QP_SYMMETRIC):
+        """Origin (x, y, z) and integrand of the per-step quasi-pressure
+        (the default reading; see LBEO_PI_CARRIED)."""
+        o = (C.c_int * 3)(*[int(v) for v in origin])
+        _check(lib().lbeo_set_quasipressure_route(self.h, o, mode))
 
     def divergence(self):
         """D = div_h u / (v_T / dx) of the barycentric velocity."""

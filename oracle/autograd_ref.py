@@ -17,8 +17,14 @@ post-streaming populations f~, g~:
     e^ (G_ab(r) + G_ab(r+e))/2 n_b(r+e)  (Appendix, lattice shell);
   * F = -grad_h V + body force, grad_h V = (1/v_T^2) sum_p w_p c_p V(r+c_p)
     with wrapped or clamped neighbours;
-  * inversion J = J~ + Y/2 (or X/2 printed), u^a = J/n,
-    Pi = Pi~ + (beta/2) C.u^a (or minus, printed), u = sum J / sum n;
+  * inversion J = J~ + Y/2 (or X/2 printed), u^a = J/n, u = sum J / sum n;
+  * Pi, by default the quasi-pressure of eq. quasipressure, n - beta times
+    the trapezoidal path integral of C^mf from the origin, the mean over the
+    six axis orders of the paths that run along x, y and z in turn (or the
+    order x, y, z alone); the zeroth moment of g~ is
+    set to Pi - (beta/2) C.u^a (plus, printed; Pi itself, Euler) before the
+    update.  With PI_CARRIED, Pi = Pi~ + (beta/2) C.u^a (minus, printed)
+    from the carried g~;
   * Hermite equilibria and sources of eqs. kernel-f-1 .. kernel-g-1 with
     the kappa of the C^mf part of S_g;
   * trapezoidal update f~* = f~ + a (f_eq - f~) + b S_f (Sec. 4.1) and the
@@ -58,6 +64,7 @@ KAPPA4 = 1 << 2
 EULER = 1 << 4
 SINGLE = 1 << 5
 DRAG = 1 << 6
+PI_CARRIED = 1 << 7
 
 
 def lattice_shell(s: float):
@@ -137,7 +144,7 @@ class Stepper:
     """One configuration: geometry, species diameters, tau, flags, body forces."""
 
     def __init__(self, geom: Geometry, sigma, tau=1.0, kT=1.0 / 3.0, flags=0, body=None,
-                 att_eps=None, att_rc=0.0):
+                 att_eps=None, att_rc=0.0, qp_origin=None, qp_symmetric=True):
         self.g = geom
         self.M = len(sigma)
         self.sigma = [float(s) for s in sigma]
@@ -156,6 +163,11 @@ class Stepper:
         self.kappa = 4.0 if flags & KAPPA4 else 2.0
         self.drag = bool(flags & DRAG) and self.M > 1
         self.visc = bool(flags & VISC)
+        # Pi from the path integral every step (default) or carried by g
+        self.qp = not (flags & PI_CARRIED) and not self.single
+        self.qp_origin = tuple(qp_origin) if qp_origin is not None else (
+            geom.nx // 2, geom.ny // 2, geom.nz // 2)
+        self.qp_symmetric = qp_symmetric
         # drag coefficients: the collision integral of C^visc over the unit
         # sphere, 2 sigma_ab^2 sqrt(kT/pi) (4 pi/3)
         self.gamma = [[(0.5 * (sa + sb)) ** 2 * 2.0 * math.sqrt(kT / math.pi) * (4.0 * math.pi / 3.0)
@@ -304,7 +316,9 @@ class Stepper:
         nsafe = torch.where(pos, n, torch.ones_like(n))
         ua = J / nsafe[:, None, :] * pos[:, None, :]
         Cu = (Cmf * ua).sum(1)
-        if self.euler or self.single:
+        if self.qp:
+            Pi = self.quasipressure(n, Cmf)
+        elif self.euler or self.single:
             Pi = Pit
         else:
             Pi = Pit - 0.5 * self.beta * Cu if self.printed else Pit + 0.5 * self.beta * Cu
@@ -312,6 +326,39 @@ class Stepper:
         tpos = ntot > 0
         u = J.sum(0) / torch.where(tpos, ntot, torch.ones_like(ntot)) * tpos
         return J, ua, Pi, u, X, Y
+
+    def quasipressure(self, n, Cmf):
+        """Pi = n - beta Phi (Sec. 2, eq. quasipressure), Phi the trapezoidal
+        line integral of C^mf from the origin along the axes in the order
+        (x, y, z), or (symmetric mode) the mean over the six axis orders; the
+        integrand and Pi vanish on solid nodes.  Returns (M, N)."""
+        g = self.g
+        o = self.qp_origin
+        v = (Cmf * self.fluid).reshape(self.M, 3, g.nz, g.ny, g.nx)
+
+        def dim(k):                 # tensor dimension of axis k in (M, z, y, x)
+            return 3 - k
+
+        def leg(vk, k):
+            # S(e) = sum_{j<e} (v(j) + v(j+1))/2 along axis k, minus S(origin)
+            d = dim(k)
+            t = 0.5 * (vk.narrow(d, 0, vk.shape[d] - 1) + vk.narrow(d, 1, vk.shape[d] - 1))
+            S = torch.cat([torch.zeros_like(vk.narrow(d, 0, 1)), torch.cumsum(t, d)], d)
+            return S - S.narrow(d, o[k], 1)
+
+        def at(t, k):               # fix axis k at the origin's coordinate
+            return t.narrow(dim(k), o[k], 1)
+
+        def order_phi(p0, p1, p2):
+            A0 = leg(at(at(v[:, p0], p1), p2), p0)
+            A1 = leg(at(v[:, p1], p2), p1)
+            A2 = leg(v[:, p2], p2)
+            return (A0 + A1) + A2
+
+        orders = ([(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+                  if self.qp_symmetric else [(0, 1, 2)])
+        phi = sum(order_phi(*od) for od in orders) / len(orders)
+        return (n - self.beta * phi.reshape(self.M, -1)) * self.fluid
 
     def fields(self, f, V):
         n = f.sum(1) * self.fluid
@@ -339,6 +386,13 @@ class Stepper:
         fs = (f + self.a * (feq - f) + self.b * sf) * self.fluid
         if self.single:                     # no g is evolved
             return self.stream(fs), torch.zeros_like(g)
+        if self.qp:
+            # the zeroth moment of g~ becomes the Pi~ that the inversion
+            # maps to the quasi-pressure Pi
+            Cu = (Cmf * ua).sum(1)
+            target = Pi if self.euler else (Pi + 0.5 * self.beta * Cu if self.printed
+                                            else Pi - 0.5 * self.beta * Cu)
+            g = g + w * (target - g.sum(1))[:, None, :]
         gs = (g + self.a * (geq - g) + self.b * sg) * self.fluid
         return self.stream(fs), self.stream(gs)
 

@@ -321,6 +321,12 @@ struct lbeo_ctx {
   hermite_t herm;
   ball_t ball[MAXM];
   int unstable;
+  /* per-step quasi-pressure (the default reading) */
+  int qp_origin[3];
+  unsigned qp_mode;
+  double *pi;                  /* [M][N] Pi of eq. quasipressure          */
+  double *qpx, *qpy;           /* running leg sums, max(n) and max(n)^2   */
+  double *qpphi, *qpsum;       /* one axis order's Phi and the sum, N     */
 };
 
 static inline long IDX(const lbeo_ctx *c, int x, int y, int z) {
@@ -369,6 +375,11 @@ static void free_ctx(lbeo_ctx *c) {
   free(c->G);
   free(c->cmf);
   free(c->cvisc);
+  free(c->pi);
+  free(c->qpx);
+  free(c->qpy);
+  free(c->qpphi);
+  free(c->qpsum);
   for (int a = 0; a < MAXM; ++a) {
     for (int b = a; b < MAXM; ++b) {
       free_shell(&c->shell[a][b]);
@@ -435,9 +446,20 @@ int lbeo_create(const lbeo_config *cfg, lbeo_ctx **out) {
   c->G = calloc((size_t)M * M * N, sizeof(double));
   c->cmf = calloc((size_t)M * 3 * N, sizeof(double));
   c->cvisc = calloc((size_t)M * 3 * N, sizeof(double));
+  c->pi = calloc((size_t)M * N, sizeof(double));
+  int nmax = c->nx > c->ny ? c->nx : c->ny;
+  if (c->nz > nmax) nmax = c->nz;
+  c->qpx = calloc((size_t)nmax, sizeof(double));
+  c->qpy = calloc((size_t)nmax * nmax, sizeof(double));
+  c->qpphi = calloc((size_t)N, sizeof(double));
+  c->qpsum = calloc((size_t)N, sizeof(double));
+  c->qp_origin[0] = c->nx / 2;
+  c->qp_origin[1] = c->ny / 2;
+  c->qp_origin[2] = c->nz / 2;
+  c->qp_mode = LBEO_QP_SYMMETRIC;
   if (!c->solid || !c->V || !c->FV || !c->f || !c->g || !c->fpost ||
       !c->gpost || !c->n || !c->Pit || !c->Jt || !c->ut || !c->nbar ||
-      !c->G || !c->cmf || !c->cvisc) {
+      !c->G || !c->cmf || !c->cvisc || !c->pi || !c->qpx || !c->qpy || !c->qpphi || !c->qpsum) {
     free_ctx(c);
     return fail(LBEO_ERR_OOM, "out of memory");
   }
@@ -460,6 +482,11 @@ int lbeo_create(const lbeo_config *cfg, lbeo_ctx **out) {
   *out = c;
   g_err[0] = 0;
   return LBEO_OK;
+}
+
+/* the default reading: Pi evaluated by the path integral every step */
+static int qp_per_step(const lbeo_ctx *c) {
+  return !(c->cfg.flags & (LBEO_PI_CARRIED | LBEO_SINGLE));
 }
 
 static const shell_t *pair_shell(const lbeo_ctx *c, int a, int b) {
@@ -618,7 +645,8 @@ static void compute_moments(lbeo_ctx *c) {
 
 /* ------------------------------------------------------------------------ */
 /* Step 2: weighted densities nbar_b (ball of radius sigma_b/2, solid and   */
-/* out-of-domain nodes count as empty, normalised by the ball size) and the */
+/* out-of-domain nodes count as empty, normalised by the ball size; with    */
+/* BALL_FLUID normalised by the number of fluid points instead) and the     */
 /* contact values G_ab(r).  The pair value used by the forces is            */
 /* g_ab(r, r') = (G_ab(r) + G_ab(r'))/2 (our reading of "g_ab at contact"). */
 /* Returns 1 if some fluid node has a packing fraction xi3 >= 1 or a        */
@@ -635,12 +663,18 @@ static int compute_contact(lbeo_ctx *c) {
       for (int y = 0; y < c->ny; ++y)
         for (int x = 0; x < c->nx; ++x) {
           double s = 0.0;
+          int nfl = 0;
           for (int k = 0; k < bl->npts; ++k) {
             long j = neighbour(c, x, y, z, bl->off[k][0], bl->off[k][1],
                                bl->off[k][2]);
-            if (is_fluid(c, j)) s += nb[j];
+            if (is_fluid(c, j)) {
+              s += nb[j];
+              ++nfl;
+            }
           }
-          c->nbar[(long)b * N + IDX(c, x, y, z)] = s / bl->npts;
+          /* BALL_FLUID: the average over the fluid points of the ball */
+          int norm = (c->cfg.flags & LBEO_BALL_FLUID) ? nfl : bl->npts;
+          c->nbar[(long)b * N + IDX(c, x, y, z)] = norm > 0 ? s / norm : 0.0;
         }
   }
   int bad = 0;
@@ -823,7 +857,8 @@ static int collide_node_tab(const hermite_t *tab, int M, double tau,
                             double kT, unsigned flags, const double *ft,
                             const double *gt, const double *cmf,
                             const double *cvisc, const double *F,
-                            double *fpost, double *gpost, double *mom);
+                            const double *pipath, double *fpost,
+                            double *gpost, double *mom);
 
 int lbeo_collide_node(int M, double tau, double kT, unsigned flags,
                       const double *ft, const double *gt, const double *cmf,
@@ -833,14 +868,15 @@ int lbeo_collide_node(int M, double tau, double kT, unsigned flags,
   hermite_t tab;
   hermite_tables(kT, &tab);
   return collide_node_tab(&tab, M, tau, kT, flags, ft, gt, cmf, cvisc, F,
-                          fpost, gpost, mom);
+                          NULL, fpost, gpost, mom);
 }
 
 static int collide_node_tab(const hermite_t *tab, int M, double tau,
                             double kT, unsigned flags, const double *ft,
                             const double *gt, const double *cmf,
                             const double *cvisc, const double *F,
-                            double *fpost, double *gpost, double *mom) {
+                            const double *pipath, double *fpost,
+                            double *gpost, double *mom) {
   const double h = 1.0;
   double vT2 = kT, beta = 1.0 / kT, omega = 1.0 / tau;
   int euler = (flags & LBEO_EULER) != 0;
@@ -854,7 +890,7 @@ static int collide_node_tab(const hermite_t *tab, int M, double tau,
   const double(*H2)[3][3] = tab->H2;
 
   double n[MAXM], Pit[MAXM], Jt[MAXM][3], J[MAXM][3], ua[MAXM][3], Pi[MAXM];
-  double X[MAXM][3], Y[MAXM][3];
+  double X[MAXM][3], Y[MAXM][3], dPit[MAXM];
   double ntot = 0.0, Jtot[3] = {0, 0, 0};
   for (int a = 0; a < M; ++a) {
     /* the current from g (DD) or from f itself (SD) */
@@ -874,6 +910,15 @@ static int collide_node_tab(const hermite_t *tab, int M, double tau,
       Pi[a] = Pit[a];
     else
       Pi[a] = printed ? Pit[a] - 0.5 * h * beta * cu : Pit[a] + 0.5 * h * beta * cu;
+    dPit[a] = 0.0;
+    if (pipath && !single) {
+      /* default reading: Pi is the path integral; the zeroth moment of g~
+         becomes the Pi~ that the same inversion maps to it */
+      double target = pipath[a];
+      if (!euler) target += (printed ? 0.5 : -0.5) * h * beta * cu;
+      Pi[a] = pipath[a];
+      dPit[a] = target - Pit[a];
+    }
     ntot += n[a];
     for (int k = 0; k < 3; ++k) Jtot[k] += J[a][k];
   }
@@ -905,7 +950,7 @@ static int collide_node_tab(const hermite_t *tab, int M, double tau,
       }
       sf *= w;
       sg *= w;
-      double fo = ft[a * Q + p], go = gt[a * Q + p];
+      double fo = ft[a * Q + p], go = gt[a * Q + p] + w * dPit[a];
       fpost[a * Q + p] = fo + acoef * (feq - fo) + bcoef * sf;
       gpost[a * Q + p] = single ? 0.0 : go + acoef * (geq - go) + bcoef * sg;
     }
@@ -957,8 +1002,11 @@ static void collide_all(lbeo_ctx *c) {
       continue;
     }
     node_inputs(c, i, ft, gt, cm, cv, F);
+    double pp[MAXM];
+    if (qp_per_step(c))
+      for (int a = 0; a < M; ++a) pp[a] = c->pi[(long)a * N + i];
     collide_node_tab(&c->herm, M, c->cfg.tau, c->cfg.kT, c->cfg.flags, ft, gt,
-                     cm, cv, F, fo, go, NULL);
+                     cm, cv, F, qp_per_step(c) ? pp : NULL, fo, go, NULL);
     for (int a = 0; a < M; ++a)
       for (int p = 0; p < Q; ++p) {
         c->fpost[((long)a * Q + p) * N + i] = fo[a * Q + p];
@@ -1000,6 +1048,9 @@ int lbeo_stream(lbeo_ctx *c, const double *post, double *out) {
   return LBEO_OK;
 }
 
+static void qp_field(const lbeo_ctx *c, int a, const int origin[3],
+                     unsigned mode, double *out);
+
 /* moments + contact values + forces of the current state */
 static int prepare(lbeo_ctx *c) {
   compute_moments(c);
@@ -1020,6 +1071,12 @@ int lbeo_step(lbeo_ctx *c, int nsteps) {
   for (int s = 0; s < nsteps; ++s) {
     int st = prepare(c);
     if (st != LBEO_OK) return st;
+    if (qp_per_step(c)) {
+      if (c->solid[IDX(c, c->qp_origin[0], c->qp_origin[1], c->qp_origin[2])])
+        return fail(LBEO_ERR_STATE, "the quasi-pressure origin is a solid node");
+      for (int a = 0; a < c->M; ++a)
+        qp_field(c, a, c->qp_origin, c->qp_mode, c->pi + (long)a * c->N);
+    }
     collide_all(c);
     for (int a = 0; a < c->M; ++a) {
       stream_one(c, c->fpost + (long)a * Q * c->N, c->f + (long)a * Q * c->N);
@@ -1056,7 +1113,7 @@ int lbeo_get_velocity(lbeo_ctx *c, int a, double *out) {
     }
     node_inputs(c, i, ft, gt, cm, cv, F);
     collide_node_tab(&c->herm, M, c->cfg.tau, c->cfg.kT, c->cfg.flags, ft, gt,
-                     cm, cv, F, fo, go, mom);
+                     cm, cv, F, NULL, fo, go, mom);
     for (int k = 0; k < 3; ++k)
       out[(long)k * N + i] = a < 0 ? mom[8 * M + k] : mom[8 * a + 5 + k];
   }
@@ -1124,23 +1181,9 @@ static double qp_integrand(const lbeo_ctx *c, int a, unsigned mode, int k,
   return v;
 }
 
-/* integral of v_k along axis k from r (updated in place) to coordinate end */
-static double qp_leg(const lbeo_ctx *c, int a, unsigned mode, int k, int r[3],
-                     int end) {
-  double acc = 0.0;
-  int dir = end > r[k] ? 1 : -1;
-  while (r[k] != end) {
-    double va = qp_integrand(c, a, mode, k, r);
-    r[k] += dir;
-    double vb = qp_integrand(c, a, mode, k, r);
-    acc += dir * 0.5 * (va + vb);
-  }
-  return acc;
-}
-
 static int qp_check(lbeo_ctx *c, const int origin[3], unsigned mode) {
   if (!c || !origin) return fail(LBEO_ERR_ARG, "null argument");
-  if (mode & ~LBEO_QP_WITH_FEXT) return fail(LBEO_ERR_ARG, "bad mode");
+  if (mode & ~(LBEO_QP_WITH_FEXT | LBEO_QP_SYMMETRIC)) return fail(LBEO_ERR_ARG, "bad mode");
   if (origin[0] < 0 || origin[0] >= c->nx || origin[1] < 0 ||
       origin[1] >= c->ny || origin[2] < 0 || origin[2] >= c->nz)
     return fail(LBEO_ERR_ARG, "origin outside the box");
@@ -1149,25 +1192,110 @@ static int qp_check(lbeo_ctx *c, const int origin[3], unsigned mode) {
   return LBEO_OK;
 }
 
-/* Pi of species a at every node, from the current forces and densities */
+/* Pi of species a at every node, from the current forces and densities.   */
+/* The path from the origin r0 to r runs along the three axes in a given    */
+/* order (p0, p1, p2): along p0 to r's p0 coordinate (the other two at the  */
+/* origin's), then along p1, then along p2.  Each leg is the trapezoidal    */
+/* sum of unit steps walked away from the origin, accumulated one step at a */
+/* time, a step from r to r' adding s (v_k(r) + v_k(r'))/2 with s = +1      */
+/* walking up and -1 walking down:                                          */
+/*   A0(c0)         along p0 (one line),                                    */
+/*   A1(c0, c1)     along p1 (one line per c0),                             */
+/*   A2(c0, c1, c2) along p2 (one line per (c0, c1)),                       */
+/* and Phi_order = (A0 + A1) + A2.  Mode 0 takes the order (x, y, z);       */
+/* LBEO_QP_SYMMETRIC takes the mean of the six orders, summed in the order  */
+/* (x,y,z), (x,z,y), (y,x,z), (y,z,x), (z,x,y), (z,y,x) and divided by 6.   */
+/* Pi = n - beta Phi on fluid nodes, 0 on solid ones.                       */
+static double qp_step_term(const lbeo_ctx *c, int a, unsigned mode, int k,
+                           const int from[3], int dir) {
+  int to[3] = {from[0], from[1], from[2]};
+  to[k] += dir;
+  double va = qp_integrand(c, a, mode, k, from);
+  double vb = qp_integrand(c, a, mode, k, to);
+  return dir * 0.5 * (va + vb);
+}
+
+/* Phi along one axis order, written to phi (N values) */
+static void qp_order(const lbeo_ctx *c, int a, const int origin[3],
+                     unsigned mode, const int ord[3], double *phi) {
+  const int ext[3] = {c->nx, c->ny, c->nz};
+  const int p0 = ord[0], p1 = ord[1], p2 = ord[2];
+  const int L0 = ext[p0], L1 = ext[p1], L2 = ext[p2];
+  double *A0 = c->qpx, *A1 = c->qpy;
+  /* leg along p0, through the origin */
+  A0[origin[p0]] = 0.0;
+  for (int k = origin[p0] + 1; k < L0; ++k) {
+    int r[3] = {origin[0], origin[1], origin[2]};
+    r[p0] = k - 1;
+    A0[k] = A0[k - 1] + qp_step_term(c, a, mode, p0, r, +1);
+  }
+  for (int k = origin[p0] - 1; k >= 0; --k) {
+    int r[3] = {origin[0], origin[1], origin[2]};
+    r[p0] = k + 1;
+    A0[k] = A0[k + 1] + qp_step_term(c, a, mode, p0, r, -1);
+  }
+  /* legs along p1, one per c0 */
+#pragma omp parallel for schedule(static)
+  for (int c0 = 0; c0 < L0; ++c0) {
+    double *a1 = A1 + (long)c0 * L1;
+    a1[origin[p1]] = 0.0;
+    for (int k = origin[p1] + 1; k < L1; ++k) {
+      int r[3] = {origin[0], origin[1], origin[2]};
+      r[p0] = c0;
+      r[p1] = k - 1;
+      a1[k] = a1[k - 1] + qp_step_term(c, a, mode, p1, r, +1);
+    }
+    for (int k = origin[p1] - 1; k >= 0; --k) {
+      int r[3] = {origin[0], origin[1], origin[2]};
+      r[p0] = c0;
+      r[p1] = k + 1;
+      a1[k] = a1[k + 1] + qp_step_term(c, a, mode, p1, r, -1);
+    }
+  }
+  /* legs along p2, one per (c0, c1) */
+#pragma omp parallel for schedule(static)
+  for (int c1 = 0; c1 < L1; ++c1)
+    for (int c0 = 0; c0 < L0; ++c0) {
+      double base = A0[c0] + A1[(long)c0 * L1 + c1];
+      int r[3];
+      r[p0] = c0;
+      r[p1] = c1;
+      double a2 = 0.0;
+      for (int k = origin[p2]; k < L2; ++k) {
+        if (k > origin[p2]) {
+          r[p2] = k - 1;
+          a2 += qp_step_term(c, a, mode, p2, r, +1);
+        }
+        r[p2] = k;
+        phi[IDX(c, r[0], r[1], r[2])] = base + a2;
+      }
+      a2 = 0.0;
+      for (int k = origin[p2] - 1; k >= 0; --k) {
+        r[p2] = k + 1;
+        a2 += qp_step_term(c, a, mode, p2, r, -1);
+        r[p2] = k;
+        phi[IDX(c, r[0], r[1], r[2])] = base + a2;
+      }
+    }
+}
+
 static void qp_field(const lbeo_ctx *c, int a, const int origin[3],
                      unsigned mode, double *out) {
+  static const int orders[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2},
+                                   {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
   double beta = 1.0 / c->cfg.kT;
-#pragma omp parallel for schedule(static)
-  for (int z = 0; z < c->nz; ++z)
-    for (int y = 0; y < c->ny; ++y)
-      for (int x = 0; x < c->nx; ++x) {
-        long i = IDX(c, x, y, z);
-        if (c->solid[i]) {
-          out[i] = 0.0;
-          continue;
-        }
-        int r[3] = {origin[0], origin[1], origin[2]};
-        double phi = qp_leg(c, a, mode, 0, r, x);
-        phi += qp_leg(c, a, mode, 1, r, y);
-        phi += qp_leg(c, a, mode, 2, r, z);
-        out[i] = c->n[(long)a * c->N + i] - beta * phi;
-      }
+  long N = c->N;
+  double *phi = c->qpphi, *sum = c->qpsum;
+  int nord = (mode & LBEO_QP_SYMMETRIC) ? 6 : 1;
+  for (long i = 0; i < N; ++i) sum[i] = 0.0;
+  for (int o = 0; o < nord; ++o) {
+    qp_order(c, a, origin, mode, orders[o], phi);
+    for (long i = 0; i < N; ++i) sum[i] += phi[i];
+  }
+  for (long i = 0; i < N; ++i) {
+    double ph = nord == 6 ? sum[i] / 6.0 : sum[i];
+    out[i] = c->solid[i] ? 0.0 : c->n[(long)a * N + i] - beta * ph;
+  }
 }
 
 int lbeo_quasipressure(lbeo_ctx *c, int a, const int origin[3], unsigned mode,
@@ -1179,6 +1307,14 @@ int lbeo_quasipressure(lbeo_ctx *c, int a, const int origin[3], unsigned mode,
   st = prepare(c);
   if (st != LBEO_OK) return st;
   qp_field(c, a, origin, mode, out);
+  return LBEO_OK;
+}
+
+int lbeo_set_quasipressure_route(lbeo_ctx *c, const int origin[3], unsigned mode) {
+  int st = qp_check(c, origin, mode);
+  if (st != LBEO_OK) return st;
+  for (int k = 0; k < 3; ++k) c->qp_origin[k] = origin[k];
+  c->qp_mode = mode;
   return LBEO_OK;
 }
 
@@ -1209,7 +1345,7 @@ int lbeo_init_quasipressure(lbeo_ctx *c, const int origin[3], unsigned mode) {
     if (c->solid[i]) continue;
     node_inputs(c, i, ft, gt, cm, cv, F);
     collide_node_tab(&c->herm, M, c->cfg.tau, c->cfg.kT, c->cfg.flags, ft, gt,
-                     cm, cv, F, fo, go, mom);
+                     cm, cv, F, NULL, fo, go, mom);
     for (int a = 0; a < M; ++a) {
       double cu = 0.0;
       for (int k = 0; k < 3; ++k) cu += cm[a * 3 + k] * mom[8 * a + 5 + k];
@@ -1319,7 +1455,7 @@ int lbeo_diagnostics(lbeo_ctx *c, lbeo_diag *out) {
     double cm[MAXM * 3], cv[MAXM * 3], F[MAXM * 3], mom[8 * MAXM + 3];
     node_inputs(c, i, ft, gt, cm, cv, F);
     collide_node_tab(&c->herm, M, c->cfg.tau, c->cfg.kT, c->cfg.flags, ft, gt,
-                     cm, cv, F, fo, go, mom);
+                     cm, cv, F, NULL, fo, go, mom);
     double uu = 0.0, jj = 0.0, nt = 0.0;
     for (int k = 0; k < 3; ++k) {
       double Jk = 0.0;

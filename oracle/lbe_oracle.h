@@ -65,7 +65,24 @@ enum {
  *               and the contact values G_ab(r),
  *               C^drag_a = -n_a sum_b 2 sigma_ab^2 sqrt(kT/pi) (4 pi/3)
  *                          G_ab n_b (u~_a - u~_b).
- *               It enters X and Y like C^visc (and is reported with it). */
+ *               It enters X and Y like C^visc (and is reported with it).
+ * How the quasi-pressure Pi^a enters the step (Sec. 2).  The zeroth moment
+ * of g is Pi^a by definition (eq. definition), and Pi^a is the potential
+ * function of eq. quasipressure, which Sec. 2 evaluates numerically by the
+ * trapezoidal rule.  Default: each step, after the forces, Pi^a is
+ * evaluated at every node from the current C^{a,mf} (plus n^a F^a with
+ * LBEO_QP_WITH_FEXT) as lbeo_quasipressure does, from the route origin and
+ * with the route mode (default the box centre and the mean over the six
+ * axis orders; lbeo_set_quasipressure_route), the zeroth
+ * moment of g~ is set to the Pi~ that the inversion of Sec. 4.2 maps to
+ * that Pi, and g_eq takes that Pi.  (Not with SINGLE, which has no g.)
+ *  PI_CARRIED   the other reading: Pi is carried by g from its initial
+ *               value, changed only by the zeroth source moment of
+ *               eq. kernel-g-1, and no path integral is evaluated.
+ *  BALL_FLUID   weighted densities average n_b over the fluid points of
+ *               the ball only (normalised by their count); default: solid
+ *               and out-of-domain points count as empty and the
+ *               normalisation is the full ball size. */
 enum {
   LBEO_VISC = 1u << 0,
   LBEO_PRINTED_INV = 1u << 1,
@@ -73,7 +90,9 @@ enum {
   LBEO_IDEAL = 1u << 3,
   LBEO_EULER = 1u << 4,
   LBEO_SINGLE = 1u << 5,
-  LBEO_DRAG = 1u << 6
+  LBEO_DRAG = 1u << 6,
+  LBEO_PI_CARRIED = 1u << 7,
+  LBEO_BALL_FLUID = 1u << 8
 };
 
 typedef struct {
@@ -125,12 +144,21 @@ int lbeo_diagnostics(lbeo_ctx *ctx, lbeo_diag *out);
 /* then y, then z from the origin r0, which must be a fluid node; no step    */
 /* crosses a periodic face.  Pi = 0 on solid nodes.                          */
 #define LBEO_QP_WITH_FEXT 1u
+/* mode bit: the mean of the integrals along the six axis orders (x,y,z),  */
+/* (x,z,y), (y,x,z), (y,z,x), (z,x,y), (z,y,x) instead of (x,y,z) alone;   */
+/* it keeps the cubic symmetry of the lattice about the origin.            */
+#define LBEO_QP_SYMMETRIC 2u
 int lbeo_quasipressure(lbeo_ctx *ctx, int species, const int origin[3],
                        unsigned mode, double *out);                 /* N */
 /* Sets the zeroth moment of every species' g~ to Pi~, the tilde value of    */
 /* the quasi-pressure above at the current state, leaving f~ and the first   */
 /* moment of g~ unchanged.  Not available with LBEO_SINGLE (no g).          */
 int lbeo_init_quasipressure(lbeo_ctx *ctx, const int origin[3], unsigned mode);
+/* Origin and mode (bits as above) of the per-step quasi-pressure (the      */
+/* default reading, see PI_CARRIED); the origin must be a fluid node when a */
+/* step runs.  Defaults: the box centre (nx/2, ny/2, nz/2) and              */
+/* LBEO_QP_SYMMETRIC.                                                       */
+int lbeo_set_quasipressure_route(lbeo_ctx *ctx, const int origin[3], unsigned mode);
 
 /* ---- velocity divergence (Sec. 4.3, the D of the channel validation) ------ */
 /* D = div_h u / (v_T / dx) of the barycentric velocity u, with the isotropic */

@@ -5,10 +5,10 @@ initialiser against what the mathematics and the method fix:
   cosine whose trapezoidal sum carries the factor (k/2) cot(k/2));
 * hydrostatic equilibrium: with the external-force term (the printed form) the
   quasi-pressure of the ideal-gas Boltzmann profile is uniform up to O(dx^2);
-* the discrete scheme's own rest state: at a relaxed hard-sphere profile the Pi
-  that the g populations carry equals the path integral of C^mf alone (the
-  default reading) up to a constant, while the printed form is off by
-  beta * integral of n F;
+* the discrete scheme's own rest state under the carried reading
+  (LBEO_PI_CARRIED): at a relaxed hard-sphere profile the Pi that the g
+  populations carry equals the path integral of C^mf alone up to a constant,
+  while the printed form is off by beta * integral of n F;
 * the initialiser: it leaves f~ and the first moment of g~ unchanged, the
   inversion of Sec. 4.2 applied to its g~ returns the path integral, it
   restores a relaxed g~ whose zeroth moment was disturbed, and it shortens the
@@ -23,6 +23,7 @@ from paper_1202_3842_amd import workloads as W
 
 KT = 1.0 / 3.0
 BETA = 1.0 / KT
+CARRIED = (1 << 0) | (1 << 7)        # LBEO_VISC | LBEO_PI_CARRIED
 
 
 def _grid(nx, ny, nz):
@@ -39,10 +40,12 @@ def _ideal(o_lib, nx, ny, nz, n, body=(0.0, 0.0, 0.0), V=None):
     return o
 
 
-def test_constant_integrand_is_integrated_exactly(oracle_lib):
+@pytest.mark.parametrize("sym", [0, 2])
+def test_constant_integrand_is_integrated_exactly(oracle_lib, sym):
     """Ideal gas, uniform n0, body force g: v = n0 g is constant, so with the
     printed integrand Pi = n0 - beta n0 g.(r - r0) exactly (the path goes
-    backwards where r < r0); without the n F term Pi = n (C^mf = 0)."""
+    backwards where r < r0), along the x, y, z path and as the mean of the six
+    axis orders; without the n F term Pi = n (C^mf = 0)."""
     nx, ny, nz = 12, 10, 8
     n0 = 0.01
     g = (1e-3, -2e-3, 5e-4)
@@ -50,9 +53,9 @@ def test_constant_integrand_is_integrated_exactly(oracle_lib):
     o = _ideal(oracle_lib, nx, ny, nz, np.full((nz, ny, nx), n0), g)
     x, y, z = _grid(nx, ny, nz)
     ref = n0 - BETA * n0 * (g[0] * (x - r0[0]) + g[1] * (y - r0[1]) + g[2] * (z - r0[2]))
-    pi = o.quasipressure(0, r0, oracle_lib.LBEO_QP_WITH_FEXT)
+    pi = o.quasipressure(0, r0, oracle_lib.LBEO_QP_WITH_FEXT | sym)
     assert np.abs(pi - ref).max() <= 1e-14 * n0
-    assert np.abs(o.quasipressure(0, r0, 0) - n0).max() == 0.0
+    assert np.abs(o.quasipressure(0, r0, sym) - n0).max() == 0.0
 
 
 def test_trapezoid_weights_on_a_cosine(oracle_lib):
@@ -127,7 +130,7 @@ def relaxed(oracle_lib):
     when max |u| has decayed to rounding level.  (Noise would seed a slowly
     growing mode of the derived DD-TR in non-uniform states; without it the
     state stays at rest over these steps.)"""
-    o, V = _slab_well(oracle_lib, [3.0], [0.1], oracle_lib.LBEO_VISC)
+    o, V = _slab_well(oracle_lib, [3.0], [0.1], CARRIED)
     o.step(1000)
     assert np.abs(o.velocity(0)).max() < 1e-11
     return o, V
@@ -163,7 +166,7 @@ def test_initialiser_restores_a_disturbed_relaxed_state(oracle_lib, relaxed):
     g = o0.populations(0, 1)
     _, w, _ = oracle_lib.d3q19()
     d = W.rng(77).uniform(-1e-3, 1e-3, size=f.shape[1:])
-    o = oracle_lib.Oracle(NX, NY, NZ, [3.0], flags=oracle_lib.LBEO_VISC)
+    o = oracle_lib.Oracle(NX, NY, NZ, [3.0], flags=CARRIED)
     o.set_potential(V)
     o.set_populations(0, 0, f)
     o.set_populations(0, 1, g + w[:, None, None, None] * d)
@@ -245,7 +248,7 @@ def test_initialiser_shortens_the_start_up_transient(oracle_lib, relaxed):
     n = o0.density(0)
     umax = {}
     for mode in (None, 0, oracle_lib.LBEO_QP_WITH_FEXT):
-        o = oracle_lib.Oracle(NX, NY, NZ, [3.0], flags=oracle_lib.LBEO_VISC)
+        o = oracle_lib.Oracle(NX, NY, NZ, [3.0], flags=CARRIED)
         o.set_potential(V)
         o.init_density(0, n)
         if mode is not None:
@@ -267,7 +270,7 @@ def test_argument_errors(oracle_lib):
     with pytest.raises(oracle_lib.OracleError):
         o.quasipressure(0, (1, 0, 1), 0)           # solid node
     with pytest.raises(oracle_lib.OracleError):
-        o.quasipressure(0, (1, 1, 1), 2)           # unknown mode bit
+        o.quasipressure(0, (1, 1, 1), 4)           # unknown mode bit
     s = oracle_lib.Oracle(8, 8, 8, [2.0], flags=oracle_lib.LBEO_SINGLE)
     s.init_density(0, np.full((8, 8, 8), 0.01))
     with pytest.raises(oracle_lib.OracleError):
