@@ -99,7 +99,18 @@ enum { LBE_HOST = 0, LBE_DEVICE = 1 };   /* the 'where' of user pointers    */
  *                   C^drag_a = -n_a sum_b 2 sigma_ab^2 sqrt(kT/pi) (4pi/3)
  *                   G_ab n_b (u~_a - u~_b) with u~ = J~/n, to the
  *                   dissipative forces (with C^visc in X, Y and
- *                   lbe_get_force(which = 1)); zero for one species.       */
+ *                   lbe_get_force(which = 1)); zero for one species.
+ * How the quasi-pressure Pi enters the step (Sec. 2).  The zeroth moment of
+ * g is Pi by definition (eq. definition), and Pi is the potential function
+ * of eq. quasipressure, which Sec. 2 computes by trapezoidal integration.
+ * Default: each step, after the forces, Pi is evaluated at every node as
+ * lbe_get_quasipressure does, with the route of lbe_set_quasipressure_route
+ * (default: origin at the box centre, the mean over the six axis orders);
+ * the zeroth moment of g~ is set to the Pi~ that the inversion below maps
+ * to that Pi, and g_eq takes Pi.  (Not with LBE_SINGLE, which has no g.)
+ *  LBE_PI_CARRIED   the other reading: Pi is carried by g from its initial
+ *                   value and changed only by the zeroth source moment of
+ *                   eq. kernel-g-1; no path integral is evaluated.          */
 enum {
   LBE_VISC = 1u << 0,
   LBE_PRINTED_INV = 1u << 1,
@@ -107,7 +118,8 @@ enum {
   LBE_IDEAL = 1u << 3,
   LBE_EULER = 1u << 4,
   LBE_SINGLE = 1u << 5,
-  LBE_DRAG = 1u << 6
+  LBE_DRAG = 1u << 6,
+  LBE_PI_CARRIED = 1u << 7
 };
 
 #define LBE_MAX_SPECIES 4
@@ -185,9 +197,10 @@ lbe_status lbe_step(lbe_ctx *ctx, int nsteps);
 
 /* One phase of lbe_step, for instrumentation (e.g. HIP events around one
  * kernel): phase 0 = moments, 1 = contact values, 2 = nonlocal forces,
- * 3 = collision + streaming store + buffer swap.  Calling phases 0..3 in
- * order is exactly one lbe_step; any other order is rejected with
- * LBE_ERR_STATE. */
+ * 3 = the per-step quasi-pressure (nothing with LBE_PI_CARRIED or
+ * LBE_SINGLE), 4 = collision + streaming store + buffer swap.  Calling
+ * phases 0..4 in order is exactly one lbe_step; any other order is rejected
+ * with LBE_ERR_STATE. */
 lbe_status lbe_step_phase(lbe_ctx *ctx, int phase);
 
 /* n^a = sum_p f~_p (Sec. 4.2), N values. */
@@ -227,9 +240,13 @@ lbe_status lbe_get_divergence(lbe_ctx *ctx, double *out, int where);
 /* ---- quasi-pressure (Sec. 2, eq. quasipressure) ----------------------------
  * Pi^a(r) = n^a(r) - beta * Phi^a(r), Phi^a the line integral of v^a from an
  * origin r0 to r, evaluated with the trapezoidal rule on unit lattice steps
- * (as the paper does): along x from r0 to (x, y0, z0), then along y to
- * (x, y, z0), then along z to r; no step crosses a periodic face.  The
- * paper fixes no path.  Its equation integrates v^a = C^{a,mf} + n^a F^a;
+ * (as the paper does) along a path that runs along the axes in turn: in the
+ * order x, y, z, from r0 to (x, y0, z0), then to (x, y, z0), then to r (mode
+ * 0), or, with LBE_QP_SYMMETRIC, the mean of the integrals over the six axis
+ * orders, which keeps the cubic symmetry of the lattice about r0 (the
+ * default route of the per-step quasi-pressure).  No step crosses a
+ * periodic face.  The paper fixes no path.  Its equation integrates
+ * v^a = C^{a,mf} + n^a F^a;
  * the discrete g source of Sec. 4.2 keeps n^a F^a as a force, so the Pi
  * that the discrete scheme carries at rest is the integral of C^{a,mf}
  * alone.  That is the default (mode 0); mode LBE_QP_WITH_FEXT adds
@@ -238,11 +255,11 @@ lbe_status lbe_get_divergence(lbe_ctx *ctx, double *out, int where);
  * LBE_ERR_ARG for a null pointer, an origin outside the box or on a solid
  * node, or unknown mode bits; LBE_ERR_UNSTABLE if the state has a packing
  * fraction >= 1 or a non-finite density. */
-enum { LBE_QP_WITH_FEXT = 1u };
+enum { LBE_QP_WITH_FEXT = 1u, LBE_QP_SYMMETRIC = 2u };
 
 /* Pi of one species, N values (0 on solid nodes); origin = {x0, y0, z0}.
- * Blocks until the result is in out.  Uses the context's second population
- * buffer as scratch (the state is not changed). */
+ * Blocks until the result is in out.  The state is not changed.  Refused
+ * inside a phased step (LBE_ERR_STATE). */
 lbe_status lbe_get_quasipressure(lbe_ctx *ctx, int species, const int origin[3],
                                  unsigned mode, double *out, int where);
 
@@ -258,6 +275,14 @@ lbe_status lbe_get_quasipressure(lbe_ctx *ctx, int species, const int origin[3],
  * LBE_ERR_ARG with LBE_SINGLE (no g) and LBE_ERR_STATE inside a phased
  * step. */
 lbe_status lbe_init_quasipressure(lbe_ctx *ctx, const int origin[3], unsigned mode);
+
+/* Route of the per-step quasi-pressure (the default reading above): origin
+ * {x0, y0, z0}, a fluid node, and mode bits as above (default: the box
+ * centre and LBE_QP_SYMMETRIC).  The integration constant (the value at the
+ * origin) does not enter n or u.  Errors as above (LBE_SINGLE accepts a
+ * route and ignores it); lbe_step returns LBE_ERR_STATE while the origin is
+ * a solid node (lbe_set_solid may make it one). */
+lbe_status lbe_set_quasipressure_route(lbe_ctx *ctx, const int origin[3], unsigned mode);
 
 /* Mass, g-momentum, spurious-current and Sec. 4.1 error measures of the
  * current state; synchronises. */

@@ -79,6 +79,7 @@ def _time_force(lbe, torch, cfg, zchunk, order, rows, reps):
         b.step_phase(2)
         ev[k][1].record(st)
         b.step_phase(3)
+        b.step_phase(4)
     torch.cuda.synchronize()
     t = min(e0.elapsed_time(e1) for e0, e1 in ev)
     b.close()

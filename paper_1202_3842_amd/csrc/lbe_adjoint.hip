@@ -41,6 +41,9 @@ lbe_status make_adj_plan(const lbe_config *cfg, int nsteps, int segment, AdjPlan
   lbe_status st = make_plan(cfg, ap.pl);
   if (st != LBE_OK) return st;
   if (nsteps < 1 || segment < 1) return fail(LBE_ERR_ARG, "nsteps and segment must be >= 1");
+  if (qp_per_step(cfg->flags))
+    return fail(LBE_ERR_UNSUPPORTED,
+                "the adjoint covers the carried reading of Pi (LBE_PI_CARRIED) and LBE_SINGLE");
   const Plan &P = ap.pl;
   const size_t N = P.g.N, Np = P.g.Np, M = P.M, npairs = P.npairs;
   ap.T = nsteps;

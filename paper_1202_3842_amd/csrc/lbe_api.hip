@@ -107,6 +107,9 @@ HostAtt make_att(double sab, double eps, double rc) {
 
 namespace lbe {
 
+// the default reading: Pi from the path integral every step (DD only)
+bool qp_per_step(unsigned flags) { return !(flags & (LBE_PI_CARRIED | LBE_SINGLE)); }
+
 lbe_status make_plan(const lbe_config *cfg, Plan &pl) {
   if (!cfg) return fail(LBE_ERR_ARG, "null config");
   if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1)
@@ -208,6 +211,10 @@ lbe_status make_plan(const lbe_config *cfg, Plan &pl) {
   pl.off_force = take(sizeof(double) * 6 * pl.M * (size_t)g.N);
   pl.off_read = take(sizeof(double) * (13 * pl.M + 9) * (size_t)g.N);
   pl.off_part = take(sizeof(double) * DIAG_K * pl.nblocks);
+  // quasi-pressure of every species and the three axis scans (the per-step
+  // reading, lbe_get_quasipressure and lbe_init_quasipressure)
+  pl.off_pi = take(sizeof(double) * pl.M * (size_t)g.N);
+  pl.off_qps = take(sizeof(double) * 3 * pl.M * (size_t)g.N);
   pl.total = o;
   return LBE_OK;
 }
@@ -352,6 +359,12 @@ lbe_status lbe_create(const lbe_config *cfg, void *ws, size_t bytes, void *strea
                         !(cfg->flags & LBE_IDEAL);
   a.Jfield = currents ? c->at<double>(P.off_J) : nullptr;
   a.errflag = c->at<unsigned>(P.off_flag);
+  a.pifield = qp_per_step(cfg->flags) ? c->at<double>(P.off_pi) : nullptr;
+  c->qp_origin[0] = g.nx / 2;
+  c->qp_origin[1] = g.ny / 2;
+  c->qp_origin[2] = g.nz / 2;
+  c->qp_mode = LBE_QP_SYMMETRIC;
+  c->qp_origin_solid = false;
   double *rb = c->at<double>(P.off_read);
   size_t N = g.N;
   int M = P.M;
@@ -416,6 +429,17 @@ static lbe_status copy_out(lbe_ctx *c, void *dst, const void *src, size_t n, int
   return LBE_OK;
 }
 
+// whether node origin is solid (reads one mask word; synchronises)
+static lbe_status qp_check_origin(lbe_ctx *c, const int origin[3], bool *solid) {
+  const Geom &g = c->pl.g;
+  const long long io = origin[0] + (long long)g.nx * (origin[1] + (long long)g.ny * origin[2]);
+  uint32_t m = 0;
+  HIP_TRY(hipMemcpyAsync(&m, c->args.bb + io, sizeof m, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *solid = (m & 1u) != 0;
+  return LBE_OK;
+}
+
 lbe_status lbe_set_solid(lbe_ctx *c, const uint8_t *mask, int where) {
   if (!c) return fail(LBE_ERR_ARG, "null context");
   lbe_status st = copy_in(c, c->ws + c->pl.off_solid, mask, c->pl.g.N, where);
@@ -423,7 +447,7 @@ lbe_status lbe_set_solid(lbe_ctx *c, const uint8_t *mask, int where) {
   launch_bbmask(c->pl.g, c->at<uint8_t>(c->pl.off_solid), c->at<uint32_t>(c->pl.off_bb), c->stream);
   launch_zero_solid(c->pl.g, c->pl.M, c->cfg.prec, c->pop(c->cur), c->args.bb, c->pl.Ns, c->stream);
   LAUNCH_CHECK();
-  return LBE_OK;
+  return qp_check_origin(c, c->qp_origin, &c->qp_origin_solid);
 }
 
 lbe_status lbe_set_potential(lbe_ctx *c, const double *V, int where) {
@@ -461,9 +485,16 @@ lbe_status lbe_init_density(lbe_ctx *c, int species, const double *n0, int where
   return clear_instability(c);
 }
 
+// the per-step quasi-pressure (default reading), after the forces
+static void launch_step_quasipressure(lbe_ctx *c) {
+  if (!c->args.pifield) return;
+  launch_quasipressure(c->args, c->qp_origin, c->qp_mode, true, c->at<double>(c->pl.off_qps),
+                       c->at<double>(c->pl.off_pi), c->stream);
+}
+
 lbe_status lbe_step_phase(lbe_ctx *c, int phase) {
   if (!c) return fail(LBE_ERR_ARG, "null context");
-  if (phase < 0 || phase > 3) return fail(LBE_ERR_ARG, "phase must be 0..3");
+  if (phase < 0 || phase > 4) return fail(LBE_ERR_ARG, "phase must be 0..4");
   if (c->poisoned) return fail(LBE_ERR_UNSTABLE, "context is unstable; reinitialise the state");
   if (phase != c->next_phase) return fail(LBE_ERR_STATE, "phase %d expected", c->next_phase);
   hipStream_t s = c->stream;
@@ -471,11 +502,16 @@ lbe_status lbe_step_phase(lbe_ctx *c, int phase) {
   if (phase == 1) launch_contact(c->args, s);
   if (phase == 2) launch_forces(c->args, s);
   if (phase == 3) {
+    if (c->args.pifield && c->qp_origin_solid)
+      return fail(LBE_ERR_STATE, "the quasi-pressure origin is a solid node");
+    launch_step_quasipressure(c);
+  }
+  if (phase == 4) {
     launch_collide(c->args, c->cfg.prec, c->pop(c->cur), c->pop(c->cur ^ 1), s);
     c->cur ^= 1;
   }
   LAUNCH_CHECK();
-  c->next_phase = (phase + 1) % 4;
+  c->next_phase = (phase + 1) % 5;
   return LBE_OK;
 }
 
@@ -484,6 +520,7 @@ static lbe_status enqueue_step(lbe_ctx *c) {
   launch_moments(c->args, c->cfg.prec, c->pop(c->cur), s);
   launch_contact(c->args, s);
   launch_forces(c->args, s);
+  launch_step_quasipressure(c);
   launch_collide(c->args, c->cfg.prec, c->pop(c->cur), c->pop(c->cur ^ 1), s);
   LAUNCH_CHECK();
   c->cur ^= 1;
@@ -495,6 +532,8 @@ lbe_status lbe_step(lbe_ctx *c, int nsteps) {
   if (nsteps < 0) return fail(LBE_ERR_ARG, "nsteps < 0");
   if (c->poisoned) return fail(LBE_ERR_UNSTABLE, "context is unstable; reinitialise the state");
   if (c->next_phase != 0) return fail(LBE_ERR_STATE, "a phased step is incomplete");
+  if (c->args.pifield && c->qp_origin_solid && nsteps > 0)
+    return fail(LBE_ERR_STATE, "the quasi-pressure origin is a solid node");
   for (int k = 0; k < nsteps; ++k) {
     lbe_status st = enqueue_step(c);
     if (st != LBE_OK) return st;
@@ -620,29 +659,47 @@ lbe_status lbe_get_divergence(lbe_ctx *c, double *out, int where) {
   return bad ? fail(LBE_ERR_UNSTABLE, "packing fraction >= 1 or non-finite density") : LBE_OK;
 }
 
-// Quasi-pressure of every species at the current state into the scratch
-// area at the start of the second population buffer (M*N doubles, well inside
-// its f~ blocks, so the g~ blocks of that buffer stay free as a stage).
-static lbe_status qp_prepare(lbe_ctx *c, const int origin[3], unsigned mode, double **phi) {
+// Origin and mode checks shared by the quasi-pressure calls.
+static lbe_status qp_args(lbe_ctx *c, const int origin[3], unsigned mode) {
   if (!origin) return fail(LBE_ERR_ARG, "null origin");
-  if (mode & ~(unsigned)LBE_QP_WITH_FEXT) return fail(LBE_ERR_ARG, "unknown mode bits 0x%x", mode);
+  if (mode & ~(unsigned)(LBE_QP_WITH_FEXT | LBE_QP_SYMMETRIC))
+    return fail(LBE_ERR_ARG, "unknown mode bits 0x%x", mode);
   const Geom &g = c->pl.g;
   if (origin[0] < 0 || origin[0] >= g.nx || origin[1] < 0 || origin[1] >= g.ny || origin[2] < 0 ||
       origin[2] >= g.nz)
     return fail(LBE_ERR_ARG, "origin (%d, %d, %d) outside the %dx%dx%d box", origin[0], origin[1],
                 origin[2], g.nx, g.ny, g.nz);
-  const long long io = origin[0] + (long long)g.nx * (origin[1] + (long long)g.ny * origin[2]);
-  uint32_t m = 0;
-  HIP_TRY(hipMemcpyAsync(&m, c->args.bb + io, sizeof m, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  if (m & 1u) return fail(LBE_ERR_ARG, "origin is a solid node");
+  bool solid = false;
+  lbe_status st = qp_check_origin(c, origin, &solid);
+  if (st != LBE_OK) return st;
+  if (solid) return fail(LBE_ERR_ARG, "origin is a solid node");
+  return LBE_OK;
+}
+
+// Quasi-pressure of every species at the current state into the context's
+// Pi buffer (M*N doubles), after the read-out pass.
+static lbe_status qp_prepare(lbe_ctx *c, const int origin[3], unsigned mode, double **phi) {
+  if (c->next_phase != 0) return fail(LBE_ERR_STATE, "a phased step is incomplete");
+  lbe_status st = qp_args(c, origin, mode);
+  if (st != LBE_OK) return st;
   bool bad = false;
-  lbe_status st = readout(c, &bad);
+  st = readout(c, &bad);
   if (st != LBE_OK) return st;
   if (bad) return fail(LBE_ERR_UNSTABLE, "packing fraction >= 1 or non-finite density");
-  *phi = reinterpret_cast<double *>(c->pop(c->cur ^ 1));
-  launch_quasipressure(c->args, c->rd, origin, (mode & LBE_QP_WITH_FEXT) != 0, *phi, c->stream);
+  *phi = c->at<double>(c->pl.off_pi);
+  launch_quasipressure(c->args, origin, mode, false, c->at<double>(c->pl.off_qps), *phi, c->stream);
   LAUNCH_CHECK();
+  return LBE_OK;
+}
+
+lbe_status lbe_set_quasipressure_route(lbe_ctx *c, const int origin[3], unsigned mode) {
+  if (!c) return fail(LBE_ERR_ARG, "null context");
+  if (c->next_phase != 0) return fail(LBE_ERR_STATE, "a phased step is incomplete");
+  lbe_status st = qp_args(c, origin, mode);
+  if (st != LBE_OK) return st;
+  for (int k = 0; k < 3; ++k) c->qp_origin[k] = origin[k];
+  c->qp_mode = mode;
+  c->qp_origin_solid = false;
   return LBE_OK;
 }
 
@@ -838,6 +895,7 @@ struct lbe_batch {
   std::vector<Group> groups, att_groups;
   std::vector<int> zchunks;          // the zchunk of each box the tables were built for
   std::vector<StepArgs> uploaded;    // the parameter blocks last copied to the device
+  std::vector<int> routes;           // the quasi-pressure routes the graphs were captured with
   hipGraphExec_t graph[2] = {nullptr, nullptr};
 
   void drop_graphs() {
@@ -959,6 +1017,14 @@ void batch_launch_step(lbe_batch *B, int cur) {
     bf.blockstart = G.blockstart;
     launch_batch_att(bf, G.nblocks, G.R, G.alpha, G.beta, B->stream);
   }
+  // the per-step quasi-pressure of every box (default reading), per box
+  for (lbe_ctx *c : B->boxes) {
+    if (!c->args.pifield) continue;
+    StepArgs a = c->args;
+    a.pop[0] = a.pop[1] = nullptr;  // the scans read fields only
+    launch_quasipressure(a, c->qp_origin, c->qp_mode, true, c->at<double>(c->pl.off_qps),
+                         c->at<double>(c->pl.off_pi), B->stream);
+  }
   launch_batch_collide(ba, B->bp.node_blocks, B->prec, B->M, B->stream);
 }
 
@@ -1045,6 +1111,19 @@ lbe_status lbe_batch_step(lbe_batch *B, int nsteps, int mode) {
     if (c->poisoned) return fail(LBE_ERR_UNSTABLE, "box %zu is unstable; reinitialise it", b);
     if (c->next_phase != 0) return fail(LBE_ERR_STATE, "box %zu has an incomplete phased step", b);
     if (c->cur != cur) return fail(LBE_ERR_STATE, "boxes are at different buffer parities");
+  }
+  // the per-box quasi-pressure launches carry each box's route: recapture
+  // the graphs when a route changed
+  std::vector<int> routes;
+  for (size_t b = 0; b < B->boxes.size(); ++b) {
+    const lbe_ctx *c = B->boxes[b];
+    if (c->args.pifield && c->qp_origin_solid)
+      return fail(LBE_ERR_STATE, "the quasi-pressure origin of box %zu is a solid node", b);
+    routes.insert(routes.end(), {c->qp_origin[0], c->qp_origin[1], c->qp_origin[2], (int)c->qp_mode});
+  }
+  if (routes != B->routes) {
+    B->drop_graphs();
+    B->routes = routes;
   }
   lbe_status st = batch_tables(B);
   if (st != LBE_OK) return st;

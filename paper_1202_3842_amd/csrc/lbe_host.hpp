@@ -65,12 +65,14 @@ struct Plan {
   size_t off_flag = 0, off_result = 0, off_ring_ofs = 0, off_ring_off = 0, off_ring_e = 0,
          off_ball = 0, off_bb = 0, off_V = 0, off_F = 0, off_solid = 0, off_pop0 = 0,
          off_pop1 = 0, off_n = 0, off_G = 0, off_J = 0, off_force = 0, off_read = 0,
-         off_part = 0, off_att_ofs = 0, total = 0;
+         off_part = 0, off_att_ofs = 0, off_pi = 0, off_qps = 0, total = 0;
   int nblocks = 0;
 };
 
 // workspace plan of one box
 lbe_status make_plan(const lbe_config *cfg, Plan &pl);
+// whether the flags select the per-step quasi-pressure (the default reading)
+bool qp_per_step(unsigned flags);
 
 }  // namespace lbe
 
@@ -83,6 +85,11 @@ struct lbe_ctx {
   int cur = 0;             // ping-pong buffer holding the current state
   int next_phase = 0;      // lbe_step_phase position inside a step
   bool poisoned = false;
+  // route of the per-step quasi-pressure: origin, mode bits, and whether the
+  // origin is a solid node (a step then fails)
+  int qp_origin[3] = {0, 0, 0};
+  unsigned qp_mode = LBE_QP_SYMMETRIC;
+  bool qp_origin_solid = false;
   lbe::StepArgs args;
   lbe::Readout rd;
 

@@ -95,6 +95,12 @@ struct alignas(8) StepArgs {
                          // per thread), 2 32x16 (512 threads)
   Tables t;
   unsigned *errflag;     // bit 0: packing fraction >= 1 or NaN
+  // the quasi-pressure of eq. quasipressure evaluated every step (the
+  // default reading; null with LBE_PI_CARRIED or LBE_SINGLE): the path
+  // integral Phi of every species (M*N); the collision forms Pi = n - beta
+  // Phi with its own n and gives Pi to g_eq and, through the inversion, to
+  // the zeroth moment of g~
+  const double *pifield;
 };
 
 // A batch launch: every block finds its box in blockbox and its first
@@ -192,10 +198,13 @@ void launch_adj_state_grad(const Geom &g, int M, const uint32_t *bb, const doubl
 void launch_fill(double *p, long long n, double v, hipStream_t s);
 void launch_divergence(const Geom &g, const uint32_t *bb, const double *u, double kT, double *out,
                        hipStream_t s);
-// quasi-pressure: Pi of every species into phi (M*N) from the read-out
-// fields; then, per species, the zeroth-moment shift of a pulled g~ stage
-void launch_quasipressure(const StepArgs &a, const Readout &r, const int origin[3], bool fext,
-                          double *phi, hipStream_t s);
+// quasi-pressure: Pi (or, phi_only, the path integral Phi) of every species
+// into pi (M*N) from the current densities and forces (after
+// launch_forces), with 3*M*N doubles of scan scratch; mode bits
+// LBE_QP_WITH_FEXT, LBE_QP_SYMMETRIC.  Then, per species,
+// the zeroth-moment shift of a pulled g~ stage (the initialiser)
+void launch_quasipressure(const StepArgs &a, const int origin[3], unsigned mode, bool phi_only,
+                          double *scan, double *pi, hipStream_t s);
 void launch_qp_apply(const StepArgs &a, const Readout &r, const double *pi, int species, int prec,
                      void *gstage, hipStream_t s);
 constexpr int DIAG_K = 12;  // reduced quantities per block

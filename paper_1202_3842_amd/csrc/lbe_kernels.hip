@@ -791,7 +791,11 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
           vy[jn][c] += tp * ap.y - tm * am.y;
         } else {
           const double gp = G0[jn] + ap.y, gm = G0[jn] + am.y;
-          const double d = gp * npl - gm * nmi;
+          // two rounded products, then the difference (no fused multiply-add
+          // across the pair), so that a uniform state gives exactly zero
+          const double dp = gp * npl;
+          const double dm = gm * nmi;
+          const double d = dp - dm;
           mx[jn][c] += e0 * d;
           my[jn][c] += e1 * d;
           mz[jn][c] += e2 * d;
@@ -1023,6 +1027,7 @@ template <int M>
 struct NodeMoments {
   double n[M], Pi[M], J[M][3], ua[M][3], X[M][3], Y[M][3];
   double u[3];
+  double dPit[M];   // shift of the zeroth moment of g~ (per-step quasi-pressure)
 };
 
 template <int M, class A>
@@ -1050,6 +1055,16 @@ __device__ inline void invert(const A &a, const double ft[M][19], const double g
     }
     nm.n[s] = n;
     nm.Pi[s] = (euler || single) ? Pit : (printed ? Pit - 0.5 * a.beta * cu : Pit + 0.5 * a.beta * cu);
+    nm.dPit[s] = 0.0;
+    if (a.pifield && !single) {
+      // the per-step quasi-pressure Pi = n - beta Phi (this node's n): g_eq
+      // takes Pi, and g~'s zeroth moment becomes the Pi~ that the inversion
+      // maps to it
+      const double pi = n - a.beta * a.pifield[(long long)s * a.g.N + i];
+      const double target = euler ? pi : (printed ? pi + 0.5 * a.beta * cu : pi - 0.5 * a.beta * cu);
+      nm.Pi[s] = pi;
+      nm.dPit[s] = target - Pit;
+    }
     ntot += n;
     Jt0 += nm.J[s][0];
     Jt1 += nm.J[s][1];
@@ -1076,9 +1091,10 @@ template <int p>
 struct CollideP {
   template <typename T, int M, class A>
   __device__ static inline void run(const A &a, int s, const NodeMoments<M> &nm,
-                                    const double cm[3], const double ft, const double gt,
+                                    const double cm[3], const double ft, const double gt_in,
                                     T *__restrict__ fo, T *__restrict__ go) {
     const double w = wgt(p);
+    const double gt = gt_in + w * nm.dPit[s];
     const double n = nm.n[s];
     const double cJ = cdot<p>(nm.J[s]);
     const double cua = cdot<p>(nm.ua[s]);
@@ -1956,36 +1972,92 @@ __global__ __launch_bounds__(BLOCK) void k_divergence(Geom g, const uint32_t *__
 // ------------------------------------------------------------------------
 // quasi-pressure (Sec. 2, eq. quasipressure): Pi^a = n^a - beta Phi^a, Phi
 // the line integral of v^a = C^{a,mf} (+ n^a F^a) from the origin by the
-// trapezoidal rule on unit lattice steps, along x, then y, then z, never
-// across a periodic face; v = 0 on solid nodes.  One launch per axis.  A
-// workgroup holds QP_LANES lines of the axis, adjacent in memory so that the
-// walks along the lines are coalesced across lanes, and cuts each line into
-// QP_SEG segments.  With P(e) = sum_{k<e} (v(k) + v(k+1))/2 along a line,
-// Phi(e) = Phi(o) + P(e) - P(o) for the line's origin coordinate o; Phi(o)
-// comes from the previous axis (zero on the first), and the last axis
-// writes Pi itself.
-constexpr int QP_LANES = 64, QP_SEG = 16;
+// trapezoidal rule on unit lattice steps; v = 0 on solid nodes.  A path runs
+// along the three axes in turn (p0, p1, p2): along p0 to r's coordinate with
+// the other two at the origin's, then along p1 with p2 at the origin's, then
+// along p2.  Every leg is a value of one of three volume scans
+//   S_k(r) = signed trapezoidal sum along axis k from (r with k -> o_k) to r,
+// so one launch per axis computes S_k on every line of that axis, and a
+// combine pass adds, for each order, S_p0(r|p1,p2 -> o) + S_p1(r|p2 -> o) +
+// S_p2(r): the order (x, y, z) alone, or the mean over the six orders.
+//
+// The scans.  Lines along x are contiguous: one wavefront takes a row and
+// scans it 64 nodes at a time with a lane prefix sum (coalesced).  Lines
+// along y and z: a workgroup holds QP_LANES lines at adjacent x (coalesced
+// across lanes) and cuts each into QP_SEG segments; a thread keeps its
+// segment's integrand in registers (at most QP_REG nodes, longer lines take
+// a second read), and with P(e) = sum_{k<e} (v(k) + v(k+1))/2 along a line,
+// S(e) = P(e) - P(o).  blockIdx.y is the species.
+constexpr int QP_LANES = 64, QP_SEG = 16, QP_REG = 16;
 
-struct QpPass {
-  int axis;                       // 0 x, 1 y, 2 z
-  int L;                          // nodes on a line
-  int o;                          // origin coordinate along the line
+struct QpScan {
+  int axis;     // 1 y, 2 z (x has its own kernel)
+  int L;        // nodes on a line
+  int o;        // origin coordinate along the line
+  int Lu;       // lines are (u, v) = (x, z) for y, (x, y) for z, u fastest
   int nlines;
-  long long b0, lstride, estride; // node of element e of line l: b0 + l lstride + e estride
-  int first, last, fext;
+  int fext;     // add n^a F^a to the integrand
 };
 
-__device__ inline double qp_v(const StepArgs &a, const Readout &r, int s, const QpPass &q,
-                              long long i) {
+// v_k at compact node i, padded node pi: n (C^mf/n + [F + body]), 0 on solid
+// nodes
+template <class A>
+__device__ inline double qp_v(const A &a, int s, int k, bool fext, long long i, long long pi) {
   if (a.bb[i] & 1u) return 0.0;
-  const long long N = a.g.N;
-  double v = r.cmf[(3LL * s + q.axis) * N + i];
-  if (q.fext) v += r.n[(long long)s * N + i] * (a.Fext[(long long)q.axis * N + i] + a.body[s][q.axis]);
-  return v;
+  const double n = a.nfield[(long long)s * a.g.Np + pi];
+  double v = a.force[(6LL * s + k) * a.g.N + i];
+  if (fext) v += a.Fext[(long long)k * a.g.N + i] + a.body[s][k];
+  return n * v;
 }
 
-__global__ __launch_bounds__(QP_LANES *QP_SEG) void k_qp_pass(StepArgs a, Readout r, QpPass q,
-                                                              double *phi) {
+// lane prefix sum over the 64 lanes of a wavefront (inclusive)
+__device__ inline double wave_scan(double t, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double u = __shfl_up(t, d, 64);
+    if (lane >= d) t += u;
+  }
+  return t;
+}
+
+// x lines: one wavefront per row (y, z), four rows per workgroup
+__global__ __launch_bounds__(256) void k_qp_scan_x(StepArgs a, int o, int fext, double *S) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int s = blockIdx.y;
+  const Geom g = geom_of(a);
+  if (row >= g.ny * g.nz) return;  // the whole wavefront leaves together
+  const int y = row % g.ny, z = row / g.ny;
+  const long long ib = (long long)g.nx * row;
+  const long long pb = g.R + (long long)g.PX * ((y + g.R) + (long long)g.PY * (z + g.R));
+  double *out = S + 3LL * s * g.N + ib;
+  // S(e) = carry + exclusive prefix of t(e) = (v(e) + v(e+1))/2 (t = 0 at the
+  // last node); a first sweep finds S(o), a second writes S(e) - S(o)
+  double so = 0.0;
+  for (int pass = 0; pass < 2; ++pass) {
+    double carry = 0.0;
+    for (int c0 = 0; c0 < g.nx; c0 += 64) {
+      if (pass == 0 && c0 > o) break;
+      const int e = c0 + lane;
+      const double ve = e < g.nx ? qp_v(a, s, 0, fext, ib + e, pb + e) : 0.0;
+      double vn = __shfl_down(ve, 1, 64);
+      if (lane == 63) vn = e + 1 < g.nx ? qp_v(a, s, 0, fext, ib + e + 1, pb + e + 1) : 0.0;
+      const double t = e + 1 < g.nx ? 0.5 * (ve + vn) : 0.0;
+      const double incl = wave_scan(t, lane);
+      const double Se = carry + (incl - t);
+      if (pass == 0) {
+        const double cand = __shfl(Se, o - c0 < 64 ? o - c0 : 0, 64);
+        if (o - c0 < 64) so = cand;
+      } else if (e < g.nx) {
+        out[e] = Se - so;
+      }
+      carry += __shfl(incl, 63, 64);
+    }
+  }
+}
+
+// y and z lines
+__global__ __launch_bounds__(QP_LANES *QP_SEG) void k_qp_scan(StepArgs a, QpScan q, double *S) {
   __shared__ double segsum[QP_SEG][QP_LANES];
   __shared__ double porigin[QP_LANES];
   const int lane = threadIdx.x % QP_LANES, sg = threadIdx.x / QP_LANES;
@@ -1994,20 +2066,49 @@ __global__ __launch_bounds__(QP_LANES *QP_SEG) void k_qp_pass(StepArgs a, Readou
   const bool live = l < q.nlines;
   const int Ls = (q.L + QP_SEG - 1) / QP_SEG;
   const int e0 = min(sg * Ls, q.L), e1 = min(e0 + Ls, q.L);
-  const long long N = a.g.N;
-  const long long base = q.b0 + (long long)(live ? l : 0) * q.lstride;
-  double *ph = phi + (long long)s * N;
-  // Phi at the origin of the line, read before any thread of the line writes
-  const double phio = (live && !q.first) ? ph[base + (long long)q.o * q.estride] : 0.0;
+  const Geom g = geom_of(a);
+  const int u = live ? l % q.Lu : 0, w = live ? l / q.Lu : 0;
+  // element 0 of the line and the strides along it (compact and padded)
+  long long ib, pb, es, ps;
+  if (q.axis == 1) {  // (x, z) = (u, w)
+    ib = u + (long long)g.nx * g.ny * w;
+    pb = (u + g.R) + (long long)g.PX * (g.R + (long long)g.PY * (w + g.R));
+    es = g.nx;
+    ps = g.PX;
+  } else {            // (x, y) = (u, w)
+    ib = u + (long long)g.nx * w;
+    pb = (u + g.R) + (long long)g.PX * ((w + g.R) + (long long)g.PY * g.R);
+    es = (long long)g.nx * g.ny;
+    ps = (long long)g.PX * g.PY;
+  }
+  // the segment's integrand, nodes e0 .. e1 (the last one belongs to the
+  // next segment), in registers when the segment is short enough
+  double vreg[QP_REG + 1];
+  const bool inreg = e1 - e0 <= QP_REG;
+  auto v = [&](int e) { return qp_v(a, s, q.axis, q.fext, ib + e * es, pb + e * ps); };
   double run = 0.0;
   if (live && e0 < e1) {
-    double vk = qp_v(a, r, s, q, base + (long long)e0 * q.estride);
-    for (int e = e0; e < e1; ++e) {
-      if (e == q.o) porigin[lane] = run;
-      if (e + 1 < q.L) {
-        const double vn = qp_v(a, r, s, q, base + (long long)(e + 1) * q.estride);
-        run += 0.5 * (vk + vn);
-        vk = vn;
+    if (inreg) {
+#pragma unroll
+      for (int k = 0; k <= QP_REG; ++k)
+        vreg[k] = (e0 + k <= e1 && e0 + k < q.L) ? v(e0 + k) : 0.0;
+#pragma unroll
+      for (int k = 0; k < QP_REG; ++k) {
+        const int e = e0 + k;
+        if (e < e1) {
+          if (e == q.o) porigin[lane] = run;
+          if (e + 1 < q.L) run += 0.5 * (vreg[k] + vreg[k + 1]);
+        }
+      }
+    } else {
+      double vk = v(e0);
+      for (int e = e0; e < e1; ++e) {
+        if (e == q.o) porigin[lane] = run;
+        if (e + 1 < q.L) {
+          const double vn = v(e + 1);
+          run += 0.5 * (vk + vn);
+          vk = vn;
+        }
       }
     }
   }
@@ -2021,19 +2122,64 @@ __global__ __launch_bounds__(QP_LANES *QP_SEG) void k_qp_pass(StepArgs a, Readou
     if (t < so) po += segsum[t][lane];
   }
   po += porigin[lane];
+  double *out = S + (3LL * s + q.axis) * g.N;
   double run2 = off;
-  double vk = qp_v(a, r, s, q, base + (long long)e0 * q.estride);
+  if (inreg) {
+#pragma unroll
+    for (int k = 0; k < QP_REG; ++k) {
+      const int e = e0 + k;
+      if (e < e1) {
+        out[ib + e * es] = run2 - po;
+        if (e + 1 < q.L) run2 += 0.5 * (vreg[k] + vreg[k + 1]);
+      }
+    }
+    return;
+  }
+  double vk = v(e0);
   for (int e = e0; e < e1; ++e) {
-    const long long i = base + (long long)e * q.estride;
-    double val = phio + (run2 - po);
-    if (q.last) val = (a.bb[i] & 1u) ? 0.0 : r.n[(long long)s * N + i] - a.beta * val;
-    ph[i] = val;
+    out[ib + e * es] = run2 - po;
     if (e + 1 < q.L) {
-      const double vn = qp_v(a, r, s, q, base + (long long)(e + 1) * q.estride);
+      const double vn = v(e + 1);
       run2 += 0.5 * (vk + vn);
       vk = vn;
     }
   }
+}
+
+// Phi from the three scans, or (write_pi) Pi = n - beta Phi (0 on solid
+// nodes); blockIdx.y is the species.  Orders are summed as (x,y,z), (x,z,y),
+// (y,x,z), (y,z,x), (z,x,y), (z,y,x), each as (leg 0 + leg 1) + leg 2.
+__global__ __launch_bounds__(BLOCK) void k_qp_combine(StepArgs a, const double *__restrict__ S, int ox,
+                                                      int oy, int oz, int sym, int write_pi,
+                                                      double *__restrict__ pi) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  const int s = blockIdx.y;
+  const Geom g = geom_of(a);
+  if (i >= g.N) return;
+  const long long N = g.N;
+  double *out = pi + (long long)s * N;
+  if (a.bb[i] & 1u) {
+    out[i] = 0.0;
+    return;
+  }
+  const int x = i % g.nx, t = i / g.nx, y = t % g.ny, z = t / g.ny;
+  const double *Sx = S + 3LL * s * N, *Sy = Sx + N, *Sz = Sy + N;
+  auto at = [&](const double *A, int X, int Y, int Z) { return A[X + (long long)g.nx * (Y + (long long)g.ny * Z)]; };
+  double phi = (at(Sx, x, oy, oz) + at(Sy, x, y, oz)) + Sz[i];
+  if (sym) {
+    phi += (at(Sx, x, oy, oz) + at(Sz, x, oy, z)) + Sy[i];
+    phi += (at(Sy, ox, y, oz) + at(Sx, x, y, oz)) + Sz[i];
+    phi += (at(Sy, ox, y, oz) + at(Sz, ox, y, z)) + Sx[i];
+    phi += (at(Sz, ox, oy, z) + at(Sx, x, oy, z)) + Sy[i];
+    phi += (at(Sz, ox, oy, z) + at(Sy, ox, y, z)) + Sx[i];
+    phi = phi / 6.0;
+  }
+  if (!write_pi) {
+    out[i] = phi;
+    return;
+  }
+  const double n = a.nfield[(long long)s * g.Np + padded_index(g, x, y, z)];
+  out[i] = n - a.beta * phi;
 }
 
 // g~_p += w_p (Pi~ - sum_q g~_q) on the post-streaming g~ of species s, with
@@ -2704,19 +2850,19 @@ void launch_divergence(const Geom &g, const uint32_t *bb, const double *u, doubl
   hipLaunchKernelGGL(k_divergence, grid_for(g.N), dim3(BLOCK), 0, s, g, bb, u, scale, out);
 }
 
-void launch_quasipressure(const StepArgs &a, const Readout &r, const int o[3], bool fext, double *phi,
-                          hipStream_t s) {
+void launch_quasipressure(const StepArgs &a, const int o[3], unsigned mode, bool phi_only, double *scan,
+                          double *pi, hipStream_t s) {
   const Geom &g = a.g;
-  const long long plane = (long long)g.nx * g.ny;
-  const dim3 blk(QP_LANES * QP_SEG);
-  // x: the line (y0, z0); y: one line per x on the plane z0; z: one line per (x, y)
-  QpPass qx = {0, g.nx, o[0], 1, (long long)g.nx * (o[1] + (long long)g.ny * o[2]), 0, 1, 1, 0, fext};
-  QpPass qy = {1, g.ny, o[1], g.nx, plane * o[2], 1, g.nx, 0, 0, fext};
-  QpPass qz = {2, g.nz, o[2], (int)plane, 0, 1, plane, 0, 1, fext};
-  hipLaunchKernelGGL(k_qp_pass, dim3(1, a.M), blk, 0, s, a, r, qx, phi);
-  hipLaunchKernelGGL(k_qp_pass, dim3((g.nx + QP_LANES - 1) / QP_LANES, a.M), blk, 0, s, a, r, qy, phi);
-  hipLaunchKernelGGL(k_qp_pass, dim3((unsigned)((plane + QP_LANES - 1) / QP_LANES), a.M), blk, 0, s, a, r,
-                     qz, phi);
+  const int fext = (mode & LBE_QP_WITH_FEXT) ? 1 : 0;
+  const int rows = g.ny * g.nz;
+  hipLaunchKernelGGL(k_qp_scan_x, dim3((rows + 3) / 4, a.M), dim3(256), 0, s, a, o[0], fext, scan);
+  const QpScan qy = {1, g.ny, o[1], g.nx, g.nx * g.nz, fext};
+  const QpScan qz = {2, g.nz, o[2], g.nx, g.nx * g.ny, fext};
+  for (const QpScan &q : {qy, qz})
+    hipLaunchKernelGGL(k_qp_scan, dim3((q.nlines + QP_LANES - 1) / QP_LANES, a.M), dim3(QP_LANES * QP_SEG), 0,
+                       s, a, q, scan);
+  hipLaunchKernelGGL(k_qp_combine, dim3((g.N + BLOCK - 1) / BLOCK, a.M), dim3(BLOCK), 0, s, a, scan, o[0],
+                     o[1], o[2], (mode & LBE_QP_SYMMETRIC) ? 1 : 0, phi_only ? 0 : 1, pi);
 }
 
 void launch_qp_apply(const StepArgs &a, const Readout &r, const double *pi, int species, int prec,

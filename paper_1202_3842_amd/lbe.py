@@ -38,7 +38,9 @@ LBE_IDEAL = 1 << 3
 LBE_EULER = 1 << 4
 LBE_SINGLE = 1 << 5
 LBE_DRAG = 1 << 6
+LBE_PI_CARRIED = 1 << 7
 LBE_QP_WITH_FEXT = 1
+LBE_QP_SYMMETRIC = 2
 
 
 class lbe_config(C.Structure):
@@ -104,6 +106,7 @@ def lib() -> C.CDLL:
     L.lbe_get_divergence.argtypes = [P, P, C.c_int]
     L.lbe_get_quasipressure.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.c_uint, P, C.c_int]
     L.lbe_init_quasipressure.argtypes = [P, C.POINTER(C.c_int), C.c_uint]
+    L.lbe_set_quasipressure_route.argtypes = [P, C.POINTER(C.c_int), C.c_uint]
     L.lbe_diagnostics.argtypes = [P, C.POINTER(lbe_diag)]
     L.lbe_synchronize.argtypes = [P]
     L.lbe_set_force_zchunk.argtypes = [P, C.c_int]
@@ -180,6 +183,7 @@ class Box:
         self.N = nx * ny * nz
         self.M = len(sigma)
         self.prec = prec
+        self.flags = flags
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         if _member is not None:  # a member context owned by a Batch
             self.h = _member
@@ -305,7 +309,8 @@ class Box:
     def quasipressure(self, species=0, origin=None, mode=0, out=None):
         """Pi of eq. quasipressure (trapezoidal path integral from origin =
         (x, y, z), the box centre by default); mode LBE_QP_WITH_FEXT adds
-        n F to the integrand as printed."""
+        n F to the integrand as printed, LBE_QP_SYMMETRIC averages the six
+        axis orders of the path."""
         p, w, arr = self._dst(out, np.float64, self.N)
         _check(lib().lbe_get_quasipressure(self.h, int(species), self._origin(origin), int(mode), p, w))
         return arr.reshape(self.shape) if out is None else arr
@@ -314,6 +319,11 @@ class Box:
         """Set the zeroth moment of every species' g~ to the quasi-pressure
         of the current state (for a start from a non-uniform profile)."""
         _check(lib().lbe_init_quasipressure(self.h, self._origin(origin), int(mode)))
+
+    def set_quasipressure_route(self, origin=None, mode=LBE_QP_SYMMETRIC):
+        """Origin (x, y, z) and mode of the per-step quasi-pressure (the
+        default reading; see LBE_PI_CARRIED)."""
+        _check(lib().lbe_set_quasipressure_route(self.h, self._origin(origin), int(mode)))
 
     def diagnostics(self):
         d = lbe_diag()
@@ -337,7 +347,14 @@ def box_from_workload(w, prec=LBE_FP64, flags=LBE_VISC) -> Box:
         b.set_body_force(a, g)
     for a, n in enumerate(w.density):
         b.init_density(a, n)
+    _set_route(b, w, flags)
     return b
+
+
+def _set_route(b: "Box", w, flags) -> None:
+    route = getattr(w, "qp_route", None)
+    if route is not None and not (flags & LBE_SINGLE):
+        b.set_quasipressure_route(*route)
 
 
 def load_workload(b: "Box", w) -> None:
@@ -350,6 +367,7 @@ def load_workload(b: "Box", w) -> None:
         b.set_body_force(a, g)
     for a, n in enumerate(w.density):
         b.init_density(a, n)
+    _set_route(b, w, b.flags)
 
 
 class Batch:

@@ -39,6 +39,9 @@ class Workload:
     body: List[List[float]] = field(default_factory=list)
     att_eps: Optional[list] = None      # attractive tail depths (M x M), None = none
     att_rc: float = 0.0                 # its cutoff
+    # route of the per-step quasi-pressure: ((x0, y0, z0), mode bits), None =
+    # the library default (box centre, mean over the six axis orders)
+    qp_route: Optional[tuple] = None
 
     @property
     def shape(self):
@@ -125,9 +128,9 @@ def well_box(L: int, sigma: float, nsig3: float, eps_kT: float, xi: float,
 
 
 def eps_for_depth(depth_kT: float) -> float:
-    """A well "depth D kT" read as the depth of the well, U(0) = -D kT,
-    i.e. eps = D/2 in eq. (extpotential)."""
-    return 0.5 * depth_kT
+    """A well "depth D kT": eps = D in eq. (extpotential), which Sec. 4.1
+    calls the potential depth (U(0) = -2 eps)."""
+    return depth_kT
 
 
 def c1_small_well() -> Workload:
@@ -152,12 +155,16 @@ def channel(nx=256, ny=64, nz=32, x0=112, x1=144, gap=24, sigma=(4.0, 6.0),
     shape = (nz, ny, nx)
     lo = (ny - gap) // 2
     solid = bottleneck_mask(nx, ny, nz, x0, x1, lo, lo + gap)
+    # quasi-pressure path: from the centre of the gap along x (the channel
+    # axis, fluid all the way), then y, then z, so that no leg crosses the
+    # obstacle; paths that start along y or z would
     return Workload(
         name=name or f"channel{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz,
         sigma=[sA, sB], periodic=PERIODIC_XZ, steps=steps,
         density=[np.full(shape, xA * ntot), np.full(shape, (1 - xA) * ntot)],
         V=np.zeros(shape), solid=solid,
-        body=[[force, 0.0, 0.0], [force, 0.0, 0.0]])
+        body=[[force, 0.0, 0.0], [force, 0.0, 0.0]],
+        qp_route=((nx // 2, lo + gap // 2, nz // 2), 0))
 
 
 def c3_channel() -> Workload:

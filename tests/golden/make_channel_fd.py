@@ -1,19 +1,20 @@
 """Central finite differences of the channel objective with respect to V.
 
 Writes ``channel96_fd_grad.json``: dL/dV at 32 seeded fluid nodes of the
-96x32x32 two-species channel (C^mf only, derived inversions, 400 steps), each
-from two runs of the oracle with V(r_i) moved by +-h.  With ``--flags 3
---steps 40 --out channel96_visc_fd_grad.json`` the same for the scheme with
-C^visc and the printed inversions over 40 steps (the channel collapses with
-C^visc well before 400 steps); ``--flags 67 --steps 40 --att-eps 0.25
---att-rc 7 --out channel96_all_fd_grad.json`` the scheme with every force
+96x32x32 two-species channel (C^mf only, derived inversions, 400 steps, Pi
+carried by g: ``--flags 128``), each from two runs of the oracle with V(r_i)
+moved by +-h.  With ``--flags 131 --steps 40 --out
+channel96_visc_fd_grad.json`` the same for the scheme with C^visc and the
+printed inversions over 40 steps (the channel collapses with C^visc well
+before 400 steps); ``--flags 195 --steps 40 --att-eps 0.25 --att-rc 7 --out
+channel96_all_fd_grad.json`` the scheme with every force
 (C^visc, the drag and the attractive tails, printed inversions).  The objective is the
 one described in ``paper_1202_3842_amd.workloads.c5_objective``.  Only the
 oracle computes anything here; the GPU adjoint is compared with these values
 by tests/test_gpu_adjoint.py.
 
-    python tests/golden/make_channel_fd.py [--threads 8]   (about 80 min on 8 cores)
-    python tests/golden/make_channel_fd.py --flags 3 --steps 40 --out channel96_visc_fd_grad.json
+    python tests/golden/make_channel_fd.py --flags 128 [--threads 8]   (about 80 min on 8 cores)
+    python tests/golden/make_channel_fd.py --flags 131 --steps 40 --out channel96_visc_fd_grad.json
 """
 from __future__ import annotations
 
@@ -59,7 +60,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=8)
     ap.add_argument("--count", type=int, default=32)
-    ap.add_argument("--flags", type=int, default=0)
+    ap.add_argument("--flags", type=int, default=128)
     ap.add_argument("--steps", type=int, default=0, help="0: the workload's 400")
     ap.add_argument("--out", default="channel96_fd_grad.json")
     ap.add_argument("--att-eps", type=float, default=0.0, help="attractive depth for every pair, in kT")

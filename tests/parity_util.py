@@ -26,6 +26,8 @@ def oracle_from_workload(w: W.Workload, flags: int):
         o.set_body_force(a, g)
     for a, n in enumerate(w.density):
         o.init_density(a, n)
+    if getattr(w, "qp_route", None) is not None:
+        o.set_quasipressure_route(*w.qp_route)
     return o
 
 

@@ -49,20 +49,20 @@ def test_workspace_size_and_validation(L):
 
 
 def test_adjoint_workspace_and_scope(L):
-    cfg = lbe.make_config(32, 32, 32, [4.0], flags=0)
+    cfg = lbe.make_config(32, 32, 32, [4.0], flags=lbe.LBE_PI_CARRIED)
     n1 = L.lbe_adjoint_workspace_bytes(C.byref(cfg), 100, 10)
     n2 = L.lbe_adjoint_workspace_bytes(C.byref(cfg), 100, 50)
     pop = 2 * 19 * 32 ** 3 * 8
     # 11 checkpoints + 10 tape slots vs 3 checkpoints + 50 tape slots
     assert n1 >= 11 * pop and n2 > n1
-    bad = lbe.make_config(32, 32, 32, [4.0], flags=0)
+    bad = lbe.make_config(32, 32, 32, [4.0], flags=lbe.LBE_PI_CARRIED)
     assert L.lbe_adjoint_workspace_bytes(C.byref(bad), 10, 0) == 0
     assert b"segment" in L.lbe_last_error()
     # FP32 storage: checkpoints and tape states at half size, the adjoint state in FP64
-    f32 = lbe.make_config(32, 32, 32, [4.0], prec=lbe.LBE_FP32_POP, flags=0)
+    f32 = lbe.make_config(32, 32, 32, [4.0], prec=lbe.LBE_FP32_POP, flags=lbe.LBE_PI_CARRIED)
     assert 0 < L.lbe_adjoint_workspace_bytes(C.byref(f32), 100, 10) < n1
     # C^visc adds the padded J~ field to every tape slot and its adjoint fields
-    visc = lbe.make_config(32, 32, 32, [4.0], flags=lbe.LBE_VISC)
+    visc = lbe.make_config(32, 32, 32, [4.0], flags=lbe.LBE_VISC | lbe.LBE_PI_CARRIED)
     assert L.lbe_adjoint_workspace_bytes(C.byref(visc), 100, 10) > n1
     assert L.lbe_adjoint_workspace_bytes(C.byref(cfg), 0, 5) == 0
 
@@ -81,6 +81,7 @@ def test_null_handles_are_rejected_without_touching_the_device(L):
         "lbe_get_force": (None, 0, 0, None, 0), "lbe_get_populations": (None, 0, 0, None, 0),
         "lbe_set_populations": (None, 0, 0, None, 0), "lbe_get_divergence": (None, None, 0),
         "lbe_get_quasipressure": (None, 0, o3, 0, None, 0), "lbe_init_quasipressure": (None, o3, 0),
+        "lbe_set_quasipressure_route": (None, o3, 0),
         "lbe_diagnostics": (None, None), "lbe_synchronize": (None,),
         "lbe_set_force_zchunk": (None, 1), "lbe_set_force_tiling": (None, 1, 0, 0),
         "lbe_batch_step": (None, 1, 2), "lbe_adjoint_forward": (None,),
@@ -119,7 +120,7 @@ def test_attraction_configuration_is_validated(L):
         with pytest.raises(lbe.LBEError):
             lbe.workspace_bytes(cfg)
         assert word in L.lbe_last_error(), L.lbe_last_error()
-    ok = lbe.make_config(16, 16, 16, [2.0], att_eps=0.1, att_rc=5.0, flags=0)
+    ok = lbe.make_config(16, 16, 16, [2.0], att_eps=0.1, att_rc=5.0, flags=lbe.LBE_PI_CARRIED)
     assert L.lbe_adjoint_workspace_bytes(C.byref(ok), 10, 5) > 0      # the adjoint covers it
     arr = (lbe.lbe_config * 1)(ok)
     assert L.lbe_batch_workspace_bytes(arr, 1) > 0              # batches take it

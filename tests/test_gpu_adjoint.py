@@ -17,6 +17,8 @@ pytestmark = pytest.mark.gpu
 GOLDEN = Path(__file__).resolve().parent / "golden" / "channel96_fd_grad.json"
 GOLDEN_VISC = Path(__file__).resolve().parent / "golden" / "channel96_visc_fd_grad.json"
 GOLDEN_ALL = Path(__file__).resolve().parent / "golden" / "channel96_all_fd_grad.json"
+# the adjoint reverses the reading in which g carries Pi (LBE_PI_CARRIED)
+CARRIED = 1 << 7
 
 
 def reference(w, flags, T, pw):
@@ -24,7 +26,7 @@ def reference(w, flags, T, pw):
     n_t, fluid, plane = objective_terms(w)
     geo = AR.Geometry(w.nx, w.ny, w.nz, w.periodic,
                       (w.solid if w.solid is not None else np.zeros(w.shape)).astype(bool))
-    st = AR.Stepper(geo, w.sigma, w.tau, w.kT, flags, w.body, att_eps=w.att_eps, att_rc=w.att_rc)
+    st = AR.Stepper(geo, w.sigma, w.tau, w.kT, flags | CARRIED, w.body, att_eps=w.att_eps, att_rc=w.att_rc)
     V = torch.tensor(w.V.reshape(-1), requires_grad=True)
     f0, g0 = st.rest_state(np.stack(w.density))
     f0.requires_grad_(True)
@@ -44,7 +46,7 @@ def reference(w, flags, T, pw):
 
 def gpu_gradient(w, flags, T, segment, pw, prec=0):
     from paper_1202_3842_amd import lbe
-    box = lbe.box_from_workload(w, prec=prec, flags=flags)
+    box = lbe.box_from_workload(w, prec=prec, flags=(flags) | CARRIED)
     adj = lbe.Adjoint(box, T, segment)
     adj.forward()
     n_t, fluid, plane = objective_terms(w)
@@ -210,7 +212,7 @@ def test_autograd_function_matches_adjoint():
     from paper_1202_3842_amd import lbe
     w = small_channel()
     n_t, fluid, plane = objective_terms(w)
-    box = lbe.box_from_workload(w, flags=0)
+    box = lbe.box_from_workload(w, flags=(0) | CARRIED)
     adj = lbe.Adjoint(box, 5, 2)
     n0 = [torch.tensor(d, device="cuda") for d in w.density]
 
@@ -248,7 +250,7 @@ def test_channel96_gradient_against_oracle_fd(golden, steps, segment):
         w.att_rc = gold["att_rc"]
     assert gold["workload"] == w.name and gold["steps"] == w.steps
     n_t, fluid, plane = W.c5_objective(w)
-    box = lbe.box_from_workload(w, flags=gold["flags"])
+    box = lbe.box_from_workload(w, flags=(gold["flags"]) | CARRIED)
     adj = lbe.Adjoint(box, w.steps, segment)
     adj.forward()
     nA = box.density(0)
@@ -289,7 +291,7 @@ def test_adjoint_tiling_does_not_change_gradient(att, flags):
     ref = None
     for zc, order, shape in ((1, 0, 0), (3, 1, 1), (8, 2, 2), (2, 0, 1)):
         print(f"adjoint tiling att {att} flags {flags} zchunk {zc} order {order} shape {shape}", flush=True)
-        box = lbe.box_from_workload(w, flags=flags)
+        box = lbe.box_from_workload(w, flags=(flags) | CARRIED)
         box.set_force_tiling(zc, order, shape)
         adj = lbe.Adjoint(box, 4, 2)
         adj.forward()
@@ -320,7 +322,7 @@ def test_adjoint_attraction_tile_rows_agree():
     grads, dens = [], []
     for zc in (1, 4):
         print(f"adjoint attraction tile rows: zchunk {zc}", flush=True)
-        box = lbe.box_from_workload(w, flags=0)
+        box = lbe.box_from_workload(w, flags=(0) | CARRIED)
         box.set_force_tiling(zc, 1, 0)
         adj = lbe.Adjoint(box, 3, 3)
         adj.forward()
@@ -352,7 +354,7 @@ def test_adjoint_full_size_directional_derivative(att):
     T = 3
     c = W.rng(61).uniform(-1.0, 1.0, size=w.shape)
     dV = W.smooth_field(w.shape, 0.1 * W.KT, 4, 62)
-    box = lbe.box_from_workload(w, flags=flags)
+    box = lbe.box_from_workload(w, flags=(flags) | CARRIED)
     autotune.tune_zchunk(box)
     print(f"full size adjoint, tiling {getattr(box, 'tiling', None)}", flush=True)
     adj = lbe.Adjoint(box, T, T)
@@ -437,11 +439,11 @@ def test_taped_forward_equals_checkpointed(flags):
     w = small_channel()
     n_t, fluid, plane = objective_terms(w)
     T = 6
-    plain = lbe.box_from_workload(w, flags=flags)
+    plain = lbe.box_from_workload(w, flags=(flags) | CARRIED)
     plain.step(T)
     grads = []
     for seg in (T, 2):
-        box = lbe.box_from_workload(w, flags=flags)
+        box = lbe.box_from_workload(w, flags=(flags) | CARRIED)
         adj = lbe.Adjoint(box, T, seg)
         adj.forward()
         for dist in (0, 1):

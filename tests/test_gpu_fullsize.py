@@ -2,6 +2,7 @@
 configuration bench.py times (autotuned force tiling), and invariance of the
 results under every force-kernel tiling (tile shape, tile order, z depth)."""
 import os
+from pathlib import Path
 
 import numpy as np
 import pytest
@@ -27,12 +28,16 @@ def L():
     return lbe
 
 
+GOLDEN = Path(__file__).resolve().parent / "golden"
+
+
 def test_well128_full_size_bench_configuration(L):
-    """128^3, sigma = 6, n sigma^3 = 0.4, well depth 2 kT, C^visc on, printed
-    inversions: the benchmark's workload, 3 steps, tuned tiling."""
+    """128^3, sigma = 6, n sigma^3 = 0.4, well depth 2 kT, C^visc on, the
+    default scheme: the benchmark's workload, 3 steps, tuned tiling, every
+    node and population."""
     from paper_1202_3842_amd import autotune
     w = W.c2_large_well()
-    flags = L.LBE_VISC | L.LBE_PRINTED_INV
+    flags = L.LBE_VISC
     banner(f"full size {w.name}")
     o = oracle_from_workload(w, flags)
     b = L.box_from_workload(w, flags=flags)
@@ -45,6 +50,87 @@ def test_well128_full_size_bench_configuration(L):
         assert rel_err(b.populations(0, dist), o.populations(0, dist)) <= TOL
     b.close()
     o.close()
+
+
+def _compare_golden(b, g, w, prefix, label):
+    """n^a, u^a and the barycentric u of the box against a stored oracle
+    state on its plane and sampled nodes (max-norm relative error)."""
+    z = int(g["zplane"]) if "zplane" in g else w.nz // 2
+    nodes = g[f"{prefix}nodes"]
+    errs = {}
+    for a in range(w.nspecies):
+        n = b.density(a)
+        u = b.velocity(a)
+        errs[f"n{a}"] = max(rel_err(n[z], g[f"{prefix}n{a}_plane"]),
+                            rel_err(n.reshape(-1)[nodes], g[f"{prefix}n{a}_nodes"]))
+        errs[f"u{a}"] = max(rel_err(u[:, z], g[f"{prefix}u{a}_plane"]),
+                            rel_err(u.reshape(3, -1)[:, nodes], g[f"{prefix}u{a}_nodes"]))
+    ub = b.velocity(-1)
+    errs["u"] = max(rel_err(ub[:, z], g[f"{prefix}u_plane"]),
+                    rel_err(ub.reshape(3, -1)[:, nodes], g[f"{prefix}u_nodes"]))
+    print(f"[parity] {label} {errs}", flush=True)
+    for k, v in errs.items():
+        assert v <= TOL, (label, k, v)
+
+
+def test_well128_stated_2000_steps_against_oracle(L):
+    """The 128^3 well over its stated 2000 steps in the benchmark's launch
+    configuration, against the oracle's state (tests/golden/well128_2000.npz,
+    written by make_fullsize_goldens.py): the full plane z = 64 and 32768
+    seeded nodes."""
+    from paper_1202_3842_amd import autotune
+    path = GOLDEN / "well128_2000.npz"
+    if not path.exists():
+        pytest.skip("well128_2000.npz not generated")
+    g = np.load(path)
+    w = W.c2_large_well()
+    assert int(g["steps"]) == w.steps == 2000
+    banner(f"full size {w.name}, {w.steps} steps against the oracle")
+    b = L.box_from_workload(w, flags=int(g["flags"]))
+    autotune.tune_zchunk(b)
+    b.step(w.steps)
+    assert not b.diagnostics()["unstable"]
+    _compare_golden(b, g, w, "", "well128 t=2000")
+    b.close()
+
+
+def test_channel256_stated_5000_steps_against_oracle(L):
+    """The 256x64x32 two-species channel over its stated 5000 steps (C^visc
+    off: with it on the channel collapses within a few hundred steps under
+    every reading tried), against the oracle's state
+    (tests/golden/channel256_5000.npz)."""
+    path = GOLDEN / "channel256_5000.npz"
+    if not path.exists():
+        pytest.skip("channel256_5000.npz not generated")
+    g = np.load(path)
+    w = W.c3_channel()
+    assert int(g["steps"]) == w.steps == 5000
+    banner(f"full size {w.name}, {w.steps} steps against the oracle")
+    b = L.box_from_workload(w, flags=int(g["flags"]))
+    b.step(w.steps)
+    assert not b.diagnostics()["unstable"]
+    _compare_golden(b, g, w, "", "channel256 t=5000")
+    b.close()
+
+
+def test_batched_boxes_500_steps_against_oracle(L):
+    """A seeded sample of the 96-box set (boxes_500.npz: four boxes with
+    edges up to 64 that stay stable), stepped 500 times inside the whole
+    batched set (graph replay), against the oracle's states."""
+    path = GOLDEN / "boxes_500.npz"
+    if not path.exists():
+        pytest.skip("boxes_500.npz not generated")
+    g = np.load(path)
+    ws = W.c4_boxes()
+    steps = int(g["steps"])
+    banner(f"batched 96 boxes, {steps} steps, boxes {list(g['boxes'])} against the oracle")
+    batch = L.batch_from_workloads(ws, flags=int(g["flags"]))
+    batch.step(steps)
+    for k in g["boxes"]:
+        b = batch.boxes[int(k)]
+        assert not b.diagnostics()["unstable"], int(k)
+        _compare_golden(b, g, ws[int(k)], f"box{int(k)}_", f"box {int(k)} t={steps}")
+    batch.close()
 
 
 def test_channel256_full_size(L):

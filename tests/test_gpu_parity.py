@@ -35,22 +35,27 @@ def _pair(L, w, flags, prec=None):
 
 
 def test_small_well_fp64(L):
-    """32^3 periodic well, sigma = 4, n sigma^3 = 0.3 with noise, C^visc on."""
+    """32^3 periodic well, sigma = 4, n sigma^3 = 0.3 with noise, depth 1 kT,
+    C^visc on, the default scheme: its stated 50 steps, compared on the way."""
     w = W.c1_small_well()
-    banner(f"small well {w.name} fp64")
+    banner(f"small well {w.name} fp64, {w.steps} steps")
     o, b = _pair(L, w, L.LBE_VISC)
     compare_state(o, b, 1, TOL, "t=0")
-    for k in range(2):
-        o.step(5)
-        b.step(5)
-        compare_state(o, b, 1, TOL, f"t={5 * (k + 1)}")
+    t = 0
+    for k in (10, 15, 25):
+        o.step(k)
+        b.step(k)
+        t += k
+        compare_state(o, b, 1, TOL, f"t={t}")
+    assert t == w.steps
     # populations too
     for dist in (0, 1):
         assert rel_err(b.populations(0, dist), o.populations(0, dist)) <= TOL
 
 
 SWITCHES = ["none", "printed", "kappa4", "ideal", "printed_kappa4_visc",
-            "dd_eu_visc", "sd_tr_visc", "sd_eu_visc", "sd_tr_ideal", "dd_eu_printed"]
+            "dd_eu_visc", "sd_tr_visc", "sd_eu_visc", "sd_tr_ideal", "dd_eu_printed",
+            "carried_visc", "carried_printed", "carried_dd_eu"]
 
 
 @pytest.mark.parametrize("flags_name", SWITCHES)
@@ -61,7 +66,10 @@ def test_scheme_switches(L, flags_name):
              "dd_eu_visc": L.LBE_EULER | L.LBE_VISC, "sd_tr_visc": L.LBE_SINGLE | L.LBE_VISC,
              "sd_eu_visc": L.LBE_SINGLE | L.LBE_EULER | L.LBE_VISC,
              "sd_tr_ideal": L.LBE_SINGLE | L.LBE_IDEAL,
-             "dd_eu_printed": L.LBE_EULER | L.LBE_PRINTED_INV}[flags_name]
+             "dd_eu_printed": L.LBE_EULER | L.LBE_PRINTED_INV,
+             "carried_visc": L.LBE_PI_CARRIED | L.LBE_VISC,
+             "carried_printed": L.LBE_PI_CARRIED | L.LBE_VISC | L.LBE_PRINTED_INV,
+             "carried_dd_eu": L.LBE_PI_CARRIED | L.LBE_EULER | L.LBE_VISC}[flags_name]
     w = W.well_box(24, 3.0, 0.3, 0.5, 6.0, 1e-3, 5, 6)
     w.body = [[1e-4, -2e-5, 0.0]]
     banner(f"switches {flags_name}")
@@ -69,6 +77,26 @@ def test_scheme_switches(L, flags_name):
     o.step(6)
     b.step(6)
     compare_state(o, b, 1, TOL, flags_name)
+
+
+@pytest.mark.parametrize("route", [((12, 7, 3), 0), ((3, 20, 9), 2), ((0, 0, 0), 3), ((23, 23, 23), 1)])
+def test_quasipressure_routes(L, route):
+    """The per-step quasi-pressure from an off-centre origin along the x, y, z
+    path or as the six-order mean, with and without n F in the integrand:
+    a non-uniform two-species well with body forces, 6 steps."""
+    shape = (24, 24, 24)
+    w = W.Workload("route24", 24, 24, 24, [3.0, 2.0], steps=6,
+                   density=[W.noisy_uniform(shape, W.packing_density(0.12, 3.0), 2e-2, 70),
+                            W.noisy_uniform(shape, W.packing_density(0.06, 2.0), 2e-2, 71)],
+                   V=W.smooth_field(shape, 0.3 * W.KT, 3, 72), body=[[1e-4, 0, 0], [0, -5e-5, 2e-5]])
+    w.qp_route = route
+    banner(f"quasi-pressure route {route}")
+    o, b = _pair(L, w, L.LBE_VISC | L.LBE_DRAG)
+    o.step(6)
+    b.step(6)
+    compare_state(o, b, 2, TOL, f"route {route}")
+    for a in range(2):
+        assert rel_err(b.populations(a, 1), o.populations(a, 1)) <= TOL
 
 
 @pytest.mark.parametrize("variant", ["sd_tr", "dd_eu", "sd_eu", "drag", "drag_visc", "drag_sd_tr"])

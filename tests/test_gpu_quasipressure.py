@@ -53,7 +53,7 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 @pytest.mark.parametrize("case", list(CASES))
 def test_quasipressure_parity(L, case, mode):
     make, origin = CASES[case]
@@ -146,8 +146,8 @@ def test_initialiser_fp32_storage(L):
 
 
 def test_initialiser_restores_a_relaxed_slab(L):
-    """The hard-sphere slab well relaxed by the library itself (no noise,
-    1000 steps): disturbing the zeroth moment of g~ and calling the
+    """The hard-sphere slab well relaxed by the library itself under the
+    reading in which g carries Pi (no noise, 1000 steps): disturbing the zeroth moment of g~ and calling the
     initialiser gives back the relaxed g~ up to a uniform shift of Pi (the
     property the oracle is pinned to)."""
     nx, ny, nz = 32, 8, 8
@@ -155,7 +155,7 @@ def test_initialiser_restores_a_relaxed_slab(L):
     V = -0.25 * KT * np.cos(2 * math.pi * x / nx)
     bz = np.exp(-3.0 * V) / np.exp(-3.0 * V).mean()
     banner("quasipressure relaxed slab")
-    b = L.Box(nx, ny, nz, [3.0], flags=L.LBE_VISC)
+    b = L.Box(nx, ny, nz, [3.0], flags=L.LBE_VISC | L.LBE_PI_CARRIED)
     b.set_potential(np.ascontiguousarray(V))
     b.init_density(0, W.packing_density(0.1, 3.0) * bz)
     b.step(1000)
@@ -172,17 +172,17 @@ def test_initialiser_restores_a_relaxed_slab(L):
 
 
 def test_quasipressure_full_size_well128(L):
-    """128^3 benchmark well (sigma = 6, n sigma^3 = 0.4, printed inversions),
-    2 steps: Pi in both modes and g~ after the initialiser, every node."""
+    """128^3 benchmark well (sigma = 6, n sigma^3 = 0.4, the default scheme),
+    2 steps: Pi in every mode and g~ after the initialiser, every node."""
     w = W.c2_large_well()
-    flags = L.LBE_VISC | L.LBE_PRINTED_INV
+    flags = L.LBE_VISC
     origin = (64, 64, 64)
     banner(f"quasipressure full size {w.name}")
     o = oracle_from_workload(w, flags)
     b = L.box_from_workload(w, flags=flags)
     o.step(2)
     b.step(2)
-    for mode in (0, 1):
+    for mode in (0, 1, 2, 3):
         err = rel_err(b.quasipressure(0, origin, mode), o.quasipressure(0, origin, mode))
         print(f"[parity] 128^3 Pi mode {mode}: {err:.2e}", flush=True)
         assert err <= TOL
@@ -199,7 +199,7 @@ def test_argument_and_state_errors(L):
     w = _small_channel()
     b = L.box_from_workload(w, flags=L.LBE_VISC)
     banner("quasipressure errors")
-    for origin, mode in [((48, 1, 1), 0), ((5, -1, 1), 0), ((22, 0, 3), 0), ((5, 12, 3), 2)]:
+    for origin, mode in [((48, 1, 1), 0), ((5, -1, 1), 0), ((22, 0, 3), 0), ((5, 12, 3), 4)]:
         with pytest.raises(L.LBEError) as e:
             b.quasipressure(0, origin, mode)
         assert e.value.code == L.LBE_ERR_ARG
@@ -207,7 +207,7 @@ def test_argument_and_state_errors(L):
     with pytest.raises(L.LBEError) as e:
         b.init_quasipressure((5, 12, 3), 0)
     assert e.value.code == L.LBE_ERR_STATE
-    for ph in (1, 2, 3):
+    for ph in (1, 2, 3, 4):
         b.step_phase(ph)
     b.init_quasipressure((5, 12, 3), 0)
     b.close()
@@ -246,3 +246,26 @@ def test_initialiser_on_batch_members(L):
     for b in singles:
         b.close()
     batch.close()
+
+
+def test_route_errors(L):
+    """lbe_set_quasipressure_route refuses a solid origin, an origin outside
+    the box and unknown mode bits; a step refuses to run once lbe_set_solid
+    has made the origin solid, and runs again after a new route."""
+    w = _small_channel()
+    b = L.box_from_workload(w, flags=L.LBE_VISC)
+    banner("quasi-pressure route errors")
+    for origin, mode in [((22, 0, 3), 0), ((48, 1, 1), 0), ((5, 12, 3), 4)]:
+        with pytest.raises(L.LBEError) as e:
+            b.set_quasipressure_route(origin, mode)
+        assert e.value.code == L.LBE_ERR_ARG
+    b.set_quasipressure_route((5, 12, 3), 0)
+    mask = w.solid.copy()
+    mask[3, 12, 5] = 1
+    b.set_solid(mask)
+    with pytest.raises(L.LBEError) as e:
+        b.step(1)
+    assert e.value.code == L.LBE_ERR_STATE
+    b.set_quasipressure_route((6, 12, 3), 0)
+    b.step(1)
+    b.close()

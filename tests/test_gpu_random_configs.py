@@ -1,7 +1,8 @@
 """GPU parity on seeded random small configurations: odd and thin boxes,
 mixed periodicity, one to three species with unequal diameters, random
-relaxation times, solid obstacles, smooth potentials, body forces and every
-scheme switch.  Each case runs 3 steps in the library and in the FP64 oracle
+relaxation times, solid obstacles, smooth potentials, body forces, every
+scheme switch, and random routes of the per-step quasi-pressure (or the
+carried reading).  Each case runs 3 steps in the library and in the FP64 oracle
 and compares n and u of every species and the barycentric u (bar 1e-11)."""
 import math
 
@@ -65,6 +66,14 @@ def _case(L, i):
     w = W.Workload(name=f"random{i}", nx=nx, ny=ny, nz=nz, sigma=sigma, periodic=periodic, tau=tau,
                    steps=3, density=density, V=W.smooth_field(shape, 0.3 * KT, 3, 9200 + i), solid=solid,
                    body=[list(g.uniform(-2e-4, 2e-4, 3)) for _ in range(M)])
+    # the quasi-pressure: a random fluid origin and path mode, or (one case
+    # in four) the reading in which g carries Pi
+    fluid = np.flatnonzero(solid.reshape(-1) == 0) if solid is not None else np.arange(nx * ny * nz)
+    o = int(fluid[int(g.integers(0, len(fluid)))])
+    mode = int(g.choice([0, L.LBE_QP_SYMMETRIC, L.LBE_QP_SYMMETRIC | L.LBE_QP_WITH_FEXT]))
+    w.qp_route = ((o % nx, (o // nx) % ny, o // (nx * ny)), mode)
+    if g.uniform() < 0.25:
+        flags |= L.LBE_PI_CARRIED
     return w, flags
 
 
