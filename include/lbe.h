@@ -284,6 +284,20 @@ lbe_status lbe_init_quasipressure(lbe_ctx *ctx, const int origin[3], unsigned mo
  * a solid node (lbe_set_solid may make it one). */
 lbe_status lbe_set_quasipressure_route(lbe_ctx *ctx, const int origin[3], unsigned mode);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): Pi of one
+ * species as lbe_get_quasipressure computes it (same origin, mode and
+ * errors), written to the caller's DEVICE buffer out (N doubles).  Its line
+ * scans work in a scratch array that the library holds on every GPU it runs
+ * on until the process ends (64 MiB: boxes of at most 2796202 nodes; larger
+ * ones give LBE_ERR_ARG), not in the context's workspace; it calls no
+ * allocation routine.  All calls on one GPU share that GPU's array, so calls
+ * that overlap on one GPU race.  Synchronises for the read-out pass (as
+ * lbe_get_quasipressure does), then the scans run asynchronously on the
+ * context's stream. */
+lbe_status lbe_get_quasipressure_noalloc(lbe_ctx *ctx, int species, const int origin[3],
+                                         unsigned mode, double *out);
+
 /* Mass, g-momentum, spurious-current and Sec. 4.1 error measures of the
  * current state; synchronises. */
 lbe_status lbe_diagnostics(lbe_ctx *ctx, lbe_diag *out);

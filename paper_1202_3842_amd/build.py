@@ -14,7 +14,7 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "liblbe.so"
-SOURCES = ["lbe_kernels.hip", "lbe_api.hip", "lbe_adjoint.hip"]
+SOURCES = ["lbe_kernels.hip", "lbe_api.hip", "lbe_adjoint.hip", "lbe_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=on",

@@ -676,9 +676,9 @@ static lbe_status qp_args(lbe_ctx *c, const int origin[3], unsigned mode) {
   return LBE_OK;
 }
 
-// Quasi-pressure of every species at the current state into the context's
-// Pi buffer (M*N doubles), after the read-out pass.
-static lbe_status qp_prepare(lbe_ctx *c, const int origin[3], unsigned mode, double **phi) {
+// Argument checks and the read-out pass (densities, contact values and
+// forces of the current state) of the quasi-pressure calls; synchronises.
+lbe_status lbe_qp_readout_for(lbe_ctx *c, const int origin[3], unsigned mode) {
   if (c->next_phase != 0) return fail(LBE_ERR_STATE, "a phased step is incomplete");
   lbe_status st = qp_args(c, origin, mode);
   if (st != LBE_OK) return st;
@@ -686,6 +686,14 @@ static lbe_status qp_prepare(lbe_ctx *c, const int origin[3], unsigned mode, dou
   st = readout(c, &bad);
   if (st != LBE_OK) return st;
   if (bad) return fail(LBE_ERR_UNSTABLE, "packing fraction >= 1 or non-finite density");
+  return LBE_OK;
+}
+
+// Quasi-pressure of every species at the current state into the context's
+// Pi buffer (M*N doubles), after the read-out pass.
+static lbe_status qp_prepare(lbe_ctx *c, const int origin[3], unsigned mode, double **phi) {
+  lbe_status st = lbe_qp_readout_for(c, origin, mode);
+  if (st != LBE_OK) return st;
   *phi = c->at<double>(c->pl.off_pi);
   launch_quasipressure(c->args, origin, mode, false, c->at<double>(c->pl.off_qps), *phi, c->stream);
   LAUNCH_CHECK();

@@ -105,3 +105,8 @@ struct lbe_ctx {
   }
 };
 
+// Argument checks and the read-out pass of the quasi-pressure calls
+// (lbe_api.hip), shared with lbe_get_quasipressure_noalloc; not exported.
+extern "C" __attribute__((visibility("hidden"))) lbe_status lbe_qp_readout_for(lbe_ctx *c,
+                                                                              const int origin[3],
+                                                                              unsigned mode);

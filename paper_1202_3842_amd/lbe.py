@@ -107,6 +107,7 @@ def lib() -> C.CDLL:
     L.lbe_get_quasipressure.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.c_uint, P, C.c_int]
     L.lbe_init_quasipressure.argtypes = [P, C.POINTER(C.c_int), C.c_uint]
     L.lbe_set_quasipressure_route.argtypes = [P, C.POINTER(C.c_int), C.c_uint]
+    L.lbe_get_quasipressure_noalloc.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.c_uint, P]
     L.lbe_diagnostics.argtypes = [P, C.POINTER(lbe_diag)]
     L.lbe_synchronize.argtypes = [P]
     L.lbe_set_force_zchunk.argtypes = [P, C.c_int]
@@ -319,6 +320,16 @@ class Box:
         """Set the zeroth moment of every species' g~ to the quasi-pressure
         of the current state (for a start from a non-uniform profile)."""
         _check(lib().lbe_init_quasipressure(self.h, self._origin(origin), int(mode)))
+
+    def quasipressure_noalloc(self, out, species=0, origin=None, mode=0):
+        """lbe_get_quasipressure_noalloc: Pi into `out`, a float64 CUDA tensor
+        of N values (the scans use the library's static scratch)."""
+        t = self.torch
+        assert isinstance(out, t.Tensor) and out.is_cuda and out.dtype == t.float64
+        assert out.numel() == self.N and out.is_contiguous()
+        _check(lib().lbe_get_quasipressure_noalloc(self.h, int(species), self._origin(origin), int(mode),
+                                                   C.c_void_p(out.data_ptr())))
+        return out
 
     def set_quasipressure_route(self, origin=None, mode=LBE_QP_SYMMETRIC):
         """Origin (x, y, z) and mode of the per-step quasi-pressure (the

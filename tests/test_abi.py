@@ -82,6 +82,7 @@ def test_null_handles_are_rejected_without_touching_the_device(L):
         "lbe_set_populations": (None, 0, 0, None, 0), "lbe_get_divergence": (None, None, 0),
         "lbe_get_quasipressure": (None, 0, o3, 0, None, 0), "lbe_init_quasipressure": (None, o3, 0),
         "lbe_set_quasipressure_route": (None, o3, 0),
+        "lbe_get_quasipressure_noalloc": (None, 0, o3, 0, None),
         "lbe_diagnostics": (None, None), "lbe_synchronize": (None,),
         "lbe_set_force_zchunk": (None, 1), "lbe_set_force_tiling": (None, 1, 0, 0),
         "lbe_batch_step": (None, 1, 2), "lbe_adjoint_forward": (None,),
