@@ -267,8 +267,8 @@ def variants_leg(lbe, torch, w, base_flags, steps, warmup):
 
 
 def adjoint_leg(lbe, torch, W, segment=20, att=False):
-    """dL/dV on the 96x32x32 two-species channel (C^mf scheme with Pi carried
-    by g, the reading the adjoint reverses; 400 steps):
+    """dL/dV on the 96x32x32 two-species channel (C^mf scheme, the default
+    per-step quasi-pressure; 400 steps):
     the forward with a checkpoint every `segment` steps and the backward
     (segment recompute + adjoint steps) against 400 plain forward steps.
     With att, the attractive tails are on (eps = kT/4 for every pair,
@@ -280,7 +280,7 @@ def adjoint_leg(lbe, torch, W, segment=20, att=False):
         w.att_eps, w.att_rc = [[0.25 * W.KT] * w.nspecies] * w.nspecies, 8.0
     T = w.steps
     n_t, fluid, plane = W.c5_objective(w)
-    box = lbe.box_from_workload(w, flags=lbe.LBE_PI_CARRIED)
+    box = lbe.box_from_workload(w, flags=0)
     autotune.tune_zchunk(box)
     st = box.stream
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
@@ -345,7 +345,7 @@ def adjoint_leg(lbe, torch, W, segment=20, att=False):
         f"checkpointed forward {t_fwd:.1f} ms, backward {t_bwd:.1f} ms ({T} steps)")
     return {
         "workload": w.name, "steps": T, "segment": segment, "species": M, "sigma": w.sigma,
-        "scheme": "C^mf, derived inversion, Pi carried by g" + (", attraction eps = kT/4, rc = 8" if att else ""),
+        "scheme": "C^mf, derived inversion, per-step quasi-pressure" + (", attraction eps = kT/4, rc = 8" if att else ""),
         "forward_ms": round(t_plain, 3), "forward_checkpointed_ms": round(t_fwd, 3),
         "backward_ms": round(t_bwd, 3),
         "adjoint_vs_forward": round(t_bwd / t_plain, 3),
@@ -355,8 +355,8 @@ def adjoint_leg(lbe, torch, W, segment=20, att=False):
 
 
 def adjoint_box_leg(lbe, torch, W, flags, T=40, segment=40):
-    """dL/dV on the 128^3 benchmark box (C^visc on, Pi carried by g, the
-    reading the adjoint reverses), T steps in one segment (the forward records the
+    """dL/dV on the 128^3 benchmark box with its own scheme (C^visc on, the
+    default per-step quasi-pressure), T steps in one segment (the forward records the
     tape, 41 slots of about 0.27 GB, and the backward recomputes nothing):
     forward, taped forward and backward times, L = sum of n^2 at the end."""
     from paper_1202_3842_amd import autotune
@@ -394,7 +394,7 @@ def adjoint_box_leg(lbe, torch, W, flags, T=40, segment=40):
     log(f"adjoint on {w.name}: plain forward {t_plain:.1f} ms, checkpointed forward {t_fwd:.1f} ms, "
         f"backward {t_bwd:.1f} ms ({T} steps)")
     return {"workload": w.name, "steps": T, "segment": segment,
-            "scheme": "C^mf + C^visc, derived inversion, Pi carried by g",
+            "scheme": "C^mf + C^visc, derived inversion, per-step quasi-pressure",
             "forward_ms": round(t_plain, 3), "forward_checkpointed_ms": round(t_fwd, 3),
             "backward_ms": round(t_bwd, 3), "adjoint_vs_forward": round(t_bwd / t_plain, 3),
             "max_abs_dL_dV": float(out.abs().max())}
@@ -609,7 +609,7 @@ def main():
     if args.adjoint_only:
         adj = adjoint_leg(lbe, torch, W)
         adj["with_attraction"] = adjoint_leg(lbe, torch, W, att=True)
-        adj["benchmark_box"] = adjoint_box_leg(lbe, torch, W, lbe.LBE_VISC | lbe.LBE_PI_CARRIED)
+        adj["benchmark_box"] = adjoint_box_leg(lbe, torch, W, lbe.LBE_VISC)
         print(json.dumps({"adjoint": adj}), flush=True)
         return
     w = W.c2_large_well()
@@ -654,7 +654,7 @@ def main():
     if not args.no_adjoint:
         adjoint = adjoint_leg(lbe, torch, W)
         adjoint["with_attraction"] = adjoint_leg(lbe, torch, W, att=True)
-        adjoint["benchmark_box"] = adjoint_box_leg(lbe, torch, W, flags | lbe.LBE_PI_CARRIED)
+        adjoint["benchmark_box"] = adjoint_box_leg(lbe, torch, W, flags)
 
     qp = None if args.no_quasipressure else quasipressure_leg(lbe, torch, w, flags)
 

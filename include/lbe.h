@@ -356,8 +356,10 @@ void lbe_batch_destroy(lbe_batch *batch);
  * (lbe_get_momentum) and the post-streaming populations
  * (lbe_get_populations).  Supported: every force
  * (C^mf, C^visc, the attractive field, the interspecies drag), either
- * inversion and either kappa, in every scheme variant (LBE_EULER,
- * LBE_SINGLE), and either storage.  With LBE_FP32_POP the result is the
+ * inversion and either kappa, either reading of Pi (the per-step
+ * quasi-pressure, every route mode, or LBE_PI_CARRIED), in every scheme
+ * variant (LBE_EULER, LBE_SINGLE), and either storage.  With LBE_FP32_POP
+ * the result is the
  * reverse of the FP64 step along the trajectory of the stored FP32
  * populations (the rounding to storage is taken as the identity), with
  * the adjoint state in FP64.  Under LBE_SINGLE the scheme has no g, so the
@@ -368,8 +370,9 @@ void lbe_batch_destroy(lbe_batch *batch);
  * tilde moments), so device memory grows as nsteps/segment states plus
  * segment slots.  With segment >= nsteps the forward itself fills the tape
  * (nsteps + 1 slots) and the backward recomputes nothing.  The context's
- * potential, body forces and solid mask must not change between
- * lbe_adjoint_forward and lbe_adjoint_backward. */
+ * potential, body forces, solid mask and quasi-pressure route must not
+ * change between lbe_adjoint_forward and lbe_adjoint_backward: the backward
+ * then fails with LBE_ERR_STATE. */
 typedef struct lbe_adjoint lbe_adjoint;
 
 /* Device workspace of an adjoint over nsteps steps checkpointed every

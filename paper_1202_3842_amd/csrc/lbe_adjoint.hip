@@ -13,7 +13,10 @@
 // of -grad_h at the end.  When the whole horizon is one segment (segment
 // >= nsteps), the forward itself fills the tape as it steps, and the
 // backward recomputes nothing.  The read-out adjoint has a tape slot of its
-// own.
+// own.  With the per-step quasi-pressure (the default reading), each reverse
+// step also runs the transpose of the path integral after the collision's
+// adjoint.  The backward refuses to run if the context's potential, body
+// forces, solid mask or quasi-pressure route changed after the forward.
 #include <string.h>
 
 #include <algorithm>
@@ -32,18 +35,16 @@ struct AdjPlan {
   size_t off_cp = 0, off_roll = 0, off_tape = 0, off_mu = 0, off_node = 0, off_nbar = 0,
          off_phibar = 0, off_Gbar = 0, off_nbb = 0, off_Fbar = 0, off_Vbar = 0, off_stage = 0;
   size_t off_psibar = 0, off_ut = 0, off_Jnl = 0;  // with C^visc
+  size_t off_qpbar = 0, off_qpv = 0, off_qpsum = 0;  // with the per-step quasi-pressure
   // inside a tape slot
   size_t so_n = 0, so_G = 0, so_force = 0, so_PJ = 0, so_J = 0;
-  bool drag = false, visc = false;
+  bool drag = false, visc = false, qp = false;
 };
 
 lbe_status make_adj_plan(const lbe_config *cfg, int nsteps, int segment, AdjPlan &ap) {
   lbe_status st = make_plan(cfg, ap.pl);
   if (st != LBE_OK) return st;
   if (nsteps < 1 || segment < 1) return fail(LBE_ERR_ARG, "nsteps and segment must be >= 1");
-  if (qp_per_step(cfg->flags))
-    return fail(LBE_ERR_UNSUPPORTED,
-                "the adjoint covers the carried reading of Pi (LBE_PI_CARRIED) and LBE_SINGLE");
   const Plan &P = ap.pl;
   const size_t N = P.g.N, Np = P.g.Np, M = P.M, npairs = P.npairs;
   ap.T = nsteps;
@@ -83,6 +84,12 @@ lbe_status make_adj_plan(const lbe_config *cfg, int nsteps, int segment, AdjPlan
     ap.off_ut = take(sizeof(double) * 3 * M * Np);
     ap.off_Jnl = take(sizeof(double) * 3 * M * N);
   }
+  ap.qp = qp_per_step(cfg->flags);
+  if (ap.qp) {
+    ap.off_qpbar = take(sizeof(double) * M * N);
+    ap.off_qpv = take(sizeof(double) * 3 * M * N);
+    ap.off_qpsum = take(sizeof(double) * M * adj_qp_sum_doubles(P.g));
+  }
   ap.total = o;
   return LBE_OK;
 }
@@ -96,6 +103,7 @@ struct lbe_adjoint {
   int cur = 0;              // mu buffer holding the adjoint state
   bool forward_done = false, backward_done = false;
   bool taped = false;       // the forward filled the tape (one segment)
+  unsigned long long fwd_epoch = 0;  // the context's parameter epoch at the forward
 
   char *cp(int k) const { return ws + ap.off_cp + (size_t)k * ap.pl.pop_bytes; }
   char *roll(int k) const { return ws + ap.off_roll + (size_t)k * ap.pl.pop_bytes; }
@@ -128,15 +136,25 @@ struct lbe_adjoint {
       d.ut = at(ap.off_ut);
       d.Jnl = at(ap.off_Jnl);
     }
+    if (ap.qp) {
+      d.qpbar = at(ap.off_qpbar);
+      d.qpv = at(ap.off_qpv);
+      d.qpsum = at(ap.off_qpsum);
+    }
     return d;
   }
 
-  // fields of state `pop` into slot j: n (padded) and Pi~, J~, then G and C^mf/n
+  // fields of state `pop` into slot j: n (padded) and Pi~, J~, then G and
+  // C^mf/n, and the per-step quasi-pressure's path integral (into the
+  // context's buffer, which the collision of this step reads)
   void fields(int j, const void *pop) const {
     StepArgs a = slot_args(j);
     launch_tape_moments(a, c->cfg.prec, pop, slot_PJ(j), c->stream);
     launch_contact(a, c->stream);
     launch_forces(a, c->stream);
+    if (ap.qp)
+      launch_quasipressure(a, c->qp_origin, c->qp_mode, true, c->at<double>(c->pl.off_qps),
+                           c->at<double>(c->pl.off_pi), c->stream);
   }
 };
 
@@ -180,6 +198,8 @@ lbe_status lbe_adjoint_forward(lbe_adjoint *A) {
   if (c->next_phase != 0) return fail(LBE_ERR_STATE, "a phased step is incomplete");
   const AdjPlan &ap = A->ap;
   A->forward_done = A->backward_done = A->taped = false;
+  if (ap.qp && c->qp_origin_solid) return fail(LBE_ERR_STATE, "the quasi-pressure origin is a solid node");
+  A->fwd_epoch = c->epoch;
   if (ap.nseg == 1) {
     // one segment: each step's fields go to its tape slot, and the
     // collision reads them there (the kernels of lbe_step, on the tape)
@@ -210,6 +230,10 @@ lbe_status lbe_adjoint_backward(lbe_adjoint *A, const double *dL_dn, const doubl
                                 const double *dL_dpop, int where, double *dL_dV, int where_out) {
   if (!A) return fail(LBE_ERR_ARG, "null adjoint");
   if (!A->forward_done) return fail(LBE_ERR_STATE, "lbe_adjoint_forward has not run");
+  if (A->c->epoch != A->fwd_epoch)
+    return fail(LBE_ERR_STATE,
+                "the potential, a body force, the solid mask or the quasi-pressure route changed since "
+                "lbe_adjoint_forward");
   if (where != LBE_HOST && where != LBE_DEVICE) return fail(LBE_ERR_ARG, "bad 'where'");
   if (where_out != LBE_HOST && where_out != LBE_DEVICE) return fail(LBE_ERR_ARG, "bad 'where_out'");
   if (!dL_dV) return fail(LBE_ERR_ARG, "null output");
@@ -240,6 +264,7 @@ lbe_status lbe_adjoint_backward(lbe_adjoint *A, const double *dL_dn, const doubl
   {
     StepArgs a = A->slot_args(term);
     AdjArgs e = d;
+    e.qpbar = e.qpv = e.qpsum = nullptr;  // the read-out has no quasi-pressure
     e.PJ = A->slot_PJ(term);
     e.mu_out = A->mu(0);
     launch_adj_readout(a, e, s);
@@ -266,6 +291,7 @@ lbe_status lbe_adjoint_backward(lbe_adjoint *A, const double *dL_dn, const doubl
       e.mu_out = A->mu(cur ^ 1);
       const StepArgs a = A->slot_args(j);
       launch_adj_collide(a, e, s);
+      if (ap.qp) launch_adj_quasipressure(a, e, c->qp_origin, c->qp_mode, s);
       launch_adj_nonlocal(a, e, s);
       launch_adj_stream(a, e, false, s);
       cur ^= 1;

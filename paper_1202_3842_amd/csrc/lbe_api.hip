@@ -442,6 +442,7 @@ static lbe_status qp_check_origin(lbe_ctx *c, const int origin[3], bool *solid) 
 
 lbe_status lbe_set_solid(lbe_ctx *c, const uint8_t *mask, int where) {
   if (!c) return fail(LBE_ERR_ARG, "null context");
+  ++c->epoch;
   lbe_status st = copy_in(c, c->ws + c->pl.off_solid, mask, c->pl.g.N, where);
   if (st != LBE_OK) return st;
   launch_bbmask(c->pl.g, c->at<uint8_t>(c->pl.off_solid), c->at<uint32_t>(c->pl.off_bb), c->stream);
@@ -452,6 +453,7 @@ lbe_status lbe_set_solid(lbe_ctx *c, const uint8_t *mask, int where) {
 
 lbe_status lbe_set_potential(lbe_ctx *c, const double *V, int where) {
   if (!c) return fail(LBE_ERR_ARG, "null context");
+  ++c->epoch;
   lbe_status st = copy_in(c, c->ws + c->pl.off_V, V, sizeof(double) * c->pl.g.N, where);
   if (st != LBE_OK) return st;
   launch_extforce(c->pl.g, c->at<double>(c->pl.off_V), c->at<double>(c->pl.off_F), c->stream);
@@ -462,6 +464,7 @@ lbe_status lbe_set_potential(lbe_ctx *c, const double *V, int where) {
 lbe_status lbe_set_body_force(lbe_ctx *c, int species, const double gb[3]) {
   if (!c || !gb) return fail(LBE_ERR_ARG, "null argument");
   if (species < 0 || species >= c->pl.M) return fail(LBE_ERR_ARG, "bad species %d", species);
+  ++c->epoch;
   for (int k = 0; k < 3; ++k) c->args.body[species][k] = gb[k];
   return LBE_OK;
 }
@@ -708,6 +711,7 @@ lbe_status lbe_set_quasipressure_route(lbe_ctx *c, const int origin[3], unsigned
   for (int k = 0; k < 3; ++k) c->qp_origin[k] = origin[k];
   c->qp_mode = mode;
   c->qp_origin_solid = false;
+  ++c->epoch;
   return LBE_OK;
 }
 

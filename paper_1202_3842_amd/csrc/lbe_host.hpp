@@ -90,6 +90,9 @@ struct lbe_ctx {
   int qp_origin[3] = {0, 0, 0};
   unsigned qp_mode = LBE_QP_SYMMETRIC;
   bool qp_origin_solid = false;
+  // bumped whenever a parameter the adjoint's backward re-reads changes
+  // (potential, body forces, solid mask, quasi-pressure route)
+  unsigned long long epoch = 0;
   lbe::StepArgs args;
   lbe::Readout rd;
 

@@ -140,6 +140,10 @@ struct AdjArgs {
   double *psibar;          // 3M*Np padded: adjoint of the viscous force per particle C^visc_a/n_a
   double *ut;              // 3M*Np padded: u~ = J~/n of the step
   double *Jnl;             // 3M*N: the nonlocal part of the J~ adjoint
+  // with the per-step quasi-pressure (null otherwise)
+  double *qpbar;           // M*N: adjoint of the path integral Phi
+  double *qpv;             // 3M*N: adjoint of its integrand v (C^mf, + n F with LBE_QP_WITH_FEXT)
+  double *qpsum;           // nx*ny + nx*nz + ny*nz + nx + ny + nz per species: column and plane sums
 };
 
 // Launchers (lbe_kernels.hip)
@@ -192,6 +196,12 @@ void launch_adj_readout(const StepArgs &a, const AdjArgs &d, hipStream_t s);
 // dpop at the final step)
 void launch_adj_stream(const StepArgs &a, const AdjArgs &d, bool terminal, hipStream_t s);
 void launch_adj_nonlocal(const StepArgs &a, const AdjArgs &d, hipStream_t s);
+// the transpose of the per-step quasi-pressure's path integral: from
+// d.qpbar (the adjoint of Phi) to the adjoint of the integrand, added to
+// phibar, the density adjoint (d.node) and, with n F in the integrand, Fbar
+void launch_adj_quasipressure(const StepArgs &a, const AdjArgs &d, const int origin[3], unsigned mode,
+                              hipStream_t s);
+size_t adj_qp_sum_doubles(const Geom &g);
 void launch_adj_extforce(const Geom &g, const double *Fbar, double *Vbar, hipStream_t s);
 void launch_adj_state_grad(const Geom &g, int M, const uint32_t *bb, const double *mu, int species,
                            int dist, double *out, hipStream_t s);

@@ -1560,11 +1560,13 @@ __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
   const Coord c = decode(g, i);
   const bool drag = drag_on(a);
   const bool visc = d.psibar != nullptr;  // C^visc (its force per particle in slots 3..5)
+  const bool qp = d.qpbar != nullptr;  // the per-step quasi-pressure
   if (m & 1u) {
     const double z[3] = {0.0, 0.0, 0.0};
     for (int s = 0; s < M; ++s) {
       store_phibar(g, d, c, s, z);
       if (visc) store_visc_fields(g, d, c, s, z, z);
+      if (qp) d.qpbar[(long long)s * g.N + i] = 0.0;
     }
     if (drag) zero_Gbar<M>(d, g.N, i);
     return;
@@ -1633,7 +1635,21 @@ __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
     const double uau = dot3(ua[s], u);
     nbar[s] = A0 + 4.5 * (2.0 * dot3(ua[s], A2u) - dot3(u, A2u)) - 1.5 * (2.0 * uau - uu) * A0 -
               ac * bg[s].m0;
-    Pibar[s] = ac * bg[s].m0;
+    // Pi through g_eq; with the per-step quasi-pressure the zeroth moment
+    // of g~ is replaced by the target T = Pi + s beta/2 C.u^a (s = -sgn; T =
+    // Pi for Euler): T gets the (1 - a) part of the g adjoint's zeroth
+    // moment, the old zeroth moment loses it (Pibar below, added to every
+    // g~_q), and Pi = n - beta Phi passes the whole of it to n and Phi
+    double pish = ac * bg[s].m0;       // what the Pi~ <-> Pi relation sees
+    Pibar[s] = pish;
+    if (qp) {
+      const double Tb = (1.0 - ac) * bg[s].m0;
+      const double pipath = ac * bg[s].m0 + Tb;
+      Pibar[s] = -Tb;
+      pish = -Tb;
+      nbar[s] += pipath;
+      d.qpbar[(long long)s * N + i] = -a.beta * pipath;
+    }
     const double ns = n[s];
     for (int k = 0; k < 3; ++k) {
       Jbar[s][k] = 3.0 * A1[k];
@@ -1644,10 +1660,11 @@ __device__ inline void adj_collide_body(const A &a, const AdjArgs &d, int i) {
       Xbar[s][k] = 3.0 * bc * bf[s].m1[k] + 9.0 * B2ua[k] - 3.0 * B0 * ua[s][k];
       Cbar[s][k] = 4.5 * kap * D2ua[k] + (3.0 - 1.5 * kap) * D0 * ua[s][k];
       Ybar[s][k] = 3.0 * bc * bg[s].m1[k] + 9.0 * D2ua[k] - 3.0 * D0 * ua[s][k];
-      // Pi = Pi~ +- (beta/2) C.u^a (Pi = Pi~ for Euler and SD)
+      // Pi = Pi~ +- (beta/2) C.u^a (Pi = Pi~ for Euler and SD), or the
+      // shift target T = Pi -+ (beta/2) C.u^a
       if (shiftPi) {
-        Cbar[s][k] += sgn * hb * Pibar[s] * ua[s][k];
-        uabar[s][k] += sgn * hb * Pibar[s] * C[s][k];
+        Cbar[s][k] += sgn * hb * pish * ua[s][k];
+        uabar[s][k] += sgn * hb * pish * C[s][k];
       }
     }
   }
@@ -2205,6 +2222,84 @@ __global__ __launch_bounds__(BLOCK) void k_qp_apply(StepArgs a, Readout r, const
   const double d = target - sum;
 #pragma unroll
   for (int p = 0; p < Q; ++p) gst[(long long)p * Ns + i] = T(v[p] + wgt(p) * d);
+}
+
+// ------------------------------------------------------------------------
+// Transpose of the per-step quasi-pressure's path integral.  Along one line
+// with origin coordinate o, the trapezoidal leg S(e) = sum_j K(e, j) v(j)
+// (K = 1/2 at the two ends and 1 between, negative when e < o) has the
+// transpose
+//   (K^T Y)(j) = theta(j) T - P(j) - Y(j)/2,
+// with P(j) = sum_{e<j} Y(e), T the line total and theta = 1, 1/2, 0 for
+// j >, =, < o.  The volume leg of an axis order is transposed line by line;
+// the middle leg, whose value is shared along the last axis, takes column
+// sums first and writes on the plane through the origin; the first leg
+// takes plane sums and writes on the line through the origin.  One thread
+// per line; blockIdx.y is the species.
+struct QpLines {
+  int nlines, L, o, Lu;
+  long long is1, is2, ies;      // input: line l, element e at (l % Lu) is1 + (l / Lu) is2 + e ies
+  long long os1, os2, oes;      // output, likewise
+  long long isp, osp;           // species strides of input and output
+};
+
+__global__ __launch_bounds__(BLOCK) void k_adj_qp_lsum(QpLines q, const double *__restrict__ in,
+                                                        double *__restrict__ out) {
+  const int l = blockIdx.x * BLOCK + threadIdx.x;
+  if (l >= q.nlines) return;
+  const double *pin = in + blockIdx.y * q.isp + (l % q.Lu) * q.is1 + (l / q.Lu) * q.is2;
+  double t = 0.0;
+  for (int e = 0; e < q.L; ++e) t += pin[e * q.ies];
+  out[blockIdx.y * q.osp + (l % q.Lu) * q.os1 + (l / q.Lu) * q.os2] = t;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_adj_qp_tscan(QpLines q, const double *__restrict__ in, double *out,
+                                                         double coef, int acc) {
+  const int l = blockIdx.x * BLOCK + threadIdx.x;
+  if (l >= q.nlines) return;
+  const double *pin = in + blockIdx.y * q.isp + (l % q.Lu) * q.is1 + (l / q.Lu) * q.is2;
+  double *pout = out + blockIdx.y * q.osp + (l % q.Lu) * q.os1 + (l / q.Lu) * q.os2;
+  double T = 0.0;
+  for (int e = 0; e < q.L; ++e) T += pin[e * q.ies];
+  double P = 0.0;
+  for (int j = 0; j < q.L; ++j) {
+    const double Y = pin[j * q.ies];
+    const double th = j > q.o ? 1.0 : (j == q.o ? 0.5 : 0.0);
+    const double v = coef * (th * T - P - 0.5 * Y);
+    pout[j * q.oes] = acc ? pout[j * q.oes] + v : v;
+    P += Y;
+  }
+}
+
+// C^mf (or C^mf + n F) adjoint vbar into the adjoints of the per-particle
+// force (phibar = n vbar, padded with images), of n (phi.vbar, or (phi +
+// F).vbar) and of the external force (n vbar, with n F in the integrand)
+template <int M>
+__global__ __launch_bounds__(BLOCK) void k_adj_qp_apply(StepArgs a, AdjArgs d, int fext) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  const Geom g = a.g;
+  if (i >= g.N) return;
+  if (a.bb[i] & 1u) return;
+  const long long N = g.N;
+  const Coord c = decode(g, i);
+  const long long P = padded_index(g, c.x, c.y, c.z);
+  double Fb[3] = {0.0, 0.0, 0.0};
+  for (int s = 0; s < M; ++s) {
+    const double n = a.nfield[(long long)s * g.Np + P];
+    double vb[3], pb[3], nb = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      vb[k] = d.qpv[(3LL * s + k) * N + i];
+      const double phi = a.force[(6LL * s + k) * N + i];
+      const double F = fext ? a.Fext[(long long)k * N + i] + a.body[s][k] : 0.0;
+      nb += (phi + F) * vb[k];
+      pb[k] = d.phibar[(long long)(3 * s + k) * g.Np + P] + n * vb[k];
+      Fb[k] += n * vb[k];
+    }
+    store_phibar(g, d, c, s, pb);
+    d.node[(long long)s * N + i] += nb;
+  }
+  if (fext)
+    for (int k = 0; k < 3; ++k) d.Fbar[(long long)k * N + i] += Fb[k];
 }
 
 }  // namespace
@@ -2773,6 +2868,79 @@ void launch_fill(double *p, long long n, double v, hipStream_t s) {
 // nbar of the step: the transposes of the shell gathers (every directed
 // pair), of the attractive tails and of the contact values and ball averages.  The first launch that
 // reaches an output writes it, later ones accumulate.
+size_t adj_qp_sum_doubles(const Geom &g) {
+  return (size_t)g.nx * g.ny + (size_t)g.nx * g.nz + (size_t)g.ny * g.nz + g.nx + g.ny + g.nz;
+}
+
+void launch_adj_quasipressure(const StepArgs &a, const AdjArgs &d, const int o[3], unsigned mode,
+                              hipStream_t s) {
+  const Geom &g = a.g;
+  const int nx = g.nx, ny = g.ny, nz = g.nz, M = a.M;
+  const long long N = g.N, pl = (long long)nx * ny;
+  const bool sym = mode & LBE_QP_SYMMETRIC;
+  const double c6 = sym ? 1.0 / 6.0 : 1.0;
+  double *vx = d.qpv, *vy = d.qpv + N, *vz = d.qpv + 2 * N;  // species 0; species stride 3N
+  const long long vsp = 3 * N;
+  // column sums Cz(x, y), Cy(x, z), Cx(y, z), then the plane sums of each
+  // axis' line through the origin: Sx(x), Sy(y), Sz(z)
+  const long long nsum = (long long)adj_qp_sum_doubles(g);
+  double *Cz = d.qpsum, *Cy = Cz + pl, *Cx = Cy + (long long)nx * nz;
+  double *Sx = Cx + (long long)ny * nz, *Sy = Sx + nx, *Sz = Sy + ny;
+  auto launch = [&](const QpLines &q, const double *in, double *out, double coef, int acc, bool sum) {
+    const dim3 gr((q.nlines + BLOCK - 1) / BLOCK, M);
+    if (sum)
+      hipLaunchKernelGGL(k_adj_qp_lsum, gr, dim3(BLOCK), 0, s, q, in, out);
+    else
+      hipLaunchKernelGGL(k_adj_qp_tscan, gr, dim3(BLOCK), 0, s, q, in, out, coef, acc);
+  };
+  // lines over the volume along each axis
+  const QpLines Vx = {ny * nz, nx, o[0], ny * nz, nx, 0, 1, nx, 0, 1, N, vsp};
+  const QpLines Vy = {nx * nz, ny, o[1], nx, 1, pl, nx, 1, pl, nx, N, vsp};
+  const QpLines Vz = {nx * ny, nz, o[2], (int)pl, 1, 0, pl, 1, 0, pl, N, vsp};
+  // volume legs: 2/6 of every axis (the mean), or the z leg alone
+  if (sym) {
+    launch(Vx, d.qpbar, vx, 2.0 * c6, 0, false);
+    launch(Vy, d.qpbar, vy, 2.0 * c6, 0, false);
+  } else {
+    launch_fill(d.qpv, 3 * M * N, 0.0, s);
+  }
+  launch(Vz, d.qpbar, vz, 2.0 * c6 * (sym ? 1.0 : 0.5), sym ? 0 : 1, false);
+  // column sums (species stride nsum)
+  launch({nx * ny, nz, 0, (int)pl, 1, 0, pl, 1, 0, 0, N, nsum}, d.qpbar, Cz, 0.0, 0, true);
+  launch({nx * nz, ny, 0, nx, 1, pl, nx, 1, nx, 0, N, nsum}, d.qpbar, Cy, 0.0, 0, true);
+  launch({ny * nz, nx, 0, ny * nz, nx, 0, 1, 1, 0, 0, N, nsum}, d.qpbar, Cx, 0.0, 0, true);
+  // middle legs, written on the plane through the origin
+  // (x,y,z): Cz(x, y) along y (per x) -> vy on z = oz
+  launch({nx, ny, o[1], nx, 1, 0, nx, 1, 0, nx, nsum, vsp}, Cz, vy + pl * o[2], c6, 1, false);
+  if (sym) {
+    // (x,z,y): Cy(x, z) along z (per x) -> vz on y = oy
+    launch({nx, nz, o[2], nx, 1, 0, nx, 1, 0, pl, nsum, vsp}, Cy, vz + (long long)nx * o[1], c6, 1, false);
+    // (y,x,z): Cz(x, y) along x (per y) -> vx on z = oz
+    launch({ny, nx, o[0], ny, nx, 0, 1, nx, 0, 1, nsum, vsp}, Cz, vx + pl * o[2], c6, 1, false);
+    // (y,z,x): Cx(y, z) along z (per y) -> vz on x = ox
+    launch({ny, nz, o[2], ny, 1, 0, ny, nx, 0, pl, nsum, vsp}, Cx, vz + o[0], c6, 1, false);
+    // (z,x,y): Cy(x, z) along x (per z) -> vx on y = oy
+    launch({nz, nx, o[0], nz, nx, 0, 1, pl, 0, 1, nsum, vsp}, Cy, vx + (long long)nx * o[1], c6, 1, false);
+    // (z,y,x): Cx(y, z) along y (per z) -> vy on x = ox
+    launch({nz, ny, o[1], nz, ny, 0, 1, pl, 0, nx, nsum, vsp}, Cx, vy + o[0], c6, 1, false);
+  }
+  // plane sums through the origin lines: Sx(x) = sum_y Cz(x, y),
+  // Sy(y) = sum_x Cz(x, y), Sz(z) = sum_y Cx(y, z)
+  launch({nx, ny, 0, nx, 1, 0, nx, 1, 0, 0, nsum, nsum}, Cz, Sx, 0.0, 0, true);
+  launch({ny, nx, 0, ny, nx, 0, 1, 1, 0, 0, nsum, nsum}, Cz, Sy, 0.0, 0, true);
+  launch({nz, ny, 0, nz, ny, 0, 1, 1, 0, 0, nsum, nsum}, Cx, Sz, 0.0, 0, true);
+  // first legs, on the line through the origin: 2/6 per axis, or x alone
+  const long long lx = (long long)nx * (o[1] + (long long)ny * o[2]);
+  launch({1, nx, o[0], 1, 0, 0, 1, 0, 0, 1, nsum, vsp}, Sx, vx + lx, 2.0 * c6 * (sym ? 1.0 : 0.5), 1, false);
+  if (sym) {
+    const long long ly = o[0] + pl * o[2], lz = o[0] + (long long)nx * o[1];
+    launch({1, ny, o[1], 1, 0, 0, 1, 0, 0, nx, nsum, vsp}, Sy, vy + ly, 2.0 * c6, 1, false);
+    launch({1, nz, o[2], 1, 0, 0, 1, 0, 0, pl, nsum, vsp}, Sz, vz + lz, 2.0 * c6, 1, false);
+  }
+  LBE_SWITCH_M(M, hipLaunchKernelGGL(k_adj_qp_apply<MM>, grid_for(N), dim3(BLOCK), 0, s, a, d,
+                                     (mode & LBE_QP_WITH_FEXT) ? 1 : 0))
+}
+
 void launch_adj_nonlocal(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
   const long long N = a.g.N;
   const int M = a.M, npairs = M * (M + 1) / 2;

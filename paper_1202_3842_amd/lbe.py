@@ -466,6 +466,8 @@ class Adjoint:
 
     def forward(self):
         _check(lib().lbe_adjoint_forward(self.h))
+        # a token of this forward: a backward through an older one is refused
+        self.forwards = getattr(self, "forwards", 0) + 1
 
     def backward(self, dn=None, dJ=None, dpop=None, out=None):
         b = self.box
@@ -536,12 +538,16 @@ def _autograd_function():
                 b.density(a, out=n[a].view(-1))
                 b.momentum(a, out=J[a].view(-1))
             ctx.adjoint = adjoint
+            ctx.token = adjoint.forwards
             ctx.V_device = V.device
             return n, J
 
         @staticmethod
         def backward(ctx, gn, gJ):
             adj = ctx.adjoint
+            if adj.forwards != ctx.token:
+                raise RuntimeError("the Adjoint ran another forward after this one; its tape "
+                                   "belongs to the later forward")
             b = adj.box
             out = torch.empty(b.shape, dtype=torch.float64, device="cuda")
             gn = None if gn is None else gn.to(device="cuda", dtype=torch.float64).contiguous()

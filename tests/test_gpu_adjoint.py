@@ -17,7 +17,8 @@ pytestmark = pytest.mark.gpu
 GOLDEN = Path(__file__).resolve().parent / "golden" / "channel96_fd_grad.json"
 GOLDEN_VISC = Path(__file__).resolve().parent / "golden" / "channel96_visc_fd_grad.json"
 GOLDEN_ALL = Path(__file__).resolve().parent / "golden" / "channel96_all_fd_grad.json"
-# the adjoint reverses the reading in which g carries Pi (LBE_PI_CARRIED)
+# the reading in which g carries Pi (LBE_PI_CARRIED); without it the
+# quasi-pressure is evaluated every step (the default)
 CARRIED = 1 << 7
 
 
@@ -26,7 +27,9 @@ def reference(w, flags, T, pw):
     n_t, fluid, plane = objective_terms(w)
     geo = AR.Geometry(w.nx, w.ny, w.nz, w.periodic,
                       (w.solid if w.solid is not None else np.zeros(w.shape)).astype(bool))
-    st = AR.Stepper(geo, w.sigma, w.tau, w.kT, flags | CARRIED, w.body, att_eps=w.att_eps, att_rc=w.att_rc)
+    route = w.qp_route if w.qp_route is not None else (None, 2)
+    st = AR.Stepper(geo, w.sigma, w.tau, w.kT, flags, w.body, att_eps=w.att_eps, att_rc=w.att_rc,
+                    qp_origin=route[0], qp_symmetric=bool(route[1] & 2))
     V = torch.tensor(w.V.reshape(-1), requires_grad=True)
     f0, g0 = st.rest_state(np.stack(w.density))
     f0.requires_grad_(True)
@@ -46,7 +49,7 @@ def reference(w, flags, T, pw):
 
 def gpu_gradient(w, flags, T, segment, pw, prec=0):
     from paper_1202_3842_amd import lbe
-    box = lbe.box_from_workload(w, prec=prec, flags=(flags) | CARRIED)
+    box = lbe.box_from_workload(w, prec=prec, flags=flags)
     adj = lbe.Adjoint(box, T, segment)
     adj.forward()
     n_t, fluid, plane = objective_terms(w)
@@ -72,7 +75,8 @@ def assert_close(got, ref, rtol, what):
 
 
 @pytest.mark.parametrize("flags,T,segment", [
-    (0, 6, 6), (0, 6, 4), (0, 7, 1), (2, 6, 3), (4, 5, 2), (2 | 4, 5, 5)])
+    (0, 6, 6), (0, 6, 4), (0, 7, 1), (2, 6, 3), (4, 5, 2), (2 | 4, 5, 5),
+    (CARRIED, 6, 4), (CARRIED | 2, 6, 3), (CARRIED | 2 | 4, 5, 5)])
 def test_adjoint_matches_reference(flags, T, segment):
     w = small_channel()
     pw = pop_weights(w) * 1e-3
@@ -120,7 +124,7 @@ def test_adjoint_with_drag_matches_reference(flags, att, T, segment):
 
 
 @pytest.mark.parametrize("flags,T,segment", [(16, 6, 3), (16 | 2 | 64, 5, 5), (32, 6, 2),
-                                               (32 | 16, 5, 3), (32 | 64, 6, 6)])
+                                               (32 | 16, 5, 3), (32 | 64, 6, 6), (CARRIED | 16, 6, 3)])
 def test_adjoint_scheme_variants_match_reference(flags, T, segment):
     """The scheme variants of Sec. 4 on the two-species channel: DD-EU
     (flag 16; with the printed inversion and the drag too), SD-TR (32),
@@ -212,7 +216,7 @@ def test_autograd_function_matches_adjoint():
     from paper_1202_3842_amd import lbe
     w = small_channel()
     n_t, fluid, plane = objective_terms(w)
-    box = lbe.box_from_workload(w, flags=(0) | CARRIED)
+    box = lbe.box_from_workload(w, flags=0)
     adj = lbe.Adjoint(box, 5, 2)
     n0 = [torch.tensor(d, device="cuda") for d in w.density]
 
@@ -250,7 +254,7 @@ def test_channel96_gradient_against_oracle_fd(golden, steps, segment):
         w.att_rc = gold["att_rc"]
     assert gold["workload"] == w.name and gold["steps"] == w.steps
     n_t, fluid, plane = W.c5_objective(w)
-    box = lbe.box_from_workload(w, flags=(gold["flags"]) | CARRIED)
+    box = lbe.box_from_workload(w, flags=gold["flags"])
     adj = lbe.Adjoint(box, w.steps, segment)
     adj.forward()
     nA = box.density(0)
@@ -291,7 +295,7 @@ def test_adjoint_tiling_does_not_change_gradient(att, flags):
     ref = None
     for zc, order, shape in ((1, 0, 0), (3, 1, 1), (8, 2, 2), (2, 0, 1)):
         print(f"adjoint tiling att {att} flags {flags} zchunk {zc} order {order} shape {shape}", flush=True)
-        box = lbe.box_from_workload(w, flags=(flags) | CARRIED)
+        box = lbe.box_from_workload(w, flags=flags)
         box.set_force_tiling(zc, order, shape)
         adj = lbe.Adjoint(box, 4, 2)
         adj.forward()
@@ -322,7 +326,7 @@ def test_adjoint_attraction_tile_rows_agree():
     grads, dens = [], []
     for zc in (1, 4):
         print(f"adjoint attraction tile rows: zchunk {zc}", flush=True)
-        box = lbe.box_from_workload(w, flags=(0) | CARRIED)
+        box = lbe.box_from_workload(w, flags=0)
         box.set_force_tiling(zc, 1, 0)
         adj = lbe.Adjoint(box, 3, 3)
         adj.forward()
@@ -354,7 +358,7 @@ def test_adjoint_full_size_directional_derivative(att):
     T = 3
     c = W.rng(61).uniform(-1.0, 1.0, size=w.shape)
     dV = W.smooth_field(w.shape, 0.1 * W.KT, 4, 62)
-    box = lbe.box_from_workload(w, flags=(flags) | CARRIED)
+    box = lbe.box_from_workload(w, flags=flags)
     autotune.tune_zchunk(box)
     print(f"full size adjoint, tiling {getattr(box, 'tiling', None)}", flush=True)
     adj = lbe.Adjoint(box, T, T)
@@ -403,6 +407,8 @@ def test_adjoint_random_configurations(seed):
                 w.periodic &= ~(1 << k)
     T = int(g.integers(3, 7))
     seg = int(g.integers(1, T + 1))
+    if g.uniform() < 0.3:                 # the carried reading of Pi (drawn last)
+        flags |= CARRIED
     print(f"random adjoint {seed}: {w.nx}x{w.ny}x{w.nz} sigma {sig} flags {flags} att {att} T {T} "
           f"segment {seg}", flush=True)
     pw = pop_weights(w) * 1e-3
@@ -430,7 +436,7 @@ def test_adjoint_fp32_storage(flags):
     assert_close(gg, rg, 1e-5, "dL/dg0 (fp32 storage)")
 
 
-@pytest.mark.parametrize("flags", [0, 1 | 2 | 64])
+@pytest.mark.parametrize("flags", [0, 1 | 2 | 64, CARRIED])
 def test_taped_forward_equals_checkpointed(flags):
     """With one segment the forward records the tape and the backward does
     no recompute: the final state equals plain stepping and the gradient
@@ -439,11 +445,11 @@ def test_taped_forward_equals_checkpointed(flags):
     w = small_channel()
     n_t, fluid, plane = objective_terms(w)
     T = 6
-    plain = lbe.box_from_workload(w, flags=(flags) | CARRIED)
+    plain = lbe.box_from_workload(w, flags=flags)
     plain.step(T)
     grads = []
     for seg in (T, 2):
-        box = lbe.box_from_workload(w, flags=(flags) | CARRIED)
+        box = lbe.box_from_workload(w, flags=flags)
         adj = lbe.Adjoint(box, T, seg)
         adj.forward()
         for dist in (0, 1):
@@ -477,3 +483,93 @@ def test_adjoint_three_species(flags, att):
     assert_close(gV, rV, 1e-10, "dL/dV")
     assert_close(gf, rf, 1e-10, "dL/df0")
     assert_close(gg, rg, 1e-10, "dL/dg0")
+
+
+@pytest.mark.parametrize("route", [((3, 5, 2), 0), ((9, 4, 6), 2), ((6, 4, 3), 3)])
+def test_adjoint_quasipressure_routes(route):
+    """The per-step quasi-pressure from off-centre origins, along the x, y, z
+    path and as the six-order mean (with n F in the integrand too: mode 3),
+    on the two-species channel with C^visc and the drag."""
+    from oracle import autograd_ref as AR
+    w = small_channel()
+    w.qp_route = route
+    pw = pop_weights(w) * 1e-3
+    flags = 1 | 64
+    print(f"small channel quasi-pressure route {route}", flush=True)
+    if route[1] & 1:
+        # the reference integrates C^mf alone: check the library against
+        # itself along a direction instead (central difference of L)
+        from paper_1202_3842_amd import lbe
+        n_t, fluid, plane = objective_terms(w)
+        dV = W.smooth_field(w.shape, 0.05 * W.KT, 3, 91)
+        box = lbe.box_from_workload(w, flags=flags)
+        adj = lbe.Adjoint(box, 5, 2)
+        adj.forward()
+        dn = np.zeros((2,) + w.shape)
+        dn[0] = 2.0 * (box.density(0) - n_t) * fluid
+        dJ = np.zeros((2, 3) + w.shape)
+        dJ[:, 0] = plane
+        gV = adj.backward(dn, dJ, None)
+        adj.close()
+
+        def L(V):
+            lbe.load_workload(box, w)
+            box.set_potential(np.ascontiguousarray(V))
+            box.step(5)
+            return float(np.sum(((box.density(0) - n_t) ** 2)[fluid])) + sum(
+                float(np.sum(box.momentum(a)[0][plane])) for a in range(2))
+
+        h = 1e-5
+        fd = (L(w.V + h * dV) - L(w.V - h * dV)) / (2 * h)
+        ana = float(np.sum(gV * dV))
+        box.close()
+        print(f"route {route}: adjoint {ana:.10e} central difference {fd:.10e}", flush=True)
+        assert abs(ana - fd) <= 1e-7 * abs(ana)
+        return
+    rV, rf, rg = reference(w, flags, 5, pw)
+    gV, gf, gg = gpu_gradient(w, flags, 5, 2, pw)
+    assert_close(gV, rV, 1e-10, "dL/dV")
+    assert_close(gf, rf, 1e-10, "dL/df0")
+    assert_close(gg, rg, 1e-10, "dL/dg0")
+
+
+def test_backward_refuses_changed_parameters():
+    """lbe_adjoint_backward after the potential, a body force or the
+    quasi-pressure route changed since the forward: LBE_ERR_STATE; and the
+    autograd Function refuses a backward whose forward was overwritten by a
+    later one on the same Adjoint."""
+    import torch
+    from paper_1202_3842_amd import lbe
+    w = small_channel()
+    n_t, fluid, plane = objective_terms(w)
+    dn = np.zeros((2,) + w.shape)
+    for change in ("potential", "body", "route"):
+        box = lbe.box_from_workload(w, flags=0)
+        adj = lbe.Adjoint(box, 3, 3)
+        adj.forward()
+        if change == "potential":
+            box.set_potential(np.ascontiguousarray(w.V * 1.01))
+        elif change == "body":
+            box.set_body_force(0, np.array([2e-4, 0.0, 0.0]))
+        else:
+            box.set_quasipressure_route((4, 5, 3), 0)
+        with pytest.raises(lbe.LBEError) as e:
+            adj.backward(dn, None, None)
+        assert e.value.code == lbe.LBE_ERR_STATE
+        adj.close()
+        box.close()
+    box = lbe.box_from_workload(w, flags=0)
+    adj = lbe.Adjoint(box, 3, 3)
+    n0 = [torch.tensor(d, device="cuda") for d in w.density]
+
+    def reset(b):
+        for a, d in enumerate(n0):
+            b.init_density(a, d.reshape(-1))
+
+    V = torch.tensor(w.V, device="cuda", requires_grad=True)
+    n1, J1 = lbe.potential_to_state(V, adj, reset)
+    n2, J2 = lbe.potential_to_state(V * 1.0, adj, reset)
+    with pytest.raises(RuntimeError):
+        n1.sum().backward()
+    adj.close()
+    box.close()
