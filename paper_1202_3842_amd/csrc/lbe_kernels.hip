@@ -2231,11 +2231,12 @@ __global__ __launch_bounds__(BLOCK) void k_qp_apply(StepArgs a, Readout r, const
 // transpose
 //   (K^T Y)(j) = theta(j) T - P(j) - Y(j)/2,
 // with P(j) = sum_{e<j} Y(e), T the line total and theta = 1, 1/2, 0 for
-// j >, =, < o.  The volume leg of an axis order is transposed line by line;
-// the middle leg, whose value is shared along the last axis, takes column
-// sums first and writes on the plane through the origin; the first leg
-// takes plane sums and writes on the line through the origin.  One thread
-// per line; blockIdx.y is the species.
+// j >, =, < o.  The last leg of an axis order is transposed along every
+// line of its axis; the middle leg, shared along the last axis, from column
+// sums, onto the plane through the origin; the first leg from plane sums,
+// onto the line through the origin.  Each term goes to an array of its own
+// and the apply pass adds them per node (no two jobs write one element).
+// One thread per line; blockIdx.y is the species, blockIdx.z the job.
 struct QpLines {
   int nlines, L, o, Lu;
   long long is1, is2, ies;      // input: line l, element e at (l % Lu) is1 + (l / Lu) is2 + e ies
@@ -2243,52 +2244,101 @@ struct QpLines {
   long long isp, osp;           // species strides of input and output
 };
 
-__global__ __launch_bounds__(BLOCK) void k_adj_qp_lsum(QpLines q, const double *__restrict__ in,
-                                                        double *__restrict__ out) {
-  const int l = blockIdx.x * BLOCK + threadIdx.x;
-  if (l >= q.nlines) return;
-  const double *pin = in + blockIdx.y * q.isp + (l % q.Lu) * q.is1 + (l / q.Lu) * q.is2;
-  double t = 0.0;
-  for (int e = 0; e < q.L; ++e) t += pin[e * q.ies];
-  out[blockIdx.y * q.osp + (l % q.Lu) * q.os1 + (l / q.Lu) * q.os2] = t;
-}
+constexpr int QP_MAXJOBS = 9;
+struct QpJobs {
+  int njobs;
+  QpLines q[QP_MAXJOBS];
+  const double *in[QP_MAXJOBS];
+  double *out[QP_MAXJOBS];
+  double coef[QP_MAXJOBS];
+  int sum[QP_MAXJOBS];          // 1: line sums, 0: the transpose K^T
+};
 
-__global__ __launch_bounds__(BLOCK) void k_adj_qp_tscan(QpLines q, const double *__restrict__ in, double *out,
-                                                         double coef, int acc) {
+__global__ __launch_bounds__(BLOCK) void k_adj_qp_jobs(QpJobs J) {
+  const int jb = blockIdx.z;
+  const QpLines &q = J.q[jb];
   const int l = blockIdx.x * BLOCK + threadIdx.x;
   if (l >= q.nlines) return;
-  const double *pin = in + blockIdx.y * q.isp + (l % q.Lu) * q.is1 + (l / q.Lu) * q.is2;
-  double *pout = out + blockIdx.y * q.osp + (l % q.Lu) * q.os1 + (l / q.Lu) * q.os2;
+  const double *pin = J.in[jb] + blockIdx.y * q.isp + (l % q.Lu) * q.is1 + (l / q.Lu) * q.is2;
+  double *pout = J.out[jb] + blockIdx.y * q.osp + (l % q.Lu) * q.os1 + (l / q.Lu) * q.os2;
   double T = 0.0;
   for (int e = 0; e < q.L; ++e) T += pin[e * q.ies];
+  if (J.sum[jb]) {
+    *pout = T;
+    return;
+  }
+  const double c = J.coef[jb];
   double P = 0.0;
   for (int j = 0; j < q.L; ++j) {
     const double Y = pin[j * q.ies];
     const double th = j > q.o ? 1.0 : (j == q.o ? 0.5 : 0.0);
-    const double v = coef * (th * T - P - 0.5 * Y);
-    pout[j * q.oes] = acc ? pout[j * q.oes] + v : v;
+    pout[j * q.oes] = c * (th * T - P - 0.5 * Y);
     P += Y;
   }
 }
 
-// C^mf (or C^mf + n F) adjoint vbar into the adjoints of the per-particle
-// force (phibar = n vbar, padded with images), of n (phi.vbar, or (phi +
-// F).vbar) and of the external force (n vbar, with n F in the integrand)
+// Small per-species arrays of the transpose (species stride: their total):
+// column sums Cz(x,y), Cy(x,z), Cx(y,z); plane sums Sx(x), Sy(y), Sz(z);
+// middle legs on the planes through the origin, Pyz(x,y) and Pxz(x,y) on
+// z = oz, Pzy(x,z) and Pxy(x,z) on y = oy, Pzx(y,z) and Pyx(y,z) on x = ox
+// (first letter: the axis of the leg); first legs Lx(x), Ly(y), Lz(z).
+struct QpSmall {
+  long long Cz, Cy, Cx, Sx, Sy, Sz, Pyz, Pxz, Pzy, Pxy, Pzx, Pyx, Lx, Ly, Lz, total;
+};
+__host__ __device__ inline QpSmall qp_small(int nx, int ny, int nz) {
+  QpSmall o;
+  const long long xy = (long long)nx * ny, xz = (long long)nx * nz, yz = (long long)ny * nz;
+  o.Cz = 0; o.Cy = xy; o.Cx = o.Cy + xz;
+  o.Sx = o.Cx + yz; o.Sy = o.Sx + nx; o.Sz = o.Sy + ny;
+  o.Pyz = o.Sz + nz; o.Pxz = o.Pyz + xy; o.Pzy = o.Pxz + xy; o.Pxy = o.Pzy + xz;
+  o.Pzx = o.Pxy + xz; o.Pyx = o.Pzx + yz;
+  o.Lx = o.Pyx + yz; o.Ly = o.Lx + nx; o.Lz = o.Ly + ny;
+  o.total = o.Lz + nz;
+  return o;
+}
+
+// vbar = the integrand's adjoint (volume terms in qpv, plane and line terms
+// from the small arrays), into the adjoints of the per-particle force
+// (phibar = n vbar, padded with images), of n (phi.vbar, or (phi + F).vbar)
+// and of the external force (n vbar, with n F in the integrand)
 template <int M>
-__global__ __launch_bounds__(BLOCK) void k_adj_qp_apply(StepArgs a, AdjArgs d, int fext) {
+__global__ __launch_bounds__(BLOCK) void k_adj_qp_apply(StepArgs a, AdjArgs d, int ox, int oy, int oz, int sym,
+                                                       int fext) {
   const int i = blockIdx.x * BLOCK + threadIdx.x;
   const Geom g = a.g;
   if (i >= g.N) return;
   if (a.bb[i] & 1u) return;
   const long long N = g.N;
   const Coord c = decode(g, i);
-  const long long P = padded_index(g, c.x, c.y, c.z);
+  const int x = c.x, y = c.y, z = c.z, nx = g.nx, ny = g.ny;
+  const long long P = padded_index(g, x, y, z);
+  const QpSmall o = qp_small(g.nx, g.ny, g.nz);
   double Fb[3] = {0.0, 0.0, 0.0};
   for (int s = 0; s < M; ++s) {
+    const double *sm = d.qpsum + s * o.total;
+    const double *vol = d.qpv + 3LL * s * N;
+    double vb[3];
+    vb[0] = sym ? vol[i] : 0.0;
+    vb[1] = sym ? vol[N + i] : 0.0;
+    vb[2] = vol[2 * N + i];
+    if (z == oz) vb[1] += sm[o.Pyz + x + (long long)nx * y];
+    if (y == oy && z == oz) vb[0] += sm[o.Lx + x];
+    if (sym) {
+      if (z == oz) vb[0] += sm[o.Pxz + x + (long long)nx * y];
+      if (y == oy) {
+        vb[2] += sm[o.Pzy + x + (long long)nx * z];
+        vb[0] += sm[o.Pxy + x + (long long)nx * z];
+      }
+      if (x == ox) {
+        vb[2] += sm[o.Pzx + y + (long long)ny * z];
+        vb[1] += sm[o.Pyx + y + (long long)ny * z];
+      }
+      if (x == ox && z == oz) vb[1] += sm[o.Ly + y];
+      if (x == ox && y == oy) vb[2] += sm[o.Lz + z];
+    }
     const double n = a.nfield[(long long)s * g.Np + P];
-    double vb[3], pb[3], nb = 0.0;
+    double pb[3], nb = 0.0;
     for (int k = 0; k < 3; ++k) {
-      vb[k] = d.qpv[(3LL * s + k) * N + i];
       const double phi = a.force[(6LL * s + k) * N + i];
       const double F = fext ? a.Fext[(long long)k * N + i] + a.body[s][k] : 0.0;
       nb += (phi + F) * vb[k];
@@ -2868,9 +2918,7 @@ void launch_fill(double *p, long long n, double v, hipStream_t s) {
 // nbar of the step: the transposes of the shell gathers (every directed
 // pair), of the attractive tails and of the contact values and ball averages.  The first launch that
 // reaches an output writes it, later ones accumulate.
-size_t adj_qp_sum_doubles(const Geom &g) {
-  return (size_t)g.nx * g.ny + (size_t)g.nx * g.nz + (size_t)g.ny * g.nz + g.nx + g.ny + g.nz;
-}
+size_t adj_qp_sum_doubles(const Geom &g) { return (size_t)qp_small(g.nx, g.ny, g.nz).total; }
 
 void launch_adj_quasipressure(const StepArgs &a, const AdjArgs &d, const int o[3], unsigned mode,
                               hipStream_t s) {
@@ -2879,66 +2927,70 @@ void launch_adj_quasipressure(const StepArgs &a, const AdjArgs &d, const int o[3
   const long long N = g.N, pl = (long long)nx * ny;
   const bool sym = mode & LBE_QP_SYMMETRIC;
   const double c6 = sym ? 1.0 / 6.0 : 1.0;
-  double *vx = d.qpv, *vy = d.qpv + N, *vz = d.qpv + 2 * N;  // species 0; species stride 3N
-  const long long vsp = 3 * N;
-  // column sums Cz(x, y), Cy(x, z), Cx(y, z), then the plane sums of each
-  // axis' line through the origin: Sx(x), Sy(y), Sz(z)
-  const long long nsum = (long long)adj_qp_sum_doubles(g);
-  double *Cz = d.qpsum, *Cy = Cz + pl, *Cx = Cy + (long long)nx * nz;
-  double *Sx = Cx + (long long)ny * nz, *Sy = Sx + nx, *Sz = Sy + ny;
-  auto launch = [&](const QpLines &q, const double *in, double *out, double coef, int acc, bool sum) {
-    const dim3 gr((q.nlines + BLOCK - 1) / BLOCK, M);
-    if (sum)
-      hipLaunchKernelGGL(k_adj_qp_lsum, gr, dim3(BLOCK), 0, s, q, in, out);
-    else
-      hipLaunchKernelGGL(k_adj_qp_tscan, gr, dim3(BLOCK), 0, s, q, in, out, coef, acc);
+  const QpSmall q = qp_small(nx, ny, nz);
+  const long long ns = q.total, vsp = 3 * N;
+  double *sm = d.qpsum;
+  double *vx = d.qpv, *vy = d.qpv + N, *vz = d.qpv + 2 * N;
+  QpJobs J;
+  int maxl = 0;
+  auto reset = [&]() {
+    memset(&J, 0, sizeof J);
+    maxl = 0;
   };
-  // lines over the volume along each axis
-  const QpLines Vx = {ny * nz, nx, o[0], ny * nz, nx, 0, 1, nx, 0, 1, N, vsp};
-  const QpLines Vy = {nx * nz, ny, o[1], nx, 1, pl, nx, 1, pl, nx, N, vsp};
-  const QpLines Vz = {nx * ny, nz, o[2], (int)pl, 1, 0, pl, 1, 0, pl, N, vsp};
-  // volume legs: 2/6 of every axis (the mean), or the z leg alone
+  auto job = [&](const QpLines &ql, const double *in, double *out, double coef, int sum) {
+    const int k = J.njobs++;
+    J.q[k] = ql;
+    J.in[k] = in;
+    J.out[k] = out;
+    J.coef[k] = coef;
+    J.sum[k] = sum;
+    maxl = std::max(maxl, ql.nlines);
+  };
+  auto run = [&]() {
+    hipLaunchKernelGGL(k_adj_qp_jobs, dim3((maxl + BLOCK - 1) / BLOCK, M, J.njobs), dim3(BLOCK), 0, s, J);
+  };
+  // last legs along every line (2/6 of each axis, or z alone) and column sums
+  reset();
   if (sym) {
-    launch(Vx, d.qpbar, vx, 2.0 * c6, 0, false);
-    launch(Vy, d.qpbar, vy, 2.0 * c6, 0, false);
-  } else {
-    launch_fill(d.qpv, 3 * M * N, 0.0, s);
+    job({ny * nz, nx, o[0], ny * nz, nx, 0, 1, nx, 0, 1, N, vsp}, d.qpbar, vx, 2.0 * c6, 0);
+    job({nx * nz, ny, o[1], nx, 1, pl, nx, 1, pl, nx, N, vsp}, d.qpbar, vy, 2.0 * c6, 0);
   }
-  launch(Vz, d.qpbar, vz, 2.0 * c6 * (sym ? 1.0 : 0.5), sym ? 0 : 1, false);
-  // column sums (species stride nsum)
-  launch({nx * ny, nz, 0, (int)pl, 1, 0, pl, 1, 0, 0, N, nsum}, d.qpbar, Cz, 0.0, 0, true);
-  launch({nx * nz, ny, 0, nx, 1, pl, nx, 1, nx, 0, N, nsum}, d.qpbar, Cy, 0.0, 0, true);
-  launch({ny * nz, nx, 0, ny * nz, nx, 0, 1, 1, 0, 0, N, nsum}, d.qpbar, Cx, 0.0, 0, true);
-  // middle legs, written on the plane through the origin
-  // (x,y,z): Cz(x, y) along y (per x) -> vy on z = oz
-  launch({nx, ny, o[1], nx, 1, 0, nx, 1, 0, nx, nsum, vsp}, Cz, vy + pl * o[2], c6, 1, false);
+  job({nx * ny, nz, o[2], (int)pl, 1, 0, pl, 1, 0, pl, N, vsp}, d.qpbar, vz, sym ? 2.0 * c6 : 1.0, 0);
+  job({nx * ny, nz, 0, (int)pl, 1, 0, pl, 1, 0, 0, N, ns}, d.qpbar, sm + q.Cz, 0.0, 1);
+  job({nx * nz, ny, 0, nx, 1, pl, nx, 1, nx, 0, N, ns}, d.qpbar, sm + q.Cy, 0.0, 1);
+  job({ny * nz, nx, 0, ny * nz, nx, 0, 1, 1, 0, 0, N, ns}, d.qpbar, sm + q.Cx, 0.0, 1);
+  run();
+  // middle legs (from column sums) and plane sums
+  reset();
+  // (x,y,z): Cz(x, y) along y per x -> Pyz(x, y)
+  job({nx, ny, o[1], nx, 1, 0, nx, 1, 0, nx, ns, ns}, sm + q.Cz, sm + q.Pyz, c6, 0);
   if (sym) {
-    // (x,z,y): Cy(x, z) along z (per x) -> vz on y = oy
-    launch({nx, nz, o[2], nx, 1, 0, nx, 1, 0, pl, nsum, vsp}, Cy, vz + (long long)nx * o[1], c6, 1, false);
-    // (y,x,z): Cz(x, y) along x (per y) -> vx on z = oz
-    launch({ny, nx, o[0], ny, nx, 0, 1, nx, 0, 1, nsum, vsp}, Cz, vx + pl * o[2], c6, 1, false);
-    // (y,z,x): Cx(y, z) along z (per y) -> vz on x = ox
-    launch({ny, nz, o[2], ny, 1, 0, ny, nx, 0, pl, nsum, vsp}, Cx, vz + o[0], c6, 1, false);
-    // (z,x,y): Cy(x, z) along x (per z) -> vx on y = oy
-    launch({nz, nx, o[0], nz, nx, 0, 1, pl, 0, 1, nsum, vsp}, Cy, vx + (long long)nx * o[1], c6, 1, false);
-    // (z,y,x): Cx(y, z) along y (per z) -> vy on x = ox
-    launch({nz, ny, o[1], nz, ny, 0, 1, pl, 0, nx, nsum, vsp}, Cx, vy + o[0], c6, 1, false);
+    // (x,z,y): Cy(x, z) along z per x -> Pzy(x, z)
+    job({nx, nz, o[2], nx, 1, 0, nx, 1, 0, nx, ns, ns}, sm + q.Cy, sm + q.Pzy, c6, 0);
+    // (y,x,z): Cz(x, y) along x per y -> Pxz(x, y)
+    job({ny, nx, o[0], ny, nx, 0, 1, nx, 0, 1, ns, ns}, sm + q.Cz, sm + q.Pxz, c6, 0);
+    // (y,z,x): Cx(y, z) along z per y -> Pzx(y, z)
+    job({ny, nz, o[2], ny, 1, 0, ny, 1, 0, ny, ns, ns}, sm + q.Cx, sm + q.Pzx, c6, 0);
+    // (z,x,y): Cy(x, z) along x per z -> Pxy(x, z)
+    job({nz, nx, o[0], nz, nx, 0, 1, nx, 0, 1, ns, ns}, sm + q.Cy, sm + q.Pxy, c6, 0);
+    // (z,y,x): Cx(y, z) along y per z -> Pyx(y, z)
+    job({nz, ny, o[1], nz, ny, 0, 1, ny, 0, 1, ns, ns}, sm + q.Cx, sm + q.Pyx, c6, 0);
   }
-  // plane sums through the origin lines: Sx(x) = sum_y Cz(x, y),
-  // Sy(y) = sum_x Cz(x, y), Sz(z) = sum_y Cx(y, z)
-  launch({nx, ny, 0, nx, 1, 0, nx, 1, 0, 0, nsum, nsum}, Cz, Sx, 0.0, 0, true);
-  launch({ny, nx, 0, ny, nx, 0, 1, 1, 0, 0, nsum, nsum}, Cz, Sy, 0.0, 0, true);
-  launch({nz, ny, 0, nz, ny, 0, 1, 1, 0, 0, nsum, nsum}, Cx, Sz, 0.0, 0, true);
-  // first legs, on the line through the origin: 2/6 per axis, or x alone
-  const long long lx = (long long)nx * (o[1] + (long long)ny * o[2]);
-  launch({1, nx, o[0], 1, 0, 0, 1, 0, 0, 1, nsum, vsp}, Sx, vx + lx, 2.0 * c6 * (sym ? 1.0 : 0.5), 1, false);
+  // Sx(x) = sum_y Cz(x, y), Sy(y) = sum_x Cz(x, y), Sz(z) = sum_y Cx(y, z)
+  job({nx, ny, 0, nx, 1, 0, nx, 1, 0, 0, ns, ns}, sm + q.Cz, sm + q.Sx, 0.0, 1);
+  job({ny, nx, 0, ny, nx, 0, 1, 1, 0, 0, ns, ns}, sm + q.Cz, sm + q.Sy, 0.0, 1);
+  job({nz, ny, 0, nz, ny, 0, 1, 1, 0, 0, ns, ns}, sm + q.Cx, sm + q.Sz, 0.0, 1);
+  run();
+  // first legs (from plane sums): 2/6 per axis, or x alone
+  reset();
+  job({1, nx, o[0], 1, 0, 0, 1, 0, 0, 1, ns, ns}, sm + q.Sx, sm + q.Lx, sym ? 2.0 * c6 : 1.0, 0);
   if (sym) {
-    const long long ly = o[0] + pl * o[2], lz = o[0] + (long long)nx * o[1];
-    launch({1, ny, o[1], 1, 0, 0, 1, 0, 0, nx, nsum, vsp}, Sy, vy + ly, 2.0 * c6, 1, false);
-    launch({1, nz, o[2], 1, 0, 0, 1, 0, 0, pl, nsum, vsp}, Sz, vz + lz, 2.0 * c6, 1, false);
+    job({1, ny, o[1], 1, 0, 0, 1, 0, 0, 1, ns, ns}, sm + q.Sy, sm + q.Ly, 2.0 * c6, 0);
+    job({1, nz, o[2], 1, 0, 0, 1, 0, 0, 1, ns, ns}, sm + q.Sz, sm + q.Lz, 2.0 * c6, 0);
   }
-  LBE_SWITCH_M(M, hipLaunchKernelGGL(k_adj_qp_apply<MM>, grid_for(N), dim3(BLOCK), 0, s, a, d,
-                                     (mode & LBE_QP_WITH_FEXT) ? 1 : 0))
+  run();
+  LBE_SWITCH_M(M, hipLaunchKernelGGL(k_adj_qp_apply<MM>, grid_for(N), dim3(BLOCK), 0, s, a, d, o[0], o[1], o[2],
+                                     sym ? 1 : 0, (mode & LBE_QP_WITH_FEXT) ? 1 : 0))
 }
 
 void launch_adj_nonlocal(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
