@@ -820,6 +820,11 @@ struct BatchPlan {
   size_t off_args = 0, off_nodebox = 0, off_nodestart = 0, off_force = 0, off_ballbox = 0,
          off_ballstart = 0, total = 0;
   int node_blocks = 0, ball_blocks = 0;
+  // the per-step quasi-pressure (default reading): the boxes' routes and
+  // the block tables of the x, y and z scans
+  bool qp = false;
+  size_t off_qproutes = 0, off_qpbox[3] = {}, off_qpstart[3] = {};
+  int qp_blocks[3] = {};
   size_t ball_lds = 0;     // LDS bytes of the batched ball kernel
   size_t force_bytes = 0;  // reserved for the force-group tables
 };
@@ -875,6 +880,16 @@ lbe_status make_batch_plan(const lbe_config *cfgs, int nboxes, BatchPlan &bp) {
   bp.off_nodestart = take(sizeof(int) * nboxes);
   bp.off_ballbox = take(sizeof(int) * bp.ball_blocks);
   bp.off_ballstart = take(sizeof(int) * nboxes);
+  bp.qp = qp_per_step(cfgs[0].flags);
+  if (bp.qp) {
+    bp.off_qproutes = take(sizeof(QpRoute) * nboxes);
+    for (int k = 0; k < 3; ++k) {
+      bp.qp_blocks[k] = 0;
+      for (const Plan &p : plans) bp.qp_blocks[k] += qp_blocks(p.g, k);
+      bp.off_qpbox[k] = take(sizeof(int) * bp.qp_blocks[k]);
+      bp.off_qpstart[k] = take(sizeof(int) * nboxes);
+    }
+  }
   // block tables of the force groups, then of the attraction groups, per
   // directed species pair
   const size_t M = (size_t)cfgs[0].nspecies;
@@ -907,7 +922,7 @@ struct lbe_batch {
   std::vector<Group> groups, att_groups;
   std::vector<int> zchunks;          // the zchunk of each box the tables were built for
   std::vector<StepArgs> uploaded;    // the parameter blocks last copied to the device
-  std::vector<int> routes;           // the quasi-pressure routes the graphs were captured with
+  std::vector<QpRoute> routes;       // the quasi-pressure routes last copied to the device
   hipGraphExec_t graph[2] = {nullptr, nullptr};
 
   void drop_graphs() {
@@ -1002,6 +1017,29 @@ lbe_status batch_upload(lbe_batch *B) {
   return LBE_OK;
 }
 
+// copy the boxes' quasi-pressure routes to the device when they changed
+// (the batched scans read them at run time: no new graph is needed)
+lbe_status batch_upload_routes(lbe_batch *B) {
+  if (!B->bp.qp) return LBE_OK;
+  const int n = (int)B->boxes.size();
+  std::vector<QpRoute> now(n);
+  for (int b = 0; b < n; ++b) {
+    lbe_ctx *c = B->boxes[b];
+    QpRoute &r = now[b];
+    r.scan = c->at<double>(c->pl.off_qps);
+    for (int k = 0; k < 3; ++k) r.o[k] = c->qp_origin[k];
+    r.sym = (c->qp_mode & LBE_QP_SYMMETRIC) ? 1 : 0;
+    r.fext = (c->qp_mode & LBE_QP_WITH_FEXT) ? 1 : 0;
+  }
+  if (B->routes.size() == now.size() && memcmp(B->routes.data(), now.data(), sizeof(QpRoute) * n) == 0)
+    return LBE_OK;
+  HIP_TRY(hipMemcpyAsync(B->ws + B->bp.off_qproutes, now.data(), sizeof(QpRoute) * n, hipMemcpyHostToDevice,
+                         B->stream));
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  B->routes = now;
+  return LBE_OK;
+}
+
 void batch_launch_step(lbe_batch *B, int cur) {
   BatchArgs ba;
   ba.boxes = (const StepArgs *)(B->ws + B->bp.off_args);
@@ -1029,13 +1067,16 @@ void batch_launch_step(lbe_batch *B, int cur) {
     bf.blockstart = G.blockstart;
     launch_batch_att(bf, G.nblocks, G.R, G.alpha, G.beta, B->stream);
   }
-  // the per-step quasi-pressure of every box (default reading), per box
-  for (lbe_ctx *c : B->boxes) {
-    if (!c->args.pifield) continue;
-    StepArgs a = c->args;
-    a.pop[0] = a.pop[1] = nullptr;  // the scans read fields only
-    launch_quasipressure(a, c->qp_origin, c->qp_mode, true, c->at<double>(c->pl.off_qps),
-                         c->at<double>(c->pl.off_pi), B->stream);
+  // the per-step quasi-pressure of every box (default reading)
+  if (B->bp.qp) {
+    QpBatchTables t;
+    for (int k = 0; k < 3; ++k) {
+      t.box[k] = (const int *)(B->ws + B->bp.off_qpbox[k]);
+      t.start[k] = (const int *)(B->ws + B->bp.off_qpstart[k]);
+      t.nblocks[k] = B->bp.qp_blocks[k];
+    }
+    launch_batch_quasipressure(ba, B->bp.node_blocks, (const QpRoute *)(B->ws + B->bp.off_qproutes), t, B->M,
+                               B->stream);
   }
   launch_batch_collide(ba, B->bp.node_blocks, B->prec, B->M, B->stream);
 }
@@ -1084,7 +1125,21 @@ lbe_status lbe_batch_create(const lbe_config *cfgs, int nboxes, void *ws, size_t
     ballstart[b] = (int)ballbox.size();
     ballbox.insert(ballbox.end(), ball_blocks(c->pl.g, BATCH_BALL_ZC), b);
   }
-  if (hipMemcpy(B->ws + bp.off_nodebox, nodebox.data(), sizeof(int) * nodebox.size(),
+  bool up_ok = true;
+  if (bp.qp)
+    for (int k = 0; k < 3 && up_ok; ++k) {
+      std::vector<int> qbox, qstart(nboxes);
+      for (int b = 0; b < nboxes; ++b) {
+        qstart[b] = (int)qbox.size();
+        qbox.insert(qbox.end(), qp_blocks(B->boxes[b]->pl.g, k), b);
+      }
+      up_ok = hipMemcpy(B->ws + bp.off_qpbox[k], qbox.data(), sizeof(int) * qbox.size(),
+                        hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(B->ws + bp.off_qpstart[k], qstart.data(), sizeof(int) * nboxes,
+                        hipMemcpyHostToDevice) == hipSuccess;
+    }
+  if (!up_ok ||
+      hipMemcpy(B->ws + bp.off_nodebox, nodebox.data(), sizeof(int) * nodebox.size(),
                 hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(B->ws + bp.off_nodestart, nodestart.data(), sizeof(int) * nboxes,
                 hipMemcpyHostToDevice) != hipSuccess ||
@@ -1124,22 +1179,16 @@ lbe_status lbe_batch_step(lbe_batch *B, int nsteps, int mode) {
     if (c->next_phase != 0) return fail(LBE_ERR_STATE, "box %zu has an incomplete phased step", b);
     if (c->cur != cur) return fail(LBE_ERR_STATE, "boxes are at different buffer parities");
   }
-  // the per-box quasi-pressure launches carry each box's route: recapture
-  // the graphs when a route changed
-  std::vector<int> routes;
   for (size_t b = 0; b < B->boxes.size(); ++b) {
     const lbe_ctx *c = B->boxes[b];
     if (c->args.pifield && c->qp_origin_solid)
       return fail(LBE_ERR_STATE, "the quasi-pressure origin of box %zu is a solid node", b);
-    routes.insert(routes.end(), {c->qp_origin[0], c->qp_origin[1], c->qp_origin[2], (int)c->qp_mode});
-  }
-  if (routes != B->routes) {
-    B->drop_graphs();
-    B->routes = routes;
   }
   lbe_status st = batch_tables(B);
   if (st != LBE_OK) return st;
   st = batch_upload(B);
+  if (st != LBE_OK) return st;
+  st = batch_upload_routes(B);
   if (st != LBE_OK) return st;
   int left = nsteps;
   if (mode == 2) {

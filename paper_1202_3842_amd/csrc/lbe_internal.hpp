@@ -112,6 +112,16 @@ struct BatchArgs {
   int cur;
 };
 
+// The quasi-pressure route of one batched box (read by the batched scans at
+// run time, so a changed route needs no new graph): the origin, the mode
+// bits as booleans, and the box's scan scratch (3*M*N doubles).  Phi goes
+// to the box's StepArgs::pifield.
+struct QpRoute {
+  double *scan;
+  int o[3];
+  int sym, fext;
+};
+
 // Per-node outputs of the read-out pass (component-major, N each):
 //   ua[M][3], u[3], cmf[M][3], cvisc[M][3], n[M], Jt_sum[3], J_sum[3], J[M][3]
 struct Readout {
@@ -217,6 +227,16 @@ void launch_quasipressure(const StepArgs &a, const int origin[3], unsigned mode,
                           double *scan, double *pi, hipStream_t s);
 void launch_qp_apply(const StepArgs &a, const Readout &r, const double *pi, int species, int prec,
                      void *gstage, hipStream_t s);
+// the path integral Phi of every box of a batch, into each box's pifield:
+// the x, y and z scans take the tables of their own block counts
+// (qp_blocks), the combine pass the node tables (node_blocks)
+struct QpBatchTables {
+  const int *box[3], *start[3];
+  int nblocks[3];
+};
+int qp_blocks(const Geom &g, int axis);
+void launch_batch_quasipressure(const BatchArgs &nodes, int node_nblocks, const QpRoute *routes,
+                                const QpBatchTables &t, int M, hipStream_t s);
 constexpr int DIAG_K = 12;  // reduced quantities per block
 
 }  // namespace lbe

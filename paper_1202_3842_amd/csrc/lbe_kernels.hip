@@ -2037,11 +2037,12 @@ __device__ inline double wave_scan(double t, int lane) {
   return t;
 }
 
-// x lines: one wavefront per row (y, z), four rows per workgroup
-__global__ __launch_bounds__(256) void k_qp_scan_x(StepArgs a, int o, int fext, double *S) {
+// x lines: one wavefront per row (y, z), four rows per workgroup (block
+// blk of the box), species s
+template <class A>
+__device__ inline void qp_scan_x_body(const A &a, int o, int fext, double *S, int blk, int s) {
   const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int s = blockIdx.y;
+  const int row = blk * 4 + (threadIdx.x >> 6);
   const Geom g = geom_of(a);
   if (row >= g.ny * g.nz) return;  // the whole wavefront leaves together
   const int y = row % g.ny, z = row / g.ny;
@@ -2073,13 +2074,23 @@ __global__ __launch_bounds__(256) void k_qp_scan_x(StepArgs a, int o, int fext, 
   }
 }
 
-// y and z lines
-__global__ __launch_bounds__(QP_LANES *QP_SEG) void k_qp_scan(StepArgs a, QpScan q, double *S) {
+__global__ __launch_bounds__(256) void k_qp_scan_x(StepArgs a, int o, int fext, double *S) {
+  qp_scan_x_body(a, o, fext, S, blockIdx.x, blockIdx.y);
+}
+
+// the y (axis 1) or z (axis 2) lines of a box
+__host__ __device__ inline QpScan qp_scan_of(const Geom &g, int axis, int o, int fext) {
+  if (axis == 1) return {1, g.ny, o, g.nx, g.nx * g.nz, fext};
+  return {2, g.nz, o, g.nx, g.nx * g.ny, fext};
+}
+
+// y and z lines: block blk of the box, species s
+template <class A>
+__device__ inline void qp_scan_body(const A &a, const QpScan &q, double *S, int blk, int s) {
   __shared__ double segsum[QP_SEG][QP_LANES];
   __shared__ double porigin[QP_LANES];
   const int lane = threadIdx.x % QP_LANES, sg = threadIdx.x / QP_LANES;
-  const int s = blockIdx.y;
-  const int l = blockIdx.x * QP_LANES + lane;
+  const int l = blk * QP_LANES + lane;
   const bool live = l < q.nlines;
   const int Ls = (q.L + QP_SEG - 1) / QP_SEG;
   const int e0 = min(sg * Ls, q.L), e1 = min(e0 + Ls, q.L);
@@ -2163,14 +2174,17 @@ __global__ __launch_bounds__(QP_LANES *QP_SEG) void k_qp_scan(StepArgs a, QpScan
   }
 }
 
+__global__ __launch_bounds__(QP_LANES *QP_SEG) void k_qp_scan(StepArgs a, QpScan q, double *S) {
+  qp_scan_body(a, q, S, blockIdx.x, blockIdx.y);
+}
+
 // Phi from the three scans, or (write_pi) Pi = n - beta Phi (0 on solid
-// nodes); blockIdx.y is the species.  Orders are summed as (x,y,z), (x,z,y),
-// (y,x,z), (y,z,x), (z,x,y), (z,y,x), each as (leg 0 + leg 1) + leg 2.
-__global__ __launch_bounds__(BLOCK) void k_qp_combine(StepArgs a, const double *__restrict__ S, int ox,
-                                                      int oy, int oz, int sym, int write_pi,
-                                                      double *__restrict__ pi) {
-  const int i = blockIdx.x * BLOCK + threadIdx.x;
-  const int s = blockIdx.y;
+// nodes); node i of the box, species s.  Orders are summed as (x,y,z),
+// (x,z,y), (y,x,z), (y,z,x), (z,x,y), (z,y,x), each as (leg 0 + leg 1) +
+// leg 2.
+template <class Args>
+__device__ inline void qp_combine_body(const Args &a, const double *__restrict__ S, int ox, int oy, int oz,
+                                       int sym, int write_pi, double *__restrict__ pi, int i, int s) {
   const Geom g = geom_of(a);
   if (i >= g.N) return;
   const long long N = g.N;
@@ -2197,6 +2211,38 @@ __global__ __launch_bounds__(BLOCK) void k_qp_combine(StepArgs a, const double *
   }
   const double n = a.nfield[(long long)s * g.Np + padded_index(g, x, y, z)];
   out[i] = n - a.beta * phi;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_qp_combine(StepArgs a, const double *__restrict__ S, int ox,
+                                                      int oy, int oz, int sym, int write_pi,
+                                                      double *__restrict__ pi) {
+  qp_combine_body(a, S, ox, oy, oz, sym, write_pi, pi, blockIdx.x * BLOCK + threadIdx.x, blockIdx.y);
+}
+
+// The path integral of every box of a batch, one launch per phase: each
+// block finds its box in the phase's block table, and the box's route in
+// routes[box]; Phi goes to the box's pifield.
+__global__ __launch_bounds__(256) void kb_qp_scan_x(BatchArgs ba, const QpRoute *routes) {
+  const int b = cptr(ba.blockbox)[blockIdx.x];
+  const auto &a = *cptr(ba.boxes + b);
+  const auto &r = *cptr(routes + b);
+  qp_scan_x_body(a, r.o[0], r.fext, r.scan, blockIdx.x - cptr(ba.blockstart)[b], blockIdx.y);
+}
+
+__global__ __launch_bounds__(QP_LANES *QP_SEG) void kb_qp_scan(BatchArgs ba, const QpRoute *routes, int axis) {
+  const int b = cptr(ba.blockbox)[blockIdx.x];
+  const auto &a = *cptr(ba.boxes + b);
+  const auto &r = *cptr(routes + b);
+  const QpScan q = qp_scan_of(geom_of(a), axis, r.o[axis], r.fext);
+  qp_scan_body(a, q, r.scan, blockIdx.x - cptr(ba.blockstart)[b], blockIdx.y);
+}
+
+__global__ __launch_bounds__(BLOCK) void kb_qp_combine(BatchArgs ba, const QpRoute *routes) {
+  const int b = cptr(ba.blockbox)[blockIdx.x];
+  const auto &a = *cptr(ba.boxes + b);
+  const auto &r = *cptr(routes + b);
+  const int i = (blockIdx.x - cptr(ba.blockstart)[b]) * BLOCK + threadIdx.x;
+  qp_combine_body(a, r.scan, r.o[0], r.o[1], r.o[2], r.sym, 0, const_cast<double *>(a.pifield), i, blockIdx.y);
 }
 
 // g~_p += w_p (Pi~ - sum_q g~_q) on the post-streaming g~ of species s, with
@@ -3076,13 +3122,32 @@ void launch_quasipressure(const StepArgs &a, const int o[3], unsigned mode, bool
   const int fext = (mode & LBE_QP_WITH_FEXT) ? 1 : 0;
   const int rows = g.ny * g.nz;
   hipLaunchKernelGGL(k_qp_scan_x, dim3((rows + 3) / 4, a.M), dim3(256), 0, s, a, o[0], fext, scan);
-  const QpScan qy = {1, g.ny, o[1], g.nx, g.nx * g.nz, fext};
-  const QpScan qz = {2, g.nz, o[2], g.nx, g.nx * g.ny, fext};
+  const QpScan qy = qp_scan_of(g, 1, o[1], fext);
+  const QpScan qz = qp_scan_of(g, 2, o[2], fext);
   for (const QpScan &q : {qy, qz})
     hipLaunchKernelGGL(k_qp_scan, dim3((q.nlines + QP_LANES - 1) / QP_LANES, a.M), dim3(QP_LANES * QP_SEG), 0,
                        s, a, q, scan);
   hipLaunchKernelGGL(k_qp_combine, dim3((g.N + BLOCK - 1) / BLOCK, a.M), dim3(BLOCK), 0, s, a, scan, o[0],
                      o[1], o[2], (mode & LBE_QP_SYMMETRIC) ? 1 : 0, phi_only ? 0 : 1, pi);
+}
+
+int qp_blocks(const Geom &g, int axis) {
+  if (axis == 0) return (g.ny * g.nz + 3) / 4;
+  return (qp_scan_of(g, axis, 0, 0).nlines + QP_LANES - 1) / QP_LANES;
+}
+
+void launch_batch_quasipressure(const BatchArgs &nodes, int node_nblocks, const QpRoute *routes,
+                                const QpBatchTables &t, int M, hipStream_t s) {
+  BatchArgs b = nodes;
+  b.blockbox = t.box[0];
+  b.blockstart = t.start[0];
+  hipLaunchKernelGGL(kb_qp_scan_x, dim3(t.nblocks[0], M), dim3(256), 0, s, b, routes);
+  for (int axis = 1; axis <= 2; ++axis) {
+    b.blockbox = t.box[axis];
+    b.blockstart = t.start[axis];
+    hipLaunchKernelGGL(kb_qp_scan, dim3(t.nblocks[axis], M), dim3(QP_LANES * QP_SEG), 0, s, b, routes, axis);
+  }
+  hipLaunchKernelGGL(kb_qp_combine, dim3(node_nblocks, M), dim3(BLOCK), 0, s, nodes, routes);
 }
 
 void launch_qp_apply(const StepArgs &a, const Readout &r, const double *pi, int species, int prec,

@@ -146,3 +146,36 @@ def test_batched_three_species(L):
     for b in singles:
         b.close()
     batch.close()
+
+
+def test_batched_quasipressure_routes(L):
+    """The batched path integral (one launch per scan for every box) reads
+    each box's route at run time: boxes with their own origins and modes,
+    and a route changed between graph replays, give bitwise the boxes
+    stepped alone with the same routes."""
+    ws = _boxes()[:4]
+    obst = W.well_box(22, 3.0, 0.25, 0.5, 5.5, 1e-3, 777, 9, name="obstacle22")
+    obst.solid = np.zeros(obst.shape, dtype=bool)
+    obst.solid[5:10, 9:13, 8:12] = True               # (z, y, x): a block inside the box
+    ws.append(obst)
+    routes = [((2, 3, 5), 0), ((29, 0, 11), L.LBE_QP_SYMMETRIC), ((8, 8, 8), 1 | L.LBE_QP_SYMMETRIC),
+              ((0, 39, 1), 1), ((20, 10, 6), L.LBE_QP_SYMMETRIC)]
+    banner("batched quasi-pressure routes")
+    batch = L.batch_from_workloads(ws, flags=L.LBE_VISC)
+    singles = [L.box_from_workload(w, flags=L.LBE_VISC) for w in ws]
+    for bx, (o, m) in zip(batch.boxes + singles, routes + routes):
+        bx.set_quasipressure_route(o, m)
+    batch.step(4, mode=2)
+    for b in singles:
+        b.step(4)
+    batch.boxes[2].set_quasipressure_route((1, 2, 3), 0)
+    singles[2].set_quasipressure_route((1, 2, 3), 0)
+    batch.step(5, mode=2)
+    for b in singles:
+        b.step(5)
+    for i, (bb, bs) in enumerate(zip(batch.boxes, singles)):
+        for dist in (0, 1):
+            assert np.array_equal(bb.populations(0, dist), bs.populations(0, dist)), (i, dist)
+    for b in singles:
+        b.close()
+    batch.close()
