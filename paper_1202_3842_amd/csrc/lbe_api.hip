@@ -829,13 +829,16 @@ struct BatchPlan {
   size_t force_bytes = 0;  // reserved for the force-group tables
 };
 
-// force-group tables are sized for the smallest zchunk (1), so that any
-// later zchunk choice fits
+// force-group tables (per directed pair: every box in one group of its
+// reach and tile shape) are sized for the smallest zchunk (1) and the
+// lowest tile (8 rows), so that any later tiling fits: the block entries
+// once, plus per possible group (RING_MAX reaches x 3 shapes) its rounding
+// and its start table
 size_t force_table_bytes(const std::vector<Plan> &plans) {
   size_t blocks = 0;
   for (const Plan &p : plans) blocks += force_blocks(p.g, 1);
-  return align256(sizeof(int) * blocks) * 1 + align256(sizeof(int) * plans.size()) * (RING_MAX + 1) +
-         align256(sizeof(int) * blocks) * RING_MAX;
+  const size_t groups = 3 * RING_MAX;
+  return align256(sizeof(int) * blocks) + groups * (256 + align256(sizeof(int) * plans.size()));
 }
 
 lbe_status make_batch_plan(const lbe_config *cfgs, int nboxes, BatchPlan &bp) {
@@ -916,11 +919,11 @@ struct lbe_batch {
   bool currents = false;             // the moments keep J~ (C^visc or the drag)
   bool ideal = false;                // no nonlocal forces: no force groups
   struct Group {
-    int R, nblocks, entries, alpha, beta;
+    int R, shape, nblocks, entries, alpha, beta;
     int *blockbox, *blockstart;
   };
   std::vector<Group> groups, att_groups;
-  std::vector<int> zchunks;          // the zchunk of each box the tables were built for
+  std::vector<int> zchunks, shapes;  // each box's zchunk and tile shape the tables were built for
   std::vector<StepArgs> uploaded;    // the parameter blocks last copied to the device
   std::vector<QpRoute> routes;       // the quasi-pressure routes last copied to the device
   hipGraphExec_t graph[2] = {nullptr, nullptr};
@@ -939,55 +942,67 @@ namespace {
 // (re)build the force-group block tables if any box's zchunk changed
 lbe_status batch_tables(lbe_batch *B) {
   int n = (int)B->boxes.size();
-  bool same = (int)B->zchunks.size() == n;
-  for (int b = 0; same && b < n; ++b) same = B->zchunks[b] == B->boxes[b]->args.zchunk;
+  bool same = (int)B->zchunks.size() == n && (int)B->shapes.size() == n;
+  for (int b = 0; same && b < n; ++b)
+    same = B->zchunks[b] == B->boxes[b]->args.zchunk && B->shapes[b] == B->boxes[b]->args.rows;
   if (same) return LBE_OK;
+  // steps already queued on the batch stream read the current tables and
+  // graphs: let them finish before either is replaced (the table uploads
+  // below are blocking copies, which do not wait for a non-blocking stream)
+  HIP_TRY(hipStreamSynchronize(B->stream));
   B->drop_graphs();
   B->groups.clear();
   B->att_groups.clear();
   B->zchunks.assign(n, 0);
+  B->shapes.assign(n, 0);
   char *base = B->ws + B->bp.off_force;
   size_t used = 0;
   int maxR = 0, maxent = 0;
-  // one group per directed species pair (alpha, beta) and reach R: the boxes
-  // whose pair reaches R nodes (its shell, or with att its attractive
-  // tail), in the order alpha, beta, R, so that for every box the pairs of
-  // one species follow each other as in a single box
+  // one group per directed species pair (alpha, beta), reach R and (for
+  // the shell gathers) tile shape: the boxes whose pair reaches R nodes (its
+  // shell, or with att its attractive tail) and that were tuned to that
+  // shape, in the order alpha, beta, R, shape, so that for every box the
+  // pairs of one species follow each other as in a single box (each box is
+  // in exactly one group per pair)
   auto build = [&](bool att, std::vector<lbe_batch::Group> &out) -> lbe_status {
     for (int al = 0; al < B->M; ++al)
       for (int be = 0; be < B->M; ++be) {
         const int k = pair_index(B->M, al, be);
-        for (int R = 1; R <= RING_MAX; ++R) {
-          std::vector<int> box_of_block, start(n, 0);
-          int ent = 0;
-          for (int b = 0; b < n; ++b) {
-            const StepArgs &a = B->boxes[b]->args;
-            if ((att ? a.t.att_R[k] : a.t.pair_R[k]) != R) continue;
-            start[b] = (int)box_of_block.size();
-            box_of_block.insert(box_of_block.end(), force_blocks(a.g, a.zchunk), b);
-            if (!att) ent = std::max(ent, a.t.pair_nent[k]);
+        for (int R = 1; R <= RING_MAX; ++R)
+          for (int shape = 0; shape < (att ? 1 : 3); ++shape) {
+            std::vector<int> box_of_block, start(n, 0);
+            int ent = 0;
+            for (int b = 0; b < n; ++b) {
+              const StepArgs &a = B->boxes[b]->args;
+              if ((att ? a.t.att_R[k] : a.t.pair_R[k]) != R) continue;
+              if (!att && a.rows != shape) continue;
+              start[b] = (int)box_of_block.size();
+              box_of_block.insert(box_of_block.end(),
+                                  force_blocks(a.g, a.zchunk, att ? FORCE_TY : force_tile_rows(shape)), b);
+              if (!att) ent = std::max(ent, a.t.pair_nent[k]);
+            }
+            if (box_of_block.empty()) continue;
+            lbe_batch::Group G;
+            G.R = R;
+            G.shape = shape;
+            G.nblocks = (int)box_of_block.size();
+            G.entries = ent;
+            G.alpha = al;
+            G.beta = be;
+            G.blockbox = (int *)(base + used);
+            used += align256(sizeof(int) * box_of_block.size());
+            G.blockstart = (int *)(base + used);
+            used += align256(sizeof(int) * n);
+            if (used > B->bp.force_bytes) return fail(LBE_ERR_OOM, "force tables exceed their reservation");
+            HIP_TRY(hipMemcpy(G.blockbox, box_of_block.data(), sizeof(int) * box_of_block.size(),
+                              hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(G.blockstart, start.data(), sizeof(int) * n, hipMemcpyHostToDevice));
+            out.push_back(G);
+            if (!att) {
+              maxR = std::max(maxR, R);
+              maxent = std::max(maxent, ent);
+            }
           }
-          if (box_of_block.empty()) continue;
-          lbe_batch::Group G;
-          G.R = R;
-          G.nblocks = (int)box_of_block.size();
-          G.entries = ent;
-          G.alpha = al;
-          G.beta = be;
-          G.blockbox = (int *)(base + used);
-          used += align256(sizeof(int) * box_of_block.size());
-          G.blockstart = (int *)(base + used);
-          used += align256(sizeof(int) * n);
-          if (used > B->bp.force_bytes) return fail(LBE_ERR_OOM, "force tables exceed their reservation");
-          HIP_TRY(hipMemcpy(G.blockbox, box_of_block.data(), sizeof(int) * box_of_block.size(),
-                            hipMemcpyHostToDevice));
-          HIP_TRY(hipMemcpy(G.blockstart, start.data(), sizeof(int) * n, hipMemcpyHostToDevice));
-          out.push_back(G);
-          if (!att) {
-            maxR = std::max(maxR, R);
-            maxent = std::max(maxent, ent);
-          }
-        }
       }
     return LBE_OK;
   };
@@ -998,7 +1013,10 @@ lbe_status batch_tables(lbe_batch *B) {
     if (st != LBE_OK) return st;
   }
   prepare_force_kernels(maxR, B->visc, maxent);
-  for (int b = 0; b < n; ++b) B->zchunks[b] = B->boxes[b]->args.zchunk;
+  for (int b = 0; b < n; ++b) {
+    B->zchunks[b] = B->boxes[b]->args.zchunk;
+    B->shapes[b] = B->boxes[b]->args.rows;
+  }
   return LBE_OK;
 }
 
@@ -1058,7 +1076,7 @@ void batch_launch_step(lbe_batch *B, int cur) {
     bf.blockbox = G.blockbox;
     bf.blockstart = G.blockstart;
     // the first pair of a species writes its force, later pairs add
-    launch_batch_force(bf, G.nblocks, G.R, B->visc, G.entries, G.alpha, G.beta, G.beta > 0 ? 1 : 0,
+    launch_batch_force(bf, G.nblocks, G.R, G.shape, B->visc, G.entries, G.alpha, G.beta, G.beta > 0 ? 1 : 0,
                        B->stream);
   }
   for (const auto &G : B->att_groups) {

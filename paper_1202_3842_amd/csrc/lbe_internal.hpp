@@ -194,8 +194,11 @@ void launch_batch_ball(const BatchArgs &b, int nblocks, int zc, size_t lds_bytes
 void launch_batch_att(const BatchArgs &b, int nblocks, int R, int alpha, int beta, hipStream_t s);
 size_t ball_lds_bytes(int ball_R, int ball_total, int zc);
 int ball_blocks(const Geom &g, int zc);
-void launch_batch_force(const BatchArgs &b, int nblocks, int R, bool visc, int entries, int alpha, int beta,
-                        int acc, hipStream_t s);
+// the force groups of a batch: boxes of one shell reach R and one tile
+// shape (StepArgs::rows); force_tile_rows gives the shape's tile height
+void launch_batch_force(const BatchArgs &b, int nblocks, int R, int shape, bool visc, int entries, int alpha,
+                        int beta, int acc, hipStream_t s);
+int force_tile_rows(int shape);
 void launch_batch_collide(const BatchArgs &b, int nblocks, int prec, int M, hipStream_t s);
 void prepare_force_kernels(int maxR, bool visc, int max_entries);
 // adjoint passes (FP64 populations, no C^visc)

@@ -30,6 +30,11 @@ constexpr int BLOCK = 256;
 // tiles of the LDS-tiled gathers: FTX x FTY nodes per workgroup of FNT threads
 constexpr int FTX = FORCE_TX, FTY = FORCE_TY;
 constexpr int FNT = FTX * FTY;
+// force-kernel tile shapes (StepArgs::rows): output rows per thread,
+// threads, and tile height
+constexpr int shape_ny(int shape) { return shape == 1 ? 2 : 1; }
+constexpr int shape_nt(int shape) { return shape == 2 ? 512 : 256; }
+constexpr int shape_ty(int shape) { return shape_nt(shape) / FTX * shape_ny(shape); }
 
 // D3Q19 velocities (order documented in lbe.h) and weights
 __host__ __device__ constexpr int cvec(int p, int k) {
@@ -1185,16 +1190,18 @@ __global__ __launch_bounds__(BLOCK) void kb_ball(BatchArgs ba) {
 }
 
 // the shell gather of the directed pair (alpha, beta) for every box of one
-// shell reach R; acc: add to the force of species alpha (later pairs)
-template <int R, bool VISC>
-__global__ __launch_bounds__(FNT) void kb_force(BatchArgs ba, int alpha, int beta, int acc) {
+// shell reach R and tile shape SHAPE (each box's own tuned shape); acc: add
+// to the force of species alpha (later pairs)
+template <int R, bool VISC, int SHAPE>
+__global__ __launch_bounds__(shape_nt(SHAPE)) void kb_force(BatchArgs ba, int alpha, int beta, int acc) {
   extern __shared__ double lds[];
+  constexpr int TY = shape_ty(SHAPE);
   const int b = cptr(ba.blockbox)[blockIdx.x];
   const auto &a = *cptr(ba.boxes + b);
   const int local = blockIdx.x - cptr(ba.blockstart)[b];
-  const int nbx = (a.g.nx + FTX - 1) / FTX, nby = (a.g.ny + FTY - 1) / FTY;
-  force_body<R, VISC ? 1 : 0, 1, FNT>(a, nullptr, alpha, beta, acc, local % nbx, (local / nbx) % nby,
-                                      local / (nbx * nby), lds);
+  const int nbx = (a.g.nx + FTX - 1) / FTX, nby = (a.g.ny + TY - 1) / TY;
+  force_body<R, VISC ? 1 : 0, shape_ny(SHAPE), shape_nt(SHAPE)>(a, nullptr, alpha, beta, acc, local % nbx,
+                                                                (local / nbx) % nby, local / (nbx * nby), lds);
 }
 
 // the attractive field of the directed pair (alpha, beta) for every box of
@@ -2522,10 +2529,7 @@ void launch_contact(const StepArgs &a, hipStream_t s) {
 
 // the force kernel's tile shapes (lbe_set_force_tiling): 0 = 256 threads,
 // one row each (32 x 8); 1 = 256 threads, two rows each (32 x 16);
-// 2 = 512 threads, one row each (32 x 16)
-constexpr int shape_ny(int shape) { return shape == 1 ? 2 : 1; }
-constexpr int shape_nt(int shape) { return shape == 2 ? 512 : 256; }
-constexpr int shape_ty(int shape) { return shape_nt(shape) / FTX * shape_ny(shape); }
+// 2 = 512 threads, one row each (32 x 16): shape_ny, shape_nt, shape_ty
 
 template <int R, bool VISC, int SHAPE>
 static void force_launch_shape(const StepArgs &a, int alpha, int beta, int acc, hipStream_t s) {
@@ -2668,16 +2672,26 @@ int force_blocks(const Geom &g, int zchunk, int ty) {
   return ((g.nx + FTX - 1) / FTX) * ((g.ny + ty - 1) / ty) * ((g.nz + zchunk - 1) / zchunk);
 }
 
-template <int R, bool VISC>
+int force_tile_rows(int shape) { return shape_ty(shape); }
+
+template <int R, bool VISC, int SHAPE>
 static size_t force_lds_bytes(int entries) {
-  return force_lds(VISC ? 1 : 0, R, FTY, entries);
+  return force_lds(VISC ? 1 : 0, R, shape_ty(SHAPE), entries, shape_ny(SHAPE));
+}
+
+template <int R, bool VISC, int SHAPE>
+static void prepare_shape(int entries) {
+  const size_t bytes = force_lds_bytes<R, VISC, SHAPE>(entries);
+  if (bytes <= 160 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_force<R, VISC, SHAPE>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 template <int R, bool VISC>
 static void prepare_one(int entries) {
-  const int bytes = (int)force_lds_bytes<R, VISC>(entries);
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&kb_force<R, VISC>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  prepare_shape<R, VISC, 0>(entries);
+  prepare_shape<R, VISC, 1>(entries);
+  prepare_shape<R, VISC, 2>(entries);
 }
 
 // raise the dynamic-LDS limit of every force kernel up to shell range maxR
@@ -2740,19 +2754,31 @@ int ball_blocks(const Geom &g, int zc) {
   return ((g.nx + FTX - 1) / FTX) * ((g.ny + FTY - 1) / FTY) * ((g.nz + zc - 1) / zc);
 }
 
-template <int R, bool VISC>
-static void batch_force_r(const BatchArgs &b, int nblocks, int entries, int alpha, int beta, int acc,
+template <int R, bool VISC, int SHAPE>
+static void batch_force_s(const BatchArgs &b, int nblocks, int entries, int alpha, int beta, int acc,
                           hipStream_t s) {
-  const size_t bytes = force_lds_bytes<R, VISC>(entries);
-  hipLaunchKernelGGL((kb_force<R, VISC>), dim3(nblocks), dim3(FNT), bytes, s, b, alpha, beta, acc);
+  const size_t bytes = force_lds_bytes<R, VISC, SHAPE>(entries);
+  hipLaunchKernelGGL((kb_force<R, VISC, SHAPE>), dim3(nblocks), dim3(shape_nt(SHAPE)), bytes, s, b, alpha, beta,
+                     acc);
 }
 
-void launch_batch_force(const BatchArgs &b, int nblocks, int R, bool visc, int entries, int alpha, int beta,
-                        int acc, hipStream_t s) {
-#define BF(RR)                                                                      \
-  case RR:                                                                          \
-    if (visc) batch_force_r<RR, true>(b, nblocks, entries, alpha, beta, acc, s);    \
-    else batch_force_r<RR, false>(b, nblocks, entries, alpha, beta, acc, s);        \
+template <int R, bool VISC>
+static void batch_force_r(const BatchArgs &b, int nblocks, int shape, int entries, int alpha, int beta,
+                          int acc, hipStream_t s) {
+  if (shape == 1)
+    batch_force_s<R, VISC, 1>(b, nblocks, entries, alpha, beta, acc, s);
+  else if (shape == 2)
+    batch_force_s<R, VISC, 2>(b, nblocks, entries, alpha, beta, acc, s);
+  else
+    batch_force_s<R, VISC, 0>(b, nblocks, entries, alpha, beta, acc, s);
+}
+
+void launch_batch_force(const BatchArgs &b, int nblocks, int R, int shape, bool visc, int entries, int alpha,
+                        int beta, int acc, hipStream_t s) {
+#define BF(RR)                                                                             \
+  case RR:                                                                                 \
+    if (visc) batch_force_r<RR, true>(b, nblocks, shape, entries, alpha, beta, acc, s);    \
+    else batch_force_r<RR, false>(b, nblocks, shape, entries, alpha, beta, acc, s);        \
     break;
   switch (R) { BF(1) BF(2) BF(3) BF(4) BF(5) BF(6) BF(7) BF(8) default: break; }
 #undef BF

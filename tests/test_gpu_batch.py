@@ -179,3 +179,32 @@ def test_batched_quasipressure_routes(L):
     for b in singles:
         b.close()
     batch.close()
+
+
+@pytest.mark.parametrize("flags", ["visc", "mf"])
+def test_batched_force_groups_by_tile_shape(L, flags):
+    """Each batched box keeps its own force tiling: the force launches are
+    grouped by shell reach and tile shape (32x8, 32x16 with two rows per
+    thread, 32x16 with 512 threads), with each box's z depth.  The batch
+    equals the boxes stepped alone, bit for bit, for one and two species."""
+    f = L.LBE_VISC if flags == "visc" else 0
+    tilings = [(2, 1, 0), (1, 0, 2), (4, 2, 1), (2, 0, 2), (1, 1, 1), (3, 1, 0)]
+    for ws in (_boxes(), _mixtures()):
+        banner(f"batched tile shapes {flags}, {len(ws[0].sigma)} species")
+        batch = L.batch_from_workloads(ws, flags=f)
+        singles = [L.box_from_workload(w, flags=f) for w in ws]
+        for bb, t in zip(batch.boxes, tilings):
+            bb.set_force_tiling(*t)
+        batch.step(3, mode=2)
+        batch.boxes[0].set_force_tiling(1, 0, 2)     # a retune between replays
+        batch.step(3, mode=2)
+        for b in singles:
+            b.step(6)
+        M = len(ws[0].sigma)
+        for i, (bb, bs) in enumerate(zip(batch.boxes, singles)):
+            for a in range(M):
+                for dist in (0, 1):
+                    assert np.array_equal(bb.populations(a, dist), bs.populations(a, dist)), (i, a, dist)
+        for b in singles:
+            b.close()
+        batch.close()
