@@ -20,7 +20,9 @@ import numpy as np
 
 HERE = Path(__file__).resolve().parent
 SRC = HERE / "lbe_oracle.c"
-LIB = HERE / "liblbe_oracle.so"
+# LBEO_LIB points the loader at another build of the same source (the
+# sanitizer test builds one with AddressSanitizer and UBSan)
+LIB = Path(os.environ.get("LBEO_LIB", HERE / "liblbe_oracle.so"))
 
 LBEO_VISC = 1 << 0
 LBEO_PRINTED_INV = 1 << 1

@@ -8,6 +8,7 @@ import-time loader raises.
 from __future__ import annotations
 
 import ctypes as C
+import os
 import re
 from pathlib import Path
 from typing import Optional, Sequence
@@ -15,7 +16,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 PKG = Path(__file__).resolve().parent
-LIB_PATH = PKG / "liblbe.so"
+# LBE_LIB points the loader at another build of the same sources (the
+# sanitizer test loads a host-only build with AddressSanitizer and UBSan)
+LIB_PATH = Path(os.environ.get("LBE_LIB", PKG / "liblbe.so"))
 HEADER = PKG.parent / "include" / "lbe.h"
 
 LBE_OK = 0
