@@ -403,6 +403,34 @@ lbe_status lbe_adjoint_backward(lbe_adjoint *adj, const double *dL_dn, const dou
 lbe_status lbe_adjoint_state_grad(lbe_adjoint *adj, int species, int dist, double *out,
                                   int where);
 
+/* Test hook of the reverse sweep, for the dot-product tests of its
+ * transposes: applies one linear stage K of the step, or (transpose = 1)
+ * its transpose K^T as the reverse sweep computes it, at the fields of the
+ * context's current state.  in and out are device pointers (FP64, no
+ * overlap); the call runs on the context's stream and synchronises.
+ *   LBE_PROBE_GRAD: K V = -grad_h V, the lattice gradient of the external
+ *     potential (Sec. 4.1, F = -grad U; wrapped where periodic, clamped at
+ *     walls); in N values, out 3N ([component][node]).
+ *   LBE_PROBE_STREAM: pull streaming with mid-point bounce-back (Sec. 4.1,
+ *     Sec. 4.3), both distributions; in and out in the population layout
+ *     [dist][species][p][Ns] with Ns = N rounded up to a multiple of 64.
+ *   LBE_PROBE_SHELL_N: the mean-field shell gather C^mf_a/n_a (Appendix) of
+ *     every species, as a function of the densities n_b with the state's
+ *     contact values; in M*N, out 3M*N ([species][component][node]).
+ *   LBE_PROBE_SHELL_G: the same gather as a function of the contact values
+ *     G_ab (pairs a <= b in the order (0,0), (0,1), ..., (1,1), ...) with the
+ *     state's densities; in M(M+1)/2 * N, out 3M*N.
+ *   LBE_PROBE_QP: the path integral Phi of eq. quasipressure along the
+ *     context's route (no n F term) as a function of its integrand v; in
+ *     3M*N, out M*N.  Needs the quasi-pressure evaluated every step.
+ * The context's derived fields (densities, contact values, forces, Phi) are
+ * overwritten; its populations are not, and the next step recomputes the
+ * rest.  LBE_ERR_UNSUPPORTED for LBE_PROBE_STREAM with LBE_SINGLE, the
+ * shell probes with LBE_IDEAL or an attractive field, and LBE_PROBE_QP with
+ * LBE_PI_CARRIED or LBE_SINGLE. */
+enum { LBE_PROBE_GRAD = 0, LBE_PROBE_STREAM = 1, LBE_PROBE_SHELL_N = 2, LBE_PROBE_SHELL_G = 3, LBE_PROBE_QP = 4 };
+lbe_status lbe_adjoint_probe(lbe_adjoint *adj, int stage, int transpose, const double *in, double *out);
+
 void lbe_adjoint_destroy(lbe_adjoint *adj);
 
 /* Thread-local text of the last failure (never NULL). */

@@ -326,6 +326,114 @@ lbe_status lbe_adjoint_state_grad(lbe_adjoint *A, int species, int dist, double 
   return LBE_OK;
 }
 
+lbe_status lbe_adjoint_probe(lbe_adjoint *A, int stage, int transpose, const double *in, double *out) {
+  if (!A) return fail(LBE_ERR_ARG, "null adjoint");
+  if (!in || !out) return fail(LBE_ERR_ARG, "null buffer");
+  if (stage < LBE_PROBE_GRAD || stage > LBE_PROBE_QP || (transpose != 0 && transpose != 1))
+    return fail(LBE_ERR_ARG, "bad stage %d or transpose %d", stage, transpose);
+  lbe_ctx *c = A->c;
+  const AdjPlan &ap = A->ap;
+  const Geom &g = ap.pl.g;
+  const unsigned flags = c->cfg.flags;
+  const long long N = g.N;
+  const int M = ap.pl.M, np = M * (M + 1) / 2;
+  if (stage == LBE_PROBE_STREAM && (flags & LBE_SINGLE))
+    return fail(LBE_ERR_UNSUPPORTED, "the streaming probe needs both distributions");
+  if ((stage == LBE_PROBE_SHELL_N || stage == LBE_PROBE_SHELL_G) && (flags & LBE_IDEAL))
+    return fail(LBE_ERR_UNSUPPORTED, "the ideal gas has no shell gather");
+  if ((stage == LBE_PROBE_SHELL_N || stage == LBE_PROBE_SHELL_G)) {
+    for (int a = 0; a < M; ++a)
+      for (int b = 0; b < M; ++b)
+        if (c->cfg.att_eps[a][b] > 0.0) return fail(LBE_ERR_UNSUPPORTED, "the shell probe takes no attraction");
+  }
+  if (stage == LBE_PROBE_QP && !ap.qp)
+    return fail(LBE_ERR_UNSUPPORTED, "the quasi-pressure probe needs Pi evaluated every step");
+  if (c->poisoned) return fail(LBE_ERR_UNSTABLE, "the context is unstable");
+  hipStream_t s = c->stream;
+  // the state's fields (n, G, forces) into tape slot 0
+  A->fields(0, c->args.pop[c->cur]);
+  StepArgs a = A->slot_args(0);
+  AdjArgs d = A->base_args();
+  // scratch: the context's own derived fields, recomputed by the next step
+  double *cn = c->args.nfield, *cG = c->args.Gfield, *cf = c->args.force;
+  auto cmf_out = [&](const double *force) {  // C^mf/n of every species -> out (3M*N)
+    for (int sp = 0; sp < M; ++sp)
+      (void)hipMemcpyAsync(out + 3LL * sp * N, force + 6LL * sp * N, sizeof(double) * 3 * N,
+                           hipMemcpyDeviceToDevice, s);
+  };
+  switch (stage) {
+    case LBE_PROBE_GRAD:
+      if (transpose) launch_adj_extforce(g, in, out, s);
+      else launch_extforce(g, in, out, s);
+      break;
+    case LBE_PROBE_STREAM:
+      if (!transpose) {
+        launch_pull_f64(g, a.bb, 2 * M, in, out, s);
+      } else {  // k_adj_stream with no collision part: (1 - a) = 1, no node adjoints
+        StepArgs t = a;
+        t.acoef = 0.0;
+        launch_fill(d.node, 5LL * M * N, 0.0, s);
+        launch_fill(d.nbar, (long long)M * N, 0.0, s);
+        d.Jnl = nullptr;
+        d.mu_in = in;
+        d.mu_out = out;
+        launch_adj_stream(t, d, false, s);
+      }
+      break;
+    case LBE_PROBE_SHELL_N:
+    case LBE_PROBE_SHELL_G: {
+      StepArgs t = a;
+      t.flags &= ~(unsigned)(LBE_VISC | LBE_DRAG);
+      const bool byn = stage == LBE_PROBE_SHELL_N;
+      if (!transpose) {
+        if (byn) {
+          launch_pad_fields(g, a.bb, M, in, cn, s);
+          t.nfield = cn;
+        } else {
+          launch_pad_fields(g, a.bb, np, in, cG, s);
+          t.Gfield = cG;
+        }
+        t.force = cf;
+        launch_forces(t, s);
+        cmf_out(cf);
+      } else {
+        launch_pad_fields(g, a.bb, 3 * M, in, d.phibar, s);
+        launch_adj_shell(t, d, s);
+        (void)hipMemcpyAsync(out, byn ? d.nbar : d.Gbar, sizeof(double) * (byn ? M : np) * N,
+                             hipMemcpyDeviceToDevice, s);
+      }
+      break;
+    }
+    case LBE_PROBE_QP: {
+      // the integrand v = n (C^mf/n) with n = 1: v is the input itself
+      StepArgs t = a;
+      launch_fill(d.node, (long long)M * N, 1.0, s);
+      launch_pad_fields(g, a.bb, M, d.node, cn, s);
+      t.nfield = cn;
+      const unsigned mode = c->qp_mode & LBE_QP_SYMMETRIC;
+      if (!transpose) {
+        for (int sp = 0; sp < M; ++sp)
+          (void)hipMemcpyAsync(cf + 6LL * sp * N, in + 3LL * sp * N, sizeof(double) * 3 * N,
+                               hipMemcpyDeviceToDevice, s);
+        t.force = cf;
+        launch_quasipressure(t, c->qp_origin, mode, true, c->at<double>(c->pl.off_qps), out, s);
+      } else {
+        launch_fill(d.node, (long long)M * N, 0.0, s);
+        launch_fill(d.phibar, 3LL * M * g.Np, 0.0, s);
+        d.qpbar = const_cast<double *>(in);
+        launch_adj_quasipressure(t, d, c->qp_origin, mode, s);
+        launch_unpad_fields(g, 3 * M, d.phibar, out, s);  // n vbar with n = 1
+      }
+      break;
+    }
+    default:
+      break;
+  }
+  LAUNCH_CHECK();
+  HIP_TRY(hipStreamSynchronize(s));
+  return LBE_OK;
+}
+
 void lbe_adjoint_destroy(lbe_adjoint *A) {
   if (!A) return;
   (void)hipStreamSynchronize(A->c->stream);

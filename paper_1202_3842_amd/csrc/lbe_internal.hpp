@@ -216,6 +216,15 @@ void launch_adj_quasipressure(const StepArgs &a, const AdjArgs &d, const int ori
                               hipStream_t s);
 size_t adj_qp_sum_doubles(const Geom &g);
 void launch_adj_extforce(const Geom &g, const double *Fbar, double *Vbar, hipStream_t s);
+// building blocks of lbe_adjoint_probe: compact <-> padded fields (nf
+// fields; padding zero-fills first, solid nodes get 0), the pull of
+// `blocks` FP64 population blocks, and the shell-gather transposes alone
+// (phibar -> nbar, Gbar for every pair, without the ball part)
+void launch_pad_fields(const Geom &g, const uint32_t *bb, int nf, const double *in, double *out, hipStream_t s);
+void launch_unpad_fields(const Geom &g, int nf, const double *in, double *out, hipStream_t s);
+void launch_pull_f64(const Geom &g, const uint32_t *bb, int blocks, const double *pre, double *out,
+                     hipStream_t s);
+void launch_adj_shell(const StepArgs &a, const AdjArgs &d, hipStream_t s);
 void launch_adj_state_grad(const Geom &g, int M, const uint32_t *bb, const double *mu, int species,
                            int dist, double *out, hipStream_t s);
 void launch_fill(double *p, long long n, double v, hipStream_t s);

@@ -1939,6 +1939,28 @@ __global__ __launch_bounds__(BLOCK) void k_adj_extforce(Geom g, const double *__
   Vbar[i] = -3.0 * acc;
 }
 
+// compact fields (nf of them, N values each, zero on solid nodes) into
+// padded ones with their periodic images; wall ghosts are left as they are
+__global__ __launch_bounds__(BLOCK) void k_pad_fields(Geom g, const uint32_t *__restrict__ bb, int nf,
+                                                     const double *__restrict__ in, double *__restrict__ out) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= g.N) return;
+  const Coord c = decode(g, i);
+  const bool solid = bb[i] & 1u;
+  for (int f = 0; f < nf; ++f)
+    store_images(g, out + (long long)f * g.Np, c, solid ? 0.0 : in[(long long)f * g.N + i]);
+}
+
+// padded fields back to compact ones (the node's own value)
+__global__ __launch_bounds__(BLOCK) void k_unpad_fields(Geom g, int nf, const double *__restrict__ in,
+                                                       double *__restrict__ out) {
+  const int i = blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= g.N) return;
+  const Coord c = decode(g, i);
+  const long long P = padded_index(g, c.x, c.y, c.z);
+  for (int f = 0; f < nf; ++f) out[(long long)f * g.N + i] = in[(long long)f * g.Np + P];
+}
+
 // the adjoint of the post-streaming populations of one (species, dist)
 // block, compact 19N layout
 __global__ __launch_bounds__(BLOCK) void k_adj_state_grad(Geom g, int M, const uint32_t *__restrict__ bb,
@@ -3122,6 +3144,50 @@ void launch_adj_nonlocal(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
     if (!wg[k]) launch_fill(d.Gbar + k * N, N, 0.0, s);
   ball_launch<1>(a, d, s);
   ball_launch<2>(a, d, s);
+}
+
+void launch_pad_fields(const Geom &g, const uint32_t *bb, int nf, const double *in, double *out, hipStream_t s) {
+  launch_fill(out, (long long)nf * g.Np, 0.0, s);
+  hipLaunchKernelGGL(k_pad_fields, grid_for(g.N), dim3(BLOCK), 0, s, g, bb, nf, in, out);
+}
+
+void launch_unpad_fields(const Geom &g, int nf, const double *in, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpad_fields, grid_for(g.N), dim3(BLOCK), 0, s, g, nf, in, out);
+}
+
+void launch_pull_f64(const Geom &g, const uint32_t *bb, int blocks, const double *pre, double *out,
+                     hipStream_t s) {
+  const long long Ns = ((long long)g.N + 63) / 64 * 64;
+  for (int b = 0; b < blocks; ++b)
+    hipLaunchKernelGGL(k_pull<double>, grid_for(g.N), dim3(BLOCK), 0, s, g, bb, pre + (long long)b * Q * Ns,
+                       out + (long long)b * Q * Ns, Ns);
+}
+
+void launch_adj_shell(const StepArgs &a, const AdjArgs &d, hipStream_t s) {
+  bool wn[MAXM] = {false, false, false, false}, wg[MAXPAIRS] = {};
+  for (int al = 0; al < a.M; ++al)
+    for (int be = 0; be < a.M; ++be) {
+      const int k = pair_index(a.M, al, be);
+      const int R = a.t.pair_R[k];
+      if (R == 0) continue;
+      const int acc = (wn[be] ? 1 : 0) | (wg[k] ? 2 : 0);
+      wn[be] = wg[k] = true;
+      switch (R) {
+        case 1: adj_force_launch<1>(a, d, al, be, acc, s); break;
+        case 2: adj_force_launch<2>(a, d, al, be, acc, s); break;
+        case 3: adj_force_launch<3>(a, d, al, be, acc, s); break;
+        case 4: adj_force_launch<4>(a, d, al, be, acc, s); break;
+        case 5: adj_force_launch<5>(a, d, al, be, acc, s); break;
+        case 6: adj_force_launch<6>(a, d, al, be, acc, s); break;
+        case 7: adj_force_launch<7>(a, d, al, be, acc, s); break;
+        default: adj_force_launch<8>(a, d, al, be, acc, s); break;
+      }
+    }
+  const long long N = a.g.N;
+  for (int b = 0; b < a.M; ++b)
+    if (!wn[b]) launch_fill(d.nbar + b * N, N, 0.0, s);
+  for (int k = 0; k < a.M * (a.M + 1) / 2; ++k)
+    if (!wg[k]) launch_fill(d.Gbar + k * N, N, 0.0, s);
 }
 
 void launch_adj_extforce(const Geom &g, const double *Fbar, double *Vbar, hipStream_t s) {

@@ -44,6 +44,7 @@ LBE_DRAG = 1 << 6
 LBE_PI_CARRIED = 1 << 7
 LBE_QP_WITH_FEXT = 1
 LBE_QP_SYMMETRIC = 2
+LBE_PROBE_GRAD, LBE_PROBE_STREAM, LBE_PROBE_SHELL_N, LBE_PROBE_SHELL_G, LBE_PROBE_QP = range(5)
 
 
 class lbe_config(C.Structure):
@@ -129,6 +130,7 @@ def lib() -> C.CDLL:
     L.lbe_adjoint_forward.argtypes = [P]
     L.lbe_adjoint_backward.argtypes = [P, P, P, P, C.c_int, P, C.c_int]
     L.lbe_adjoint_state_grad.argtypes = [P, C.c_int, C.c_int, P, C.c_int]
+    L.lbe_adjoint_probe.argtypes = [P, C.c_int, C.c_int, P, P]
     L.lbe_adjoint_destroy.argtypes = [P]
     L.lbe_adjoint_destroy.restype = None
     _lib = L
@@ -494,6 +496,30 @@ class Adjoint:
         p, w, arr = b._dst(out, np.float64, N)
         _check(lib().lbe_adjoint_backward(self.h, ptrs[0], ptrs[1], ptrs[2], where, p, w))
         return arr.reshape(b.shape) if out is None else arr
+
+    def probe(self, stage, transpose, x):
+        """lbe_adjoint_probe: one linear stage K of the step (LBE_PROBE_*) or,
+        with transpose, K^T as the reverse sweep computes it, applied to the
+        torch CUDA tensor x (FP64) at the box's current state.  Returns a new
+        flat tensor of the output's length."""
+        b = self.box
+        t = b.torch
+        M, N = b.M, b.N
+        Ns = (N + 63) // 64 * 64
+        npairs = M * (M + 1) // 2
+        sizes = {LBE_PROBE_GRAD: (N, 3 * N), LBE_PROBE_STREAM: (2 * M * 19 * Ns, 2 * M * 19 * Ns),
+                 LBE_PROBE_SHELL_N: (M * N, 3 * M * N), LBE_PROBE_SHELL_G: (npairs * N, 3 * M * N),
+                 LBE_PROBE_QP: (3 * M * N, M * N)}
+        n_in, n_out = sizes[stage]
+        if transpose:
+            n_in, n_out = n_out, n_in
+        x = t.as_tensor(x, dtype=t.float64, device="cuda").contiguous().reshape(-1)
+        assert x.numel() == n_in, (x.numel(), n_in)
+        out = t.zeros(n_out, dtype=t.float64, device="cuda")
+        t.cuda.synchronize()
+        _check(lib().lbe_adjoint_probe(self.h, int(stage), int(transpose), C.c_void_p(x.data_ptr()),
+                                       C.c_void_p(out.data_ptr())))
+        return out
 
     def state_grad(self, species=0, dist=0, out=None):
         b = self.box

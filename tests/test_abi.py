@@ -88,6 +88,7 @@ def test_null_handles_are_rejected_without_touching_the_device(L):
         "lbe_batch_step": (None, 1, 2), "lbe_adjoint_forward": (None,),
         "lbe_adjoint_backward": (None, None, None, None, 0, None, 0),
         "lbe_adjoint_state_grad": (None, 0, 0, None, 0),
+        "lbe_adjoint_probe": (None, 0, 0, None, None),
         "lbe_adjoint_create": (None, 10, 5, None, 0, C.byref(C.c_void_p())),
         "lbe_create": (None, None, 0, None, C.byref(C.c_void_p())),
     }
