@@ -11,9 +11,12 @@ channel96_all_fd_grad.json`` the scheme with every force
 (C^visc, the drag and the attractive tails, printed inversions).  The objective is the
 one described in ``paper_1202_3842_amd.workloads.c5_objective``.  Only the
 oracle computes anything here; the GPU adjoint is compared with these values
-by tests/test_gpu_adjoint.py.
+by tests/test_gpu_adjoint.py.  ``--flags 0 --out channel96_qp_fd_grad.json``
+is the default reading (the quasi-pressure evaluated every step, along the
+channel's route from the gap centre), C^mf only, 400 steps.
 
     python tests/golden/make_channel_fd.py --flags 128 [--threads 8]   (about 80 min on 8 cores)
+    python tests/golden/make_channel_fd.py --flags 0 --out channel96_qp_fd_grad.json   (the default reading)
     python tests/golden/make_channel_fd.py --flags 131 --steps 40 --out channel96_visc_fd_grad.json
 """
 from __future__ import annotations
@@ -44,6 +47,8 @@ def objective(w, V, flags, steps):
     for a in range(w.nspecies):
         o.init_density(a, w.density[a])
         o.set_body_force(a, w.body[a])
+    if w.qp_route is not None:  # the per-step quasi-pressure's route (default reading)
+        o.set_quasipressure_route(*w.qp_route)
     o.step(steps)
     n_t, fluid, plane = W.c5_objective(w)
     nA = o.density(0)

@@ -83,7 +83,11 @@ def run(w, flags, steps, label, every=100):
     done = 0
     while done < steps:
         k = min(every, steps - done)
-        o.step(k)
+        try:
+            o.step(k)
+        except oracle.OracleError as e:  # the oracle refuses to step a collapsed state
+            print(f"{label}: {e} within steps {done + 1}..{done + k}", flush=True)
+            return o, done + k, True
         done += k
         d = o.diagnostics()
         print(f"{label}: step {done}/{steps} umax {d['umax']:.4e} unstable {d['unstable']} "

@@ -17,6 +17,7 @@ pytestmark = pytest.mark.gpu
 GOLDEN = Path(__file__).resolve().parent / "golden" / "channel96_fd_grad.json"
 GOLDEN_VISC = Path(__file__).resolve().parent / "golden" / "channel96_visc_fd_grad.json"
 GOLDEN_ALL = Path(__file__).resolve().parent / "golden" / "channel96_all_fd_grad.json"
+GOLDEN_QP = Path(__file__).resolve().parent / "golden" / "channel96_qp_fd_grad.json"
 # the reading in which g carries Pi (LBE_PI_CARRIED); without it the
 # quasi-pressure is evaluated every step (the default)
 CARRIED = 1 << 7
@@ -235,11 +236,14 @@ def test_autograd_function_matches_adjoint():
     assert_close(V.grad.cpu().numpy(), rV, 1e-10, "autograd dL/dV")
 
 
-@pytest.mark.parametrize("golden,steps,segment", [(GOLDEN, 400, 20), (GOLDEN_VISC, 40, 10), (GOLDEN_ALL, 40, 40)],
-                         ids=["cmf_400", "visc_printed_40", "all_forces_40"])
+@pytest.mark.parametrize("golden,steps,segment", [(GOLDEN_QP, 400, 20), (GOLDEN, 400, 20), (GOLDEN_VISC, 40, 10),
+                                                    (GOLDEN_ALL, 40, 40)],
+                         ids=["cmf_400_default", "cmf_400_carried", "visc_printed_40", "all_forces_40"])
 def test_channel96_gradient_against_oracle_fd(golden, steps, segment):
     """dL/dV on the 96x32x32 channel against central differences of the
-    oracle: C^mf with the derived inversions over 400 steps; C^visc with
+    oracle: C^mf with the derived inversions over 400 steps, with the
+    quasi-pressure evaluated every step (the default) and with Pi carried by
+    g; C^visc with
     the printed inversions over 40 steps; and every force (C^visc, the drag
     and the attractive tails, printed inversions) over 40 steps in one
     segment."""
