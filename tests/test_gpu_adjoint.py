@@ -279,12 +279,23 @@ def test_channel96_gradient_against_oracle_fd(golden, steps, segment):
     # central differences carry ~eps |L| / h of rounding noise
     noise = 2.2e-16 * abs(gold["L0"]) / gold["h"]
     worst = 0.0
+    rel = []
     for r in rows:
         err = abs(gV[r["node"]] - r["grad"])
         worst = max(worst, err)
         assert err <= 1e-6 * scale + 10 * noise, (r["node"], gV[r["node"]], r["grad"])
+        # per node, relative to its own gradient where that stands clear of
+        # the finite-difference noise; the two runs of a central difference
+        # round differently over hundreds of steps (two FP64 forwards agree
+        # to ~1e-13 relative after 400 steps, ~500 eps), so the noise floor
+        # here is 100 x eps |L| / h
+        if abs(r["grad"]) > 1e4 * noise:
+            rel.append(err / abs(r["grad"]))
+            assert err <= 1e-6 * abs(r["grad"]) + 100 * noise, (r["node"], gV[r["node"]], r["grad"])
+    rel = np.array(rel if rel else [0.0])
     print(f"channel96: {len(rows)} nodes, max|grad| {scale:.3e}, worst err {worst:.3e}, "
-          f"fd noise {noise:.1e}", flush=True)
+          f"fd noise {noise:.1e}; per node ({len(rel)} above 1e4 x noise): relative error "
+          f"median {np.median(rel):.1e}, max {rel.max():.1e}", flush=True)
 
 
 @pytest.mark.parametrize("att,flags", [(False, 0), (True, 0), (False, 1)])
