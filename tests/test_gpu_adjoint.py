@@ -171,16 +171,18 @@ def test_adjoint_with_visc_matches_reference(flags, att, T, segment):
         assert_close(gg, rg, 1e-10, "dL/dg0")
 
 
-def test_adjoint_visc_one_species_periodic_well():
-    """One species, sigma = 3, periodic, C^visc on, printed inversions (the
-    scheme of the 128^3 benchmark box)."""
+@pytest.mark.parametrize("flags", [1, 1 | 2], ids=["default", "printed"])
+def test_adjoint_visc_one_species_periodic_well(flags):
+    """One species, sigma = 3, periodic, C^visc on: the default scheme (the
+    128^3 benchmark box's: derived inversion, quasi-pressure every step as
+    the six-order mean from the centre) and the printed inversions."""
     w = W.well_box(16, 3.0, 0.3, W.eps_for_depth(1.0), 5.0, 1e-2, 33, 5, "well16_s3_visc")
     w.V = w.V + W.smooth_field(w.shape, 0.02, 3, 34)
     w.solid = np.zeros(w.shape, dtype=np.uint8)
     pw = pop_weights(w, 8) * 1e-3
-    print("well16 sigma 3 one species with C^visc", flush=True)
-    rV, rf, rg = reference(w, 1 | 2, 5, pw)
-    gV, gf, gg = gpu_gradient(w, 1 | 2, 5, 2, pw)
+    print(f"well16 sigma 3 one species with C^visc, flags {flags}", flush=True)
+    rV, rf, rg = reference(w, flags, 5, pw)
+    gV, gf, gg = gpu_gradient(w, flags, 5, 2, pw)
     assert_close(gV, rV, 1e-10, "dL/dV")
     assert_close(gf, rf, 1e-10, "dL/df0")
     assert_close(gg, rg, 1e-10, "dL/dg0")
@@ -358,7 +360,7 @@ def test_adjoint_attraction_tile_rows_agree():
 
 @pytest.mark.parametrize("att", [False, True], ids=["visc", "visc_attraction"])
 def test_adjoint_full_size_directional_derivative(att):
-    """The 128^3 benchmark box (sigma = 6, C^visc, printed inversions) in the
+    """The 128^3 benchmark box (sigma = 6, C^visc, the default scheme) in the
     launch configuration bench.py times, 3 steps: the adjoint's dL/dV along
     a smooth direction dV equals the central difference of L along dV (the
     library's own forward at V +- h dV), for L = sum_r c(r) n(r, T) with
@@ -369,7 +371,7 @@ def test_adjoint_full_size_directional_derivative(att):
     w = W.c2_large_well()
     if att:
         w.att_eps, w.att_rc = [[0.25 * W.KT]], 8.0
-    flags = lbe.LBE_VISC | lbe.LBE_PRINTED_INV
+    flags = lbe.LBE_VISC
     T = 3
     c = W.rng(61).uniform(-1.0, 1.0, size=w.shape)
     dV = W.smooth_field(w.shape, 0.1 * W.KT, 4, 62)
