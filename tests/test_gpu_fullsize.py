@@ -94,6 +94,34 @@ def test_well128_stated_2000_steps_against_oracle(L):
     b.close()
 
 
+def test_well128_fp32_populations_2000_steps(L):
+    """The FP32-population variant of the 128^3 well over its stated 2000
+    steps against the same FP64 oracle golden: the storage rounds every
+    population to 24 bits each step, so the state drifts from the FP64 one
+    by far more than 1e-11; the measured errors are printed and held to
+    1e-5 (n) and 1e-2 (u, whose max is 4e-4), with the spurious max|u|."""
+    from paper_1202_3842_amd import autotune
+    path = GOLDEN / "well128_2000.npz"
+    if not path.exists():
+        pytest.skip("well128_2000.npz not generated")
+    g = np.load(path)
+    w = W.c2_large_well()
+    banner(f"full size {w.name}, FP32 populations, {w.steps} steps against the FP64 oracle")
+    b = L.box_from_workload(w, prec=L.LBE_FP32_POP, flags=int(g["flags"]))
+    autotune.tune_zchunk(b)
+    b.step(w.steps)
+    d = b.diagnostics()
+    assert not d["unstable"]
+    z = int(g["zplane"])
+    en = max(rel_err(b.density(0)[z], g["n0_plane"]),
+             rel_err(b.density(0).reshape(-1)[g["nodes"]], g["n0_nodes"]))
+    eu = max(rel_err(b.velocity(-1)[:, z], g["u_plane"]),
+             rel_err(b.velocity(-1).reshape(3, -1)[:, g["nodes"]], g["u_nodes"]))
+    print(f"[fp32] well128 t=2000: n rel err {en:.2e}, u rel err {eu:.2e}, max|u| {d['umax']:.3e}", flush=True)
+    assert en <= 1e-5 and eu <= 1e-2, (en, eu)
+    b.close()
+
+
 def test_channel256_stated_5000_steps_against_oracle(L):
     """The 256x64x32 two-species channel over its stated 5000 steps (C^visc
     off: with it on the channel collapses within a few hundred steps under
