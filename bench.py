@@ -41,8 +41,8 @@ def alg_bytes_collide(M, P, qp=True):
 
 def alg_flops_force(pairs, visc):
     """FP64 flops per node of the shell gather (FMA = 2): per +-e pair the
-    mean-field term costs 11 and the viscous term 28."""
-    return pairs * (11 + (28 if visc else 0))
+    mean-field term costs 11 and the viscous term 27."""
+    return pairs * (11 + (27 if visc else 0))
 
 
 def alg_bytes_step(M, npairs, P, visc, qp=True):
@@ -75,7 +75,7 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_well128_s6.json")
 # the kernel sources the committed counter summary was taken on; a summary of
 # other sources is not used
-TRAFFIC_REV = "pi-per-step-1"
+TRAFFIC_REV = "pi-per-step-2"
 TRAFFIC_SOURCE = ("profiles/hbm_traffic_well128_s6.json: rocprofv3 FETCH_SIZE and WRITE_SIZE "
                   "of this launch, committed, scaled by a plain copy (not measured in this run)")
 

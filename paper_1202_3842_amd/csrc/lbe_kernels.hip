@@ -805,10 +805,12 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
           my[jn][c] += e1 * d;
           mz[jn][c] += e2 * d;
           if (VISC) {
+            // g(e.J~ - (e.u) n) at both points, with the products g n of
+            // the C^mf term: (gp e.J~p + gm e.J~m) - (e.u)(dp + dm)
             const double eu = e0 * u0x[jn] + e1 * u0y[jn] + e2 * u0z[jn];
-            const double tp = gp * (e0 * vp.x + e1 * vp.y + e2 * vpz - eu * npl);
-            const double tm = gm * (e0 * vm.x + e1 * vm.y + e2 * vmz - eu * nmi);
-            const double tt = tp + tm;
+            const double ejp = e0 * vp.x + e1 * vp.y + e2 * vpz;
+            const double ejm = e0 * vm.x + e1 * vm.y + e2 * vmz;
+            const double tt = (gp * ejp + gm * ejm) - eu * (dp + dm);
             vx[jn][c] += e0 * tt;
             vy[jn][c] += e1 * tt;
             vz[jn][c] += e2 * tt;
