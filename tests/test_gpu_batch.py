@@ -120,6 +120,38 @@ def test_batched_mixture_against_oracle(L):
     batch.close()
 
 
+def test_batch_of_boxes_at_the_smallest_edges(L):
+    """Boxes whose periodic edges equal the interaction reach (6 at sigma = 6,
+    4 at sigma = 4, 3 at sigma = 3) and a few just above it, batched: each
+    force tile is mostly outside its box, every halo plane is an image, and
+    the block -> box tables hold one or two blocks per box.  The batch equals
+    the boxes stepped alone bit for bit, and the sigma = 6 box equals the
+    oracle to 1e-11 (C^visc, the default scheme, 9 steps)."""
+    import oracle
+    from tests.parity_util import compare_state, oracle_from_workload
+    if not oracle.LIB.exists():
+        oracle.build()
+    spec = [(6, 6.0, 0.2, 0.5), (4, 4.0, 0.25, 0.5), (3, 3.0, 0.2, 0.5), (7, 3.0, 0.3, 1.0),
+            (5, 4.0, 0.2, 0.25)]
+    ws = [W.well_box(L_, s, ns3, eps, L_ / 4.0, 1e-2, 900 + i, 9, name=f"t{i}")
+          for i, (L_, s, ns3, eps) in enumerate(spec)]
+    banner("batch of boxes at the smallest edges")
+    batch = L.batch_from_workloads(ws, flags=L.LBE_VISC)
+    singles = [L.box_from_workload(w, flags=L.LBE_VISC) for w in ws]
+    batch.step(9)
+    for b in singles:
+        b.step(9)
+    for i, (bb, bs) in enumerate(zip(batch.boxes, singles)):
+        for dist in (0, 1):
+            assert np.array_equal(bb.populations(0, dist), bs.populations(0, dist)), (i, dist)
+    o = oracle_from_workload(ws[0], L.LBE_VISC)
+    o.step(9)
+    compare_state(o, batch.boxes[0], 1, 1e-11, "batched 6^3 at sigma 6")
+    for b in singles:
+        b.close()
+    batch.close()
+
+
 def test_batched_three_species(L):
     """Three-species boxes of uneven sizes (C^visc and the drag): the batch
     equals the boxes stepped alone, bit for bit."""

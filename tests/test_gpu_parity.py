@@ -157,6 +157,53 @@ def test_three_species_ragged(L):
     compare_state(o, b, 3, TOL, "ragged t=4")
 
 
+@pytest.mark.parametrize("walls", [False, True])
+def test_box_edge_at_the_interaction_range(L, walls):
+    """The smallest periodic edge the library accepts: x = R = 6 for sigma = 6
+    (y = 7, z = 9), where a shell point and its mirror r +- e can be the same
+    node through the periodic wrap and every halo plane is an image of the
+    box.  With walls beyond y, and a solid node, the shell also meets the
+    walls from both sides.  C^visc on, the default scheme, 6 steps."""
+    shape = (9, 7, 6)
+    dens = [W.noisy_uniform(shape, W.packing_density(0.15, 6.0), 2e-2, 77 + walls)]
+    solid = None
+    if walls:
+        solid = np.zeros(shape, dtype=bool)
+        solid[4, 3, 2] = True
+    w = W.Workload("edge_at_range", 6, 7, 9, [6.0], density=dens,
+                   V=W.smooth_field(shape, 0.05, 2, 78), body=[[1e-4, 0, 0]],
+                   periodic=W.PERIODIC_XZ if walls else 7, solid=solid)
+    banner(f"box edge at the interaction range 6x7x9, walls={walls}")
+    o, b = _pair(L, w, L.LBE_VISC)
+    t = 0
+    for k in (1, 2, 3):
+        o.step(k)
+        b.step(k)
+        t += k
+        compare_state(o, b, 1, TOL, f"edge at range, walls={walls}, t={t}")
+    for dist in (0, 1):
+        assert rel_err(b.populations(0, dist), o.populations(0, dist)) <= TOL
+
+
+def test_channel_one_node_wide(L):
+    """A non-periodic edge of one node: walls on both sides of every node
+    (12 x 1 x 10, x and z periodic, sigma = 3, C^visc on), so every shell
+    point off the y = 0 plane lies beyond a wall and the y pulls all bounce
+    back.  6 steps."""
+    shape = (10, 1, 12)
+    dens = [W.noisy_uniform(shape, W.packing_density(0.15, 3.0), 2e-2, 79)]
+    w = W.Workload("one_node_channel", 12, 1, 10, [3.0], density=dens,
+                   V=W.smooth_field(shape, 0.05, 2, 80), body=[[1e-4, 0, 0]],
+                   periodic=W.PERIODIC_XZ)
+    banner("channel one node wide 12x1x10")
+    o, b = _pair(L, w, L.LBE_VISC)
+    o.step(6)
+    b.step(6)
+    compare_state(o, b, 1, TOL, "one node wide, t=6")
+    for dist in (0, 1):
+        assert rel_err(b.populations(0, dist), o.populations(0, dist)) <= TOL
+
+
 def test_populations_roundtrip(L):
     w = W.channel(nx=20, ny=12, nz=8, x0=8, x1=12, gap=4, sigma=(3.0, 2.0), steps=1)
     banner("populations roundtrip")
