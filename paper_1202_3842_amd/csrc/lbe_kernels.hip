@@ -222,8 +222,8 @@ __global__ void k_extforce(Geom g, const double *__restrict__ V, double *__restr
   }
   // 1/v_T^2 = 3 for D3Q19
   F[i] = -3.0 * gx;
-  F[g.N + i] = -3.0 * gy;
-  F[2 * g.N + i] = -3.0 * gz;
+  F[(long long)g.N + i] = -3.0 * gy;
+  F[2LL * g.N + i] = -3.0 * gz;
 }
 
 template <typename T>

@@ -48,6 +48,18 @@ def test_workspace_size_and_validation(L):
     assert b"sigma" in L.lbe_last_error()
 
 
+def test_workspace_at_the_node_limit(L):
+    """Node indices are 32-bit: 1290^3 < 2^31 nodes is sized without overflow
+    (per node the same bytes as 64^3, to within the halos), 1291^3 is refused."""
+    for prec in (lbe.LBE_FP64, lbe.LBE_FP32_POP):
+        per_node = lbe.workspace_bytes(lbe.make_config(64, 64, 64, [6.0], prec=prec)) / 64 ** 3
+        big = lbe.workspace_bytes(lbe.make_config(1290, 1290, 1290, [6.0], prec=prec))
+        assert 0.9 < big / 1290 ** 3 / per_node < 1.0, (prec, big)
+    with pytest.raises(lbe.LBEError):
+        lbe.workspace_bytes(lbe.make_config(1291, 1291, 1291, [6.0]))
+    assert b"2^31" in L.lbe_last_error()
+
+
 def test_adjoint_workspace_and_scope(L):
     cfg = lbe.make_config(32, 32, 32, [4.0], flags=lbe.LBE_PI_CARRIED)
     n1 = L.lbe_adjoint_workspace_bytes(C.byref(cfg), 100, 10)
