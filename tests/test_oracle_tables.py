@@ -110,3 +110,32 @@ def test_bmcsl_limits(oracle_lib):
     # point-particle/big-sphere contact is the "ideal-wall" limit 1/(1-eta)
     g = oracle_lib.bmcsl([sa, 0.0], [1e-3, 5e-2], 0, 1)
     assert abs(g - 1 / (1 - eta_a)) < 1e-13
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_bmcsl_contact_values_give_the_bmcsl_pressure(oracle_lib, seed):
+    """Thermodynamic consistency of the mixture contact values (Appendix):
+    the virial pressure built from them,
+        beta p = sum_a n_a + (2 pi / 3) sum_ab n_a n_b sigma_ab^3 g_ab(sigma_ab),
+    is the Boublik-Mansoori-Carnahan-Starling-Leland equation of state,
+        beta p = (6/pi) [xi0/(1-xi3) + 3 xi1 xi2/(1-xi3)^2 + (3-xi3) xi2^3/(1-xi3)^3],
+    with xi_k = (pi/6) sum_a n_a sigma_a^k.  The identity holds for every
+    composition, so a dropped term, a wrong pair diameter or a wrong
+    coefficient in any g_ab breaks it for some of these 2- and 3-species
+    mixtures with unequal diameters."""
+    rng = np.random.default_rng(1100 + seed)
+    M = 2 + seed % 2
+    sig = list(rng.uniform(1.0, 7.0, M))
+    eta = rng.uniform(0.05, 0.45)
+    frac = rng.dirichlet(np.ones(M))
+    # partial packing fractions frac_a * eta -> number densities
+    n = [6 * frac[a] * eta / (math.pi * sig[a] ** 3) for a in range(M)]
+    xi = [math.pi / 6 * sum(n[a] * sig[a] ** k for a in range(M)) for k in range(4)]
+    x3 = xi[3]
+    p_eos = 6 / math.pi * (xi[0] / (1 - x3) + 3 * xi[1] * xi[2] / (1 - x3) ** 2
+                           + (3 - x3) * xi[2] ** 3 / (1 - x3) ** 3)
+    p_vir = sum(n) + 2 * math.pi / 3 * sum(
+        n[a] * n[b] * (0.5 * (sig[a] + sig[b])) ** 3 * oracle_lib.bmcsl(sig, n, a, b)
+        for a in range(M) for b in range(M))
+    assert abs(x3 - eta) < 1e-14
+    assert abs(p_vir - p_eos) <= 1e-13 * p_eos
