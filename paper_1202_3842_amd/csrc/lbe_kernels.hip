@@ -21,6 +21,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <type_traits>
+
 #include "lbe_internal.hpp"
 
 namespace lbe {
@@ -698,7 +700,140 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
       }
     }
     const int jbeg = rofs[ez] - j0, jend = rofs[ez + 1] - j0;
+    // C^mf + C^visc: the ten staged values of a pair for every row (n, G,
+    // J~x, J~y, J~z at r + e and at r - e), and the pair's terms from them
+    auto visc_load = [&](int o, double (&v)[NY][10]) {
+#pragma unroll
+      for (int jn = 0; jn < NY; ++jn) {
+        const int qa = base + jn * ROW + o, qb = base + jn * ROW - o;
+        v[jn][0] = Bp[qa];
+        v[jn][1] = Bp[WH + qa];
+        v[jn][2] = Bm[qb];
+        v[jn][3] = Bm[WH + qb];
+        v[jn][4] = Bp[2 * WH + qa];
+        v[jn][5] = Bp[3 * WH + qa];
+        v[jn][6] = Bm[2 * WH + qb];
+        v[jn][7] = Bm[3 * WH + qb];
+        v[jn][8] = Bp[4 * WH + qa];
+        v[jn][9] = Bm[4 * WH + qb];
+      }
+    };
+    auto visc_pair = [&](const double (&v)[NY][10], double e0, double e1, double e2, int c) {
+#pragma unroll
+      for (int jn = 0; jn < NY; ++jn) {
+        const double npl = v[jn][0], nmi = v[jn][2];
+        const double gp = G0[jn] + v[jn][1], gm = G0[jn] + v[jn][3];
+        // two rounded products, then the difference (no fused multiply-add
+        // across the pair), so that a uniform state gives exactly zero
+        const double dp = gp * npl;
+        const double dm = gm * nmi;
+        const double d = dp - dm;
+        mx[jn][c] += e0 * d;
+        my[jn][c] += e1 * d;
+        mz[jn][c] += e2 * d;
+        // g(e.J~ - (e.u) n) at both points, with the products g n of the
+        // C^mf term: (gp e.J~p + gm e.J~m) - (e.u)(dp + dm)
+        const double eu = e0 * u0x[jn] + e1 * u0y[jn] + e2 * u0z[jn];
+        const double ejp = e0 * v[jn][4] + e1 * v[jn][5] + e2 * v[jn][8];
+        const double ejm = e0 * v[jn][6] + e1 * v[jn][7] + e2 * v[jn][9];
+        const double tt = (gp * ejp + gm * ejm) - eu * (dp + dm);
+        vx[jn][c] += e0 * tt;
+        vy[jn][c] += e1 * tt;
+        vz[jn][c] += e2 * tt;
+      }
+    };
     // one +-e pair for every row of the thread, into accumulator set c
+    auto pair_at = [&](double e0, double e1, double e2, int o, int c) {
+      if constexpr (VISC) {
+        double v[NY][10];
+        visc_load(o, v);
+        visc_pair(v, e0, e1, e2, c);
+      } else {
+#pragma unroll
+        for (int jn = 0; jn < NY; ++jn) {
+          const int qa = base + jn * ROW + o, qb = base + jn * ROW - o;
+          if constexpr (VTF) {
+            // e^.phibar', e^.u~, G and n at r+e and r-e (the -e terms carry the
+            // same signs: (-e^)(-e^.v) = e^(e^.v)); e^.J~ = n (e^.u~) there
+            const double pp = e0 * Bp[qa] + e1 * Bp[WH + qa] + e2 * Bp[2 * WH + qa];
+            const double pm = e0 * Bm[qb] + e1 * Bm[WH + qb] + e2 * Bm[2 * WH + qb];
+            const double Gp = Bp[3 * WH + qa], Gm = Bm[3 * WH + qb];
+            const double up = e0 * Bp[4 * WH + qa] + e1 * Bp[5 * WH + qa] + e2 * Bp[6 * WH + qa];
+            const double um = e0 * Bm[4 * WH + qb] + e1 * Bm[5 * WH + qb] + e2 * Bm[6 * WH + qb];
+            const double npl = Bp[7 * WH + qa], nmi = Bm[7 * WH + qb];
+            const double s1 = pp + pm, s2 = pp * Gp + pm * Gm;
+            mx[jn][c] += e0 * s1;
+            my[jn][c] += e1 * s1;
+            mz[jn][c] += e2 * s1;
+            vx[jn][c] += e0 * s2;
+            vy[jn][c] += e1 * s2;
+            vz[jn][c] += e2 * s2;
+            const double bp = pp * up, bm = pm * um;
+            ox[jn][c] += bp + bm;
+            oy[jn][c] += bp * Gp + bm * Gm;
+            const double ep = e0 * p0x[jn] + e1 * p0y[jn] + e2 * p0z[jn];
+            const double eu = e0 * u0x[jn] + e1 * u0y[jn] + e2 * u0z[jn];
+            const double t1 = ep * (npl * (G0[jn] + Gp) + nmi * (G0[jn] + Gm));
+            wx[jn][c] += e0 * t1;
+            wy[jn][c] += e1 * t1;
+            wz[jn][c] += e2 * t1;
+            we[jn][c] += ep * (npl * (up - eu) + nmi * (um - eu));
+            continue;
+          }
+          dbl2 ap, am, vp = {0.0, 0.0}, vm = {0.0, 0.0};
+          double vpz = 0.0, vmz = 0.0;
+          if (PAIRED) {
+            ap = *reinterpret_cast<const dbl2 *>(Bp + 2 * qa);
+            am = *reinterpret_cast<const dbl2 *>(Bm + 2 * qb);
+            if (NF == 5) {
+              vp = *reinterpret_cast<const dbl2 *>(Bp + 2 * WH + 2 * qa);
+              vm = *reinterpret_cast<const dbl2 *>(Bm + 2 * WH + 2 * qb);
+              vpz = Bp[4 * WH + qa];
+              vmz = Bm[4 * WH + qb];
+            }
+          } else if (ATT) {
+            ap = dbl2{Bp[qa], 0.0};
+            am = dbl2{Bm[qb], 0.0};
+          } else {  // AADJ
+            ap = dbl2{Bp[qa], Bp[WH + qa]};
+            am = dbl2{Bm[qb], Bm[WH + qb]};
+            vpz = Bp[2 * WH + qa];
+            vmz = Bm[2 * WH + qb];
+          }
+          const double npl = ap.x, nmi = am.x;
+          if (AADJ) {
+            // K(-e) = -K(e): the pair adds K.(phibar(r+e) - phibar(r-e))
+            mx[jn][c] += e0 * (ap.x - am.x) + e1 * (ap.y - am.y) + e2 * (vpz - vmz);
+          } else if (ATT) {
+            // the table holds U'(|e|) e^; the pair adds K.(n_b(r+e) - n_b(r-e))
+            const double dn = npl - nmi;
+            mx[jn][c] += e0 * dn;
+            my[jn][c] += e1 * dn;
+            mz[jn][c] += e2 * dn;
+          } else if (ADJ) {
+            // m: sum_S e^ n_b(r+e); v: sum_S e^.phibar(r+e) and
+            // sum_S (e^.phibar(r+e)) G(r+e), over both points of the pair
+            const double tp = e0 * vp.x + e1 * vp.y + e2 * vpz;
+            const double tm = e0 * vm.x + e1 * vm.y + e2 * vmz;
+            const double dn = npl - nmi;
+            mx[jn][c] += e0 * dn;
+            my[jn][c] += e1 * dn;
+            mz[jn][c] += e2 * dn;
+            vx[jn][c] += tp - tm;
+            vy[jn][c] += tp * ap.y - tm * am.y;
+          } else {  // C^mf alone
+            const double gp = G0[jn] + ap.y, gm = G0[jn] + am.y;
+            // two rounded products, then the difference, as with C^visc
+            const double dp = gp * npl;
+            const double dm = gm * nmi;
+            const double d = dp - dm;
+            mx[jn][c] += e0 * d;
+            my[jn][c] += e1 * d;
+            mz[jn][c] += e2 * d;
+          }
+        }
+      }
+    };
     auto pair = [&](int j, int c) {
       double e0, e1, e2;
       int o;
@@ -713,125 +848,62 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
         e2 = tab[4 * j + 2];
         o = (int)__double_as_longlong(tab[4 * j + 3]);
       }
-#pragma unroll
-      for (int jn = 0; jn < NY; ++jn) {
-        const int qa = base + jn * ROW + o, qb = base + jn * ROW - o;
-        if constexpr (VTF) {
-          // e^.phibar', e^.u~, G and n at r+e and r-e (the -e terms carry the
-          // same signs: (-e^)(-e^.v) = e^(e^.v)); e^.J~ = n (e^.u~) there
-          const double pp = e0 * Bp[qa] + e1 * Bp[WH + qa] + e2 * Bp[2 * WH + qa];
-          const double pm = e0 * Bm[qb] + e1 * Bm[WH + qb] + e2 * Bm[2 * WH + qb];
-          const double Gp = Bp[3 * WH + qa], Gm = Bm[3 * WH + qb];
-          const double up = e0 * Bp[4 * WH + qa] + e1 * Bp[5 * WH + qa] + e2 * Bp[6 * WH + qa];
-          const double um = e0 * Bm[4 * WH + qb] + e1 * Bm[5 * WH + qb] + e2 * Bm[6 * WH + qb];
-          const double npl = Bp[7 * WH + qa], nmi = Bm[7 * WH + qb];
-          const double s1 = pp + pm, s2 = pp * Gp + pm * Gm;
-          mx[jn][c] += e0 * s1;
-          my[jn][c] += e1 * s1;
-          mz[jn][c] += e2 * s1;
-          vx[jn][c] += e0 * s2;
-          vy[jn][c] += e1 * s2;
-          vz[jn][c] += e2 * s2;
-          const double bp = pp * up, bm = pm * um;
-          ox[jn][c] += bp + bm;
-          oy[jn][c] += bp * Gp + bm * Gm;
-          const double ep = e0 * p0x[jn] + e1 * p0y[jn] + e2 * p0z[jn];
-          const double eu = e0 * u0x[jn] + e1 * u0y[jn] + e2 * u0z[jn];
-          const double t1 = ep * (npl * (G0[jn] + Gp) + nmi * (G0[jn] + Gm));
-          wx[jn][c] += e0 * t1;
-          wy[jn][c] += e1 * t1;
-          wz[jn][c] += e2 * t1;
-          we[jn][c] += ep * (npl * (up - eu) + nmi * (um - eu));
-          continue;
-        }
-        dbl2 ap, am, vp = {0.0, 0.0}, vm = {0.0, 0.0};
-        double vpz = 0.0, vmz = 0.0;
-        if (PAIRED) {
-          ap = *reinterpret_cast<const dbl2 *>(Bp + 2 * qa);
-          am = *reinterpret_cast<const dbl2 *>(Bm + 2 * qb);
-          if (NF == 5) {
-            vp = *reinterpret_cast<const dbl2 *>(Bp + 2 * WH + 2 * qa);
-            vm = *reinterpret_cast<const dbl2 *>(Bm + 2 * WH + 2 * qb);
-          }
-        } else if (ATT) {
-          ap = dbl2{Bp[qa], 0.0};
-          am = dbl2{Bm[qb], 0.0};
-        } else if (AADJ) {
-          ap = dbl2{Bp[qa], Bp[WH + qa]};
-          am = dbl2{Bm[qb], Bm[WH + qb]};
-          vpz = Bp[2 * WH + qa];
-          vmz = Bm[2 * WH + qb];
-        } else {
-          ap = dbl2{Bp[qa], Bp[WH + qa]};
-          am = dbl2{Bm[qb], Bm[WH + qb]};
-          if (NF == 5) {
-            vp = dbl2{Bp[2 * WH + qa], Bp[3 * WH + qa]};
-            vm = dbl2{Bm[2 * WH + qb], Bm[3 * WH + qb]};
-          }
-        }
-        if (NF == 5) {
-          vpz = Bp[4 * WH + qa];
-          vmz = Bm[4 * WH + qb];
-        }
-        const double npl = ap.x, nmi = am.x;
-        if (AADJ) {
-          // K(-e) = -K(e): the pair adds K.(phibar(r+e) - phibar(r-e))
-          mx[jn][c] += e0 * (ap.x - am.x) + e1 * (ap.y - am.y) + e2 * (vpz - vmz);
-        } else if (ATT) {
-          // the table holds U'(|e|) e^; the pair adds K.(n_b(r+e) - n_b(r-e))
-          const double dn = npl - nmi;
-          mx[jn][c] += e0 * dn;
-          my[jn][c] += e1 * dn;
-          mz[jn][c] += e2 * dn;
-        } else if (ADJ) {
-          // m: sum_S e^ n_b(r+e); v: sum_S e^.phibar(r+e) and
-          // sum_S (e^.phibar(r+e)) G(r+e), over both points of the pair
-          const double tp = e0 * vp.x + e1 * vp.y + e2 * vpz;
-          const double tm = e0 * vm.x + e1 * vm.y + e2 * vmz;
-          const double dn = npl - nmi;
-          mx[jn][c] += e0 * dn;
-          my[jn][c] += e1 * dn;
-          mz[jn][c] += e2 * dn;
-          vx[jn][c] += tp - tm;
-          vy[jn][c] += tp * ap.y - tm * am.y;
-        } else {
-          const double gp = G0[jn] + ap.y, gm = G0[jn] + am.y;
-          // two rounded products, then the difference (no fused multiply-add
-          // across the pair), so that a uniform state gives exactly zero
-          const double dp = gp * npl;
-          const double dm = gm * nmi;
-          const double d = dp - dm;
-          mx[jn][c] += e0 * d;
-          my[jn][c] += e1 * d;
-          mz[jn][c] += e2 * d;
-          if (VISC) {
-            // g(e.J~ - (e.u) n) at both points, with the products g n of
-            // the C^mf term: (gp e.J~p + gm e.J~m) - (e.u)(dp + dm)
-            const double eu = e0 * u0x[jn] + e1 * u0y[jn] + e2 * u0z[jn];
-            const double ejp = e0 * vp.x + e1 * vp.y + e2 * vpz;
-            const double ejm = e0 * vm.x + e1 * vm.y + e2 * vmz;
-            const double tt = (gp * ejp + gm * ejm) - eu * (dp + dm);
-            vx[jn][c] += e0 * tt;
-            vy[jn][c] += e1 * tt;
-            vz[jn][c] += e2 * tt;
-          }
-        }
-      }
+      pair_at(e0, e1, e2, o, c);
     };
     // a pair's terms are combined before they are accumulated, so a uniform
     // state still sums to exactly zero
     int j = jbeg;
-    // C^mf + C^visc: eight pairs per iteration, the same sets in the same
-    // order (bitwise the same sums; 0.766 -> 0.761 ms at 128^3).  For the
-    // other gathers it made no consistent difference.
-    if (MODE == 1)
-      for (; j + 2 * NS - 1 < jend; j += 2 * NS) {
+    if constexpr (VISC) {
+      // Pairs in groups of K, the K table entries first (scalar loads), then
+      // the pairs, each one's LDS reads issued ahead of the previous pair's
+      // arithmetic; pair c of a group goes to set c mod NS, as one at a time.
+      // A scalar load shares its completion counter with the LDS reads and
+      // may return out of order, so waiting for one waits for every read in
+      // flight: with each entry loaded next to its pair, every pair waited
+      // for all of its reads before any arithmetic.  Groups of eight and
+      // four, pipelined: 128^3 step 1.328 -> 1.278 ms, the same sums bit
+      // for bit.
+      // (the 512-thread tile at reach 8 would spill; it loads each entry
+      // next to its pair)
+      constexpr bool PIPE = !(R >= 8 && NT >= 512);
+      auto group = [&](auto kc) {
+        constexpr int K = decltype(kc)::value;
+        if constexpr (PIPE) {
+          double E0[K], E1[K], E2[K];
+          int O[K];
 #pragma unroll
-        for (int c = 0; c < 2 * NS; ++c) pair(j + c, c % NS);
+          for (int c = 0; c < K; ++c) {
+            const int jj = j0 + j + c;
+            E0[c] = re[3 * jj];
+            E1[c] = re[3 * jj + 1];
+            E2[c] = re[3 * jj + 2];
+            O[c] = roff[jj];
+          }
+          double cur[NY][10], nxt[NY][10];
+          visc_load(O[0], cur);
+#pragma unroll
+          for (int c = 0; c < K; ++c) {
+            if (c + 1 < K) visc_load(O[c + 1], nxt);
+            visc_pair(cur, E0[c], E1[c], E2[c], c % NS);
+            if (c + 1 < K) {
+#pragma unroll
+              for (int jn = 0; jn < NY; ++jn)
+#pragma unroll
+                for (int q = 0; q < 10; ++q) cur[jn][q] = nxt[jn][q];
+            }
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < K; ++c) pair(j + c, c % NS);
+        }
+      };
+      for (; j + 2 * NS - 1 < jend; j += 2 * NS) group(std::integral_constant<int, 2 * NS>{});
+      for (; j + NS - 1 < jend; j += NS) group(std::integral_constant<int, NS>{});
+    } else {
+      for (; j + NS - 1 < jend; j += NS) {
+#pragma unroll
+        for (int c = 0; c < NS; ++c) pair(j + c, c);
       }
-    for (; j + NS - 1 < jend; j += NS) {
-#pragma unroll
-      for (int c = 0; c < NS; ++c) pair(j + c, c);
     }
     for (int c = 0; j < jend; ++j, ++c) pair(j, c);
     if (ez == R) {
