@@ -899,6 +899,30 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
       };
       for (; j + 2 * NS - 1 < jend; j += 2 * NS) group(std::integral_constant<int, 2 * NS>{});
       for (; j + NS - 1 < jend; j += NS) group(std::integral_constant<int, NS>{});
+    } else if constexpr (STAB && (ADJ || ATT || AADJ)) {
+      // the same grouped table loads, without the pipelining, for the C^mf
+      // transpose and the attraction gathers (channel adjoint backward
+      // 233 -> 227 ms; with the attraction 577 -> 518 ms).  The C^visc
+      // transpose, already at 256 VGPRs, was slower with them (128^3
+      // adjoint backward 125 -> 141 ms) and keeps the per-pair loads, as
+      // does C^mf alone, not measured with them.
+      auto group = [&](auto kc) {
+        constexpr int K = decltype(kc)::value;
+        double E0[K], E1[K], E2[K];
+        int O[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+          const int jj = j0 + j + c;
+          E0[c] = re[3 * jj];
+          E1[c] = re[3 * jj + 1];
+          E2[c] = re[3 * jj + 2];
+          O[c] = roff[jj];
+        }
+#pragma unroll
+        for (int c = 0; c < K; ++c) pair_at(E0[c], E1[c], E2[c], O[c], c % NS);
+      };
+      for (; j + 2 * NS - 1 < jend; j += 2 * NS) group(std::integral_constant<int, 2 * NS>{});
+      for (; j + NS - 1 < jend; j += NS) group(std::integral_constant<int, NS>{});
     } else {
       for (; j + NS - 1 < jend; j += NS) {
 #pragma unroll
