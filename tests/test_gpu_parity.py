@@ -185,6 +185,25 @@ def test_box_edge_at_the_interaction_range(L, walls):
         assert rel_err(b.populations(0, dist), o.populations(0, dist)) <= TOL
 
 
+@pytest.mark.parametrize("shape", [0, 1, 2])
+def test_widest_shells_in_every_tile_shape(L, shape):
+    """Diameters 8 and 6: shells of reach 8, 7 and 6, the widest the kernels
+    take, with C^visc on, in each force tile shape (32 x 8 with 256 threads,
+    32 x 16 with two rows per thread, 32 x 16 with 512 threads), where the
+    gathers hold the most registers.  3 steps against the oracle."""
+    dims = (17, 18, 20)
+    sig = [8.0, 6.0]
+    dens = [W.noisy_uniform(dims, W.packing_density(0.05, s), 1e-2, 120 + a) for a, s in enumerate(sig)]
+    w = W.Workload("widest", 20, 18, 17, sig, density=dens, V=W.smooth_field(dims, 0.05, 3, 122),
+                   body=[[1e-4, 0, 0], [0, 0, 0]], periodic=7)
+    banner(f"widest shells 20x18x17, sigma 8 and 6, tile shape {shape}")
+    o, b = _pair(L, w, L.LBE_VISC)
+    b.set_force_tiling(1, 1, shape)
+    o.step(3)
+    b.step(3)
+    compare_state(o, b, 2, TOL, f"widest shells, shape {shape}, t=3")
+
+
 def test_channel_one_node_wide(L):
     """A non-periodic edge of one node: walls on both sides of every node
     (12 x 1 x 10, x and z periodic, sigma = 3, C^visc on), so every shell
