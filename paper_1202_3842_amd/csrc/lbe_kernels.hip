@@ -2598,15 +2598,17 @@ void launch_moments(const StepArgs &a, int prec, const void *pop, hipStream_t s)
   }
 }
 
-// z depth of a ball-kernel workgroup: the largest of 8, 4, 2 that still
-// gives at least 2048 workgroups, else 1.  At 128^3 that is depth 4 (2048
-// workgroups of 43 KB LDS, three per CU) rather than 8 (1024 of 60 KB, two
-// per CU, in two rounds with the staging exposed): 0.078 -> 0.068 ms, the
-// same sums (each node adds its ball in table order at any depth)
+// z depth of a ball-kernel workgroup: the largest of 4 and 2 that still
+// gives at least 1024 workgroups, else 1.  Depth 8 is not used: at 128^3
+// its 60 KB workgroups fit two to a CU and ran in two rounds with the
+// staging exposed, where depth 4 fits three (0.078 -> 0.068 ms).  A smaller
+// depth costs more staging per node (2R planes of halo per ZC planes), so
+// boxes that reach 1024 workgroups at depth 2 keep it.  The sums do not
+// depend on the depth (each node adds its ball in table order).
 int ball_block_zc(const Geom &g) {
   const long long tiles = (long long)((g.nx + FTX - 1) / FTX) * ((g.ny + FTY - 1) / FTY);
-  for (int zc = 8; zc > 1; zc /= 2)
-    if (tiles * ((g.nz + zc - 1) / zc) >= 2048) return zc;
+  for (int zc = 4; zc > 1; zc /= 2)
+    if (tiles * ((g.nz + zc - 1) / zc) >= 1024) return zc;
   return 1;
 }
 
