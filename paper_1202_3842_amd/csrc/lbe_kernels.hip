@@ -834,14 +834,18 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
         }
       }
     };
+    // table entry jj (scalar loads): unit vector and LDS offset of a pair
+    auto entry = [&](int jj, double &e0, double &e1, double &e2, int &o) {
+      e0 = re[3 * jj];
+      e1 = re[3 * jj + 1];
+      e2 = re[3 * jj + 2];
+      o = roff[jj];
+    };
     auto pair = [&](int j, int c) {
       double e0, e1, e2;
       int o;
       if (STAB) {
-        e0 = re[3 * (j0 + j)];
-        e1 = re[3 * (j0 + j) + 1];
-        e2 = re[3 * (j0 + j) + 2];
-        o = roff[j0 + j];
+        entry(j0 + j, e0, e1, e2, o);
       } else {
         e0 = tab[4 * j];
         e1 = tab[4 * j + 1];
@@ -872,13 +876,7 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
           double E0[K], E1[K], E2[K];
           int O[K];
 #pragma unroll
-          for (int c = 0; c < K; ++c) {
-            const int jj = j0 + j + c;
-            E0[c] = re[3 * jj];
-            E1[c] = re[3 * jj + 1];
-            E2[c] = re[3 * jj + 2];
-            O[c] = roff[jj];
-          }
+          for (int c = 0; c < K; ++c) entry(j0 + j + c, E0[c], E1[c], E2[c], O[c]);
           double cur[NY][10], nxt[NY][10];
           visc_load(O[0], cur);
 #pragma unroll
@@ -900,10 +898,11 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
       for (; j + 2 * NS - 1 < jend; j += 2 * NS) group(std::integral_constant<int, 2 * NS>{});
       for (; j + NS - 1 < jend; j += NS) group(std::integral_constant<int, NS>{});
     } else if constexpr (STAB && (ADJ || ATT || AADJ)) {
-      // the same grouped table loads, without the pipelining, for the C^mf
-      // transpose and the attraction gathers (channel adjoint backward
-      // 233 -> 227 ms; with the attraction 577 -> 518 ms).  The C^visc
-      // transpose, already at 256 VGPRs, was slower with them (128^3
+      // the same grouped table loads for the C^mf transpose and the
+      // attraction gathers (channel adjoint backward 233 -> 227 ms; with the
+      // attraction 577 -> 518 ms), and for the attraction also the reads
+      // pipelined (128^3 step with the attraction 1.655 -> 1.611 ms).  The
+      // C^visc transpose, already at 256 VGPRs, was slower with them (128^3
       // adjoint backward 125 -> 141 ms) and keeps the per-pair loads, as
       // does C^mf alone, not measured with them.
       auto group = [&](auto kc) {
@@ -911,15 +910,41 @@ __device__ inline void force_body(const A &a, const AdjArgs *ad, int alpha, int 
         double E0[K], E1[K], E2[K];
         int O[K];
 #pragma unroll
-        for (int c = 0; c < K; ++c) {
-          const int jj = j0 + j + c;
-          E0[c] = re[3 * jj];
-          E1[c] = re[3 * jj + 1];
-          E2[c] = re[3 * jj + 2];
-          O[c] = roff[jj];
-        }
+        for (int c = 0; c < K; ++c) entry(j0 + j + c, E0[c], E1[c], E2[c], O[c]);
+        if constexpr (ATT) {
+          // n_b at r + e and r - e for every row, the next pair's ahead of
+          // this pair's arithmetic
+          auto att_load = [&](int o, double (&v)[NY][2]) {
 #pragma unroll
-        for (int c = 0; c < K; ++c) pair_at(E0[c], E1[c], E2[c], O[c], c % NS);
+            for (int jn = 0; jn < NY; ++jn) {
+              v[jn][0] = Bp[base + jn * ROW + o];
+              v[jn][1] = Bm[base + jn * ROW - o];
+            }
+          };
+          double cur[NY][2], nxt[NY][2];
+          att_load(O[0], cur);
+#pragma unroll
+          for (int c = 0; c < K; ++c) {
+            if (c + 1 < K) att_load(O[c + 1], nxt);
+#pragma unroll
+            for (int jn = 0; jn < NY; ++jn) {
+              const double dn = cur[jn][0] - cur[jn][1];
+              mx[jn][c % NS] += E0[c] * dn;
+              my[jn][c % NS] += E1[c] * dn;
+              mz[jn][c % NS] += E2[c] * dn;
+            }
+            if (c + 1 < K) {
+#pragma unroll
+              for (int jn = 0; jn < NY; ++jn) {
+                cur[jn][0] = nxt[jn][0];
+                cur[jn][1] = nxt[jn][1];
+              }
+            }
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < K; ++c) pair_at(E0[c], E1[c], E2[c], O[c], c % NS);
+        }
       };
       for (; j + 2 * NS - 1 < jend; j += 2 * NS) group(std::integral_constant<int, 2 * NS>{});
       for (; j + NS - 1 < jend; j += NS) group(std::integral_constant<int, NS>{});
