@@ -75,7 +75,7 @@ FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_well128_s6.json")
 # the kernel sources the committed counter summary was taken on; a summary of
 # other sources is not used
-TRAFFIC_REV = "pi-per-step-3"
+TRAFFIC_REV = "pi-per-step-4"
 TRAFFIC_SOURCE = ("profiles/hbm_traffic_well128_s6.json: rocprofv3 FETCH_SIZE and WRITE_SIZE "
                   "of this launch, committed, scaled by a plain copy (not measured in this run)")
 
