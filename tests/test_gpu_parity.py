@@ -204,6 +204,45 @@ def test_widest_shells_in_every_tile_shape(L, shape):
     compare_state(o, b, 2, TOL, f"widest shells, shape {shape}, t=3")
 
 
+@pytest.mark.parametrize("drag", [False, True])
+def test_a_species_with_no_particles(L, drag):
+    """Empty input for one species: the second of two has zero density
+    everywhere (walls beyond y, body forces on both, C^visc, with and
+    without the drag).  Its density and velocity stay exactly zero (u = J/n
+    is not formed where n = 0) and the first species evolves as in the
+    oracle.  5 steps."""
+    dims = (10, 12, 14)
+    dens = [W.noisy_uniform(dims, W.packing_density(0.1, 3.0), 1e-2, 31), np.zeros(dims)]
+    w = W.Workload("empty_species", 14, 12, 10, [3.0, 2.0], density=dens,
+                   V=W.smooth_field(dims, 0.05, 2, 32), body=[[1e-4, 0, 0], [0, 1e-4, 0]],
+                   periodic=W.PERIODIC_XZ)
+    flags = L.LBE_VISC | (L.LBE_DRAG if drag else 0)
+    banner(f"a species with no particles, drag={drag}")
+    o, b = _pair(L, w, flags)
+    o.step(5)
+    b.step(5)
+    compare_state(o, b, 2, TOL, f"empty species, drag={drag}, t=5")
+    assert not np.any(b.density(1)) and not np.any(b.velocity(1))
+    for dist in (0, 1):
+        assert not np.any(b.populations(1, dist))
+
+
+def test_an_empty_box(L):
+    """No particles at all (one species, zero density, a potential and a
+    body force): every population stays zero, and the diagnostics report
+    zero mass and velocity without flagging the state."""
+    dims = (8, 9, 10)
+    w = W.Workload("empty_box", 10, 9, 8, [3.0], density=[np.zeros(dims)],
+                   V=W.smooth_field(dims, 0.05, 2, 33), body=[[1e-4, 0, 0]], periodic=7)
+    banner("an empty box")
+    b = L.box_from_workload(w, flags=L.LBE_VISC)
+    b.step(3)
+    for dist in (0, 1):
+        assert not np.any(b.populations(0, dist))
+    d = b.diagnostics()
+    assert d["mass"][0] == 0.0 and d["umax"] == 0.0 and not d["unstable"]
+
+
 def test_channel_one_node_wide(L):
     """A non-periodic edge of one node: walls on both sides of every node
     (12 x 1 x 10, x and z periodic, sigma = 3, C^visc on), so every shell
