@@ -756,9 +756,9 @@ lbe_status lbe_diagnostics(lbe_ctx *c, lbe_diag *out) {
   double *res = c->at<double>(P.off_result);
   const double *V = c->at<double>(P.off_V);
   launch_diag_partials(P.g, P.M, c->args.bb, c->rd, V, c->args.beta, part, P.nblocks, s);
-  launch_diag_final(P.M, part, P.nblocks, res, s);
+  launch_diag_final(part, P.nblocks, res, s);
   launch_diag_errn(P.g, P.M, c->args.bb, c->rd, V, c->args.beta, res, part, P.nblocks, s);
-  launch_diag_final(P.M, part, P.nblocks, res, s);
+  launch_diag_final(part, P.nblocks, res, s);
   LAUNCH_CHECK();
   double h[DIAG_K];
   HIP_TRY(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s));

@@ -177,7 +177,7 @@ void launch_rest_equilibrium(const Geom &g, int prec, const uint32_t *bb, const 
 void launch_diag_partials(const Geom &g, int M, const uint32_t *bb, const Readout &r,
                           const double *V, double beta, double *partials, int nblocks,
                           hipStream_t s);
-void launch_diag_final(int M, const double *partials, int nblocks, double *result, hipStream_t s);
+void launch_diag_final(const double *partials, int nblocks, double *result, hipStream_t s);
 // overwrites slot 11 of each block's partials with max |n - n_eq|
 void launch_diag_errn(const Geom &g, int M, const uint32_t *bb, const Readout &r,
                       const double *V, double beta, const double *result, double *partials,

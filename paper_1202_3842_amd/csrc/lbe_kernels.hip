@@ -1464,17 +1464,25 @@ __global__ __launch_bounds__(BLOCK) void k_diag_partials(Geom g, int M, const ui
   }
 }
 
-__global__ void k_diag_final(int M, const double *__restrict__ partials, int nblocks,
-                             double *__restrict__ result) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double acc[DIAG_K];
-  for (int k = 0; k < DIAG_K; ++k) acc[k] = 0.0;
-  for (int b = 0; b < nblocks; ++b)
-    for (int k = 0; k < DIAG_K; ++k) {
-      double v = partials[(long long)b * DIAG_K + k];
-      acc[k] = (k == 8 || k == 9 || k == 11) ? fmax(acc[k], v) : acc[k] + v;
+// one wave: lane l combines the partials of blocks l, l + 64, ... in order,
+// then a fixed shuffle tree combines the 64 lanes (the same order on every
+// call, so the result is deterministic)
+__global__ __launch_bounds__(64) void k_diag_final(const double *__restrict__ partials, int nblocks,
+                                                   double *__restrict__ result) {
+  const int l = threadIdx.x;
+  for (int k = 0; k < DIAG_K; ++k) {
+    const bool mx = k == 8 || k == 9 || k == 11;
+    double a = 0.0;
+    for (int b = l; b < nblocks; b += 64) {
+      const double v = partials[(long long)b * DIAG_K + k];
+      a = mx ? fmax(a, v) : a + v;
     }
-  for (int k = 0; k < DIAG_K; ++k) result[k] = acc[k];
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_down(a, off, 64);
+      a = mx ? fmax(a, o) : a + o;
+    }
+    if (l == 0) result[k] = a;
+  }
 }
 
 // second pass: max |n_tot - n_eq| with n_eq = mass e^{-beta V} / Z
@@ -2971,8 +2979,8 @@ void launch_diag_partials(const Geom &g, int M, const uint32_t *bb, const Readou
   hipLaunchKernelGGL(k_diag_partials, dim3(nblocks), dim3(BLOCK), 0, s, g, M, bb, r, V, beta, partials);
 }
 
-void launch_diag_final(int M, const double *partials, int nblocks, double *result, hipStream_t s) {
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, M, partials, nblocks, result);
+void launch_diag_final(const double *partials, int nblocks, double *result, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, partials, nblocks, result);
 }
 
 void launch_diag_errn(const Geom &g, int M, const uint32_t *bb, const Readout &r, const double *V,
